@@ -1,0 +1,423 @@
+"""FP64 CPU oracle for the Fourier-spectral PCG ground-state solver of rotating
+spin-orbit-coupled spin-1 condensates (arXiv 2602.17950).
+
+TEST INFRASTRUCTURE. Only the test suite, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package. It shares no code
+with the GPU library (``paper_2602_17950_amd``) and never imports it.
+
+The arithmetic lives in ``gs_oracle.c`` (plain C, double precision, its own
+radix-2 FFT and naive DFT). This module only marshals numpy arrays into it.
+Wave functions are complex128 arrays of shape ``(3,) + grid_shape`` with
+``grid_shape = (Ny, Nx)`` in 2D and ``(Nz, Ny, Nx)`` in 3D (x fastest) and
+component order (phi_1, phi_0, phi_-1).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gs_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+STOP_ENERGY, STOP_RESIDUAL, STOP_BOTH = 0, 1, 2
+OK, MAXITER, STAGNATED, NONFINITE = 0, 1, 2, -4
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no GPU code involved)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-shared", "-fPIC",
+               "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Grid(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("L", C.c_double * 3)]
+
+
+class _Trap(C.Structure):
+    _fields_ = [("g", C.c_double * 3), ("q2", C.c_double), ("q4", C.c_double),
+                ("V", C.POINTER(C.c_double))]
+
+
+class _Params(C.Structure):
+    _fields_ = [("omega", C.c_double), ("gamma", C.c_double),
+                ("c0", C.c_double), ("c1", C.c_double)]
+
+
+class _Options(C.Structure):
+    _fields_ = [("stop_kind", C.c_int), ("tol", C.c_double), ("max_iter", C.c_int),
+                ("theta_trial", C.c_double), ("sigma", C.c_double),
+                ("max_backtrack", C.c_int)]
+
+
+class _Eval(C.Structure):
+    _fields_ = [(k, C.c_double) for k in
+                ("E", "e_kin", "e_pot", "e_rot", "e_spin", "e_soc", "e_pot2", "e_pot4", "mu")] + \
+               [("mu_comp", C.c_double * 3), ("norm_comp", C.c_double * 3),
+                ("norm", C.c_double), ("alpha", C.c_double * 3),
+                ("virial", C.c_double), ("resid_inf", C.c_double)]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("iters", C.c_int), ("backtracks", C.c_int), ("resets", C.c_int),
+                ("status", C.c_int), ("dE_last", C.c_double), ("resid_inf", C.c_double)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        _lib = C.CDLL(_LIB)
+    return _lib
+
+
+@dataclass
+class Grid:
+    """Domain prod_a [-L_a, L_a] with n_a points per axis (n = (Nx, Ny[, Nz]))."""
+    dim: int
+    n: tuple
+    L: tuple
+
+    @property
+    def shape(self):
+        return tuple(reversed(self.n[: self.dim]))
+
+    @property
+    def h(self):
+        return tuple(2.0 * self.L[a] / self.n[a] for a in range(self.dim))
+
+    @property
+    def cell(self):
+        return float(np.prod(self.h))
+
+    def axes(self):
+        """Grid coordinates x_m = -L + m h, one array per axis (x first)."""
+        return [-self.L[a] + np.arange(self.n[a]) * self.h[a] for a in range(self.dim)]
+
+    def _c(self):
+        g = _Grid()
+        g.dim = self.dim
+        for a in range(3):
+            g.n[a] = int(self.n[a]) if a < self.dim else 1
+            g.L[a] = float(self.L[a]) if a < self.dim else 1.0
+        return g
+
+
+@dataclass
+class Trap:
+    """V = 1/2 sum g_a^2 x_a^2 + q2 r^2 + q4 r^4, or a sampled array V."""
+    g: tuple = (1.0, 1.0, 1.0)
+    q2: float = 0.0
+    q4: float = 0.0
+    V: np.ndarray | None = None
+
+    def _c(self, keep):
+        t = _Trap()
+        for a in range(3):
+            t.g[a] = float(self.g[a]) if a < len(self.g) else 1.0
+        t.q2, t.q4 = float(self.q2), float(self.q4)
+        if self.V is not None:
+            v = np.ascontiguousarray(self.V, dtype=np.float64)
+            keep.append(v)
+            t.V = v.ctypes.data_as(C.POINTER(C.c_double))
+        else:
+            t.V = None
+        return t
+
+
+@dataclass
+class Params:
+    omega: float = 0.0
+    gamma: float = 0.0
+    c0: float = 0.0
+    c1: float = 0.0
+
+    def _c(self):
+        return _Params(self.omega, self.gamma, self.c0, self.c1)
+
+
+@dataclass
+class Options:
+    stop_kind: int = STOP_ENERGY
+    tol: float = 1e-12
+    max_iter: int = 20000
+    theta_trial: float = 0.1
+    sigma: float = 0.5
+    max_backtrack: int = 40
+
+    def _c(self):
+        return _Options(self.stop_kind, self.tol, self.max_iter, self.theta_trial,
+                        self.sigma, self.max_backtrack)
+
+
+@dataclass
+class Result:
+    psi: np.ndarray
+    iters: int
+    backtracks: int
+    resets: int
+    status: int
+    dE_last: float
+    resid_inf: float
+    etrace: np.ndarray = field(default=None)
+
+
+def _cplx(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    if shape is not None and a.shape != shape:
+        raise ValueError(f"expected shape {shape}, got {a.shape}")
+    return a
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def set_threads(n: int):
+    _load().orc_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(_load().orc_get_threads())
+
+
+def dft(x, sign=-1):
+    """Naive DFT of a 1-D array, straight from the definition."""
+    x = _cplx(x)
+    out = np.empty_like(x)
+    _load().orc_dft(C.c_int(x.size), _p(x), _p(out), C.c_int(sign))
+    return out
+
+
+def fft1d(x, sign=-1):
+    x = _cplx(x).copy()
+    _load().orc_fft1d(C.c_int(x.size), _p(x), C.c_int(sign))
+    return x
+
+
+def fftn(grid: Grid, f, sign=-1):
+    """Transform one grid array over all axes (inverse divided by the point count)."""
+    f = _cplx(f, grid.shape).copy()
+    g = grid._c()
+    _load().orc_fftn(C.byref(g), _p(f), C.c_int(sign))
+    return f
+
+
+def _field_op(name, grid, u, *extra_before):
+    u = _cplx(u, (3,) + grid.shape)
+    out = np.empty_like(u)
+    g = grid._c()
+    getattr(_load(), name)(C.byref(g), *extra_before, _p(u), _p(out))
+    return out
+
+
+def potential(grid: Grid, trap: Trap):
+    keep = []
+    V = np.empty(grid.shape, dtype=np.float64)
+    g, t = grid._c(), trap._c(keep)
+    _load().orc_potential(C.byref(g), C.byref(t), V.ctypes.data_as(C.c_void_p))
+    return V
+
+
+def apply_soc(grid, u):
+    """S u with S = [[0, L0, 0], [L1, 0, L0], [0, L1, 0]]."""
+    return _field_op("orc_apply_soc", grid, u)
+
+
+def apply_Lz(grid, u):
+    return _field_op("orc_apply_Lz", grid, u)
+
+
+def apply_deriv(grid, axis, f):
+    """D_a f = -i d f / dx_a (one grid array)."""
+    f = _cplx(f, grid.shape)
+    out = np.empty_like(f)
+    g = grid._c()
+    _load().orc_apply_deriv(C.byref(g), C.c_int(axis), _p(f), _p(out))
+    return out
+
+
+def apply_HL(grid, trap, params, u):
+    keep = []
+    t, p = trap._c(keep), params._c()
+    return _field_op("orc_apply_HL", grid, u, C.byref(t), C.byref(p))
+
+
+def apply_H(grid, trap, params, phi):
+    keep = []
+    t, p = trap._c(keep), params._c()
+    return _field_op("orc_apply_H", grid, phi, C.byref(t), C.byref(p))
+
+
+def apply_H_frozen(grid, trap, params, phi, u):
+    keep = []
+    t, p = trap._c(keep), params._c()
+    phi = _cplx(phi, (3,) + grid.shape)
+    return _field_op("orc_apply_H_frozen", grid, u, C.byref(t), C.byref(p), _p(phi))
+
+
+def spin_density(grid, phi):
+    phi = _cplx(phi, (3,) + grid.shape)
+    F = [np.empty(grid.shape) for _ in range(3)]
+    g = grid._c()
+    _load().orc_spin_density(C.byref(g), _p(phi), *[f.ctypes.data_as(C.c_void_p) for f in F])
+    return F
+
+
+def spin_sq_realform(grid, phi):
+    phi = _cplx(phi, (3,) + grid.shape)
+    out = np.empty(grid.shape)
+    g = grid._c()
+    _load().orc_spin_sq_realform(C.byref(g), _p(phi), out.ctypes.data_as(C.c_void_p))
+    return out
+
+
+def re_inner(grid, v, u):
+    v = _cplx(v, (3,) + grid.shape)
+    u = _cplx(u, (3,) + grid.shape)
+    g = grid._c()
+    f = _load().orc_re_inner
+    f.restype = C.c_double
+    return float(f(C.byref(g), _p(v), _p(u)))
+
+
+def energy(grid, trap, params, phi) -> float:
+    keep = []
+    phi = _cplx(phi, (3,) + grid.shape)
+    g, t, p = grid._c(), trap._c(keep), params._c()
+    f = _load().orc_energy
+    f.restype = C.c_double
+    return float(f(C.byref(g), C.byref(t), C.byref(p), _p(phi)))
+
+
+def evaluate(grid, trap, params, phi) -> dict:
+    """Energy and parts, mu, mu_l, N_l, alpha_l, residual sup-norm, virial residual."""
+    keep = []
+    phi = _cplx(phi, (3,) + grid.shape)
+    g, t, p = grid._c(), trap._c(keep), params._c()
+    e = _Eval()
+    _load().orc_evaluate(C.byref(g), C.byref(t), C.byref(p), _p(phi), C.byref(e))
+    out = {k: getattr(e, k) for k in ("E", "e_kin", "e_pot", "e_rot", "e_spin", "e_soc",
+                                      "e_pot2", "e_pot4", "mu", "norm", "virial", "resid_inf")}
+    for k in ("mu_comp", "norm_comp", "alpha"):
+        out[k] = list(getattr(e, k))
+    return out
+
+
+def alpha(grid, trap, params, phi):
+    keep = []
+    phi = _cplx(phi, (3,) + grid.shape)
+    g, t, p = grid._c(), trap._c(keep), params._c()
+    a = (C.c_double * 3)()
+    _load().orc_alpha(C.byref(g), C.byref(t), C.byref(p), _p(phi), a)
+    return list(a)
+
+
+def precond(grid, trap, params, phi, alpha_, r):
+    keep = []
+    phi = _cplx(phi, (3,) + grid.shape)
+    r = _cplx(r, (3,) + grid.shape)
+    out = np.empty_like(r)
+    g, t, p = grid._c(), trap._c(keep), params._c()
+    a = (C.c_double * 3)(*alpha_)
+    _load().orc_precond(C.byref(g), C.byref(t), C.byref(p), _p(phi), a, _p(r), _p(out))
+    return out
+
+
+def linesearch_coeffs(grid, trap, params, phi, P, mu=None, hphi=None):
+    """(a_n, b_n) of the quadratic model for the unnormalised direction P."""
+    keep = []
+    phi = _cplx(phi, (3,) + grid.shape)
+    P = _cplx(P, (3,) + grid.shape)
+    if hphi is None:
+        hphi = apply_H(grid, trap, params, phi)
+    hphi = _cplx(hphi, (3,) + grid.shape)
+    if mu is None:
+        mu = re_inner(grid, hphi, phi)
+    g, t, p = grid._c(), trap._c(keep), params._c()
+    a, b = C.c_double(), C.c_double()
+    _load().orc_linesearch_coeffs(C.byref(g), C.byref(t), C.byref(p), _p(phi), _p(hphi), _p(P),
+                                  C.c_double(mu), C.byref(a), C.byref(b))
+    return a.value, b.value
+
+
+def pcg(grid, trap, params, psi0, options: Options | None = None, trace=False) -> Result:
+    """Algorithm 1 (PCG) with Algorithm 2 (line search and backtracking)."""
+    keep = []
+    o = options or Options()
+    psi = _cplx(psi0, (3,) + grid.shape).copy()
+    g, t, p, oc = grid._c(), trap._c(keep), params._c(), o._c()
+    st = _Stats()
+    et = np.full(o.max_iter + 1, np.nan) if trace else None
+    _load().orc_pcg(C.byref(g), C.byref(t), C.byref(p), C.byref(oc), _p(psi), C.byref(st),
+                    _p(et) if trace else None)
+    if trace:
+        et = et[: st.iters + 1]
+    return Result(psi, st.iters, st.backtracks, st.resets, st.status, st.dE_last,
+                  st.resid_inf, et)
+
+
+def interp(grid_c: Grid, psi_c, grid_f: Grid):
+    """Trigonometric interpolation of a coarse field to a finer grid (same domain)."""
+    psi_c = _cplx(psi_c, (3,) + grid_c.shape)
+    out = np.empty((3,) + grid_f.shape, dtype=np.complex128)
+    gc, gf = grid_c._c(), grid_f._c()
+    rc = _load().orc_interp(C.byref(gc), _p(psi_c), C.byref(gf), _p(out))
+    if rc != 0:
+        raise ValueError("interp: fine grid must be at least as fine, same domain")
+    return out
+
+
+def cmpcg(grids, trap_for, params, psi0, options: Options | None = None):
+    """Algorithm 3: solve on each grid of ``grids`` (coarse to fine), warm-starting
+    each level from the interpolated solution of the previous one. ``trap_for``
+    maps a Grid to its Trap (a sampled V must match the level)."""
+    psi = psi0
+    results = []
+    for lvl, g in enumerate(grids):
+        if lvl > 0:
+            psi = interp(grids[lvl - 1], psi, g)
+        res = pcg(g, trap_for(g), params, psi, options)
+        results.append(res)
+        psi = res.psi
+    return results
+
+
+class _TPoly(C.Structure):
+    _fields_ = [("A", C.c_double), ("B", C.c_double), ("C", C.c_double), ("e", C.c_double * 5)]
+
+
+def tpoly(grid, trap, params, phi, ph):
+    """Coefficients of E(cos t Phi + sin t Ph) written in cos/sin (Ph unit, Re<Ph,Phi> = 0)."""
+    keep = []
+    phi = _cplx(phi, (3,) + grid.shape)
+    ph = _cplx(ph, (3,) + grid.shape)
+    g, t, p = grid._c(), trap._c(keep), params._c()
+    q = _TPoly()
+    _load().orc_tpoly_coeffs(C.byref(g), C.byref(t), C.byref(p), _p(phi), _p(ph), C.byref(q))
+    return q
+
+
+def tpoly_energy(q, theta):
+    f = _load().orc_tpoly_energy
+    f.restype = C.c_double
+    return float(f(C.byref(q), C.c_double(theta)))
+
+
+def tpoly_change(q, theta):
+    f = _load().orc_tpoly_change
+    f.restype = C.c_double
+    return float(f(C.byref(q), C.c_double(theta)))
