@@ -1,0 +1,177 @@
+/*
+ * gs.h - C ABI of the MI355X (gfx950) ground-state library for rotating
+ * spin-orbit-coupled spin-1 Bose-Einstein condensates.
+ *
+ * The library computes
+ *
+ *     Phi_g = argmin E(Phi)  over  { Phi = (phi_1, phi_0, phi_-1) : N(Phi) = 1 },
+ *
+ * the ground state of eqs. (1.8)-(1.9) of Wang, Yang, Yuan and Zhang (arXiv
+ * 2602.17950), with the energy E of eq. (1.7) and the mass N of eq. (1.6),
+ * by the preconditioned nonlinear conjugate gradient method of Sec. 3.1
+ * (Algorithm 1, line search and backtracking of Algorithm 2), the combined
+ * preconditioner P_C of eq. (3.15) with the shifts of eq. (3.13), and the
+ * Fourier spectral discretisation of Sec. 3.2 on the periodic box
+ * prod_a [-L_a, L_a].
+ *
+ * Conventions shared by every entry point
+ *   - Wave functions are three consecutive complex grid arrays in the order
+ *     (phi_1, phi_0, phi_-1), each [Nz][Ny][Nx] (x fastest; Nz = 1 in 2D),
+ *     complex numbers interleaved (re, im). Host arrays are complex128.
+ *   - Grid points x_m = -L + m h, h = 2L/N; integrals are h^d times grid sums,
+ *     so a normalised Phi has h^d sum |Phi|^2 = 1.
+ *   - The caller owns every buffer. The library copies inputs and keeps no
+ *     caller pointer after a call returns (after the stream has completed, for
+ *     entry points that take a stream).
+ *   - Return codes: GS_OK (0); negative = error, outputs untouched;
+ *     positive = completed with a warning, outputs valid.
+ *   - A context serves one device; calls on one context must not overlap.
+ */
+#ifndef GS_H
+#define GS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GS_OK 0
+#define GS_EINVAL (-1)       /* invalid argument (message in gs_last_error) */
+#define GS_ENOMEM (-2)       /* device allocation failed */
+#define GS_EDEVICE (-3)      /* HIP runtime error */
+#define GS_ENONFINITE (-4)   /* NaN or Inf in the input or during the iteration */
+#define GS_WMAXITER 1        /* max_iter reached before the stopping criterion */
+#define GS_WSTAGNATED 2      /* no descent step found: rounding floor reached */
+
+/* stopping criteria (Sec. 3.4) */
+#define GS_STOP_ENERGY 0     /* |E(Phi^{n+1}) - E(Phi^n)| < tol, eq. (3.11) */
+#define GS_STOP_RESIDUAL 1   /* max_l ||r_l^n||_inf < tol, eq. (3.10) */
+#define GS_STOP_EITHER 2     /* stop at whichever holds first */
+
+/* arithmetic of the iteration */
+#define GS_FP64 0            /* all fields and transforms in double */
+#define GS_FP32 1            /* fields and transforms in float, reductions in double */
+#define GS_MIXED 2           /* float until the residual reaches switch_resid (or stalls), then double */
+
+typedef struct gs_ctx gs_ctx;
+
+/* Grid: dim = 2 or 3; n[a] points on [-L[a], L[a]] along x, y, z. Each n[a]
+ * is a power of two between 16 and 1024 (Sec. 3.2 requires N even). */
+typedef struct {
+    int dim;
+    int n[3];
+    double L[3];
+} gs_grid;
+
+/* Trap: V = 1/2 sum_a g[a]^2 x_a^2 + q2 r^2 + q4 r^4 with r^2 = sum_a x_a^2
+ * (harmonic trap eq. (1.4); harmonic-plus-quartic trap eq. (4.1)), or, when V
+ * is not NULL, the sampled potential V[Nz][Ny][Nx] (host, double, copied). */
+typedef struct {
+    double g[3];
+    double q2;
+    double q4;
+    const double* V;
+} gs_trap;
+
+/* Physical parameters (Sec. 1): rotation Omega, SOC strength gamma,
+ * interactions c0 (spin independent) and c1 (spin exchange). */
+typedef struct {
+    double omega;
+    double gamma;
+    double c0;
+    double c1;
+} gs_params;
+
+typedef struct {
+    int stop_kind;        /* GS_STOP_* */
+    double tol;           /* tolerance of the stopping criterion */
+    int max_iter;         /* cap on accepted PCG steps (all phases) */
+    int precision;        /* GS_FP64, GS_FP32 or GS_MIXED */
+    double switch_resid;  /* GS_MIXED: leave float when max_l ||r_l||_inf < switch_resid */
+    int fp32_max_iter;    /* GS_MIXED: cap on float steps */
+    int stall_window;     /* GS_MIXED: leave float when the residual has not halved for this many steps */
+    double theta_trial;   /* Algorithm 2: trial step when the quadratic model has no minimiser */
+    double sigma;         /* Algorithm 2: backtracking factor in (0, 1) */
+    int max_backtrack;    /* cap on backtracking steps per iteration */
+    int check_every;      /* iterations enqueued between two host checks of completion */
+} gs_options;
+
+/* Results; quantities refer to the returned Phi. */
+typedef struct {
+    double E;             /* energy, eq. (1.7) */
+    double mu;            /* chemical potential, eq. (2.9) */
+    double mu_comp[3];    /* Re<H_l(Phi), phi_l> / N_l; each equals mu at a stationary state */
+    double norm_comp[3];  /* N_l = ||phi_l||^2 */
+    double e_kin, e_pot, e_rot, e_spin, e_soc;   /* energy parts of the virial identity (2.11) */
+    double virial;        /* 2 E_kin - 2 E_pot2 - 4 E_pot4 + d E_spin + E_soc (NaN for a sampled V) */
+    double resid_inf;     /* max_l ||H_l(Phi) - mu phi_l||_inf */
+    double dE_last;       /* energy change of the last accepted step */
+    int iters;            /* accepted PCG steps, all phases */
+    int iters_fp32;       /* of which in float arithmetic */
+    int backtracks;       /* backtracking steps taken */
+    int resets;           /* descent-safeguard resets of beta to 0 */
+    int status;           /* return code of the solve */
+    double wall_s;        /* wall time of the call */
+} gs_result;
+
+/* Create a context on HIP device `device`. Returns GS_OK and *out, or an error. */
+int gs_create(gs_ctx** out, int device);
+/* Release the context and all device memory it owns. NULL is ignored. */
+void gs_destroy(gs_ctx* ctx);
+/* Fill *o with the defaults: energy criterion, tol 1e-12, max_iter 100000,
+ * FP64, switch_resid 1e-6, fp32_max_iter 20000, stall_window 50,
+ * theta_trial 0.1, sigma 0.5, max_backtrack 40, check_every 32. */
+void gs_default_options(gs_options* o);
+/* Device bytes a solve of this grid needs at this precision (GS_MIXED counts
+ * both the float and the double working sets). 0 for an invalid grid. */
+size_t gs_footprint_bytes(const gs_grid* g, int precision);
+
+/* Ground state from a host initial guess (Algorithm 1). psi0: host complex128
+ * [3][Nz][Ny][Nx], or NULL for the Gaussian guess (a, a, a)/sqrt(3) of Sec. 4;
+ * it is normalised before the iteration. psi_out: host complex128, same shape,
+ * caller-allocated (may equal psi0). res: filled on success and on warnings.
+ * Synchronous. */
+int gs_solve(gs_ctx* ctx, const gs_grid* g, const gs_trap* t, const gs_params* p,
+             const gs_options* o, const double* psi0, double* psi_out, gs_result* res);
+
+/* As gs_solve with device buffers: d_psi0 and d_psi_out are complex128 device
+ * arrays (d_psi0 may be NULL for the Gaussian guess); the work runs on
+ * `stream` (a hipStream_t; NULL = the null stream). The call returns after
+ * the solve has finished (it polls completion flags on the stream). */
+int gs_solve_device(gs_ctx* ctx, const gs_grid* g, const gs_trap* t, const gs_params* p,
+                    const gs_options* o, const void* d_psi0, void* d_psi_out, gs_result* res,
+                    void* stream);
+
+/* Forward (sign = -1, unnormalised) or inverse (sign = +1, divided by the
+ * number of points) discrete Fourier transform of each of the three
+ * components of d_in, written to d_out in the same [3][Nz][Ny][Nx] layout
+ * with spectral index j_a <-> wavenumber pi p / L_a, p = j (j < n/2) or j - n
+ * (Sec. 3.2). Element type: complex128 (GS_FP64) or complex64 (GS_FP32).
+ * d_in is not modified. Asynchronous on `stream`. */
+int gs_fft(gs_ctx* ctx, const gs_grid* g, int precision, int sign, const void* d_in,
+           void* d_out, void* stream);
+
+/* H(Phi)Phi, the right-hand side of the Euler-Lagrange equations (2.6)-(2.8),
+ * for the device field d_psi (taken as given, not normalised), written to
+ * d_hpsi; when res is not NULL also E, its parts, mu, mu_l, N_l, the virial
+ * residual and max_l ||H_l(Phi) - mu phi_l||_inf (mu from eq. (2.9)).
+ * Element type as for gs_fft. Synchronous when res is not NULL. */
+int gs_hamiltonian(gs_ctx* ctx, const gs_grid* g, const gs_trap* t, const gs_params* p,
+                   int precision, const void* d_psi, void* d_hpsi, gs_result* res, void* stream);
+
+/* Combined preconditioner of eq. (3.15): d_out = P_V^{1/2} P_Delta P_V^{1/2} d_r
+ * with alpha_l of eq. (3.13) evaluated at d_psi. Element type as for gs_fft.
+ * Asynchronous on `stream`. */
+int gs_precondition(gs_ctx* ctx, const gs_grid* g, const gs_trap* t, const gs_params* p,
+                    int precision, const void* d_psi, const void* d_r, void* d_out, void* stream);
+
+/* Message of the last error on this thread ("" if none). */
+const char* gs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GS_H */

@@ -1,0 +1,513 @@
+// Batched three-component FFT passes for gfx950.
+//
+// The d-dimensional transforms of the Fourier spectral method (Sec. 3.2 of the
+// paper: coefficients by FFT, derivatives as multipliers) are done one axis per
+// pass. Every pass works on whole lines in LDS and moves the transformed axis
+// between the contiguous and the slowest position on its way out, so that
+// every global access is a run of contiguous elements:
+//
+//   fwdT:  in[3][A][B][N]  --FFT along N-->  out[3][N][A][B]
+//   invT:  in[3][N][B][C]  --IFFT along N--> out[3][B][C][N]
+//   mid:   in[3][L][N]     --FFT, spectral operator on all 3 components, IFFT--> out[3][L][N]
+//
+// In 2D the H_L chain is fwdT (x) -> mid (y) -> invT (x); in 3D it is
+// fwdT (x) -> fwdT (y) -> mid (z) -> invT (y) -> invT (x). Line transforms are
+// Stockham autosort radix-4 stages plus one radix-2 stage for odd log2 N, with
+// the data of all lines of a block resident in LDS and the butterflies of a
+// stage held in registers between two barriers.
+#include "gs_internal.h"
+
+namespace gs {
+
+constexpr int NT = 256;   // threads per block of every FFT pass
+
+template <int N> struct Log2 { static constexpr int v = 1 + Log2<N / 2>::v; };
+template <> struct Log2<1> { static constexpr int v = 0; };
+
+template <typename R, bool INV>
+__device__ __forceinline__ cpx<R> twid(const cpx<R>* __restrict__ tw, int m) {
+    cpx<R> w = tw[m];
+    if (INV) w.y = -w.y;
+    return w;
+}
+
+// in-place 4-point DFT, kernel e^{-+2 pi i r q / 4}
+template <typename R, bool INV>
+__device__ __forceinline__ void dft4(cpx<R>& v0, cpx<R>& v1, cpx<R>& v2, cpx<R>& v3) {
+    const cpx<R> a = v0 + v2, b = v0 - v2, c = v1 + v3, d = v1 - v3;
+    const cpx<R> id = cmuli(d);
+    v0 = a + c;
+    v2 = a - c;
+    if (INV) { v1 = b + id; v3 = b - id; }
+    else     { v1 = b - id; v3 = b + id; }
+}
+
+// Transform NL lines of length N held in LDS at buf + l * PITCH (natural order
+// in and out, unnormalised). tw[m] = exp(-2 pi i m / N).
+template <typename R, int N, int NL, int PITCH, bool INV>
+__device__ __forceinline__ void lds_fft(cpx<R>* buf, const cpx<R>* __restrict__ tw) {
+    constexpr int LOG2N = Log2<N>::v;
+    constexpr int N4 = N / 4;
+    constexpr int NB4 = NL * N4;
+    constexpr int BPT4 = (NB4 + NT - 1) / NT;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int st = 0; st < LOG2N / 2; ++st) {
+        const int Ns = 1 << (2 * st);
+        cpx<R> v[BPT4][4];
+        int jj[BPT4], ll[BPT4];
+#pragma unroll
+        for (int i = 0; i < BPT4; ++i) {
+            const int b = tid + i * NT;
+            ll[i] = -1;
+            jj[i] = 0;
+            if (b < NB4) {
+                const int l = b / N4, j = b - l * N4;
+                ll[i] = l;
+                jj[i] = j;
+                const cpx<R>* src = buf + l * PITCH + j;
+                v[i][0] = src[0];
+                v[i][1] = src[N4];
+                v[i][2] = src[2 * N4];
+                v[i][3] = src[3 * N4];
+                if (st > 0) {
+                    const int k = j & (Ns - 1);
+                    const int step = k * (N / (4 * Ns));
+                    v[i][1] = cmul(v[i][1], twid<R, INV>(tw, step));
+                    v[i][2] = cmul(v[i][2], twid<R, INV>(tw, 2 * step));
+                    v[i][3] = cmul(v[i][3], twid<R, INV>(tw, 3 * step));
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < BPT4; ++i) {
+            if (ll[i] >= 0) {
+                dft4<R, INV>(v[i][0], v[i][1], v[i][2], v[i][3]);
+                const int j = jj[i];
+                const int k = j & (Ns - 1);
+                cpx<R>* dst = buf + ll[i] * PITCH + ((j - k) << 2) + k;
+                dst[0] = v[i][0];
+                dst[Ns] = v[i][1];
+                dst[2 * Ns] = v[i][2];
+                dst[3 * Ns] = v[i][3];
+            }
+        }
+        __syncthreads();
+    }
+    if (LOG2N & 1) {
+        // last stage, radix 2 with Ns = N/2: reads and writes the same pair
+        constexpr int N2 = N / 2;
+        constexpr int NB2 = NL * N2;
+        for (int b = tid; b < NB2; b += NT) {
+            const int l = b / N2, j = b - l * N2;
+            cpx<R>* p = buf + l * PITCH + j;
+            const cpx<R> u = p[0];
+            const cpx<R> w = cmul(p[N2], twid<R, INV>(tw, j));
+            p[0] = u + w;
+            p[N2] = u - w;
+        }
+        __syncthreads();
+    }
+}
+
+// deterministic block sum of NV doubles; thread 0 ends with the totals
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV]) {
+    __shared__ double sh[NT / 64][NV];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_down(v[k], off, 64);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) sh[wv][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double s = 0.0;
+            for (int w = 0; w < NT / 64; ++w) s += sh[w][k];
+            v[k] = s;
+        }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// forward pass with transposed store
+// ---------------------------------------------------------------------------
+template <typename R, int N, int TILE, int PRO>
+__global__ __launch_bounds__(NT) void k_fwdT(cpx<R>* inp, cpx<R>* __restrict__ out, int A, int B,
+                                             const cpx<R>* __restrict__ aux0,
+                                             const cpx<R>* __restrict__ aux1,
+                                             const SolveState* __restrict__ st,
+                                             const cpx<R>* __restrict__ tw) {
+    if (st && st->done) return;
+    constexpr int PITCH = N + 1;
+    extern __shared__ unsigned char smem_raw[];
+    cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
+    const int tiles = B / TILE;
+    int blk = blockIdx.x;
+    const int bt = blk % tiles;
+    blk /= tiles;
+    const int a = blk % A;
+    const int c = blk / A;
+    const int b0 = bt * TILE;
+    const long long base = (((long long)c * A + a) * B + b0) * N;
+
+    int mode = PRO;
+    R k0 = 1, k1 = 0, k2 = 1;
+    if (PRO == PRO_UPDATE) {
+        if (!st->pending_step) mode = PRO_PLAIN;
+        else {
+            k0 = (R)st->c;
+            k1 = (R)(st->s * st->invnP);
+            k2 = (R)st->inv_norm;
+            if (st->s == 0.0) mode = -1;   // rescale only
+        }
+    } else if (PRO == PRO_DIR) {
+        k0 = (R)st->beta;
+        k1 = (R)st->dphi;
+        k2 = (R)st->invnP;
+    }
+    for (int e = threadIdx.x; e < TILE * N; e += NT) {
+        const int l = e / N, m = e - l * N;
+        const long long gi = base + (long long)l * N + m;
+        cpx<R> v = inp[gi];
+        if (PRO == PRO_UPDATE && mode == PRO_UPDATE) {
+            v = k2 * (k0 * v + k1 * aux0[gi]);
+            inp[gi] = v;
+        } else if (PRO == PRO_UPDATE && mode == -1) {
+            v = k2 * (k0 * v);
+            inp[gi] = v;
+        } else if (PRO == PRO_DIR) {
+            // D = -P r + beta P^{n-1};  P^n = D - Re<D,Phi> Phi  (stored), transform P^n / |P^n|
+            v = k0 * v - aux0[gi] - k1 * aux1[gi];
+            inp[gi] = v;
+            v = k2 * v;
+        }
+        lds[l * PITCH + m] = v;
+    }
+    __syncthreads();
+    lds_fft<R, N, TILE, PITCH, false>(lds, tw);
+    for (int e = threadIdx.x; e < TILE * N; e += NT) {
+        const int l = e % TILE, m = e / TILE;
+        out[(((long long)c * N + m) * A + a) * B + b0 + l] = lds[l * PITCH + m];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// inverse pass with transposed load and physical-space epilogue
+// ---------------------------------------------------------------------------
+//   EPI_SCALE: out = scale * v
+//   EPI_HL:    last pass of the H_L chain, physical [z][y][x]:
+//              out = IFFT(A) + V u - Omega x IFFT(B)      (u = uin, times 1/|P| if use_invnP)
+//   EPI_ROTX:  3D y-pass of the H_L chain, layout [kx][z][y]:
+//              out = IFFT(A) + Omega y k_x uin / Nx, out2 = IFFT(B)
+//              (uin = the x-transformed input, same layout)
+//   EPI_PRE:   out = pv * v  (second P_V^{1/2} factor of the preconditioner)
+template <typename R, int N, int TILE, int EPI>
+__global__ __launch_bounds__(NT) void k_invT(const cpx<R>* __restrict__ in, const cpx<R>* __restrict__ in2,
+                                             cpx<R>* __restrict__ out, cpx<R>* __restrict__ out2,
+                                             int B, int Cc, int nin, Phys p,
+                                             const cpx<R>* __restrict__ uin, double scale,
+                                             const R* __restrict__ pv, const SolveState* __restrict__ st,
+                                             int use_invnP, const cpx<R>* __restrict__ tw) {
+    if (st && st->done) return;
+    constexpr int PITCH = N + 1;
+    extern __shared__ unsigned char smem_raw[];
+    cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
+    cpx<R>* lds2 = lds + TILE * PITCH;
+    const int tiles = Cc / TILE;
+    int blk = blockIdx.x;
+    const int ct = blk % tiles;
+    blk /= tiles;
+    const int bb = blk % B;
+    const int c = blk / B;
+    const int c0 = ct * TILE;
+    for (int e = threadIdx.x; e < TILE * N; e += NT) {
+        const int l = e % TILE, m = e / TILE;
+        const long long gi = (((long long)c * N + m) * B + bb) * Cc + c0 + l;
+        lds[l * PITCH + m] = in[gi];
+        if (nin == 2) lds2[l * PITCH + m] = in2[gi];
+    }
+    __syncthreads();
+    lds_fft<R, N, TILE, PITCH, true>(lds, tw);
+    if (nin == 2) lds_fft<R, N, TILE, PITCH, true>(lds2, tw);
+    const R uscale = (EPI == EPI_HL && use_invnP) ? (R)st->invnP : (R)1;
+    for (int e = threadIdx.x; e < TILE * N; e += NT) {
+        const int l = e / N, m = e - l * N;
+        const long long go = (((long long)c * B + bb) * Cc + c0 + l) * N + m;
+        cpx<R> v = lds[l * PITCH + m];
+        if (EPI == EPI_SCALE) {
+            out[go] = (R)scale * v;
+        } else if (EPI == EPI_HL) {
+            const int ix = m, iy = c0 + l, iz = bb;
+            const double x = -p.L[0] + ix * p.h[0];
+            const double y = -p.L[1] + iy * p.h[1];
+            const double z = p.dim == 3 ? -p.L[2] + iz * p.h[2] : 0.0;
+            double V2, V4;
+            trap_at(p, go - (long long)c * p.M, x, y, z, V2, V4);
+            const cpx<R> u = uscale * uin[go];
+            v = v + (R)(V2 + V4) * u;
+            if (nin == 2) v = v - (R)(p.omega * x) * lds2[l * PITCH + m];
+            out[go] = v;
+        } else if (EPI == EPI_ROTX) {
+            const int jx = bb, iy = m;
+            const double kx = wavenum(jx, p.n[0], p.L[0]);
+            const double y = -p.L[1] + iy * p.h[1];
+            v = v + (R)(p.omega * y * kx / p.n[0]) * uin[go];
+            out[go] = v;
+            if (nin == 2) out2[go] = lds2[l * PITCH + m];
+        } else if (EPI == EPI_PRE) {
+            out[go] = pv[go] * v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// middle pass: spectral operators acting on all three components at each k
+// ---------------------------------------------------------------------------
+//   MID_HL:  A = (1/2 |k|^2 - gamma S(k)) v / M, B = k_y v / M (rotation only),
+//            S(k) = [[0, s0, 0], [s1, 0, s0], [0, s1, 0]], s0 = -k_x + i k_y (L0),
+//            s1 = -k_x - i k_y (L1); reduces sum 1/2|k|^2 |v_l|^2 and Re v^dag S v.
+//            In 2D the rotation term Omega y k_x C / Nx (C the input, x-transformed
+//            and y-physical) is added to A after the inverse transform.
+//   MID_PRE: A = v_l / (alpha_l + 1/2 |k|^2) / M.
+template <typename R, int N, int LPB, int OP>
+__global__ __launch_bounds__(NT) void k_mid(const cpx<R>* __restrict__ in, cpx<R>* __restrict__ outA,
+                                            cpx<R>* __restrict__ outB, int nlines, int rot, Phys p,
+                                            const SolveState* __restrict__ st, double* __restrict__ red,
+                                            const cpx<R>* __restrict__ tw) {
+    if (st && st->done) return;
+    constexpr int PITCH = N + 1;
+    constexpr int NLN = 3 * LPB;
+    extern __shared__ unsigned char smem_raw[];
+    cpx<R>* X = reinterpret_cast<cpx<R>*>(smem_raw);
+    cpx<R>* Y = X + NLN * PITCH;
+    const bool doB = (OP == MID_HL) && rot;
+    const int l0 = blockIdx.x * LPB;
+    const long long cs = (long long)nlines * N;
+    for (int e = threadIdx.x; e < NLN * N; e += NT) {
+        const int L = e / N, m = e - L * N;
+        const int c = L / LPB, q = L - c * LPB;
+        X[L * PITCH + m] = in[c * cs + (long long)(l0 + q) * N + m];
+    }
+    __syncthreads();
+    lds_fft<R, N, NLN, PITCH, false>(X, tw);
+    const double invM = 1.0 / (double)p.M;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    double al[3] = {0.0, 0.0, 0.0}, fl = 0.0;
+    if (OP == MID_PRE) {
+        al[0] = st->alpha[0]; al[1] = st->alpha[1]; al[2] = st->alpha[2];
+        fl = 1e-12 * fmax(1.0, fmax(al[0], fmax(al[1], al[2])));
+    }
+    for (int e = threadIdx.x; e < LPB * N; e += NT) {
+        const int q = e / N, m = e - q * N;
+        const int line = l0 + q;
+        double kx, ky, kz;
+        if (p.dim == 2) {
+            kx = wavenum(line, p.n[0], p.L[0]);
+            ky = wavenum(m, p.n[1], p.L[1]);
+            kz = 0.0;
+        } else {
+            kx = wavenum(line % p.n[0], p.n[0], p.L[0]);
+            ky = wavenum(line / p.n[0], p.n[1], p.L[1]);
+            kz = wavenum(m, p.n[2], p.L[2]);
+        }
+        const double K = 0.5 * (kx * kx + ky * ky + kz * kz);
+        cpx<R>* x0 = X + (0 * LPB + q) * PITCH + m;
+        cpx<R>* x1 = X + (1 * LPB + q) * PITCH + m;
+        cpx<R>* x2 = X + (2 * LPB + q) * PITCH + m;
+        if (OP == MID_HL) {
+            const cpx<double> v0 = wid(*x0), v1 = wid(*x1), v2 = wid(*x2);
+            const cpx<double> s0 = cmk(-kx, ky), s1 = cmk(-kx, -ky);
+            const cpx<double> S0 = cmul(s0, v1);
+            const cpx<double> S1 = cmul(s1, v0) + cmul(s0, v2);
+            const cpx<double> S2 = cmul(s1, v1);
+            acc[0] += K * cabs2(v0);
+            acc[1] += K * cabs2(v1);
+            acc[2] += K * cabs2(v2);
+            acc[3] += cmulc(S0, v0).x + cmulc(S1, v1).x + cmulc(S2, v2).x;
+            const double gm = p.gamma;
+            const cpx<double> a0 = invM * (K * v0 - gm * S0);
+            const cpx<double> a1 = invM * (K * v1 - gm * S1);
+            const cpx<double> a2 = invM * (K * v2 - gm * S2);
+            if (doB) {
+                const double f = ky * invM;
+                Y[(0 * LPB + q) * PITCH + m] = cmk((R)(f * v0.x), (R)(f * v0.y));
+                Y[(1 * LPB + q) * PITCH + m] = cmk((R)(f * v1.x), (R)(f * v1.y));
+                Y[(2 * LPB + q) * PITCH + m] = cmk((R)(f * v2.x), (R)(f * v2.y));
+            }
+            *x0 = cmk((R)a0.x, (R)a0.y);
+            *x1 = cmk((R)a1.x, (R)a1.y);
+            *x2 = cmk((R)a2.x, (R)a2.y);
+        } else {
+            const R d0 = (R)(invM / fmax(al[0] + K, fl));
+            const R d1 = (R)(invM / fmax(al[1] + K, fl));
+            const R d2 = (R)(invM / fmax(al[2] + K, fl));
+            *x0 = d0 * *x0;
+            *x1 = d1 * *x1;
+            *x2 = d2 * *x2;
+        }
+    }
+    __syncthreads();
+    lds_fft<R, N, NLN, PITCH, true>(X, tw);
+    if (doB) lds_fft<R, N, NLN, PITCH, true>(Y, tw);
+    const bool rot2d = (OP == MID_HL) && rot && p.dim == 2;
+    for (int e = threadIdx.x; e < NLN * N; e += NT) {
+        const int L = e / N, m = e - L * N;
+        const int c = L / LPB, q = L - c * LPB;
+        const long long go = c * cs + (long long)(l0 + q) * N + m;
+        cpx<R> v = X[L * PITCH + m];
+        if (rot2d) {
+            const double kx = wavenum(l0 + q, p.n[0], p.L[0]);
+            const double y = -p.L[1] + m * p.h[1];
+            v = v + (R)(p.omega * y * kx / p.n[0]) * in[go];
+        }
+        outA[go] = v;
+        if (doB) outB[go] = Y[L * PITCH + m];
+    }
+    if (OP == MID_HL && red) {
+        block_sum<4>(acc);
+        if (threadIdx.x == 0)
+            for (int k = 0; k < 4; ++k) red[(long long)blockIdx.x * 4 + k] = acc[k];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launch configuration (tile sizes keep each block's LDS within 64 KB)
+// ---------------------------------------------------------------------------
+template <typename R> constexpr int tile_fwd(int N) {
+    return sizeof(R) == 8 ? (N >= 1024 ? 4 : 8) : (N >= 1024 ? 8 : 16);
+}
+template <typename R> constexpr int tile_inv(int N) {
+    return sizeof(R) == 8 ? (N >= 1024 ? 2 : (N >= 512 ? 4 : 8)) : (N >= 1024 ? 4 : (N >= 512 ? 8 : 16));
+}
+constexpr int lpb_mid(int N) { return N >= 256 ? 1 : (N >= 128 ? 2 : (N >= 64 ? 4 : 8)); }
+
+int mid_blocks(int N, int nlines) { return nlines / lpb_mid(N); }
+
+template <typename R, int N>
+static hipError_t fwdT_n(int pro, cpx<R>* inp, cpx<R>* out, int A, int B, const cpx<R>* aux0,
+                         const cpx<R>* aux1, const SolveState* st, const cpx<R>* tw, hipStream_t s) {
+    constexpr int TILE = tile_fwd<R>(N) > 0 ? tile_fwd<R>(N) : 1;
+    if (B % TILE) return hipErrorInvalidValue;
+    const size_t lds = (size_t)TILE * (N + 1) * sizeof(cpx<R>);
+    dim3 grid((unsigned)(3LL * A * (B / TILE)));
+    switch (pro) {
+    case PRO_PLAIN:
+        hipLaunchKernelGGL((k_fwdT<R, N, TILE, PRO_PLAIN>), grid, dim3(NT), lds, s, inp, out, A, B, aux0, aux1, st, tw);
+        break;
+    case PRO_UPDATE:
+        hipLaunchKernelGGL((k_fwdT<R, N, TILE, PRO_UPDATE>), grid, dim3(NT), lds, s, inp, out, A, B, aux0, aux1, st, tw);
+        break;
+    case PRO_DIR:
+        hipLaunchKernelGGL((k_fwdT<R, N, TILE, PRO_DIR>), grid, dim3(NT), lds, s, inp, out, A, B, aux0, aux1, st, tw);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename R, int N>
+static hipError_t invT_n(int epi, int nin, const cpx<R>* in, const cpx<R>* in2, cpx<R>* out, cpx<R>* out2,
+                         int B, int Cc, const Phys& p, const cpx<R>* uin, double scale, const R* pv,
+                         const SolveState* st, int use_invnP, const cpx<R>* tw, hipStream_t s) {
+    constexpr int TILE = tile_inv<R>(N);
+    if (Cc % TILE) return hipErrorInvalidValue;
+    const size_t lds = (size_t)2 * TILE * (N + 1) * sizeof(cpx<R>);
+    dim3 grid((unsigned)(3LL * B * (Cc / TILE)));
+    switch (epi) {
+    case EPI_SCALE:
+        hipLaunchKernelGGL((k_invT<R, N, TILE, EPI_SCALE>), grid, dim3(NT), lds, s, in, in2, out, out2, B, Cc, nin, p, uin, scale, pv, st, use_invnP, tw);
+        break;
+    case EPI_HL:
+        hipLaunchKernelGGL((k_invT<R, N, TILE, EPI_HL>), grid, dim3(NT), lds, s, in, in2, out, out2, B, Cc, nin, p, uin, scale, pv, st, use_invnP, tw);
+        break;
+    case EPI_ROTX:
+        hipLaunchKernelGGL((k_invT<R, N, TILE, EPI_ROTX>), grid, dim3(NT), lds, s, in, in2, out, out2, B, Cc, nin, p, uin, scale, pv, st, use_invnP, tw);
+        break;
+    case EPI_PRE:
+        hipLaunchKernelGGL((k_invT<R, N, TILE, EPI_PRE>), grid, dim3(NT), lds, s, in, in2, out, out2, B, Cc, nin, p, uin, scale, pv, st, use_invnP, tw);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename R, int N>
+static hipError_t mid_n(int op, int rot, const cpx<R>* in, cpx<R>* outA, cpx<R>* outB, int nlines,
+                        const Phys& p, const SolveState* st, double* red, const cpx<R>* tw, hipStream_t s) {
+    constexpr int LPB = lpb_mid(N);
+    if (nlines % LPB) return hipErrorInvalidValue;
+    const int nB = (op == MID_HL && rot) ? 2 : 1;
+    const size_t lds = (size_t)nB * 3 * LPB * (N + 1) * sizeof(cpx<R>);
+    dim3 grid((unsigned)(nlines / LPB));
+    if (op == MID_HL)
+        hipLaunchKernelGGL((k_mid<R, N, LPB, MID_HL>), grid, dim3(NT), lds, s, in, outA, outB, nlines, rot, p, st, red, tw);
+    else
+        hipLaunchKernelGGL((k_mid<R, N, LPB, MID_PRE>), grid, dim3(NT), lds, s, in, outA, outB, nlines, rot, p, st, red, tw);
+    return hipGetLastError();
+}
+
+#define GS_SWITCH_N(CALL)                        \
+    switch (N) {                                 \
+    case 16: return CALL(16);                    \
+    case 32: return CALL(32);                    \
+    case 64: return CALL(64);                    \
+    case 128: return CALL(128);                  \
+    case 256: return CALL(256);                  \
+    case 512: return CALL(512);                  \
+    case 1024: return CALL(1024);                \
+    default: return hipErrorInvalidValue;        \
+    }
+
+template <typename R>
+hipError_t launch_fwdT(int N, int pro, const cpx<R>* in_c, cpx<R>* in_w, cpx<R>* out, int A, int B,
+                       const cpx<R>* aux0, const cpx<R>* aux1, const SolveState* st,
+                       const cpx<R>* tw, hipStream_t s) {
+    cpx<R>* inp = in_w ? in_w : const_cast<cpx<R>*>(in_c);
+#define CALL(n) fwdT_n<R, n>(pro, inp, out, A, B, aux0, aux1, st, tw, s)
+    GS_SWITCH_N(CALL)
+#undef CALL
+}
+
+template <typename R>
+hipError_t launch_invT(int N, int epi, int nin, const cpx<R>* in, const cpx<R>* in2, cpx<R>* out,
+                       cpx<R>* out2, int B, int Cc, const Phys& p, const cpx<R>* uin, double scale,
+                       const R* pv, const SolveState* st, int use_invnP, const cpx<R>* tw, hipStream_t s) {
+#define CALL(n) invT_n<R, n>(epi, nin, in, in2, out, out2, B, Cc, p, uin, scale, pv, st, use_invnP, tw, s)
+    GS_SWITCH_N(CALL)
+#undef CALL
+}
+
+template <typename R>
+hipError_t launch_mid(int N, int op, int rot, const cpx<R>* in, cpx<R>* outA, cpx<R>* outB,
+                      int nlines, const Phys& p, const SolveState* st, double* red_mid,
+                      const cpx<R>* tw, hipStream_t s) {
+#define CALL(n) mid_n<R, n>(op, rot, in, outA, outB, nlines, p, st, red_mid, tw, s)
+    GS_SWITCH_N(CALL)
+#undef CALL
+}
+
+template hipError_t launch_fwdT<double>(int, int, const cpx<double>*, cpx<double>*, cpx<double>*, int, int,
+                                        const cpx<double>*, const cpx<double>*, const SolveState*,
+                                        const cpx<double>*, hipStream_t);
+template hipError_t launch_fwdT<float>(int, int, const cpx<float>*, cpx<float>*, cpx<float>*, int, int,
+                                       const cpx<float>*, const cpx<float>*, const SolveState*,
+                                       const cpx<float>*, hipStream_t);
+template hipError_t launch_invT<double>(int, int, int, const cpx<double>*, const cpx<double>*, cpx<double>*,
+                                        cpx<double>*, int, int, const Phys&, const cpx<double>*, double,
+                                        const double*, const SolveState*, int, const cpx<double>*, hipStream_t);
+template hipError_t launch_invT<float>(int, int, int, const cpx<float>*, const cpx<float>*, cpx<float>*,
+                                       cpx<float>*, int, int, const Phys&, const cpx<float>*, double,
+                                       const float*, const SolveState*, int, const cpx<float>*, hipStream_t);
+template hipError_t launch_mid<double>(int, int, int, const cpx<double>*, cpx<double>*, cpx<double>*, int,
+                                       const Phys&, const SolveState*, double*, const cpx<double>*, hipStream_t);
+template hipError_t launch_mid<float>(int, int, int, const cpx<float>*, cpx<float>*, cpx<float>*, int,
+                                      const Phys&, const SolveState*, double*, const cpx<float>*, hipStream_t);
+
+}  // namespace gs

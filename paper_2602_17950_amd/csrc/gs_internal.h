@@ -1,0 +1,187 @@
+// Internal declarations of the gfx950 ground-state library: complex helpers,
+// the problem description handed to kernels, the device-resident solver state
+// and the launch entry points of the kernel translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace gs {
+
+// ---------------------------------------------------------------------------
+// complex numbers (interleaved re, im; 8 or 16 bytes, naturally aligned)
+// ---------------------------------------------------------------------------
+template <typename R>
+struct __attribute__((aligned(2 * sizeof(R)))) cpx {
+    R x, y;
+};
+
+template <typename R> __host__ __device__ __forceinline__ cpx<R> cmk(R a, R b) { return cpx<R>{a, b}; }
+template <typename R> __host__ __device__ __forceinline__ cpx<R> operator+(cpx<R> a, cpx<R> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename R> __host__ __device__ __forceinline__ cpx<R> operator-(cpx<R> a, cpx<R> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename R> __host__ __device__ __forceinline__ cpx<R> operator*(R s, cpx<R> a) { return {s * a.x, s * a.y}; }
+// complex product
+template <typename R> __host__ __device__ __forceinline__ cpx<R> cmul(cpx<R> a, cpx<R> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// a * conj(b)
+template <typename R> __host__ __device__ __forceinline__ cpx<R> cmulc(cpx<R> a, cpx<R> b) {
+    return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+template <typename R> __host__ __device__ __forceinline__ cpx<R> cconj(cpx<R> a) { return {a.x, -a.y}; }
+// i * a
+template <typename R> __host__ __device__ __forceinline__ cpx<R> cmuli(cpx<R> a) { return {-a.y, a.x}; }
+template <typename R> __host__ __device__ __forceinline__ R cabs2(cpx<R> a) { return a.x * a.x + a.y * a.y; }
+// widen to double
+template <typename R> __host__ __device__ __forceinline__ cpx<double> wid(cpx<R> a) { return {(double)a.x, (double)a.y}; }
+
+// ---------------------------------------------------------------------------
+// problem description passed by value to kernels
+// ---------------------------------------------------------------------------
+struct Phys {
+    int dim;                  // 2 or 3
+    int n[3];                 // Nx, Ny, Nz (Nz = 1 in 2D)
+    double L[3];              // half-widths
+    double h[3];              // h_a = 2 L_a / n_a
+    long long M;              // points per component
+    double cell;              // h^d (rectangle-rule weight)
+    double hg[3];             // 1/2 gamma_a^2 (harmonic part)
+    double q2, q4;            // isotropic r^2 and r^4 coefficients
+    const double* V;          // user potential on the grid (device), or null
+    double omega, gamma, c0, c1;
+};
+
+// trap potential, split into its degree-2 and degree-4 parts (V2 + V4 = V)
+__device__ __forceinline__ void trap_at(const Phys& p, long long i, double x, double y, double z,
+                                        double& V2, double& V4) {
+    if (p.V) { V2 = p.V[i]; V4 = 0.0; return; }
+    double r2 = x * x + y * y + z * z;
+    V2 = p.hg[0] * x * x + p.hg[1] * y * y + p.hg[2] * z * z + p.q2 * r2;
+    V4 = p.q4 * r2 * r2;
+}
+
+// wavenumber of FFT index j on an axis of n points and half-width L:
+// p = j for j < n/2 and j - n otherwise (the mode -n/2 is kept), k = pi p / L
+__device__ __forceinline__ double wavenum(int j, int n, double L) {
+    int p = (j < n / 2) ? j : j - n;
+    return 3.141592653589793238462643 * (double)p / L;
+}
+
+// ---------------------------------------------------------------------------
+// device-resident solver state (one per solve). All control decisions of the
+// PCG iteration are taken on the device from these scalars, so a chunk of
+// iterations can be enqueued (or replayed as a graph) without host round trips.
+// ---------------------------------------------------------------------------
+enum : int { ST_RUNNING = 0 };
+enum : int { PH_FP64 = 0, PH_FP32 = 1 };
+
+struct SolveState {
+    // control flags
+    int done;            // nonzero: every kernel of the iteration returns at once
+    int status;          // GS_* code of the solve
+    int iter;            // accepted PCG steps
+    int iter_phase;      // accepted steps in the current precision phase
+    int backtracks, resets;
+    int pending_step;    // 1: the next chain input Phi <- (c Phi + s P/|P|) * inv_norm
+    int have_prev;       // r^{n-1}, P^{n-1} valid (beta may be nonzero)
+    int cur;             // index of the r buffer that holds r^n
+    int final_pending;   // energy criterion met: evaluate the new iterate, then stop
+    int phase;           // PH_FP64 or PH_FP32
+    int switch_req;      // FP32 phase finished: continue in FP64
+    int best_iter;       // stagnation tracking (FP32 phase)
+    int nonfinite;
+    // options
+    int stop_kind, max_iter, max_backtrack, phase_max_iter, stall_window;
+    double tol, switch_resid, theta_trial, sigma;
+    // current iterate
+    double E, mu, norm2, alpha[3];
+    double e_kin, e_pot, e_rot, e_spin, e_soc, e_pot2, e_pot4, virial;
+    double mu_comp[3], norm_comp[3];
+    double lin;          // <H_L Phi, Phi>
+    double resid_inf, best_resid;
+    // direction
+    double rpr, rpr_prev, beta, dphi, nP, invnP, bdir;
+    // step
+    double a, b, theta, c, s, inv_norm, dE, dE_last;
+};
+
+// reduction scratch: per-block partial sums, a completion counter per reducer
+struct RedBuf {
+    double* mid;        // [nblk_mid][4]   kinetic per component, SOC (spectral)
+    double* pw;         // [nblk_pw][NS_MAX]
+    unsigned* counter;  // one counter per reducing kernel
+    int nblk_mid;
+    int nblk_pw;
+};
+constexpr int NS_MAX = 24;
+
+// ---------------------------------------------------------------------------
+// FFT pass launchers (fft_kernels.hip)
+// ---------------------------------------------------------------------------
+enum Pro : int { PRO_PLAIN = 0, PRO_UPDATE = 1, PRO_DIR = 2 };
+enum Epi : int { EPI_SCALE = 0, EPI_HL = 1, EPI_ROTX = 2, EPI_PRE = 3 };
+enum MidOp : int { MID_HL = 0, MID_PRE = 1 };
+
+// Forward transform along the contiguous axis of in[3][A][B][N], written with
+// that axis moved to the slowest position: out[3][N][A][B].
+// Prologue (in-place on the physical input, before the transform):
+//   PRO_PLAIN:  transform in as is
+//   PRO_UPDATE: if pending_step, in <- (c in + s invnP aux0) inv_norm (written back)
+//   PRO_DIR:    in <- -aux0 + beta in - dphi aux1 (written back), transform invnP * in
+template <typename R>
+hipError_t launch_fwdT(int N, int pro, const cpx<R>* in_c, cpx<R>* in_w, cpx<R>* out, int A, int B,
+                       const cpx<R>* aux0, const cpx<R>* aux1, const SolveState* st,
+                       const cpx<R>* tw, hipStream_t s);
+
+// Inverse transform along the slowest axis of in[3][N][B][Cc] (and in2 when
+// nin = 2), written with that axis contiguous: out[3][B][Cc][N]; the epilogue
+// adds the physical-space terms (see fft_kernels.hip).
+template <typename R>
+hipError_t launch_invT(int N, int epi, int nin, const cpx<R>* in, const cpx<R>* in2, cpx<R>* out,
+                       cpx<R>* out2, int B, int Cc, const Phys& p, const cpx<R>* uin, double scale,
+                       const R* pv, const SolveState* st, int use_invnP, const cpx<R>* tw, hipStream_t s);
+
+// Middle pass: transform the contiguous axis of three component lines,
+// apply the spectral operator (all three components at each wavenumber),
+// transform back. in/outA/outB are [3][nlines][N].
+template <typename R>
+hipError_t launch_mid(int N, int op, int rot, const cpx<R>* in, cpx<R>* outA, cpx<R>* outB,
+                      int nlines, const Phys& p, const SolveState* st, double* red_mid,
+                      const cpx<R>* tw, hipStream_t s);
+
+int mid_blocks(int N, int nlines);
+
+// ---------------------------------------------------------------------------
+// pointwise kernels with fused reductions and device-side control (pw_kernels.hip)
+// ---------------------------------------------------------------------------
+template <typename R>
+struct Fields {
+    cpx<R>* phi;     // Phi
+    cpx<R>* hl;      // H_L Phi
+    cpx<R>* r[2];    // r^n and r^{n-1} (double buffer, SolveState::cur)
+    cpx<R>* pr;      // preconditioned residual
+    cpx<R>* P;       // search direction P^n (P^{n-1} before the direction pass)
+    cpx<R>* hlp;     // H_L P^ (P^ = P / |P|)
+    cpx<R>* u;       // preconditioner input P_V^{1/2} r
+    R* pv;           // [3][M] P_V^{1/2} factors (alpha_l + V + c0 rho)^{-1/2}
+};
+
+template <typename R> hipError_t launch_eval(const Fields<R>& f, const Phys& p, SolveState* st, RedBuf rb, hipStream_t s);
+template <typename R> hipError_t launch_resid(const Fields<R>& f, const Phys& p, SolveState* st, RedBuf rb, hipStream_t s);
+template <typename R> hipError_t launch_dirred(const Fields<R>& f, const Phys& p, SolveState* st, RedBuf rb, hipStream_t s);
+template <typename R> hipError_t launch_lsred(const Fields<R>& f, const Phys& p, SolveState* st, RedBuf rb, hipStream_t s);
+// Phi <- Phi / |Phi| (sets pending_step with c = 1/|Phi|, s = 0)
+template <typename R> hipError_t launch_normalize(const cpx<R>* phi, const Phys& p, SolveState* st, RedBuf rb, hipStream_t s);
+// precision conversion of a field of 3M points
+hipError_t launch_convert_d2f(const cpx<double>* in, cpx<float>* out, long long n, hipStream_t s);
+hipError_t launch_convert_f2d(const cpx<float>* in, cpx<double>* out, long long n, hipStream_t s);
+// H(Phi)Phi = H_L Phi + nonlinear terms (operator-level entry point)
+template <typename R> hipError_t launch_hphi(const cpx<R>* phi, const cpx<R>* hl, cpx<R>* out, const Phys& p, hipStream_t s);
+// out = pv * r elementwise over 3M points (preconditioner input for a given r)
+template <typename R> hipError_t launch_pv_apply(const R* pv, const cpx<R>* r, cpx<R>* out, long long n3, hipStream_t s);
+// Gaussian (a, a, a) initial guess
+hipError_t launch_gaussian(cpx<double>* out, const Phys& p, hipStream_t s);
+
+int pw_blocks(long long M);
+
+}  // namespace gs

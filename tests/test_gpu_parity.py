@@ -1,0 +1,233 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Every comparison uses the same seeded input on both sides. Floating-point
+tolerances: FP64 transforms and operators to 1e-12 (max-norm relative to the
+largest entry; the rounding of a radix FFT grows like eps log N), energies and
+chemical potentials of converged solves to 1e-10 relative; FP32 to 2e-5 for
+operators and 1e-6 relative for converged energies.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2602_17950_amd import gs, inputs
+
+from helpers import orc, rel, smooth_field
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def to_dev(a, prec=gs.GS_FP64):
+    dt = torch.complex128 if prec == gs.GS_FP64 else torch.complex64
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV).to(dt)
+
+
+def to_host(t):
+    torch.cuda.synchronize()
+    return t.to(torch.complex128).cpu().numpy()
+
+
+GRIDS = [
+    (2, (16, 16), (4.0, 4.0)),
+    (2, (32, 64), (8.0, 6.0)),
+    (2, (256, 128), (12.0, 10.0)),
+    (2, (1024, 16), (16.0, 2.0)),
+    (3, (16, 32, 16), (6.0, 6.0, 5.0)),
+    (3, (32, 16, 64), (6.0, 5.0, 8.0)),
+]
+
+
+@pytest.mark.parametrize("dim,n,L", GRIDS)
+@pytest.mark.parametrize("prec", [gs.GS_FP64, gs.GS_FP32])
+def test_fft_forward_inverse(gpu_ctx, dim, n, L, prec):
+    print(f"[fft] dim={dim} n={n} prec={prec}", flush=True)
+    rng = np.random.default_rng(7)
+    g = O.Grid(dim, n, L)
+    shape = (3,) + g.shape
+    x = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    ref = np.stack([O.fftn(g, x[c], -1) for c in range(3)])
+    xd = to_dev(x, prec)
+    yd = torch.empty_like(xd)
+    gg = gs.make_grid(dim, n, L)
+    gpu_ctx.fft(gg, xd, yd, -1, prec)
+    y = to_host(yd)
+    tol = 1e-12 if prec == gs.GS_FP64 else 2e-5
+    assert rel(y, ref) < tol
+    # input untouched
+    assert np.array_equal(to_host(xd), to_host(to_dev(x, prec)))
+    # inverse of the spectrum returns the input
+    zd = torch.empty_like(xd)
+    gpu_ctx.fft(gg, to_dev(ref, prec), zd, +1, prec)
+    assert rel(to_host(zd), x) < tol
+
+
+def _problems():
+    return [
+        inputs.Problem(dim=2, n=(64, 64), L=(8.0, 8.0), omega=0.0, gamma=0.5, c0=100.0, c1=-0.5),
+        inputs.Problem(dim=2, n=(64, 32), L=(10.0, 8.0), omega=0.6, gamma=1.0, c0=500.0, c1=-2.0),
+        inputs.Problem(dim=2, n=(32, 32), L=(8.0, 8.0), g=(1.0, 1.3, 1.0), q2=-0.2, q4=0.05,
+                       omega=1.2, gamma=0.8, c0=300.0, c1=3.0),
+        inputs.Problem(dim=3, n=(32, 16, 32), L=(8.0, 7.0, 8.0), g=(1.0, 1.0, 2.0), omega=0.5,
+                       gamma=1.0, c0=800.0, c1=5.0),
+        inputs.Problem(dim=3, n=(16, 16, 16), L=(6.0, 6.0, 6.0), omega=0.0, gamma=0.3, c0=50.0, c1=-1.0),
+    ]
+
+
+@pytest.mark.parametrize("k", range(5))
+@pytest.mark.parametrize("prec", [gs.GS_FP64, gs.GS_FP32])
+def test_hamiltonian_and_energy(gpu_ctx, k, prec):
+    pb = _problems()[k]
+    print(f"[ham] problem {k} {pb.n} prec={prec}", flush=True)
+    psi = smooth_field(pb, seed=11 + k)
+    g, t, p = orc(pb)
+    H_ref = O.apply_H(g, t, p, psi)
+    ev = O.evaluate(g, t, p, psi)
+    psid = to_dev(psi, prec)
+    hd = torch.empty_like(psid)
+    res = gpu_ctx.hamiltonian(pb, psid, hd, prec)
+    H = to_host(hd)
+    op_tol = 1e-12 if prec == gs.GS_FP64 else 2e-5
+    sc_tol = 1e-12 if prec == gs.GS_FP64 else 2e-5
+    assert rel(H, H_ref) < op_tol
+    for key in ("E", "mu", "e_kin", "e_pot", "e_rot", "e_spin", "e_soc", "virial", "resid_inf"):
+        assert rel(res[key], ev[key]) < sc_tol, (key, res[key], ev[key])
+    for c in range(3):
+        assert rel(res["mu_comp"][c], ev["mu_comp"][c]) < sc_tol
+        assert rel(res["norm_comp"][c], ev["norm_comp"][c]) < sc_tol
+
+
+def test_hamiltonian_user_potential(gpu_ctx):
+    pb = inputs.Problem(dim=2, n=(32, 64), L=(8.0, 8.0), omega=0.3, gamma=0.4, c0=80.0, c1=1.0)
+    X = pb.coords()
+    V = 0.5 * X[0] ** 2 + 0.7 * X[1] ** 2 + 0.3 * np.sin(X[0]) * np.cos(2 * X[1])
+    psi = smooth_field(pb, seed=5)
+    g, t, p = orc(pb, V)
+    H_ref = O.apply_H(g, t, p, psi)
+    ev = O.evaluate(g, t, p, psi)
+    psid = to_dev(psi)
+    hd = torch.empty_like(psid)
+    res = gpu_ctx.hamiltonian(pb, psid, hd, V=V)
+    assert rel(to_host(hd), H_ref) < 1e-12
+    assert rel(res["E"], ev["E"]) < 1e-12
+    assert np.isnan(res["virial"])
+
+
+@pytest.mark.parametrize("k", [0, 1, 3])
+@pytest.mark.parametrize("prec", [gs.GS_FP64, gs.GS_FP32])
+def test_preconditioner(gpu_ctx, k, prec):
+    pb = _problems()[k]
+    print(f"[pre] problem {k} {pb.n} prec={prec}", flush=True)
+    psi = smooth_field(pb, seed=21 + k)
+    r = smooth_field(pb, seed=31 + k, kinds=("b", "a", "a"), noise=0.2)
+    g, t, p = orc(pb)
+    al = O.alpha(g, t, p, psi)
+    ref = O.precond(g, t, p, psi, al, r)
+    out = torch.empty_like(to_dev(psi, prec))
+    gpu_ctx.precondition(pb, to_dev(psi, prec), to_dev(r, prec), out, prec)
+    tol = 1e-12 if prec == gs.GS_FP64 else 2e-5
+    assert rel(to_host(out), ref) < tol
+
+
+def _solve_both(gpu_ctx, pb, psi0, stop, tol, prec=gs.GS_FP64, max_iter=20000):
+    g, t, p = orc(pb)
+    ref = O.pcg(g, t, p, psi0, O.Options(stop_kind=stop, tol=tol, max_iter=max_iter))
+    ev = O.evaluate(g, t, p, ref.psi)
+    psi, res = gpu_ctx.solve(pb, psi0, gs.default_options(stop_kind=stop, tol=tol, precision=prec,
+                                                           max_iter=max_iter))
+    return ref, ev, psi, res
+
+
+def test_solve_small_2d_energy_stop(gpu_ctx):
+    """64x64 workload, energy criterion 1e-12: E and mu against the oracle."""
+    pb, psi0 = inputs.workload_small_2d()
+    ref, ev, psi, res = _solve_both(gpu_ctx, pb, psi0, gs.GS_STOP_ENERGY, 1e-12)
+    print(f"[solve small] gpu E={res['E']!r} it={res['iters']} | oracle E={ev['E']!r} it={ref.iters}")
+    assert res["status"] == 0 and ref.status == 0
+    assert rel(res["E"], ev["E"]) < 1e-10
+    assert rel(res["mu"], ev["mu"]) < 1e-5     # mu is first order in the state error
+    assert abs(sum(res["norm_comp"]) - 1.0) < 1e-13
+
+
+def test_solve_small_2d_residual_stop(gpu_ctx):
+    """Residual criterion 1e-11: E, mu and the component densities."""
+    pb, psi0 = inputs.workload_small_2d()
+    ref, ev, psi, res = _solve_both(gpu_ctx, pb, psi0, gs.GS_STOP_RESIDUAL, 1e-11)
+    print(f"[solve small res] gpu mu={res['mu']!r} it={res['iters']} | oracle mu={ev['mu']!r} it={ref.iters}")
+    assert res["status"] == 0 and ref.status == 0
+    assert rel(res["E"], ev["E"]) < 1e-12
+    assert rel(res["mu"], ev["mu"]) < 1e-10
+    assert res["resid_inf"] < 1e-11
+    rho_g = np.abs(psi) ** 2
+    rho_o = np.abs(ref.psi) ** 2
+    assert rel(rho_g, rho_o) < 1e-8
+
+
+def test_solve_rotating_vortex_2d(gpu_ctx):
+    """Rotating SOC case with a vortex guess (the 256^2 workload's parameters on
+    64^2). The iteration converges slowly here, so both sides stop on the
+    residual: at 1e-9 the energy is within ~1e-15 of its limit."""
+    pb, psi0 = inputs.workload_vortex_2d(n=64)
+    ref, ev, psi, res = _solve_both(gpu_ctx, pb, psi0, gs.GS_STOP_RESIDUAL, 1e-9)
+    print(f"[solve vortex64] gpu E={res['E']!r} it={res['iters']} | oracle E={ev['E']!r} it={ref.iters}")
+    assert res["status"] == 0 and ref.status == 0
+    assert rel(res["E"], ev["E"]) < 1e-10
+    assert rel(res["mu"], ev["mu"]) < 1e-8
+    assert res["e_soc"] <= 0.0
+
+
+def test_solve_mixed_matches_fp64(gpu_ctx):
+    pb, psi0 = inputs.workload_vortex_2d(n=64)
+    _, r64 = gpu_ctx.solve(pb, psi0, gs.default_options(tol=1e-12, precision=gs.GS_FP64))
+    _, rmx = gpu_ctx.solve(pb, psi0, gs.default_options(tol=1e-12, precision=gs.GS_MIXED))
+    _, r32 = gpu_ctx.solve(pb, psi0, gs.default_options(tol=1e-9, precision=gs.GS_FP32))
+    print(f"[mixed] fp64 E={r64['E']!r} it={r64['iters']} mixed E={rmx['E']!r} it={rmx['iters']} "
+          f"(fp32 {rmx['iters_fp32']}) fp32 E={r32['E']!r}")
+    assert rmx["iters_fp32"] > 0
+    assert rel(rmx["E"], r64["E"]) < 1e-10
+    assert rel(r32["E"], r64["E"]) < 1e-6
+
+
+def test_solve_3d_small(gpu_ctx):
+    pb = inputs.Problem(dim=3, n=(16, 16, 16), L=(6.0, 6.0, 6.0), g=(1.0, 1.0, 2.0), omega=0.5,
+                        gamma=1.0, c0=200.0, c1=5.0)
+    psi0 = inputs.initial_guess(pb, ("a", "a", "a"))
+    ref, ev, psi, res = _solve_both(gpu_ctx, pb, psi0, gs.GS_STOP_ENERGY, 1e-12)
+    print(f"[solve 3d] gpu E={res['E']!r} it={res['iters']} | oracle E={ev['E']!r} it={ref.iters}")
+    assert rel(res["E"], ev["E"]) < 1e-10
+
+
+def test_solve_gaussian_default_guess(gpu_ctx):
+    pb, psi0 = inputs.workload_small_2d()
+    _, r1 = gpu_ctx.solve(pb, psi0, gs.default_options())
+    _, r2 = gpu_ctx.solve(pb, None, gs.default_options())
+    assert r1["E"] == r2["E"] or rel(r1["E"], r2["E"]) < 1e-13
+
+
+def test_solve_device_matches_host(gpu_ctx):
+    pb, psi0 = inputs.workload_small_2d()
+    psi_h, rh = gpu_ctx.solve(pb, psi0, gs.default_options())
+    out = torch.empty((3,) + pb.shape, dtype=torch.complex128, device=DEV)
+    rd = gpu_ctx.solve_device(pb, to_dev(psi0), out, gs.default_options())
+    assert rd["E"] == rh["E"]
+    assert np.array_equal(to_host(out), psi_h)
+
+
+def test_errors_and_warnings(gpu_ctx):
+    pb, psi0 = inputs.workload_small_2d()
+    bad = inputs.Problem(dim=2, n=(48, 64), L=(8.0, 8.0))
+    with pytest.raises(gs.GsError) as e:
+        gpu_ctx.solve(bad, None, gs.default_options())
+    assert e.value.code == gs.GS_EINVAL
+    nan_psi = psi0.copy()
+    nan_psi[0, 3, 3] = np.nan
+    with pytest.raises(gs.GsError) as e:
+        gpu_ctx.solve(pb, nan_psi, gs.default_options())
+    assert e.value.code == gs.GS_ENONFINITE
+    _, res = gpu_ctx.solve(pb, psi0, gs.default_options(max_iter=3))
+    assert res["rc"] == gs.GS_WMAXITER and res["iters"] == 3
+    # the library is still usable after errors
+    _, res = gpu_ctx.solve(pb, psi0, gs.default_options())
+    assert res["rc"] == 0
