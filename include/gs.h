@@ -167,6 +167,20 @@ int gs_hamiltonian(gs_ctx* ctx, const gs_grid* g, const gs_trap* t, const gs_par
 int gs_precondition(gs_ctx* ctx, const gs_grid* g, const gs_trap* t, const gs_params* p,
                     int precision, const void* d_psi, const void* d_r, void* d_out, void* stream);
 
+/* Measurement helpers. Kernel kinds of one PCG iteration:
+ *   0 first FFT pass of an H_L application, 1 its spectral middle pass,
+ *   2 its last FFT pass, 3/4/5 the same for the preconditioner, 6 energy and
+ *   mu reduction, 7 residual, 8 direction reduction, 9 step-size reduction,
+ *   10/11 the second forward / inverse passes of a 3D H_L application.
+ * gs_kernel_timer_start(ctx, kind) makes later solves on ctx bracket every
+ * launch of that kernel with HIP events on the solve's stream (kind -1: off)
+ * and resets the totals; gs_kernel_timer_read returns the summed elapsed time
+ * (ms), the summed algorithmic bytes (each array the kernel reads or writes
+ * counted once) and the number of launches timed. Launches that return at
+ * once because the solve has already finished are not counted. */
+int gs_kernel_timer_start(gs_ctx* ctx, int kind);
+int gs_kernel_timer_read(gs_ctx* ctx, double* total_ms, double* total_bytes, long long* launches);
+
 /* Message of the last error on this thread ("" if none). */
 const char* gs_last_error(void);
 

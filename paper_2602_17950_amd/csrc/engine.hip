@@ -72,6 +72,65 @@ struct Plan {
     }
 };
 
+// Optional per-kernel timer: brackets every launch of one kernel kind of the
+// iteration with HIP events on the solve's stream and accumulates the elapsed
+// time and the kernel's algorithmic bytes (each distinct array read or written
+// once). Launches that return at once because the solve has finished (the
+// tail of the last chunk) are left out.
+enum KKind : int {
+    KK_HL_FWD = 0, KK_HL_MID = 1, KK_HL_INV = 2, KK_PRE_FWD = 3, KK_PRE_MID = 4, KK_PRE_INV = 5,
+    KK_EVAL = 6, KK_RESID = 7, KK_DIRRED = 8, KK_LSRED = 9, KK_HL_FWD2 = 10, KK_HL_INV2 = 11,
+    KK_COUNT = 12
+};
+struct Timer {
+    int kind = -1;
+    struct Rec { int k, chain; double bytes; };
+    std::vector<hipEvent_t> ev;
+    std::vector<Rec> rec;
+    int iter_in_chunk = 0;
+    int chain = 0;
+    double ms = 0.0, bytes = 0.0;
+    long long launches = 0;
+    ~Timer() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+};
+
+template <typename F>
+static hipError_t timed(Timer* tm, int kind, double bytes, hipStream_t s, F&& f) {
+    if (!tm || tm->kind != kind) return f();
+    const size_t i = tm->rec.size();
+    while (tm->ev.size() < 2 * (i + 1)) {
+        hipEvent_t e;
+        hipError_t er = hipEventCreate(&e);
+        if (er != hipSuccess) return er;
+        tm->ev.push_back(e);
+    }
+    hipError_t e = hipEventRecord(tm->ev[2 * i], s);
+    if (e == hipSuccess) e = f();
+    if (e == hipSuccess) e = hipEventRecord(tm->ev[2 * i + 1], s);
+    tm->rec.push_back({tm->iter_in_chunk, tm->chain, bytes});
+    return e;
+}
+
+// After a chunk has completed: n_full iterations ran to the end; when the solve
+// finished in the chunk, the first part (chain 1) of iteration n_full also ran.
+static hipError_t timer_collect(Timer* tm, int n_full, bool done) {
+    if (!tm) return hipSuccess;
+    for (size_t i = 0; i < tm->rec.size(); ++i) {
+        const Timer::Rec& r = tm->rec[i];
+        if (!(r.k < n_full || (done && r.k == n_full && r.chain == 1))) continue;
+        float ms = 0.0f;
+        hipError_t e = hipEventElapsedTime(&ms, tm->ev[2 * i], tm->ev[2 * i + 1]);
+        if (e != hipSuccess) return e;
+        tm->ms += ms;
+        tm->bytes += r.bytes;
+        tm->launches++;
+    }
+    tm->rec.clear();
+    return hipSuccess;
+}
+
 struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -85,6 +144,7 @@ struct Ctx {
     double* Vdev = nullptr;
     size_t Vbytes = 0;
     std::vector<void*> allocs;
+    Timer timer;
     ~Ctx() {
         (void)hipSetDevice(device);
         p64.clear();
@@ -234,43 +294,52 @@ static RedBuf redbuf(Ctx& cx, double* red_mid, int nblk_mid, long long M) {
 template <typename R>
 static hipError_t chain_HL(Plan<R>& pl, const Phys& ph, int pro, cpx<R>* in, cpx<R>* out,
                            const cpx<R>* aux0, const cpx<R>* aux1, int use_invnP,
-                           const SolveState* st, hipStream_t s) {
+                           const SolveState* st, hipStream_t s, Timer* tm = nullptr) {
     const int rot = ph.omega != 0.0;
     const int Nx = pl.n[0], Ny = pl.n[1], Nz = pl.n[2];
+    const double F = 3.0 * pl.M * sizeof(cpx<R>);
+    const double b_fwd = pro == PRO_DIR ? 5 * F : (pro == PRO_UPDATE ? 4 * F : 2 * F);
+    const double b_mid = (rot ? 3 : 2) * F, b_inv = (rot ? 4 : 3) * F;
     hipError_t e;
     if (pl.dim == 2) {
-        if ((e = launch_fwdT<R>(Nx, pro, in, in, pl.t[0], 1, Ny, aux0, aux1, st, pl.tw[0], s))) return e;
-        if ((e = launch_mid<R>(Ny, MID_HL, rot, pl.t[0], pl.t[1], pl.t[2], Nx, ph, st, pl.red_mid, pl.tw[1], s))) return e;
-        return launch_invT<R>(Nx, EPI_HL, rot ? 2 : 1, pl.t[1], pl.t[2], out, nullptr, 1, Ny, ph, in, 1.0,
-                              nullptr, st, use_invnP, pl.tw[0], s);
+        if ((e = timed(tm, KK_HL_FWD, b_fwd, s, [&] { return launch_fwdT<R>(Nx, pro, in, in, pl.t[0], 1, Ny, aux0, aux1, st, pl.tw[0], s); }))) return e;
+        if ((e = timed(tm, KK_HL_MID, b_mid, s, [&] { return launch_mid<R>(Ny, MID_HL, rot, pl.t[0], pl.t[1], pl.t[2], Nx, ph, st, pl.red_mid, pl.tw[1], s); }))) return e;
+        return timed(tm, KK_HL_INV, b_inv, s, [&] {
+            return launch_invT<R>(Nx, EPI_HL, rot ? 2 : 1, pl.t[1], pl.t[2], out, nullptr, 1, Ny, ph, in, 1.0,
+                                  nullptr, st, use_invnP, pl.tw[0], s); });
     }
-    if ((e = launch_fwdT<R>(Nx, pro, in, in, pl.t[0], Nz, Ny, aux0, aux1, st, pl.tw[0], s))) return e;
-    if ((e = launch_fwdT<R>(Ny, PRO_PLAIN, pl.t[0], nullptr, pl.t[1], Nx, Nz, nullptr, nullptr, st, pl.tw[1], s))) return e;
-    if ((e = launch_mid<R>(Nz, MID_HL, rot, pl.t[1], pl.t[2], pl.t[3], Ny * Nx, ph, st, pl.red_mid, pl.tw[2], s))) return e;
-    if ((e = launch_invT<R>(Ny, rot ? EPI_ROTX : EPI_SCALE, rot ? 2 : 1, pl.t[2], pl.t[3], pl.t[1], pl.t[4], Nx, Nz,
-                            ph, pl.t[0], 1.0, nullptr, st, 0, pl.tw[1], s))) return e;
-    return launch_invT<R>(Nx, EPI_HL, rot ? 2 : 1, pl.t[1], pl.t[4], out, nullptr, Nz, Ny, ph, in, 1.0, nullptr,
-                          st, use_invnP, pl.tw[0], s);
+    if ((e = timed(tm, KK_HL_FWD, b_fwd, s, [&] { return launch_fwdT<R>(Nx, pro, in, in, pl.t[0], Nz, Ny, aux0, aux1, st, pl.tw[0], s); }))) return e;
+    if ((e = timed(tm, KK_HL_FWD2, 2 * F, s, [&] { return launch_fwdT<R>(Ny, PRO_PLAIN, pl.t[0], nullptr, pl.t[1], Nx, Nz, nullptr, nullptr, st, pl.tw[1], s); }))) return e;
+    if ((e = timed(tm, KK_HL_MID, b_mid, s, [&] { return launch_mid<R>(Nz, MID_HL, rot, pl.t[1], pl.t[2], pl.t[3], Ny * Nx, ph, st, pl.red_mid, pl.tw[2], s); }))) return e;
+    if ((e = timed(tm, KK_HL_INV2, (rot ? 5 : 2) * F, s, [&] {
+             return launch_invT<R>(Ny, rot ? EPI_ROTX : EPI_SCALE, rot ? 2 : 1, pl.t[2], pl.t[3], pl.t[1], pl.t[4], Nx, Nz,
+                                   ph, pl.t[0], 1.0, nullptr, st, 0, pl.tw[1], s); }))) return e;
+    return timed(tm, KK_HL_INV, b_inv, s, [&] {
+        return launch_invT<R>(Nx, EPI_HL, rot ? 2 : 1, pl.t[1], pl.t[4], out, nullptr, Nz, Ny, ph, in, 1.0, nullptr,
+                              st, use_invnP, pl.tw[0], s); });
 }
 
-// out = P_V^{1/2} P_Delta (input already multiplied by P_V^{1/2}, in f.u)
+// pr = P_V^{1/2} P_Delta P_V^{1/2} r (the first factor is already applied: input in f.u)
 template <typename R>
-static hipError_t chain_pre(Plan<R>& pl, const Phys& ph, const SolveState* st, hipStream_t s) {
+static hipError_t chain_pre(Plan<R>& pl, const Phys& ph, const SolveState* st, hipStream_t s, Timer* tm = nullptr) {
     const int Nx = pl.n[0], Ny = pl.n[1], Nz = pl.n[2];
+    const double F = 3.0 * pl.M * sizeof(cpx<R>), Fr = 3.0 * pl.M * sizeof(R);
     hipError_t e;
     if (pl.dim == 2) {
-        if ((e = launch_fwdT<R>(Nx, PRO_PLAIN, pl.f.u, nullptr, pl.t[0], 1, Ny, nullptr, nullptr, st, pl.tw[0], s))) return e;
-        if ((e = launch_mid<R>(Ny, MID_PRE, 0, pl.t[0], pl.t[1], nullptr, Nx, ph, st, nullptr, pl.tw[1], s))) return e;
-        return launch_invT<R>(Nx, EPI_PRE, 1, pl.t[1], nullptr, pl.f.pr, nullptr, 1, Ny, ph, nullptr, 1.0, pl.f.pv, st,
-                              0, pl.tw[0], s);
+        if ((e = timed(tm, KK_PRE_FWD, 2 * F, s, [&] { return launch_fwdT<R>(Nx, PRO_PLAIN, pl.f.u, nullptr, pl.t[0], 1, Ny, nullptr, nullptr, st, pl.tw[0], s); }))) return e;
+        if ((e = timed(tm, KK_PRE_MID, 2 * F, s, [&] { return launch_mid<R>(Ny, MID_PRE, 0, pl.t[0], pl.t[1], nullptr, Nx, ph, st, nullptr, pl.tw[1], s); }))) return e;
+        return timed(tm, KK_PRE_INV, 2 * F + Fr, s, [&] {
+            return launch_invT<R>(Nx, EPI_PRE, 1, pl.t[1], nullptr, pl.f.pr, nullptr, 1, Ny, ph, nullptr, 1.0, pl.f.pv, st,
+                                  0, pl.tw[0], s); });
     }
-    if ((e = launch_fwdT<R>(Nx, PRO_PLAIN, pl.f.u, nullptr, pl.t[0], Nz, Ny, nullptr, nullptr, st, pl.tw[0], s))) return e;
+    if ((e = timed(tm, KK_PRE_FWD, 2 * F, s, [&] { return launch_fwdT<R>(Nx, PRO_PLAIN, pl.f.u, nullptr, pl.t[0], Nz, Ny, nullptr, nullptr, st, pl.tw[0], s); }))) return e;
     if ((e = launch_fwdT<R>(Ny, PRO_PLAIN, pl.t[0], nullptr, pl.t[1], Nx, Nz, nullptr, nullptr, st, pl.tw[1], s))) return e;
-    if ((e = launch_mid<R>(Nz, MID_PRE, 0, pl.t[1], pl.t[2], nullptr, Ny * Nx, ph, st, nullptr, pl.tw[2], s))) return e;
+    if ((e = timed(tm, KK_PRE_MID, 2 * F, s, [&] { return launch_mid<R>(Nz, MID_PRE, 0, pl.t[1], pl.t[2], nullptr, Ny * Nx, ph, st, nullptr, pl.tw[2], s); }))) return e;
     if ((e = launch_invT<R>(Ny, EPI_SCALE, 1, pl.t[2], nullptr, pl.t[1], nullptr, Nx, Nz, ph, nullptr, 1.0, nullptr,
                             st, 0, pl.tw[1], s))) return e;
-    return launch_invT<R>(Nx, EPI_PRE, 1, pl.t[1], nullptr, pl.f.pr, nullptr, Nz, Ny, ph, nullptr, 1.0, pl.f.pv, st, 0,
-                          pl.tw[0], s);
+    return timed(tm, KK_PRE_INV, 2 * F + Fr, s, [&] {
+        return launch_invT<R>(Nx, EPI_PRE, 1, pl.t[1], nullptr, pl.f.pr, nullptr, Nz, Ny, ph, nullptr, 1.0, pl.f.pv, st, 0,
+                              pl.tw[0], s); });
 }
 
 // One PCG iteration (Algorithm 1 with Algorithm 2), entirely on the device:
@@ -282,15 +351,19 @@ static hipError_t chain_pre(Plan<R>& pl, const Phys& ph, const SolveState* st, h
 //   6. P^n = D - Re<D,Phi>Phi, H_L P^                      (3 or 5 FFT passes)
 //   7. exact energy along the retraction, step size, backtracking (reduction, control)
 template <typename R>
-static hipError_t iterate(Plan<R>& pl, const Phys& ph, SolveState* st, RedBuf rb, hipStream_t s) {
+static hipError_t iterate(Plan<R>& pl, const Phys& ph, SolveState* st, RedBuf rb, hipStream_t s, Timer* tm) {
+    const double F = 3.0 * pl.M * sizeof(cpx<R>), Fr = 3.0 * pl.M * sizeof(R);
     hipError_t e;
-    if ((e = chain_HL<R>(pl, ph, PRO_UPDATE, pl.f.phi, pl.f.hl, pl.f.P, nullptr, 0, st, s))) return e;
-    if ((e = launch_eval<R>(pl.f, ph, st, rb, s))) return e;
-    if ((e = launch_resid<R>(pl.f, ph, st, rb, s))) return e;
-    if ((e = chain_pre<R>(pl, ph, st, s))) return e;
-    if ((e = launch_dirred<R>(pl.f, ph, st, rb, s))) return e;
-    if ((e = chain_HL<R>(pl, ph, PRO_DIR, pl.f.P, pl.f.hlp, pl.f.pr, pl.f.phi, 1, st, s))) return e;
-    return launch_lsred<R>(pl.f, ph, st, rb, s);
+    if (tm) tm->chain = 1;
+    if ((e = chain_HL<R>(pl, ph, PRO_UPDATE, pl.f.phi, pl.f.hl, pl.f.P, nullptr, 0, st, s, tm))) return e;
+    if ((e = timed(tm, KK_EVAL, 2 * F, s, [&] { return launch_eval<R>(pl.f, ph, st, rb, s); }))) return e;
+    if ((e = timed(tm, KK_RESID, 4 * F + Fr, s, [&] { return launch_resid<R>(pl.f, ph, st, rb, s); }))) return e;
+    if (tm) tm->chain = 2;
+    if ((e = chain_pre<R>(pl, ph, st, s, tm))) return e;
+    if ((e = timed(tm, KK_DIRRED, 5 * F, s, [&] { return launch_dirred<R>(pl.f, ph, st, rb, s); }))) return e;
+    if (tm) tm->chain = 3;
+    if ((e = chain_HL<R>(pl, ph, PRO_DIR, pl.f.P, pl.f.hlp, pl.f.pr, pl.f.phi, 1, st, s, tm))) return e;
+    return timed(tm, KK_LSRED, 4 * F, s, [&] { return launch_lsred<R>(pl.f, ph, st, rb, s); });
 }
 
 // ---------------------------------------------------------------------------
@@ -331,11 +404,17 @@ template <typename R>
 static int run_phase(Ctx& cx, Plan<R>& pl, const Phys& ph, int check_every, hipStream_t s) {
     RedBuf rb = redbuf(cx, pl.red_mid, pl.nblk_mid, pl.M);
     HIPCHK(launch_normalize<R>(pl.f.phi, ph, cx.st, rb, s));
+    Timer* tm = cx.timer.kind >= 0 ? &cx.timer : nullptr;
     int last_iter = -1;
     for (;;) {
-        for (int k = 0; k < check_every; ++k) HIPCHK(iterate<R>(pl, ph, cx.st, rb, s));
+        const int iter0 = cx.st_host->iter;
+        for (int k = 0; k < check_every; ++k) {
+            if (tm) tm->iter_in_chunk = k;
+            HIPCHK(iterate<R>(pl, ph, cx.st, rb, s, tm));
+        }
         HIPCHK(hipMemcpyAsync(cx.st_host, cx.st, sizeof(SolveState), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
+        HIPCHK(timer_collect(tm, cx.st_host->iter - iter0, cx.st_host->done != 0));
         if (cx.st_host->done) break;
         // every iteration either accepts a step or ends the solve
         if (cx.st_host->iter == last_iter) return fail(GS_EDEVICE, "solver made no progress (device state not updated)");
@@ -647,6 +726,27 @@ int gs_solve_device(gs_ctx* ctx, const gs_grid* g, const gs_trap* t, const gs_pa
     if (!d_psi_out) return fail(GS_EINVAL, "d_psi_out is NULL");
     return solve_impl(ctx->impl, g, t, p, o, (const cpx<double>*)d_psi0, (cpx<double>*)d_psi_out, res,
                       (hipStream_t)stream);
+}
+
+int gs_kernel_timer_start(gs_ctx* ctx, int kind) {
+    if (!ctx) return fail(GS_EINVAL, "ctx is NULL");
+    if (kind < -1 || kind >= KK_COUNT) return fail(GS_EINVAL, "unknown kernel kind");
+    Timer& t = ctx->impl.timer;
+    t.kind = kind;
+    t.rec.clear();
+    t.ms = 0.0;
+    t.bytes = 0.0;
+    t.launches = 0;
+    return GS_OK;
+}
+
+int gs_kernel_timer_read(gs_ctx* ctx, double* total_ms, double* total_bytes, long long* launches) {
+    if (!ctx) return fail(GS_EINVAL, "ctx is NULL");
+    const Timer& t = ctx->impl.timer;
+    if (total_ms) *total_ms = t.ms;
+    if (total_bytes) *total_bytes = t.bytes;
+    if (launches) *launches = t.launches;
+    return GS_OK;
 }
 
 int gs_fft(gs_ctx* ctx, const gs_grid* g, int precision, int sign, const void* d_in, void* d_out, void* stream) {

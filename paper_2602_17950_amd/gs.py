@@ -20,7 +20,11 @@ GS_STOP_ENERGY, GS_STOP_RESIDUAL, GS_STOP_EITHER = 0, 1, 2
 GS_FP64, GS_FP32, GS_MIXED = 0, 1, 2
 
 EXPORTS = ("gs_create", "gs_destroy", "gs_default_options", "gs_footprint_bytes", "gs_solve",
-           "gs_solve_device", "gs_fft", "gs_hamiltonian", "gs_precondition", "gs_last_error")
+           "gs_solve_device", "gs_fft", "gs_hamiltonian", "gs_precondition", "gs_kernel_timer_start",
+           "gs_kernel_timer_read", "gs_last_error")
+
+KERNEL_KINDS = {"hl_fwd": 0, "hl_mid": 1, "hl_inv": 2, "pre_fwd": 3, "pre_mid": 4, "pre_inv": 5,
+                "eval": 6, "resid": 7, "dirred": 8, "lsred": 9, "hl_fwd2": 10, "hl_inv2": 11}
 
 
 class GsError(RuntimeError):
@@ -94,6 +98,9 @@ def load():
                                    C.c_int, vp, vp, C.POINTER(gs_result), vp]
     lib.gs_precondition.argtypes = [vp, C.POINTER(gs_grid), C.POINTER(gs_trap), C.POINTER(gs_params),
                                     C.c_int, vp, vp, vp, vp]
+    lib.gs_kernel_timer_start.argtypes = [vp, C.c_int]
+    lib.gs_kernel_timer_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                         C.POINTER(C.c_longlong)]
     lib.gs_last_error.restype = C.c_char_p
     _lib = lib
     return lib
@@ -221,6 +228,17 @@ class Context:
         d = res.to_dict()
         d["rc"] = rc
         return d
+
+    # -- measurement ---------------------------------------------------------------
+    def kernel_timer_start(self, kind):
+        """Time every launch of one kernel kind (name in KERNEL_KINDS or int; None = off)."""
+        k = -1 if kind is None else (KERNEL_KINDS[kind] if isinstance(kind, str) else int(kind))
+        _check(load().gs_kernel_timer_start(self._h, k))
+
+    def kernel_timer_read(self):
+        ms, by, n = C.c_double(), C.c_double(), C.c_longlong()
+        _check(load().gs_kernel_timer_read(self._h, C.byref(ms), C.byref(by), C.byref(n)))
+        return {"ms": ms.value, "bytes": by.value, "launches": n.value}
 
     # -- operator-level calls ----------------------------------------------------
     def fft(self, grid: gs_grid, x, out, sign: int, precision=GS_FP64, stream=None):
