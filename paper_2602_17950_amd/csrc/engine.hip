@@ -17,6 +17,11 @@
 
 namespace gs {
 
+LaunchEvents& launch_events() {
+    static thread_local LaunchEvents e;
+    return e;
+}
+
 static thread_local std::string g_err;
 static int fail(int code, const std::string& msg) {
     g_err = msg;
@@ -72,10 +77,10 @@ struct Plan {
     }
 };
 
-// Optional per-kernel timer: brackets every launch of one kernel kind of the
-// iteration with HIP events on the solve's stream and accumulates the elapsed
-// time and the kernel's algorithmic bytes (each distinct array read or written
-// once). Launches that return at once because the solve has finished (the
+// Optional per-kernel timer: every launch of one kernel kind of the iteration
+// records its own start and end (dispatch timestamps, hipExtLaunchKernelGGL)
+// into HIP events on the solve's stream; the elapsed times and the kernel's
+// algorithmic bytes (each distinct array read or written once) are summed. Launches that return at once because the solve has finished (the
 // tail of the last chunk) are left out.
 enum KKind : int {
     KK_HL_FWD = 0, KK_HL_MID = 1, KK_HL_INV = 2, KK_PRE_FWD = 3, KK_PRE_MID = 4, KK_PRE_INV = 5,
@@ -106,9 +111,14 @@ static hipError_t timed(Timer* tm, int kind, double bytes, hipStream_t s, F&& f)
         if (er != hipSuccess) return er;
         tm->ev.push_back(e);
     }
-    hipError_t e = hipEventRecord(tm->ev[2 * i], s);
-    if (e == hipSuccess) e = f();
-    if (e == hipSuccess) e = hipEventRecord(tm->ev[2 * i + 1], s);
+    // the launch itself records its start and end into the two events
+    LaunchEvents& le = launch_events();
+    le.start = tm->ev[2 * i];
+    le.stop = tm->ev[2 * i + 1];
+    hipError_t e = f();
+    const bool consumed = le.start == nullptr;
+    le.start = le.stop = nullptr;
+    if (e == hipSuccess && !consumed) e = hipErrorInvalidValue;
     tm->rec.push_back({tm->iter_in_chunk, tm->chain, bytes});
     return e;
 }

@@ -397,13 +397,13 @@ static hipError_t fwdT_n(int pro, cpx<R>* inp, cpx<R>* out, int A, int B, const 
     dim3 grid((unsigned)(3LL * A * (B / TILE)));
     switch (pro) {
     case PRO_PLAIN:
-        hipLaunchKernelGGL((k_fwdT<R, N, TILE, PRO_PLAIN>), grid, dim3(NT), lds, s, inp, out, A, B, aux0, aux1, st, tw);
+        GS_LAUNCH((k_fwdT<R, N, TILE, PRO_PLAIN>), grid, dim3(NT), lds, s, inp, out, A, B, aux0, aux1, st, tw);
         break;
     case PRO_UPDATE:
-        hipLaunchKernelGGL((k_fwdT<R, N, TILE, PRO_UPDATE>), grid, dim3(NT), lds, s, inp, out, A, B, aux0, aux1, st, tw);
+        GS_LAUNCH((k_fwdT<R, N, TILE, PRO_UPDATE>), grid, dim3(NT), lds, s, inp, out, A, B, aux0, aux1, st, tw);
         break;
     case PRO_DIR:
-        hipLaunchKernelGGL((k_fwdT<R, N, TILE, PRO_DIR>), grid, dim3(NT), lds, s, inp, out, A, B, aux0, aux1, st, tw);
+        GS_LAUNCH((k_fwdT<R, N, TILE, PRO_DIR>), grid, dim3(NT), lds, s, inp, out, A, B, aux0, aux1, st, tw);
         break;
     default:
         return hipErrorInvalidValue;
@@ -421,16 +421,16 @@ static hipError_t invT_n(int epi, int nin, const cpx<R>* in, const cpx<R>* in2, 
     dim3 grid((unsigned)(3LL * B * (Cc / TILE)));
     switch (epi) {
     case EPI_SCALE:
-        hipLaunchKernelGGL((k_invT<R, N, TILE, EPI_SCALE>), grid, dim3(NT), lds, s, in, in2, out, out2, B, Cc, nin, p, uin, scale, pv, st, use_invnP, tw);
+        GS_LAUNCH((k_invT<R, N, TILE, EPI_SCALE>), grid, dim3(NT), lds, s, in, in2, out, out2, B, Cc, nin, p, uin, scale, pv, st, use_invnP, tw);
         break;
     case EPI_HL:
-        hipLaunchKernelGGL((k_invT<R, N, TILE, EPI_HL>), grid, dim3(NT), lds, s, in, in2, out, out2, B, Cc, nin, p, uin, scale, pv, st, use_invnP, tw);
+        GS_LAUNCH((k_invT<R, N, TILE, EPI_HL>), grid, dim3(NT), lds, s, in, in2, out, out2, B, Cc, nin, p, uin, scale, pv, st, use_invnP, tw);
         break;
     case EPI_ROTX:
-        hipLaunchKernelGGL((k_invT<R, N, TILE, EPI_ROTX>), grid, dim3(NT), lds, s, in, in2, out, out2, B, Cc, nin, p, uin, scale, pv, st, use_invnP, tw);
+        GS_LAUNCH((k_invT<R, N, TILE, EPI_ROTX>), grid, dim3(NT), lds, s, in, in2, out, out2, B, Cc, nin, p, uin, scale, pv, st, use_invnP, tw);
         break;
     case EPI_PRE:
-        hipLaunchKernelGGL((k_invT<R, N, TILE, EPI_PRE>), grid, dim3(NT), lds, s, in, in2, out, out2, B, Cc, nin, p, uin, scale, pv, st, use_invnP, tw);
+        GS_LAUNCH((k_invT<R, N, TILE, EPI_PRE>), grid, dim3(NT), lds, s, in, in2, out, out2, B, Cc, nin, p, uin, scale, pv, st, use_invnP, tw);
         break;
     default:
         return hipErrorInvalidValue;
@@ -447,9 +447,9 @@ static hipError_t mid_n(int op, int rot, const cpx<R>* in, cpx<R>* outA, cpx<R>*
     const size_t lds = (size_t)nB * 3 * LPB * (N + 1) * sizeof(cpx<R>);
     dim3 grid((unsigned)(nlines / LPB));
     if (op == MID_HL)
-        hipLaunchKernelGGL((k_mid<R, N, LPB, MID_HL>), grid, dim3(NT), lds, s, in, outA, outB, nlines, rot, p, st, red, tw);
+        GS_LAUNCH((k_mid<R, N, LPB, MID_HL>), grid, dim3(NT), lds, s, in, outA, outB, nlines, rot, p, st, red, tw);
     else
-        hipLaunchKernelGGL((k_mid<R, N, LPB, MID_PRE>), grid, dim3(NT), lds, s, in, outA, outB, nlines, rot, p, st, red, tw);
+        GS_LAUNCH((k_mid<R, N, LPB, MID_PRE>), grid, dim3(NT), lds, s, in, outA, outB, nlines, rot, p, st, red, tw);
     return hipGetLastError();
 }
 

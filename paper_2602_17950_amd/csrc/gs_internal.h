@@ -3,10 +3,31 @@
 // and the launch entry points of the kernel translation units.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <cstddef>
 #include <cstdint>
 
 namespace gs {
+
+// Events into which the next kernel launch on this thread writes its own
+// start and end timestamps (used by the per-kernel timer); consumed by that
+// launch. Every kernel of the library is launched through GS_LAUNCH.
+struct LaunchEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+LaunchEvents& launch_events();
+
+#define GS_LAUNCH(KERNEL, GRID, BLOCK, SHMEM, STREAM, ...)                                          \
+    do {                                                                                            \
+        gs::LaunchEvents& le_ = gs::launch_events();                                                \
+        if (le_.start) {                                                                            \
+            hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, SHMEM, STREAM, le_.start, le_.stop, 0u,      \
+                                  __VA_ARGS__);                                                     \
+            le_.start = le_.stop = nullptr;                                                         \
+        } else {                                                                                    \
+            hipLaunchKernelGGL(KERNEL, GRID, BLOCK, SHMEM, STREAM, __VA_ARGS__);                    \
+        }                                                                                           \
+    } while (0)
 
 // ---------------------------------------------------------------------------
 // complex numbers (interleaved re, im; 8 or 16 bytes, naturally aligned)

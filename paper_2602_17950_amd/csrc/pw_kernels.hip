@@ -536,43 +536,43 @@ __global__ void k_gaussian(cpx<double>* out, Phys p) {
 // launchers
 // ---------------------------------------------------------------------------
 template <typename R> hipError_t launch_eval(const Fields<R>& f, const Phys& p, SolveState* st, RedBuf rb, hipStream_t s) {
-    hipLaunchKernelGGL(k_eval<R>, dim3(rb.nblk_pw), dim3(PT), 0, s, f, p, st, rb);
+    GS_LAUNCH(k_eval<R>, dim3(rb.nblk_pw), dim3(PT), 0, s, f, p, st, rb);
     return hipGetLastError();
 }
 template <typename R> hipError_t launch_resid(const Fields<R>& f, const Phys& p, SolveState* st, RedBuf rb, hipStream_t s) {
-    hipLaunchKernelGGL(k_resid<R>, dim3(rb.nblk_pw), dim3(PT), 0, s, f, p, st, rb);
+    GS_LAUNCH(k_resid<R>, dim3(rb.nblk_pw), dim3(PT), 0, s, f, p, st, rb);
     return hipGetLastError();
 }
 template <typename R> hipError_t launch_dirred(const Fields<R>& f, const Phys& p, SolveState* st, RedBuf rb, hipStream_t s) {
-    hipLaunchKernelGGL(k_dirred<R>, dim3(rb.nblk_pw), dim3(PT), 0, s, f, p, st, rb);
+    GS_LAUNCH(k_dirred<R>, dim3(rb.nblk_pw), dim3(PT), 0, s, f, p, st, rb);
     return hipGetLastError();
 }
 template <typename R> hipError_t launch_lsred(const Fields<R>& f, const Phys& p, SolveState* st, RedBuf rb, hipStream_t s) {
-    hipLaunchKernelGGL(k_lsred<R>, dim3(rb.nblk_pw), dim3(PT), 0, s, f, p, st, rb);
+    GS_LAUNCH(k_lsred<R>, dim3(rb.nblk_pw), dim3(PT), 0, s, f, p, st, rb);
     return hipGetLastError();
 }
 template <typename R> hipError_t launch_normalize(const cpx<R>* phi, const Phys& p, SolveState* st, RedBuf rb, hipStream_t s) {
-    hipLaunchKernelGGL(k_normalize<R>, dim3(rb.nblk_pw), dim3(PT), 0, s, phi, p, st, rb);
+    GS_LAUNCH(k_normalize<R>, dim3(rb.nblk_pw), dim3(PT), 0, s, phi, p, st, rb);
     return hipGetLastError();
 }
 hipError_t launch_convert_d2f(const cpx<double>* in, cpx<float>* out, long long n, hipStream_t s) {
-    hipLaunchKernelGGL(k_d2f, dim3(pw_blocks(n)), dim3(PT), 0, s, in, out, n);
+    GS_LAUNCH(k_d2f, dim3(pw_blocks(n)), dim3(PT), 0, s, in, out, n);
     return hipGetLastError();
 }
 hipError_t launch_convert_f2d(const cpx<float>* in, cpx<double>* out, long long n, hipStream_t s) {
-    hipLaunchKernelGGL(k_f2d, dim3(pw_blocks(n)), dim3(PT), 0, s, in, out, n);
+    GS_LAUNCH(k_f2d, dim3(pw_blocks(n)), dim3(PT), 0, s, in, out, n);
     return hipGetLastError();
 }
 template <typename R> hipError_t launch_hphi(const cpx<R>* phi, const cpx<R>* hl, cpx<R>* out, const Phys& p, hipStream_t s) {
-    hipLaunchKernelGGL(k_hphi<R>, dim3(pw_blocks(p.M)), dim3(PT), 0, s, phi, hl, out, p);
+    GS_LAUNCH(k_hphi<R>, dim3(pw_blocks(p.M)), dim3(PT), 0, s, phi, hl, out, p);
     return hipGetLastError();
 }
 template <typename R> hipError_t launch_pv_apply(const R* pv, const cpx<R>* r, cpx<R>* out, long long n3, hipStream_t s) {
-    hipLaunchKernelGGL(k_pv_apply<R>, dim3(pw_blocks(n3)), dim3(PT), 0, s, pv, r, out, n3);
+    GS_LAUNCH(k_pv_apply<R>, dim3(pw_blocks(n3)), dim3(PT), 0, s, pv, r, out, n3);
     return hipGetLastError();
 }
 hipError_t launch_gaussian(cpx<double>* out, const Phys& p, hipStream_t s) {
-    hipLaunchKernelGGL(k_gaussian, dim3(pw_blocks(p.M)), dim3(PT), 0, s, out, p);
+    GS_LAUNCH(k_gaussian, dim3(pw_blocks(p.M)), dim3(PT), 0, s, out, p);
     return hipGetLastError();
 }
 
