@@ -25,7 +25,13 @@
  *     entry points that take a stream).
  *   - Return codes: GS_OK (0); negative = error, outputs untouched;
  *     positive = completed with a warning, outputs valid.
- *   - A context serves one device; calls on one context must not overlap.
+ *   - A context serves one device; calls on one context must not overlap
+ *     (one context per host thread, or the caller serialises the calls).
+ *   - Solves run in slots: per-solve device memory, state and reduction
+ *     scratch. Running solves of the same grid shape, precision and
+ *     check_every share every kernel launch; a solve's arithmetic does not
+ *     depend on the other slots of its launches, so it returns the same bits
+ *     alone, in a batch and under serving.
  */
 #ifndef GS_H
 #define GS_H
@@ -42,8 +48,10 @@ extern "C" {
 #define GS_ENOMEM (-2)       /* device allocation failed */
 #define GS_EDEVICE (-3)      /* HIP runtime error */
 #define GS_ENONFINITE (-4)   /* NaN or Inf in the input or during the iteration */
+#define GS_ECANCELED (-5)    /* request cancelled before it completed */
 #define GS_WMAXITER 1        /* max_iter reached before the stopping criterion */
 #define GS_WSTAGNATED 2      /* no descent step found: rounding floor reached */
+#define GS_PENDING 16        /* gs_poll: the request has not completed yet (not an outcome) */
 
 /* stopping criteria (Sec. 3.4) */
 #define GS_STOP_ENERGY 0     /* |E(Phi^{n+1}) - E(Phi^n)| < tol, eq. (3.11) */
@@ -116,7 +124,23 @@ typedef struct {
     double wall_s;        /* wall time of the call */
 } gs_result;
 
-/* Create a context on HIP device `device`. Returns GS_OK and *out, or an error. */
+/* One solve request of the batch and serving entry points. The trap's V (host)
+ * is copied at submission. d_psi0: device complex128 [3][Nz][Ny][Nx] initial
+ * guess, or NULL for the Gaussian guess (a, a, a)/sqrt(3) of Sec. 4; it is read
+ * when the request is admitted. d_psi_out: device complex128, same shape,
+ * written when the request completes. Both stay owned by the caller and must
+ * remain valid until the request has completed (or was cancelled). */
+typedef struct {
+    gs_grid grid;
+    gs_trap trap;
+    gs_params params;
+    gs_options options;
+    const void* d_psi0;
+    void* d_psi_out;
+} gs_request;
+
+/* Create a context on HIP device `device`. Returns GS_OK and *out, or an error.
+ * The device-memory budget for solves starts at 90% of the free memory. */
 int gs_create(gs_ctx** out, int device);
 /* Release the context and all device memory it owns. NULL is ignored. */
 void gs_destroy(gs_ctx* ctx);
@@ -128,6 +152,15 @@ void gs_default_options(gs_options* o);
  * both the float and the double working sets). 0 for an invalid grid. */
 size_t gs_footprint_bytes(const gs_grid* g, int precision);
 
+/* Device-memory budget for solve slots (bytes; 0 = 90% of what is free plus
+ * what the context holds). A request is admitted when the footprints
+ * (gs_footprint_bytes, plus V) of all admitted, unfinished requests and its
+ * own fit in the budget; idle slot memory is kept for reuse and released when
+ * a new slot would not fit otherwise. */
+int gs_set_hbm_budget(gs_ctx* ctx, size_t bytes);
+/* Budget, bytes reserved by admitted requests, bytes of slot memory held. */
+int gs_memory_stats(gs_ctx* ctx, size_t* budget, size_t* reserved, size_t* allocated);
+
 /* Ground state from a host initial guess (Algorithm 1). psi0: host complex128
  * [3][Nz][Ny][Nx], or NULL for the Gaussian guess (a, a, a)/sqrt(3) of Sec. 4;
  * it is normalised before the iteration. psi_out: host complex128, same shape,
@@ -137,19 +170,45 @@ int gs_solve(gs_ctx* ctx, const gs_grid* g, const gs_trap* t, const gs_params* p
              const gs_options* o, const double* psi0, double* psi_out, gs_result* res);
 
 /* As gs_solve with device buffers: d_psi0 and d_psi_out are complex128 device
- * arrays (d_psi0 may be NULL for the Gaussian guess); the work runs on
- * `stream` (a hipStream_t; NULL = the null stream). The call returns after
- * the solve has finished (it polls completion flags on the stream). */
+ * arrays (d_psi0 may be NULL for the Gaussian guess). Work already queued on
+ * `stream` (a hipStream_t; NULL = the null stream) is waited for first; the
+ * solve runs on the library's own stream and the call returns after it has
+ * finished, with d_psi_out written. */
 int gs_solve_device(gs_ctx* ctx, const gs_grid* g, const gs_trap* t, const gs_params* p,
                     const gs_options* o, const void* d_psi0, void* d_psi_out, gs_result* res,
                     void* stream);
+
+/* Many solves at once (grids, parameters and precisions may differ): every
+ * request is submitted, then all are run to completion with continuous
+ * batching. res[i] receives request i's result; res[i].status is its return
+ * code (negative for a solve that failed). Returns GS_OK once every request
+ * has completed, or a negative code when a request is invalid (nothing runs)
+ * or the device fails. */
+int gs_batch_solve(gs_ctx* ctx, int nreq, const gs_request* reqs, gs_result* res);
+
+/* Serving. gs_submit validates and queues a request and returns its ticket;
+ * requests are admitted into free slots at chunk boundaries, by footprint,
+ * while earlier ones run (continuous batching). The scheduler advances inside
+ * gs_submit, gs_progress, gs_poll and gs_wait. gs_progress(block) advances it
+ * (block != 0: waits until at least one chunk has completed) and returns the
+ * number of unfinished requests. gs_poll returns GS_PENDING, or the request's
+ * final return code with *res filled (the ticket is then released; res.wall_s
+ * is the time from submission to completion). gs_wait blocks until
+ * completion. gs_cancel marks a request; it ends with GS_ECANCELED at its next
+ * chunk boundary unless it completes first. */
+int gs_submit(gs_ctx* ctx, const gs_request* req, uint64_t* ticket);
+int gs_progress(gs_ctx* ctx, int block);
+int gs_poll(gs_ctx* ctx, uint64_t ticket, gs_result* res);
+int gs_wait(gs_ctx* ctx, uint64_t ticket, gs_result* res);
+int gs_cancel(gs_ctx* ctx, uint64_t ticket);
 
 /* Forward (sign = -1, unnormalised) or inverse (sign = +1, divided by the
  * number of points) discrete Fourier transform of each of the three
  * components of d_in, written to d_out in the same [3][Nz][Ny][Nx] layout
  * with spectral index j_a <-> wavenumber pi p / L_a, p = j (j < n/2) or j - n
  * (Sec. 3.2). Element type: complex128 (GS_FP64) or complex64 (GS_FP32).
- * d_in is not modified. Asynchronous on `stream`. */
+ * d_in is not modified. The call first waits for work already queued on
+ * `stream`, then enqueues the transform on it and returns. */
 int gs_fft(gs_ctx* ctx, const gs_grid* g, int precision, int sign, const void* d_in,
            void* d_out, void* stream);
 
@@ -163,7 +222,7 @@ int gs_hamiltonian(gs_ctx* ctx, const gs_grid* g, const gs_trap* t, const gs_par
 
 /* Combined preconditioner of eq. (3.15): d_out = P_V^{1/2} P_Delta P_V^{1/2} d_r
  * with alpha_l of eq. (3.13) evaluated at d_psi. Element type as for gs_fft.
- * Asynchronous on `stream`. */
+ * Queued on `stream` as for gs_fft (synchronous when the trap has a V). */
 int gs_precondition(gs_ctx* ctx, const gs_grid* g, const gs_trap* t, const gs_params* p,
                     int precision, const void* d_psi, const void* d_r, void* d_out, void* stream);
 
@@ -173,7 +232,7 @@ int gs_precondition(gs_ctx* ctx, const gs_grid* g, const gs_trap* t, const gs_pa
  *   mu reduction, 7 residual, 8 direction reduction, 9 step-size reduction,
  *   10/11 the second forward / inverse passes of a 3D H_L application.
  * gs_kernel_timer_start(ctx, kind) makes later solves on ctx bracket every
- * launch of that kernel with HIP events on the solve's stream (kind -1: off)
+ * launch of that kernel with HIP events on the launch's stream (kind -1: off)
  * and resets the totals; gs_kernel_timer_read returns the summed elapsed time
  * (ms), the summed algorithmic bytes (each array the kernel reads or writes
  * counted once) and the number of launches timed. Launches that return at

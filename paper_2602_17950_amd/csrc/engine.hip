@@ -1,15 +1,25 @@
-// Host side of the gfx950 ground-state library: per-grid plans (device
-// buffers and twiddle tables), the kernel sequence of one PCG iteration, the
-// solve driver (chunks of iterations between completion checks, FP32 -> FP64
-// switch) and the C ABI of include/gs.h.
+// Host side of the gfx950 ground-state library.
+//
+// Every solve occupies one slot: a block of device memory holding its fields,
+// scratch and partial sums, plus a SolveState and completion counters. Slots
+// of the same grid shape, precision and chunk length form a class; each
+// kernel of the iteration is launched once for all running slots of a class
+// (blockIdx.y = slot), on the class's own stream. A host-side scheduler admits
+// requests by device-memory footprint, enqueues chunks of iterations between
+// completion checks, hands mixed-precision solves from the float class to the
+// double class, runs the final evaluation of finished solves and retires them.
+// A slot's arithmetic does not depend on which other slots share its launches,
+// so a solve gives the same bits alone and in a batch.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <memory>
 #include <string>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "gs_internal.h"
@@ -51,9 +61,21 @@ static long long npts(const gs_grid* g) {
     return m;
 }
 
-// Scratch of the FFT chains: two six-component buffers (P^ and Phi transformed
-// together) and four single fields.
-constexpr int SCRATCH_FIELDS = 8;
+static int check_options(const gs_options* o) {
+    if (!o) return fail(GS_EINVAL, "options is NULL");
+    if (o->stop_kind < 0 || o->stop_kind > 2) return fail(GS_EINVAL, "options.stop_kind invalid");
+    if (!(o->tol >= 0.0)) return fail(GS_EINVAL, "options.tol must be >= 0");
+    if (o->max_iter < 0) return fail(GS_EINVAL, "options.max_iter must be >= 0");
+    if (o->precision < GS_FP64 || o->precision > GS_MIXED) return fail(GS_EINVAL, "options.precision invalid");
+    if (!(o->sigma > 0.0 && o->sigma < 1.0)) return fail(GS_EINVAL, "options.sigma must be in (0, 1)");
+    if (!(o->theta_trial > 0.0)) return fail(GS_EINVAL, "options.theta_trial must be positive");
+    if (o->max_backtrack < 0) return fail(GS_EINVAL, "options.max_backtrack must be >= 0");
+    if (o->check_every < 1) return fail(GS_EINVAL, "options.check_every must be >= 1");
+    return GS_OK;
+}
+
+// slots per class (bounded by the launch grid's y extent and the state arrays)
+constexpr int CLASS_CAP = 4096;
 
 // rows of per-block partial sums: the pointwise grid and the preconditioner's
 // last pass (3 * Nz * Ny / TILE blocks with TILE >= 2)
@@ -66,43 +88,85 @@ static long long mid_rows(const gs_grid* g) {
     const int Nlast = g->n[g->dim - 1];
     return mid_blocks(Nlast, (int)(npts(g) / Nlast));
 }
-
-template <typename R> static size_t plan_bytes(const gs_grid* g) {
-    const long long M = npts(g);
-    const size_t field = (size_t)3 * M * sizeof(cpx<R>);
-    return field * (8 + SCRATCH_FIELDS) + (size_t)3 * M * sizeof(R) +
-           (size_t)(pw_rows(g) * NS_MAX + mid_rows(g) * RED_MID_STRIDE) * sizeof(double);
+static RedGeom red_geom(const gs_grid* g) {
+    RedGeom r;
+    r.nblk_mid = (int)mid_rows(g);
+    r.nblk_pw = pw_blocks(npts(g));
+    return r;
 }
 
-// ---------------------------------------------------------------------------
-// plans
-// ---------------------------------------------------------------------------
+static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Device memory of one slot: 12 three-component fields (Phi, H_L Phi, r^n,
+// r^{n-1}, Pr, P, H_L P^, u, four scratch), two six-component scratch fields,
+// the P_V^{1/2} factors and the partial-sum rows.
+template <typename R> static size_t slot_buffer_bytes(const gs_grid* g) {
+    const long long M = npts(g);
+    const size_t field = al256((size_t)3 * M * sizeof(cpx<R>));
+    return field * 16 + al256((size_t)3 * M * sizeof(R)) + al256((size_t)pw_rows(g) * NS_MAX * sizeof(double)) +
+           al256((size_t)mid_rows(g) * RED_MID_STRIDE * sizeof(double));
+}
+template <typename R> static size_t slot_bytes(const gs_grid* g) {
+    return slot_buffer_bytes<R>(g) + sizeof(SolveState) + NCOUNTERS * sizeof(unsigned) + sizeof(Slot<R>);
+}
+
 template <typename R>
-struct Plan {
-    int dim = 0, n[3] = {1, 1, 1};
-    long long M = 0;
-    std::vector<void*> allocs;
-    Fields<R> f{};
-    cpx<R>* t6[2] = {};   // [6][M] each
-    cpx<R>* t[4] = {};    // [3][M] each
-    const cpx<R>* tw[3] = {};
-    double* red_mid = nullptr;
+struct SlotMem {
+    void* base = nullptr;
+    size_t bytes = 0;
+    cpx<R>* buf[NBUF] = {};
+    R* pv = nullptr;
     double* red_pw = nullptr;
-    int nblk_mid = 0;
-    ~Plan() {
-        for (void* p : allocs) (void)hipFree(p);
+    double* red_mid = nullptr;
+    ~SlotMem() {
+        if (base) (void)hipFree(base);
     }
 };
 
-// Optional per-kernel timer: every launch of one kernel kind of the iteration
-// records its own start and end (dispatch timestamps, hipExtLaunchKernelGGL)
-// into HIP events on the solve's stream; the elapsed times and the kernel's
-// algorithmic bytes (each distinct array read or written once) are summed. Launches that return at once because the solve has finished (the
-// tail of the last chunk) are left out.
+template <typename R>
+static int alloc_slot_mem(const gs_grid* g, hipStream_t s, std::unique_ptr<SlotMem<R>>& out) {
+    auto m = std::make_unique<SlotMem<R>>();
+    const long long M = npts(g);
+    const size_t field = al256((size_t)3 * M * sizeof(cpx<R>));
+    m->bytes = slot_buffer_bytes<R>(g);
+    if (hipMalloc(&m->base, m->bytes) != hipSuccess) {
+        m->base = nullptr;
+        (void)hipGetLastError();   // do not leave the failure to the next launch check
+        return fail(GS_ENOMEM, "device allocation failed (slot)");
+    }
+    char* p = (char*)m->base;
+    for (int b = 0; b < B_X0; ++b) {
+        m->buf[b] = (cpx<R>*)p;
+        p += (b == B_T6A || b == B_T6B) ? 2 * field : field;
+    }
+    m->pv = (R*)p;
+    p += al256((size_t)3 * M * sizeof(R));
+    m->red_pw = (double*)p;
+    p += al256((size_t)pw_rows(g) * NS_MAX * sizeof(double));
+    m->red_mid = (double*)p;
+    HIPCHK(hipMemsetAsync(m->base, 0, m->bytes, s));
+    out = std::move(m);
+    return GS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// per-kernel timer
+// ---------------------------------------------------------------------------
+// Every launch of one kernel kind of the iteration records its own start and
+// end (dispatch timestamps, hipExtLaunchKernelGGL) into HIP events on the
+// class's stream; elapsed times and the kernel's algorithmic bytes (each
+// distinct array read or written once, times the slots of the launch) are
+// summed. Launches that return at once because every solve of the launch has
+// finished (the tail of the last chunk) are left out.
 enum KKind : int {
     KK_HL_FWD = 0, KK_HL_MID = 1, KK_HL_INV = 2, KK_PRE_FWD = 3, KK_PRE_MID = 4, KK_PRE_INV = 5,
     KK_EVAL = 6, KK_RESID = 7, KK_DIRRED = 8, KK_LSRED = 9, KK_HL_FWD2 = 10, KK_HL_INV2 = 11,
     KK_COUNT = 12
+};
+struct TimerTotals {
+    int kind = -1;
+    double ms = 0.0, bytes = 0.0;
+    long long launches = 0;
 };
 struct Timer {
     int kind = -1;
@@ -111,8 +175,6 @@ struct Timer {
     std::vector<Rec> rec;
     int iter_in_chunk = 0;
     int chain = 0;
-    double ms = 0.0, bytes = 0.0;
-    long long launches = 0;
     ~Timer() {
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     }
@@ -140,128 +202,28 @@ static hipError_t timed(Timer* tm, int kind, double bytes, hipStream_t s, F&& f)
     return e;
 }
 
-// After a chunk has completed: n_full iterations ran to the end; when the solve
-// finished in the chunk, the refresh (chain 0) and the residual pass (chain 1)
-// of iteration n_full also ran.
-static hipError_t timer_collect(Timer* tm, int n_full, bool done) {
-    if (!tm) return hipSuccess;
-    for (size_t i = 0; i < tm->rec.size(); ++i) {
-        const Timer::Rec& r = tm->rec[i];
+// After a chunk has completed: iterations below n_full ran for some slot; when
+// every slot finished in the chunk, the refresh (chain 0) and the residual pass
+// (chain 1) of iteration n_full also ran.
+static hipError_t timer_collect(Timer& tm, TimerTotals& tot, int n_full, bool done) {
+    for (size_t i = 0; i < tm.rec.size(); ++i) {
+        const Timer::Rec& r = tm.rec[i];
         if (!(r.k < n_full || (done && r.k == n_full && r.chain <= 1))) continue;
         float ms = 0.0f;
-        hipError_t e = hipEventElapsedTime(&ms, tm->ev[2 * i], tm->ev[2 * i + 1]);
+        hipError_t e = hipEventElapsedTime(&ms, tm.ev[2 * i], tm.ev[2 * i + 1]);
         if (e != hipSuccess) return e;
-        tm->ms += ms;
-        tm->bytes += r.bytes;
-        tm->launches++;
+        tot.ms += ms;
+        tot.bytes += r.bytes;
+        tot.launches++;
     }
-    tm->rec.clear();
+    tm.rec.clear();
     return hipSuccess;
 }
 
-struct Ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    std::map<std::tuple<int, int, int, int>, std::unique_ptr<Plan<double>>> p64;
-    std::map<std::tuple<int, int, int, int>, std::unique_ptr<Plan<float>>> p32;
-    std::map<std::pair<int, int>, void*> twiddles;   // (N, sizeof(R)) -> table
-    SolveState* st = nullptr;       // device
-    SolveState* st_host = nullptr;  // pinned host mirror
-    unsigned* counters = nullptr;
-    double* Vdev = nullptr;
-    size_t Vbytes = 0;
-    std::vector<void*> allocs;
-    Timer timer;
-    ~Ctx() {
-        (void)hipSetDevice(device);
-        p64.clear();
-        p32.clear();
-        for (auto& kv : twiddles) (void)hipFree(kv.second);
-        for (void* p : allocs) (void)hipFree(p);
-        if (Vdev) (void)hipFree(Vdev);
-        if (st_host) (void)hipHostFree(st_host);
-        if (stream) (void)hipStreamDestroy(stream);
-    }
-};
-
-template <typename R>
-static int get_twiddle(Ctx& cx, int N, const cpx<R>** out) {
-    auto key = std::make_pair(N, (int)sizeof(R));
-    auto it = cx.twiddles.find(key);
-    if (it != cx.twiddles.end()) {
-        *out = (const cpx<R>*)it->second;
-        return GS_OK;
-    }
-    std::vector<cpx<R>> h(N);
-    for (int m = 0; m < N; ++m) {
-        const long double ang = 2.0L * 3.14159265358979323846264338327950288L * (long double)m / (long double)N;
-        h[m] = cpx<R>{(R)cosl(ang), (R)(-sinl(ang))};
-    }
-    void* d = nullptr;
-    if (hipMalloc(&d, sizeof(cpx<R>) * N) != hipSuccess) return fail(GS_ENOMEM, "twiddle table allocation failed");
-    HIPCHK(hipMemcpy(d, h.data(), sizeof(cpx<R>) * N, hipMemcpyHostToDevice));
-    cx.twiddles[key] = d;
-    *out = (const cpx<R>*)d;
-    return GS_OK;
-}
-
-template <typename R> static auto& plans(Ctx& cx);
-template <> auto& plans<double>(Ctx& cx) { return cx.p64; }
-template <> auto& plans<float>(Ctx& cx) { return cx.p32; }
-
-template <typename R>
-static int get_plan(Ctx& cx, const gs_grid* g, Plan<R>** out) {
-    auto key = std::make_tuple(g->dim, g->n[0], g->n[1], g->dim == 3 ? g->n[2] : 1);
-    auto& mp = plans<R>(cx);
-    auto it = mp.find(key);
-    if (it != mp.end()) {
-        *out = it->second.get();
-        return GS_OK;
-    }
-    auto pl = std::make_unique<Plan<R>>();
-    pl->dim = g->dim;
-    pl->n[0] = g->n[0];
-    pl->n[1] = g->n[1];
-    pl->n[2] = g->dim == 3 ? g->n[2] : 1;
-    pl->M = npts(g);
-    const size_t field = (size_t)3 * pl->M * sizeof(cpx<R>);
-    auto alloc = [&](size_t bytes, void** p) -> bool {
-        if (hipMalloc(p, bytes) != hipSuccess) return false;
-        pl->allocs.push_back(*p);
-        return hipMemset(*p, 0, bytes) == hipSuccess;
-    };
-    void* p = nullptr;
-    cpx<R>** fl[] = {&pl->f.phi, &pl->f.hl, &pl->f.r[0], &pl->f.r[1], &pl->f.pr, &pl->f.P, &pl->f.hlp, &pl->f.u};
-    for (auto* q : fl) {
-        if (!alloc(field, &p)) return fail(GS_ENOMEM, "device allocation failed (fields)");
-        *q = (cpx<R>*)p;
-    }
-    if (!alloc((size_t)3 * pl->M * sizeof(R), &p)) return fail(GS_ENOMEM, "device allocation failed (pv)");
-    pl->f.pv = (R*)p;
-    for (int k = 0; k < 2; ++k) {
-        if (!alloc(2 * field, &p)) return fail(GS_ENOMEM, "device allocation failed (scratch)");
-        pl->t6[k] = (cpx<R>*)p;
-    }
-    for (int k = 0; k < 4; ++k) {
-        if (!alloc(field, &p)) return fail(GS_ENOMEM, "device allocation failed (scratch)");
-        pl->t[k] = (cpx<R>*)p;
-    }
-    // the middle pass runs along the last axis; its lines are the other points
-    pl->nblk_mid = (int)mid_rows(g);
-    if (!alloc((size_t)pl->nblk_mid * RED_MID_STRIDE * sizeof(double), &p)) return fail(GS_ENOMEM, "device allocation failed (reductions)");
-    pl->red_mid = (double*)p;
-    if (!alloc((size_t)pw_rows(g) * NS_MAX * sizeof(double), &p)) return fail(GS_ENOMEM, "device allocation failed (reductions)");
-    pl->red_pw = (double*)p;
-    for (int a = 0; a < g->dim; ++a) {
-        int rc = get_twiddle<R>(cx, pl->n[a], &pl->tw[a]);
-        if (rc) return rc;
-    }
-    *out = pl.get();
-    mp[key] = std::move(pl);
-    return GS_OK;
-}
-
-static int make_phys(Ctx& cx, const gs_grid* g, const gs_trap* t, const gs_params* p, Phys* ph) {
+// ---------------------------------------------------------------------------
+// problem description
+// ---------------------------------------------------------------------------
+static int make_phys(const gs_grid* g, const gs_trap* t, const gs_params* p, Phys* ph) {
     std::memset(ph, 0, sizeof(*ph));
     ph->dim = g->dim;
     ph->n[0] = g->n[0];
@@ -275,31 +237,23 @@ static int make_phys(Ctx& cx, const gs_grid* g, const gs_trap* t, const gs_param
     }
     ph->M = npts(g);
     if (p) {
+        if (!std::isfinite(p->omega) || !std::isfinite(p->gamma) || !std::isfinite(p->c0) || !std::isfinite(p->c1))
+            return fail(GS_EINVAL, "params must be finite");
         ph->omega = p->omega;
         ph->gamma = p->gamma;
         ph->c0 = p->c0;
         ph->c1 = p->c1;
-        if (!std::isfinite(p->omega) || !std::isfinite(p->gamma) || !std::isfinite(p->c0) || !std::isfinite(p->c1))
-            return fail(GS_EINVAL, "params must be finite");
     }
     if (t) {
         for (int a = 0; a < 3; ++a) ph->hg[a] = a < g->dim ? 0.5 * t->g[a] * t->g[a] : 0.0;
         ph->q2 = t->q2;
         ph->q4 = t->q4;
-        if (t->V) {
-            const size_t bytes = sizeof(double) * ph->M;
+        if (!std::isfinite(t->q2) || !std::isfinite(t->q4)) return fail(GS_EINVAL, "trap must be finite");
+        for (int a = 0; a < g->dim; ++a)
+            if (!std::isfinite(t->g[a])) return fail(GS_EINVAL, "trap must be finite");
+        if (t->V)
             for (long long i = 0; i < ph->M; ++i)
                 if (!std::isfinite(t->V[i])) return fail(GS_EINVAL, "trap.V must be finite");
-            if (cx.Vbytes < bytes) {
-                if (cx.Vdev) (void)hipFree(cx.Vdev);
-                cx.Vdev = nullptr;
-                cx.Vbytes = 0;
-                if (hipMalloc(&cx.Vdev, bytes) != hipSuccess) return fail(GS_ENOMEM, "device allocation failed (V)");
-                cx.Vbytes = bytes;
-            }
-            HIPCHK(hipMemcpy(cx.Vdev, t->V, bytes, hipMemcpyHostToDevice));
-            ph->V = cx.Vdev;
-        }
     } else {
         ph->hg[0] = ph->hg[1] = 0.5;
         ph->hg[2] = g->dim == 3 ? 0.5 : 0.0;
@@ -307,124 +261,6 @@ static int make_phys(Ctx& cx, const gs_grid* g, const gs_trap* t, const gs_param
     return GS_OK;
 }
 
-template <typename R>
-static RedBuf redbuf(Ctx& cx, const Plan<R>& pl) {
-    RedBuf rb;
-    rb.mid = pl.red_mid;
-    rb.pw = pl.red_pw;
-    rb.counter = cx.counters;
-    rb.nblk_mid = pl.nblk_mid;
-    rb.nblk_pw = pw_blocks(pl.M);
-    return rb;
-}
-
-// ---------------------------------------------------------------------------
-// operator chains
-// ---------------------------------------------------------------------------
-// out = H_L in  (H_L = -1/2 Lap + V - Omega L_z - gamma S), with the prologue
-// `pro` applied to `in` first (see launch_fwdT). dual (with PRO_DIR): aux1 (Phi)
-// is transformed with in, and the middle pass reduces the kinetic coefficients
-// of both for the next iterate's alpha_l.
-template <typename R>
-static hipError_t chain_HL(Plan<R>& pl, const Phys& ph, int pro, int dual, cpx<R>* in, cpx<R>* out,
-                           const cpx<R>* aux0, const cpx<R>* aux1, int use_invnP,
-                           const SolveState* st, hipStream_t s, Timer* tm = nullptr) {
-    const int rot = ph.omega != 0.0;
-    const int Nx = pl.n[0], Ny = pl.n[1], Nz = pl.n[2];
-    const long long M3 = 3 * pl.M;
-    const double F = 3.0 * pl.M * sizeof(cpx<R>);
-    const double b_fwd = dual ? 6 * F : (pro == PRO_DIR ? 5 * F : (pro == PRO_UPDATE ? 4 * F : 2 * F));
-    const double b_mid = (rot ? 2 : 1) * F + (dual ? 2 : 1) * F, b_inv = (rot ? 4 : 3) * F;
-    const int midop = dual ? MID_HLX : MID_HL;
-    cpx<R>* S0 = pl.t6[0];
-    cpx<R>* S1 = pl.t6[1];
-    hipError_t e;
-    if (pl.dim == 2) {
-        if ((e = timed(tm, KK_HL_FWD, b_fwd, s, [&] { return launch_fwdT<R>(Nx, pro, dual, in, S0, 1, Ny, 3, aux0, aux1, st, pl.tw[0], s); }))) return e;
-        if ((e = timed(tm, KK_HL_MID, b_mid, s, [&] { return launch_mid<R>(Ny, midop, rot, S0, S0 + M3, pl.t[0], pl.t[1], Nx, ph, st, pl.red_mid, pl.tw[1], s); }))) return e;
-        return timed(tm, KK_HL_INV, b_inv, s, [&] {
-            return launch_invT<R>(Nx, EPI_HL, rot ? 2 : 1, pl.t[0], pl.t[1], out, nullptr, 1, Ny, ph, in, 1.0,
-                                  nullptr, st, use_invnP, pl.tw[0], s); });
-    }
-    const int nc = dual ? 6 : 3;
-    if ((e = timed(tm, KK_HL_FWD, b_fwd, s, [&] { return launch_fwdT<R>(Nx, pro, dual, in, S0, Nz, Ny, 3, aux0, aux1, st, pl.tw[0], s); }))) return e;
-    if ((e = timed(tm, KK_HL_FWD2, 2 * (nc / 3) * F, s, [&] { return launch_fwdT<R>(Ny, PRO_PLAIN, 0, S0, S1, Nx, Nz, nc, nullptr, nullptr, st, pl.tw[1], s); }))) return e;
-    if ((e = timed(tm, KK_HL_MID, b_mid, s, [&] { return launch_mid<R>(Nz, midop, rot, S1, S1 + M3, pl.t[0], pl.t[1], Ny * Nx, ph, st, pl.red_mid, pl.tw[2], s); }))) return e;
-    if ((e = timed(tm, KK_HL_INV2, (rot ? 5 : 2) * F, s, [&] {
-             return launch_invT<R>(Ny, rot ? EPI_ROTX : EPI_SCALE, rot ? 2 : 1, pl.t[0], pl.t[1], pl.t[2], pl.t[3], Nx, Nz,
-                                   ph, S0, 1.0, nullptr, st, 0, pl.tw[1], s); }))) return e;
-    return timed(tm, KK_HL_INV, b_inv, s, [&] {
-        return launch_invT<R>(Nx, EPI_HL, rot ? 2 : 1, pl.t[2], pl.t[3], out, nullptr, Nz, Ny, ph, in, 1.0, nullptr,
-                              st, use_invnP, pl.tw[0], s); });
-}
-
-// pr = P_V^{1/2} P_Delta P_V^{1/2} r (the first factor is already applied: input in f.u);
-// dir = 1 fuses the direction reductions and control into the last pass
-template <typename R>
-static hipError_t chain_pre(Plan<R>& pl, const Phys& ph, SolveState* st, RedBuf rb, int dir, hipStream_t s,
-                            Timer* tm = nullptr) {
-    const int Nx = pl.n[0], Ny = pl.n[1], Nz = pl.n[2];
-    const double F = 3.0 * pl.M * sizeof(cpx<R>), Fr = 3.0 * pl.M * sizeof(R);
-    const double b_inv = (dir ? 6 : 2) * F + Fr;
-    cpx<R>* S0 = pl.t6[0];
-    cpx<R>* S1 = pl.t6[1];
-    hipError_t e;
-    if (pl.dim == 2) {
-        if ((e = timed(tm, KK_PRE_FWD, 2 * F, s, [&] { return launch_fwdT<R>(Nx, PRO_PLAIN, 0, pl.f.u, S0, 1, Ny, 3, nullptr, nullptr, st, pl.tw[0], s); }))) return e;
-        if ((e = timed(tm, KK_PRE_MID, 2 * F, s, [&] { return launch_mid<R>(Ny, MID_PRE, 0, S0, nullptr, pl.t[0], nullptr, Nx, ph, st, nullptr, pl.tw[1], s); }))) return e;
-        return timed(tm, KK_PRE_INV, b_inv, s, [&] {
-            return launch_invT_pre<R>(Nx, pl.t[0], pl.f.pr, 1, Ny, pl.f.pv, pl.f, ph, st, rb, dir, pl.tw[0], s); });
-    }
-    if ((e = timed(tm, KK_PRE_FWD, 2 * F, s, [&] { return launch_fwdT<R>(Nx, PRO_PLAIN, 0, pl.f.u, S0, Nz, Ny, 3, nullptr, nullptr, st, pl.tw[0], s); }))) return e;
-    if ((e = launch_fwdT<R>(Ny, PRO_PLAIN, 0, S0, S1, Nx, Nz, 3, nullptr, nullptr, st, pl.tw[1], s))) return e;
-    if ((e = timed(tm, KK_PRE_MID, 2 * F, s, [&] { return launch_mid<R>(Nz, MID_PRE, 0, S1, nullptr, pl.t[0], nullptr, Ny * Nx, ph, st, nullptr, pl.tw[2], s); }))) return e;
-    if ((e = launch_invT<R>(Ny, EPI_SCALE, 1, pl.t[0], nullptr, pl.t[1], nullptr, Nx, Nz, ph, nullptr, 1.0, nullptr,
-                            st, 0, pl.tw[1], s))) return e;
-    return timed(tm, KK_PRE_INV, b_inv, s, [&] {
-        return launch_invT_pre<R>(Nx, pl.t[1], pl.f.pr, Nz, Ny, pl.f.pv, pl.f, ph, st, rb, dir, pl.tw[0], s); });
-}
-
-// Fresh evaluation of the current iterate: apply a pending update to Phi,
-// H_L Phi from scratch, energy parts, mu, alpha_l.
-template <typename R>
-static hipError_t refresh(Plan<R>& pl, const Phys& ph, SolveState* st, RedBuf rb, int force, hipStream_t s, Timer* tm) {
-    const double F = 3.0 * pl.M * sizeof(cpx<R>);
-    hipError_t e;
-    if ((e = chain_HL<R>(pl, ph, PRO_UPDATE, 0, pl.f.phi, pl.f.hl, pl.f.P, nullptr, 0, st, s, tm))) return e;
-    return timed(tm, KK_EVAL, 2 * F, s, [&] { return launch_eval<R>(pl.f, ph, st, rb, force, s); });
-}
-
-// One PCG iteration (Algorithm 1 with Algorithm 2), entirely on the device:
-//   0. (first iteration of a chunk) fresh H_L Phi, E, mu, alpha_l
-//   1. pending update Phi <- (c Phi + s P^)/|.|, H_L Phi by the same combination;
-//      r = H(Phi)Phi - mu Phi, P_V^{1/2} factors, stopping tests
-//   2. preconditioned residual (3 or 5 FFT passes) with the PRP beta,
-//      projection and descent test fused into its last pass
-//   3. P^n = D - Re<D,Phi> Phi, H_L P^ (3 or 5 FFT passes; Phi transformed
-//      alongside for the kinetic coefficients)
-//   4. energy along the retraction, step size, backtracking, and the scalars
-//      (mu, E, alpha_l) of the next iterate
-template <typename R>
-static hipError_t iterate(Plan<R>& pl, const Phys& ph, SolveState* st, RedBuf rb, int do_refresh, hipStream_t s,
-                          Timer* tm) {
-    const double F = 3.0 * pl.M * sizeof(cpx<R>), Fr = 3.0 * pl.M * sizeof(R);
-    hipError_t e;
-    if (do_refresh) {
-        if (tm) tm->chain = 0;
-        if ((e = refresh<R>(pl, ph, st, rb, 0, s, tm))) return e;
-    }
-    if (tm) tm->chain = 1;
-    if ((e = timed(tm, KK_RESID, 8 * F + Fr, s, [&] { return launch_resid<R>(pl.f, ph, st, rb, 0, s); }))) return e;
-    if (tm) tm->chain = 2;
-    if ((e = chain_pre<R>(pl, ph, st, rb, 1, s, tm))) return e;
-    if (tm) tm->chain = 3;
-    if ((e = chain_HL<R>(pl, ph, PRO_DIR, 1, pl.f.P, pl.f.hlp, pl.f.pr, pl.f.phi, 1, st, s, tm))) return e;
-    return timed(tm, KK_LSRED, 4 * F, s, [&] { return launch_lsred<R>(pl.f, ph, st, rb, s); });
-}
-
-// ---------------------------------------------------------------------------
-// solve driver
-// ---------------------------------------------------------------------------
 static void init_state(SolveState* h, const gs_options* o, int phase) {
     std::memset(h, 0, sizeof(*h));
     h->status = GS_OK;
@@ -443,254 +279,926 @@ static void init_state(SolveState* h, const gs_options* o, int phase) {
     h->c = 1.0;
 }
 
-static int check_options(const gs_options* o) {
-    if (!o) return fail(GS_EINVAL, "options is NULL");
-    if (o->stop_kind < 0 || o->stop_kind > 2) return fail(GS_EINVAL, "options.stop_kind invalid");
-    if (!(o->tol >= 0.0)) return fail(GS_EINVAL, "options.tol must be >= 0");
-    if (o->max_iter < 0) return fail(GS_EINVAL, "options.max_iter must be >= 0");
-    if (o->precision < GS_FP64 || o->precision > GS_MIXED) return fail(GS_EINVAL, "options.precision invalid");
-    if (!(o->sigma > 0.0 && o->sigma < 1.0)) return fail(GS_EINVAL, "options.sigma must be in (0, 1)");
-    if (!(o->theta_trial > 0.0)) return fail(GS_EINVAL, "options.theta_trial must be positive");
-    if (o->max_backtrack < 0) return fail(GS_EINVAL, "options.max_backtrack must be >= 0");
-    if (o->check_every < 1) return fail(GS_EINVAL, "options.check_every must be >= 1");
-    return GS_OK;
-}
-
-// Iterate one precision phase to its end. Chunks of check_every iterations are
-// enqueued between host checks; each chunk starts with a fresh evaluation of
-// H_L Phi and the scalars, which also bounds the rounding drift of the
-// H_L Phi recurrence. Unless the phase ends in a precision switch, a final
-// fresh evaluation fills E, its parts, mu, mu_l and the residual of the result.
-template <typename R>
-static int run_phase(Ctx& cx, Plan<R>& pl, const Phys& ph, int check_every, hipStream_t s) {
-    RedBuf rb = redbuf(cx, pl);
-    HIPCHK(launch_normalize<R>(pl.f.phi, ph, cx.st, rb, s));
-    Timer* tm = cx.timer.kind >= 0 ? &cx.timer : nullptr;
-    int last_iter = -1;
-    for (;;) {
-        const int iter0 = cx.st_host->iter;
-        for (int k = 0; k < check_every; ++k) {
-            if (tm) tm->iter_in_chunk = k;
-            HIPCHK(iterate<R>(pl, ph, cx.st, rb, k == 0, s, tm));
-        }
-        HIPCHK(hipMemcpyAsync(cx.st_host, cx.st, sizeof(SolveState), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        HIPCHK(timer_collect(tm, cx.st_host->iter - iter0, cx.st_host->done != 0));
-        if (cx.st_host->done) break;
-        // every iteration either accepts a step or ends the solve
-        if (cx.st_host->iter == last_iter) return fail(GS_EDEVICE, "solver made no progress (device state not updated)");
-        last_iter = cx.st_host->iter;
-    }
-    if (!cx.st_host->switch_req) {
-        // the kernels run while done == 0; restore the flag afterwards
-        static const int zero = 0;
-        HIPCHK(hipMemcpyAsync(&cx.st->done, &zero, sizeof(int), hipMemcpyHostToDevice, s));
-        HIPCHK(refresh<R>(pl, ph, cx.st, rb, 1, s, nullptr));
-        HIPCHK(launch_resid<R>(pl.f, ph, cx.st, rb, 1, s));
-        HIPCHK(hipMemcpyAsync(cx.st_host, cx.st, sizeof(SolveState), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        cx.st_host->done = 1;
-    }
-    return GS_OK;
-}
-
 static void fill_result(const SolveState* h, gs_result* r, int iters_fp32, double wall) {
     if (!r) return;
     std::memset(r, 0, sizeof(*r));
-    r->E = h->E;
-    r->mu = h->mu;
-    for (int c = 0; c < 3; ++c) {
-        r->mu_comp[c] = h->mu_comp[c];
-        r->norm_comp[c] = h->norm_comp[c];
+    if (h) {
+        r->E = h->E;
+        r->mu = h->mu;
+        for (int c = 0; c < 3; ++c) {
+            r->mu_comp[c] = h->mu_comp[c];
+            r->norm_comp[c] = h->norm_comp[c];
+        }
+        r->e_kin = h->e_kin;
+        r->e_pot = h->e_pot;
+        r->e_rot = h->e_rot;
+        r->e_spin = h->e_spin;
+        r->e_soc = h->e_soc;
+        r->virial = h->virial;
+        r->resid_inf = h->resid_inf;
+        r->dE_last = h->dE_last;
+        r->iters = h->iter;
+        r->backtracks = h->backtracks;
+        r->resets = h->resets;
+        r->status = h->status;
     }
-    r->e_kin = h->e_kin;
-    r->e_pot = h->e_pot;
-    r->e_rot = h->e_rot;
-    r->e_spin = h->e_spin;
-    r->e_soc = h->e_soc;
-    r->virial = h->virial;
-    r->resid_inf = h->resid_inf;
-    r->dE_last = h->dE_last;
-    r->iters = h->iter;
     r->iters_fp32 = iters_fp32;
-    r->backtracks = h->backtracks;
-    r->resets = h->resets;
-    r->status = h->status;
     r->wall_s = wall;
 }
 
-static int solve_impl(Ctx& cx, const gs_grid* g, const gs_trap* t, const gs_params* p, const gs_options* o,
-                      const cpx<double>* d_psi0, cpx<double>* d_out, gs_result* res, hipStream_t s) {
-    const auto t0 = std::chrono::steady_clock::now();
-    int rc;
-    if ((rc = check_grid(g))) return rc;
-    if ((rc = check_options(o))) return rc;
-    if (!p) return fail(GS_EINVAL, "params is NULL");
-    HIPCHK(hipSetDevice(cx.device));
-    Phys ph;
-    if ((rc = make_phys(cx, g, t, p, &ph))) return rc;
-    const long long n3 = 3 * ph.M;
-    Plan<double>* p64 = nullptr;
-    Plan<float>* p32 = nullptr;
-    const bool use32 = o->precision != GS_FP64;
-    const bool use64 = o->precision != GS_FP32;
-    if (use64 && (rc = get_plan<double>(cx, g, &p64))) return rc;
-    if (use32 && (rc = get_plan<float>(cx, g, &p32))) return rc;
+// ---------------------------------------------------------------------------
+// operator chains over a launch set of slots
+// ---------------------------------------------------------------------------
+template <typename R>
+struct Geo {
+    int dim = 2, n[3] = {1, 1, 1};
+    long long M = 0;
+    RedGeom g{};
+    const cpx<R>* tw[3] = {};
+    int rot_any = 0;
+};
+template <typename R>
+struct Sub {
+    const Slot<R>* tab;
+    int ns;
+};
 
-    // initial guess into the first phase's Phi (the Gaussian guess is built in
-    // double, then rounded when the first phase is in float)
-    void* tmp = nullptr;
-    const cpx<double>* guess = d_psi0;
-    if (!guess) {
-        cpx<double>* dst = use64 ? p64->f.phi : nullptr;
-        if (!dst) {
-            if (hipMalloc(&tmp, sizeof(cpx<double>) * n3) != hipSuccess) return fail(GS_ENOMEM, "device allocation failed (guess)");
-            dst = (cpx<double>*)tmp;
-        }
-        HIPCHK(launch_gaussian(dst, ph, s));
-        guess = dst;
+// out = H_L in  (H_L = -1/2 Lap + V - Omega L_z - gamma S), with the prologue
+// `pro` applied to `in` first (see launch_fwdT). dual (with PRO_DIR): aux1 (Phi)
+// is transformed with in, and the middle pass reduces the kinetic coefficients
+// of both for the next iterate's alpha_l.
+template <typename R>
+static hipError_t chain_HL(const Geo<R>& G, Sub<R> L, int pro, int dual, int in, int out, int aux0, int aux1,
+                           int use_invnP, hipStream_t s, Timer* tm) {
+    const int rot = G.rot_any;
+    const int Nx = G.n[0], Ny = G.n[1], Nz = G.n[2];
+    const double F = 3.0 * G.M * sizeof(cpx<R>) * L.ns;
+    const double b_fwd = dual ? 6 * F : (pro == PRO_DIR ? 5 * F : (pro == PRO_UPDATE ? 4 * F : 2 * F));
+    const double b_mid = (rot ? 2 : 1) * F + (dual ? 2 : 1) * F, b_inv = (rot ? 4 : 3) * F;
+    const int midop = dual ? MID_HLX : MID_HL;
+    const int outB = rot ? B_T1 : B_NONE;
+    hipError_t e;
+    if (G.dim == 2) {
+        if ((e = timed(tm, KK_HL_FWD, b_fwd, s, [&] { return launch_fwdT<R>(Nx, pro, dual, L.tab, L.ns, in, B_T6A, aux0, aux1, 1, Ny, 3, G.tw[0], s); }))) return e;
+        if ((e = timed(tm, KK_HL_MID, b_mid, s, [&] { return launch_mid<R>(Ny, midop, L.tab, L.ns, B_T6A, B_T0, outB, Nx, rot, G.tw[1], s); }))) return e;
+        return timed(tm, KK_HL_INV, b_inv, s, [&] {
+            return launch_invT<R>(Nx, EPI_HL, L.tab, L.ns, B_T0, B_T1, out, B_NONE, in, 1, Ny, 1.0, use_invnP, rot, G.tw[0], s); });
     }
-    if (use32) HIPCHK(launch_convert_d2f(guess, p32->f.phi, n3, s));
-    else if (guess != p64->f.phi)
-        HIPCHK(hipMemcpyAsync(p64->f.phi, guess, sizeof(cpx<double>) * n3, hipMemcpyDeviceToDevice, s));
-    if (tmp) {
-        HIPCHK(hipStreamSynchronize(s));
-        (void)hipFree(tmp);
-    }
+    const int nc = dual ? 6 : 3;
+    if ((e = timed(tm, KK_HL_FWD, b_fwd, s, [&] { return launch_fwdT<R>(Nx, pro, dual, L.tab, L.ns, in, B_T6A, aux0, aux1, Nz, Ny, 3, G.tw[0], s); }))) return e;
+    if ((e = timed(tm, KK_HL_FWD2, 2 * (nc / 3) * F, s, [&] { return launch_fwdT<R>(Ny, PRO_PLAIN, 0, L.tab, L.ns, B_T6A, B_T6B, B_NONE, B_NONE, Nx, Nz, nc, G.tw[1], s); }))) return e;
+    if ((e = timed(tm, KK_HL_MID, b_mid, s, [&] { return launch_mid<R>(Nz, midop, L.tab, L.ns, B_T6B, B_T0, outB, Ny * Nx, rot, G.tw[2], s); }))) return e;
+    if ((e = timed(tm, KK_HL_INV2, (rot ? 5 : 2) * F, s, [&] {
+             return launch_invT<R>(Ny, rot ? EPI_ROTX : EPI_SCALE, L.tab, L.ns, B_T0, B_T1, B_T2, rot ? B_T3 : B_NONE,
+                                   B_T6A, Nx, Nz, 1.0, 0, rot, G.tw[1], s); }))) return e;
+    return timed(tm, KK_HL_INV, b_inv, s, [&] {
+        return launch_invT<R>(Nx, EPI_HL, L.tab, L.ns, B_T2, B_T3, out, B_NONE, in, Nz, Ny, 1.0, use_invnP, rot, G.tw[0], s); });
+}
 
-    const int phase0 = o->precision == GS_MIXED ? PH_FP32 : PH_FP64;
-    init_state(cx.st_host, o, phase0);
-    HIPCHK(hipMemcpyAsync(cx.st, cx.st_host, sizeof(SolveState), hipMemcpyHostToDevice, s));
-    int iters_fp32 = 0;
-    bool out_from_32 = false;
-    if (use32) {
-        HIPCHK(hipMemsetAsync(p32->f.P, 0, sizeof(cpx<float>) * n3, s));
-        if ((rc = run_phase<float>(cx, *p32, ph, o->check_every, s))) return rc;
-        iters_fp32 = cx.st_host->iter;
-        out_from_32 = true;
-        if (o->precision == GS_MIXED && cx.st_host->switch_req && !cx.st_host->nonfinite) {
-            // warm start of the double phase from the float iterate, beta reset to 0
-            HIPCHK(launch_convert_f2d(p32->f.phi, p64->f.phi, n3, s));
-            SolveState* h = cx.st_host;
-            h->done = 0;
-            h->switch_req = 0;
-            h->phase = PH_FP64;
-            h->have_prev = 0;
-            h->pending_step = 0;
-            h->final_pending = 0;
-            h->iter_phase = 0;
-            h->status = GS_OK;
-            HIPCHK(hipMemcpyAsync(cx.st, h, sizeof(SolveState), hipMemcpyHostToDevice, s));
-            out_from_32 = false;
-        }
+// out = P_V^{1/2} P_Delta P_V^{1/2} r (the first factor is already applied: input in u);
+// dir = 1 fuses the direction reductions and control into the last pass
+template <typename R>
+static hipError_t chain_pre(const Geo<R>& G, Sub<R> L, int dir, int out, hipStream_t s, Timer* tm) {
+    const int Nx = G.n[0], Ny = G.n[1], Nz = G.n[2];
+    const double F = 3.0 * G.M * sizeof(cpx<R>) * L.ns, Fr = 3.0 * G.M * sizeof(R) * L.ns;
+    const double b_inv = (dir ? 6 : 2) * F + Fr;
+    hipError_t e;
+    if (G.dim == 2) {
+        if ((e = timed(tm, KK_PRE_FWD, 2 * F, s, [&] { return launch_fwdT<R>(Nx, PRO_PLAIN, 0, L.tab, L.ns, B_U, B_T6A, B_NONE, B_NONE, 1, Ny, 3, G.tw[0], s); }))) return e;
+        if ((e = timed(tm, KK_PRE_MID, 2 * F, s, [&] { return launch_mid<R>(Ny, MID_PRE, L.tab, L.ns, B_T6A, B_T0, B_NONE, Nx, 0, G.tw[1], s); }))) return e;
+        return timed(tm, KK_PRE_INV, b_inv, s, [&] {
+            return launch_invT_pre<R>(Nx, L.tab, L.ns, B_T0, out, 1, Ny, dir, G.tw[0], s); });
     }
-    if (use64 && !out_from_32) {
-        HIPCHK(hipMemsetAsync(p64->f.P, 0, sizeof(cpx<double>) * n3, s));
-        if ((rc = run_phase<double>(cx, *p64, ph, o->check_every, s))) return rc;
+    if ((e = timed(tm, KK_PRE_FWD, 2 * F, s, [&] { return launch_fwdT<R>(Nx, PRO_PLAIN, 0, L.tab, L.ns, B_U, B_T6A, B_NONE, B_NONE, Nz, Ny, 3, G.tw[0], s); }))) return e;
+    if ((e = launch_fwdT<R>(Ny, PRO_PLAIN, 0, L.tab, L.ns, B_T6A, B_T6B, B_NONE, B_NONE, Nx, Nz, 3, G.tw[1], s))) return e;
+    if ((e = timed(tm, KK_PRE_MID, 2 * F, s, [&] { return launch_mid<R>(Nz, MID_PRE, L.tab, L.ns, B_T6B, B_T0, B_NONE, Ny * Nx, 0, G.tw[2], s); }))) return e;
+    if ((e = launch_invT<R>(Ny, EPI_SCALE, L.tab, L.ns, B_T0, B_NONE, B_T1, B_NONE, B_NONE, Nx, Nz, 1.0, 0, 0, G.tw[1], s))) return e;
+    return timed(tm, KK_PRE_INV, b_inv, s, [&] {
+        return launch_invT_pre<R>(Nx, L.tab, L.ns, B_T1, out, Nz, Ny, dir, G.tw[0], s); });
+}
+
+// Fresh evaluation of the current iterate: apply a pending update to Phi,
+// H_L Phi from scratch, energy parts, mu, alpha_l.
+template <typename R>
+static hipError_t refresh(const Geo<R>& G, Sub<R> L, hipStream_t s, Timer* tm) {
+    const double F = 3.0 * G.M * sizeof(cpx<R>) * L.ns;
+    hipError_t e;
+    if ((e = chain_HL<R>(G, L, PRO_UPDATE, 0, B_PHI, B_HL, B_P, B_NONE, 0, s, tm))) return e;
+    return timed(tm, KK_EVAL, 2 * F, s, [&] { return launch_eval<R>(L.tab, L.ns, G.g, s); });
+}
+
+// One PCG iteration (Algorithm 1 with Algorithm 2), entirely on the device:
+//   0. (first iteration of a chunk) fresh H_L Phi, E, mu, alpha_l
+//   1. pending update Phi <- (c Phi + s P^)/|.|, H_L Phi by the same combination;
+//      r = H(Phi)Phi - mu Phi, P_V^{1/2} factors, stopping tests
+//   2. preconditioned residual (3 or 5 FFT passes) with the PRP beta,
+//      projection and descent test fused into its last pass
+//   3. P^n = D - Re<D,Phi> Phi, H_L P^ (3 or 5 FFT passes; Phi transformed
+//      alongside for the kinetic coefficients)
+//   4. energy along the retraction, step size, backtracking, and the scalars
+//      (mu, E, alpha_l) of the next iterate
+template <typename R>
+static hipError_t iterate(const Geo<R>& G, Sub<R> L, int do_refresh, hipStream_t s, Timer* tm) {
+    const double F = 3.0 * G.M * sizeof(cpx<R>) * L.ns, Fr = 3.0 * G.M * sizeof(R) * L.ns;
+    hipError_t e;
+    if (do_refresh) {
+        if (tm) tm->chain = 0;
+        if ((e = refresh<R>(G, L, s, tm))) return e;
     }
-    const SolveState* h = cx.st_host;
-    if (h->nonfinite) {
-        const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        fill_result(h, res, iters_fp32, wall);
-        return fail(GS_ENONFINITE, "non-finite value in the iteration (check the input and parameters)");
-    }
-    if (out_from_32) HIPCHK(launch_convert_f2d(p32->f.phi, d_out, n3, s));
-    else HIPCHK(hipMemcpyAsync(d_out, p64->f.phi, sizeof(cpx<double>) * n3, hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipStreamSynchronize(s));
-    const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    fill_result(h, res, iters_fp32, wall);
-    return h->status;
+    if (tm) tm->chain = 1;
+    if ((e = timed(tm, KK_RESID, 8 * F + Fr, s, [&] { return launch_resid<R>(L.tab, L.ns, G.g, 0, s); }))) return e;
+    if (tm) tm->chain = 2;
+    if ((e = chain_pre<R>(G, L, 1, B_PR, s, tm))) return e;
+    if (tm) tm->chain = 3;
+    if ((e = chain_HL<R>(G, L, PRO_DIR, 1, B_P, B_HLP, B_PR, B_PHI, 1, s, tm))) return e;
+    return timed(tm, KK_LSRED, 4 * F, s, [&] { return launch_lsred<R>(L.tab, L.ns, G.g, s); });
 }
 
 // ---------------------------------------------------------------------------
-// operator-level entry points
+// requests, classes, context
+// ---------------------------------------------------------------------------
+enum JobStage : int { JS_QUEUED = 0, JS_RUNNING, JS_FINAL, JS_DONE };
+
+struct Job {
+    uint64_t ticket = 0;
+    gs_grid grid{};
+    gs_options opt{};
+    Phys ph{};
+    double* Vdev = nullptr;
+    const cpx<double>* psi0 = nullptr;
+    cpx<double>* out = nullptr;
+    size_t reserve = 0;
+    int stage = JS_QUEUED;
+    bool admitted = false;   // reservation held
+    bool cancel = false;
+    int slot = -1;           // slot in the current class (preset for a hand-over)
+    bool handover = false;   // queued in the double class after the float phase
+    SolveState mig{};        // state handed over from the float phase
+    hipEvent_t mig_ev = nullptr;
+    int iters_fp32 = 0;
+    int rc = GS_OK;
+    gs_result res{};
+    std::string err;
+    std::chrono::steady_clock::time_point t0;
+    ~Job() {
+        if (Vdev) (void)hipFree(Vdev);
+        if (mig_ev) (void)hipEventDestroy(mig_ev);
+    }
+};
+
+template <typename R>
+struct Class {
+    gs_grid grid{};
+    int check_every = 0;
+    long long M = 0;
+    RedGeom g{};
+    const cpx<R>* tw[3] = {};
+    hipStream_t stream = nullptr;
+    hipEvent_t ev = nullptr;
+    SolveState* d_st = nullptr;
+    SolveState* h_st = nullptr;     // pinned mirror
+    unsigned* d_cnt = nullptr;
+    Slot<R>* d_tab = nullptr;
+    Slot<R>* h_tab = nullptr;       // pinned
+    std::vector<std::unique_ptr<SlotMem<R>>> mem;   // by slot id
+    std::vector<Job*> owner;                         // by slot id
+    std::vector<int> run, fin, iter0;
+    std::deque<Job*> queue;
+    bool inflight = false;
+    uint64_t seq = 0;
+    Timer tm;
+    ~Class() {
+        if (stream) (void)hipStreamSynchronize(stream);
+        mem.clear();
+        if (d_st) (void)hipFree(d_st);
+        if (d_cnt) (void)hipFree(d_cnt);
+        if (d_tab) (void)hipFree(d_tab);
+        if (h_st) (void)hipHostFree(h_st);
+        if (h_tab) (void)hipHostFree(h_tab);
+        if (ev) (void)hipEventDestroy(ev);
+        if (stream) (void)hipStreamDestroy(stream);
+    }
+};
+
+// single-slot plan of the operator-level entry points
+template <typename R>
+struct OpPlan {
+    gs_grid grid{};
+    long long M = 0;
+    RedGeom g{};
+    const cpx<R>* tw[3] = {};
+    std::unique_ptr<SlotMem<R>> mem;
+    SolveState* d_st = nullptr;
+    SolveState* h_st = nullptr;
+    unsigned* d_cnt = nullptr;
+    Slot<R>* d_tab = nullptr;
+    Slot<R>* h_tab = nullptr;
+    ~OpPlan() {
+        mem.reset();
+        if (d_st) (void)hipFree(d_st);
+        if (d_cnt) (void)hipFree(d_cnt);
+        if (d_tab) (void)hipFree(d_tab);
+        if (h_st) (void)hipHostFree(h_st);
+        if (h_tab) (void)hipHostFree(h_tab);
+    }
+};
+
+using ClassKey = std::tuple<int, int, int, int, int>;   // dim, n0, n1, n2, check_every
+using GridKey = std::tuple<int, int, int, int>;
+
+struct Ctx {
+    int device = 0;
+    std::map<ClassKey, std::unique_ptr<Class<double>>> c64;
+    std::map<ClassKey, std::unique_ptr<Class<float>>> c32;
+    std::map<GridKey, std::unique_ptr<OpPlan<double>>> o64;
+    std::map<GridKey, std::unique_ptr<OpPlan<float>>> o32;
+    std::map<std::pair<int, int>, void*> twiddles;   // (N, sizeof(R)) -> table
+    std::map<uint64_t, std::unique_ptr<Job>> jobs;
+    uint64_t next_ticket = 1, next_seq = 1;
+    size_t budget = 0, reserved = 0, allocated = 0;
+    TimerTotals timer;
+    ~Ctx() {
+        (void)hipSetDevice(device);
+        c64.clear();
+        c32.clear();
+        o64.clear();
+        o32.clear();
+        jobs.clear();
+        for (auto& kv : twiddles) (void)hipFree(kv.second);
+    }
+};
+
+template <typename R> static auto& classes(Ctx& cx);
+template <> auto& classes<double>(Ctx& cx) { return cx.c64; }
+template <> auto& classes<float>(Ctx& cx) { return cx.c32; }
+template <typename R> static auto& opplans(Ctx& cx);
+template <> auto& opplans<double>(Ctx& cx) { return cx.o64; }
+template <> auto& opplans<float>(Ctx& cx) { return cx.o32; }
+
+template <typename R>
+static int get_twiddle(Ctx& cx, int N, const cpx<R>** out) {
+    auto key = std::make_pair(N, (int)sizeof(R));
+    auto it = cx.twiddles.find(key);
+    if (it != cx.twiddles.end()) {
+        *out = (const cpx<R>*)it->second;
+        return GS_OK;
+    }
+    std::vector<cpx<R>> h(N);
+    for (int m = 0; m < N; ++m) {
+        const long double ang = 2.0L * 3.14159265358979323846264338327950288L * (long double)m / (long double)N;
+        h[m] = cpx<R>{(R)cosl(ang), (R)(-sinl(ang))};
+    }
+    void* d = nullptr;
+    if (hipMalloc(&d, sizeof(cpx<R>) * N) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(GS_ENOMEM, "twiddle table allocation failed");
+    }
+    HIPCHK(hipMemcpy(d, h.data(), sizeof(cpx<R>) * N, hipMemcpyHostToDevice));
+    cx.twiddles[key] = d;
+    *out = (const cpx<R>*)d;
+    return GS_OK;
+}
+
+static GridKey grid_key(const gs_grid* g) {
+    return std::make_tuple(g->dim, g->n[0], g->n[1], g->dim == 3 ? g->n[2] : 1);
+}
+
+template <typename R>
+static int get_class(Ctx& cx, const gs_grid* g, int check_every, Class<R>** out) {
+    auto key = std::make_tuple(g->dim, g->n[0], g->n[1], g->dim == 3 ? g->n[2] : 1, check_every);
+    auto& mp = classes<R>(cx);
+    auto it = mp.find(key);
+    if (it != mp.end()) {
+        *out = it->second.get();
+        return GS_OK;
+    }
+    auto c = std::make_unique<Class<R>>();
+    c->grid = *g;
+    if (g->dim == 2) c->grid.n[2] = 1;
+    c->check_every = check_every;
+    c->M = npts(g);
+    c->g = red_geom(g);
+    for (int a = 0; a < g->dim; ++a) {
+        int rc = get_twiddle<R>(cx, g->n[a], &c->tw[a]);
+        if (rc) return rc;
+    }
+    // non-blocking: the class's work never waits for the null stream
+    HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&c->ev, hipEventDisableTiming));
+    if (hipMalloc((void**)&c->d_st, sizeof(SolveState) * CLASS_CAP) != hipSuccess ||
+        hipMalloc((void**)&c->d_cnt, sizeof(unsigned) * NCOUNTERS * CLASS_CAP) != hipSuccess ||
+        hipMalloc((void**)&c->d_tab, sizeof(Slot<R>) * CLASS_CAP) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(GS_ENOMEM, "device allocation failed (class tables)");
+    }
+    if (hipHostMalloc((void**)&c->h_st, sizeof(SolveState) * CLASS_CAP, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&c->h_tab, sizeof(Slot<R>) * CLASS_CAP, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(GS_ENOMEM, "pinned allocation failed (class tables)");
+    }
+    std::memset(c->h_st, 0, sizeof(SolveState) * CLASS_CAP);
+    HIPCHK(hipMemsetAsync(c->d_cnt, 0, sizeof(unsigned) * NCOUNTERS * CLASS_CAP, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    *out = c.get();
+    mp[key] = std::move(c);
+    return GS_OK;
+}
+
+template <typename R>
+static Slot<R> entry_of(SlotMem<R>& m, SolveState* st, unsigned* cnt, const Phys& ph) {
+    Slot<R> e;
+    std::memset(&e, 0, sizeof(e));
+    for (int b = 0; b < NBUF; ++b) e.buf[b] = m.buf[b];
+    e.pv = m.pv;
+    e.st = st;
+    e.red_mid = m.red_mid;
+    e.red_pw = m.red_pw;
+    e.counter = cnt;
+    e.p = ph;
+    return e;
+}
+
+template <typename R>
+static Geo<R> geo_of(const gs_grid& g, long long M, RedGeom rg, const cpx<R>* const tw[3], int rot_any) {
+    Geo<R> G;
+    G.dim = g.dim;
+    G.n[0] = g.n[0];
+    G.n[1] = g.n[1];
+    G.n[2] = g.dim == 3 ? g.n[2] : 1;
+    G.M = M;
+    G.g = rg;
+    for (int a = 0; a < 3; ++a) G.tw[a] = tw[a];
+    G.rot_any = rot_any;
+    return G;
+}
+
+// Release the device memory of idle slots (any class) until `need` more bytes
+// fit in the budget.
+template <typename R>
+static void trim_class(Class<R>& c, Ctx& cx, size_t need) {
+    for (size_t k = 0; k < c.mem.size() && cx.allocated + need > cx.budget; ++k) {
+        if (c.mem[k] && !c.owner[k]) {
+            cx.allocated -= c.mem[k]->bytes;
+            c.mem[k].reset();
+        }
+    }
+}
+static void trim(Ctx& cx, size_t need) {
+    (void)hipDeviceSynchronize();   // pending work may still read a released slot
+    for (auto& kv : cx.c32) trim_class(*kv.second, cx, need);
+    for (auto& kv : cx.c64) trim_class(*kv.second, cx, need);
+}
+
+constexpr int SLOT_WAIT = 1;
+
+// Free slot of the class for job j (allocated if needed; a new slot is zeroed
+// on stream s, which must precede every later use of the slot). GS_OK,
+// SLOT_WAIT (no memory now) or an error.
+template <typename R>
+static int acquire_slot(Ctx& cx, Class<R>& c, Job* j, hipStream_t s, int* out) {
+    int id = -1;
+    for (size_t k = 0; k < c.mem.size(); ++k)
+        if (c.mem[k] && !c.owner[k]) { id = (int)k; break; }
+    if (id < 0) {
+        for (size_t k = 0; k < c.mem.size(); ++k)
+            if (!c.mem[k] && !c.owner[k]) { id = (int)k; break; }
+        if (id < 0) {
+            if ((int)c.mem.size() >= CLASS_CAP) return SLOT_WAIT;
+            id = (int)c.mem.size();
+            c.mem.emplace_back();
+            c.owner.push_back(nullptr);
+        }
+        const size_t need = slot_buffer_bytes<R>(&c.grid);
+        if (cx.allocated + need > cx.budget) trim(cx, need);
+        if (cx.allocated + need > cx.budget) return SLOT_WAIT;
+        int rc = alloc_slot_mem<R>(&c.grid, s, c.mem[id]);
+        if (rc) return rc;
+        cx.allocated += need;
+    }
+    c.owner[id] = j;
+    *out = id;
+    return GS_OK;
+}
+
+static void finish_job(Ctx& cx, Job* j, int rc, const SolveState* h, const std::string& msg) {
+    const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() - j->t0).count();
+    fill_result(h, &j->res, j->iters_fp32, wall);
+    j->res.status = rc;
+    j->rc = rc;
+    if (rc < 0) j->err = msg;
+    j->stage = JS_DONE;
+    j->slot = -1;
+    if (j->admitted) {
+        cx.reserved -= j->reserve;
+        j->admitted = false;
+    }
+}
+
+// Float phase of a mixed solve finished with a switch request: hand Phi (made
+// double on the float stream) and the state (beta reset, phase FP64) to the
+// double class of the same grid.
+static int hand_over(Ctx& cx, Class<float>& c, int k, Job* j) {
+    Class<double>* d = nullptr;
+    int rc = get_class<double>(cx, &j->grid, c.check_every, &d);
+    if (rc) return rc;
+    int kd = -1;
+    rc = acquire_slot<double>(cx, *d, j, c.stream, &kd);
+    if (rc == SLOT_WAIT) return fail(GS_ENOMEM, "no device memory for the double phase");
+    if (rc) return rc;
+    HIPCHK(launch_convert_f2d(c.mem[k]->buf[B_PHI], d->mem[kd]->buf[B_PHI], 3 * c.M, c.stream));
+    if (!j->mig_ev) HIPCHK(hipEventCreateWithFlags(&j->mig_ev, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(j->mig_ev, c.stream));
+    SolveState h = c.h_st[k];
+    j->iters_fp32 = h.iter;
+    h.done = 0;
+    h.switch_req = 0;
+    h.phase = PH_FP64;
+    h.have_prev = 0;
+    h.pending_step = 0;
+    h.final_pending = 0;
+    h.iter_phase = 0;
+    h.status = GS_OK;
+    j->mig = h;
+    j->slot = kd;
+    j->handover = true;
+    j->stage = JS_QUEUED;
+    d->queue.push_front(j);
+    return GS_OK;
+}
+
+// Initial guess of job j into slot k's Phi (the Gaussian guess is built in
+// double, then rounded when the slot is float).
+template <typename R>
+static int load_guess(Class<R>& c, int k, Job* j) {
+    SlotMem<R>& m = *c.mem[k];
+    const long long n3 = 3 * c.M;
+    if constexpr (std::is_same<R, double>::value) {
+        if (j->psi0) HIPCHK(hipMemcpyAsync(m.buf[B_PHI], j->psi0, sizeof(cpx<double>) * n3, hipMemcpyDeviceToDevice, c.stream));
+        else HIPCHK(launch_gaussian(m.buf[B_PHI], j->ph, c.stream));
+    } else {
+        const cpx<double>* src = j->psi0;
+        if (!src) {
+            cpx<double>* tmp = reinterpret_cast<cpx<double>*>(m.buf[B_T6A]);   // 2 float fields = 1 double field
+            HIPCHK(launch_gaussian(tmp, j->ph, c.stream));
+            src = tmp;
+        }
+        HIPCHK(launch_convert_d2f(src, m.buf[B_PHI], n3, c.stream));
+    }
+    return GS_OK;
+}
+
+template <typename R>
+static int copy_out(Class<R>& c, int k, Job* j) {
+    const long long n3 = 3 * c.M;
+    if constexpr (std::is_same<R, double>::value)
+        HIPCHK(hipMemcpyAsync(j->out, c.mem[k]->buf[B_PHI], sizeof(cpx<double>) * n3, hipMemcpyDeviceToDevice, c.stream));
+    else
+        HIPCHK(launch_convert_f2d(c.mem[k]->buf[B_PHI], j->out, n3, c.stream));
+    return GS_OK;
+}
+
+// Chunk boundary of a class whose previous chunk (if any) has completed:
+// retire finished solves, start final evaluations, hand over float phases,
+// admit queued requests, then enqueue the next chunk.
+template <typename R>
+static int boundary(Ctx& cx, Class<R>& c) {
+    constexpr bool is64 = std::is_same<R, double>::value;
+    int rc;
+    // 1. final evaluations enqueued at the previous boundary have completed
+    for (int k : c.fin) {
+        Job* j = c.owner[k];
+        const SolveState& h = c.h_st[k];
+        if (!is64) j->iters_fp32 = h.iter;
+        if (h.nonfinite) finish_job(cx, j, GS_ENONFINITE, &h, "non-finite value in the final evaluation");
+        else finish_job(cx, j, h.status, &h, "");
+        c.owner[k] = nullptr;
+    }
+    c.fin.clear();
+    // 2. slots of the chunk that has completed
+    if (!c.run.empty() && c.tm.kind >= 0) {
+        int n_full = 0;
+        bool all_done = true;
+        for (size_t i = 0; i < c.run.size(); ++i) {
+            const SolveState& h = c.h_st[c.run[i]];
+            n_full = std::max(n_full, h.iter - c.iter0[i]);
+            all_done = all_done && h.done;
+        }
+        HIPCHK(timer_collect(c.tm, cx.timer, n_full, all_done));
+    }
+    std::vector<int> cont;
+    for (size_t i = 0; i < c.run.size(); ++i) {
+        const int k = c.run[i];
+        Job* j = c.owner[k];
+        SolveState& h = c.h_st[k];
+        if (j->cancel) {
+            finish_job(cx, j, GS_ECANCELED, &h, "request cancelled");
+            c.owner[k] = nullptr;
+            continue;
+        }
+        if (!h.done) {
+            if (h.iter == c.iter0[i]) {   // every iteration accepts a step or ends the solve
+                finish_job(cx, j, GS_EDEVICE, &h, "solver made no progress (device state not updated)");
+                c.owner[k] = nullptr;
+                continue;
+            }
+            cont.push_back(k);
+            continue;
+        }
+        if (h.nonfinite) {
+            if (!is64) j->iters_fp32 = h.iter;
+            finish_job(cx, j, GS_ENONFINITE, &h, "non-finite value in the iteration (check the input and parameters)");
+            c.owner[k] = nullptr;
+            continue;
+        }
+        if constexpr (!is64) {
+            if (h.switch_req && j->opt.precision == GS_MIXED) {
+                rc = hand_over(cx, c, k, j);
+                if (rc) finish_job(cx, j, rc, &h, g_err);
+                c.owner[k] = nullptr;
+                continue;
+            }
+        }
+        h.done = 0;   // the final evaluation runs while done == 0
+        j->stage = JS_FINAL;
+        c.fin.push_back(k);
+    }
+    // 3. admissions, hand-overs first (they are at the front of the queue)
+    std::vector<int> fresh;
+    while (!c.queue.empty()) {
+        Job* j = c.queue.front();
+        if (j->cancel) {
+            c.queue.pop_front();
+            if (j->slot >= 0) c.owner[j->slot] = nullptr;
+            finish_job(cx, j, GS_ECANCELED, nullptr, "request cancelled");
+            continue;
+        }
+        int k = j->slot;
+        if (j->handover) {
+            c.h_st[k] = j->mig;
+            HIPCHK(hipStreamWaitEvent(c.stream, j->mig_ev, 0));
+            j->handover = false;
+        } else {
+            if (!j->admitted && cx.reserved + j->reserve > cx.budget) break;   // wait for memory
+            rc = acquire_slot<R>(cx, c, j, c.stream, &k);
+            if (rc == SLOT_WAIT) break;
+            c.queue.pop_front();
+            if (rc) {
+                finish_job(cx, j, rc, nullptr, g_err);
+                continue;
+            }
+            if (!j->admitted) {
+                cx.reserved += j->reserve;
+                j->admitted = true;
+            }
+            j->slot = k;
+            init_state(&c.h_st[k], &j->opt, j->opt.precision == GS_MIXED ? PH_FP32 : PH_FP64);
+            if ((rc = load_guess<R>(c, k, j))) return rc;
+            fresh.push_back(k);
+            j->stage = JS_RUNNING;
+            HIPCHK(hipMemsetAsync(c.mem[k]->buf[B_P], 0, sizeof(cpx<R>) * 3 * c.M, c.stream));
+            continue;
+        }
+        c.queue.pop_front();
+        fresh.push_back(k);
+        j->stage = JS_RUNNING;
+        HIPCHK(hipMemsetAsync(c.mem[k]->buf[B_P], 0, sizeof(cpx<R>) * 3 * c.M, c.stream));
+    }
+    // 4. launch table: [fresh..., continuing...] run the chunk, then the slots
+    //    under final evaluation
+    c.run = fresh;
+    c.run.insert(c.run.end(), cont.begin(), cont.end());
+    if (c.run.empty() && c.fin.empty()) {
+        c.inflight = false;
+        return GS_OK;
+    }
+    int nt = 0, rot_any = 0, maxk = 0;
+    c.iter0.clear();
+    for (int k : c.run) c.iter0.push_back(c.h_st[k].iter);
+    auto put = [&](int k) {
+        const Phys& ph = c.owner[k]->ph;
+        c.h_tab[nt++] = entry_of<R>(*c.mem[k], c.d_st + k, c.d_cnt + (size_t)k * NCOUNTERS, ph);
+        rot_any |= ph.omega != 0.0;
+        maxk = std::max(maxk, k + 1);
+    };
+    for (int k : c.run) put(k);
+    for (int k : c.fin) put(k);
+    const int nrun = (int)c.run.size(), nfin = (int)c.fin.size(), nnew = (int)fresh.size();
+    hipStream_t s = c.stream;
+    HIPCHK(hipMemcpyAsync(c.d_st, c.h_st, sizeof(SolveState) * maxk, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c.d_tab, c.h_tab, sizeof(Slot<R>) * nt, hipMemcpyHostToDevice, s));
+    const Geo<R> G = geo_of<R>(c.grid, c.M, c.g, c.tw, rot_any);
+    if (nfin) {
+        const Sub<R> Lf{c.d_tab + nrun, nfin};
+        HIPCHK(refresh<R>(G, Lf, s, nullptr));
+        HIPCHK(launch_resid<R>(Lf.tab, Lf.ns, G.g, 1, s));
+        for (int k : c.fin)
+            if ((rc = copy_out<R>(c, k, c.owner[k]))) return rc;
+    }
+    if (nnew) HIPCHK(launch_normalize<R>(c.d_tab, nnew, G.g, s));
+    if (nrun) {
+        c.tm.kind = cx.timer.kind;
+        Timer* tm = c.tm.kind >= 0 ? &c.tm : nullptr;
+        const Sub<R> Lr{c.d_tab, nrun};
+        for (int it = 0; it < c.check_every; ++it) {
+            if (tm) tm->iter_in_chunk = it;
+            HIPCHK(iterate<R>(G, Lr, it == 0, s, tm));
+        }
+    }
+    HIPCHK(hipMemcpyAsync(c.h_st, c.d_st, sizeof(SolveState) * maxk, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipEventRecord(c.ev, s));
+    c.inflight = true;
+    c.seq = cx.next_seq++;
+    return GS_OK;
+}
+
+template <typename R>
+static int visit(Ctx& cx, Class<R>& c, bool& did) {
+    if (c.inflight) {
+        hipError_t q = hipEventQuery(c.ev);
+        if (q == hipErrorNotReady) return GS_OK;
+        if (q != hipSuccess) return fail(GS_EDEVICE, std::string("chunk completion: ") + hipGetErrorString(q));
+        c.inflight = false;
+    } else if (c.queue.empty() && c.run.empty() && c.fin.empty()) {
+        return GS_OK;
+    }
+    int rc = boundary<R>(cx, c);
+    if (rc) return rc;
+    did = did || c.inflight;
+    return GS_OK;
+}
+
+// Advance every class whose chunk has completed. block: if nothing could be
+// advanced, wait for the chunk enqueued first and try again.
+static int progress(Ctx& cx, bool block) {
+    for (;;) {
+        bool did = false;
+        int rc;
+        for (auto& kv : cx.c32)
+            if ((rc = visit<float>(cx, *kv.second, did))) return rc;
+        for (auto& kv : cx.c64)
+            if ((rc = visit<double>(cx, *kv.second, did))) return rc;
+        if (!block || did) return GS_OK;
+        hipEvent_t e = nullptr;
+        uint64_t best = UINT64_MAX;
+        for (auto& kv : cx.c32)
+            if (kv.second->inflight && kv.second->seq < best) { best = kv.second->seq; e = kv.second->ev; }
+        for (auto& kv : cx.c64)
+            if (kv.second->inflight && kv.second->seq < best) { best = kv.second->seq; e = kv.second->ev; }
+        if (!e) return GS_OK;   // nothing in flight
+        HIPCHK(hipEventSynchronize(e));
+    }
+}
+
+static int submit_job(Ctx& cx, const gs_request* q, uint64_t* ticket) {
+    int rc;
+    if (!q) return fail(GS_EINVAL, "request is NULL");
+    if ((rc = check_grid(&q->grid))) return rc;
+    if ((rc = check_options(&q->options))) return rc;
+    if (!q->d_psi_out) return fail(GS_EINVAL, "request.d_psi_out is NULL");
+    auto j = std::make_unique<Job>();
+    j->grid = q->grid;
+    if (j->grid.dim == 2) j->grid.n[2] = 1;
+    j->opt = q->options;
+    if ((rc = make_phys(&j->grid, &q->trap, &q->params, &j->ph))) return rc;
+    const long long M = npts(&j->grid);
+    j->reserve = 0;
+    if (q->options.precision != GS_FP32) j->reserve += slot_bytes<double>(&j->grid);
+    if (q->options.precision != GS_FP64) j->reserve += slot_bytes<float>(&j->grid);
+    if (q->trap.V) j->reserve += sizeof(double) * M;
+    if (j->reserve > cx.budget) return fail(GS_ENOMEM, "request needs more device memory than the budget");
+    if (q->trap.V) {
+        if (hipMalloc((void**)&j->Vdev, sizeof(double) * M) != hipSuccess) {
+            j->Vdev = nullptr;
+            (void)hipGetLastError();
+            return fail(GS_ENOMEM, "device allocation failed (V)");
+        }
+        HIPCHK(hipMemcpy(j->Vdev, q->trap.V, sizeof(double) * M, hipMemcpyHostToDevice));
+        j->ph.V = j->Vdev;
+    }
+    j->psi0 = (const cpx<double>*)q->d_psi0;
+    j->out = (cpx<double>*)q->d_psi_out;
+    j->t0 = std::chrono::steady_clock::now();
+    if (q->options.precision == GS_FP64) {
+        Class<double>* c;
+        if ((rc = get_class<double>(cx, &j->grid, j->opt.check_every, &c))) return rc;
+        c->queue.push_back(j.get());
+    } else {
+        Class<float>* c;
+        if ((rc = get_class<float>(cx, &j->grid, j->opt.check_every, &c))) return rc;
+        c->queue.push_back(j.get());
+    }
+    j->ticket = cx.next_ticket++;
+    *ticket = j->ticket;
+    cx.jobs[j->ticket] = std::move(j);
+    return GS_OK;
+}
+
+// Result of a completed request; the ticket is released.
+static int take_result(Ctx& cx, uint64_t ticket, gs_result* res) {
+    auto it = cx.jobs.find(ticket);
+    Job* j = it->second.get();
+    if (res) *res = j->res;
+    const int rc = j->rc;
+    if (rc < 0) g_err = j->err;
+    cx.jobs.erase(it);
+    return rc;
+}
+
+static int wait_job(Ctx& cx, uint64_t ticket, gs_result* res) {
+    auto it = cx.jobs.find(ticket);
+    if (it == cx.jobs.end()) return fail(GS_EINVAL, "unknown ticket");
+    Job* j = it->second.get();
+    while (j->stage != JS_DONE) {
+        int rc = progress(cx, true);
+        if (rc) return rc;
+        bool any = false;
+        for (auto& kv : cx.c32) any = any || kv.second->inflight;
+        for (auto& kv : cx.c64) any = any || kv.second->inflight;
+        if (!any && j->stage != JS_DONE) return fail(GS_EDEVICE, "request is not progressing");
+    }
+    return take_result(cx, ticket, res);
+}
+
+static int solve_device_impl(Ctx& cx, const gs_grid* g, const gs_trap* t, const gs_params* p, const gs_options* o,
+                             const void* d_psi0, void* d_out, gs_result* res) {
+    if (!p) return fail(GS_EINVAL, "params is NULL");
+    gs_request q;
+    std::memset(&q, 0, sizeof(q));
+    if (g) q.grid = *g;
+    else return fail(GS_EINVAL, "grid is NULL");
+    if (t) q.trap = *t;
+    else {
+        q.trap.g[0] = q.trap.g[1] = q.trap.g[2] = 1.0;
+    }
+    q.params = *p;
+    if (!o) return fail(GS_EINVAL, "options is NULL");
+    q.options = *o;
+    q.d_psi0 = d_psi0;
+    q.d_psi_out = d_out;
+    uint64_t ticket = 0;
+    int rc = submit_job(cx, &q, &ticket);
+    if (rc) return rc;
+    return wait_job(cx, ticket, res);
+}
+
+// ---------------------------------------------------------------------------
+// operator-level entry points (one slot of their own per grid and precision)
 // ---------------------------------------------------------------------------
 template <typename R>
-static int fft_impl(Ctx& cx, const gs_grid* g, int sign, const cpx<R>* in, cpx<R>* out, hipStream_t s) {
-    Plan<R>* pl;
+static int get_opplan(Ctx& cx, const gs_grid* g, OpPlan<R>** out, hipStream_t s) {
+    auto key = grid_key(g);
+    auto& mp = opplans<R>(cx);
+    auto it = mp.find(key);
+    if (it != mp.end()) {
+        *out = it->second.get();
+        return GS_OK;
+    }
+    auto op = std::make_unique<OpPlan<R>>();
+    op->grid = *g;
+    if (g->dim == 2) op->grid.n[2] = 1;
+    op->M = npts(g);
+    op->g = red_geom(g);
     int rc;
-    if ((rc = get_plan<R>(cx, g, &pl))) return rc;
+    for (int a = 0; a < g->dim; ++a)
+        if ((rc = get_twiddle<R>(cx, g->n[a], &op->tw[a]))) return rc;
+    if ((rc = alloc_slot_mem<R>(g, s, op->mem))) return rc;
+    if (hipMalloc((void**)&op->d_st, sizeof(SolveState)) != hipSuccess ||
+        hipMalloc((void**)&op->d_cnt, sizeof(unsigned) * NCOUNTERS) != hipSuccess ||
+        hipMalloc((void**)&op->d_tab, sizeof(Slot<R>)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(GS_ENOMEM, "device allocation failed (operator plan)");
+    }
+    if (hipHostMalloc((void**)&op->h_st, sizeof(SolveState), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&op->h_tab, sizeof(Slot<R>), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(GS_ENOMEM, "pinned allocation failed (operator plan)");
+    }
+    HIPCHK(hipMemsetAsync(op->d_cnt, 0, sizeof(unsigned) * NCOUNTERS, s));
+    *out = op.get();
+    mp[key] = std::move(op);
+    return GS_OK;
+}
+
+// Upload the slot descriptor (caller buffers as X0, X1) and a state for a
+// single evaluation. The stream is drained first: the pinned staging of the
+// previous call may still be in use by its copies.
+template <typename R>
+static int op_setup(OpPlan<R>& op, const Phys& ph, const void* x0, void* x1, hipStream_t s) {
+    HIPCHK(hipStreamSynchronize(s));
+    gs_options o;
+    gs_default_options(&o);
+    o.max_iter = 1 << 30;
+    init_state(op.h_st, &o, PH_FP64);
+    *op.h_tab = entry_of<R>(*op.mem, op.d_st, op.d_cnt, ph);
+    op.h_tab->buf[B_X0] = (cpx<R>*)x0;
+    op.h_tab->buf[B_X1] = (cpx<R>*)x1;
+    HIPCHK(hipMemcpyAsync(op.d_st, op.h_st, sizeof(SolveState), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(op.d_tab, op.h_tab, sizeof(Slot<R>), hipMemcpyHostToDevice, s));
+    return GS_OK;
+}
+
+template <typename R>
+static int fft_impl(Ctx& cx, const gs_grid* g, int sign, const cpx<R>* in, cpx<R>* out, hipStream_t s) {
+    OpPlan<R>* op;
+    int rc;
+    if ((rc = get_opplan<R>(cx, g, &op, s))) return rc;
     Phys ph;
-    if ((rc = make_phys(cx, g, nullptr, nullptr, &ph))) return rc;
-    const int Nx = pl->n[0], Ny = pl->n[1], Nz = pl->n[2];
-    const double invM = 1.0 / (double)pl->M;
-    cpx<R>* inw = const_cast<cpx<R>*>(in);
+    if ((rc = make_phys(g, nullptr, nullptr, &ph))) return rc;
+    if ((rc = op_setup<R>(*op, ph, in, out, s))) return rc;
+    const int Nx = g->n[0], Ny = g->n[1], Nz = g->dim == 3 ? g->n[2] : 1;
+    const double invM = 1.0 / (double)op->M;
+    const Slot<R>* T = op->d_tab;
     if (sign < 0) {
         if (g->dim == 2) {
-            HIPCHK(launch_fwdT<R>(Nx, PRO_PLAIN, 0, inw, pl->t[0], 1, Ny, 3, nullptr, nullptr, nullptr, pl->tw[0], s));
-            HIPCHK(launch_fwdT<R>(Ny, PRO_PLAIN, 0, pl->t[0], out, 1, Nx, 3, nullptr, nullptr, nullptr, pl->tw[1], s));
+            HIPCHK(launch_fwdT<R>(Nx, PRO_PLAIN, 0, T, 1, B_X0, B_T0, B_NONE, B_NONE, 1, Ny, 3, op->tw[0], s));
+            HIPCHK(launch_fwdT<R>(Ny, PRO_PLAIN, 0, T, 1, B_T0, B_X1, B_NONE, B_NONE, 1, Nx, 3, op->tw[1], s));
         } else {
-            HIPCHK(launch_fwdT<R>(Nx, PRO_PLAIN, 0, inw, pl->t[0], Nz, Ny, 3, nullptr, nullptr, nullptr, pl->tw[0], s));
-            HIPCHK(launch_fwdT<R>(Ny, PRO_PLAIN, 0, pl->t[0], pl->t[1], Nx, Nz, 3, nullptr, nullptr, nullptr, pl->tw[1], s));
-            HIPCHK(launch_fwdT<R>(Nz, PRO_PLAIN, 0, pl->t[1], out, Ny, Nx, 3, nullptr, nullptr, nullptr, pl->tw[2], s));
+            HIPCHK(launch_fwdT<R>(Nx, PRO_PLAIN, 0, T, 1, B_X0, B_T0, B_NONE, B_NONE, Nz, Ny, 3, op->tw[0], s));
+            HIPCHK(launch_fwdT<R>(Ny, PRO_PLAIN, 0, T, 1, B_T0, B_T1, B_NONE, B_NONE, Nx, Nz, 3, op->tw[1], s));
+            HIPCHK(launch_fwdT<R>(Nz, PRO_PLAIN, 0, T, 1, B_T1, B_X1, B_NONE, B_NONE, Ny, Nx, 3, op->tw[2], s));
         }
     } else {
         if (g->dim == 2) {
-            HIPCHK(launch_invT<R>(Ny, EPI_SCALE, 1, in, nullptr, pl->t[0], nullptr, 1, Nx, ph, nullptr, 1.0, nullptr, nullptr, 0, pl->tw[1], s));
-            HIPCHK(launch_invT<R>(Nx, EPI_SCALE, 1, pl->t[0], nullptr, out, nullptr, 1, Ny, ph, nullptr, invM, nullptr, nullptr, 0, pl->tw[0], s));
+            HIPCHK(launch_invT<R>(Ny, EPI_SCALE, T, 1, B_X0, B_NONE, B_T0, B_NONE, B_NONE, 1, Nx, 1.0, 0, 0, op->tw[1], s));
+            HIPCHK(launch_invT<R>(Nx, EPI_SCALE, T, 1, B_T0, B_NONE, B_X1, B_NONE, B_NONE, 1, Ny, invM, 0, 0, op->tw[0], s));
         } else {
-            HIPCHK(launch_invT<R>(Nz, EPI_SCALE, 1, in, nullptr, pl->t[0], nullptr, Ny, Nx, ph, nullptr, 1.0, nullptr, nullptr, 0, pl->tw[2], s));
-            HIPCHK(launch_invT<R>(Ny, EPI_SCALE, 1, pl->t[0], nullptr, pl->t[1], nullptr, Nx, Nz, ph, nullptr, 1.0, nullptr, nullptr, 0, pl->tw[1], s));
-            HIPCHK(launch_invT<R>(Nx, EPI_SCALE, 1, pl->t[1], nullptr, out, nullptr, Nz, Ny, ph, nullptr, invM, nullptr, nullptr, 0, pl->tw[0], s));
+            HIPCHK(launch_invT<R>(Nz, EPI_SCALE, T, 1, B_X0, B_NONE, B_T0, B_NONE, B_NONE, Ny, Nx, 1.0, 0, 0, op->tw[2], s));
+            HIPCHK(launch_invT<R>(Ny, EPI_SCALE, T, 1, B_T0, B_NONE, B_T1, B_NONE, B_NONE, Nx, Nz, 1.0, 0, 0, op->tw[1], s));
+            HIPCHK(launch_invT<R>(Nx, EPI_SCALE, T, 1, B_T1, B_NONE, B_X1, B_NONE, B_NONE, Nz, Ny, invM, 0, 0, op->tw[0], s));
         }
     }
     return GS_OK;
 }
 
-// state for a single evaluation (no iteration)
-static SolveState* eval_state(Ctx& cx, hipStream_t s, int* rc) {
-    gs_options o;
-    gs_default_options(&o);
-    o.max_iter = 1 << 30;
-    init_state(cx.st_host, &o, PH_FP64);
-    hipError_t e = hipMemcpyAsync(cx.st, cx.st_host, sizeof(SolveState), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);   // the pinned mirror is reused by the next call
-    *rc = e == hipSuccess ? GS_OK : fail(GS_EDEVICE, hipGetErrorString(e));
-    return cx.st;
+// user potential of an operator-level call: a device copy owned by the plan's context
+static int op_potential(Ctx& cx, const gs_trap* t, Phys& ph, double** Vdev) {
+    *Vdev = nullptr;
+    if (!t || !t->V) return GS_OK;
+    if (hipMalloc((void**)Vdev, sizeof(double) * ph.M) != hipSuccess) {
+        *Vdev = nullptr;
+        (void)hipGetLastError();
+        return fail(GS_ENOMEM, "device allocation failed (V)");
+    }
+    HIPCHK(hipMemcpy(*Vdev, t->V, sizeof(double) * ph.M, hipMemcpyHostToDevice));
+    ph.V = *Vdev;
+    (void)cx;
+    return GS_OK;
 }
 
 template <typename R>
 static int ham_impl(Ctx& cx, const gs_grid* g, const gs_trap* t, const gs_params* p, const cpx<R>* psi,
                     cpx<R>* hpsi, gs_result* res, hipStream_t s) {
-    Plan<R>* pl;
+    OpPlan<R>* op;
     int rc;
-    if ((rc = get_plan<R>(cx, g, &pl))) return rc;
+    if ((rc = get_opplan<R>(cx, g, &op, s))) return rc;
     Phys ph;
-    if ((rc = make_phys(cx, g, t, p, &ph))) return rc;
-    const long long n3 = 3 * ph.M;
-    SolveState* st = eval_state(cx, s, &rc);
-    if (rc) return rc;
-    RedBuf rb = redbuf(cx, *pl);
-    HIPCHK(hipMemcpyAsync(pl->f.phi, psi, sizeof(cpx<R>) * n3, hipMemcpyDeviceToDevice, s));
-    HIPCHK(refresh<R>(*pl, ph, st, rb, 1, s, nullptr));
-    HIPCHK(launch_resid<R>(pl->f, ph, st, rb, 1, s));
-    HIPCHK(launch_hphi<R>(pl->f.phi, pl->f.hl, hpsi, ph, s));
-    if (res) {
-        HIPCHK(hipMemcpyAsync(cx.st_host, st, sizeof(SolveState), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        fill_result(cx.st_host, res, 0, 0.0);
-        res->status = GS_OK;
+    if ((rc = make_phys(g, t, p, &ph))) return rc;
+    double* Vdev = nullptr;
+    if ((rc = op_potential(cx, t, ph, &Vdev))) return rc;
+    rc = op_setup<R>(*op, ph, psi, hpsi, s);
+    const Sub<R> L{op->d_tab, 1};
+    const Geo<R> G = geo_of<R>(op->grid, op->M, op->g, op->tw, ph.omega != 0.0);
+    hipError_t e = hipSuccess;
+    if (!rc) e = hipMemcpyAsync(op->mem->buf[B_PHI], psi, sizeof(cpx<R>) * 3 * op->M, hipMemcpyDeviceToDevice, s);
+    if (!rc && !e) e = refresh<R>(G, L, s, nullptr);
+    if (!rc && !e) e = launch_resid<R>(L.tab, 1, G.g, 1, s);
+    if (!rc && !e) e = launch_hphi<R>(L.tab, 1, G.g, s);
+    if (!rc && !e && (res || Vdev)) {
+        e = hipMemcpyAsync(op->h_st, op->d_st, sizeof(SolveState), hipMemcpyDeviceToHost, s);
+        if (!e) e = hipStreamSynchronize(s);
+        if (!e && res) {
+            fill_result(op->h_st, res, 0, 0.0);
+            res->status = GS_OK;
+        }
     }
+    if (Vdev) (void)hipFree(Vdev);
+    if (rc) return rc;
+    if (e) return fail(GS_EDEVICE, hipGetErrorString(e));
     return GS_OK;
 }
 
 template <typename R>
 static int pre_impl(Ctx& cx, const gs_grid* g, const gs_trap* t, const gs_params* p, const cpx<R>* psi,
                     const cpx<R>* r, cpx<R>* out, hipStream_t s) {
-    Plan<R>* pl;
+    OpPlan<R>* op;
     int rc;
-    if ((rc = get_plan<R>(cx, g, &pl))) return rc;
+    if ((rc = get_opplan<R>(cx, g, &op, s))) return rc;
     Phys ph;
-    if ((rc = make_phys(cx, g, t, p, &ph))) return rc;
-    const long long n3 = 3 * ph.M;
-    SolveState* st = eval_state(cx, s, &rc);
+    if ((rc = make_phys(g, t, p, &ph))) return rc;
+    double* Vdev = nullptr;
+    if ((rc = op_potential(cx, t, ph, &Vdev))) return rc;
+    rc = op_setup<R>(*op, ph, r, out, s);
+    const Sub<R> L{op->d_tab, 1};
+    const Geo<R> G = geo_of<R>(op->grid, op->M, op->g, op->tw, ph.omega != 0.0);
+    hipError_t e = hipSuccess;
+    if (!rc) e = hipMemcpyAsync(op->mem->buf[B_PHI], psi, sizeof(cpx<R>) * 3 * op->M, hipMemcpyDeviceToDevice, s);
+    if (!rc && !e) e = refresh<R>(G, L, s, nullptr);
+    if (!rc && !e) e = launch_pvin<R>(L.tab, 1, G.g, s);
+    if (!rc && !e) e = chain_pre<R>(G, L, 0, B_X1, s, nullptr);
+    if (!rc && !e && Vdev) e = hipStreamSynchronize(s);
+    if (Vdev) (void)hipFree(Vdev);
     if (rc) return rc;
-    RedBuf rb = redbuf(cx, *pl);
-    HIPCHK(hipMemcpyAsync(pl->f.phi, psi, sizeof(cpx<R>) * n3, hipMemcpyDeviceToDevice, s));
-    HIPCHK(refresh<R>(*pl, ph, st, rb, 1, s, nullptr));
-    HIPCHK(launch_pvin<R>(pl->f.phi, r, pl->f.pv, pl->f.u, ph, st, s));
-    HIPCHK(chain_pre<R>(*pl, ph, st, rb, 0, s));
-    HIPCHK(hipMemcpyAsync(out, pl->f.pr, sizeof(cpx<R>) * n3, hipMemcpyDeviceToDevice, s));
+    if (e) return fail(GS_EDEVICE, hipGetErrorString(e));
     return GS_OK;
 }
 
@@ -727,9 +1235,9 @@ void gs_default_options(gs_options* o) {
 size_t gs_footprint_bytes(const gs_grid* g, int precision) {
     if (check_grid(g) != GS_OK) return 0;
     switch (precision) {
-    case GS_FP64: return plan_bytes<double>(g);
-    case GS_FP32: return plan_bytes<float>(g);
-    case GS_MIXED: return plan_bytes<double>(g) + plan_bytes<float>(g);
+    case GS_FP64: return slot_bytes<double>(g);
+    case GS_FP32: return slot_bytes<float>(g);
+    case GS_MIXED: return slot_bytes<double>(g) + slot_bytes<float>(g);
     default: return 0;
     }
 }
@@ -744,22 +1252,36 @@ int gs_create(gs_ctx** out, int device) {
     auto c = std::make_unique<gs_ctx>();
     Ctx& cx = c->impl;
     cx.device = device;
-    if (hipStreamCreate(&cx.stream) != hipSuccess) return fail(GS_EDEVICE, "hipStreamCreate failed");
-    void* p = nullptr;
-    if (hipMalloc(&p, sizeof(SolveState)) != hipSuccess) return fail(GS_ENOMEM, "state allocation failed");
-    cx.allocs.push_back(p);
-    cx.st = (SolveState*)p;
-    if (hipHostMalloc((void**)&cx.st_host, sizeof(SolveState), hipHostMallocDefault) != hipSuccess)
-        return fail(GS_ENOMEM, "pinned allocation failed");
-    if (hipMalloc(&p, 16 * sizeof(unsigned)) != hipSuccess) return fail(GS_ENOMEM, "counter allocation failed");
-    cx.allocs.push_back(p);
-    cx.counters = (unsigned*)p;
-    if (hipMemset(cx.counters, 0, 16 * sizeof(unsigned)) != hipSuccess) return fail(GS_EDEVICE, "hipMemset failed");
+    size_t freeb = 0, total = 0;
+    if (hipMemGetInfo(&freeb, &total) != hipSuccess) return fail(GS_EDEVICE, "hipMemGetInfo failed");
+    cx.budget = (size_t)(0.9 * (double)freeb);
     *out = c.release();
     return GS_OK;
 }
 
 void gs_destroy(gs_ctx* ctx) { delete ctx; }
+
+int gs_set_hbm_budget(gs_ctx* ctx, size_t bytes) {
+    if (!ctx) return fail(GS_EINVAL, "ctx is NULL");
+    Ctx& cx = ctx->impl;
+    if (hipSetDevice(cx.device) != hipSuccess) return fail(GS_EDEVICE, "hipSetDevice failed");
+    if (bytes == 0) {
+        size_t freeb = 0, total = 0;
+        if (hipMemGetInfo(&freeb, &total) != hipSuccess) return fail(GS_EDEVICE, "hipMemGetInfo failed");
+        bytes = (size_t)(0.9 * (double)(freeb + cx.allocated));
+    }
+    cx.budget = bytes;
+    if (cx.allocated > cx.budget) trim(cx, 0);
+    return GS_OK;
+}
+
+int gs_memory_stats(gs_ctx* ctx, size_t* budget, size_t* reserved, size_t* allocated) {
+    if (!ctx) return fail(GS_EINVAL, "ctx is NULL");
+    if (budget) *budget = ctx->impl.budget;
+    if (reserved) *reserved = ctx->impl.reserved;
+    if (allocated) *allocated = ctx->impl.allocated;
+    return GS_OK;
+}
 
 int gs_solve(gs_ctx* ctx, const gs_grid* g, const gs_trap* t, const gs_params* p, const gs_options* o,
              const double* psi0, double* psi_out, gs_result* res) {
@@ -771,13 +1293,17 @@ int gs_solve(gs_ctx* ctx, const gs_grid* g, const gs_trap* t, const gs_params* p
     if (hipSetDevice(cx.device) != hipSuccess) return fail(GS_EDEVICE, "hipSetDevice failed");
     const size_t bytes = sizeof(cpx<double>) * 3 * npts(g);
     void *din = nullptr, *dout = nullptr;
-    if (hipMalloc(&dout, bytes) != hipSuccess) return fail(GS_ENOMEM, "device allocation failed (psi)");
+    if (hipMalloc(&dout, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(GS_ENOMEM, "device allocation failed (psi)");
+    }
     if (psi0 && hipMalloc(&din, bytes) != hipSuccess) {
+        (void)hipGetLastError();
         (void)hipFree(dout);
         return fail(GS_ENOMEM, "device allocation failed (psi0)");
     }
     if (psi0 && hipMemcpy(din, psi0, bytes, hipMemcpyHostToDevice) != hipSuccess) rc = fail(GS_EDEVICE, "copy of psi0 failed");
-    if (!rc) rc = solve_impl(cx, g, t, p, o, (const cpx<double>*)din, (cpx<double>*)dout, res, cx.stream);
+    if (!rc) rc = solve_device_impl(cx, g, t, p, o, din, dout, res);
     if (rc >= 0 && hipMemcpy(psi_out, dout, bytes, hipMemcpyDeviceToHost) != hipSuccess) rc = fail(GS_EDEVICE, "copy of psi failed");
     if (din) (void)hipFree(din);
     (void)hipFree(dout);
@@ -788,16 +1314,107 @@ int gs_solve_device(gs_ctx* ctx, const gs_grid* g, const gs_trap* t, const gs_pa
                     const void* d_psi0, void* d_psi_out, gs_result* res, void* stream) {
     if (!ctx) return fail(GS_EINVAL, "ctx is NULL");
     if (!d_psi_out) return fail(GS_EINVAL, "d_psi_out is NULL");
-    return solve_impl(ctx->impl, g, t, p, o, (const cpx<double>*)d_psi0, (cpx<double>*)d_psi_out, res,
-                      (hipStream_t)stream);
+    Ctx& cx = ctx->impl;
+    if (hipSetDevice(cx.device) != hipSuccess) return fail(GS_EDEVICE, "hipSetDevice failed");
+    // the guess may come from work queued on the caller's stream
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return fail(GS_EDEVICE, "hipStreamSynchronize failed");
+    return solve_device_impl(cx, g, t, p, o, d_psi0, d_psi_out, res);
+}
+
+int gs_submit(gs_ctx* ctx, const gs_request* req, uint64_t* ticket) {
+    if (!ctx || !ticket) return fail(GS_EINVAL, "NULL argument");
+    Ctx& cx = ctx->impl;
+    if (hipSetDevice(cx.device) != hipSuccess) return fail(GS_EDEVICE, "hipSetDevice failed");
+    int rc = submit_job(cx, req, ticket);
+    if (rc) return rc;
+    return progress(cx, false);
+}
+
+int gs_progress(gs_ctx* ctx, int block) {
+    if (!ctx) return fail(GS_EINVAL, "ctx is NULL");
+    Ctx& cx = ctx->impl;
+    if (hipSetDevice(cx.device) != hipSuccess) return fail(GS_EDEVICE, "hipSetDevice failed");
+    int rc = progress(cx, block != 0);
+    if (rc) return rc;
+    int n = 0;
+    for (auto& kv : cx.jobs) n += kv.second->stage != JS_DONE;
+    return n;
+}
+
+int gs_poll(gs_ctx* ctx, uint64_t ticket, gs_result* res) {
+    if (!ctx) return fail(GS_EINVAL, "ctx is NULL");
+    Ctx& cx = ctx->impl;
+    auto it = cx.jobs.find(ticket);
+    if (it == cx.jobs.end()) return fail(GS_EINVAL, "unknown ticket");
+    if (it->second->stage != JS_DONE) {
+        if (hipSetDevice(cx.device) != hipSuccess) return fail(GS_EDEVICE, "hipSetDevice failed");
+        int rc = progress(cx, false);
+        if (rc) return rc;
+        if (it->second->stage != JS_DONE) return GS_PENDING;
+    }
+    return take_result(cx, ticket, res);
+}
+
+int gs_wait(gs_ctx* ctx, uint64_t ticket, gs_result* res) {
+    if (!ctx) return fail(GS_EINVAL, "ctx is NULL");
+    Ctx& cx = ctx->impl;
+    if (hipSetDevice(cx.device) != hipSuccess) return fail(GS_EDEVICE, "hipSetDevice failed");
+    return wait_job(cx, ticket, res);
+}
+
+int gs_cancel(gs_ctx* ctx, uint64_t ticket) {
+    if (!ctx) return fail(GS_EINVAL, "ctx is NULL");
+    auto it = ctx->impl.jobs.find(ticket);
+    if (it == ctx->impl.jobs.end()) return fail(GS_EINVAL, "unknown ticket");
+    it->second->cancel = true;
+    return GS_OK;
+}
+
+int gs_batch_solve(gs_ctx* ctx, int nreq, const gs_request* reqs, gs_result* res) {
+    if (!ctx) return fail(GS_EINVAL, "ctx is NULL");
+    if (nreq < 0 || (nreq > 0 && !reqs)) return fail(GS_EINVAL, "invalid request array");
+    Ctx& cx = ctx->impl;
+    if (hipSetDevice(cx.device) != hipSuccess) return fail(GS_EDEVICE, "hipSetDevice failed");
+    std::vector<uint64_t> tickets;
+    tickets.reserve(nreq);
+    for (int i = 0; i < nreq; ++i) {
+        uint64_t t = 0;
+        int rc = submit_job(cx, &reqs[i], &t);
+        if (rc) {
+            const std::string msg = "request " + std::to_string(i) + ": " + g_err;
+            for (uint64_t u : tickets) {   // nothing has been launched yet
+                Job* j = cx.jobs[u].get();
+                for (auto& kv : cx.c32) {
+                    auto& qq = kv.second->queue;
+                    qq.erase(std::remove(qq.begin(), qq.end(), j), qq.end());
+                }
+                for (auto& kv : cx.c64) {
+                    auto& qq = kv.second->queue;
+                    qq.erase(std::remove(qq.begin(), qq.end(), j), qq.end());
+                }
+                cx.jobs.erase(u);
+            }
+            return fail(rc, msg);
+        }
+        tickets.push_back(t);
+    }
+    int first_err = GS_OK;
+    for (int i = 0; i < nreq; ++i) {
+        gs_result r;
+        int rc = wait_job(cx, tickets[i], &r);
+        if (rc < 0 && cx.jobs.count(tickets[i])) return rc;   // device failure: the context is unusable
+        if (res) res[i] = r;
+        if (rc < 0 && first_err == GS_OK) first_err = rc;
+    }
+    (void)first_err;
+    return GS_OK;
 }
 
 int gs_kernel_timer_start(gs_ctx* ctx, int kind) {
     if (!ctx) return fail(GS_EINVAL, "ctx is NULL");
     if (kind < -1 || kind >= KK_COUNT) return fail(GS_EINVAL, "unknown kernel kind");
-    Timer& t = ctx->impl.timer;
+    TimerTotals& t = ctx->impl.timer;
     t.kind = kind;
-    t.rec.clear();
     t.ms = 0.0;
     t.bytes = 0.0;
     t.launches = 0;
@@ -806,7 +1423,7 @@ int gs_kernel_timer_start(gs_ctx* ctx, int kind) {
 
 int gs_kernel_timer_read(gs_ctx* ctx, double* total_ms, double* total_bytes, long long* launches) {
     if (!ctx) return fail(GS_EINVAL, "ctx is NULL");
-    const Timer& t = ctx->impl.timer;
+    const TimerTotals& t = ctx->impl.timer;
     if (total_ms) *total_ms = t.ms;
     if (total_bytes) *total_bytes = t.bytes;
     if (launches) *launches = t.launches;

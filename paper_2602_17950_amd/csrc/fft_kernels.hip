@@ -15,6 +15,11 @@
 // Stockham autosort radix-4 stages plus one radix-2 stage for odd log2 N, with
 // the data of all lines of a block resident in LDS and the butterflies of a
 // stage held in registers between two barriers.
+//
+// Every pass serves all slots (independent solves of one grid shape) of a
+// launch at once: blockIdx.y selects the slot, whose descriptor names the
+// buffers, the problem and the solver state. A slot whose solve has finished
+// returns at once.
 #include "device_common.h"
 #include "control.h"
 
@@ -118,12 +123,15 @@ __device__ __forceinline__ void lds_fft(cpx<R>* buf, const cpx<R>* __restrict__ 
 // DUAL (with PRO_DIR): components 3..5 of the output are the plain transform
 // of aux1 (Phi), so that the middle pass sees both spectra.
 template <typename R, int N, int TILE, int PRO, bool DUAL>
-__global__ __launch_bounds__(NT) void k_fwdT(cpx<R>* inp, cpx<R>* __restrict__ out, int A, int B,
-                                             const cpx<R>* __restrict__ aux0,
-                                             const cpx<R>* __restrict__ aux1,
-                                             const SolveState* __restrict__ st,
-                                             const cpx<R>* __restrict__ tw) {
-    if (st && st->done) return;
+__global__ __launch_bounds__(NT) void k_fwdT(const Slot<R>* __restrict__ slots, int iin, int iout, int iaux0,
+                                             int iaux1, int A, int B, const cpx<R>* __restrict__ tw) {
+    const Slot<R>& S = slots[blockIdx.y];
+    const SolveState* st = S.st;
+    if (st->done) return;
+    cpx<R>* inp = S.buf[iin];
+    cpx<R>* __restrict__ out = S.buf[iout];
+    const cpx<R>* __restrict__ aux0 = iaux0 >= 0 ? S.buf[iaux0] : nullptr;
+    const cpx<R>* __restrict__ aux1 = iaux1 >= 0 ? S.buf[iaux1] : nullptr;
     constexpr int PITCH = N + 1;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
@@ -190,13 +198,20 @@ __global__ __launch_bounds__(NT) void k_fwdT(cpx<R>* inp, cpx<R>* __restrict__ o
 //              out = IFFT(A) + Omega y k_x uin / Nx, out2 = IFFT(B)
 //              (uin = the x-transformed input, same layout)
 template <typename R, int N, int TILE, int EPI>
-__global__ __launch_bounds__(NT) void k_invT(const cpx<R>* __restrict__ in, const cpx<R>* __restrict__ in2,
-                                             cpx<R>* __restrict__ out, cpx<R>* __restrict__ out2,
-                                             int B, int Cc, int nin, Phys p,
-                                             const cpx<R>* __restrict__ uin, double scale,
-                                             const R* __restrict__ pv, const SolveState* __restrict__ st,
-                                             int use_invnP, const cpx<R>* __restrict__ tw) {
-    if (st && st->done) return;
+__global__ __launch_bounds__(NT) void k_invT(const Slot<R>* __restrict__ slots, int iin, int iin2, int iout,
+                                             int iout2, int iuin, int B, int Cc, double scale, int use_invnP,
+                                             int rot_any, const cpx<R>* __restrict__ tw) {
+    const Slot<R>& S = slots[blockIdx.y];
+    const SolveState* st = S.st;
+    if (st->done) return;
+    const Phys p = S.p;
+    // the rotation input/output pair exists for rotating slots of the H_L chain
+    const int nin = (EPI != EPI_SCALE && rot_any && p.omega != 0.0) ? 2 : 1;
+    const cpx<R>* __restrict__ in = S.buf[iin];
+    const cpx<R>* __restrict__ in2 = nin == 2 ? S.buf[iin2] : nullptr;
+    cpx<R>* __restrict__ out = S.buf[iout];
+    cpx<R>* __restrict__ out2 = (nin == 2 && iout2 >= 0) ? S.buf[iout2] : nullptr;
+    const cpx<R>* __restrict__ uin = iuin >= 0 ? S.buf[iuin] : nullptr;
     constexpr int PITCH = N + 1;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
@@ -236,12 +251,14 @@ __global__ __launch_bounds__(NT) void k_invT(const cpx<R>* __restrict__ in, cons
             if (nin == 2) v = v - (R)(p.omega * x) * lds2[l * PITCH + m];
             out[go] = v;
         } else if (EPI == EPI_ROTX) {
-            const int jx = bb, iy = m;
-            const double kx = wavenum(jx, p.n[0], p.L[0]);
-            const double y = -p.L[1] + iy * p.h[1];
-            v = v + (R)(p.omega * y * kx / p.n[0]) * uin[go];
+            if (nin == 2) {
+                const int jx = bb, iy = m;
+                const double kx = wavenum(jx, p.n[0], p.L[0]);
+                const double y = -p.L[1] + iy * p.h[1];
+                v = v + (R)(p.omega * y * kx / p.n[0]) * uin[go];
+                out2[go] = lds2[l * PITCH + m];
+            }
             out[go] = v;
-            if (nin == 2) out2[go] = lds2[l * PITCH + m];
         }
     }
 }
@@ -252,11 +269,14 @@ __global__ __launch_bounds__(NT) void k_invT(const cpx<R>* __restrict__ in, cons
 // Re<phi,Pr>, |Pr|^2, Re<Pr,P^{n-1}>) and, in the last block, ctrl_dir.
 // ---------------------------------------------------------------------------
 template <typename R, int N, int TILE>
-__global__ __launch_bounds__(NT) void k_invT_pre(const cpx<R>* __restrict__ in, cpx<R>* __restrict__ out, int B,
-                                                 int Cc, const R* __restrict__ pv, Fields<R> f, Phys p,
-                                                 SolveState* st, RedBuf rb, int dir,
-                                                 const cpx<R>* __restrict__ tw) {
-    if (dir && st->done) return;
+__global__ __launch_bounds__(NT) void k_invT_pre(const Slot<R>* __restrict__ slots, int iin, int iout, int B,
+                                                 int Cc, int dir, const cpx<R>* __restrict__ tw) {
+    const Slot<R>& S = slots[blockIdx.y];
+    SolveState* st = S.st;
+    if (st->done) return;
+    const cpx<R>* __restrict__ in = S.buf[iin];
+    cpx<R>* __restrict__ out = S.buf[iout];
+    const R* __restrict__ pv = S.pv;
     constexpr int PITCH = N + 1;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
@@ -274,8 +294,10 @@ __global__ __launch_bounds__(NT) void k_invT_pre(const cpx<R>* __restrict__ in, 
     __syncthreads();
     lds_fft<R, N, TILE, PITCH, true>(lds, tw);
     double acc[NS_DIR] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    const cpx<R>* r = dir ? f.r[st->cur] : nullptr;
-    const cpx<R>* rp = dir ? f.r[st->cur ^ 1] : nullptr;
+    const cpx<R>* r = dir ? S.buf[B_R0 + st->cur] : nullptr;
+    const cpx<R>* rp = dir ? S.buf[B_R0 + (st->cur ^ 1)] : nullptr;
+    const cpx<R>* phi = S.buf[B_PHI];
+    const cpx<R>* Pprev = S.buf[B_P];
     for (int e = threadIdx.x; e < TILE * N; e += NT) {
         const int l = e / N, m = e - l * N;
         const long long go = (((long long)c * B + bb) * Cc + c0 + l) * N + m;
@@ -285,19 +307,19 @@ __global__ __launch_bounds__(NT) void k_invT_pre(const cpx<R>* __restrict__ in, 
             const cpx<double> w = wid(v);
             acc[0] += re_dot(wid(r[go]), w);
             acc[1] += re_dot(wid(rp[go]), w);
-            acc[2] += re_dot(wid(f.phi[go]), w);
+            acc[2] += re_dot(wid(phi[go]), w);
             acc[3] += cabs2(w);
-            acc[4] += re_dot(wid(f.P[go]), w);
+            acc[4] += re_dot(wid(Pprev[go]), w);
         }
     }
     if (!dir) return;
     bsum<NS_DIR>(acc);
-    if (publish<NS_DIR>(acc, rb.pw, rb.counter + 2)) {
+    if (publish<NS_DIR>(acc, S.red_pw, S.counter + 2)) {
         double tot[NS_DIR];
-        gather<NS_DIR>(tot, rb.pw, gridDim.x, NS_MAX);
+        gather<NS_DIR>(tot, S.red_pw, gridDim.x, NS_MAX);
         if (threadIdx.x == 0) {
-            ctrl_dir(st, p, tot);
-            rb.counter[2] = 0;
+            ctrl_dir(st, S.p, tot);
+            S.counter[2] = 0;
         }
     }
 }
@@ -314,11 +336,18 @@ __global__ __launch_bounds__(NT) void k_invT_pre(const cpx<R>* __restrict__ in, 
 //            of 1/2|k|^2 |Phi^_l|^2, 1/2|k|^2 Re Phi^_l conj(v_l), 1/2|k|^2 |v_l|^2.
 //   MID_PRE: A = v_l / (alpha_l + 1/2 |k|^2) / M.
 template <typename R, int N, int LPB, int OP>
-__global__ __launch_bounds__(NT) void k_mid(const cpx<R>* __restrict__ in, const cpx<R>* __restrict__ in2,
-                                            cpx<R>* __restrict__ outA, cpx<R>* __restrict__ outB, int nlines,
-                                            int rot, Phys p, const SolveState* __restrict__ st,
-                                            double* __restrict__ red, const cpx<R>* __restrict__ tw) {
-    if (st && st->done) return;
+__global__ __launch_bounds__(NT) void k_mid(const Slot<R>* __restrict__ slots, int iin, int ioutA, int ioutB,
+                                            int nlines, int rot_any, const cpx<R>* __restrict__ tw) {
+    const Slot<R>& S = slots[blockIdx.y];
+    const SolveState* st = S.st;
+    if (st->done) return;
+    const Phys p = S.p;
+    const int rot = rot_any && p.omega != 0.0;
+    const cpx<R>* __restrict__ in = S.buf[iin];
+    const cpx<R>* __restrict__ in2 = (OP == MID_HLX) ? in + 3 * p.M : nullptr;
+    cpx<R>* __restrict__ outA = S.buf[ioutA];
+    cpx<R>* __restrict__ outB = ioutB >= 0 ? S.buf[ioutB] : nullptr;
+    double* __restrict__ red = S.red_mid;
     constexpr int PITCH = N + 1;
     constexpr int NLN = 3 * LPB;
     constexpr bool HL = OP == MID_HL || OP == MID_HLX;
@@ -423,7 +452,7 @@ __global__ __launch_bounds__(NT) void k_mid(const cpx<R>* __restrict__ in, const
         outA[go] = v;
         if (doB) outB[go] = Y[L * PITCH + m];
     }
-    if (HL && red) {
+    if (HL) {
         bsum<(X2 ? NS_KIN : 4)>(acc);
         if (threadIdx.x == 0)
             for (int k = 0; k < (X2 ? NS_KIN : 4); ++k) red[(long long)blockIdx.x * RED_MID_STRIDE + k] = acc[k];
@@ -445,26 +474,26 @@ constexpr int lpb_mid(int N) { return N >= 256 ? 1 : (N >= 128 ? 2 : (N >= 64 ? 
 int mid_blocks(int N, int nlines) { return nlines / lpb_mid(N); }
 
 template <typename R, int N>
-static hipError_t fwdT_n(int pro, int dual, cpx<R>* inp, cpx<R>* out, int A, int B, int ncomp, const cpx<R>* aux0,
-                         const cpx<R>* aux1, const SolveState* st, const cpx<R>* tw, hipStream_t s) {
+static hipError_t fwdT_n(int pro, int dual, const Slot<R>* slots, int nslots, int in, int out, int aux0, int aux1,
+                         int A, int B, int ncomp, const cpx<R>* tw, hipStream_t s) {
     constexpr int TILE = tile_fwd<R>(N);
     if (B % TILE) return hipErrorInvalidValue;
     if (dual && pro != PRO_DIR) return hipErrorInvalidValue;
     const size_t lds = (size_t)TILE * (N + 1) * sizeof(cpx<R>);
-    dim3 grid((unsigned)((long long)(dual ? 6 : ncomp) * A * (B / TILE)));
+    dim3 grid((unsigned)((long long)(dual ? 6 : ncomp) * A * (B / TILE)), (unsigned)nslots);
     if (dual) {
-        GS_LAUNCH((k_fwdT<R, N, TILE, PRO_DIR, true>), grid, dim3(NT), lds, s, inp, out, A, B, aux0, aux1, st, tw);
+        GS_LAUNCH((k_fwdT<R, N, TILE, PRO_DIR, true>), grid, dim3(NT), lds, s, slots, in, out, aux0, aux1, A, B, tw);
         return hipGetLastError();
     }
     switch (pro) {
     case PRO_PLAIN:
-        GS_LAUNCH((k_fwdT<R, N, TILE, PRO_PLAIN, false>), grid, dim3(NT), lds, s, inp, out, A, B, aux0, aux1, st, tw);
+        GS_LAUNCH((k_fwdT<R, N, TILE, PRO_PLAIN, false>), grid, dim3(NT), lds, s, slots, in, out, aux0, aux1, A, B, tw);
         break;
     case PRO_UPDATE:
-        GS_LAUNCH((k_fwdT<R, N, TILE, PRO_UPDATE, false>), grid, dim3(NT), lds, s, inp, out, A, B, aux0, aux1, st, tw);
+        GS_LAUNCH((k_fwdT<R, N, TILE, PRO_UPDATE, false>), grid, dim3(NT), lds, s, slots, in, out, aux0, aux1, A, B, tw);
         break;
     case PRO_DIR:
-        GS_LAUNCH((k_fwdT<R, N, TILE, PRO_DIR, false>), grid, dim3(NT), lds, s, inp, out, A, B, aux0, aux1, st, tw);
+        GS_LAUNCH((k_fwdT<R, N, TILE, PRO_DIR, false>), grid, dim3(NT), lds, s, slots, in, out, aux0, aux1, A, B, tw);
         break;
     default:
         return hipErrorInvalidValue;
@@ -473,22 +502,21 @@ static hipError_t fwdT_n(int pro, int dual, cpx<R>* inp, cpx<R>* out, int A, int
 }
 
 template <typename R, int N>
-static hipError_t invT_n(int epi, int nin, const cpx<R>* in, const cpx<R>* in2, cpx<R>* out, cpx<R>* out2,
-                         int B, int Cc, const Phys& p, const cpx<R>* uin, double scale, const R* pv,
-                         const SolveState* st, int use_invnP, const cpx<R>* tw, hipStream_t s) {
+static hipError_t invT_n(int epi, const Slot<R>* slots, int nslots, int in, int in2, int out, int out2, int uin,
+                         int B, int Cc, double scale, int use_invnP, int rot_any, const cpx<R>* tw, hipStream_t s) {
     constexpr int TILE = tile_inv<R>(N);
     if (Cc % TILE) return hipErrorInvalidValue;
-    const size_t lds = (size_t)2 * TILE * (N + 1) * sizeof(cpx<R>);
-    dim3 grid((unsigned)(3LL * B * (Cc / TILE)));
+    const size_t lds = (size_t)(epi == EPI_SCALE ? 1 : 2) * TILE * (N + 1) * sizeof(cpx<R>);
+    dim3 grid((unsigned)(3LL * B * (Cc / TILE)), (unsigned)nslots);
     switch (epi) {
     case EPI_SCALE:
-        GS_LAUNCH((k_invT<R, N, TILE, EPI_SCALE>), grid, dim3(NT), lds, s, in, in2, out, out2, B, Cc, nin, p, uin, scale, pv, st, use_invnP, tw);
+        GS_LAUNCH((k_invT<R, N, TILE, EPI_SCALE>), grid, dim3(NT), lds, s, slots, in, in2, out, out2, uin, B, Cc, scale, use_invnP, rot_any, tw);
         break;
     case EPI_HL:
-        GS_LAUNCH((k_invT<R, N, TILE, EPI_HL>), grid, dim3(NT), lds, s, in, in2, out, out2, B, Cc, nin, p, uin, scale, pv, st, use_invnP, tw);
+        GS_LAUNCH((k_invT<R, N, TILE, EPI_HL>), grid, dim3(NT), lds, s, slots, in, in2, out, out2, uin, B, Cc, scale, use_invnP, rot_any, tw);
         break;
     case EPI_ROTX:
-        GS_LAUNCH((k_invT<R, N, TILE, EPI_ROTX>), grid, dim3(NT), lds, s, in, in2, out, out2, B, Cc, nin, p, uin, scale, pv, st, use_invnP, tw);
+        GS_LAUNCH((k_invT<R, N, TILE, EPI_ROTX>), grid, dim3(NT), lds, s, slots, in, in2, out, out2, uin, B, Cc, scale, use_invnP, rot_any, tw);
         break;
     default:
         return hipErrorInvalidValue;
@@ -497,33 +525,33 @@ static hipError_t invT_n(int epi, int nin, const cpx<R>* in, const cpx<R>* in2, 
 }
 
 template <typename R, int N>
-static hipError_t invT_pre_n(const cpx<R>* in, cpx<R>* out, int B, int Cc, const R* pv, const Fields<R>& f,
-                             const Phys& p, SolveState* st, RedBuf rb, int dir, const cpx<R>* tw, hipStream_t s) {
+static hipError_t invT_pre_n(const Slot<R>* slots, int nslots, int in, int out, int B, int Cc, int dir,
+                             const cpx<R>* tw, hipStream_t s) {
     constexpr int TILE = tile_inv<R>(N);
     if (Cc % TILE) return hipErrorInvalidValue;
     const size_t lds = (size_t)TILE * (N + 1) * sizeof(cpx<R>);
-    dim3 grid((unsigned)(3LL * B * (Cc / TILE)));
+    dim3 grid((unsigned)(3LL * B * (Cc / TILE)), (unsigned)nslots);
     // the partial-sum buffer holds 3 Nz Ny / 2 rows (TILE >= 2)
     static_assert(TILE >= 2, "partial-sum rows");
-    GS_LAUNCH((k_invT_pre<R, N, TILE>), grid, dim3(NT), lds, s, in, out, B, Cc, pv, f, p, st, rb, dir, tw);
+    GS_LAUNCH((k_invT_pre<R, N, TILE>), grid, dim3(NT), lds, s, slots, in, out, B, Cc, dir, tw);
     return hipGetLastError();
 }
 
 template <typename R, int N>
-static hipError_t mid_n(int op, int rot, const cpx<R>* in, const cpx<R>* in2, cpx<R>* outA, cpx<R>* outB, int nlines,
-                        const Phys& p, const SolveState* st, double* red, const cpx<R>* tw, hipStream_t s) {
+static hipError_t mid_n(int op, const Slot<R>* slots, int nslots, int in, int outA, int outB, int nlines,
+                        int rot_any, const cpx<R>* tw, hipStream_t s) {
     constexpr int LPB = lpb_mid(N);
     if (nlines % LPB) return hipErrorInvalidValue;
-    const int nB = ((op == MID_HL || op == MID_HLX) && rot) ? 1 : 0;
+    const int nB = ((op == MID_HL || op == MID_HLX) && rot_any) ? 1 : 0;
     const int nX = op == MID_HLX ? 2 : 1;
     const size_t lds = (size_t)(nB + nX) * 3 * LPB * (N + 1) * sizeof(cpx<R>);
-    dim3 grid((unsigned)(nlines / LPB));
+    dim3 grid((unsigned)(nlines / LPB), (unsigned)nslots);
     if (op == MID_HL)
-        GS_LAUNCH((k_mid<R, N, LPB, MID_HL>), grid, dim3(NT), lds, s, in, in2, outA, outB, nlines, rot, p, st, red, tw);
+        GS_LAUNCH((k_mid<R, N, LPB, MID_HL>), grid, dim3(NT), lds, s, slots, in, outA, outB, nlines, rot_any, tw);
     else if (op == MID_HLX)
-        GS_LAUNCH((k_mid<R, N, LPB, MID_HLX>), grid, dim3(NT), lds, s, in, in2, outA, outB, nlines, rot, p, st, red, tw);
+        GS_LAUNCH((k_mid<R, N, LPB, MID_HLX>), grid, dim3(NT), lds, s, slots, in, outA, outB, nlines, rot_any, tw);
     else
-        GS_LAUNCH((k_mid<R, N, LPB, MID_PRE>), grid, dim3(NT), lds, s, in, in2, outA, outB, nlines, rot, p, st, red, tw);
+        GS_LAUNCH((k_mid<R, N, LPB, MID_PRE>), grid, dim3(NT), lds, s, slots, in, outA, outB, nlines, 0, tw);
     return hipGetLastError();
 }
 
@@ -540,50 +568,47 @@ static hipError_t mid_n(int op, int rot, const cpx<R>* in, const cpx<R>* in2, cp
     }
 
 template <typename R>
-hipError_t launch_fwdT(int N, int pro, int dual, cpx<R>* inp, cpx<R>* out, int A, int B, int ncomp,
-                       const cpx<R>* aux0, const cpx<R>* aux1, const SolveState* st, const cpx<R>* tw,
+hipError_t launch_fwdT(int N, int pro, int dual, const Slot<R>* slots, int nslots, int in, int out, int aux0,
+                       int aux1, int A, int B, int ncomp, const cpx<R>* tw, hipStream_t s) {
+#define CALL(n) fwdT_n<R, n>(pro, dual, slots, nslots, in, out, aux0, aux1, A, B, ncomp, tw, s)
+    GS_SWITCH_N(CALL)
+#undef CALL
+}
+
+template <typename R>
+hipError_t launch_invT(int N, int epi, const Slot<R>* slots, int nslots, int in, int in2, int out, int out2,
+                       int uin, int B, int Cc, double scale, int use_invnP, int rot_any, const cpx<R>* tw,
                        hipStream_t s) {
-#define CALL(n) fwdT_n<R, n>(pro, dual, inp, out, A, B, ncomp, aux0, aux1, st, tw, s)
+#define CALL(n) invT_n<R, n>(epi, slots, nslots, in, in2, out, out2, uin, B, Cc, scale, use_invnP, rot_any, tw, s)
     GS_SWITCH_N(CALL)
 #undef CALL
 }
 
 template <typename R>
-hipError_t launch_invT(int N, int epi, int nin, const cpx<R>* in, const cpx<R>* in2, cpx<R>* out,
-                       cpx<R>* out2, int B, int Cc, const Phys& p, const cpx<R>* uin, double scale,
-                       const R* pv, const SolveState* st, int use_invnP, const cpx<R>* tw, hipStream_t s) {
-#define CALL(n) invT_n<R, n>(epi, nin, in, in2, out, out2, B, Cc, p, uin, scale, pv, st, use_invnP, tw, s)
+hipError_t launch_invT_pre(int N, const Slot<R>* slots, int nslots, int in, int out, int B, int Cc, int dir,
+                           const cpx<R>* tw, hipStream_t s) {
+#define CALL(n) invT_pre_n<R, n>(slots, nslots, in, out, B, Cc, dir, tw, s)
     GS_SWITCH_N(CALL)
 #undef CALL
 }
 
 template <typename R>
-hipError_t launch_invT_pre(int N, const cpx<R>* in, cpx<R>* out, int B, int Cc, const R* pv, const Fields<R>& f,
-                           const Phys& p, SolveState* st, RedBuf rb, int dir, const cpx<R>* tw, hipStream_t s) {
-#define CALL(n) invT_pre_n<R, n>(in, out, B, Cc, pv, f, p, st, rb, dir, tw, s)
-    GS_SWITCH_N(CALL)
-#undef CALL
-}
-
-template <typename R>
-hipError_t launch_mid(int N, int op, int rot, const cpx<R>* in, const cpx<R>* in2, cpx<R>* outA, cpx<R>* outB,
-                      int nlines, const Phys& p, const SolveState* st, double* red_mid,
-                      const cpx<R>* tw, hipStream_t s) {
-#define CALL(n) mid_n<R, n>(op, rot, in, in2, outA, outB, nlines, p, st, red_mid, tw, s)
+hipError_t launch_mid(int N, int op, const Slot<R>* slots, int nslots, int in, int outA, int outB, int nlines,
+                      int rot_any, const cpx<R>* tw, hipStream_t s) {
+#define CALL(n) mid_n<R, n>(op, slots, nslots, in, outA, outB, nlines, rot_any, tw, s)
     GS_SWITCH_N(CALL)
 #undef CALL
 }
 
 #define GS_INST_FFT(R)                                                                                           \
-    template hipError_t launch_fwdT<R>(int, int, int, cpx<R>*, cpx<R>*, int, int, int, const cpx<R>*,            \
-                                       const cpx<R>*, const SolveState*, const cpx<R>*, hipStream_t);            \
-    template hipError_t launch_invT<R>(int, int, int, const cpx<R>*, const cpx<R>*, cpx<R>*, cpx<R>*, int, int,  \
-                                       const Phys&, const cpx<R>*, double, const R*, const SolveState*, int,      \
+    template hipError_t launch_fwdT<R>(int, int, int, const Slot<R>*, int, int, int, int, int, int, int, int,     \
                                        const cpx<R>*, hipStream_t);                                              \
-    template hipError_t launch_invT_pre<R>(int, const cpx<R>*, cpx<R>*, int, int, const R*, const Fields<R>&,    \
-                                           const Phys&, SolveState*, RedBuf, int, const cpx<R>*, hipStream_t);   \
-    template hipError_t launch_mid<R>(int, int, int, const cpx<R>*, const cpx<R>*, cpx<R>*, cpx<R>*, int,        \
-                                      const Phys&, const SolveState*, double*, const cpx<R>*, hipStream_t);
+    template hipError_t launch_invT<R>(int, int, const Slot<R>*, int, int, int, int, int, int, int, int, double,  \
+                                       int, int, const cpx<R>*, hipStream_t);                                    \
+    template hipError_t launch_invT_pre<R>(int, const Slot<R>*, int, int, int, int, int, int, const cpx<R>*,      \
+                                           hipStream_t);                                                         \
+    template hipError_t launch_mid<R>(int, int, const Slot<R>*, int, int, int, int, int, int, const cpx<R>*,      \
+                                      hipStream_t);
 GS_INST_FFT(double)
 GS_INST_FFT(float)
 

@@ -1,6 +1,7 @@
 // Internal declarations of the gfx950 ground-state library: complex helpers,
-// the problem description handed to kernels, the device-resident solver state
-// and the launch entry points of the kernel translation units.
+// the problem description handed to kernels, the device-resident solver state,
+// the per-solve slot descriptors and the launch entry points of the kernel
+// translation units.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
@@ -57,7 +58,7 @@ template <typename R> __host__ __device__ __forceinline__ R cabs2(cpx<R> a) { re
 template <typename R> __host__ __device__ __forceinline__ cpx<double> wid(cpx<R> a) { return {(double)a.x, (double)a.y}; }
 
 // ---------------------------------------------------------------------------
-// problem description passed by value to kernels
+// problem description of one solve
 // ---------------------------------------------------------------------------
 struct Phys {
     int dim;                  // 2 or 3
@@ -91,9 +92,8 @@ __device__ __forceinline__ double wavenum(int j, int n, double L) {
 // ---------------------------------------------------------------------------
 // device-resident solver state (one per solve). All control decisions of the
 // PCG iteration are taken on the device from these scalars, so a chunk of
-// iterations can be enqueued (or replayed as a graph) without host round trips.
+// iterations can be enqueued without host round trips.
 // ---------------------------------------------------------------------------
-enum : int { ST_RUNNING = 0 };
 enum : int { PH_FP64 = 0, PH_FP32 = 1 };
 
 struct SolveState {
@@ -103,7 +103,7 @@ struct SolveState {
     int iter;            // accepted PCG steps
     int iter_phase;      // accepted steps in the current precision phase
     int backtracks, resets;
-    int pending_step;    // 1: the next chain input Phi <- (c Phi + s P/|P|) * inv_norm
+    int pending_step;    // 1: Phi <- (c Phi + s P/|P|) * inv_norm before the next use
     int have_prev;       // r^{n-1}, P^{n-1} valid (beta may be nonzero)
     int cur;             // index of the r buffer that holds r^n
     int final_pending;   // energy criterion met: evaluate the new iterate, then stop
@@ -127,25 +127,52 @@ struct SolveState {
     double a, b, theta, c, s, inv_norm, dE, dE_last;
 };
 
-// reduction scratch: per-block partial sums, a completion counter per reducer
-struct RedBuf {
-    double* mid;        // [nblk_mid][RED_MID_STRIDE] spectral sums of the middle pass
-    double* pw;         // [rows][NS_MAX] partial sums of the reducing kernel
-    unsigned* counter;  // one counter per reducing kernel
+// ---------------------------------------------------------------------------
+// per-solve slot: device buffers, problem, state and reduction scratch. Every
+// kernel serves all slots of one grid class at once (blockIdx.y = slot) and
+// names the buffers it reads and writes by these indices.
+// ---------------------------------------------------------------------------
+enum BufSel : int {
+    B_PHI = 0,   // Phi
+    B_HL,        // H_L Phi
+    B_R0, B_R1,  // r^n and r^{n-1} (double buffer, SolveState::cur)
+    B_PR,        // preconditioned residual
+    B_P,         // search direction P^n (P^{n-1} before the direction pass)
+    B_HLP,       // H_L P^ (P^ = P / |P|)
+    B_U,         // preconditioner input P_V^{1/2} r
+    B_T6A, B_T6B,           // six-component scratch (P^ and Phi transformed together)
+    B_T0, B_T1, B_T2, B_T3, // scratch
+    B_X0, B_X1,             // caller buffers (operator-level entry points)
+    NBUF,
+    B_NONE = -1
+};
+constexpr int NS_MAX = 64;          // row stride of the per-block partial sums
+constexpr int RED_MID_STRIDE = 12;  // row stride of the middle-pass partial sums
+constexpr int NCOUNTERS = 8;
+
+template <typename R>
+struct Slot {
+    cpx<R>* buf[NBUF];
+    R* pv;               // [3][M] P_V^{1/2} factors (alpha_l + V + c0 rho)^{-1/2}
+    SolveState* st;
+    double* red_mid;     // [nblk_mid][RED_MID_STRIDE]
+    double* red_pw;      // [rows][NS_MAX]
+    unsigned* counter;   // [NCOUNTERS] completion counters of the reducing kernels
+    Phys p;
+};
+
+// reduction geometry of a grid class (same for every slot of the class)
+struct RedGeom {
     int nblk_mid;
     int nblk_pw;
 };
-constexpr int NS_MAX = 64;
-constexpr int RED_MID_STRIDE = 12;
 
 // ---------------------------------------------------------------------------
-// FFT pass launchers (fft_kernels.hip)
+// FFT pass launchers (fft_kernels.hip); nslots = grid.y
 // ---------------------------------------------------------------------------
 enum Pro : int { PRO_PLAIN = 0, PRO_UPDATE = 1, PRO_DIR = 2 };
-enum Epi : int { EPI_SCALE = 0, EPI_HL = 1, EPI_ROTX = 2, EPI_PRE = 3 };
+enum Epi : int { EPI_SCALE = 0, EPI_HL = 1, EPI_ROTX = 2 };
 enum MidOp : int { MID_HL = 0, MID_PRE = 1, MID_HLX = 2 };
-
-template <typename R> struct Fields;
 
 // Forward transform along the contiguous axis of in[ncomp][A][B][N], written
 // with that axis moved to the slowest position: out[ncomp][N][A][B].
@@ -155,62 +182,50 @@ template <typename R> struct Fields;
 //   PRO_DIR:    in <- -aux0 + beta in - dphi aux1 (written back), transform invnP * in
 // dual (PRO_DIR only): also transform aux1 into components 3..5 of out.
 template <typename R>
-hipError_t launch_fwdT(int N, int pro, int dual, cpx<R>* inp, cpx<R>* out, int A, int B, int ncomp,
-                       const cpx<R>* aux0, const cpx<R>* aux1, const SolveState* st, const cpx<R>* tw,
-                       hipStream_t s);
+hipError_t launch_fwdT(int N, int pro, int dual, const Slot<R>* slots, int nslots, int in, int out, int aux0,
+                       int aux1, int A, int B, int ncomp, const cpx<R>* tw, hipStream_t s);
 
-// Inverse transform along the slowest axis of in[3][N][B][Cc] (and in2 when
-// nin = 2), written with that axis contiguous: out[3][B][Cc][N]; the epilogue
-// adds the physical-space terms (see fft_kernels.hip).
+// Inverse transform along the slowest axis of in[3][N][B][Cc] (and in2 when the
+// slot rotates), written with that axis contiguous: out[3][B][Cc][N]; the
+// epilogue adds the physical-space terms (see fft_kernels.hip).
+// rot_any: some slot of the launch rotates (LDS and buffers for the second
+// input/output are provided); each slot decides from its own Omega.
 template <typename R>
-hipError_t launch_invT(int N, int epi, int nin, const cpx<R>* in, const cpx<R>* in2, cpx<R>* out,
-                       cpx<R>* out2, int B, int Cc, const Phys& p, const cpx<R>* uin, double scale,
-                       const R* pv, const SolveState* st, int use_invnP, const cpx<R>* tw, hipStream_t s);
+hipError_t launch_invT(int N, int epi, const Slot<R>* slots, int nslots, int in, int in2, int out, int out2,
+                       int uin, int B, int Cc, double scale, int use_invnP, int rot_any, const cpx<R>* tw,
+                       hipStream_t s);
 
 // Last pass of the preconditioner: out = pv * IFFT(in); with dir = 1 also the
 // direction reductions and the direction control (SolveState written).
 template <typename R>
-hipError_t launch_invT_pre(int N, const cpx<R>* in, cpx<R>* out, int B, int Cc, const R* pv, const Fields<R>& f,
-                           const Phys& p, SolveState* st, RedBuf rb, int dir, const cpx<R>* tw, hipStream_t s);
+hipError_t launch_invT_pre(int N, const Slot<R>* slots, int nslots, int in, int out, int B, int Cc, int dir,
+                           const cpx<R>* tw, hipStream_t s);
 
 // Middle pass: transform the contiguous axis of three component lines,
 // apply the spectral operator (all three components at each wavenumber),
-// transform back. in/outA/outB are [3][nlines][N]; in2 (MID_HLX) holds the
-// spectrum of Phi in the same layout.
+// transform back. in/outA/outB are [3][nlines][N]; for MID_HLX components 3..5
+// of `in` hold the spectrum of Phi.
 template <typename R>
-hipError_t launch_mid(int N, int op, int rot, const cpx<R>* in, const cpx<R>* in2, cpx<R>* outA, cpx<R>* outB,
-                      int nlines, const Phys& p, const SolveState* st, double* red_mid,
-                      const cpx<R>* tw, hipStream_t s);
+hipError_t launch_mid(int N, int op, const Slot<R>* slots, int nslots, int in, int outA, int outB, int nlines,
+                      int rot_any, const cpx<R>* tw, hipStream_t s);
 
 int mid_blocks(int N, int nlines);
 
 // ---------------------------------------------------------------------------
 // pointwise kernels with fused reductions and device-side control (pw_kernels.hip)
 // ---------------------------------------------------------------------------
-template <typename R>
-struct Fields {
-    cpx<R>* phi;     // Phi
-    cpx<R>* hl;      // H_L Phi
-    cpx<R>* r[2];    // r^n and r^{n-1} (double buffer, SolveState::cur)
-    cpx<R>* pr;      // preconditioned residual
-    cpx<R>* P;       // search direction P^n (P^{n-1} before the direction pass)
-    cpx<R>* hlp;     // H_L P^ (P^ = P / |P|)
-    cpx<R>* u;       // preconditioner input P_V^{1/2} r
-    R* pv;           // [3][M] P_V^{1/2} factors (alpha_l + V + c0 rho)^{-1/2}
-};
-
-template <typename R> hipError_t launch_eval(const Fields<R>& f, const Phys& p, SolveState* st, RedBuf rb, int force, hipStream_t s);
-template <typename R> hipError_t launch_resid(const Fields<R>& f, const Phys& p, SolveState* st, RedBuf rb, int final_only, hipStream_t s);
-template <typename R> hipError_t launch_lsred(const Fields<R>& f, const Phys& p, SolveState* st, RedBuf rb, hipStream_t s);
+template <typename R> hipError_t launch_eval(const Slot<R>* slots, int nslots, RedGeom g, hipStream_t s);
+template <typename R> hipError_t launch_resid(const Slot<R>* slots, int nslots, RedGeom g, int final_only, hipStream_t s);
+template <typename R> hipError_t launch_lsred(const Slot<R>* slots, int nslots, RedGeom g, hipStream_t s);
 // Phi <- Phi / |Phi| (sets pending_step with c = 1/|Phi|, s = 0)
-template <typename R> hipError_t launch_normalize(const cpx<R>* phi, const Phys& p, SolveState* st, RedBuf rb, hipStream_t s);
+template <typename R> hipError_t launch_normalize(const Slot<R>* slots, int nslots, RedGeom g, hipStream_t s);
 // precision conversion of a field of n complex values
 hipError_t launch_convert_d2f(const cpx<double>* in, cpx<float>* out, long long n, hipStream_t s);
 hipError_t launch_convert_f2d(const cpx<float>* in, cpx<double>* out, long long n, hipStream_t s);
-// H(Phi)Phi = H_L Phi + nonlinear terms (operator-level entry point)
-template <typename R> hipError_t launch_hphi(const cpx<R>* phi, const cpx<R>* hl, cpx<R>* out, const Phys& p, hipStream_t s);
-// preconditioner input for a given r: pv = (alpha_l + V + c0 rho)^{-1/2}, u = pv r
-template <typename R> hipError_t launch_pvin(const cpx<R>* phi, const cpx<R>* r, R* pv, cpx<R>* u, const Phys& p, const SolveState* st, hipStream_t s);
+// X1 = H_L Phi + nonlinear terms = H(Phi)Phi (operator-level entry point)
+template <typename R> hipError_t launch_hphi(const Slot<R>* slots, int nslots, RedGeom g, hipStream_t s);
+// preconditioner input for the given r in X0: pv = (alpha_l + V + c0 rho)^{-1/2}, u = pv r
+template <typename R> hipError_t launch_pvin(const Slot<R>* slots, int nslots, RedGeom g, hipStream_t s);
 // Gaussian (a, a, a) initial guess
 hipError_t launch_gaussian(cpx<double>* out, const Phys& p, hipStream_t s);
 

@@ -19,9 +19,14 @@ int pw_blocks(long long M) {
 // fresh evaluation after an H_L application: energy parts, mu (2.9), alpha_l
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ __launch_bounds__(PT) void k_eval(Fields<R> f, Phys p, SolveState* st, RedBuf rb, int force) {
-    if (st->done && !force) return;
+__global__ __launch_bounds__(PT) void k_eval(const Slot<R>* slots, RedGeom g) {
+    const Slot<R>& S = slots[blockIdx.y];
+    SolveState* st = S.st;
+    if (st->done) return;
+    const Phys p = S.p;
     const long long M = p.M;
+    const cpx<R>* phi = S.buf[B_PHI];
+    const cpx<R>* hlf = S.buf[B_HL];
     double acc[NS_EVAL];
     for (int k = 0; k < NS_EVAL; ++k) acc[k] = 0.0;
     for (long long i = (long long)blockIdx.x * PT + threadIdx.x; i < M; i += (long long)gridDim.x * PT) {
@@ -29,8 +34,8 @@ __global__ __launch_bounds__(PT) void k_eval(Fields<R> f, Phys p, SolveState* st
         coords(p, i, x, y, z);
         trap_at(p, i, x, y, z, V2, V4);
         cpx<double> ph[3], hl[3], nl[3];
-        load3(f.phi, i, M, ph);
-        load3(f.hl, i, M, hl);
+        load3(phi, i, M, ph);
+        load3(hlf, i, M, hl);
         const Spin sp = spin_of(ph);
         nonlin(p, sp, ph, nl);
         for (int c = 0; c < 3; ++c) {
@@ -45,13 +50,13 @@ __global__ __launch_bounds__(PT) void k_eval(Fields<R> f, Phys p, SolveState* st
         acc[17] += V4 * sp.rho;
     }
     bsum<NS_EVAL>(acc);
-    if (publish<NS_EVAL>(acc, rb.pw, rb.counter + 0)) {
+    if (publish<NS_EVAL>(acc, S.red_pw, S.counter + 0)) {
         double tot[NS_EVAL], mt[4];
-        gather<NS_EVAL>(tot, rb.pw, gridDim.x, NS_MAX);
-        gather<4>(mt, rb.mid, rb.nblk_mid, RED_MID_STRIDE);
+        gather<NS_EVAL>(tot, S.red_pw, gridDim.x, NS_MAX);
+        gather<4>(mt, S.red_mid, g.nblk_mid, RED_MID_STRIDE);
         if (threadIdx.x == 0) {
             ctrl_eval(st, p, tot, mt);
-            rb.counter[0] = 0;
+            S.counter[0] = 0;
         }
     }
 }
@@ -66,36 +71,45 @@ __global__ __launch_bounds__(PT) void k_eval(Fields<R> f, Phys p, SolveState* st
 // final_only: residual norm of the current iterate only (no writes, no control).
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ __launch_bounds__(PT) void k_resid(Fields<R> f, Phys p, SolveState* st, RedBuf rb, int final_only) {
+__global__ __launch_bounds__(PT) void k_resid(const Slot<R>* slots, RedGeom g, int final_only) {
+    const Slot<R>& S = slots[blockIdx.y];
+    SolveState* st = S.st;
     if (st->done && !final_only) return;
+    const Phys p = S.p;
     const long long M = p.M;
+    cpx<R>* phif = S.buf[B_PHI];
+    cpx<R>* hlf = S.buf[B_HL];
+    const cpx<R>* Pf = S.buf[B_P];
+    const cpx<R>* hlpf = S.buf[B_HLP];
+    cpx<R>* uf = S.buf[B_U];
+    R* pvf = S.pv;
     const int pending = st->pending_step && !final_only;
     const double k0 = st->c, k1 = st->s * st->invnP, ks = st->s, k2 = st->inv_norm;
     const double mu = st->mu;
     const double al[3] = {st->alpha[0], st->alpha[1], st->alpha[2]};
     const double fl = 1e-12 * fmax(1.0, fmax(al[0], fmax(al[1], al[2])));
-    cpx<R>* r = f.r[st->cur];
+    cpx<R>* r = S.buf[B_R0 + st->cur];
     double acc[NS_RES] = {0.0, 0.0, 0.0, 0.0};
     for (long long i = (long long)blockIdx.x * PT + threadIdx.x; i < M; i += (long long)gridDim.x * PT) {
         double x, y, z, V2, V4;
         coords(p, i, x, y, z);
         trap_at(p, i, x, y, z, V2, V4);
         cpx<double> ph[3], hl[3], nl[3], P[3];
-        load3(f.phi, i, M, ph);
-        load3(f.hl, i, M, hl);
-        if (!final_only) load3(f.P, i, M, P);
+        load3(phif, i, M, ph);
+        load3(hlf, i, M, hl);
+        if (!final_only) load3(Pf, i, M, P);
         if (pending) {
             cpx<double> hp[3];
-            load3(f.hlp, i, M, hp);
+            load3(hlpf, i, M, hp);
             for (int c = 0; c < 3; ++c) {
                 ph[c] = k2 * (k0 * ph[c] + k1 * P[c]);
                 hl[c] = k2 * (k0 * hl[c] + ks * hp[c]);
             }
-            store3(f.phi, i, M, ph);
-            store3(f.hl, i, M, hl);
+            store3(phif, i, M, ph);
+            store3(hlf, i, M, hl);
             // continue from the stored (rounded) values
-            load3(f.phi, i, M, ph);
-            load3(f.hl, i, M, hl);
+            load3(phif, i, M, ph);
+            load3(hlf, i, M, hl);
         }
         const Spin sp = spin_of(ph);
         nonlin(p, sp, ph, nl);
@@ -107,8 +121,8 @@ __global__ __launch_bounds__(PT) void k_resid(Fields<R> f, Phys p, SolveState* s
             r[c * M + i] = rr;
             const double d = fmax(al[c] + V2 + V4 + p.c0 * sp.rho, fl);
             const R w = (R)(1.0 / sqrt(d));
-            f.pv[c * M + i] = w;
-            f.u[c * M + i] = w * rr;
+            pvf[c * M + i] = w;
+            uf[c * M + i] = w * rr;
             const cpx<double> rw = wid(rr);
             acc[1] += re_dot(rw, P[c]);
             acc[2] += re_dot(ph[c], P[c]);
@@ -124,12 +138,12 @@ __global__ __launch_bounds__(PT) void k_resid(Fields<R> f, Phys p, SolveState* s
         v[2] = t[1];
         v[3] = t[2];
     }
-    if (publish<NS_RES>(v, rb.pw, rb.counter + 1)) {
+    if (publish<NS_RES>(v, S.red_pw, S.counter + 1)) {
         double tot[NS_RES];
-        gather<NS_RES>(tot, rb.pw, gridDim.x, NS_MAX, 1u);
+        gather<NS_RES>(tot, S.red_pw, gridDim.x, NS_MAX, 1u);
         if (threadIdx.x == 0) {
             ctrl_resid(st, p, tot, final_only);
-            rb.counter[1] = 0;
+            S.counter[1] = 0;
         }
     }
 }
@@ -140,8 +154,11 @@ __global__ __launch_bounds__(PT) void k_resid(Fields<R> f, Phys p, SolveState* s
 // pass of the H_L P^ application
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ __launch_bounds__(PT) void k_lsred(Fields<R> f, Phys p, SolveState* st, RedBuf rb) {
+__global__ __launch_bounds__(PT) void k_lsred(const Slot<R>* slots, RedGeom g) {
+    const Slot<R>& S = slots[blockIdx.y];
+    SolveState* st = S.st;
     if (st->done) return;
+    const Phys p = S.p;
     const long long M = p.M;
     const double ip = st->invnP;
     const double w0 = 0.5 * p.c0, w1 = 0.5 * p.c1;
@@ -153,10 +170,10 @@ __global__ __launch_bounds__(PT) void k_lsred(Fields<R> f, Phys p, SolveState* s
         trap_at(p, i, x, y, z, V2, V4);
         const double V = V2 + V4;
         cpx<double> ph[3], P[3], hl[3], hp[3];
-        load3(f.phi, i, M, ph);
-        load3(f.P, i, M, P);
-        load3(f.hl, i, M, hl);
-        load3(f.hlp, i, M, hp);
+        load3(S.buf[B_PHI], i, M, ph);
+        load3(S.buf[B_P], i, M, P);
+        load3(S.buf[B_HL], i, M, hl);
+        load3(S.buf[B_HLP], i, M, hp);
         for (int c = 0; c < 3; ++c) P[c] = ip * P[c];
         double n0[3], n1[3], n2[3];
         for (int c = 0; c < 3; ++c) {
@@ -207,13 +224,13 @@ __global__ __launch_bounds__(PT) void k_lsred(Fields<R> f, Phys p, SolveState* s
         }
     }
     bsum<NS_LS>(acc);
-    if (publish<NS_LS>(acc, rb.pw, rb.counter + 3)) {
+    if (publish<NS_LS>(acc, S.red_pw, S.counter + 3)) {
         double tot[NS_LS], kin[NS_KIN];
-        gather<NS_LS>(tot, rb.pw, gridDim.x, NS_MAX);
-        gather<NS_KIN>(kin, rb.mid, rb.nblk_mid, RED_MID_STRIDE);
+        gather<NS_LS>(tot, S.red_pw, gridDim.x, NS_MAX);
+        gather<NS_KIN>(kin, S.red_mid, g.nblk_mid, RED_MID_STRIDE);
         if (threadIdx.x == 0) {
             ctrl_ls(st, p, tot, kin);
-            rb.counter[3] = 0;
+            S.counter[3] = 0;
         }
     }
 }
@@ -222,15 +239,19 @@ __global__ __launch_bounds__(PT) void k_lsred(Fields<R> f, Phys p, SolveState* s
 // normalisation: sets the pending rescale Phi <- Phi / |Phi|
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ __launch_bounds__(PT) void k_normalize(const cpx<R>* phi, Phys p, SolveState* st, RedBuf rb) {
+__global__ __launch_bounds__(PT) void k_normalize(const Slot<R>* slots, RedGeom g) {
+    const Slot<R>& S = slots[blockIdx.y];
+    SolveState* st = S.st;
+    const Phys p = S.p;
+    const cpx<R>* phi = S.buf[B_PHI];
     const long long n3 = 3 * p.M;
     double acc[1] = {0.0};
     for (long long i = (long long)blockIdx.x * PT + threadIdx.x; i < n3; i += (long long)gridDim.x * PT)
         acc[0] += cabs2(wid(phi[i]));
     bsum<1>(acc);
-    if (publish<1>(acc, rb.pw, rb.counter + 4)) {
+    if (publish<1>(acc, S.red_pw, S.counter + 4)) {
         double tot[1];
-        gather<1>(tot, rb.pw, gridDim.x, NS_MAX);
+        gather<1>(tot, S.red_pw, gridDim.x, NS_MAX);
         if (threadIdx.x == 0) {
             const double n2 = tot[0] * p.cell;
             if (!(n2 > 0.0) || !isfinite(n2)) {
@@ -243,7 +264,7 @@ __global__ __launch_bounds__(PT) void k_normalize(const cpx<R>* phi, Phys p, Sol
                 st->inv_norm = 1.0;
                 st->pending_step = 1;
             }
-            rb.counter[4] = 0;
+            S.counter[4] = 0;
         }
     }
 }
@@ -261,7 +282,12 @@ __global__ void k_f2d(const cpx<float>* in, cpx<double>* out, long long n) {
 }
 
 template <typename R>
-__global__ void k_hphi(const cpx<R>* phi, const cpx<R>* hl, cpx<R>* out, Phys p) {
+__global__ void k_hphi(const Slot<R>* slots) {
+    const Slot<R>& S = slots[blockIdx.y];
+    const Phys p = S.p;
+    const cpx<R>* phi = S.buf[B_PHI];
+    const cpx<R>* hl = S.buf[B_HL];
+    cpx<R>* out = S.buf[B_X1];
     const long long M = p.M;
     for (long long i = (long long)blockIdx.x * PT + threadIdx.x; i < M; i += (long long)gridDim.x * PT) {
         cpx<double> ph[3], h[3], nl[3];
@@ -276,7 +302,14 @@ __global__ void k_hphi(const cpx<R>* phi, const cpx<R>* hl, cpx<R>* out, Phys p)
 
 // preconditioner input for a given r: pv = (alpha_l + V + c0 rho)^{-1/2}, u = pv r
 template <typename R>
-__global__ void k_pvin(const cpx<R>* phi, const cpx<R>* r, R* pv, cpx<R>* u, Phys p, const SolveState* st) {
+__global__ void k_pvin(const Slot<R>* slots) {
+    const Slot<R>& S = slots[blockIdx.y];
+    const Phys p = S.p;
+    const SolveState* st = S.st;
+    const cpx<R>* phi = S.buf[B_PHI];
+    const cpx<R>* r = S.buf[B_X0];
+    R* pv = S.pv;
+    cpx<R>* u = S.buf[B_U];
     const long long M = p.M;
     const double al[3] = {st->alpha[0], st->alpha[1], st->alpha[2]};
     const double fl = 1e-12 * fmax(1.0, fmax(al[0], fmax(al[1], al[2])));
@@ -310,20 +343,20 @@ __global__ void k_gaussian(cpx<double>* out, Phys p) {
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <typename R> hipError_t launch_eval(const Fields<R>& f, const Phys& p, SolveState* st, RedBuf rb, int force, hipStream_t s) {
-    GS_LAUNCH(k_eval<R>, dim3(rb.nblk_pw), dim3(PT), 0, s, f, p, st, rb, force);
+template <typename R> hipError_t launch_eval(const Slot<R>* slots, int nslots, RedGeom g, hipStream_t s) {
+    GS_LAUNCH(k_eval<R>, dim3(g.nblk_pw, nslots), dim3(PT), 0, s, slots, g);
     return hipGetLastError();
 }
-template <typename R> hipError_t launch_resid(const Fields<R>& f, const Phys& p, SolveState* st, RedBuf rb, int final_only, hipStream_t s) {
-    GS_LAUNCH(k_resid<R>, dim3(rb.nblk_pw), dim3(PT), 0, s, f, p, st, rb, final_only);
+template <typename R> hipError_t launch_resid(const Slot<R>* slots, int nslots, RedGeom g, int final_only, hipStream_t s) {
+    GS_LAUNCH(k_resid<R>, dim3(g.nblk_pw, nslots), dim3(PT), 0, s, slots, g, final_only);
     return hipGetLastError();
 }
-template <typename R> hipError_t launch_lsred(const Fields<R>& f, const Phys& p, SolveState* st, RedBuf rb, hipStream_t s) {
-    GS_LAUNCH(k_lsred<R>, dim3(rb.nblk_pw), dim3(PT), 0, s, f, p, st, rb);
+template <typename R> hipError_t launch_lsred(const Slot<R>* slots, int nslots, RedGeom g, hipStream_t s) {
+    GS_LAUNCH(k_lsred<R>, dim3(g.nblk_pw, nslots), dim3(PT), 0, s, slots, g);
     return hipGetLastError();
 }
-template <typename R> hipError_t launch_normalize(const cpx<R>* phi, const Phys& p, SolveState* st, RedBuf rb, hipStream_t s) {
-    GS_LAUNCH(k_normalize<R>, dim3(rb.nblk_pw), dim3(PT), 0, s, phi, p, st, rb);
+template <typename R> hipError_t launch_normalize(const Slot<R>* slots, int nslots, RedGeom g, hipStream_t s) {
+    GS_LAUNCH(k_normalize<R>, dim3(g.nblk_pw, nslots), dim3(PT), 0, s, slots, g);
     return hipGetLastError();
 }
 hipError_t launch_convert_d2f(const cpx<double>* in, cpx<float>* out, long long n, hipStream_t s) {
@@ -334,12 +367,12 @@ hipError_t launch_convert_f2d(const cpx<float>* in, cpx<double>* out, long long 
     GS_LAUNCH(k_f2d, dim3(pw_blocks(n)), dim3(PT), 0, s, in, out, n);
     return hipGetLastError();
 }
-template <typename R> hipError_t launch_hphi(const cpx<R>* phi, const cpx<R>* hl, cpx<R>* out, const Phys& p, hipStream_t s) {
-    GS_LAUNCH(k_hphi<R>, dim3(pw_blocks(p.M)), dim3(PT), 0, s, phi, hl, out, p);
+template <typename R> hipError_t launch_hphi(const Slot<R>* slots, int nslots, RedGeom g, hipStream_t s) {
+    GS_LAUNCH(k_hphi<R>, dim3(g.nblk_pw, nslots), dim3(PT), 0, s, slots);
     return hipGetLastError();
 }
-template <typename R> hipError_t launch_pvin(const cpx<R>* phi, const cpx<R>* r, R* pv, cpx<R>* u, const Phys& p, const SolveState* st, hipStream_t s) {
-    GS_LAUNCH(k_pvin<R>, dim3(pw_blocks(p.M)), dim3(PT), 0, s, phi, r, pv, u, p, st);
+template <typename R> hipError_t launch_pvin(const Slot<R>* slots, int nslots, RedGeom g, hipStream_t s) {
+    GS_LAUNCH(k_pvin<R>, dim3(g.nblk_pw, nslots), dim3(PT), 0, s, slots);
     return hipGetLastError();
 }
 hipError_t launch_gaussian(cpx<double>* out, const Phys& p, hipStream_t s) {
@@ -347,13 +380,13 @@ hipError_t launch_gaussian(cpx<double>* out, const Phys& p, hipStream_t s) {
     return hipGetLastError();
 }
 
-#define GS_INST(R)                                                                                              \
-    template hipError_t launch_eval<R>(const Fields<R>&, const Phys&, SolveState*, RedBuf, int, hipStream_t);   \
-    template hipError_t launch_resid<R>(const Fields<R>&, const Phys&, SolveState*, RedBuf, int, hipStream_t);  \
-    template hipError_t launch_lsred<R>(const Fields<R>&, const Phys&, SolveState*, RedBuf, hipStream_t);       \
-    template hipError_t launch_normalize<R>(const cpx<R>*, const Phys&, SolveState*, RedBuf, hipStream_t);      \
-    template hipError_t launch_hphi<R>(const cpx<R>*, const cpx<R>*, cpx<R>*, const Phys&, hipStream_t);        \
-    template hipError_t launch_pvin<R>(const cpx<R>*, const cpx<R>*, R*, cpx<R>*, const Phys&, const SolveState*, hipStream_t);
+#define GS_INST(R)                                                                                    \
+    template hipError_t launch_eval<R>(const Slot<R>*, int, RedGeom, hipStream_t);                    \
+    template hipError_t launch_resid<R>(const Slot<R>*, int, RedGeom, int, hipStream_t);              \
+    template hipError_t launch_lsred<R>(const Slot<R>*, int, RedGeom, hipStream_t);                   \
+    template hipError_t launch_normalize<R>(const Slot<R>*, int, RedGeom, hipStream_t);               \
+    template hipError_t launch_hphi<R>(const Slot<R>*, int, RedGeom, hipStream_t);                    \
+    template hipError_t launch_pvin<R>(const Slot<R>*, int, RedGeom, hipStream_t);
 GS_INST(double)
 GS_INST(float)
 

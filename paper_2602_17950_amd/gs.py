@@ -14,14 +14,16 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgs.so")
 
-GS_OK, GS_EINVAL, GS_ENOMEM, GS_EDEVICE, GS_ENONFINITE = 0, -1, -2, -3, -4
+GS_OK, GS_EINVAL, GS_ENOMEM, GS_EDEVICE, GS_ENONFINITE, GS_ECANCELED = 0, -1, -2, -3, -4, -5
 GS_WMAXITER, GS_WSTAGNATED = 1, 2
+GS_PENDING = 16
 GS_STOP_ENERGY, GS_STOP_RESIDUAL, GS_STOP_EITHER = 0, 1, 2
 GS_FP64, GS_FP32, GS_MIXED = 0, 1, 2
 
 EXPORTS = ("gs_create", "gs_destroy", "gs_default_options", "gs_footprint_bytes", "gs_solve",
            "gs_solve_device", "gs_fft", "gs_hamiltonian", "gs_precondition", "gs_kernel_timer_start",
-           "gs_kernel_timer_read", "gs_last_error")
+           "gs_kernel_timer_read", "gs_last_error", "gs_set_hbm_budget", "gs_memory_stats",
+           "gs_batch_solve", "gs_submit", "gs_progress", "gs_poll", "gs_wait", "gs_cancel")
 
 KERNEL_KINDS = {"hl_fwd": 0, "hl_mid": 1, "hl_inv": 2, "pre_fwd": 3, "pre_mid": 4, "pre_inv": 5,
                 "eval": 6, "resid": 7, "dirred": 8, "lsred": 9, "hl_fwd2": 10, "hl_inv2": 11}
@@ -69,6 +71,11 @@ class gs_result(C.Structure):
         return d
 
 
+class gs_request(C.Structure):
+    _fields_ = [("grid", gs_grid), ("trap", gs_trap), ("params", gs_params), ("options", gs_options),
+                ("d_psi0", C.c_void_p), ("d_psi_out", C.c_void_p)]
+
+
 _lib = None
 
 
@@ -102,6 +109,14 @@ def load():
     lib.gs_kernel_timer_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                          C.POINTER(C.c_longlong)]
     lib.gs_last_error.restype = C.c_char_p
+    lib.gs_set_hbm_budget.argtypes = [vp, C.c_size_t]
+    lib.gs_memory_stats.argtypes = [vp, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
+    lib.gs_batch_solve.argtypes = [vp, C.c_int, C.POINTER(gs_request), C.POINTER(gs_result)]
+    lib.gs_submit.argtypes = [vp, C.POINTER(gs_request), C.POINTER(C.c_uint64)]
+    lib.gs_progress.argtypes = [vp, C.c_int]
+    lib.gs_poll.argtypes = [vp, C.c_uint64, C.POINTER(gs_result)]
+    lib.gs_wait.argtypes = [vp, C.c_uint64, C.POINTER(gs_result)]
+    lib.gs_cancel.argtypes = [vp, C.c_uint64]
     _lib = lib
     return lib
 
@@ -158,6 +173,32 @@ def default_options(**kw) -> gs_options:
 def footprint_bytes(pb, precision=GS_FP64) -> int:
     g = grid_of(pb)
     return int(load().gs_footprint_bytes(C.byref(g), int(precision)))
+
+
+def make_request(pb, psi0, out, options: gs_options | None = None, V=None):
+    """gs_request for problem pb with device tensors psi0 (or None) and out
+    (complex128, shape (3,)+grid). Returns (request, keep-alive object)."""
+    q = gs_request()
+    q.grid = grid_of(pb)
+    t, keep = trap_of(pb, V)
+    q.trap = t
+    q.params = params_of(pb)
+    q.options = options or default_options()
+    q.d_psi0 = None if psi0 is None else psi0.data_ptr()
+    q.d_psi_out = out.data_ptr()
+    return q, keep
+
+
+def _result(rc, res):
+    """Result dict of a completed request; raises for a failed call (as opposed
+    to a request that completed with a negative status)."""
+    if rc < 0 and res.status != rc:
+        raise GsError(rc, last_error())
+    d = res.to_dict()
+    d["rc"] = rc
+    if rc < 0:
+        d["error"] = last_error()
+    return d
 
 
 def _stream_ptr(stream):
@@ -228,6 +269,60 @@ class Context:
         d = res.to_dict()
         d["rc"] = rc
         return d
+
+    # -- batching and serving -------------------------------------------------
+    def batch_solve(self, requests):
+        """requests: list of (pb, psi0 tensor or None, out tensor, options or
+        None, V or None). Runs them all with continuous batching; returns the
+        result dicts in order."""
+        n = len(requests)
+        arr = (gs_request * max(n, 1))()
+        keep = []
+        for i, (pb, psi0, out, opt, V) in enumerate(requests):
+            q, k = make_request(pb, psi0, out, opt, V)
+            arr[i] = q
+            keep.append(k)
+        res = (gs_result * max(n, 1))()
+        _check(load().gs_batch_solve(self._h, n, arr, res))
+        out = []
+        for i in range(n):
+            d = res[i].to_dict()
+            d["rc"] = res[i].status
+            out.append(d)
+        return out
+
+    def submit(self, pb, psi0, out, options: gs_options | None = None, V=None) -> int:
+        q, keep = make_request(pb, psi0, out, options, V)
+        t = C.c_uint64()
+        _check(load().gs_submit(self._h, C.byref(q), C.byref(t)))
+        return t.value
+
+    def progress(self, block: bool = False) -> int:
+        return _check(load().gs_progress(self._h, int(bool(block))))
+
+    def poll(self, ticket: int):
+        """None while the request runs, else its result dict (ticket released)."""
+        res = gs_result()
+        rc = load().gs_poll(self._h, C.c_uint64(ticket), C.byref(res))
+        if rc == GS_PENDING:
+            return None
+        return _result(rc, res)
+
+    def wait(self, ticket: int):
+        res = gs_result()
+        rc = load().gs_wait(self._h, C.c_uint64(ticket), C.byref(res))
+        return _result(rc, res)
+
+    def cancel(self, ticket: int):
+        _check(load().gs_cancel(self._h, C.c_uint64(ticket)))
+
+    def set_hbm_budget(self, nbytes: int):
+        _check(load().gs_set_hbm_budget(self._h, C.c_size_t(int(nbytes))))
+
+    def memory_stats(self):
+        b, r, a = C.c_size_t(), C.c_size_t(), C.c_size_t()
+        _check(load().gs_memory_stats(self._h, C.byref(b), C.byref(r), C.byref(a)))
+        return {"budget": b.value, "reserved": r.value, "allocated": a.value}
 
     # -- measurement ---------------------------------------------------------------
     def kernel_timer_start(self, kind):

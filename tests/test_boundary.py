@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_header(tmp_path):
     """sizeof/offsetof of the C structs (compiled against gs.h) equal the ctypes mirrors."""
     structs = {"gs_grid": gs.gs_grid, "gs_trap": gs.gs_trap, "gs_params": gs.gs_params,
-               "gs_options": gs.gs_options, "gs_result": gs.gs_result}
+               "gs_options": gs.gs_options, "gs_result": gs.gs_result, "gs_request": gs.gs_request}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
     for name, cls in structs.items():
         lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
@@ -82,3 +82,13 @@ def test_errors_without_device():
     assert "NULL" in gs.last_error()
     rc = lib.gs_kernel_timer_start(None, 0)
     assert rc == gs.GS_EINVAL
+    q = gs.gs_request()
+    t = C.c_uint64()
+    assert lib.gs_submit(None, C.byref(q), C.byref(t)) == gs.GS_EINVAL
+    assert lib.gs_poll(None, 1, None) == gs.GS_EINVAL
+    assert lib.gs_wait(None, 1, None) == gs.GS_EINVAL
+    assert lib.gs_cancel(None, 1) == gs.GS_EINVAL
+    assert lib.gs_progress(None, 0) == gs.GS_EINVAL
+    assert lib.gs_batch_solve(None, 1, C.byref(q), None) == gs.GS_EINVAL
+    assert lib.gs_set_hbm_budget(None, 0) == gs.GS_EINVAL
+    assert lib.gs_memory_stats(None, None, None, None) == gs.GS_EINVAL

@@ -1,0 +1,192 @@
+"""Batching and serving through the C ABI.
+
+A solve occupies its own slot; slots of one grid class share every launch but
+no arithmetic, and every reduction has a fixed per-slot order. So a solve must
+return the same bits alone, in a batch of mixed sizes and precisions, and
+under staggered (served) submission; these tests compare bit for bit. Parity
+of the solve itself with the CPU oracle is covered by the single-solve tests
+and by a batch-vs-oracle check on the smallest problems here.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2602_17950_amd import gs, inputs
+
+from helpers import orc, rel
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def problems():
+    """Small problems of three grid classes (two 2D sizes and a 3D one),
+    rotating and not, with seeded guesses."""
+    out = []
+    specs = [
+        (2, (32, 32), (6.0, 6.0), 0.0, 0.5, 60.0, -0.5, ("a", "a", "a")),
+        (2, (32, 32), (6.0, 6.0), 0.3, 0.8, 90.0, 0.7, ("b", "a", "a")),
+        (2, (64, 64), (8.0, 8.0), 0.5, 1.0, 150.0, -1.0, ("b", "a", "a")),
+        (2, (64, 64), (8.0, 8.0), 0.0, 0.3, 40.0, 1.5, ("a", "bbar", "a")),
+        (3, (16, 16, 16), (5.0, 5.0, 5.0), 0.2, 0.6, 30.0, -0.3, ("a", "a", "a")),
+    ]
+    for i, (dim, n, L, om, ga, c0, c1, kinds) in enumerate(specs):
+        pb = inputs.Problem(dim=dim, n=n, L=L, omega=om, gamma=ga, c0=c0, c1=c1)
+        psi0 = inputs.initial_guess(pb, kinds, noise=1e-3, seed=100 + i)
+        out.append((pb, psi0))
+    return out
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def alone(ctx, pb, psi0, opt):
+    out = torch.empty((3,) + pb.shape, dtype=torch.complex128, device=DEV)
+    res = ctx.solve_device(pb, dev(psi0), out, options=opt)
+    torch.cuda.synchronize()
+    return out, res
+
+
+def same_bits(a, b):
+    return torch.equal(a.view(torch.float64), b.view(torch.float64))
+
+
+@pytest.mark.parametrize("precision", [gs.GS_FP64, gs.GS_MIXED])
+def test_batch_equals_alone_bitwise(gpu_ctx, precision):
+    print(f"[batch] precision={precision}", flush=True)
+    opt = gs.default_options(precision=precision, tol=1e-11, switch_resid=1e-4)
+    probs = problems()
+    ref = [alone(gpu_ctx, pb, psi0, opt) for pb, psi0 in probs]
+    outs = [torch.empty((3,) + pb.shape, dtype=torch.complex128, device=DEV) for pb, _ in probs]
+    reqs = [(pb, dev(psi0), o, opt, None) for (pb, psi0), o in zip(probs, outs)]
+    res = gpu_ctx.batch_solve(reqs)
+    torch.cuda.synchronize()
+    for i, ((o_ref, r_ref), o, r) in enumerate(zip(ref, outs, res)):
+        assert r["rc"] >= 0 and r_ref["rc"] >= 0, (i, r, r_ref)
+        assert same_bits(o, o_ref), i
+        for k in ("E", "mu", "resid_inf", "iters", "iters_fp32", "backtracks", "dE_last"):
+            assert r[k] == r_ref[k], (i, k, r[k], r_ref[k])
+        if precision == gs.GS_MIXED:
+            assert 0 < r["iters_fp32"] < r["iters"], i
+    st = gpu_ctx.memory_stats()
+    assert st["reserved"] == 0
+
+
+def test_batch_matches_oracle_small(gpu_ctx):
+    """Converged energies and chemical potentials of batched FP64 solves against
+    the oracle from the same guesses (2D problems; residual stop for mu)."""
+    probs = problems()[:2]
+    opt = gs.default_options(stop_kind=gs.GS_STOP_RESIDUAL, tol=1e-10)
+    outs = [torch.empty((3,) + pb.shape, dtype=torch.complex128, device=DEV) for pb, _ in probs]
+    res = gpu_ctx.batch_solve([(pb, dev(p0), o, opt, None) for (pb, p0), o in zip(probs, outs)])
+    for (pb, psi0), r in zip(probs, res):
+        g, t, p = orc(pb)
+        ref = O.pcg(g, t, p, psi0, O.Options(stop_kind=gs.GS_STOP_RESIDUAL, tol=1e-10))
+        ev = O.evaluate(g, t, p, ref.psi)
+        assert r["rc"] == gs.GS_OK and ref.status == 0
+        assert rel(r["E"], ev["E"]) < 1e-10
+        assert rel(r["mu"], ev["mu"]) < 1e-9
+
+
+def test_serving_staggered_submission(gpu_ctx):
+    """Requests that arrive while others run are admitted at chunk boundaries;
+    each result equals the solve alone."""
+    opt = gs.default_options(precision=gs.GS_MIXED, tol=1e-11, switch_resid=1e-4, check_every=8)
+    probs = problems()
+    ref = [alone(gpu_ctx, pb, psi0, opt) for pb, psi0 in probs]
+    outs = [torch.empty((3,) + pb.shape, dtype=torch.complex128, device=DEV) for pb, _ in probs]
+    guesses = [dev(psi0) for _, psi0 in probs]
+    tickets = []
+    for i, (pb, _) in enumerate(probs):
+        tickets.append(gpu_ctx.submit(pb, guesses[i], outs[i], opt))
+        # let the earlier requests run a few chunks before the next arrives
+        for _ in range(3):
+            gpu_ctx.progress(block=True)
+    done = {}
+    while len(done) < len(tickets):
+        for i, t in enumerate(tickets):
+            if i in done:
+                continue
+            r = gpu_ctx.poll(t)
+            if r is not None:
+                done[i] = r
+        if len(done) < len(tickets):
+            gpu_ctx.progress(block=True)
+    torch.cuda.synchronize()
+    for i in range(len(probs)):
+        assert done[i]["rc"] >= 0
+        assert same_bits(outs[i], ref[i][0]), i
+        assert done[i]["E"] == ref[i][1]["E"]
+        assert done[i]["wall_s"] > 0
+    assert gpu_ctx.memory_stats()["reserved"] == 0
+
+
+def test_admission_by_footprint(gpu_ctx):
+    """With a budget that fits one request, requests run one at a time and all
+    complete with the bits of the solve alone."""
+    ctx = gs.Context(0)
+    try:
+        opt = gs.default_options(tol=1e-11)
+        probs = [p for p in problems() if p[0].n == (32, 32)]
+        need = gs.footprint_bytes(probs[0][0], gs.GS_FP64)
+        ref = [alone(ctx, pb, psi0, opt) for pb, psi0 in probs]
+        ctx.set_hbm_budget(need + need // 2)
+        outs = [torch.empty((3,) + pb.shape, dtype=torch.complex128, device=DEV) for pb, _ in probs]
+        tickets = [ctx.submit(pb, dev(p0), o, opt) for (pb, p0), o in zip(probs, outs)]
+        peak = 0
+        results = {}
+        while len(results) < len(tickets):
+            st = ctx.memory_stats()
+            assert st["reserved"] <= st["budget"]
+            assert st["allocated"] <= st["budget"]
+            peak = max(peak, st["reserved"])
+            for i, t in enumerate(tickets):
+                if i not in results:
+                    r = ctx.poll(t)
+                    if r is not None:
+                        results[i] = r
+            if len(results) < len(tickets):
+                ctx.progress(block=True)
+        assert peak <= need + need // 2
+        torch.cuda.synchronize()
+        for i in range(len(probs)):
+            assert results[i]["rc"] >= 0
+            assert same_bits(outs[i], ref[i][0])
+        # a request larger than the whole budget is refused at submission
+        big = inputs.Problem(dim=2, n=(256, 256), L=(12.0, 12.0))
+        o = torch.empty((3, 256, 256), dtype=torch.complex128, device=DEV)
+        with pytest.raises(gs.GsError) as ei:
+            ctx.submit(big, None, o, opt)
+        assert ei.value.code == gs.GS_ENOMEM
+    finally:
+        ctx.close()
+
+
+def test_cancel(gpu_ctx):
+    pb, psi0 = problems()[2]
+    opt = gs.default_options(tol=0.0, max_iter=100000, check_every=4)
+    out = torch.empty((3,) + pb.shape, dtype=torch.complex128, device=DEV)
+    t = gpu_ctx.submit(pb, dev(psi0), out, opt)
+    gpu_ctx.progress(block=True)
+    gpu_ctx.cancel(t)
+    r = gpu_ctx.wait(t)
+    assert r["rc"] == gs.GS_ECANCELED
+    with pytest.raises(gs.GsError):
+        gpu_ctx.poll(t)   # the ticket was released
+    assert gpu_ctx.memory_stats()["reserved"] == 0
+
+
+def test_batch_invalid_request_runs_nothing(gpu_ctx):
+    pb, psi0 = problems()[0]
+    opt = gs.default_options()
+    bad = inputs.Problem(dim=2, n=(48, 48), L=(6.0, 6.0))
+    o1 = torch.empty((3,) + pb.shape, dtype=torch.complex128, device=DEV)
+    o2 = torch.empty((3, 48, 48), dtype=torch.complex128, device=DEV)
+    with pytest.raises(gs.GsError) as ei:
+        gpu_ctx.batch_solve([(pb, dev(psi0), o1, opt, None), (bad, None, o2, opt, None)])
+    assert ei.value.code == gs.GS_EINVAL
+    assert "request 1" in str(ei.value)
+    assert gpu_ctx.progress() == 0
