@@ -229,8 +229,9 @@ int gs_precondition(gs_ctx* ctx, const gs_grid* g, const gs_trap* t, const gs_pa
 /* Measurement helpers. Kernel kinds of one PCG iteration:
  *   0 first FFT pass of an H_L application, 1 its spectral middle pass,
  *   2 its last FFT pass, 3/4/5 the same for the preconditioner, 6 energy and
- *   mu reduction, 7 residual, 8 direction reduction, 9 step-size reduction,
- *   10/11 the second forward / inverse passes of a 3D H_L application.
+ *   mu sums, 7 residual, 8 (reserved), 9 step-size sums, 10/11 the second
+ *   forward / inverse passes of a 3D H_L application, 12 the control steps
+ *   (fixed-order totals of the partial sums and the scalar decisions).
  * gs_kernel_timer_start(ctx, kind) makes later solves on ctx bracket every
  * launch of that kernel with HIP events on the launch's stream (kind -1: off)
  * and resets the totals; gs_kernel_timer_read returns the summed elapsed time

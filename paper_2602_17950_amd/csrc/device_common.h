@@ -1,6 +1,7 @@
 // Device helpers shared by the kernel translation units: deterministic block
-// reductions with a last-block epilogue, grid coordinates, and the pointwise
-// spin-1 algebra of the Hamiltonian (Sec. 1 of the paper).
+// reductions into per-block rows, the fixed-order gather of those rows, grid
+// coordinates, and the pointwise spin-1 algebra of the Hamiltonian (Sec. 1 of
+// the paper).
 #pragma once
 #include "gs_internal.h"
 
@@ -45,32 +46,76 @@ __device__ __forceinline__ double bmax(double v) {
     return v;
 }
 
-// Thread 0 writes this block's row of NV partials; returns (on every thread)
-// whether this block is the last of the grid to do so.
+// Thread 0 writes this block's row of NV partial sums (plain stores: the rows
+// are read by a later kernel, after the kernel boundary has made them visible).
 template <int NV>
-__device__ __forceinline__ bool publish(const double (&v)[NV], double* rows, unsigned* counter) {
-    __shared__ int last;
-    if (threadIdx.x == 0) {
-        for (int k = 0; k < NV; ++k) rows[(long long)blockIdx.x * NS_MAX + k] = v[k];
-        __threadfence();
-        const unsigned prev = atomicAdd(counter, 1u);
-        last = (prev == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (last) __threadfence();
-    return last != 0;
+__device__ __forceinline__ void write_row(const double (&v)[NV], double* rows, int stride) {
+    if (threadIdx.x == 0)
+        for (int k = 0; k < NV; ++k) rows[(long long)blockIdx.x * stride + k] = v[k];
 }
 
-// In the last block: totals over nrows rows (fixed order) of NV values at the
-// given stride, on thread 0. Entries k with (maxmask >> k) & 1 are maxima.
+template <int N> struct Pow2Ceil { static constexpr int v = 2 * Pow2Ceil<(N + 1) / 2>::v; };
+template <> struct Pow2Ceil<1> { static constexpr int v = 1; };
+template <int N> struct ILog2 { static constexpr int v = 1 + ILog2<N / 2>::v; };
+template <> struct ILog2<1> { static constexpr int v = 0; };
+
+// One reduce-scatter step across lanes `O` apart: each lane keeps the half of
+// its H*2 partials selected by its lane bit O and adds the partner's copy of
+// that half.
+template <int H, int O>
+__device__ __forceinline__ void halve_step(double* v, int lane) {
+    const bool b = (lane & O) != 0;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        const double keep = b ? v[H + i] : v[i];
+        const double send = b ? v[i] : v[H + i];
+        v[i] = keep + __shfl_xor(send, O, 64);
+    }
+}
+template <int P, int O>
+__device__ __forceinline__ void halve_all(double* v, int lane) {
+    if constexpr (P > 1) {
+        halve_step<P / 2, O>(v, lane);
+        halve_all<P / 2, O / 2>(v, lane);
+    } else if constexpr (O >= 1) {
+        v[0] += __shfl_xor(v[0], O, 64);
+        halve_all<1, O / 2>(v, lane);
+    }
+}
+
+// Block sums of NV doubles written as this block's row: a recursive-halving
+// reduce-scatter inside each wave (about P shuffles for P = NV rounded up to a
+// power of two, instead of 6 NV), the four wave totals of each value added in
+// a fixed order, and the row stored by NV threads at once.
+template <int NV>
+__device__ __forceinline__ void block_row(const double (&acc)[NV], double* rows, int stride) {
+    constexpr int P = Pow2Ceil<NV>::v;
+    static_assert(P <= 64, "at most 64 sums per row");
+    constexpr int SH = 6 - ILog2<P>::v;   // lanes 2^SH apart hold the same value index
+    __shared__ double sh[PT / 64][P];
+    double v[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) v[k] = k < NV ? acc[k] : 0.0;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    halve_all<P, 32>(v, lane);
+    if ((lane & ((1 << SH) - 1)) == 0) sh[wv][lane >> SH] = v[0];
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        double t = sh[0][threadIdx.x];
+        for (int w = 1; w < PT / 64; ++w) t += sh[w][threadIdx.x];
+        rows[(long long)blockIdx.x * stride + threadIdx.x] = t;
+    }
+}
+
+// Totals over nrows rows (fixed order) of NV values at the given stride, on
+// thread 0 of a block of PT threads. Entries k with (maxmask >> k) & 1 are maxima.
 template <int NV>
 __device__ __forceinline__ void gather(double (&tot)[NV], const double* rows, int nrows, int stride,
                                        unsigned maxmask = 0u) {
     for (int k = 0; k < NV; ++k) tot[k] = 0.0;
-    const volatile double* vr = rows;
     for (int b = threadIdx.x; b < nrows; b += PT)
         for (int k = 0; k < NV; ++k) {
-            const double x = vr[(long long)b * stride + k];
+            const double x = rows[(long long)b * stride + k];
             tot[k] = ((maxmask >> k) & 1u) ? fmax(tot[k], x) : tot[k] + x;
         }
     double s[NV], m[NV];

@@ -1,7 +1,7 @@
 // Host side of the gfx950 ground-state library.
 //
 // Every solve occupies one slot: a block of device memory holding its fields,
-// scratch and partial sums, plus a SolveState and completion counters. Slots
+// scratch and partial sums, plus a SolveState. Slots
 // of the same grid shape, precision and chunk length form a class; each
 // kernel of the iteration is launched once for all running slots of a class
 // (blockIdx.y = slot), on the class's own stream. A host-side scheduler admits
@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "gs_internal.h"
+#include "control.h"
 #include "../../include/gs.h"
 
 namespace gs {
@@ -77,21 +78,14 @@ static int check_options(const gs_options* o) {
 // slots per class (bounded by the launch grid's y extent and the state arrays)
 constexpr int CLASS_CAP = 4096;
 
-// rows of per-block partial sums: the pointwise grid and the preconditioner's
-// last pass (3 * Nz * Ny / TILE blocks with TILE >= 2)
-static long long pw_rows(const gs_grid* g) {
-    const long long M = npts(g);
-    const long long pre = 3LL * M / g->n[0] / 2;
-    return std::max<long long>(pw_blocks(M), pre);
-}
-static long long mid_rows(const gs_grid* g) {
-    const int Nlast = g->n[g->dim - 1];
-    return mid_blocks(Nlast, (int)(npts(g) / Nlast));
-}
-static RedGeom red_geom(const gs_grid* g) {
+// rows of per-block partial sums of the reducing passes
+template <typename R> static RedGeom red_geom(const gs_grid* g) {
     RedGeom r;
-    r.nblk_mid = (int)mid_rows(g);
-    r.nblk_pw = pw_blocks(npts(g));
+    const long long M = npts(g);
+    const int Nlast = g->n[g->dim - 1];
+    r.nblk_mid = mid_blocks(Nlast, (int)(M / Nlast));
+    r.nblk_pw = pw_blocks(M);
+    r.nblk_dir = g->dim == 2 ? invT_pre_blocks<R>(g->n[0], 1, g->n[1]) : invT_pre_blocks<R>(g->n[0], g->n[2], g->n[1]);
     return r;
 }
 
@@ -102,12 +96,14 @@ static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 // the P_V^{1/2} factors and the partial-sum rows.
 template <typename R> static size_t slot_buffer_bytes(const gs_grid* g) {
     const long long M = npts(g);
+    const RedGeom rg = red_geom<R>(g);
     const size_t field = al256((size_t)3 * M * sizeof(cpx<R>));
-    return field * 16 + al256((size_t)3 * M * sizeof(R)) + al256((size_t)pw_rows(g) * NS_MAX * sizeof(double)) +
-           al256((size_t)mid_rows(g) * RED_MID_STRIDE * sizeof(double));
+    return field * 16 + al256((size_t)3 * M * sizeof(R)) + al256((size_t)rg.nblk_pw * NS_MAX * sizeof(double)) +
+           al256((size_t)rg.nblk_mid * RED_MID_STRIDE * sizeof(double)) +
+           al256((size_t)rg.nblk_dir * RED_DIR_STRIDE * sizeof(double));
 }
 template <typename R> static size_t slot_bytes(const gs_grid* g) {
-    return slot_buffer_bytes<R>(g) + sizeof(SolveState) + NCOUNTERS * sizeof(unsigned) + sizeof(Slot<R>);
+    return slot_buffer_bytes<R>(g) + sizeof(SolveState) + sizeof(Slot<R>);
 }
 
 template <typename R>
@@ -118,6 +114,7 @@ struct SlotMem {
     R* pv = nullptr;
     double* red_pw = nullptr;
     double* red_mid = nullptr;
+    double* red_dir = nullptr;
     ~SlotMem() {
         if (base) (void)hipFree(base);
     }
@@ -141,9 +138,12 @@ static int alloc_slot_mem(const gs_grid* g, hipStream_t s, std::unique_ptr<SlotM
     }
     m->pv = (R*)p;
     p += al256((size_t)3 * M * sizeof(R));
+    const RedGeom rg = red_geom<R>(g);
     m->red_pw = (double*)p;
-    p += al256((size_t)pw_rows(g) * NS_MAX * sizeof(double));
+    p += al256((size_t)rg.nblk_pw * NS_MAX * sizeof(double));
     m->red_mid = (double*)p;
+    p += al256((size_t)rg.nblk_mid * RED_MID_STRIDE * sizeof(double));
+    m->red_dir = (double*)p;
     HIPCHK(hipMemsetAsync(m->base, 0, m->bytes, s));
     out = std::move(m);
     return GS_OK;
@@ -161,7 +161,7 @@ static int alloc_slot_mem(const gs_grid* g, hipStream_t s, std::unique_ptr<SlotM
 enum KKind : int {
     KK_HL_FWD = 0, KK_HL_MID = 1, KK_HL_INV = 2, KK_PRE_FWD = 3, KK_PRE_MID = 4, KK_PRE_INV = 5,
     KK_EVAL = 6, KK_RESID = 7, KK_DIRRED = 8, KK_LSRED = 9, KK_HL_FWD2 = 10, KK_HL_INV2 = 11,
-    KK_COUNT = 12
+    KK_CTRL = 12, KK_COUNT = 13
 };
 struct TimerTotals {
     int kind = -1;
@@ -203,12 +203,13 @@ static hipError_t timed(Timer* tm, int kind, double bytes, hipStream_t s, F&& f)
 }
 
 // After a chunk has completed: iterations below n_full ran for some slot; when
-// every slot finished in the chunk, the refresh (chain 0) and the residual pass
-// (chain 1) of iteration n_full also ran.
+// every slot finished in the chunk, the refresh (chain 0), the residual pass
+// (chain 1) and the preconditioner with its control step (chain 2) of
+// iteration n_full also ran.
 static hipError_t timer_collect(Timer& tm, TimerTotals& tot, int n_full, bool done) {
     for (size_t i = 0; i < tm.rec.size(); ++i) {
         const Timer::Rec& r = tm.rec[i];
-        if (!(r.k < n_full || (done && r.k == n_full && r.chain <= 1))) continue;
+        if (!(r.k < n_full || (done && r.k == n_full && r.chain <= 2))) continue;
         float ms = 0.0f;
         hipError_t e = hipEventElapsedTime(&ms, tm.ev[2 * i], tm.ev[2 * i + 1]);
         if (e != hipSuccess) return e;
@@ -379,24 +380,58 @@ static hipError_t chain_pre(const Geo<R>& G, Sub<R> L, int dir, int out, hipStre
 
 // Fresh evaluation of the current iterate: apply a pending update to Phi,
 // H_L Phi from scratch, energy parts, mu, alpha_l.
+// bytes of partial-sum rows a control step reads
+template <typename R> static double fin_bytes(const Geo<R>& G, int what, int ns) {
+    double rows = 0.0;
+    switch (what) {
+    case FIN_EVAL: rows = (double)G.g.nblk_pw * NS_EVAL + (double)G.g.nblk_mid * 4; break;
+    case FIN_DIR: rows = (double)G.g.nblk_pw * NS_RES + (double)G.g.nblk_dir * NS_DIR; break;
+    case FIN_LS: rows = (double)G.g.nblk_pw * NS_LS + (double)G.g.nblk_mid * NS_KIN; break;
+    default: rows = (double)G.g.nblk_pw * NS_RES; break;
+    }
+    return rows * sizeof(double) * ns;
+}
+template <typename R>
+static hipError_t fin(const Geo<R>& G, Sub<R> L, int what, hipStream_t s, Timer* tm) {
+    return timed(tm, KK_CTRL, fin_bytes<R>(G, what, L.ns), s, [&] { return launch_fin<R>(L.tab, L.ns, G.g, what, s); });
+}
+
 template <typename R>
 static hipError_t refresh(const Geo<R>& G, Sub<R> L, hipStream_t s, Timer* tm) {
     const double F = 3.0 * G.M * sizeof(cpx<R>) * L.ns;
     hipError_t e;
     if ((e = chain_HL<R>(G, L, PRO_UPDATE, 0, B_PHI, B_HL, B_P, B_NONE, 0, s, tm))) return e;
-    return timed(tm, KK_EVAL, 2 * F, s, [&] { return launch_eval<R>(L.tab, L.ns, G.g, s); });
+    if ((e = timed(tm, KK_EVAL, 2 * F, s, [&] { return launch_eval<R>(L.tab, L.ns, G.g, s); }))) return e;
+    return fin<R>(G, L, FIN_EVAL, s, tm);
+}
+
+// normalisation of Phi (applied as a pending rescale by the next pass)
+template <typename R>
+static hipError_t normalize(const Geo<R>& G, Sub<R> L, hipStream_t s) {
+    hipError_t e;
+    if ((e = launch_normalize<R>(L.tab, L.ns, G.g, s))) return e;
+    return fin<R>(G, L, FIN_NORM, s, nullptr);
+}
+
+// residual norm of the current iterate (after a refresh)
+template <typename R>
+static hipError_t resid_final(const Geo<R>& G, Sub<R> L, hipStream_t s) {
+    hipError_t e;
+    if ((e = launch_resid<R>(L.tab, L.ns, G.g, 1, s))) return e;
+    return fin<R>(G, L, FIN_RFINAL, s, nullptr);
 }
 
 // One PCG iteration (Algorithm 1 with Algorithm 2), entirely on the device:
 //   0. (first iteration of a chunk) fresh H_L Phi, E, mu, alpha_l
 //   1. pending update Phi <- (c Phi + s P^)/|.|, H_L Phi by the same combination;
-//      r = H(Phi)Phi - mu Phi, P_V^{1/2} factors, stopping tests
-//   2. preconditioned residual (3 or 5 FFT passes) with the PRP beta,
-//      projection and descent test fused into its last pass
+//      r = H(Phi)Phi - mu Phi, P_V^{1/2} factors
+//   2. preconditioned residual (3 or 5 FFT passes) with the sums of the
+//      direction scalars fused into its last pass; control: stopping tests,
+//      PRP beta, projection and descent test
 //   3. P^n = D - Re<D,Phi> Phi, H_L P^ (3 or 5 FFT passes; Phi transformed
 //      alongside for the kinetic coefficients)
-//   4. energy along the retraction, step size, backtracking, and the scalars
-//      (mu, E, alpha_l) of the next iterate
+//   4. energy along the retraction; control: step size, backtracking, and the
+//      scalars (mu, E, alpha_l) of the next iterate
 template <typename R>
 static hipError_t iterate(const Geo<R>& G, Sub<R> L, int do_refresh, hipStream_t s, Timer* tm) {
     const double F = 3.0 * G.M * sizeof(cpx<R>) * L.ns, Fr = 3.0 * G.M * sizeof(R) * L.ns;
@@ -409,9 +444,11 @@ static hipError_t iterate(const Geo<R>& G, Sub<R> L, int do_refresh, hipStream_t
     if ((e = timed(tm, KK_RESID, 8 * F + Fr, s, [&] { return launch_resid<R>(L.tab, L.ns, G.g, 0, s); }))) return e;
     if (tm) tm->chain = 2;
     if ((e = chain_pre<R>(G, L, 1, B_PR, s, tm))) return e;
+    if ((e = fin<R>(G, L, FIN_DIR, s, tm))) return e;
     if (tm) tm->chain = 3;
     if ((e = chain_HL<R>(G, L, PRO_DIR, 1, B_P, B_HLP, B_PR, B_PHI, 1, s, tm))) return e;
-    return timed(tm, KK_LSRED, 4 * F, s, [&] { return launch_lsred<R>(L.tab, L.ns, G.g, s); });
+    if ((e = timed(tm, KK_LSRED, 4 * F, s, [&] { return launch_lsred<R>(L.tab, L.ns, G.g, s); }))) return e;
+    return fin<R>(G, L, FIN_LS, s, tm);
 }
 
 // ---------------------------------------------------------------------------
@@ -457,7 +494,6 @@ struct Class {
     hipEvent_t ev = nullptr;
     SolveState* d_st = nullptr;
     SolveState* h_st = nullptr;     // pinned mirror
-    unsigned* d_cnt = nullptr;
     Slot<R>* d_tab = nullptr;
     Slot<R>* h_tab = nullptr;       // pinned
     std::vector<std::unique_ptr<SlotMem<R>>> mem;   // by slot id
@@ -471,7 +507,6 @@ struct Class {
         if (stream) (void)hipStreamSynchronize(stream);
         mem.clear();
         if (d_st) (void)hipFree(d_st);
-        if (d_cnt) (void)hipFree(d_cnt);
         if (d_tab) (void)hipFree(d_tab);
         if (h_st) (void)hipHostFree(h_st);
         if (h_tab) (void)hipHostFree(h_tab);
@@ -490,13 +525,11 @@ struct OpPlan {
     std::unique_ptr<SlotMem<R>> mem;
     SolveState* d_st = nullptr;
     SolveState* h_st = nullptr;
-    unsigned* d_cnt = nullptr;
     Slot<R>* d_tab = nullptr;
     Slot<R>* h_tab = nullptr;
     ~OpPlan() {
         mem.reset();
         if (d_st) (void)hipFree(d_st);
-        if (d_cnt) (void)hipFree(d_cnt);
         if (d_tab) (void)hipFree(d_tab);
         if (h_st) (void)hipHostFree(h_st);
         if (h_tab) (void)hipHostFree(h_tab);
@@ -577,7 +610,7 @@ static int get_class(Ctx& cx, const gs_grid* g, int check_every, Class<R>** out)
     if (g->dim == 2) c->grid.n[2] = 1;
     c->check_every = check_every;
     c->M = npts(g);
-    c->g = red_geom(g);
+    c->g = red_geom<R>(g);
     for (int a = 0; a < g->dim; ++a) {
         int rc = get_twiddle<R>(cx, g->n[a], &c->tw[a]);
         if (rc) return rc;
@@ -586,7 +619,6 @@ static int get_class(Ctx& cx, const gs_grid* g, int check_every, Class<R>** out)
     HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&c->ev, hipEventDisableTiming));
     if (hipMalloc((void**)&c->d_st, sizeof(SolveState) * CLASS_CAP) != hipSuccess ||
-        hipMalloc((void**)&c->d_cnt, sizeof(unsigned) * NCOUNTERS * CLASS_CAP) != hipSuccess ||
         hipMalloc((void**)&c->d_tab, sizeof(Slot<R>) * CLASS_CAP) != hipSuccess) {
         (void)hipGetLastError();
         return fail(GS_ENOMEM, "device allocation failed (class tables)");
@@ -597,15 +629,13 @@ static int get_class(Ctx& cx, const gs_grid* g, int check_every, Class<R>** out)
         return fail(GS_ENOMEM, "pinned allocation failed (class tables)");
     }
     std::memset(c->h_st, 0, sizeof(SolveState) * CLASS_CAP);
-    HIPCHK(hipMemsetAsync(c->d_cnt, 0, sizeof(unsigned) * NCOUNTERS * CLASS_CAP, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
     *out = c.get();
     mp[key] = std::move(c);
     return GS_OK;
 }
 
 template <typename R>
-static Slot<R> entry_of(SlotMem<R>& m, SolveState* st, unsigned* cnt, const Phys& ph) {
+static Slot<R> entry_of(SlotMem<R>& m, SolveState* st, const Phys& ph) {
     Slot<R> e;
     std::memset(&e, 0, sizeof(e));
     for (int b = 0; b < NBUF; ++b) e.buf[b] = m.buf[b];
@@ -613,7 +643,7 @@ static Slot<R> entry_of(SlotMem<R>& m, SolveState* st, unsigned* cnt, const Phys
     e.st = st;
     e.red_mid = m.red_mid;
     e.red_pw = m.red_pw;
-    e.counter = cnt;
+    e.red_dir = m.red_dir;
     e.p = ph;
     return e;
 }
@@ -876,7 +906,7 @@ static int boundary(Ctx& cx, Class<R>& c) {
     for (int k : c.run) c.iter0.push_back(c.h_st[k].iter);
     auto put = [&](int k) {
         const Phys& ph = c.owner[k]->ph;
-        c.h_tab[nt++] = entry_of<R>(*c.mem[k], c.d_st + k, c.d_cnt + (size_t)k * NCOUNTERS, ph);
+        c.h_tab[nt++] = entry_of<R>(*c.mem[k], c.d_st + k, ph);
         rot_any |= ph.omega != 0.0;
         maxk = std::max(maxk, k + 1);
     };
@@ -890,11 +920,11 @@ static int boundary(Ctx& cx, Class<R>& c) {
     if (nfin) {
         const Sub<R> Lf{c.d_tab + nrun, nfin};
         HIPCHK(refresh<R>(G, Lf, s, nullptr));
-        HIPCHK(launch_resid<R>(Lf.tab, Lf.ns, G.g, 1, s));
+        HIPCHK(resid_final<R>(G, Lf, s));
         for (int k : c.fin)
             if ((rc = copy_out<R>(c, k, c.owner[k]))) return rc;
     }
-    if (nnew) HIPCHK(launch_normalize<R>(c.d_tab, nnew, G.g, s));
+    if (nnew) HIPCHK(normalize<R>(G, Sub<R>{c.d_tab, nnew}, s));
     if (nrun) {
         c.tm.kind = cx.timer.kind;
         Timer* tm = c.tm.kind >= 0 ? &c.tm : nullptr;
@@ -1057,13 +1087,12 @@ static int get_opplan(Ctx& cx, const gs_grid* g, OpPlan<R>** out, hipStream_t s)
     op->grid = *g;
     if (g->dim == 2) op->grid.n[2] = 1;
     op->M = npts(g);
-    op->g = red_geom(g);
+    op->g = red_geom<R>(g);
     int rc;
     for (int a = 0; a < g->dim; ++a)
         if ((rc = get_twiddle<R>(cx, g->n[a], &op->tw[a]))) return rc;
     if ((rc = alloc_slot_mem<R>(g, s, op->mem))) return rc;
     if (hipMalloc((void**)&op->d_st, sizeof(SolveState)) != hipSuccess ||
-        hipMalloc((void**)&op->d_cnt, sizeof(unsigned) * NCOUNTERS) != hipSuccess ||
         hipMalloc((void**)&op->d_tab, sizeof(Slot<R>)) != hipSuccess) {
         (void)hipGetLastError();
         return fail(GS_ENOMEM, "device allocation failed (operator plan)");
@@ -1073,7 +1102,6 @@ static int get_opplan(Ctx& cx, const gs_grid* g, OpPlan<R>** out, hipStream_t s)
         (void)hipGetLastError();
         return fail(GS_ENOMEM, "pinned allocation failed (operator plan)");
     }
-    HIPCHK(hipMemsetAsync(op->d_cnt, 0, sizeof(unsigned) * NCOUNTERS, s));
     *out = op.get();
     mp[key] = std::move(op);
     return GS_OK;
@@ -1089,7 +1117,7 @@ static int op_setup(OpPlan<R>& op, const Phys& ph, const void* x0, void* x1, hip
     gs_default_options(&o);
     o.max_iter = 1 << 30;
     init_state(op.h_st, &o, PH_FP64);
-    *op.h_tab = entry_of<R>(*op.mem, op.d_st, op.d_cnt, ph);
+    *op.h_tab = entry_of<R>(*op.mem, op.d_st, ph);
     op.h_tab->buf[B_X0] = (cpx<R>*)x0;
     op.h_tab->buf[B_X1] = (cpx<R>*)x1;
     HIPCHK(hipMemcpyAsync(op.d_st, op.h_st, sizeof(SolveState), hipMemcpyHostToDevice, s));
@@ -1161,7 +1189,7 @@ static int ham_impl(Ctx& cx, const gs_grid* g, const gs_trap* t, const gs_params
     hipError_t e = hipSuccess;
     if (!rc) e = hipMemcpyAsync(op->mem->buf[B_PHI], psi, sizeof(cpx<R>) * 3 * op->M, hipMemcpyDeviceToDevice, s);
     if (!rc && !e) e = refresh<R>(G, L, s, nullptr);
-    if (!rc && !e) e = launch_resid<R>(L.tab, 1, G.g, 1, s);
+    if (!rc && !e) e = resid_final<R>(G, L, s);
     if (!rc && !e) e = launch_hphi<R>(L.tab, 1, G.g, s);
     if (!rc && !e && (res || Vdev)) {
         e = hipMemcpyAsync(op->h_st, op->d_st, sizeof(SolveState), hipMemcpyDeviceToHost, s);

@@ -265,8 +265,8 @@ __global__ __launch_bounds__(NT) void k_invT(const Slot<R>* __restrict__ slots, 
 
 // ---------------------------------------------------------------------------
 // last pass of the preconditioner: P r = P_V^{1/2} (inverse transform), with the
-// direction reductions of the next step fused in (Re<r,Pr>, Re<r_prev,Pr>,
-// Re<phi,Pr>, |Pr|^2, Re<Pr,P^{n-1}>) and, in the last block, ctrl_dir.
+// partial sums of the direction reductions of the next step fused in
+// (Re<r,Pr>, Re<r_prev,Pr>, Re<phi,Pr>, |Pr|^2, Re<Pr,P^{n-1}>).
 // ---------------------------------------------------------------------------
 template <typename R, int N, int TILE>
 __global__ __launch_bounds__(NT) void k_invT_pre(const Slot<R>* __restrict__ slots, int iin, int iout, int B,
@@ -313,15 +313,7 @@ __global__ __launch_bounds__(NT) void k_invT_pre(const Slot<R>* __restrict__ slo
         }
     }
     if (!dir) return;
-    bsum<NS_DIR>(acc);
-    if (publish<NS_DIR>(acc, S.red_pw, S.counter + 2)) {
-        double tot[NS_DIR];
-        gather<NS_DIR>(tot, S.red_pw, gridDim.x, NS_MAX);
-        if (threadIdx.x == 0) {
-            ctrl_dir(st, S.p, tot);
-            S.counter[2] = 0;
-        }
-    }
+    block_row<NS_DIR>(acc, S.red_dir, RED_DIR_STRIDE);
 }
 
 // ---------------------------------------------------------------------------
@@ -452,11 +444,7 @@ __global__ __launch_bounds__(NT) void k_mid(const Slot<R>* __restrict__ slots, i
         outA[go] = v;
         if (doB) outB[go] = Y[L * PITCH + m];
     }
-    if (HL) {
-        bsum<(X2 ? NS_KIN : 4)>(acc);
-        if (threadIdx.x == 0)
-            for (int k = 0; k < (X2 ? NS_KIN : 4); ++k) red[(long long)blockIdx.x * RED_MID_STRIDE + k] = acc[k];
-    }
+    if (HL) block_row<(X2 ? NS_KIN : 4)>(acc, red, RED_MID_STRIDE);
 }
 
 // ---------------------------------------------------------------------------
@@ -472,6 +460,9 @@ template <typename R> constexpr int tile_inv(int N) {
 constexpr int lpb_mid(int N) { return N >= 256 ? 1 : (N >= 128 ? 2 : (N >= 64 ? 4 : 8)); }
 
 int mid_blocks(int N, int nlines) { return nlines / lpb_mid(N); }
+template <typename R> int invT_pre_blocks(int N, int B, int Cc) { return 3 * B * (Cc / tile_inv<R>(N)); }
+template int invT_pre_blocks<double>(int, int, int);
+template int invT_pre_blocks<float>(int, int, int);
 
 template <typename R, int N>
 static hipError_t fwdT_n(int pro, int dual, const Slot<R>* slots, int nslots, int in, int out, int aux0, int aux1,
@@ -531,8 +522,7 @@ static hipError_t invT_pre_n(const Slot<R>* slots, int nslots, int in, int out, 
     if (Cc % TILE) return hipErrorInvalidValue;
     const size_t lds = (size_t)TILE * (N + 1) * sizeof(cpx<R>);
     dim3 grid((unsigned)(3LL * B * (Cc / TILE)), (unsigned)nslots);
-    // the partial-sum buffer holds 3 Nz Ny / 2 rows (TILE >= 2)
-    static_assert(TILE >= 2, "partial-sum rows");
+    static_assert(NS_DIR <= RED_DIR_STRIDE, "partial-sum row");
     GS_LAUNCH((k_invT_pre<R, N, TILE>), grid, dim3(NT), lds, s, slots, in, out, B, Cc, dir, tw);
     return hipGetLastError();
 }

@@ -146,9 +146,9 @@ enum BufSel : int {
     NBUF,
     B_NONE = -1
 };
-constexpr int NS_MAX = 64;          // row stride of the per-block partial sums
+constexpr int NS_MAX = 64;          // row stride of the pointwise partial sums
 constexpr int RED_MID_STRIDE = 12;  // row stride of the middle-pass partial sums
-constexpr int NCOUNTERS = 8;
+constexpr int RED_DIR_STRIDE = 8;   // row stride of the preconditioner's last-pass partial sums
 
 template <typename R>
 struct Slot {
@@ -156,15 +156,17 @@ struct Slot {
     R* pv;               // [3][M] P_V^{1/2} factors (alpha_l + V + c0 rho)^{-1/2}
     SolveState* st;
     double* red_mid;     // [nblk_mid][RED_MID_STRIDE]
-    double* red_pw;      // [rows][NS_MAX]
-    unsigned* counter;   // [NCOUNTERS] completion counters of the reducing kernels
+    double* red_pw;      // [nblk_pw][NS_MAX]
+    double* red_dir;     // [nblk_dir][RED_DIR_STRIDE]
     Phys p;
 };
 
-// reduction geometry of a grid class (same for every slot of the class)
+// reduction geometry of a grid class (same for every slot of the class): the
+// number of partial-sum rows each reducing pass writes
 struct RedGeom {
-    int nblk_mid;
-    int nblk_pw;
+    int nblk_mid;   // middle pass of an H_L application
+    int nblk_pw;    // pointwise kernels
+    int nblk_dir;   // last pass of the preconditioner
 };
 
 // ---------------------------------------------------------------------------
@@ -196,7 +198,7 @@ hipError_t launch_invT(int N, int epi, const Slot<R>* slots, int nslots, int in,
                        hipStream_t s);
 
 // Last pass of the preconditioner: out = pv * IFFT(in); with dir = 1 also the
-// direction reductions and the direction control (SolveState written).
+// partial sums of the direction reductions (rows in red_dir).
 template <typename R>
 hipError_t launch_invT_pre(int N, const Slot<R>* slots, int nslots, int in, int out, int B, int Cc, int dir,
                            const cpx<R>* tw, hipStream_t s);
@@ -210,15 +212,28 @@ hipError_t launch_mid(int N, int op, const Slot<R>* slots, int nslots, int in, i
                       int rot_any, const cpx<R>* tw, hipStream_t s);
 
 int mid_blocks(int N, int nlines);
+// blocks (= partial-sum rows) of launch_invT_pre for these sizes
+template <typename R> int invT_pre_blocks(int N, int B, int Cc);
 
 // ---------------------------------------------------------------------------
-// pointwise kernels with fused reductions and device-side control (pw_kernels.hip)
+// pointwise kernels with fused partial sums (pw_kernels.hip), and the control
+// kernel that reduces the rows and takes the decisions of the iteration
 // ---------------------------------------------------------------------------
 template <typename R> hipError_t launch_eval(const Slot<R>* slots, int nslots, RedGeom g, hipStream_t s);
 template <typename R> hipError_t launch_resid(const Slot<R>* slots, int nslots, RedGeom g, int final_only, hipStream_t s);
 template <typename R> hipError_t launch_lsred(const Slot<R>* slots, int nslots, RedGeom g, hipStream_t s);
-// Phi <- Phi / |Phi| (sets pending_step with c = 1/|Phi|, s = 0)
+// partial sums of |Phi|^2 (the control step FIN_NORM sets the rescale Phi <- Phi / |Phi|)
 template <typename R> hipError_t launch_normalize(const Slot<R>* slots, int nslots, RedGeom g, hipStream_t s);
+enum Fin : int {
+    FIN_EVAL = 0,     // energy parts, mu, alpha_l of a fresh evaluation
+    FIN_DIR = 1,      // stopping tests of the residual pass, then PRP beta and projection
+    FIN_LS = 2,       // step size and the next iterate's scalars
+    FIN_NORM = 3,     // normalisation
+    FIN_RFINAL = 4,   // residual norm of the final iterate
+};
+// one block per slot: gather the partial-sum rows of the preceding pass(es) in
+// a fixed order and run the scalar control on thread 0
+template <typename R> hipError_t launch_fin(const Slot<R>* slots, int nslots, RedGeom g, int what, hipStream_t s);
 // precision conversion of a field of n complex values
 hipError_t launch_convert_d2f(const cpx<double>* in, cpx<float>* out, long long n, hipStream_t s);
 hipError_t launch_convert_f2d(const cpx<float>* in, cpx<double>* out, long long n, hipStream_t s);

@@ -1,10 +1,13 @@
-// Pointwise kernels of the PCG iteration with fused FP64 reductions.
+// Pointwise kernels of the PCG iteration with fused FP64 reductions, and the
+// control kernel.
 //
-// Every reducing kernel writes one row of per-block partial sums; the last
-// block to finish (completion counter) sums the rows in a fixed order and runs
-// the scalar part of the iteration (control.h) on thread 0. The grid size
-// depends only on the number of grid points, so the reduction order, and with
-// it every scalar, is reproducible run to run.
+// Every reducing kernel writes one row of per-block partial sums with plain
+// stores. A following control kernel (one block per slot) sums the rows in a
+// fixed order and runs the scalar part of the iteration (control.h) on thread
+// 0; the kernel boundary between them makes the rows visible, so no block
+// needs a device-wide fence. The grid size depends only on the number of grid
+// points, so the reduction order, and with it every scalar, is the same run to
+// run and whatever other slots share the launch.
 #include "device_common.h"
 #include "control.h"
 
@@ -49,16 +52,7 @@ __global__ __launch_bounds__(PT) void k_eval(const Slot<R>* slots, RedGeom g) {
         acc[16] += 0.5 * p.c1 * (2.0 * cabs2(sp.G) + sp.Fz * sp.Fz);   // |F|^2 = 2|G|^2 + F_z^2
         acc[17] += V4 * sp.rho;
     }
-    bsum<NS_EVAL>(acc);
-    if (publish<NS_EVAL>(acc, S.red_pw, S.counter + 0)) {
-        double tot[NS_EVAL], mt[4];
-        gather<NS_EVAL>(tot, S.red_pw, gridDim.x, NS_MAX);
-        gather<4>(mt, S.red_mid, g.nblk_mid, RED_MID_STRIDE);
-        if (threadIdx.x == 0) {
-            ctrl_eval(st, p, tot, mt);
-            S.counter[0] = 0;
-        }
-    }
+    block_row<NS_EVAL>(acc, S.red_pw, NS_MAX);
 }
 
 // ---------------------------------------------------------------------------
@@ -129,23 +123,10 @@ __global__ __launch_bounds__(PT) void k_resid(const Slot<R>* slots, RedGeom g, i
             acc[3] += cabs2(P[c]);
         }
     }
-    double v[NS_RES];
-    v[0] = bmax(acc[0]);
-    {
-        double t[3] = {acc[1], acc[2], acc[3]};
-        bsum<3>(t);
-        v[1] = t[0];
-        v[2] = t[1];
-        v[3] = t[2];
-    }
-    if (publish<NS_RES>(v, S.red_pw, S.counter + 1)) {
-        double tot[NS_RES];
-        gather<NS_RES>(tot, S.red_pw, gridDim.x, NS_MAX, 1u);
-        if (threadIdx.x == 0) {
-            ctrl_resid(st, p, tot, final_only);
-            S.counter[1] = 0;
-        }
-    }
+    const double m = bmax(acc[0]);
+    if (threadIdx.x == 0) S.red_pw[(long long)blockIdx.x * NS_MAX] = m;
+    const double t[3] = {acc[1], acc[2], acc[3]};
+    block_row<3>(t, S.red_pw + 1, NS_MAX);   // entries 1..3 of the row
 }
 
 // ---------------------------------------------------------------------------
@@ -223,16 +204,7 @@ __global__ __launch_bounds__(PT) void k_lsred(const Slot<R>* slots, RedGeom g) {
             T[4] += p.c0 * q2r * n2[c];
         }
     }
-    bsum<NS_LS>(acc);
-    if (publish<NS_LS>(acc, S.red_pw, S.counter + 3)) {
-        double tot[NS_LS], kin[NS_KIN];
-        gather<NS_LS>(tot, S.red_pw, gridDim.x, NS_MAX);
-        gather<NS_KIN>(kin, S.red_mid, g.nblk_mid, RED_MID_STRIDE);
-        if (threadIdx.x == 0) {
-            ctrl_ls(st, p, tot, kin);
-            S.counter[3] = 0;
-        }
-    }
+    block_row<NS_LS>(acc, S.red_pw, NS_MAX);
 }
 
 // ---------------------------------------------------------------------------
@@ -248,10 +220,50 @@ __global__ __launch_bounds__(PT) void k_normalize(const Slot<R>* slots, RedGeom 
     double acc[1] = {0.0};
     for (long long i = (long long)blockIdx.x * PT + threadIdx.x; i < n3; i += (long long)gridDim.x * PT)
         acc[0] += cabs2(wid(phi[i]));
-    bsum<1>(acc);
-    if (publish<1>(acc, S.red_pw, S.counter + 4)) {
+    block_row<1>(acc, S.red_pw, NS_MAX);
+}
+
+// ---------------------------------------------------------------------------
+// control: one block per slot gathers the rows of the preceding pass(es)
+// ---------------------------------------------------------------------------
+//   FIN_EVAL:   eval rows + middle-pass rows -> ctrl_eval
+//   FIN_DIR:    residual rows -> ctrl_resid; unless that ended the solve,
+//               preconditioner rows -> ctrl_dir
+//   FIN_LS:     line-search rows + middle-pass rows -> ctrl_ls
+//   FIN_NORM:   |Phi|^2 rows -> rescale of Phi (pending step with s = 0)
+//   FIN_RFINAL: residual rows of a final-only residual pass
+template <typename R>
+__global__ __launch_bounds__(PT) void k_fin(const Slot<R>* slots, RedGeom g, int what) {
+    const Slot<R>& S = slots[blockIdx.y];
+    SolveState* st = S.st;
+    const Phys p = S.p;
+    if (what != FIN_NORM && what != FIN_RFINAL && st->done) return;
+    if (what == FIN_EVAL) {
+        double tot[NS_EVAL], mt[4];
+        gather<NS_EVAL>(tot, S.red_pw, g.nblk_pw, NS_MAX);
+        gather<4>(mt, S.red_mid, g.nblk_mid, RED_MID_STRIDE);
+        if (threadIdx.x == 0) ctrl_eval(st, p, tot, mt);
+    } else if (what == FIN_DIR) {
+        double tot[NS_RES];
+        gather<NS_RES>(tot, S.red_pw, g.nblk_pw, NS_MAX, 1u);
+        __shared__ int stop;
+        if (threadIdx.x == 0) {
+            ctrl_resid(st, p, tot, 0);
+            stop = st->done;
+        }
+        __syncthreads();
+        if (stop) return;
+        double dt[NS_DIR];
+        gather<NS_DIR>(dt, S.red_dir, g.nblk_dir, RED_DIR_STRIDE);
+        if (threadIdx.x == 0) ctrl_dir(st, p, dt);
+    } else if (what == FIN_LS) {
+        double tot[NS_LS], kin[NS_KIN];
+        gather<NS_LS>(tot, S.red_pw, g.nblk_pw, NS_MAX);
+        gather<NS_KIN>(kin, S.red_mid, g.nblk_mid, RED_MID_STRIDE);
+        if (threadIdx.x == 0) ctrl_ls(st, p, tot, kin);
+    } else if (what == FIN_NORM) {
         double tot[1];
-        gather<1>(tot, S.red_pw, gridDim.x, NS_MAX);
+        gather<1>(tot, S.red_pw, g.nblk_pw, NS_MAX);
         if (threadIdx.x == 0) {
             const double n2 = tot[0] * p.cell;
             if (!(n2 > 0.0) || !isfinite(n2)) {
@@ -264,8 +276,11 @@ __global__ __launch_bounds__(PT) void k_normalize(const Slot<R>* slots, RedGeom 
                 st->inv_norm = 1.0;
                 st->pending_step = 1;
             }
-            S.counter[4] = 0;
         }
+    } else if (what == FIN_RFINAL) {
+        double tot[NS_RES];
+        gather<NS_RES>(tot, S.red_pw, g.nblk_pw, NS_MAX, 1u);
+        if (threadIdx.x == 0) ctrl_resid(st, p, tot, 1);
     }
 }
 
@@ -359,6 +374,10 @@ template <typename R> hipError_t launch_normalize(const Slot<R>* slots, int nslo
     GS_LAUNCH(k_normalize<R>, dim3(g.nblk_pw, nslots), dim3(PT), 0, s, slots, g);
     return hipGetLastError();
 }
+template <typename R> hipError_t launch_fin(const Slot<R>* slots, int nslots, RedGeom g, int what, hipStream_t s) {
+    GS_LAUNCH(k_fin<R>, dim3(1, nslots), dim3(PT), 0, s, slots, g, what);
+    return hipGetLastError();
+}
 hipError_t launch_convert_d2f(const cpx<double>* in, cpx<float>* out, long long n, hipStream_t s) {
     GS_LAUNCH(k_d2f, dim3(pw_blocks(n)), dim3(PT), 0, s, in, out, n);
     return hipGetLastError();
@@ -385,6 +404,7 @@ hipError_t launch_gaussian(cpx<double>* out, const Phys& p, hipStream_t s) {
     template hipError_t launch_resid<R>(const Slot<R>*, int, RedGeom, int, hipStream_t);              \
     template hipError_t launch_lsred<R>(const Slot<R>*, int, RedGeom, hipStream_t);                   \
     template hipError_t launch_normalize<R>(const Slot<R>*, int, RedGeom, hipStream_t);               \
+    template hipError_t launch_fin<R>(const Slot<R>*, int, RedGeom, int, hipStream_t);                \
     template hipError_t launch_hphi<R>(const Slot<R>*, int, RedGeom, hipStream_t);                    \
     template hipError_t launch_pvin<R>(const Slot<R>*, int, RedGeom, hipStream_t);
 GS_INST(double)

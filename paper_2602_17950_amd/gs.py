@@ -26,7 +26,7 @@ EXPORTS = ("gs_create", "gs_destroy", "gs_default_options", "gs_footprint_bytes"
            "gs_batch_solve", "gs_submit", "gs_progress", "gs_poll", "gs_wait", "gs_cancel")
 
 KERNEL_KINDS = {"hl_fwd": 0, "hl_mid": 1, "hl_inv": 2, "pre_fwd": 3, "pre_mid": 4, "pre_inv": 5,
-                "eval": 6, "resid": 7, "dirred": 8, "lsred": 9, "hl_fwd2": 10, "hl_inv2": 11}
+                "eval": 6, "resid": 7, "lsred": 9, "hl_fwd2": 10, "hl_inv2": 11, "ctrl": 12}
 
 
 class GsError(RuntimeError):
