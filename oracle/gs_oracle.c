@@ -669,11 +669,13 @@ int orc_pcg(const orc_grid* g, const orc_trap* t, const orc_params* p, const orc
     size_t bytes = sizeof(cplx) * n3;
     cplx* hphi = (cplx*)malloc(bytes);
     cplx* r = (cplx*)malloc(bytes);
-    cplx* r_prev = (cplx*)malloc(bytes);
+    /* no previous residual or direction exists at n = 0 (beta = 0 there);
+     * zero them so that 0 * P^{-1} is exactly 0 */
+    cplx* r_prev = (cplx*)calloc((size_t)n3, sizeof(cplx));
     cplx* pr = (cplx*)malloc(bytes);
     cplx* D = (cplx*)malloc(bytes);
     cplx* P = (cplx*)malloc(bytes);
-    cplx* P_prev = (cplx*)malloc(bytes);
+    cplx* P_prev = (cplx*)calloc((size_t)n3, sizeof(cplx));
     cplx* trial = (cplx*)malloc(bytes);
     memset(st, 0, sizeof(*st));
     int status = ORC_OK;
