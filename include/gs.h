@@ -104,6 +104,9 @@ typedef struct {
     double sigma;         /* Algorithm 2: backtracking factor in (0, 1) */
     int max_backtrack;    /* cap on backtracking steps per iteration */
     int check_every;      /* iterations enqueued between two host checks of completion */
+    int cm_levels;        /* cascadic multigrid (Algorithm 3): solve on grids n/2^(L-1), ..., n/2, n
+                             (every n[a]/2^(L-1) >= 16), each level warm-started from the
+                             interpolated result of the previous one; 1 = plain PCG */
 } gs_options;
 
 /* Results; quantities refer to the returned Phi. */
@@ -122,6 +125,7 @@ typedef struct {
     int resets;           /* descent-safeguard resets of beta to 0 */
     int status;           /* return code of the solve */
     double wall_s;        /* wall time of the call */
+    int iters_coarse;     /* accepted steps on the coarser levels of a cascadic multigrid solve */
 } gs_result;
 
 /* One solve request of the batch and serving entry points. The trap's V (host)
@@ -146,7 +150,7 @@ int gs_create(gs_ctx** out, int device);
 void gs_destroy(gs_ctx* ctx);
 /* Fill *o with the defaults: energy criterion, tol 1e-12, max_iter 100000,
  * FP64, switch_resid 1e-6, fp32_max_iter 20000, stall_window 50,
- * theta_trial 0.1, sigma 0.5, max_backtrack 40, check_every 32. */
+ * theta_trial 0.1, sigma 0.5, max_backtrack 40, check_every 32, cm_levels 1. */
 void gs_default_options(gs_options* o);
 /* Device bytes a solve of this grid needs at this precision (GS_MIXED counts
  * both the float and the double working sets). 0 for an invalid grid. */
@@ -163,7 +167,9 @@ int gs_memory_stats(gs_ctx* ctx, size_t* budget, size_t* reserved, size_t* alloc
 
 /* Ground state from a host initial guess (Algorithm 1). psi0: host complex128
  * [3][Nz][Ny][Nx], or NULL for the Gaussian guess (a, a, a)/sqrt(3) of Sec. 4;
- * it is normalised before the iteration. psi_out: host complex128, same shape,
+ * it is normalised before the iteration. With options.cm_levels = L > 1 the
+ * guess lives on the coarsest grid (n[a] / 2^(L-1) points per axis), the
+ * result on the grid g; a sampled trap V is not accepted then. psi_out: host complex128, same shape,
  * caller-allocated (may equal psi0). res: filled on success and on warnings.
  * Synchronous. */
 int gs_solve(gs_ctx* ctx, const gs_grid* g, const gs_trap* t, const gs_params* p,
@@ -201,6 +207,16 @@ int gs_progress(gs_ctx* ctx, int block);
 int gs_poll(gs_ctx* ctx, uint64_t ticket, gs_result* res);
 int gs_wait(gs_ctx* ctx, uint64_t ticket, gs_result* res);
 int gs_cancel(gs_ctx* ctx, uint64_t ticket);
+
+/* Fourier interpolation between grids of the same box (Sec. 3.3, the
+ * interpolation step of Algorithm 3): the spectrum of d_in on gc (complex128
+ * [3][gc]) is zero-padded to gf (each gf->n[a] >= gc->n[a], same L), the
+ * coarse Nyquist coefficient split equally between +n/2 and -n/2, and
+ * transformed back, so the coarse grid points are reproduced. d_out: complex128
+ * [3][gf]. The call first waits for work already queued on `stream`, then
+ * enqueues the interpolation on it and returns. */
+int gs_interpolate(gs_ctx* ctx, const gs_grid* gc, const void* d_in, const gs_grid* gf, void* d_out,
+                   void* stream);
 
 /* Forward (sign = -1, unnormalised) or inverse (sign = +1, divided by the
  * number of points) discrete Fourier transform of each of the three

@@ -72,6 +72,7 @@ static int check_options(const gs_options* o) {
     if (!(o->theta_trial > 0.0)) return fail(GS_EINVAL, "options.theta_trial must be positive");
     if (o->max_backtrack < 0) return fail(GS_EINVAL, "options.max_backtrack must be >= 0");
     if (o->check_every < 1) return fail(GS_EINVAL, "options.check_every must be >= 1");
+    if (o->cm_levels < 1 || o->cm_levels > 7) return fail(GS_EINVAL, "options.cm_levels must be in [1, 7]");
     return GS_OK;
 }
 
@@ -305,6 +306,7 @@ static void fill_result(const SolveState* h, gs_result* r, int iters_fp32, doubl
     }
     r->iters_fp32 = iters_fp32;
     r->wall_s = wall;
+    r->iters_coarse = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -471,15 +473,26 @@ struct Job {
     int slot = -1;           // slot in the current class (preset for a hand-over)
     bool handover = false;   // queued in the double class after the float phase
     SolveState mig{};        // state handed over from the float phase
-    hipEvent_t mig_ev = nullptr;
+    hipEvent_t ev = nullptr; // the guess or hand-over is complete (recorded on another stream)
+    bool wait_ev = false;
     int iters_fp32 = 0;
+    // cascadic multigrid: levels coarse to fine; the current level's grid is `grid`
+    int level = 0, nlevels = 1;
+    gs_grid fine{};
+    gs_trap trap{};
+    gs_params prm{};
+    cpx<double>* cm_buf[2] = {nullptr, nullptr};   // level result / interpolated guess (finest size)
+    cpx<double>* user_out = nullptr;
+    int iters_coarse = 0;
     int rc = GS_OK;
     gs_result res{};
     std::string err;
     std::chrono::steady_clock::time_point t0;
     ~Job() {
         if (Vdev) (void)hipFree(Vdev);
-        if (mig_ev) (void)hipEventDestroy(mig_ev);
+        for (auto* b : cm_buf)
+            if (b) (void)hipFree(b);
+        if (ev) (void)hipEventDestroy(ev);
     }
 };
 
@@ -548,6 +561,7 @@ struct Ctx {
     std::map<std::pair<int, int>, void*> twiddles;   // (N, sizeof(R)) -> table
     std::map<uint64_t, std::unique_ptr<Job>> jobs;
     uint64_t next_ticket = 1, next_seq = 1;
+    uint64_t moves = 0;   // requests queued into another class (hand-overs, multigrid levels)
     size_t budget = 0, reserved = 0, allocated = 0;
     TimerTotals timer;
     ~Ctx() {
@@ -713,6 +727,7 @@ static int acquire_slot(Ctx& cx, Class<R>& c, Job* j, hipStream_t s, int* out) {
 static void finish_job(Ctx& cx, Job* j, int rc, const SolveState* h, const std::string& msg) {
     const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() - j->t0).count();
     fill_result(h, &j->res, j->iters_fp32, wall);
+    j->res.iters_coarse = j->iters_coarse;
     j->res.status = rc;
     j->rc = rc;
     if (rc < 0) j->err = msg;
@@ -736,8 +751,9 @@ static int hand_over(Ctx& cx, Class<float>& c, int k, Job* j) {
     if (rc == SLOT_WAIT) return fail(GS_ENOMEM, "no device memory for the double phase");
     if (rc) return rc;
     HIPCHK(launch_convert_f2d(c.mem[k]->buf[B_PHI], d->mem[kd]->buf[B_PHI], 3 * c.M, c.stream));
-    if (!j->mig_ev) HIPCHK(hipEventCreateWithFlags(&j->mig_ev, hipEventDisableTiming));
-    HIPCHK(hipEventRecord(j->mig_ev, c.stream));
+    if (!j->ev) HIPCHK(hipEventCreateWithFlags(&j->ev, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(j->ev, c.stream));
+    j->wait_ev = true;
     SolveState h = c.h_st[k];
     j->iters_fp32 = h.iter;
     h.done = 0;
@@ -753,6 +769,7 @@ static int hand_over(Ctx& cx, Class<float>& c, int k, Job* j) {
     j->handover = true;
     j->stage = JS_QUEUED;
     d->queue.push_front(j);
+    cx.moves++;
     return GS_OK;
 }
 
@@ -787,6 +804,69 @@ static int copy_out(Class<R>& c, int k, Job* j) {
     return GS_OK;
 }
 
+template <typename R> static int fft_impl(Ctx& cx, const gs_grid* g, int sign, const cpx<R>* in, cpx<R>* out,
+                                          hipStream_t s);
+
+// Fourier interpolation gc -> gf (same box): forward transform on gc,
+// zero-padding of the spectrum, inverse transform on gf. tmp: [3][gc] scratch.
+static int interp_impl(Ctx& cx, const gs_grid* gc, const cpx<double>* in, const gs_grid* gf, cpx<double>* out,
+                       cpx<double>* tmp, hipStream_t s) {
+    int rc;
+    if ((rc = fft_impl<double>(cx, gc, -1, in, tmp, s))) return rc;     // coarse spectrum in tmp
+    const int nc[3] = {gc->n[0], gc->n[1], gc->dim == 3 ? gc->n[2] : 1};
+    const int nf[3] = {gf->n[0], gf->n[1], gf->dim == 3 ? gf->n[2] : 1};
+    HIPCHK(launch_spec_pad(tmp, out, gc->dim, nc, nf, s));                // fine spectrum in out
+    // in place: the first pass of the transform only reads, the last only writes
+    return fft_impl<double>(cx, gf, +1, out, out, s);
+}
+
+static gs_grid level_grid(const gs_grid& fine, int nlevels, int level) {
+    gs_grid g = fine;
+    const int sh = nlevels - 1 - level;
+    for (int a = 0; a < fine.dim; ++a) g.n[a] = fine.n[a] >> sh;
+    if (fine.dim == 2) g.n[2] = 1;
+    return g;
+}
+
+// Cascadic multigrid: the level just finished wrote its result to cm_buf[0];
+// interpolate it to the next grid (into cm_buf[1], the next level's guess) on
+// stream s and queue the request in the next grid's class.
+static int next_level(Ctx& cx, Job* j, hipStream_t s) {
+    const gs_grid gc = j->grid;
+    const gs_grid gf = level_grid(j->fine, j->nlevels, j->level + 1);
+    int rc;
+    // cm_buf[0] (coarse result) is free after the forward transform: it holds
+    // the padded spectrum; cm_buf[1] is scratch, then the result
+    if ((rc = fft_impl<double>(cx, &gc, -1, j->cm_buf[0], j->cm_buf[1], s))) return rc;
+    const int nc[3] = {gc.n[0], gc.n[1], gc.dim == 3 ? gc.n[2] : 1};
+    const int nf[3] = {gf.n[0], gf.n[1], gf.dim == 3 ? gf.n[2] : 1};
+    HIPCHK(launch_spec_pad(j->cm_buf[1], j->cm_buf[0], gc.dim, nc, nf, s));
+    if ((rc = fft_impl<double>(cx, &gf, +1, j->cm_buf[0], j->cm_buf[1], s))) return rc;
+    if (!j->ev) HIPCHK(hipEventCreateWithFlags(&j->ev, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(j->ev, s));
+    j->wait_ev = true;
+    j->level++;
+    j->grid = gf;
+    if ((rc = make_phys(&gf, &j->trap, &j->prm, &j->ph))) return rc;
+    j->psi0 = j->cm_buf[1];
+    j->out = j->level + 1 == j->nlevels ? j->user_out : j->cm_buf[0];
+    j->iters_fp32 = 0;
+    j->stage = JS_QUEUED;
+    j->slot = -1;
+    j->handover = false;
+    if (j->opt.precision == GS_FP64) {
+        Class<double>* c;
+        if ((rc = get_class<double>(cx, &gf, j->opt.check_every, &c))) return rc;
+        c->queue.push_front(j);
+    } else {
+        Class<float>* c;
+        if ((rc = get_class<float>(cx, &gf, j->opt.check_every, &c))) return rc;
+        c->queue.push_front(j);
+    }
+    cx.moves++;
+    return GS_OK;
+}
+
 // Chunk boundary of a class whose previous chunk (if any) has completed:
 // retire finished solves, start final evaluations, hand over float phases,
 // admit queued requests, then enqueue the next chunk.
@@ -798,10 +878,13 @@ static int boundary(Ctx& cx, Class<R>& c) {
     for (int k : c.fin) {
         Job* j = c.owner[k];
         const SolveState& h = c.h_st[k];
+        c.owner[k] = nullptr;
         if (!is64) j->iters_fp32 = h.iter;
         if (h.nonfinite) finish_job(cx, j, GS_ENONFINITE, &h, "non-finite value in the final evaluation");
-        else finish_job(cx, j, h.status, &h, "");
-        c.owner[k] = nullptr;
+        else if (j->level + 1 < j->nlevels && !j->cancel) {
+            j->iters_coarse += h.iter;
+            if ((rc = next_level(cx, j, c.stream))) finish_job(cx, j, rc, &h, g_err);
+        } else finish_job(cx, j, h.status, &h, "");
     }
     c.fin.clear();
     // 2. slots of the chunk that has completed
@@ -852,26 +935,33 @@ static int boundary(Ctx& cx, Class<R>& c) {
         j->stage = JS_FINAL;
         c.fin.push_back(k);
     }
-    // 3. admissions, hand-overs first (they are at the front of the queue)
+    // 3. admissions. Requests that already hold their reservation (hand-overs
+    //    and later multigrid levels) are always admitted; new requests in
+    //    arrival order while their footprint fits in the budget.
     std::vector<int> fresh;
+    std::deque<Job*> waiting;
+    bool blocked = false;
     while (!c.queue.empty()) {
         Job* j = c.queue.front();
+        c.queue.pop_front();
         if (j->cancel) {
-            c.queue.pop_front();
             if (j->slot >= 0) c.owner[j->slot] = nullptr;
             finish_job(cx, j, GS_ECANCELED, nullptr, "request cancelled");
             continue;
         }
         int k = j->slot;
-        if (j->handover) {
-            c.h_st[k] = j->mig;
-            HIPCHK(hipStreamWaitEvent(c.stream, j->mig_ev, 0));
-            j->handover = false;
-        } else {
-            if (!j->admitted && cx.reserved + j->reserve > cx.budget) break;   // wait for memory
+        if (!j->handover) {
+            if (!j->admitted && (blocked || cx.reserved + j->reserve > cx.budget)) {
+                blocked = true;   // wait for memory; later new requests wait behind it
+                waiting.push_back(j);
+                continue;
+            }
             rc = acquire_slot<R>(cx, c, j, c.stream, &k);
-            if (rc == SLOT_WAIT) break;
-            c.queue.pop_front();
+            if (rc == SLOT_WAIT) {
+                blocked = blocked || !j->admitted;
+                waiting.push_back(j);
+                continue;
+            }
             if (rc) {
                 finish_job(cx, j, rc, nullptr, g_err);
                 continue;
@@ -881,18 +971,23 @@ static int boundary(Ctx& cx, Class<R>& c) {
                 j->admitted = true;
             }
             j->slot = k;
+        }
+        if (j->wait_ev) {
+            HIPCHK(hipStreamWaitEvent(c.stream, j->ev, 0));
+            j->wait_ev = false;
+        }
+        if (j->handover) {
+            c.h_st[k] = j->mig;
+            j->handover = false;
+        } else {
             init_state(&c.h_st[k], &j->opt, j->opt.precision == GS_MIXED ? PH_FP32 : PH_FP64);
             if ((rc = load_guess<R>(c, k, j))) return rc;
-            fresh.push_back(k);
-            j->stage = JS_RUNNING;
-            HIPCHK(hipMemsetAsync(c.mem[k]->buf[B_P], 0, sizeof(cpx<R>) * 3 * c.M, c.stream));
-            continue;
         }
-        c.queue.pop_front();
+        HIPCHK(hipMemsetAsync(c.mem[k]->buf[B_P], 0, sizeof(cpx<R>) * 3 * c.M, c.stream));
         fresh.push_back(k);
         j->stage = JS_RUNNING;
-        HIPCHK(hipMemsetAsync(c.mem[k]->buf[B_P], 0, sizeof(cpx<R>) * 3 * c.M, c.stream));
     }
+    c.queue = std::move(waiting);
     // 4. launch table: [fresh..., continuing...] run the chunk, then the slots
     //    under final evaluation
     c.run = fresh;
@@ -963,10 +1058,12 @@ static int progress(Ctx& cx, bool block) {
     for (;;) {
         bool did = false;
         int rc;
+        const uint64_t moves0 = cx.moves;
         for (auto& kv : cx.c32)
             if ((rc = visit<float>(cx, *kv.second, did))) return rc;
         for (auto& kv : cx.c64)
             if ((rc = visit<double>(cx, *kv.second, did))) return rc;
+        if (cx.moves != moves0) continue;   // a request entered a class already visited
         if (!block || did) return GS_OK;
         hipEvent_t e = nullptr;
         uint64_t best = UINT64_MAX;
@@ -986,16 +1083,36 @@ static int submit_job(Ctx& cx, const gs_request* q, uint64_t* ticket) {
     if ((rc = check_options(&q->options))) return rc;
     if (!q->d_psi_out) return fail(GS_EINVAL, "request.d_psi_out is NULL");
     auto j = std::make_unique<Job>();
-    j->grid = q->grid;
-    if (j->grid.dim == 2) j->grid.n[2] = 1;
+    j->fine = q->grid;
+    if (j->fine.dim == 2) j->fine.n[2] = 1;
     j->opt = q->options;
+    j->nlevels = q->options.cm_levels;
+    j->trap = q->trap;
+    j->trap.V = nullptr;
+    j->prm = q->params;
+    if (j->nlevels > 1) {
+        if (q->trap.V) return fail(GS_EINVAL, "a sampled trap V cannot be used with cm_levels > 1");
+        for (int a = 0; a < j->fine.dim; ++a)
+            if ((j->fine.n[a] >> (j->nlevels - 1)) < 16)
+                return fail(GS_EINVAL, "cm_levels too large: the coarsest grid needs n[a] >= 16");
+    }
+    j->grid = level_grid(j->fine, j->nlevels, 0);
+    if ((rc = make_phys(&j->fine, &q->trap, &q->params, &j->ph))) return rc;   // validates the full-size V
     if ((rc = make_phys(&j->grid, &q->trap, &q->params, &j->ph))) return rc;
-    const long long M = npts(&j->grid);
+    const long long M = npts(&j->fine);
     j->reserve = 0;
-    if (q->options.precision != GS_FP32) j->reserve += slot_bytes<double>(&j->grid);
-    if (q->options.precision != GS_FP64) j->reserve += slot_bytes<float>(&j->grid);
+    if (q->options.precision != GS_FP32) j->reserve += slot_bytes<double>(&j->fine);
+    if (q->options.precision != GS_FP64) j->reserve += slot_bytes<float>(&j->fine);
     if (q->trap.V) j->reserve += sizeof(double) * M;
+    if (j->nlevels > 1) j->reserve += 2 * sizeof(cpx<double>) * 3 * M;
     if (j->reserve > cx.budget) return fail(GS_ENOMEM, "request needs more device memory than the budget");
+    if (j->nlevels > 1)
+        for (auto*& b : j->cm_buf)
+            if (hipMalloc((void**)&b, sizeof(cpx<double>) * 3 * M) != hipSuccess) {
+                b = nullptr;
+                (void)hipGetLastError();
+                return fail(GS_ENOMEM, "device allocation failed (multigrid buffers)");
+            }
     if (q->trap.V) {
         if (hipMalloc((void**)&j->Vdev, sizeof(double) * M) != hipSuccess) {
             j->Vdev = nullptr;
@@ -1006,7 +1123,8 @@ static int submit_job(Ctx& cx, const gs_request* q, uint64_t* ticket) {
         j->ph.V = j->Vdev;
     }
     j->psi0 = (const cpx<double>*)q->d_psi0;
-    j->out = (cpx<double>*)q->d_psi_out;
+    j->user_out = (cpx<double>*)q->d_psi_out;
+    j->out = j->nlevels > 1 ? j->cm_buf[0] : j->user_out;
     j->t0 = std::chrono::steady_clock::now();
     if (q->options.precision == GS_FP64) {
         Class<double>* c;
@@ -1258,6 +1376,7 @@ void gs_default_options(gs_options* o) {
     o->sigma = 0.5;
     o->max_backtrack = 40;
     o->check_every = 32;
+    o->cm_levels = 1;
 }
 
 size_t gs_footprint_bytes(const gs_grid* g, int precision) {
@@ -1436,6 +1555,28 @@ int gs_batch_solve(gs_ctx* ctx, int nreq, const gs_request* reqs, gs_result* res
     }
     (void)first_err;
     return GS_OK;
+}
+
+int gs_interpolate(gs_ctx* ctx, const gs_grid* gc, const void* d_in, const gs_grid* gf, void* d_out, void* stream) {
+    if (!ctx || !d_in || !d_out) return fail(GS_EINVAL, "NULL argument");
+    int rc;
+    if ((rc = check_grid(gc)) || (rc = check_grid(gf))) return rc;
+    if (gc->dim != gf->dim) return fail(GS_EINVAL, "grids of different dimension");
+    for (int a = 0; a < gc->dim; ++a)
+        if (gf->n[a] < gc->n[a] || gf->L[a] != gc->L[a])
+            return fail(GS_EINVAL, "the fine grid must have at least as many points per axis on the same box");
+    Ctx& cx = ctx->impl;
+    if (hipSetDevice(cx.device) != hipSuccess) return fail(GS_EDEVICE, "hipSetDevice failed");
+    cpx<double>* tmp = nullptr;
+    if (hipMalloc((void**)&tmp, sizeof(cpx<double>) * 3 * npts(gc)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(GS_ENOMEM, "device allocation failed (interpolation scratch)");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    rc = interp_impl(cx, gc, (const cpx<double>*)d_in, gf, (cpx<double>*)d_out, tmp, s);
+    if (hipStreamSynchronize(s) != hipSuccess && !rc) rc = fail(GS_EDEVICE, "hipStreamSynchronize failed");
+    (void)hipFree(tmp);
+    return rc;
 }
 
 int gs_kernel_timer_start(gs_ctx* ctx, int kind) {

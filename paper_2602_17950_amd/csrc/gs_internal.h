@@ -241,6 +241,9 @@ hipError_t launch_convert_f2d(const cpx<float>* in, cpx<double>* out, long long 
 template <typename R> hipError_t launch_hphi(const Slot<R>* slots, int nslots, RedGeom g, hipStream_t s);
 // preconditioner input for the given r in X0: pv = (alpha_l + V + c0 rho)^{-1/2}, u = pv r
 template <typename R> hipError_t launch_pvin(const Slot<R>* slots, int nslots, RedGeom g, hipStream_t s);
+// zero-padding of a [3][nc] spectrum to [3][nf] (n[2] = 1 in 2D), scaled by Mf/Mc
+hipError_t launch_spec_pad(const cpx<double>* in, cpx<double>* out, int dim, const int nc[3], const int nf[3],
+                           hipStream_t s);
 // Gaussian (a, a, a) initial guess
 hipError_t launch_gaussian(cpx<double>* out, const Phys& p, hipStream_t s);
 

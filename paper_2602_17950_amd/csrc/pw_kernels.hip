@@ -355,6 +355,33 @@ __global__ void k_gaussian(cpx<double>* out, Phys p) {
     }
 }
 
+// Zero-padding of a spectrum from grid nc to grid nf (both in natural FFT
+// order, [3][Nz][Ny][Nx]): the coefficient of wavenumber index p (|p| < nc/2)
+// moves to the fine index of p; the coarse Nyquist coefficient (p = -nc/2)
+// goes half to +nc/2 and half to -nc/2 of the fine grid (whole when the axis
+// is not refined); all other fine coefficients are zero. `scale` = Mf/Mc keeps
+// the values after the 1/Mf of the inverse transform.
+__device__ __forceinline__ double pad_weight(int jf, int nf, int nc, int& jc) {
+    const int p = (jf < nf / 2) ? jf : jf - nf;
+    if (p > -nc / 2 && p < nc / 2) { jc = (p + nc) % nc; return 1.0; }
+    if (p == nc / 2 || p == -nc / 2) { jc = nc / 2; return nf == nc ? 1.0 : 0.5; }
+    jc = 0;
+    return 0.0;
+}
+__global__ void k_spec_pad(const cpx<double>* in, cpx<double>* out, int dim, int ncx, int ncy, int ncz, int nfx,
+                           int nfy, int nfz, double scale) {
+    const long long Mf = (long long)nfx * nfy * nfz, Mc = (long long)ncx * ncy * ncz;
+    for (long long i = (long long)blockIdx.x * PT + threadIdx.x; i < Mf; i += (long long)gridDim.x * PT) {
+        const int jx = (int)(i % nfx), jy = (int)((i / nfx) % nfy), jz = (int)(i / ((long long)nfx * nfy));
+        int cx, cy, cz = 0;
+        double w = pad_weight(jx, nfx, ncx, cx) * pad_weight(jy, nfy, ncy, cy);
+        if (dim == 3) w *= pad_weight(jz, nfz, ncz, cz);
+        const long long ic = ((long long)cz * ncy + cy) * ncx + cx;
+        for (int c = 0; c < 3; ++c)
+            out[c * Mf + i] = w == 0.0 ? cmk(0.0, 0.0) : (scale * w) * in[c * Mc + ic];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -392,6 +419,13 @@ template <typename R> hipError_t launch_hphi(const Slot<R>* slots, int nslots, R
 }
 template <typename R> hipError_t launch_pvin(const Slot<R>* slots, int nslots, RedGeom g, hipStream_t s) {
     GS_LAUNCH(k_pvin<R>, dim3(g.nblk_pw, nslots), dim3(PT), 0, s, slots);
+    return hipGetLastError();
+}
+hipError_t launch_spec_pad(const cpx<double>* in, cpx<double>* out, int dim, const int nc[3], const int nf[3],
+                           hipStream_t s) {
+    const long long Mf = (long long)nf[0] * nf[1] * nf[2], Mc = (long long)nc[0] * nc[1] * nc[2];
+    GS_LAUNCH(k_spec_pad, dim3(pw_blocks(Mf)), dim3(PT), 0, s, in, out, dim, nc[0], nc[1], nc[2], nf[0], nf[1],
+              nf[2], (double)Mf / (double)Mc);
     return hipGetLastError();
 }
 hipError_t launch_gaussian(cpx<double>* out, const Phys& p, hipStream_t s) {

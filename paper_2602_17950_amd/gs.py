@@ -23,7 +23,8 @@ GS_FP64, GS_FP32, GS_MIXED = 0, 1, 2
 EXPORTS = ("gs_create", "gs_destroy", "gs_default_options", "gs_footprint_bytes", "gs_solve",
            "gs_solve_device", "gs_fft", "gs_hamiltonian", "gs_precondition", "gs_kernel_timer_start",
            "gs_kernel_timer_read", "gs_last_error", "gs_set_hbm_budget", "gs_memory_stats",
-           "gs_batch_solve", "gs_submit", "gs_progress", "gs_poll", "gs_wait", "gs_cancel")
+           "gs_batch_solve", "gs_submit", "gs_progress", "gs_poll", "gs_wait", "gs_cancel",
+           "gs_interpolate")
 
 KERNEL_KINDS = {"hl_fwd": 0, "hl_mid": 1, "hl_inv": 2, "pre_fwd": 3, "pre_mid": 4, "pre_inv": 5,
                 "eval": 6, "resid": 7, "lsred": 9, "hl_fwd2": 10, "hl_inv2": 11, "ctrl": 12}
@@ -52,7 +53,7 @@ class gs_options(C.Structure):
     _fields_ = [("stop_kind", C.c_int), ("tol", C.c_double), ("max_iter", C.c_int),
                 ("precision", C.c_int), ("switch_resid", C.c_double), ("fp32_max_iter", C.c_int),
                 ("stall_window", C.c_int), ("theta_trial", C.c_double), ("sigma", C.c_double),
-                ("max_backtrack", C.c_int), ("check_every", C.c_int)]
+                ("max_backtrack", C.c_int), ("check_every", C.c_int), ("cm_levels", C.c_int)]
 
 
 class gs_result(C.Structure):
@@ -61,7 +62,8 @@ class gs_result(C.Structure):
                 ("e_rot", C.c_double), ("e_spin", C.c_double), ("e_soc", C.c_double),
                 ("virial", C.c_double), ("resid_inf", C.c_double), ("dE_last", C.c_double),
                 ("iters", C.c_int), ("iters_fp32", C.c_int), ("backtracks", C.c_int),
-                ("resets", C.c_int), ("status", C.c_int), ("wall_s", C.c_double)]
+                ("resets", C.c_int), ("status", C.c_int), ("wall_s", C.c_double),
+                ("iters_coarse", C.c_int)]
 
     def to_dict(self):
         d = {}
@@ -117,6 +119,7 @@ def load():
     lib.gs_poll.argtypes = [vp, C.c_uint64, C.POINTER(gs_result)]
     lib.gs_wait.argtypes = [vp, C.c_uint64, C.POINTER(gs_result)]
     lib.gs_cancel.argtypes = [vp, C.c_uint64]
+    lib.gs_interpolate.argtypes = [vp, C.POINTER(gs_grid), vp, C.POINTER(gs_grid), vp, vp]
     _lib = lib
     return lib
 
@@ -339,6 +342,12 @@ class Context:
     def fft(self, grid: gs_grid, x, out, sign: int, precision=GS_FP64, stream=None):
         _check(load().gs_fft(self._h, C.byref(grid), int(precision), int(sign),
                              C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out
+
+    def interpolate(self, grid_c: gs_grid, x, grid_f: gs_grid, out, stream=None):
+        """Fourier interpolation of complex128 device field x on grid_c to grid_f."""
+        _check(load().gs_interpolate(self._h, C.byref(grid_c), C.c_void_p(x.data_ptr()), C.byref(grid_f),
+                                     C.c_void_p(out.data_ptr()), _stream_ptr(stream)))
         return out
 
     def hamiltonian(self, pb, psi, out, precision=GS_FP64, stream=None, V=None):

@@ -190,3 +190,93 @@ def test_batch_invalid_request_runs_nothing(gpu_ctx):
     assert ei.value.code == gs.GS_EINVAL
     assert "request 1" in str(ei.value)
     assert gpu_ctx.progress() == 0
+
+
+# ---------------------------------------------------------------------------
+# cascadic multigrid (Algorithm 3)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dim,nc,nf,L", [
+    (2, (16, 32), (64, 32), (5.0, 7.0)),
+    (2, (32, 32), (64, 64), (8.0, 8.0)),
+    (3, (16, 16, 16), (32, 16, 32), (5.0, 5.0, 6.0)),
+])
+def test_interpolate_matches_oracle(gpu_ctx, dim, nc, nf, L):
+    from helpers import smooth_field
+    pc = inputs.Problem(dim=dim, n=nc, L=L)
+    x = smooth_field(pc, seed=5, noise=0.3)
+    gc, gf = O.Grid(dim, nc, L), O.Grid(dim, nf, L)
+    ref = O.interp(gc, x, gf)
+    out = torch.empty((3,) + tuple(reversed(nf)), dtype=torch.complex128, device=DEV)
+    gpu_ctx.interpolate(gs.make_grid(dim, nc, L), dev(x), gs.make_grid(dim, nf, L), out)
+    got = out.cpu().numpy()
+    assert rel(got, ref) < 1e-13
+
+
+def _cm_problem(dim):
+    if dim == 2:
+        pb = inputs.Problem(dim=2, n=(64, 64), L=(8.0, 8.0), omega=0.4, gamma=0.7, c0=120.0, c1=-1.0)
+        pc = inputs.Problem(dim=2, n=(32, 32), L=(8.0, 8.0), omega=0.4, gamma=0.7, c0=120.0, c1=-1.0)
+    else:
+        pb = inputs.Problem(dim=3, n=(32, 32, 32), L=(6.0, 6.0, 6.0), g=(1.0, 1.0, 2.0), omega=0.5,
+                            gamma=1.0, c0=200.0, c1=5.0)
+        pc = inputs.Problem(dim=3, n=(16, 16, 16), L=(6.0, 6.0, 6.0), g=(1.0, 1.0, 2.0), omega=0.5,
+                            gamma=1.0, c0=200.0, c1=5.0)
+    return pb, pc, inputs.initial_guess(pc, ("a", "a", "a"))
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_cm_solve_matches_oracle(gpu_ctx, dim):
+    """Two-level cascadic multigrid: the coarse level from the Gaussian guess,
+    the fine level from its interpolant; energies, chemical potential and the
+    coarse-level iteration count against the oracle's Algorithm 3."""
+    print(f"[cm] dim={dim}", flush=True)
+    pb, pc, psi0 = _cm_problem(dim)
+    tol = 1e-10
+    g_f, t, p = orc(pb)
+    g_c, _, _ = orc(pc)
+    rs = O.cmpcg([g_c, g_f], lambda gg: t, p, psi0, O.Options(stop_kind=gs.GS_STOP_RESIDUAL, tol=tol))
+    ev = O.evaluate(g_f, t, p, rs[-1].psi)
+    opt = gs.default_options(stop_kind=gs.GS_STOP_RESIDUAL, tol=tol, cm_levels=2)
+    out = torch.empty((3,) + pb.shape, dtype=torch.complex128, device=DEV)
+    r = gpu_ctx.solve_device(pb, dev(psi0), out, options=opt)
+    print(f"[cm] gpu E={r['E']!r} it={r['iters']}+{r['iters_coarse']} | oracle E={ev['E']!r} "
+          f"it={rs[1].iters}+{rs[0].iters}", flush=True)
+    assert r["rc"] == gs.GS_OK and rs[-1].status == 0
+    assert rel(r["E"], ev["E"]) < 1e-10
+    assert rel(r["mu"], ev["mu"]) < 1e-8
+    assert r["iters_coarse"] > 0 and r["iters"] > 0
+    assert abs(sum(r["norm_comp"]) - 1.0) < 1e-13
+
+
+def test_cm_mixed_batch_equals_alone(gpu_ctx):
+    """Cascadic multigrid with mixed precision (each level float then double),
+    batched with plain solves: bitwise the same as alone."""
+    pb, pc, psi0 = _cm_problem(2)
+    opt_cm = gs.default_options(precision=gs.GS_MIXED, tol=1e-11, switch_resid=1e-4, cm_levels=2)
+    ref, rref = alone(gpu_ctx, pb, psi0, opt_cm)
+    others = problems()[:3]
+    opt = gs.default_options(precision=gs.GS_MIXED, tol=1e-11, switch_resid=1e-4)
+    out = torch.empty((3,) + pb.shape, dtype=torch.complex128, device=DEV)
+    reqs = [(pb, dev(psi0), out, opt_cm, None)]
+    outs = []
+    for q, g0 in others:
+        o = torch.empty((3,) + q.shape, dtype=torch.complex128, device=DEV)
+        outs.append(o)
+        reqs.append((q, dev(g0), o, opt, None))
+    res = gpu_ctx.batch_solve(reqs)
+    torch.cuda.synchronize()
+    assert res[0]["rc"] >= 0 and rref["rc"] >= 0
+    assert same_bits(out, ref)
+    assert res[0]["E"] == rref["E"] and res[0]["iters_coarse"] == rref["iters_coarse"] > 0
+
+
+def test_cm_rejects_bad_levels(gpu_ctx):
+    pb, pc, psi0 = _cm_problem(2)
+    out = torch.empty((3,) + pb.shape, dtype=torch.complex128, device=DEV)
+    with pytest.raises(gs.GsError) as ei:
+        gpu_ctx.solve_device(pb, None, out, options=gs.default_options(cm_levels=4))   # 64/8 < 16
+    assert ei.value.code == gs.GS_EINVAL
+    V = np.zeros(pb.shape)
+    with pytest.raises(gs.GsError) as ei:
+        gpu_ctx.solve_device(pb, None, out, options=gs.default_options(cm_levels=2), V=V)
+    assert ei.value.code == gs.GS_EINVAL
