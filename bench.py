@@ -2,16 +2,21 @@
 """Benchmark: ground-state solves per second of the rotating SOC spin-1 PCG
 solver on one MI355X, mixed FP32->FP64 against plain FP64.
 
-A step is one complete ground-state solve (Algorithm 1 with the line search of
-Algorithm 2, to the energy criterion at the paper's default tolerance 1e-14) of
-the 2D workload
-256x256 on [-12,12]^2, harmonic trap, Omega = 0.6, SOC strength 1.0,
+Headline (`value`): a step is one batch of B independent solves of the 2D
+workload 256x256 on [-12,12]^2, harmonic trap, Omega = 0.6, SOC strength 1.0,
 c0 = 500, c1 = -2, initial guess ((x+iy) phi_a, phi_a, phi_a) + 1e-3 complex
-noise (seed 2602). The initial guess is resident in device memory before the
-timed region. A mixed solve counts only when its energy agrees with the
-plain-FP64 solve of the same input to |dE| / max(|E|, 1) < 1e-10.
+noise, seeds 2602 ... 2602+B-1, each to the energy criterion at the paper's
+default tolerance 1e-14 (Algorithm 1 with the line search of Algorithm 2). The
+guesses are resident in device memory before the timed region; the solves of
+a batch share every kernel launch (continuous batching). A mixed solve counts
+only when its energy agrees with the plain-FP64 solve of the same seed to
+|dE| / max(|E|, 1) < 1e-10.
 
-Prints one JSON line (see the keys below); progress goes to stderr.
+Further sections of the same JSON line: the same workload one solve at a time
+(latency), the 3D 128^3 cascadic-multigrid solve, the 96-solve parameter sweep
+of mixed grid sizes, and a served stream with Poisson arrivals.
+
+Prints one JSON line; progress goes to stderr.
 """
 from __future__ import annotations
 
@@ -31,8 +36,11 @@ METRIC = "ground-state solves/s at |dE|<1e-10 (mixed vs FP64 PCG); p50/p99 solve
 HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, vendor figure
 DE_GATE = 1e-10
 TOL = 1e-14               # energy criterion (3.11), the paper's default tolerance (Sec. 4)
-KERNEL_SOURCES = ("paper_2602_17950_amd/csrc/fft_kernels.hip", "paper_2602_17950_amd/csrc/gs_internal.h")
-TRAFFIC_SUMMARY = "profiles/hbm_traffic_solve256_vortex.md"
+KERNEL_SOURCES = ("paper_2602_17950_amd/csrc/fft_kernels.hip", "paper_2602_17950_amd/csrc/pw_kernels.hip",
+                  "paper_2602_17950_amd/csrc/device_common.h", "paper_2602_17950_amd/csrc/control.h",
+                  "paper_2602_17950_amd/csrc/gs_internal.h")
+TRAFFIC_SUMMARY = "profiles/hbm_traffic_batch256_vortex.md"
+SECTIONS = ("batch", "single", "cm3d", "sweep", "serve")
 
 
 def kernel_source_hash():
@@ -69,10 +77,14 @@ def percentile(xs, q):
     return xs[k]
 
 
+def rel(a, b):
+    return abs(a - b) / max(abs(b), 1.0)
+
+
 def cpu_baseline(pb, psi0, iters_per_solve, seconds):
     """The FP64 CPU oracle on the same input, timed on the host cores for a
-    bounded number of PCG iterations and scaled to solves/s by the iteration
-    count of the FP64 solve."""
+    bounded number of PCG iterations and scaled to solves/s by the mean
+    iteration count of the GPU's FP64 solves of the workload."""
     import oracle as O
     threads = max(1, min(16, os.cpu_count() or 1))
     O.set_threads(threads)
@@ -94,29 +106,50 @@ def cpu_baseline(pb, psi0, iters_per_solve, seconds):
         "unit": "solves/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": (f"first {done} PCG iterations of the same 256^2 solve on the host "
-                   f"({dt:.1f} s, {per_iter * 1e3:.1f} ms/iteration), scaled by the "
-                   f"{iters_per_solve} iterations of the FP64 solve"),
+        "sample": (f"first {done} PCG iterations of the seed-2602 256^2 solve on the host "
+                   f"({dt:.1f} s, {per_iter * 1e3:.1f} ms/iteration), scaled by the mean "
+                   f"{iters_per_solve:.0f} iterations of the GPU's FP64 solves of the workload"),
     }
+
+
+class Batch:
+    """Device-resident guesses and outputs for a list of (Problem, guess)."""
+
+    def __init__(self, torch, probs):
+        self.probs = [pb for pb, _ in probs]
+        self.guess = [None if g is None else torch.from_numpy(g).to("cuda") for _, g in probs]
+        self.out = [torch.empty((3,) + pb.shape, dtype=torch.complex128, device="cuda") for pb in self.probs]
+
+    def requests(self, opt):
+        return [(pb, g, o, opt, None) for pb, g, o in zip(self.probs, self.guess, self.out)]
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=256, help="grid points per axis")
-    ap.add_argument("--kernel", default="hl_inv", help="kernel kind timed for the roofline")
+    ap.add_argument("--batch", type=int, default=32, help="solves per headline step")
+    ap.add_argument("--n", type=int, default=256, help="grid points per axis of the headline workload")
+    ap.add_argument("--kernel", default="hl_mid", help="kernel kind timed for the roofline")
+    ap.add_argument("--sections", default=",".join(SECTIONS))
+    ap.add_argument("--serve-requests", type=int, default=32)
+    ap.add_argument("--serve-load", type=float, default=0.5, help="arrival rate / measured sweep capacity")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 1 GiB device to device (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: every solve of this workload fits one MI355X "
+        print("bench.py runs on one GPU only: every solve of these workloads fits one MI355X "
               "(use --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    sections = [s for s in args.sections.split(",") if s]
+    for s in sections:
+        if s not in SECTIONS:
+            sys.exit(f"unknown section {s!r}; choose from {SECTIONS}")
 
+    import numpy as np
     import torch
     from paper_2602_17950_amd import gs, inputs
 
@@ -129,107 +162,207 @@ def main():
         log("copied 1 GiB")
         return
 
-    pb, psi0 = inputs.workload_vortex_2d(n=args.n)
     ctx = gs.Context(0)
-    stream = torch.cuda.Stream()
-    d_psi0 = torch.from_numpy(psi0).to("cuda")
-    out = torch.empty_like(d_psi0)
-    o64 = gs.default_options(precision=gs.GS_FP64, stop_kind=gs.GS_STOP_ENERGY, tol=TOL)
-    omx = gs.default_options(precision=gs.GS_MIXED, stop_kind=gs.GS_STOP_ENERGY, tol=TOL)
+    o64 = gs.default_options(precision=gs.GS_FP64, tol=TOL)
+    omx = gs.default_options(precision=gs.GS_MIXED, tol=TOL)
+    line = {"metric": METRIC, "value": None, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "fp32->fp64", "data": "synthetic"}
 
-    def run(opts):
-        return ctx.solve_device(pb, d_psi0, out, opts, stream=stream.cuda_stream)
+    # ------------------------------------------------------------------ headline
+    seeds = [2602 + i for i in range(args.batch)]
+    work = [inputs.workload_vortex_2d(n=args.n, seed=s) for s in seeds]
+    head = Batch(torch, work)
+    res64 = None
+    if "batch" in sections:
+        for w in range(args.warmup):
+            t = time.perf_counter()
+            ctx.batch_solve(head.requests(omx))
+            log(f"warmup {w}: mixed batch of {args.batch} {time.perf_counter() - t:.3f}s")
+        # plain FP64 batch: reference energies and the roofline kernel's timing
+        ctx.kernel_timer_start(args.kernel)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res64 = ctx.batch_solve(head.requests(o64))
+        torch.cuda.synchronize()
+        T64 = time.perf_counter() - t0
+        kt = ctx.kernel_timer_read()
+        ctx.kernel_timer_start(None)
+        E64 = [r["E"] for r in res64]
+        log(f"fp64 batch: {T64:.3f}s iters mean {np.mean([r['iters'] for r in res64]):.0f} "
+            f"max {max(r['iters'] for r in res64)}")
+        # timed region: K mixed batches
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        resmx = []
+        for k in range(args.steps):
+            resmx.append(ctx.batch_solve(head.requests(omx)))
+        torch.cuda.synchronize()
+        Tmx = time.perf_counter() - t0
+        dEs = [rel(r["E"], e) for rs in resmx for r, e in zip(rs, E64)]
+        counted = sum(1 for d in dEs if d < DE_GATE)
+        lat = [r["wall_s"] for rs in resmx for r in rs]
+        itmx = [r["iters"] for rs in resmx for r in rs]
+        log(f"mixed batches: {Tmx:.3f}s for {args.steps} x {args.batch}; counted {counted}; "
+            f"iters mean {np.mean(itmx):.0f} max {max(itmx)}")
+        line["value"] = counted / Tmx
+        line["ms_per_step"] = Tmx / args.steps * 1e3
+        line["p50_ms"] = percentile(lat, 50) * 1e3
+        line["p99_ms"] = percentile(lat, 99) * 1e3
+        line["iters_per_s"] = sum(itmx) / Tmx
+        line["batch"] = {
+            "solves_per_step": args.batch, "counted": counted, "solves": len(dEs),
+            "dE_rel_max": max(dEs), "dE_rel_median": float(np.median(dEs)),
+            "mixed_iters_mean": float(np.mean(itmx)), "mixed_iters_fp32_mean":
+                float(np.mean([r["iters_fp32"] for rs in resmx for r in rs])),
+            "fp64_solves_per_s": args.batch / T64, "fp64_iters_mean": float(np.mean([r["iters"] for r in res64])),
+            "fp64_p50_ms": percentile([r["wall_s"] for r in res64], 50) * 1e3,
+            "fp64_p99_ms": percentile([r["wall_s"] for r in res64], 99) * 1e3,
+            "speedup_mixed_vs_fp64": (len(dEs) / Tmx) / (args.batch / T64),
+            "latency_note": "p50/p99: submission to completion of each solve inside its batch",
+        }
+        roof = None
+        if kt["launches"] > 0 and kt["ms"] > 0:
+            avg_s = kt["ms"] * 1e-3 / kt["launches"]
+            bpl = kt["bytes"] / kt["launches"]
+            achieved = bpl / avg_s / 1e9
+            roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.kernel),
+                    "kernel": args.kernel, "launches": kt["launches"], "avg_us": avg_s * 1e6,
+                    "bytes_per_launch": bpl, "timed_in": f"FP64 batch of {args.batch} solves"}
+        line["roofline"] = roof
 
-    for w in range(args.warmup):
-        r = run(o64)
-        log(f"warmup {w}: fp64 E={r['E']:.15f} iters={r['iters']} {r['wall_s']:.3f}s")
-        r = run(omx)
-        log(f"warmup {w}: mixed E={r['E']:.15f} iters={r['iters']} ({r['iters_fp32']} fp32) {r['wall_s']:.3f}s")
+    # ------------------------------------------------------------ single solve
+    if "single" in sections:
+        pb, g0 = work[0]
+        one = Batch(torch, [(pb, g0)])
+        single = {}
+        for name, opt in (("fp64", o64), ("mixed", omx)):
+            ctx.solve_device(pb, one.guess[0], one.out[0], opt)   # warm
+            lat, r = [], None
+            for k in range(args.steps):
+                t = time.perf_counter()
+                r = ctx.solve_device(pb, one.guess[0], one.out[0], opt)
+                lat.append(time.perf_counter() - t)
+            single[name] = {"solves_per_s": len(lat) / sum(lat), "p50_ms": percentile(lat, 50) * 1e3,
+                            "p99_ms": percentile(lat, 99) * 1e3, "iters": r["iters"],
+                            "iters_fp32": r["iters_fp32"], "E": r["E"]}
+            log(f"single {name}: {single[name]['p50_ms']:.1f} ms, iters {r['iters']}")
+        single["dE_rel"] = rel(single["mixed"]["E"], single["fp64"]["E"])
+        single["speedup_mixed_vs_fp64"] = single["mixed"]["solves_per_s"] / single["fp64"]["solves_per_s"]
+        line["single"] = single
+        if line["value"] is None:   # headline section skipped
+            line["value"] = single["mixed"]["solves_per_s"] if single["dE_rel"] < DE_GATE else 0.0
+            line["ms_per_step"] = single["mixed"]["p50_ms"]
 
-    # plain FP64 PCG: the reference energy and the speedup denominator; the
-    # roofline kernel is timed here (HIP events on the solve's stream), where
-    # every launch is the double-precision variant
-    ctx.kernel_timer_start(args.kernel)
-    torch.cuda.synchronize()
-    lat64, res64 = [], None
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        t = time.perf_counter()
-        res64 = run(o64)
-        lat64.append(time.perf_counter() - t)
-        log(f"fp64 {k}: E={res64['E']:.15f} iters={res64['iters']} {lat64[-1]:.3f}s")
-    torch.cuda.synchronize()
-    T64 = time.perf_counter() - t0
-    E64 = res64["E"]
-    kt = ctx.kernel_timer_read()
-    ctx.kernel_timer_start(None)
+    # ------------------------------------------------------- 3D multigrid solve
+    if "cm3d" in sections:
+        pb3, _ = inputs.workload_aniso_3d(n=128)
+        pc = inputs.Problem(dim=3, n=(32, 32, 32), L=pb3.L, g=pb3.g, omega=pb3.omega, gamma=pb3.gamma,
+                            c0=pb3.c0, c1=pb3.c1)
+        g3 = torch.from_numpy(inputs.initial_guess(pc, ("a", "a", "a"))).to("cuda")
+        out3 = torch.empty((3,) + pb3.shape, dtype=torch.complex128, device="cuda")
+        cm = {}
+        for name, prec in (("fp64", gs.GS_FP64), ("mixed", gs.GS_MIXED)):
+            opt = gs.default_options(precision=prec, tol=1e-12, cm_levels=3)
+            t = time.perf_counter()
+            r = ctx.solve_device(pb3, g3, out3, opt)
+            cm[name] = {"s": time.perf_counter() - t, "E": r["E"], "mu": r["mu"], "iters_fine": r["iters"],
+                        "iters_coarse": r["iters_coarse"], "iters_fp32": r["iters_fp32"],
+                        "resid_inf": r["resid_inf"], "virial": r["virial"], "status": r["rc"]}
+            log(f"cm3d {name}: {cm[name]['s']:.2f}s E={r['E']:.15f} iters {r['iters']}+{r['iters_coarse']}")
+        cm["dE_rel"] = rel(cm["mixed"]["E"], cm["fp64"]["E"])
+        cm["workload"] = ("3D 128^3 on [-8,8]^3, V=(x^2+y^2+4z^2)/2, Omega=0.5, SOC 1.0, c0=800, c1=5; "
+                          "cascadic multigrid 32^3->64^3->128^3 from (a,a,a); energy criterion 1e-12 per level")
+        line["cm3d"] = cm
+        del g3, out3
 
-    # mixed FP32 -> FP64: the timed region of the metric
-    torch.cuda.synchronize()
-    latmx, resmx = [], []
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        t = time.perf_counter()
-        resmx.append(run(omx))
-        latmx.append(time.perf_counter() - t)
-    torch.cuda.synchronize()
-    Tmx = time.perf_counter() - t0
-    for k, r in enumerate(resmx):
-        log(f"mixed {k}: E={r['E']:.15f} iters={r['iters']} ({r['iters_fp32']} fp32) {latmx[k]:.3f}s")
+    # ------------------------------------------------------------------- sweep
+    cap = None
+    if "sweep" in sections:
+        spec = inputs.workload_sweep_2d()
+        sw = Batch(torch, [(pb, inputs.initial_guess(pb, k)) for pb, k in spec])
+        out = {}
+        E = {}
+        for name, prec in (("fp64", gs.GS_FP64), ("mixed", gs.GS_MIXED)):
+            opt = gs.default_options(precision=prec, tol=1e-12)
+            t = time.perf_counter()
+            rs = ctx.batch_solve(sw.requests(opt))
+            dt = time.perf_counter() - t
+            E[name] = [r["E"] for r in rs]
+            out[name] = {"s": dt, "solves_per_s": len(rs) / dt, "iters_mean": float(np.mean([r["iters"] for r in rs])),
+                         "p50_ms": percentile([r["wall_s"] for r in rs], 50) * 1e3,
+                         "p99_ms": percentile([r["wall_s"] for r in rs], 99) * 1e3,
+                         "warnings": sum(1 for r in rs if r["rc"] > 0), "errors": sum(1 for r in rs if r["rc"] < 0)}
+            log(f"sweep {name}: {dt:.2f}s ({out[name]['solves_per_s']:.2f} solves/s)")
+        d = [rel(a, b) for a, b in zip(E["mixed"], E["fp64"])]
+        out["counted"] = sum(1 for x in d if x < DE_GATE)
+        out["counted_solves_per_s"] = out["counted"] / out["mixed"]["s"]
+        out["workload"] = ("96 2D solves, n uniform over {128,256,512}, L=16, Omega~U[0,0.9], SOC~U[0,2], "
+                           "c0~U[100,2000], c1~U[-5,5], guesses over {(a,a,a),(b,a,a),(f,f,f)}, seed 17950; "
+                           "energy criterion 1e-12, one batch")
+        out["note"] = ("solves whose mixed and FP64 runs end in different local minima are not counted "
+                       "(the landscape of the rotating problems has many)")
+        line["sweep"] = out
+        cap = out["mixed"]["solves_per_s"]
+        del sw
 
-    dEs = [abs(r["E"] - E64) / max(abs(E64), 1.0) for r in resmx]
-    counted = sum(1 for d in dEs if d < DE_GATE)
-    value = counted / Tmx
-    iters_mx = sum(r["iters"] for r in resmx)
-
-    roof = None
-    if kt["launches"] > 0 and kt["ms"] > 0:
-        avg_s = kt["ms"] * 1e-3 / kt["launches"]
-        bpl = kt["bytes"] / kt["launches"]
-        achieved = bpl / avg_s / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.kernel), "kernel": args.kernel,
-                "launches": kt["launches"], "avg_us": avg_s * 1e6, "bytes_per_launch": bpl,
-                "timed_in": "plain FP64 solves"}
+    # ------------------------------------------------------------------- serve
+    if "serve" in sections:
+        rate = args.serve_load * (cap if cap else 1.0)
+        spec = inputs.workload_serve(args.serve_requests)
+        sv = Batch(torch, [(pb, inputs.initial_guess(pb, k)) for pb, k in spec])
+        rng = np.random.default_rng(2603)
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(spec)))
+        opt = gs.default_options(precision=gs.GS_MIXED, tol=1e-12)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pending, tickets, done = 0, {}, {}
+        while len(done) < len(spec):
+            now = time.perf_counter() - t0
+            while pending < len(spec) and arrivals[pending] <= now:
+                i = pending
+                tickets[i] = ctx.submit(sv.probs[i], sv.guess[i], sv.out[i], opt)
+                pending += 1
+            for i in list(tickets):
+                r = ctx.poll(tickets[i])
+                if r is not None:
+                    done[i] = r
+                    del tickets[i]
+            if len(done) < len(spec):
+                if tickets:
+                    ctx.progress(block=pending >= len(spec) or arrivals[pending] > time.perf_counter() - t0 + 0.005)
+                else:
+                    time.sleep(max(0.0, min(0.01, arrivals[pending] - (time.perf_counter() - t0))))
+        T = time.perf_counter() - t0
+        lat = [done[i]["wall_s"] for i in range(len(spec))]
+        line["serve"] = {
+            "requests": len(spec), "arrival_rate_per_s": rate, "load_vs_sweep_capacity": args.serve_load,
+            "s": T, "solves_per_s": len(spec) / T, "p50_ms": percentile(lat, 50) * 1e3,
+            "p99_ms": percentile(lat, 99) * 1e3,
+            "warnings": sum(1 for r in done.values() if r["rc"] > 0),
+            "errors": sum(1 for r in done.values() if r["rc"] < 0),
+            "workload": ("Poisson arrivals (seed 2603); 75% 2D n in {128,256,512,1024} L=16, 25% 3D n in {64,128} "
+                         "L=10; parameters as the sweep; trap harmonic or 0.5r^2+0.01r^4; mixed precision, "
+                         "energy criterion 1e-12; latency = arrival to completion"),
+        }
+        log(f"serve: {T:.2f}s, p50 {line['serve']['p50_ms']:.0f} ms p99 {line['serve']['p99_ms']:.0f} ms")
+        del sv
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and res64 is not None:
         log("cpu baseline: timing the oracle ...")
-        cpu = cpu_baseline(pb, psi0, res64["iters"], args.cpu_seconds)
+        cpu = cpu_baseline(work[0][0], work[0][1], float(np.mean([r["iters"] for r in res64])), args.cpu_seconds)
         log(f"cpu baseline: {cpu['value']:.4g} solves/s ({cpu['sample']})")
-
-    line = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "solves/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": Tmx / args.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "fp32->fp64",
-        "data": "synthetic",
-        "config": {
-            "workload": (f"2D {args.n}x{args.n} on [-12,12]^2, harmonic trap, Omega=0.6, SOC 1.0, "
-                         "c0=500, c1=-2, guess ((x+iy)phi_a, phi_a, phi_a)+1e-3 noise (seed 2602), "
-                         "energy criterion 1e-14; mixed FP32->FP64 PCG vs plain FP64 PCG"),
-            "parallelism": "single GPU, one solve at a time",
-        },
-        "p50_ms": percentile(latmx, 50) * 1e3,
-        "p99_ms": percentile(latmx, 99) * 1e3,
-        "iters_per_s": iters_mx / Tmx,
-        "mixed": {"iters": resmx[-1]["iters"], "iters_fp32": resmx[-1]["iters_fp32"],
-                  "E": resmx[-1]["E"], "dE_rel_max": max(dEs), "counted": counted},
-        "fp64": {"solves_per_s": args.steps / T64, "ms_per_solve": T64 / args.steps * 1e3,
-                 "iters": res64["iters"], "E": E64,
-                 "p50_ms": percentile(lat64, 50) * 1e3, "p99_ms": percentile(lat64, 99) * 1e3},
-        "speedup_mixed_vs_fp64": (args.steps / Tmx) / (args.steps / T64),
-        "roofline": roof,
-        "kernel_source_sha256_16": kernel_source_hash(),
-        "cpu_baseline": cpu,
+    line["cpu_baseline"] = cpu
+    line["config"] = {
+        "workload": (f"2D {args.n}x{args.n} on [-12,12]^2, harmonic trap, Omega=0.6, SOC 1.0, c0=500, c1=-2, "
+                     "guess ((x+iy)phi_a, phi_a, phi_a)+1e-3 noise; a step = one batch of "
+                     f"{args.batch} solves (noise seeds 2602..{2601 + args.batch}), energy criterion 1e-14; "
+                     "mixed FP32->FP64 PCG, counted against plain FP64 PCG of the same seed"),
+        "parallelism": "single GPU; the solves of a batch share every kernel launch",
     }
+    line["kernel_source_sha256_16"] = kernel_source_hash()
     print(json.dumps(line), flush=True)
     ctx.close()
 

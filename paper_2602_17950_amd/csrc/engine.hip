@@ -156,9 +156,9 @@ static int alloc_slot_mem(const gs_grid* g, hipStream_t s, std::unique_ptr<SlotM
 // Every launch of one kernel kind of the iteration records its own start and
 // end (dispatch timestamps, hipExtLaunchKernelGGL) into HIP events on the
 // class's stream; elapsed times and the kernel's algorithmic bytes (each
-// distinct array read or written once, times the slots of the launch) are
-// summed. Launches that return at once because every solve of the launch has
-// finished (the tail of the last chunk) are left out.
+// distinct array read or written once, times the slots that were still
+// running at that iteration) are summed. Launches in which every slot had
+// already finished (the tail of the last chunk) are left out.
 enum KKind : int {
     KK_HL_FWD = 0, KK_HL_MID = 1, KK_HL_INV = 2, KK_PRE_FWD = 3, KK_PRE_MID = 4, KK_PRE_INV = 5,
     KK_EVAL = 6, KK_RESID = 7, KK_DIRRED = 8, KK_LSRED = 9, KK_HL_FWD2 = 10, KK_HL_INV2 = 11,
@@ -171,7 +171,7 @@ struct TimerTotals {
 };
 struct Timer {
     int kind = -1;
-    struct Rec { int k, chain; double bytes; };
+    struct Rec { int k, chain; double bytes_per_slot; };
     std::vector<hipEvent_t> ev;
     std::vector<Rec> rec;
     int iter_in_chunk = 0;
@@ -181,8 +181,9 @@ struct Timer {
     }
 };
 
+// `bytes`: algorithmic bytes of the launch for all its slots; `ns` slots.
 template <typename F>
-static hipError_t timed(Timer* tm, int kind, double bytes, hipStream_t s, F&& f) {
+static hipError_t timed_ns(Timer* tm, int kind, double bytes, int ns, hipStream_t s, F&& f) {
     if (!tm || tm->kind != kind) return f();
     const size_t i = tm->rec.size();
     while (tm->ev.size() < 2 * (i + 1)) {
@@ -199,23 +200,28 @@ static hipError_t timed(Timer* tm, int kind, double bytes, hipStream_t s, F&& f)
     const bool consumed = le.start == nullptr;
     le.start = le.stop = nullptr;
     if (e == hipSuccess && !consumed) e = hipErrorInvalidValue;
-    tm->rec.push_back({tm->iter_in_chunk, tm->chain, bytes});
+    tm->rec.push_back({tm->iter_in_chunk, tm->chain, bytes / (ns > 0 ? ns : 1)});
     return e;
 }
 
-// After a chunk has completed: iterations below n_full ran for some slot; when
-// every slot finished in the chunk, the refresh (chain 0), the residual pass
-// (chain 1) and the preconditioner with its control step (chain 2) of
-// iteration n_full also ran.
-static hipError_t timer_collect(Timer& tm, TimerTotals& tot, int n_full, bool done) {
+// After a chunk has completed, with adv[i] the steps slot i accepted in it and
+// fin[i] whether it finished: iteration k ran in full for the slots with
+// adv > k; for a slot that finished at iteration adv, the refresh (chain 0),
+// the residual pass (chain 1) and the preconditioner with its control step
+// (chain 2) of that iteration also ran.
+static hipError_t timer_collect(Timer& tm, TimerTotals& tot, const std::vector<int>& adv,
+                                const std::vector<char>& fin) {
     for (size_t i = 0; i < tm.rec.size(); ++i) {
         const Timer::Rec& r = tm.rec[i];
-        if (!(r.k < n_full || (done && r.k == n_full && r.chain <= 2))) continue;
+        int active = 0;
+        for (size_t q = 0; q < adv.size(); ++q)
+            active += adv[q] > r.k || (fin[q] && adv[q] == r.k && r.chain <= 2);
+        if (!active) continue;
         float ms = 0.0f;
         hipError_t e = hipEventElapsedTime(&ms, tm.ev[2 * i], tm.ev[2 * i + 1]);
         if (e != hipSuccess) return e;
         tot.ms += ms;
-        tot.bytes += r.bytes;
+        tot.bytes += r.bytes_per_slot * active;
         tot.launches++;
     }
     tm.rec.clear();
@@ -342,19 +348,19 @@ static hipError_t chain_HL(const Geo<R>& G, Sub<R> L, int pro, int dual, int in,
     const int outB = rot ? B_T1 : B_NONE;
     hipError_t e;
     if (G.dim == 2) {
-        if ((e = timed(tm, KK_HL_FWD, b_fwd, s, [&] { return launch_fwdT<R>(Nx, pro, dual, L.tab, L.ns, in, B_T6A, aux0, aux1, 1, Ny, 3, G.tw[0], s); }))) return e;
-        if ((e = timed(tm, KK_HL_MID, b_mid, s, [&] { return launch_mid<R>(Ny, midop, L.tab, L.ns, B_T6A, B_T0, outB, Nx, rot, G.tw[1], s); }))) return e;
-        return timed(tm, KK_HL_INV, b_inv, s, [&] {
+        if ((e = timed_ns(tm, KK_HL_FWD, b_fwd, L.ns, s, [&] { return launch_fwdT<R>(Nx, pro, dual, L.tab, L.ns, in, B_T6A, aux0, aux1, 1, Ny, 3, G.tw[0], s); }))) return e;
+        if ((e = timed_ns(tm, KK_HL_MID, b_mid, L.ns, s, [&] { return launch_mid<R>(Ny, midop, L.tab, L.ns, B_T6A, B_T0, outB, Nx, rot, G.tw[1], s); }))) return e;
+        return timed_ns(tm, KK_HL_INV, b_inv, L.ns, s, [&] {
             return launch_invT<R>(Nx, EPI_HL, L.tab, L.ns, B_T0, B_T1, out, B_NONE, in, 1, Ny, 1.0, use_invnP, rot, G.tw[0], s); });
     }
     const int nc = dual ? 6 : 3;
-    if ((e = timed(tm, KK_HL_FWD, b_fwd, s, [&] { return launch_fwdT<R>(Nx, pro, dual, L.tab, L.ns, in, B_T6A, aux0, aux1, Nz, Ny, 3, G.tw[0], s); }))) return e;
-    if ((e = timed(tm, KK_HL_FWD2, 2 * (nc / 3) * F, s, [&] { return launch_fwdT<R>(Ny, PRO_PLAIN, 0, L.tab, L.ns, B_T6A, B_T6B, B_NONE, B_NONE, Nx, Nz, nc, G.tw[1], s); }))) return e;
-    if ((e = timed(tm, KK_HL_MID, b_mid, s, [&] { return launch_mid<R>(Nz, midop, L.tab, L.ns, B_T6B, B_T0, outB, Ny * Nx, rot, G.tw[2], s); }))) return e;
-    if ((e = timed(tm, KK_HL_INV2, (rot ? 5 : 2) * F, s, [&] {
+    if ((e = timed_ns(tm, KK_HL_FWD, b_fwd, L.ns, s, [&] { return launch_fwdT<R>(Nx, pro, dual, L.tab, L.ns, in, B_T6A, aux0, aux1, Nz, Ny, 3, G.tw[0], s); }))) return e;
+    if ((e = timed_ns(tm, KK_HL_FWD2, 2 * (nc / 3) * F, L.ns, s, [&] { return launch_fwdT<R>(Ny, PRO_PLAIN, 0, L.tab, L.ns, B_T6A, B_T6B, B_NONE, B_NONE, Nx, Nz, nc, G.tw[1], s); }))) return e;
+    if ((e = timed_ns(tm, KK_HL_MID, b_mid, L.ns, s, [&] { return launch_mid<R>(Nz, midop, L.tab, L.ns, B_T6B, B_T0, outB, Ny * Nx, rot, G.tw[2], s); }))) return e;
+    if ((e = timed_ns(tm, KK_HL_INV2, (rot ? 5 : 2) * F, L.ns, s, [&] {
              return launch_invT<R>(Ny, rot ? EPI_ROTX : EPI_SCALE, L.tab, L.ns, B_T0, B_T1, B_T2, rot ? B_T3 : B_NONE,
                                    B_T6A, Nx, Nz, 1.0, 0, rot, G.tw[1], s); }))) return e;
-    return timed(tm, KK_HL_INV, b_inv, s, [&] {
+    return timed_ns(tm, KK_HL_INV, b_inv, L.ns, s, [&] {
         return launch_invT<R>(Nx, EPI_HL, L.tab, L.ns, B_T2, B_T3, out, B_NONE, in, Nz, Ny, 1.0, use_invnP, rot, G.tw[0], s); });
 }
 
@@ -367,16 +373,16 @@ static hipError_t chain_pre(const Geo<R>& G, Sub<R> L, int dir, int out, hipStre
     const double b_inv = (dir ? 6 : 2) * F + Fr;
     hipError_t e;
     if (G.dim == 2) {
-        if ((e = timed(tm, KK_PRE_FWD, 2 * F, s, [&] { return launch_fwdT<R>(Nx, PRO_PLAIN, 0, L.tab, L.ns, B_U, B_T6A, B_NONE, B_NONE, 1, Ny, 3, G.tw[0], s); }))) return e;
-        if ((e = timed(tm, KK_PRE_MID, 2 * F, s, [&] { return launch_mid<R>(Ny, MID_PRE, L.tab, L.ns, B_T6A, B_T0, B_NONE, Nx, 0, G.tw[1], s); }))) return e;
-        return timed(tm, KK_PRE_INV, b_inv, s, [&] {
+        if ((e = timed_ns(tm, KK_PRE_FWD, 2 * F, L.ns, s, [&] { return launch_fwdT<R>(Nx, PRO_PLAIN, 0, L.tab, L.ns, B_U, B_T6A, B_NONE, B_NONE, 1, Ny, 3, G.tw[0], s); }))) return e;
+        if ((e = timed_ns(tm, KK_PRE_MID, 2 * F, L.ns, s, [&] { return launch_mid<R>(Ny, MID_PRE, L.tab, L.ns, B_T6A, B_T0, B_NONE, Nx, 0, G.tw[1], s); }))) return e;
+        return timed_ns(tm, KK_PRE_INV, b_inv, L.ns, s, [&] {
             return launch_invT_pre<R>(Nx, L.tab, L.ns, B_T0, out, 1, Ny, dir, G.tw[0], s); });
     }
-    if ((e = timed(tm, KK_PRE_FWD, 2 * F, s, [&] { return launch_fwdT<R>(Nx, PRO_PLAIN, 0, L.tab, L.ns, B_U, B_T6A, B_NONE, B_NONE, Nz, Ny, 3, G.tw[0], s); }))) return e;
+    if ((e = timed_ns(tm, KK_PRE_FWD, 2 * F, L.ns, s, [&] { return launch_fwdT<R>(Nx, PRO_PLAIN, 0, L.tab, L.ns, B_U, B_T6A, B_NONE, B_NONE, Nz, Ny, 3, G.tw[0], s); }))) return e;
     if ((e = launch_fwdT<R>(Ny, PRO_PLAIN, 0, L.tab, L.ns, B_T6A, B_T6B, B_NONE, B_NONE, Nx, Nz, 3, G.tw[1], s))) return e;
-    if ((e = timed(tm, KK_PRE_MID, 2 * F, s, [&] { return launch_mid<R>(Nz, MID_PRE, L.tab, L.ns, B_T6B, B_T0, B_NONE, Ny * Nx, 0, G.tw[2], s); }))) return e;
+    if ((e = timed_ns(tm, KK_PRE_MID, 2 * F, L.ns, s, [&] { return launch_mid<R>(Nz, MID_PRE, L.tab, L.ns, B_T6B, B_T0, B_NONE, Ny * Nx, 0, G.tw[2], s); }))) return e;
     if ((e = launch_invT<R>(Ny, EPI_SCALE, L.tab, L.ns, B_T0, B_NONE, B_T1, B_NONE, B_NONE, Nx, Nz, 1.0, 0, 0, G.tw[1], s))) return e;
-    return timed(tm, KK_PRE_INV, b_inv, s, [&] {
+    return timed_ns(tm, KK_PRE_INV, b_inv, L.ns, s, [&] {
         return launch_invT_pre<R>(Nx, L.tab, L.ns, B_T1, out, Nz, Ny, dir, G.tw[0], s); });
 }
 
@@ -395,7 +401,7 @@ template <typename R> static double fin_bytes(const Geo<R>& G, int what, int ns)
 }
 template <typename R>
 static hipError_t fin(const Geo<R>& G, Sub<R> L, int what, hipStream_t s, Timer* tm) {
-    return timed(tm, KK_CTRL, fin_bytes<R>(G, what, L.ns), s, [&] { return launch_fin<R>(L.tab, L.ns, G.g, what, s); });
+    return timed_ns(tm, KK_CTRL, fin_bytes<R>(G, what, L.ns), L.ns, s, [&] { return launch_fin<R>(L.tab, L.ns, G.g, what, s); });
 }
 
 template <typename R>
@@ -403,7 +409,7 @@ static hipError_t refresh(const Geo<R>& G, Sub<R> L, hipStream_t s, Timer* tm) {
     const double F = 3.0 * G.M * sizeof(cpx<R>) * L.ns;
     hipError_t e;
     if ((e = chain_HL<R>(G, L, PRO_UPDATE, 0, B_PHI, B_HL, B_P, B_NONE, 0, s, tm))) return e;
-    if ((e = timed(tm, KK_EVAL, 2 * F, s, [&] { return launch_eval<R>(L.tab, L.ns, G.g, s); }))) return e;
+    if ((e = timed_ns(tm, KK_EVAL, 2 * F, L.ns, s, [&] { return launch_eval<R>(L.tab, L.ns, G.g, s); }))) return e;
     return fin<R>(G, L, FIN_EVAL, s, tm);
 }
 
@@ -443,13 +449,13 @@ static hipError_t iterate(const Geo<R>& G, Sub<R> L, int do_refresh, hipStream_t
         if ((e = refresh<R>(G, L, s, tm))) return e;
     }
     if (tm) tm->chain = 1;
-    if ((e = timed(tm, KK_RESID, 8 * F + Fr, s, [&] { return launch_resid<R>(L.tab, L.ns, G.g, 0, s); }))) return e;
+    if ((e = timed_ns(tm, KK_RESID, 8 * F + Fr, L.ns, s, [&] { return launch_resid<R>(L.tab, L.ns, G.g, 0, s); }))) return e;
     if (tm) tm->chain = 2;
     if ((e = chain_pre<R>(G, L, 1, B_PR, s, tm))) return e;
     if ((e = fin<R>(G, L, FIN_DIR, s, tm))) return e;
     if (tm) tm->chain = 3;
     if ((e = chain_HL<R>(G, L, PRO_DIR, 1, B_P, B_HLP, B_PR, B_PHI, 1, s, tm))) return e;
-    if ((e = timed(tm, KK_LSRED, 4 * F, s, [&] { return launch_lsred<R>(L.tab, L.ns, G.g, s); }))) return e;
+    if ((e = timed_ns(tm, KK_LSRED, 4 * F, L.ns, s, [&] { return launch_lsred<R>(L.tab, L.ns, G.g, s); }))) return e;
     return fin<R>(G, L, FIN_LS, s, tm);
 }
 
@@ -889,14 +895,14 @@ static int boundary(Ctx& cx, Class<R>& c) {
     c.fin.clear();
     // 2. slots of the chunk that has completed
     if (!c.run.empty() && c.tm.kind >= 0) {
-        int n_full = 0;
-        bool all_done = true;
+        std::vector<int> adv;
+        std::vector<char> fin;
         for (size_t i = 0; i < c.run.size(); ++i) {
             const SolveState& h = c.h_st[c.run[i]];
-            n_full = std::max(n_full, h.iter - c.iter0[i]);
-            all_done = all_done && h.done;
+            adv.push_back(h.iter - c.iter0[i]);
+            fin.push_back(h.done ? 1 : 0);
         }
-        HIPCHK(timer_collect(c.tm, cx.timer, n_full, all_done));
+        HIPCHK(timer_collect(c.tm, cx.timer, adv, fin));
     }
     std::vector<int> cont;
     for (size_t i = 0; i < c.run.size(); ++i) {

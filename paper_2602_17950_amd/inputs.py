@@ -185,3 +185,35 @@ def workload_sweep_2d(count: int = 96, seed: int = 17950, sizes=(128, 256, 512))
         pb = Problem(dim=2, n=(n, n), L=(16.0, 16.0), omega=omega, gamma=gamma, c0=c0, c1=c1)
         out.append((pb, k))
     return out
+
+
+def workload_serve(count: int = 400, seed: int = 2603, sizes2d=(128, 256, 512, 1024), sizes3d=(64, 128)):
+    """Served request stream: 75% 2D (grid uniform over ``sizes2d``, L = 16),
+    25% 3D (grid uniform over ``sizes3d``, L = 10); Omega, gamma, c0, c1 and the
+    guess kind drawn as in the batched sweep; trap half harmonic, half harmonic
+    plus quartic 0.5 r^2 + 0.01 r^4. Returns (Problem, guess kinds) pairs; all
+    draws from one generator in a fixed order. Only power-of-two grids are
+    drawn (the transforms are radix 2 and 4)."""
+    rng = np.random.default_rng(seed)
+    kinds = [("a", "a", "a"), ("b", "a", "a"), ("f", "f", "f")]
+    out = []
+    for _ in range(count):
+        three = bool(rng.random() < 0.25)
+        if three:
+            n = int(sizes3d[rng.integers(len(sizes3d))])
+        else:
+            n = int(sizes2d[rng.integers(len(sizes2d))])
+        omega = float(rng.uniform(0.0, 0.9))
+        gamma = float(rng.uniform(0.0, 2.0))
+        c0 = float(rng.uniform(100.0, 2000.0))
+        c1 = float(rng.uniform(-5.0, 5.0))
+        k = kinds[int(rng.integers(3))]
+        quartic = bool(rng.random() < 0.5)
+        q4 = 0.01 if quartic else 0.0
+        if three:
+            pb = Problem(dim=3, n=(n, n, n), L=(10.0, 10.0, 10.0), q4=q4, omega=omega, gamma=gamma,
+                         c0=c0, c1=c1)
+        else:
+            pb = Problem(dim=2, n=(n, n), L=(16.0, 16.0), q4=q4, omega=omega, gamma=gamma, c0=c0, c1=c1)
+        out.append((pb, k))
+    return out
