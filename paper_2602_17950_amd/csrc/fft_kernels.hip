@@ -27,8 +27,14 @@ namespace gs {
 
 constexpr int NT = PT;   // threads per block of every FFT pass
 
-template <int N> struct Log2 { static constexpr int v = 1 + Log2<N / 2>::v; };
-template <> struct Log2<1> { static constexpr int v = 0; };
+// LDS layout of a line of N complex values: element e at e + e/16 (one pad
+// slot per 16), lines PITCH apart (odd). Radix-16 passes write with stride 16
+// and the transposed global accesses read columns; both then fall on distinct
+// banks.
+template <int N> struct Lay {
+    static constexpr int P = (N + N / 16) | 1;
+};
+__device__ __forceinline__ int lx(int e) { return e + (e >> 4); }
 
 template <typename R, bool INV>
 __device__ __forceinline__ cpx<R> twid(const cpx<R>* __restrict__ tw, int m) {
@@ -37,7 +43,48 @@ __device__ __forceinline__ cpx<R> twid(const cpx<R>* __restrict__ tw, int m) {
     return w;
 }
 
-// in-place 4-point DFT, kernel e^{-+2 pi i r q / 4}
+// exp(-2 pi i m / 16) (cos, -sin), m = 0..15
+__host__ __device__ constexpr double w16c(int m) {
+    switch (m & 15) {
+    case 0: return 1.0;
+    case 1: return 0.923879532511286756128;
+    case 2: return 0.707106781186547524401;
+    case 3: return 0.382683432365089771728;
+    case 4: return 0.0;
+    case 5: return -0.382683432365089771728;
+    case 6: return -0.707106781186547524401;
+    case 7: return -0.923879532511286756128;
+    case 8: return -1.0;
+    case 9: return -0.923879532511286756128;
+    case 10: return -0.707106781186547524401;
+    case 11: return -0.382683432365089771728;
+    case 12: return 0.0;
+    case 13: return 0.382683432365089771728;
+    case 14: return 0.707106781186547524401;
+    default: return 0.923879532511286756128;
+    }
+}
+__host__ __device__ constexpr double w16s(int m) { return -w16c((m & 15) + 12); }   // -sin = cos(. + 3/4 turn)
+
+// v * exp(-+2 pi i m / 16) for a compile-time m (after unrolling)
+template <typename R, bool INV>
+__device__ __forceinline__ cpx<R> rot16(cpx<R> v, int m) {
+    m &= 15;
+    if (m == 0) return v;
+    if (m == 8) return cmk(-v.x, -v.y);
+    if (m == 4) return INV ? cmk(-v.y, v.x) : cmk(v.y, -v.x);     // * (+-i)
+    if (m == 12) return INV ? cmk(v.y, -v.x) : cmk(-v.y, v.x);
+    const R c = (R)w16c(m), sn = (R)(INV ? -w16s(m) : w16s(m));
+    return cmk(v.x * c - v.y * sn, v.x * sn + v.y * c);
+}
+
+// in-place DFT of RAD values in registers, kernel exp(-+2 pi i r q / RAD)
+template <typename R, bool INV>
+__device__ __forceinline__ void dft2(cpx<R>& a, cpx<R>& b) {
+    const cpx<R> t = a - b;
+    a = a + b;
+    b = t;
+}
 template <typename R, bool INV>
 __device__ __forceinline__ void dft4(cpx<R>& v0, cpx<R>& v1, cpx<R>& v2, cpx<R>& v3) {
     const cpx<R> a = v0 + v2, b = v0 - v2, c = v1 + v3, d = v1 - v3;
@@ -47,74 +94,118 @@ __device__ __forceinline__ void dft4(cpx<R>& v0, cpx<R>& v1, cpx<R>& v2, cpx<R>&
     if (INV) { v1 = b + id; v3 = b - id; }
     else     { v1 = b - id; v3 = b + id; }
 }
+// RAD = A * B with r = r1 + A r2, q = q2 + B q1: DFT_B over r2, twiddle
+// exp(-+2 pi i r1 q2 / RAD), DFT_A over r1.
+template <typename R, int RAD, bool INV>
+__device__ __forceinline__ void dftr(cpx<R> (&v)[RAD]) {
+    if constexpr (RAD == 2) {
+        dft2<R, INV>(v[0], v[1]);
+    } else if constexpr (RAD == 4) {
+        dft4<R, INV>(v[0], v[1], v[2], v[3]);
+    } else if constexpr (RAD == 8) {
+        // A = 2, B = 4
+        cpx<R> y[2][4];
+#pragma unroll
+        for (int r1 = 0; r1 < 2; ++r1) {
+            y[r1][0] = v[r1]; y[r1][1] = v[r1 + 2]; y[r1][2] = v[r1 + 4]; y[r1][3] = v[r1 + 6];
+            dft4<R, INV>(y[r1][0], y[r1][1], y[r1][2], y[r1][3]);
+        }
+#pragma unroll
+        for (int q2 = 1; q2 < 4; ++q2) y[1][q2] = rot16<R, INV>(y[1][q2], 2 * q2);
+#pragma unroll
+        for (int q2 = 0; q2 < 4; ++q2) {
+            dft2<R, INV>(y[0][q2], y[1][q2]);
+            v[q2] = y[0][q2];
+            v[q2 + 4] = y[1][q2];
+        }
+    } else {
+        static_assert(RAD == 16, "radix 2, 4, 8 or 16");
+        // A = 4, B = 4
+        cpx<R> y[4][4];
+#pragma unroll
+        for (int r1 = 0; r1 < 4; ++r1) {
+            y[r1][0] = v[r1]; y[r1][1] = v[r1 + 4]; y[r1][2] = v[r1 + 8]; y[r1][3] = v[r1 + 12];
+            dft4<R, INV>(y[r1][0], y[r1][1], y[r1][2], y[r1][3]);
+        }
+#pragma unroll
+        for (int r1 = 1; r1 < 4; ++r1)
+#pragma unroll
+            for (int q2 = 1; q2 < 4; ++q2) y[r1][q2] = rot16<R, INV>(y[r1][q2], r1 * q2);
+#pragma unroll
+        for (int q2 = 0; q2 < 4; ++q2) {
+            dft4<R, INV>(y[0][q2], y[1][q2], y[2][q2], y[3][q2]);
+#pragma unroll
+            for (int q1 = 0; q1 < 4; ++q1) v[q2 + 4 * q1] = y[q1][q2];
+        }
+    }
+}
 
-// Transform NL lines of length N held in LDS at buf + l * PITCH (natural order
-// in and out, unnormalised). tw[m] = exp(-2 pi i m / N).
-template <typename R, int N, int NL, int PITCH, bool INV>
+// One Stockham pass of radix RAD on NL lines of N values (in LDS, layout Lay):
+// butterfly j of a line reads x[j + r N/RAD], applies the twiddles of the
+// pass, transforms, and writes to (j - k) RAD + k + r NS with k = j mod NS
+// (NS = product of the radices of the earlier passes). tw[m] = exp(-2 pi i m / N).
+template <typename R, int N, int NL, int NT, int RAD, int NS, bool INV>
+__device__ __forceinline__ void fft_pass(cpx<R>* buf, const cpx<R>* __restrict__ tw) {
+    constexpr int NB = N / RAD;
+    constexpr int TOT = NL * NB;
+    constexpr int BPT = (TOT + NT - 1) / NT;
+    constexpr int P = Lay<N>::P;
+    constexpr int TWS = N / (NS * RAD);
+    cpx<R> v[BPT][RAD];
+    int lb[BPT], db[BPT];
+#pragma unroll
+    for (int i = 0; i < BPT; ++i) {
+        const int b = threadIdx.x + i * NT;
+        lb[i] = -1;
+        if (TOT % NT == 0 || b < TOT) {
+            const int l = b / NB, j = b - l * NB;
+            const int k = j & (NS - 1);
+            const cpx<R>* src = buf + l * P;
+#pragma unroll
+            for (int r = 0; r < RAD; ++r) v[i][r] = src[lx(j + r * NB)];
+            if constexpr (NS > 1) {
+#pragma unroll
+                for (int r = 1; r < RAD; ++r) v[i][r] = cmul(v[i][r], twid<R, INV>(tw, r * k * TWS));
+            }
+            dftr<R, RAD, INV>(v[i]);
+            lb[i] = l * P;
+            db[i] = (j - k) * RAD + k;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < BPT; ++i) {
+        if (lb[i] >= 0) {
+#pragma unroll
+            for (int r = 0; r < RAD; ++r) buf[lb[i] + lx(db[i] + r * NS)] = v[i][r];
+        }
+    }
+    __syncthreads();
+}
+
+// Passes of radix RMAX while it divides the rest, then one pass of the
+// remaining factor (NS = product of the radices done so far).
+template <typename R, int N, int NL, int NT, int RMAX, int NS, bool INV>
+__device__ __forceinline__ void fft_passes(cpx<R>* buf, const cpx<R>* __restrict__ tw) {
+    constexpr int REST = N / NS;
+    if constexpr (REST >= RMAX) {
+        fft_pass<R, N, NL, NT, RMAX, NS, INV>(buf, tw);
+        fft_passes<R, N, NL, NT, RMAX, NS * RMAX, INV>(buf, tw);
+    } else if constexpr (REST > 1) {
+        fft_pass<R, N, NL, NT, REST, NS, INV>(buf, tw);
+    }
+}
+
+// Largest radix per pass: 16 in float; 8 in double, which halves the
+// registers a butterfly holds and so keeps more waves resident.
+template <typename R> constexpr int rmax() { return sizeof(R) == 8 ? 8 : 16; }
+
+// Transform NL lines of length N held in LDS (layout Lay<N>, line l at
+// buf + l * Lay<N>::P; natural order in and out, unnormalised).
+template <typename R, int N, int NL, int NT, bool INV>
 __device__ __forceinline__ void lds_fft(cpx<R>* buf, const cpx<R>* __restrict__ tw) {
-    constexpr int LOG2N = Log2<N>::v;
-    constexpr int N4 = N / 4;
-    constexpr int NB4 = NL * N4;
-    constexpr int BPT4 = (NB4 + NT - 1) / NT;
-    const int tid = threadIdx.x;
-#pragma unroll
-    for (int st = 0; st < LOG2N / 2; ++st) {
-        const int Ns = 1 << (2 * st);
-        cpx<R> v[BPT4][4];
-        int jj[BPT4], ll[BPT4];
-#pragma unroll
-        for (int i = 0; i < BPT4; ++i) {
-            const int b = tid + i * NT;
-            ll[i] = -1;
-            jj[i] = 0;
-            if (b < NB4) {
-                const int l = b / N4, j = b - l * N4;
-                ll[i] = l;
-                jj[i] = j;
-                const cpx<R>* src = buf + l * PITCH + j;
-                v[i][0] = src[0];
-                v[i][1] = src[N4];
-                v[i][2] = src[2 * N4];
-                v[i][3] = src[3 * N4];
-                if (st > 0) {
-                    const int k = j & (Ns - 1);
-                    const int step = k * (N / (4 * Ns));
-                    v[i][1] = cmul(v[i][1], twid<R, INV>(tw, step));
-                    v[i][2] = cmul(v[i][2], twid<R, INV>(tw, 2 * step));
-                    v[i][3] = cmul(v[i][3], twid<R, INV>(tw, 3 * step));
-                }
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < BPT4; ++i) {
-            if (ll[i] >= 0) {
-                dft4<R, INV>(v[i][0], v[i][1], v[i][2], v[i][3]);
-                const int j = jj[i];
-                const int k = j & (Ns - 1);
-                cpx<R>* dst = buf + ll[i] * PITCH + ((j - k) << 2) + k;
-                dst[0] = v[i][0];
-                dst[Ns] = v[i][1];
-                dst[2 * Ns] = v[i][2];
-                dst[3 * Ns] = v[i][3];
-            }
-        }
-        __syncthreads();
-    }
-    if (LOG2N & 1) {
-        // last stage, radix 2 with Ns = N/2: reads and writes the same pair
-        constexpr int N2 = N / 2;
-        constexpr int NB2 = NL * N2;
-        for (int b = tid; b < NB2; b += NT) {
-            const int l = b / N2, j = b - l * N2;
-            cpx<R>* p = buf + l * PITCH + j;
-            const cpx<R> u = p[0];
-            const cpx<R> w = cmul(p[N2], twid<R, INV>(tw, j));
-            p[0] = u + w;
-            p[N2] = u - w;
-        }
-        __syncthreads();
-    }
+    static_assert(N >= 16 && N <= 1024 && (N & (N - 1)) == 0, "N");
+    fft_passes<R, N, NL, NT, rmax<R>(), 1, INV>(buf, tw);
 }
 
 // ---------------------------------------------------------------------------
@@ -132,7 +223,7 @@ __global__ __launch_bounds__(NT) void k_fwdT(const Slot<R>* __restrict__ slots, 
     cpx<R>* __restrict__ out = S.buf[iout];
     const cpx<R>* __restrict__ aux0 = iaux0 >= 0 ? S.buf[iaux0] : nullptr;
     const cpx<R>* __restrict__ aux1 = iaux1 >= 0 ? S.buf[iaux1] : nullptr;
-    constexpr int PITCH = N + 1;
+    constexpr int PITCH = Lay<N>::P;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
     const int tiles = B / TILE;
@@ -178,13 +269,13 @@ __global__ __launch_bounds__(NT) void k_fwdT(const Slot<R>* __restrict__ slots, 
             inp[gi] = v;
             v = k2 * v;
         }
-        lds[l * PITCH + m] = v;
+        lds[l * PITCH + lx(m)] = v;
     }
     __syncthreads();
-    lds_fft<R, N, TILE, PITCH, false>(lds, tw);
+    lds_fft<R, N, TILE, NT, false>(lds, tw);
     for (int e = threadIdx.x; e < TILE * N; e += NT) {
         const int l = e % TILE, m = e / TILE;
-        out[(((long long)c * N + m) * A + a) * B + b0 + l] = lds[l * PITCH + m];
+        out[(((long long)c * N + m) * A + a) * B + b0 + l] = lds[l * PITCH + lx(m)];
     }
 }
 
@@ -212,7 +303,7 @@ __global__ __launch_bounds__(NT) void k_invT(const Slot<R>* __restrict__ slots, 
     cpx<R>* __restrict__ out = S.buf[iout];
     cpx<R>* __restrict__ out2 = (nin == 2 && iout2 >= 0) ? S.buf[iout2] : nullptr;
     const cpx<R>* __restrict__ uin = iuin >= 0 ? S.buf[iuin] : nullptr;
-    constexpr int PITCH = N + 1;
+    constexpr int PITCH = Lay<N>::P;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
     cpx<R>* lds2 = lds + TILE * PITCH;
@@ -226,17 +317,17 @@ __global__ __launch_bounds__(NT) void k_invT(const Slot<R>* __restrict__ slots, 
     for (int e = threadIdx.x; e < TILE * N; e += NT) {
         const int l = e % TILE, m = e / TILE;
         const long long gi = (((long long)c * N + m) * B + bb) * Cc + c0 + l;
-        lds[l * PITCH + m] = in[gi];
-        if (nin == 2) lds2[l * PITCH + m] = in2[gi];
+        lds[l * PITCH + lx(m)] = in[gi];
+        if (nin == 2) lds2[l * PITCH + lx(m)] = in2[gi];
     }
     __syncthreads();
-    lds_fft<R, N, TILE, PITCH, true>(lds, tw);
-    if (nin == 2) lds_fft<R, N, TILE, PITCH, true>(lds2, tw);
+    lds_fft<R, N, TILE, NT, true>(lds, tw);
+    if (nin == 2) lds_fft<R, N, TILE, NT, true>(lds2, tw);
     const R uscale = (EPI == EPI_HL && use_invnP) ? (R)st->invnP : (R)1;
     for (int e = threadIdx.x; e < TILE * N; e += NT) {
         const int l = e / N, m = e - l * N;
         const long long go = (((long long)c * B + bb) * Cc + c0 + l) * N + m;
-        cpx<R> v = lds[l * PITCH + m];
+        cpx<R> v = lds[l * PITCH + lx(m)];
         if (EPI == EPI_SCALE) {
             out[go] = (R)scale * v;
         } else if (EPI == EPI_HL) {
@@ -248,7 +339,7 @@ __global__ __launch_bounds__(NT) void k_invT(const Slot<R>* __restrict__ slots, 
             trap_at(p, go - (long long)c * p.M, x, y, z, V2, V4);
             const cpx<R> u = uscale * uin[go];
             v = v + (R)(V2 + V4) * u;
-            if (nin == 2) v = v - (R)(p.omega * x) * lds2[l * PITCH + m];
+            if (nin == 2) v = v - (R)(p.omega * x) * lds2[l * PITCH + lx(m)];
             out[go] = v;
         } else if (EPI == EPI_ROTX) {
             if (nin == 2) {
@@ -256,7 +347,7 @@ __global__ __launch_bounds__(NT) void k_invT(const Slot<R>* __restrict__ slots, 
                 const double kx = wavenum(jx, p.n[0], p.L[0]);
                 const double y = -p.L[1] + iy * p.h[1];
                 v = v + (R)(p.omega * y * kx / p.n[0]) * uin[go];
-                out2[go] = lds2[l * PITCH + m];
+                out2[go] = lds2[l * PITCH + lx(m)];
             }
             out[go] = v;
         }
@@ -277,7 +368,7 @@ __global__ __launch_bounds__(NT) void k_invT_pre(const Slot<R>* __restrict__ slo
     const cpx<R>* __restrict__ in = S.buf[iin];
     cpx<R>* __restrict__ out = S.buf[iout];
     const R* __restrict__ pv = S.pv;
-    constexpr int PITCH = N + 1;
+    constexpr int PITCH = Lay<N>::P;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
     const int tiles = Cc / TILE;
@@ -289,10 +380,10 @@ __global__ __launch_bounds__(NT) void k_invT_pre(const Slot<R>* __restrict__ slo
     const int c0 = ct * TILE;
     for (int e = threadIdx.x; e < TILE * N; e += NT) {
         const int l = e % TILE, m = e / TILE;
-        lds[l * PITCH + m] = in[(((long long)c * N + m) * B + bb) * Cc + c0 + l];
+        lds[l * PITCH + lx(m)] = in[(((long long)c * N + m) * B + bb) * Cc + c0 + l];
     }
     __syncthreads();
-    lds_fft<R, N, TILE, PITCH, true>(lds, tw);
+    lds_fft<R, N, TILE, NT, true>(lds, tw);
     double acc[NS_DIR] = {0.0, 0.0, 0.0, 0.0, 0.0};
     const cpx<R>* r = dir ? S.buf[B_R0 + st->cur] : nullptr;
     const cpx<R>* rp = dir ? S.buf[B_R0 + (st->cur ^ 1)] : nullptr;
@@ -301,7 +392,7 @@ __global__ __launch_bounds__(NT) void k_invT_pre(const Slot<R>* __restrict__ slo
     for (int e = threadIdx.x; e < TILE * N; e += NT) {
         const int l = e / N, m = e - l * N;
         const long long go = (((long long)c * B + bb) * Cc + c0 + l) * N + m;
-        const cpx<R> v = pv[go] * lds[l * PITCH + m];
+        const cpx<R> v = pv[go] * lds[l * PITCH + lx(m)];
         out[go] = v;
         if (dir) {
             const cpx<double> w = wid(v);
@@ -340,14 +431,16 @@ __global__ __launch_bounds__(NT) void k_mid(const Slot<R>* __restrict__ slots, i
     cpx<R>* __restrict__ outA = S.buf[ioutA];
     cpx<R>* __restrict__ outB = ioutB >= 0 ? S.buf[ioutB] : nullptr;
     double* __restrict__ red = S.red_mid;
-    constexpr int PITCH = N + 1;
+    constexpr int PITCH = Lay<N>::P;
     constexpr int NLN = 3 * LPB;
     constexpr bool HL = OP == MID_HL || OP == MID_HLX;
     constexpr bool X2 = OP == MID_HLX;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     cpx<R>* X = reinterpret_cast<cpx<R>*>(smem_raw);
     cpx<R>* Z = X + NLN * PITCH;                       // spectrum of Phi (MID_HLX)
-    cpx<R>* Y = X + (X2 ? 2 : 1) * NLN * PITCH;        // rotation output B
+    // rotation output B; with MID_HLX it takes Z's place (each point's Z values
+    // are read by the thread that then writes its B values)
+    cpx<R>* Y = X + NLN * PITCH;
     const bool doB = HL && rot;
     const int l0 = blockIdx.x * LPB;
     const long long cs = (long long)nlines * N;
@@ -355,11 +448,16 @@ __global__ __launch_bounds__(NT) void k_mid(const Slot<R>* __restrict__ slots, i
         const int L = e / N, m = e - L * N;
         const int c = L / LPB, q = L - c * LPB;
         const long long gi = c * cs + (long long)(l0 + q) * N + m;
-        X[L * PITCH + m] = in[gi];
-        if (X2) Z[L * PITCH + m] = in2[gi];
+        X[L * PITCH + lx(m)] = in[gi];
+        if (X2) Z[L * PITCH + lx(m)] = in2[gi];
     }
     __syncthreads();
-    lds_fft<R, N, (X2 ? 2 : 1) * NLN, PITCH, false>(X, tw);
+    if constexpr (X2 && 2 * NLN * N <= 16 * NT) {
+        lds_fft<R, N, 2 * NLN, NT, false>(X, tw);   // X and Z are adjacent
+    } else {
+        lds_fft<R, N, NLN, NT, false>(X, tw);
+        if constexpr (X2) lds_fft<R, N, NLN, NT, false>(Z, tw);
+    }
     const double invM = 1.0 / (double)p.M;
     double acc[X2 ? NS_KIN : 4];
     for (int k = 0; k < (X2 ? NS_KIN : 4); ++k) acc[k] = 0.0;
@@ -382,9 +480,9 @@ __global__ __launch_bounds__(NT) void k_mid(const Slot<R>* __restrict__ slots, i
             kz = wavenum(m, p.n[2], p.L[2]);
         }
         const double K = 0.5 * (kx * kx + ky * ky + kz * kz);
-        cpx<R>* x0 = X + (0 * LPB + q) * PITCH + m;
-        cpx<R>* x1 = X + (1 * LPB + q) * PITCH + m;
-        cpx<R>* x2 = X + (2 * LPB + q) * PITCH + m;
+        cpx<R>* x0 = X + (0 * LPB + q) * PITCH + lx(m);
+        cpx<R>* x1 = X + (1 * LPB + q) * PITCH + lx(m);
+        cpx<R>* x2 = X + (2 * LPB + q) * PITCH + lx(m);
         if (HL) {
             const cpx<double> v0 = wid(*x0), v1 = wid(*x1), v2 = wid(*x2);
             const cpx<double> s0 = cmk(-kx, ky), s1 = cmk(-kx, -ky);
@@ -394,7 +492,7 @@ __global__ __launch_bounds__(NT) void k_mid(const Slot<R>* __restrict__ slots, i
             if (X2) {
                 const cpx<double> v[3] = {v0, v1, v2};
                 for (int cc = 0; cc < 3; ++cc) {
-                    const cpx<double> z = wid(Z[(cc * LPB + q) * PITCH + m]);
+                    const cpx<double> z = wid(Z[(cc * LPB + q) * PITCH + lx(m)]);
                     acc[3 * cc] += K * cabs2(z);
                     acc[3 * cc + 1] += K * re_dot(z, v[cc]);
                     acc[3 * cc + 2] += K * cabs2(v[cc]);
@@ -411,9 +509,9 @@ __global__ __launch_bounds__(NT) void k_mid(const Slot<R>* __restrict__ slots, i
             const cpx<double> a2 = invM * (K * v2 - gm * S2);
             if (doB) {
                 const double fb = ky * invM;
-                Y[(0 * LPB + q) * PITCH + m] = cmk((R)(fb * v0.x), (R)(fb * v0.y));
-                Y[(1 * LPB + q) * PITCH + m] = cmk((R)(fb * v1.x), (R)(fb * v1.y));
-                Y[(2 * LPB + q) * PITCH + m] = cmk((R)(fb * v2.x), (R)(fb * v2.y));
+                Y[(0 * LPB + q) * PITCH + lx(m)] = cmk((R)(fb * v0.x), (R)(fb * v0.y));
+                Y[(1 * LPB + q) * PITCH + lx(m)] = cmk((R)(fb * v1.x), (R)(fb * v1.y));
+                Y[(2 * LPB + q) * PITCH + lx(m)] = cmk((R)(fb * v2.x), (R)(fb * v2.y));
             }
             *x0 = cmk((R)a0.x, (R)a0.y);
             *x1 = cmk((R)a1.x, (R)a1.y);
@@ -428,21 +526,21 @@ __global__ __launch_bounds__(NT) void k_mid(const Slot<R>* __restrict__ slots, i
         }
     }
     __syncthreads();
-    lds_fft<R, N, NLN, PITCH, true>(X, tw);
-    if (doB) lds_fft<R, N, NLN, PITCH, true>(Y, tw);
+    lds_fft<R, N, NLN, NT, true>(X, tw);
+    if (doB) lds_fft<R, N, NLN, NT, true>(Y, tw);
     const bool rot2d = HL && rot && p.dim == 2;
     for (int e = threadIdx.x; e < NLN * N; e += NT) {
         const int L = e / N, m = e - L * N;
         const int c = L / LPB, q = L - c * LPB;
         const long long go = c * cs + (long long)(l0 + q) * N + m;
-        cpx<R> v = X[L * PITCH + m];
+        cpx<R> v = X[L * PITCH + lx(m)];
         if (rot2d) {
             const double kx = wavenum(l0 + q, p.n[0], p.L[0]);
             const double y = -p.L[1] + m * p.h[1];
             v = v + (R)(p.omega * y * kx / p.n[0]) * in[go];
         }
         outA[go] = v;
-        if (doB) outB[go] = Y[L * PITCH + m];
+        if (doB) outB[go] = Y[L * PITCH + lx(m)];
     }
     if (HL) block_row<(X2 ? NS_KIN : 4)>(acc, red, RED_MID_STRIDE);
 }
@@ -470,7 +568,7 @@ static hipError_t fwdT_n(int pro, int dual, const Slot<R>* slots, int nslots, in
     constexpr int TILE = tile_fwd<R>(N);
     if (B % TILE) return hipErrorInvalidValue;
     if (dual && pro != PRO_DIR) return hipErrorInvalidValue;
-    const size_t lds = (size_t)TILE * (N + 1) * sizeof(cpx<R>);
+    const size_t lds = (size_t)TILE * Lay<N>::P * sizeof(cpx<R>);
     dim3 grid((unsigned)((long long)(dual ? 6 : ncomp) * A * (B / TILE)), (unsigned)nslots);
     if (dual) {
         GS_LAUNCH((k_fwdT<R, N, TILE, PRO_DIR, true>), grid, dim3(NT), lds, s, slots, in, out, aux0, aux1, A, B, tw);
@@ -497,7 +595,7 @@ static hipError_t invT_n(int epi, const Slot<R>* slots, int nslots, int in, int 
                          int B, int Cc, double scale, int use_invnP, int rot_any, const cpx<R>* tw, hipStream_t s) {
     constexpr int TILE = tile_inv<R>(N);
     if (Cc % TILE) return hipErrorInvalidValue;
-    const size_t lds = (size_t)(epi == EPI_SCALE ? 1 : 2) * TILE * (N + 1) * sizeof(cpx<R>);
+    const size_t lds = (size_t)(epi == EPI_SCALE ? 1 : 2) * TILE * Lay<N>::P * sizeof(cpx<R>);
     dim3 grid((unsigned)(3LL * B * (Cc / TILE)), (unsigned)nslots);
     switch (epi) {
     case EPI_SCALE:
@@ -520,7 +618,7 @@ static hipError_t invT_pre_n(const Slot<R>* slots, int nslots, int in, int out, 
                              const cpx<R>* tw, hipStream_t s) {
     constexpr int TILE = tile_inv<R>(N);
     if (Cc % TILE) return hipErrorInvalidValue;
-    const size_t lds = (size_t)TILE * (N + 1) * sizeof(cpx<R>);
+    const size_t lds = (size_t)TILE * Lay<N>::P * sizeof(cpx<R>);
     dim3 grid((unsigned)(3LL * B * (Cc / TILE)), (unsigned)nslots);
     static_assert(NS_DIR <= RED_DIR_STRIDE, "partial-sum row");
     GS_LAUNCH((k_invT_pre<R, N, TILE>), grid, dim3(NT), lds, s, slots, in, out, B, Cc, dir, tw);
@@ -532,9 +630,8 @@ static hipError_t mid_n(int op, const Slot<R>* slots, int nslots, int in, int ou
                         int rot_any, const cpx<R>* tw, hipStream_t s) {
     constexpr int LPB = lpb_mid(N);
     if (nlines % LPB) return hipErrorInvalidValue;
-    const int nB = ((op == MID_HL || op == MID_HLX) && rot_any) ? 1 : 0;
-    const int nX = op == MID_HLX ? 2 : 1;
-    const size_t lds = (size_t)(nB + nX) * 3 * LPB * (N + 1) * sizeof(cpx<R>);
+    const int nbuf = (op == MID_HLX || (op == MID_HL && rot_any)) ? 2 : 1;
+    const size_t lds = (size_t)nbuf * 3 * LPB * Lay<N>::P * sizeof(cpx<R>);
     dim3 grid((unsigned)(nlines / LPB), (unsigned)nslots);
     if (op == MID_HL)
         GS_LAUNCH((k_mid<R, N, LPB, MID_HL>), grid, dim3(NT), lds, s, slots, in, outA, outB, nlines, rot_any, tw);
