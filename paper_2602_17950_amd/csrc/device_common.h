@@ -87,12 +87,13 @@ __device__ __forceinline__ void halve_all(double* v, int lane) {
 // reduce-scatter inside each wave (about P shuffles for P = NV rounded up to a
 // power of two, instead of 6 NV), the four wave totals of each value added in
 // a fixed order, and the row stored by NV threads at once.
-template <int NV>
+template <int NV, int NTB = PT>
 __device__ __forceinline__ void block_row(const double (&acc)[NV], double* rows, int stride) {
     constexpr int P = Pow2Ceil<NV>::v;
     static_assert(P <= 64, "at most 64 sums per row");
+    static_assert(NTB % 64 == 0 && NTB <= 1024, "whole waves");
     constexpr int SH = 6 - ILog2<P>::v;   // lanes 2^SH apart hold the same value index
-    __shared__ double sh[PT / 64][P];
+    __shared__ double sh[NTB / 64][P];
     double v[P];
 #pragma unroll
     for (int k = 0; k < P; ++k) v[k] = k < NV ? acc[k] : 0.0;
@@ -102,7 +103,7 @@ __device__ __forceinline__ void block_row(const double (&acc)[NV], double* rows,
     __syncthreads();
     if (threadIdx.x < NV) {
         double t = sh[0][threadIdx.x];
-        for (int w = 1; w < PT / 64; ++w) t += sh[w][threadIdx.x];
+        for (int w = 1; w < NTB / 64; ++w) t += sh[w][threadIdx.x];
         rows[(long long)blockIdx.x * stride + threadIdx.x] = t;
     }
 }

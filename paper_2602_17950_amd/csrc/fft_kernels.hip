@@ -25,7 +25,7 @@
 
 namespace gs {
 
-constexpr int NT = PT;   // threads per block of every FFT pass
+// threads per block: a template parameter NT of each kernel (whole waves)
 
 // LDS layout of a line of N complex values: element e at e + e/16 (one pad
 // slot per 16), lines PITCH apart (odd). Radix-16 passes write with stride 16
@@ -213,7 +213,7 @@ __device__ __forceinline__ void lds_fft(cpx<R>* buf, const cpx<R>* __restrict__ 
 // ---------------------------------------------------------------------------
 // DUAL (with PRO_DIR): components 3..5 of the output are the plain transform
 // of aux1 (Phi), so that the middle pass sees both spectra.
-template <typename R, int N, int TILE, int PRO, bool DUAL>
+template <typename R, int N, int TILE, int PRO, bool DUAL, int NT>
 __global__ __launch_bounds__(NT) void k_fwdT(const Slot<R>* __restrict__ slots, int iin, int iout, int iaux0,
                                              int iaux1, int A, int B, const cpx<R>* __restrict__ tw) {
     const Slot<R>& S = slots[blockIdx.y];
@@ -288,7 +288,7 @@ __global__ __launch_bounds__(NT) void k_fwdT(const Slot<R>* __restrict__ slots, 
 //   EPI_ROTX:  3D y-pass of the H_L chain, layout [kx][z][y]:
 //              out = IFFT(A) + Omega y k_x uin / Nx, out2 = IFFT(B)
 //              (uin = the x-transformed input, same layout)
-template <typename R, int N, int TILE, int EPI>
+template <typename R, int N, int TILE, int EPI, int NT>
 __global__ __launch_bounds__(NT) void k_invT(const Slot<R>* __restrict__ slots, int iin, int iin2, int iout,
                                              int iout2, int iuin, int B, int Cc, double scale, int use_invnP,
                                              int rot_any, const cpx<R>* __restrict__ tw) {
@@ -359,7 +359,7 @@ __global__ __launch_bounds__(NT) void k_invT(const Slot<R>* __restrict__ slots, 
 // partial sums of the direction reductions of the next step fused in
 // (Re<r,Pr>, Re<r_prev,Pr>, Re<phi,Pr>, |Pr|^2, Re<Pr,P^{n-1}>).
 // ---------------------------------------------------------------------------
-template <typename R, int N, int TILE>
+template <typename R, int N, int TILE, int NT>
 __global__ __launch_bounds__(NT) void k_invT_pre(const Slot<R>* __restrict__ slots, int iin, int iout, int B,
                                                  int Cc, int dir, const cpx<R>* __restrict__ tw) {
     const Slot<R>& S = slots[blockIdx.y];
@@ -404,7 +404,7 @@ __global__ __launch_bounds__(NT) void k_invT_pre(const Slot<R>* __restrict__ slo
         }
     }
     if (!dir) return;
-    block_row<NS_DIR>(acc, S.red_dir, RED_DIR_STRIDE);
+    block_row<NS_DIR, NT>(acc, S.red_dir, RED_DIR_STRIDE);
 }
 
 // ---------------------------------------------------------------------------
@@ -418,7 +418,7 @@ __global__ __launch_bounds__(NT) void k_invT_pre(const Slot<R>* __restrict__ slo
 //   MID_HLX: as MID_HL for v = P^, and in2 holds the spectrum of Phi: block sums
 //            of 1/2|k|^2 |Phi^_l|^2, 1/2|k|^2 Re Phi^_l conj(v_l), 1/2|k|^2 |v_l|^2.
 //   MID_PRE: A = v_l / (alpha_l + 1/2 |k|^2) / M.
-template <typename R, int N, int LPB, int OP>
+template <typename R, int N, int LPB, int OP, int NT>
 __global__ __launch_bounds__(NT) void k_mid(const Slot<R>* __restrict__ slots, int iin, int ioutA, int ioutB,
                                             int nlines, int rot_any, const cpx<R>* __restrict__ tw) {
     const Slot<R>& S = slots[blockIdx.y];
@@ -442,17 +442,32 @@ __global__ __launch_bounds__(NT) void k_mid(const Slot<R>* __restrict__ slots, i
     // are read by the thread that then writes its B values)
     cpx<R>* Y = X + NLN * PITCH;
     const bool doB = HL && rot;
+    const bool rot2d = doB && p.dim == 2;
     const int l0 = blockIdx.x * LPB;
     const long long cs = (long long)nlines * N;
-    for (int e = threadIdx.x; e < NLN * N; e += NT) {
-        const int L = e / N, m = e - L * N;
-        const int c = L / LPB, q = L - c * LPB;
-        const long long gi = c * cs + (long long)(l0 + q) * N + m;
-        X[L * PITCH + lx(m)] = in[gi];
-        if (X2) Z[L * PITCH + lx(m)] = in2[gi];
+    // the input values stay in registers for the 2D rotation term of the
+    // epilogue when a thread holds few of them (else they are read again)
+    constexpr int EPT = (NLN * N + NT - 1) / NT;
+    constexpr bool KEEP = EPT <= 4;
+    // transforms of two line groups at once when a thread then holds at most
+    // 8 (double) or 16 (float) values
+    constexpr bool JOINT = 2 * NLN * N <= (sizeof(R) == 8 ? 8 : 16) * NT;
+    cpx<R> keep[KEEP ? EPT : 1];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const int e = threadIdx.x + i * NT;
+        if (NLN * N % NT == 0 || e < NLN * N) {
+            const int L = e / N, m = e - L * N;
+            const int c = L / LPB, q = L - c * LPB;
+            const long long gi = c * cs + (long long)(l0 + q) * N + m;
+            const cpx<R> x = in[gi];
+            if constexpr (KEEP) keep[i] = x;
+            X[L * PITCH + lx(m)] = x;
+            if (X2) Z[L * PITCH + lx(m)] = in2[gi];
+        }
     }
     __syncthreads();
-    if constexpr (X2 && 2 * NLN * N <= 16 * NT) {
+    if constexpr (X2 && JOINT) {
         lds_fft<R, N, 2 * NLN, NT, false>(X, tw);   // X and Z are adjacent
     } else {
         lds_fft<R, N, NLN, NT, false>(X, tw);
@@ -526,39 +541,57 @@ __global__ __launch_bounds__(NT) void k_mid(const Slot<R>* __restrict__ slots, i
         }
     }
     __syncthreads();
-    lds_fft<R, N, NLN, NT, true>(X, tw);
-    if (doB) lds_fft<R, N, NLN, NT, true>(Y, tw);
-    const bool rot2d = HL && rot && p.dim == 2;
-    for (int e = threadIdx.x; e < NLN * N; e += NT) {
-        const int L = e / N, m = e - L * N;
-        const int c = L / LPB, q = L - c * LPB;
-        const long long go = c * cs + (long long)(l0 + q) * N + m;
-        cpx<R> v = X[L * PITCH + lx(m)];
-        if (rot2d) {
-            const double kx = wavenum(l0 + q, p.n[0], p.L[0]);
-            const double y = -p.L[1] + m * p.h[1];
-            v = v + (R)(p.omega * y * kx / p.n[0]) * in[go];
-        }
-        outA[go] = v;
-        if (doB) outB[go] = Y[L * PITCH + lx(m)];
+    if constexpr (HL && JOINT) {
+        if (doB) lds_fft<R, N, 2 * NLN, NT, true>(X, tw);   // X and Y are adjacent
+        else lds_fft<R, N, NLN, NT, true>(X, tw);
+    } else {
+        lds_fft<R, N, NLN, NT, true>(X, tw);
+        if (doB) lds_fft<R, N, NLN, NT, true>(Y, tw);
     }
-    if (HL) block_row<(X2 ? NS_KIN : 4)>(acc, red, RED_MID_STRIDE);
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const int e = threadIdx.x + i * NT;
+        if (NLN * N % NT == 0 || e < NLN * N) {
+            const int L = e / N, m = e - L * N;
+            const int c = L / LPB, q = L - c * LPB;
+            const long long go = c * cs + (long long)(l0 + q) * N + m;
+            cpx<R> v = X[L * PITCH + lx(m)];
+            if (rot2d) {
+                const double kx = wavenum(l0 + q, p.n[0], p.L[0]);
+                const double y = -p.L[1] + m * p.h[1];
+                const cpx<R> x = KEEP ? keep[KEEP ? i : 0] : in[go];
+                v = v + (R)(p.omega * y * kx / p.n[0]) * x;
+            }
+            outA[go] = v;
+            if (doB) outB[go] = Y[L * PITCH + lx(m)];
+        }
+    }
+    if (HL) block_row<(X2 ? NS_KIN : 4), NT>(acc, red, RED_MID_STRIDE);
 }
 
 // ---------------------------------------------------------------------------
 // launch configuration (tiles sized so that small grids still give >= ~200
 // blocks and each block's LDS stays near or under 64 KB)
 // ---------------------------------------------------------------------------
+// Lines per block of the transposing passes. In double, 8 lines give 128-byte
+// runs in the transposed accesses of the forward and the preconditioner passes;
+// the H_L inverse pass, which holds two transforms in LDS, keeps 4 (measured).
 template <typename R> constexpr int tile_fwd(int N) {
-    return sizeof(R) == 8 ? (N >= 1024 ? 2 : 4) : (N >= 1024 ? 4 : 8);
+    return sizeof(R) == 8 ? (N >= 1024 ? 2 : (N >= 512 ? 4 : 8)) : (N >= 1024 ? 4 : 8);
 }
+template <typename R> constexpr int tile_pre(int N) { return tile_fwd<R>(N); }
 template <typename R> constexpr int tile_inv(int N) {
     return sizeof(R) == 8 ? (N >= 512 ? 2 : 4) : (N >= 512 ? 4 : 8);
 }
 constexpr int lpb_mid(int N) { return N >= 256 ? 1 : (N >= 128 ? 2 : (N >= 64 ? 4 : 8)); }
 
 int mid_blocks(int N, int nlines) { return nlines / lpb_mid(N); }
-template <typename R> int invT_pre_blocks(int N, int B, int Cc) { return 3 * B * (Cc / tile_inv<R>(N)); }
+
+// threads per block of the FFT passes (whole waves; the transforms of a block
+// hold TILE * N or 3 * LPB * N values)
+template <typename R> constexpr int nt_tile(int N) { return 256; }
+template <typename R> constexpr int nt_mid(int N) { return N >= 1024 ? 512 : 256; }
+template <typename R> int invT_pre_blocks(int N, int B, int Cc) { return 3 * B * (Cc / tile_pre<R>(N)); }
 template int invT_pre_blocks<double>(int, int, int);
 template int invT_pre_blocks<float>(int, int, int);
 
@@ -566,23 +599,24 @@ template <typename R, int N>
 static hipError_t fwdT_n(int pro, int dual, const Slot<R>* slots, int nslots, int in, int out, int aux0, int aux1,
                          int A, int B, int ncomp, const cpx<R>* tw, hipStream_t s) {
     constexpr int TILE = tile_fwd<R>(N);
+    constexpr int NTB = nt_tile<R>(N);
     if (B % TILE) return hipErrorInvalidValue;
     if (dual && pro != PRO_DIR) return hipErrorInvalidValue;
     const size_t lds = (size_t)TILE * Lay<N>::P * sizeof(cpx<R>);
     dim3 grid((unsigned)((long long)(dual ? 6 : ncomp) * A * (B / TILE)), (unsigned)nslots);
     if (dual) {
-        GS_LAUNCH((k_fwdT<R, N, TILE, PRO_DIR, true>), grid, dim3(NT), lds, s, slots, in, out, aux0, aux1, A, B, tw);
+        GS_LAUNCH((k_fwdT<R, N, TILE, PRO_DIR, true, NTB>), grid, dim3(NTB), lds, s, slots, in, out, aux0, aux1, A, B, tw);
         return hipGetLastError();
     }
     switch (pro) {
     case PRO_PLAIN:
-        GS_LAUNCH((k_fwdT<R, N, TILE, PRO_PLAIN, false>), grid, dim3(NT), lds, s, slots, in, out, aux0, aux1, A, B, tw);
+        GS_LAUNCH((k_fwdT<R, N, TILE, PRO_PLAIN, false, NTB>), grid, dim3(NTB), lds, s, slots, in, out, aux0, aux1, A, B, tw);
         break;
     case PRO_UPDATE:
-        GS_LAUNCH((k_fwdT<R, N, TILE, PRO_UPDATE, false>), grid, dim3(NT), lds, s, slots, in, out, aux0, aux1, A, B, tw);
+        GS_LAUNCH((k_fwdT<R, N, TILE, PRO_UPDATE, false, NTB>), grid, dim3(NTB), lds, s, slots, in, out, aux0, aux1, A, B, tw);
         break;
     case PRO_DIR:
-        GS_LAUNCH((k_fwdT<R, N, TILE, PRO_DIR, false>), grid, dim3(NT), lds, s, slots, in, out, aux0, aux1, A, B, tw);
+        GS_LAUNCH((k_fwdT<R, N, TILE, PRO_DIR, false, NTB>), grid, dim3(NTB), lds, s, slots, in, out, aux0, aux1, A, B, tw);
         break;
     default:
         return hipErrorInvalidValue;
@@ -594,18 +628,19 @@ template <typename R, int N>
 static hipError_t invT_n(int epi, const Slot<R>* slots, int nslots, int in, int in2, int out, int out2, int uin,
                          int B, int Cc, double scale, int use_invnP, int rot_any, const cpx<R>* tw, hipStream_t s) {
     constexpr int TILE = tile_inv<R>(N);
+    constexpr int NTB = nt_tile<R>(N);
     if (Cc % TILE) return hipErrorInvalidValue;
     const size_t lds = (size_t)(epi == EPI_SCALE ? 1 : 2) * TILE * Lay<N>::P * sizeof(cpx<R>);
     dim3 grid((unsigned)(3LL * B * (Cc / TILE)), (unsigned)nslots);
     switch (epi) {
     case EPI_SCALE:
-        GS_LAUNCH((k_invT<R, N, TILE, EPI_SCALE>), grid, dim3(NT), lds, s, slots, in, in2, out, out2, uin, B, Cc, scale, use_invnP, rot_any, tw);
+        GS_LAUNCH((k_invT<R, N, TILE, EPI_SCALE, NTB>), grid, dim3(NTB), lds, s, slots, in, in2, out, out2, uin, B, Cc, scale, use_invnP, rot_any, tw);
         break;
     case EPI_HL:
-        GS_LAUNCH((k_invT<R, N, TILE, EPI_HL>), grid, dim3(NT), lds, s, slots, in, in2, out, out2, uin, B, Cc, scale, use_invnP, rot_any, tw);
+        GS_LAUNCH((k_invT<R, N, TILE, EPI_HL, NTB>), grid, dim3(NTB), lds, s, slots, in, in2, out, out2, uin, B, Cc, scale, use_invnP, rot_any, tw);
         break;
     case EPI_ROTX:
-        GS_LAUNCH((k_invT<R, N, TILE, EPI_ROTX>), grid, dim3(NT), lds, s, slots, in, in2, out, out2, uin, B, Cc, scale, use_invnP, rot_any, tw);
+        GS_LAUNCH((k_invT<R, N, TILE, EPI_ROTX, NTB>), grid, dim3(NTB), lds, s, slots, in, in2, out, out2, uin, B, Cc, scale, use_invnP, rot_any, tw);
         break;
     default:
         return hipErrorInvalidValue;
@@ -616,12 +651,13 @@ static hipError_t invT_n(int epi, const Slot<R>* slots, int nslots, int in, int 
 template <typename R, int N>
 static hipError_t invT_pre_n(const Slot<R>* slots, int nslots, int in, int out, int B, int Cc, int dir,
                              const cpx<R>* tw, hipStream_t s) {
-    constexpr int TILE = tile_inv<R>(N);
+    constexpr int TILE = tile_pre<R>(N);
+    constexpr int NTB = nt_tile<R>(N);
     if (Cc % TILE) return hipErrorInvalidValue;
     const size_t lds = (size_t)TILE * Lay<N>::P * sizeof(cpx<R>);
     dim3 grid((unsigned)(3LL * B * (Cc / TILE)), (unsigned)nslots);
     static_assert(NS_DIR <= RED_DIR_STRIDE, "partial-sum row");
-    GS_LAUNCH((k_invT_pre<R, N, TILE>), grid, dim3(NT), lds, s, slots, in, out, B, Cc, dir, tw);
+    GS_LAUNCH((k_invT_pre<R, N, TILE, NTB>), grid, dim3(NTB), lds, s, slots, in, out, B, Cc, dir, tw);
     return hipGetLastError();
 }
 
@@ -629,16 +665,17 @@ template <typename R, int N>
 static hipError_t mid_n(int op, const Slot<R>* slots, int nslots, int in, int outA, int outB, int nlines,
                         int rot_any, const cpx<R>* tw, hipStream_t s) {
     constexpr int LPB = lpb_mid(N);
+    constexpr int NTB = nt_mid<R>(N);
     if (nlines % LPB) return hipErrorInvalidValue;
     const int nbuf = (op == MID_HLX || (op == MID_HL && rot_any)) ? 2 : 1;
     const size_t lds = (size_t)nbuf * 3 * LPB * Lay<N>::P * sizeof(cpx<R>);
     dim3 grid((unsigned)(nlines / LPB), (unsigned)nslots);
     if (op == MID_HL)
-        GS_LAUNCH((k_mid<R, N, LPB, MID_HL>), grid, dim3(NT), lds, s, slots, in, outA, outB, nlines, rot_any, tw);
+        GS_LAUNCH((k_mid<R, N, LPB, MID_HL, NTB>), grid, dim3(NTB), lds, s, slots, in, outA, outB, nlines, rot_any, tw);
     else if (op == MID_HLX)
-        GS_LAUNCH((k_mid<R, N, LPB, MID_HLX>), grid, dim3(NT), lds, s, slots, in, outA, outB, nlines, rot_any, tw);
+        GS_LAUNCH((k_mid<R, N, LPB, MID_HLX, NTB>), grid, dim3(NTB), lds, s, slots, in, outA, outB, nlines, rot_any, tw);
     else
-        GS_LAUNCH((k_mid<R, N, LPB, MID_PRE>), grid, dim3(NT), lds, s, slots, in, outA, outB, nlines, 0, tw);
+        GS_LAUNCH((k_mid<R, N, LPB, MID_PRE, NTB>), grid, dim3(NTB), lds, s, slots, in, outA, outB, nlines, 0, tw);
     return hipGetLastError();
 }
 
