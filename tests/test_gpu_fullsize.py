@@ -1,0 +1,76 @@
+"""Parity at the benchmark's full sizes, in its launch configuration.
+
+The oracle cannot iterate these solves to convergence in test time, but it can
+evaluate any state: each converged GPU state is handed to the oracle, which
+recomputes the energy, chemical potential, residual, norm and virial residual
+on its own (FP64, its own FFT), and these must match what the GPU reported for
+the same state; the physical properties that hold at any size (unit norm,
+E_soc <= 0 for a rotation-invariant trap, virial residual -> 0, equal mu_l)
+are checked as well.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2602_17950_amd import gs, inputs
+
+from helpers import orc, rel
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _check_against_oracle(pb, psi, r, tol_E=1e-12, tol_mu=1e-10):
+    g, t, p = orc(pb)
+    ev = O.evaluate(g, t, p, psi)
+    print(f"[fullsize] {pb.n} gpu E={r['E']!r} mu={r['mu']!r} res={r['resid_inf']:.3e} | oracle "
+          f"E={ev['E']!r} mu={ev['mu']!r} res={ev['resid_inf']:.3e}", flush=True)
+    assert rel(r["E"], ev["E"]) < tol_E
+    assert rel(r["mu"], ev["mu"]) < tol_mu
+    assert abs(r["resid_inf"] - ev["resid_inf"]) < 1e-9 + 1e-3 * ev["resid_inf"]
+    # the GPU sums in a tree; the oracle sums the 3 M terms one after the other,
+    # whose rounding grows like 3 M eps (5e-13 seen at 128^3)
+    assert abs(sum(r["norm_comp"]) - 1.0) < 1e-13
+    assert abs(ev["norm"] - 1.0) < max(1e-13, 3 * pb.npts * 1.1e-16)
+    for a, b in zip(r["mu_comp"], ev["mu_comp"]):
+        assert rel(a, b) < 1e-8
+    assert abs(r["virial"] - ev["virial"]) < 1e-8
+    return ev
+
+
+def test_batched_256_vortex_states_match_oracle(gpu_ctx):
+    """Four seeds of the 256^2 rotating workload solved in one batch (one grid
+    class, every launch shared), FP64 to the paper's energy criterion 1e-14."""
+    O.set_threads(16)
+    work = [inputs.workload_vortex_2d(seed=2602 + i) for i in range(4)]
+    opt = gs.default_options(precision=gs.GS_FP64, tol=1e-14)
+    outs = [torch.empty((3,) + pb.shape, dtype=torch.complex128, device=DEV) for pb, _ in work]
+    res = gpu_ctx.batch_solve([(pb, torch.from_numpy(p0).to(DEV), o, opt, None)
+                               for (pb, p0), o in zip(work, outs)])
+    torch.cuda.synchronize()
+    for (pb, _), o, r in zip(work, outs, res):
+        assert r["rc"] == gs.GS_OK, r
+        ev = _check_against_oracle(pb, o.cpu().numpy(), r)
+        assert ev["e_soc"] <= 0.0
+        assert abs(ev["virial"]) < 1e-6
+        assert r["resid_inf"] < 1e-6
+
+
+def test_cm3d_128_state_matches_oracle(gpu_ctx):
+    """The 128^3 anisotropic rotating solve by three-level cascadic multigrid."""
+    O.set_threads(16)
+    pb, _ = inputs.workload_aniso_3d(n=128)
+    pc = inputs.Problem(dim=3, n=(32, 32, 32), L=pb.L, g=pb.g, omega=pb.omega, gamma=pb.gamma, c0=pb.c0, c1=pb.c1)
+    g0 = torch.from_numpy(inputs.initial_guess(pc, ("a", "a", "a"))).to(DEV)
+    out = torch.empty((3,) + pb.shape, dtype=torch.complex128, device=DEV)
+    opt = gs.default_options(precision=gs.GS_FP64, stop_kind=gs.GS_STOP_RESIDUAL, tol=1e-9, cm_levels=3)
+    r = gpu_ctx.solve_device(pb, g0, out, options=opt)
+    torch.cuda.synchronize()
+    assert r["rc"] == gs.GS_OK, r
+    assert r["iters_coarse"] > 0
+    ev = _check_against_oracle(pb, out.cpu().numpy(), r)
+    assert ev["e_soc"] <= 0.0
+    assert abs(ev["virial"]) < 1e-6
+    assert ev["resid_inf"] < 1e-9 * 1.01

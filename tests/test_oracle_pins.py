@@ -417,6 +417,21 @@ def test_table1_spatial_accuracy(case):
     assert abs(evs[2]["virial"]) < 1e-9
 
 
+def test_example2_iteration_count():
+    """Example 2: Algorithm 1 converges on Case 2 at N = 128 in 323 iterations
+    (residual 1e-12). The paper does not give the guess, so this is a soft pin
+    on the efficiency of the iteration (preconditioner, PRP beta, step size):
+    from the Gaussian guess the count must be within a factor 2 of 323."""
+    gd = _golden("example2_iterations.json")
+    L, N = gd["domain_half_width"], gd["n"]
+    pb = inputs.Problem(dim=2, n=(N, N), L=(L, L), omega=gd["omega"], gamma=gd["gamma"], c0=gd["c0"], c1=gd["c1"])
+    g, t, p = orc(pb)
+    r = O.pcg(g, t, p, inputs.initial_guess(pb, ("a", "a", "a")),
+              O.Options(stop_kind=O.STOP_RESIDUAL, tol=gd["tol"], max_iter=5000))
+    assert r.status == 0
+    assert gd["iterations"] / 2 <= r.iters <= 2 * gd["iterations"], r.iters
+
+
 @pytest.mark.slow
 def test_table2_lowest_energy_omega_06():
     """Table 2 (Example 3): E = 2.2833 for Omega = 0.6 from guess (b) in every
