@@ -107,6 +107,12 @@ typedef struct {
     int cm_levels;        /* cascadic multigrid (Algorithm 3): solve on grids n/2^(L-1), ..., n/2, n
                              (every n[a]/2^(L-1) >= 16), each level warm-started from the
                              interpolated result of the previous one; 1 = plain PCG */
+    int dir_precision;    /* precision of the search direction, of its preconditioning (3.15) and of
+                             H_L applied to it while Phi, H_L Phi and the residuals are double
+                             (GS_FP64 solves and the double phase of GS_MIXED): GS_FP64 (default)
+                             or GS_FP32. Every reduction stays double; the line search and the
+                             stopping tests act on double quantities, so the limit is the same
+                             and only the path to it changes. */
 } gs_options;
 
 /* Results; quantities refer to the returned Phi. */
@@ -150,11 +156,13 @@ int gs_create(gs_ctx** out, int device);
 void gs_destroy(gs_ctx* ctx);
 /* Fill *o with the defaults: energy criterion, tol 1e-12, max_iter 100000,
  * FP64, switch_resid 1e-6, fp32_max_iter 20000, stall_window 50,
- * theta_trial 0.1, sigma 0.5, max_backtrack 40, check_every 32, cm_levels 1. */
+ * theta_trial 0.1, sigma 0.5, max_backtrack 40, check_every 32, cm_levels 1,
+ * dir_precision GS_FP64. */
 void gs_default_options(gs_options* o);
-/* Device bytes a solve of this grid needs at this precision (GS_MIXED counts
- * both the float and the double working sets). 0 for an invalid grid. */
-size_t gs_footprint_bytes(const gs_grid* g, int precision);
+/* Device bytes a solve of this grid needs with these options (GS_MIXED counts
+ * both the float and the double working sets; dir_precision GS_FP32 halves the
+ * direction fields of the double one). 0 for an invalid grid or options. */
+size_t gs_footprint_bytes(const gs_grid* g, const gs_options* o);
 
 /* Device-memory budget for solve slots (bytes; 0 = 90% of what is free plus
  * what the context holds). A request is admitted when the footprints

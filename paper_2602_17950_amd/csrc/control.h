@@ -147,9 +147,27 @@ __device__ inline void ctrl_dir(SolveState* st, const Phys& p, const double (&s)
 constexpr int NS_LS = 43;
 constexpr int NS_KIN = 9;
 
-__device__ __forceinline__ double dE_at(double c, double s, double CmA, double B, const double* I) {
-    return s * s * CmA + 2.0 * c * s * B + 2.0 * s * s * I[1] + 4.0 * c * s * I[0] + s * s * s * s * I[4] +
-           4.0 * c * s * s * s * I[3] + 4.0 * c * c * s * s * I[2];
+// Energy change along the normalised curve (c Phi + s P^)/|c Phi + s P^|, formed
+// without subtracting two energies. With N = |Phi|^2, X = Re<Phi,P^>, Y = |P^|^2
+// and n = c^2 N + 2cs X + s^2 Y (so n - N = 2cs X + s^2 (Y - N)), the quadratic
+// part is (N L(t) - A n)/(N n) = (2cs (N B - A X) + s^2 (N C - A Y))/(N n) and the
+// quartic part (N^2 (D(t) - D0) - D0 (n - N)(n + N))/(N n)^2, D(t) - D0 being the
+// polynomial in I01..I22. For a unit P^ orthogonal to Phi (N = Y = 1, X = 0) this
+// is the plain expansion; a direction rounded to float is neither, to its
+// rounding, and the X and Y - N terms keep that rounding (a spurious first-order
+// term A X) out of the descent test.
+struct LsPoly {
+    double N, A, B, C, X, Y, D0, I[5];
+};
+__device__ __forceinline__ double dE_at(double c, double s, const LsPoly& k) {
+    const double cs2 = 2.0 * c * s, ss = s * s;
+    const double n = c * c * k.N + cs2 * k.X + ss * k.Y;
+    const double dn = cs2 * k.X + ss * (k.Y - k.N);
+    const double dL = cs2 * (k.N * k.B - k.A * k.X) + ss * (k.N * k.C - k.A * k.Y);
+    const double dD = 2.0 * ss * k.I[1] + 2.0 * cs2 * k.I[0] + ss * ss * k.I[4] + 2.0 * cs2 * ss * k.I[3] +
+                      cs2 * cs2 * k.I[2];
+    const double Nn = k.N * n;
+    return dL / Nn + (k.N * k.N * dD - k.D0 * dn * (n + k.N)) / (Nn * Nn);
 }
 
 __device__ inline void ctrl_ls(SolveState* st, const Phys& p, const double (&s)[NS_LS], const double (&kin)[NS_KIN]) {
@@ -157,9 +175,10 @@ __device__ inline void ctrl_ls(SolveState* st, const Phys& p, const double (&s)[
     const double Cq = s[0] * h, B = s[1] * h, PhPh = s[2] * h, phiPh = s[3] * h;
     const double I[5] = {s[4] * h, s[5] * h, s[6] * h, s[7] * h, s[8] * h};
     const double I00 = s[9] * h;
-    const double CmA = Cq - st->lin;
-    const double a = CmA + 2.0 * I[1] + 4.0 * I[2];
-    const double b = 2.0 * B + 4.0 * I[0];
+    const LsPoly K{st->norm2, st->lin, B, Cq, phiPh, PhPh, I00, {I[0], I[1], I[2], I[3], I[4]}};
+    // second-order model (3.7)-(3.8), the direction's Phi component and norm error removed
+    const double a = (Cq - st->lin * PhPh) + 2.0 * I[1] + 4.0 * I[2];
+    const double b = 2.0 * (B - st->lin * phiPh) + 4.0 * (I[0] - I00 * phiPh);
     st->a = a;
     st->b = b;
     double theta = (a > 0.0 && b < 0.0) ? -b / (2.0 * a) : st->theta_trial;
@@ -168,7 +187,7 @@ __device__ inline void ctrl_ls(SolveState* st, const Phys& p, const double (&s)[
     for (int k = 0; k <= st->max_backtrack; ++k) {
         c = cos(theta);
         sn = sin(theta);
-        dE = dE_at(c, sn, CmA, B, I);
+        dE = dE_at(c, sn, K);
         if (dE < 0.0) { accepted = 1; break; }   // the energy decreases
         theta *= st->sigma;
         st->backtracks++;

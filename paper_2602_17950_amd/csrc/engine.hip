@@ -73,46 +73,54 @@ static int check_options(const gs_options* o) {
     if (o->max_backtrack < 0) return fail(GS_EINVAL, "options.max_backtrack must be >= 0");
     if (o->check_every < 1) return fail(GS_EINVAL, "options.check_every must be >= 1");
     if (o->cm_levels < 1 || o->cm_levels > 7) return fail(GS_EINVAL, "options.cm_levels must be in [1, 7]");
+    if (o->dir_precision != GS_FP64 && o->dir_precision != GS_FP32)
+        return fail(GS_EINVAL, "options.dir_precision must be GS_FP64 or GS_FP32");
     return GS_OK;
 }
 
 // slots per class (bounded by the launch grid's y extent and the state arrays)
 constexpr int CLASS_CAP = 4096;
 
-// rows of per-block partial sums of the reducing passes
-template <typename R> static RedGeom red_geom(const gs_grid* g) {
+// rows of per-block partial sums of the reducing passes (the preconditioner's
+// last pass runs in the direction type RD)
+template <typename RD> static RedGeom red_geom(const gs_grid* g) {
     RedGeom r;
     const long long M = npts(g);
     const int Nlast = g->n[g->dim - 1];
     r.nblk_mid = mid_blocks(Nlast, (int)(M / Nlast));
     r.nblk_pw = pw_blocks(M);
-    r.nblk_dir = g->dim == 2 ? invT_pre_blocks<R>(g->n[0], 1, g->n[1]) : invT_pre_blocks<R>(g->n[0], g->n[2], g->n[1]);
+    r.nblk_dir = g->dim == 2 ? invT_pre_blocks<RD>(g->n[0], 1, g->n[1]) : invT_pre_blocks<RD>(g->n[0], g->n[2], g->n[1]);
     return r;
 }
 
 static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// buffers of the state type (the others are of the direction type; scratch
+// fields are sized for the state type, the wider of the two)
+static bool state_buf(int b) { return b == B_PHI || b == B_HL || b == B_R0 || b == B_R1 || b >= B_T6A; }
+
 // Device memory of one slot: 12 three-component fields (Phi, H_L Phi, r^n,
 // r^{n-1}, Pr, P, H_L P^, u, four scratch), two six-component scratch fields,
 // the P_V^{1/2} factors and the partial-sum rows.
-template <typename R> static size_t slot_buffer_bytes(const gs_grid* g) {
+template <typename RS, typename RD> static size_t slot_buffer_bytes(const gs_grid* g) {
     const long long M = npts(g);
-    const RedGeom rg = red_geom<R>(g);
-    const size_t field = al256((size_t)3 * M * sizeof(cpx<R>));
-    return field * 16 + al256((size_t)3 * M * sizeof(R)) + al256((size_t)rg.nblk_pw * NS_MAX * sizeof(double)) +
+    const RedGeom rg = red_geom<RD>(g);
+    const size_t fs = al256((size_t)3 * M * sizeof(cpx<RS>)), fd = al256((size_t)3 * M * sizeof(cpx<RD>));
+    size_t b = 0;
+    for (int k = 0; k < B_X0; ++k) b += (k == B_T6A || k == B_T6B ? 2 : 1) * (state_buf(k) ? fs : fd);
+    return b + al256((size_t)3 * M * sizeof(RD)) + al256((size_t)rg.nblk_pw * NS_MAX * sizeof(double)) +
            al256((size_t)rg.nblk_mid * RED_MID_STRIDE * sizeof(double)) +
            al256((size_t)rg.nblk_dir * RED_DIR_STRIDE * sizeof(double));
 }
-template <typename R> static size_t slot_bytes(const gs_grid* g) {
-    return slot_buffer_bytes<R>(g) + sizeof(SolveState) + sizeof(Slot<R>);
+template <typename RS, typename RD> static size_t slot_bytes(const gs_grid* g) {
+    return slot_buffer_bytes<RS, RD>(g) + sizeof(SolveState) + sizeof(Slot);
 }
 
-template <typename R>
 struct SlotMem {
     void* base = nullptr;
     size_t bytes = 0;
-    cpx<R>* buf[NBUF] = {};
-    R* pv = nullptr;
+    void* buf[NBUF] = {};
+    void* pv = nullptr;
     double* red_pw = nullptr;
     double* red_mid = nullptr;
     double* red_dir = nullptr;
@@ -121,12 +129,12 @@ struct SlotMem {
     }
 };
 
-template <typename R>
-static int alloc_slot_mem(const gs_grid* g, hipStream_t s, std::unique_ptr<SlotMem<R>>& out) {
-    auto m = std::make_unique<SlotMem<R>>();
+template <typename RS, typename RD>
+static int alloc_slot_mem(const gs_grid* g, hipStream_t s, std::unique_ptr<SlotMem>& out) {
+    auto m = std::make_unique<SlotMem>();
     const long long M = npts(g);
-    const size_t field = al256((size_t)3 * M * sizeof(cpx<R>));
-    m->bytes = slot_buffer_bytes<R>(g);
+    const size_t fs = al256((size_t)3 * M * sizeof(cpx<RS>)), fd = al256((size_t)3 * M * sizeof(cpx<RD>));
+    m->bytes = slot_buffer_bytes<RS, RD>(g);
     if (hipMalloc(&m->base, m->bytes) != hipSuccess) {
         m->base = nullptr;
         (void)hipGetLastError();   // do not leave the failure to the next launch check
@@ -134,12 +142,12 @@ static int alloc_slot_mem(const gs_grid* g, hipStream_t s, std::unique_ptr<SlotM
     }
     char* p = (char*)m->base;
     for (int b = 0; b < B_X0; ++b) {
-        m->buf[b] = (cpx<R>*)p;
-        p += (b == B_T6A || b == B_T6B) ? 2 * field : field;
+        m->buf[b] = p;
+        p += (b == B_T6A || b == B_T6B ? 2 : 1) * (state_buf(b) ? fs : fd);
     }
-    m->pv = (R*)p;
-    p += al256((size_t)3 * M * sizeof(R));
-    const RedGeom rg = red_geom<R>(g);
+    m->pv = p;
+    p += al256((size_t)3 * M * sizeof(RD));
+    const RedGeom rg = red_geom<RD>(g);
     m->red_pw = (double*)p;
     p += al256((size_t)rg.nblk_pw * NS_MAX * sizeof(double));
     m->red_mid = (double*)p;
@@ -318,115 +326,116 @@ static void fill_result(const SolveState* h, gs_result* r, int iters_fp32, doubl
 // ---------------------------------------------------------------------------
 // operator chains over a launch set of slots
 // ---------------------------------------------------------------------------
-template <typename R>
+template <typename RS, typename RD>
 struct Geo {
     int dim = 2, n[3] = {1, 1, 1};
     long long M = 0;
     RedGeom g{};
-    const cpx<R>* tw[3] = {};
+    const cpx<RS>* tws[3] = {};   // twiddles of the state-type transforms
+    const cpx<RD>* twd[3] = {};   // and of the direction-type ones
     int rot_any = 0;
 };
-template <typename R>
 struct Sub {
-    const Slot<R>* tab;
+    const Slot* tab;
     int ns;
 };
 
-// out = H_L in  (H_L = -1/2 Lap + V - Omega L_z - gamma S), with the prologue
-// `pro` applied to `in` first (see launch_fwdT). dual (with PRO_DIR): aux1 (Phi)
-// is transformed with in, and the middle pass reduces the kinetic coefficients
-// of both for the next iterate's alpha_l.
-template <typename R>
-static hipError_t chain_HL(const Geo<R>& G, Sub<R> L, int pro, int dual, int in, int out, int aux0, int aux1,
-                           int use_invnP, hipStream_t s, Timer* tm) {
-    const int rot = G.rot_any;
-    const int Nx = G.n[0], Ny = G.n[1], Nz = G.n[2];
-    const double F = 3.0 * G.M * sizeof(cpx<R>) * L.ns;
-    const double b_fwd = dual ? 6 * F : (pro == PRO_DIR ? 5 * F : (pro == PRO_UPDATE ? 4 * F : 2 * F));
+// out = H_L in  (H_L = -1/2 Lap + V - Omega L_z - gamma S), transforms in type R,
+// with the prologue `pro` applied to `in` first (see launch_fwdT; the operand
+// of the other type RX is aux0 for PRO_UPDATE, aux1 for PRO_DIR). dual (with
+// PRO_DIR): aux1 (Phi) is transformed with in, and the middle pass reduces the
+// kinetic coefficients of both for the next iterate's alpha_l.
+template <typename R, typename RX>
+static hipError_t chain_HL(int dim, const int n[3], long long M, int rot, const cpx<R>* const tw[3], Sub L, int pro,
+                           int dual, int in, int out, int aux0, int aux1, int use_invnP, hipStream_t s, Timer* tm) {
+    const int Nx = n[0], Ny = n[1], Nz = n[2];
+    const double F = 3.0 * M * sizeof(cpx<R>) * L.ns, Fx = 3.0 * M * sizeof(cpx<RX>) * L.ns;
+    const double b_fwd = dual ? 5 * F + Fx : (pro == PRO_DIR ? 4 * F + Fx : (pro == PRO_UPDATE ? 3 * F + Fx : 2 * F));
     const double b_mid = (rot ? 2 : 1) * F + (dual ? 2 : 1) * F, b_inv = (rot ? 4 : 3) * F;
     const int midop = dual ? MID_HLX : MID_HL;
     const int outB = rot ? B_T1 : B_NONE;
     hipError_t e;
-    if (G.dim == 2) {
-        if ((e = timed_ns(tm, KK_HL_FWD, b_fwd, L.ns, s, [&] { return launch_fwdT<R>(Nx, pro, dual, L.tab, L.ns, in, B_T6A, aux0, aux1, 1, Ny, 3, G.tw[0], s); }))) return e;
-        if ((e = timed_ns(tm, KK_HL_MID, b_mid, L.ns, s, [&] { return launch_mid<R>(Ny, midop, L.tab, L.ns, B_T6A, B_T0, outB, Nx, rot, G.tw[1], s); }))) return e;
+    if (dim == 2) {
+        if ((e = timed_ns(tm, KK_HL_FWD, b_fwd, L.ns, s, [&] { return launch_fwdT<R, RX>(Nx, pro, dual, L.tab, L.ns, in, B_T6A, aux0, aux1, 1, Ny, 3, tw[0], s); }))) return e;
+        if ((e = timed_ns(tm, KK_HL_MID, b_mid, L.ns, s, [&] { return launch_mid<R>(Ny, midop, L.tab, L.ns, B_T6A, B_T0, outB, Nx, rot, tw[1], s); }))) return e;
         return timed_ns(tm, KK_HL_INV, b_inv, L.ns, s, [&] {
-            return launch_invT<R>(Nx, EPI_HL, L.tab, L.ns, B_T0, B_T1, out, B_NONE, in, 1, Ny, 1.0, use_invnP, rot, G.tw[0], s); });
+            return launch_invT<R>(Nx, EPI_HL, L.tab, L.ns, B_T0, B_T1, out, B_NONE, in, 1, Ny, 1.0, use_invnP, rot, tw[0], s); });
     }
     const int nc = dual ? 6 : 3;
-    if ((e = timed_ns(tm, KK_HL_FWD, b_fwd, L.ns, s, [&] { return launch_fwdT<R>(Nx, pro, dual, L.tab, L.ns, in, B_T6A, aux0, aux1, Nz, Ny, 3, G.tw[0], s); }))) return e;
-    if ((e = timed_ns(tm, KK_HL_FWD2, 2 * (nc / 3) * F, L.ns, s, [&] { return launch_fwdT<R>(Ny, PRO_PLAIN, 0, L.tab, L.ns, B_T6A, B_T6B, B_NONE, B_NONE, Nx, Nz, nc, G.tw[1], s); }))) return e;
-    if ((e = timed_ns(tm, KK_HL_MID, b_mid, L.ns, s, [&] { return launch_mid<R>(Nz, midop, L.tab, L.ns, B_T6B, B_T0, outB, Ny * Nx, rot, G.tw[2], s); }))) return e;
+    if ((e = timed_ns(tm, KK_HL_FWD, b_fwd, L.ns, s, [&] { return launch_fwdT<R, RX>(Nx, pro, dual, L.tab, L.ns, in, B_T6A, aux0, aux1, Nz, Ny, 3, tw[0], s); }))) return e;
+    if ((e = timed_ns(tm, KK_HL_FWD2, 2 * (nc / 3) * F, L.ns, s, [&] { return launch_fwdT<R, RX>(Ny, PRO_PLAIN, 0, L.tab, L.ns, B_T6A, B_T6B, B_NONE, B_NONE, Nx, Nz, nc, tw[1], s); }))) return e;
+    if ((e = timed_ns(tm, KK_HL_MID, b_mid, L.ns, s, [&] { return launch_mid<R>(Nz, midop, L.tab, L.ns, B_T6B, B_T0, outB, Ny * Nx, rot, tw[2], s); }))) return e;
     if ((e = timed_ns(tm, KK_HL_INV2, (rot ? 5 : 2) * F, L.ns, s, [&] {
              return launch_invT<R>(Ny, rot ? EPI_ROTX : EPI_SCALE, L.tab, L.ns, B_T0, B_T1, B_T2, rot ? B_T3 : B_NONE,
-                                   B_T6A, Nx, Nz, 1.0, 0, rot, G.tw[1], s); }))) return e;
+                                   B_T6A, Nx, Nz, 1.0, 0, rot, tw[1], s); }))) return e;
     return timed_ns(tm, KK_HL_INV, b_inv, L.ns, s, [&] {
-        return launch_invT<R>(Nx, EPI_HL, L.tab, L.ns, B_T2, B_T3, out, B_NONE, in, Nz, Ny, 1.0, use_invnP, rot, G.tw[0], s); });
+        return launch_invT<R>(Nx, EPI_HL, L.tab, L.ns, B_T2, B_T3, out, B_NONE, in, Nz, Ny, 1.0, use_invnP, rot, tw[0], s); });
 }
 
-// out = P_V^{1/2} P_Delta P_V^{1/2} r (the first factor is already applied: input in u);
-// dir = 1 fuses the direction reductions and control into the last pass
-template <typename R>
-static hipError_t chain_pre(const Geo<R>& G, Sub<R> L, int dir, int out, hipStream_t s, Timer* tm) {
+// out = P_V^{1/2} P_Delta P_V^{1/2} r in the direction type RD (the first factor
+// is already applied: input in u); dir = 1 fuses the partial sums of the
+// direction scalars into the last pass
+template <typename RS, typename RD>
+static hipError_t chain_pre(const Geo<RS, RD>& G, Sub L, int dir, int out, hipStream_t s, Timer* tm) {
     const int Nx = G.n[0], Ny = G.n[1], Nz = G.n[2];
-    const double F = 3.0 * G.M * sizeof(cpx<R>) * L.ns, Fr = 3.0 * G.M * sizeof(R) * L.ns;
-    const double b_inv = (dir ? 6 : 2) * F + Fr;
+    const double F = 3.0 * G.M * sizeof(cpx<RD>) * L.ns, Fr = 3.0 * G.M * sizeof(RD) * L.ns;
+    const double Fs = 3.0 * G.M * sizeof(cpx<RS>) * L.ns;
+    const double b_inv = (dir ? 3 * F + 3 * Fs : 2 * F) + Fr;
     hipError_t e;
     if (G.dim == 2) {
-        if ((e = timed_ns(tm, KK_PRE_FWD, 2 * F, L.ns, s, [&] { return launch_fwdT<R>(Nx, PRO_PLAIN, 0, L.tab, L.ns, B_U, B_T6A, B_NONE, B_NONE, 1, Ny, 3, G.tw[0], s); }))) return e;
-        if ((e = timed_ns(tm, KK_PRE_MID, 2 * F, L.ns, s, [&] { return launch_mid<R>(Ny, MID_PRE, L.tab, L.ns, B_T6A, B_T0, B_NONE, Nx, 0, G.tw[1], s); }))) return e;
+        if ((e = timed_ns(tm, KK_PRE_FWD, 2 * F, L.ns, s, [&] { return launch_fwdT<RD, RD>(Nx, PRO_PLAIN, 0, L.tab, L.ns, B_U, B_T6A, B_NONE, B_NONE, 1, Ny, 3, G.twd[0], s); }))) return e;
+        if ((e = timed_ns(tm, KK_PRE_MID, 2 * F, L.ns, s, [&] { return launch_mid<RD>(Ny, MID_PRE, L.tab, L.ns, B_T6A, B_T0, B_NONE, Nx, 0, G.twd[1], s); }))) return e;
         return timed_ns(tm, KK_PRE_INV, b_inv, L.ns, s, [&] {
-            return launch_invT_pre<R>(Nx, L.tab, L.ns, B_T0, out, 1, Ny, dir, G.tw[0], s); });
+            return launch_invT_pre<RD, RS>(Nx, L.tab, L.ns, B_T0, out, 1, Ny, dir, G.twd[0], s); });
     }
-    if ((e = timed_ns(tm, KK_PRE_FWD, 2 * F, L.ns, s, [&] { return launch_fwdT<R>(Nx, PRO_PLAIN, 0, L.tab, L.ns, B_U, B_T6A, B_NONE, B_NONE, Nz, Ny, 3, G.tw[0], s); }))) return e;
-    if ((e = launch_fwdT<R>(Ny, PRO_PLAIN, 0, L.tab, L.ns, B_T6A, B_T6B, B_NONE, B_NONE, Nx, Nz, 3, G.tw[1], s))) return e;
-    if ((e = timed_ns(tm, KK_PRE_MID, 2 * F, L.ns, s, [&] { return launch_mid<R>(Nz, MID_PRE, L.tab, L.ns, B_T6B, B_T0, B_NONE, Ny * Nx, 0, G.tw[2], s); }))) return e;
-    if ((e = launch_invT<R>(Ny, EPI_SCALE, L.tab, L.ns, B_T0, B_NONE, B_T1, B_NONE, B_NONE, Nx, Nz, 1.0, 0, 0, G.tw[1], s))) return e;
+    if ((e = timed_ns(tm, KK_PRE_FWD, 2 * F, L.ns, s, [&] { return launch_fwdT<RD, RD>(Nx, PRO_PLAIN, 0, L.tab, L.ns, B_U, B_T6A, B_NONE, B_NONE, Nz, Ny, 3, G.twd[0], s); }))) return e;
+    if ((e = launch_fwdT<RD, RD>(Ny, PRO_PLAIN, 0, L.tab, L.ns, B_T6A, B_T6B, B_NONE, B_NONE, Nx, Nz, 3, G.twd[1], s))) return e;
+    if ((e = timed_ns(tm, KK_PRE_MID, 2 * F, L.ns, s, [&] { return launch_mid<RD>(Nz, MID_PRE, L.tab, L.ns, B_T6B, B_T0, B_NONE, Ny * Nx, 0, G.twd[2], s); }))) return e;
+    if ((e = launch_invT<RD>(Ny, EPI_SCALE, L.tab, L.ns, B_T0, B_NONE, B_T1, B_NONE, B_NONE, Nx, Nz, 1.0, 0, 0, G.twd[1], s))) return e;
     return timed_ns(tm, KK_PRE_INV, b_inv, L.ns, s, [&] {
-        return launch_invT_pre<R>(Nx, L.tab, L.ns, B_T1, out, Nz, Ny, dir, G.tw[0], s); });
+        return launch_invT_pre<RD, RS>(Nx, L.tab, L.ns, B_T1, out, Nz, Ny, dir, G.twd[0], s); });
 }
 
-// Fresh evaluation of the current iterate: apply a pending update to Phi,
-// H_L Phi from scratch, energy parts, mu, alpha_l.
 // bytes of partial-sum rows a control step reads
-template <typename R> static double fin_bytes(const Geo<R>& G, int what, int ns) {
+static double fin_bytes(const RedGeom& g, int what, int ns) {
     double rows = 0.0;
     switch (what) {
-    case FIN_EVAL: rows = (double)G.g.nblk_pw * NS_EVAL + (double)G.g.nblk_mid * 4; break;
-    case FIN_DIR: rows = (double)G.g.nblk_pw * NS_RES + (double)G.g.nblk_dir * NS_DIR; break;
-    case FIN_LS: rows = (double)G.g.nblk_pw * NS_LS + (double)G.g.nblk_mid * NS_KIN; break;
-    default: rows = (double)G.g.nblk_pw * NS_RES; break;
+    case FIN_EVAL: rows = (double)g.nblk_pw * NS_EVAL + (double)g.nblk_mid * 4; break;
+    case FIN_DIR: rows = (double)g.nblk_pw * NS_RES + (double)g.nblk_dir * NS_DIR; break;
+    case FIN_LS: rows = (double)g.nblk_pw * NS_LS + (double)g.nblk_mid * NS_KIN; break;
+    default: rows = (double)g.nblk_pw * NS_RES; break;
     }
     return rows * sizeof(double) * ns;
 }
-template <typename R>
-static hipError_t fin(const Geo<R>& G, Sub<R> L, int what, hipStream_t s, Timer* tm) {
-    return timed_ns(tm, KK_CTRL, fin_bytes<R>(G, what, L.ns), L.ns, s, [&] { return launch_fin<R>(L.tab, L.ns, G.g, what, s); });
+static hipError_t fin(const RedGeom& g, Sub L, int what, hipStream_t s, Timer* tm) {
+    return timed_ns(tm, KK_CTRL, fin_bytes(g, what, L.ns), L.ns, s, [&] { return launch_fin(L.tab, L.ns, g, what, s); });
 }
 
-template <typename R>
-static hipError_t refresh(const Geo<R>& G, Sub<R> L, hipStream_t s, Timer* tm) {
-    const double F = 3.0 * G.M * sizeof(cpx<R>) * L.ns;
+// Fresh evaluation of the current iterate, in the state type: apply a pending
+// update to Phi, H_L Phi from scratch, energy parts, mu, alpha_l.
+template <typename RS, typename RD>
+static hipError_t refresh(const Geo<RS, RD>& G, Sub L, hipStream_t s, Timer* tm) {
+    const double Fs = 3.0 * G.M * sizeof(cpx<RS>) * L.ns;
     hipError_t e;
-    if ((e = chain_HL<R>(G, L, PRO_UPDATE, 0, B_PHI, B_HL, B_P, B_NONE, 0, s, tm))) return e;
-    if ((e = timed_ns(tm, KK_EVAL, 2 * F, L.ns, s, [&] { return launch_eval<R>(L.tab, L.ns, G.g, s); }))) return e;
-    return fin<R>(G, L, FIN_EVAL, s, tm);
+    if ((e = chain_HL<RS, RD>(G.dim, G.n, G.M, G.rot_any, G.tws, L, PRO_UPDATE, 0, B_PHI, B_HL, B_P, B_NONE, 0, s, tm))) return e;
+    if ((e = timed_ns(tm, KK_EVAL, 2 * Fs, L.ns, s, [&] { return launch_eval<RS>(L.tab, L.ns, G.g, s); }))) return e;
+    return fin(G.g, L, FIN_EVAL, s, tm);
 }
 
 // normalisation of Phi (applied as a pending rescale by the next pass)
-template <typename R>
-static hipError_t normalize(const Geo<R>& G, Sub<R> L, hipStream_t s) {
+template <typename RS, typename RD>
+static hipError_t normalize(const Geo<RS, RD>& G, Sub L, hipStream_t s) {
     hipError_t e;
-    if ((e = launch_normalize<R>(L.tab, L.ns, G.g, s))) return e;
-    return fin<R>(G, L, FIN_NORM, s, nullptr);
+    if ((e = launch_normalize<RS>(L.tab, L.ns, G.g, s))) return e;
+    return fin(G.g, L, FIN_NORM, s, nullptr);
 }
 
 // residual norm of the current iterate (after a refresh)
-template <typename R>
-static hipError_t resid_final(const Geo<R>& G, Sub<R> L, hipStream_t s) {
+template <typename RS, typename RD>
+static hipError_t resid_final(const Geo<RS, RD>& G, Sub L, hipStream_t s) {
     hipError_t e;
-    if ((e = launch_resid<R>(L.tab, L.ns, G.g, 1, s))) return e;
-    return fin<R>(G, L, FIN_RFINAL, s, nullptr);
+    if ((e = launch_resid<RS, RD>(L.tab, L.ns, G.g, 1, s))) return e;
+    return fin(G.g, L, FIN_RFINAL, s, nullptr);
 }
 
 // One PCG iteration (Algorithm 1 with Algorithm 2), entirely on the device:
@@ -440,23 +449,26 @@ static hipError_t resid_final(const Geo<R>& G, Sub<R> L, hipStream_t s) {
 //      alongside for the kinetic coefficients)
 //   4. energy along the retraction; control: step size, backtracking, and the
 //      scalars (mu, E, alpha_l) of the next iterate
-template <typename R>
-static hipError_t iterate(const Geo<R>& G, Sub<R> L, int do_refresh, hipStream_t s, Timer* tm) {
-    const double F = 3.0 * G.M * sizeof(cpx<R>) * L.ns, Fr = 3.0 * G.M * sizeof(R) * L.ns;
+// Steps 2 and 3 run in the direction type RD, the rest in the state type RS;
+// every reduction and scalar is double.
+template <typename RS, typename RD>
+static hipError_t iterate(const Geo<RS, RD>& G, Sub L, int do_refresh, hipStream_t s, Timer* tm) {
+    const double Fs = 3.0 * G.M * sizeof(cpx<RS>) * L.ns, Fd = 3.0 * G.M * sizeof(cpx<RD>) * L.ns;
+    const double Frd = 3.0 * G.M * sizeof(RD) * L.ns;
     hipError_t e;
     if (do_refresh) {
         if (tm) tm->chain = 0;
-        if ((e = refresh<R>(G, L, s, tm))) return e;
+        if ((e = refresh<RS, RD>(G, L, s, tm))) return e;
     }
     if (tm) tm->chain = 1;
-    if ((e = timed_ns(tm, KK_RESID, 8 * F + Fr, L.ns, s, [&] { return launch_resid<R>(L.tab, L.ns, G.g, 0, s); }))) return e;
+    if ((e = timed_ns(tm, KK_RESID, 5 * Fs + 3 * Fd + Frd, L.ns, s, [&] { return launch_resid<RS, RD>(L.tab, L.ns, G.g, 0, s); }))) return e;
     if (tm) tm->chain = 2;
-    if ((e = chain_pre<R>(G, L, 1, B_PR, s, tm))) return e;
-    if ((e = fin<R>(G, L, FIN_DIR, s, tm))) return e;
+    if ((e = chain_pre<RS, RD>(G, L, 1, B_PR, s, tm))) return e;
+    if ((e = fin(G.g, L, FIN_DIR, s, tm))) return e;
     if (tm) tm->chain = 3;
-    if ((e = chain_HL<R>(G, L, PRO_DIR, 1, B_P, B_HLP, B_PR, B_PHI, 1, s, tm))) return e;
-    if ((e = timed_ns(tm, KK_LSRED, 4 * F, L.ns, s, [&] { return launch_lsred<R>(L.tab, L.ns, G.g, s); }))) return e;
-    return fin<R>(G, L, FIN_LS, s, tm);
+    if ((e = chain_HL<RD, RS>(G.dim, G.n, G.M, G.rot_any, G.twd, L, PRO_DIR, 1, B_P, B_HLP, B_PR, B_PHI, 1, s, tm))) return e;
+    if ((e = timed_ns(tm, KK_LSRED, 2 * Fs + 2 * Fd, L.ns, s, [&] { return launch_lsred<RS, RD>(L.tab, L.ns, G.g, s); }))) return e;
+    return fin(G.g, L, FIN_LS, s, tm);
 }
 
 // ---------------------------------------------------------------------------
@@ -502,21 +514,22 @@ struct Job {
     }
 };
 
-template <typename R>
+template <typename RS, typename RD>
 struct Class {
     gs_grid grid{};
     int check_every = 0;
     long long M = 0;
     RedGeom g{};
-    const cpx<R>* tw[3] = {};
+    const cpx<RS>* tws[3] = {};
+    const cpx<RD>* twd[3] = {};
     hipStream_t stream = nullptr;
     hipEvent_t ev = nullptr;
     SolveState* d_st = nullptr;
     SolveState* h_st = nullptr;     // pinned mirror
-    Slot<R>* d_tab = nullptr;
-    Slot<R>* h_tab = nullptr;       // pinned
-    std::vector<std::unique_ptr<SlotMem<R>>> mem;   // by slot id
-    std::vector<Job*> owner;                         // by slot id
+    Slot* d_tab = nullptr;
+    Slot* h_tab = nullptr;          // pinned
+    std::vector<std::unique_ptr<SlotMem>> mem;   // by slot id
+    std::vector<Job*> owner;                      // by slot id
     std::vector<int> run, fin, iter0;
     std::deque<Job*> queue;
     bool inflight = false;
@@ -534,18 +547,18 @@ struct Class {
     }
 };
 
-// single-slot plan of the operator-level entry points
+// single-slot plan of the operator-level entry points (one precision)
 template <typename R>
 struct OpPlan {
     gs_grid grid{};
     long long M = 0;
     RedGeom g{};
     const cpx<R>* tw[3] = {};
-    std::unique_ptr<SlotMem<R>> mem;
+    std::unique_ptr<SlotMem> mem;
     SolveState* d_st = nullptr;
     SolveState* h_st = nullptr;
-    Slot<R>* d_tab = nullptr;
-    Slot<R>* h_tab = nullptr;
+    Slot* d_tab = nullptr;
+    Slot* h_tab = nullptr;
     ~OpPlan() {
         mem.reset();
         if (d_st) (void)hipFree(d_st);
@@ -560,8 +573,9 @@ using GridKey = std::tuple<int, int, int, int>;
 
 struct Ctx {
     int device = 0;
-    std::map<ClassKey, std::unique_ptr<Class<double>>> c64;
-    std::map<ClassKey, std::unique_ptr<Class<float>>> c32;
+    std::map<ClassKey, std::unique_ptr<Class<double, double>>> c64;
+    std::map<ClassKey, std::unique_ptr<Class<float, float>>> c32;
+    std::map<ClassKey, std::unique_ptr<Class<double, float>>> cmx;   // double phase of mixed solves
     std::map<GridKey, std::unique_ptr<OpPlan<double>>> o64;
     std::map<GridKey, std::unique_ptr<OpPlan<float>>> o32;
     std::map<std::pair<int, int>, void*> twiddles;   // (N, sizeof(R)) -> table
@@ -574,6 +588,7 @@ struct Ctx {
         (void)hipSetDevice(device);
         c64.clear();
         c32.clear();
+        cmx.clear();
         o64.clear();
         o32.clear();
         jobs.clear();
@@ -581,9 +596,21 @@ struct Ctx {
     }
 };
 
-template <typename R> static auto& classes(Ctx& cx);
-template <> auto& classes<double>(Ctx& cx) { return cx.c64; }
-template <> auto& classes<float>(Ctx& cx) { return cx.c32; }
+template <typename RS, typename RD> struct ClassMap;
+template <> struct ClassMap<double, double> { static auto& get(Ctx& cx) { return cx.c64; } };
+template <> struct ClassMap<float, float> { static auto& get(Ctx& cx) { return cx.c32; } };
+template <> struct ClassMap<double, float> { static auto& get(Ctx& cx) { return cx.cmx; } };
+// f(class) over every class (float state first); stops at the first nonzero return
+template <typename F> static int each_class(Ctx& cx, F&& f) {
+    int rc;
+    for (auto& kv : cx.c32)
+        if ((rc = f(*kv.second))) return rc;
+    for (auto& kv : cx.cmx)
+        if ((rc = f(*kv.second))) return rc;
+    for (auto& kv : cx.c64)
+        if ((rc = f(*kv.second))) return rc;
+    return 0;
+}
 template <typename R> static auto& opplans(Ctx& cx);
 template <> auto& opplans<double>(Ctx& cx) { return cx.o64; }
 template <> auto& opplans<float>(Ctx& cx) { return cx.o32; }
@@ -616,35 +643,36 @@ static GridKey grid_key(const gs_grid* g) {
     return std::make_tuple(g->dim, g->n[0], g->n[1], g->dim == 3 ? g->n[2] : 1);
 }
 
-template <typename R>
-static int get_class(Ctx& cx, const gs_grid* g, int check_every, Class<R>** out) {
+template <typename RS, typename RD>
+static int get_class(Ctx& cx, const gs_grid* g, int check_every, Class<RS, RD>** out) {
     auto key = std::make_tuple(g->dim, g->n[0], g->n[1], g->dim == 3 ? g->n[2] : 1, check_every);
-    auto& mp = classes<R>(cx);
+    auto& mp = ClassMap<RS, RD>::get(cx);
     auto it = mp.find(key);
     if (it != mp.end()) {
         *out = it->second.get();
         return GS_OK;
     }
-    auto c = std::make_unique<Class<R>>();
+    auto c = std::make_unique<Class<RS, RD>>();
     c->grid = *g;
     if (g->dim == 2) c->grid.n[2] = 1;
     c->check_every = check_every;
     c->M = npts(g);
-    c->g = red_geom<R>(g);
+    c->g = red_geom<RD>(g);
     for (int a = 0; a < g->dim; ++a) {
-        int rc = get_twiddle<R>(cx, g->n[a], &c->tw[a]);
+        int rc = get_twiddle<RS>(cx, g->n[a], &c->tws[a]);
+        if (!rc) rc = get_twiddle<RD>(cx, g->n[a], &c->twd[a]);
         if (rc) return rc;
     }
     // non-blocking: the class's work never waits for the null stream
     HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&c->ev, hipEventDisableTiming));
     if (hipMalloc((void**)&c->d_st, sizeof(SolveState) * CLASS_CAP) != hipSuccess ||
-        hipMalloc((void**)&c->d_tab, sizeof(Slot<R>) * CLASS_CAP) != hipSuccess) {
+        hipMalloc((void**)&c->d_tab, sizeof(Slot) * CLASS_CAP) != hipSuccess) {
         (void)hipGetLastError();
         return fail(GS_ENOMEM, "device allocation failed (class tables)");
     }
     if (hipHostMalloc((void**)&c->h_st, sizeof(SolveState) * CLASS_CAP, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&c->h_tab, sizeof(Slot<R>) * CLASS_CAP, hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void**)&c->h_tab, sizeof(Slot) * CLASS_CAP, hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         return fail(GS_ENOMEM, "pinned allocation failed (class tables)");
     }
@@ -654,9 +682,8 @@ static int get_class(Ctx& cx, const gs_grid* g, int check_every, Class<R>** out)
     return GS_OK;
 }
 
-template <typename R>
-static Slot<R> entry_of(SlotMem<R>& m, SolveState* st, const Phys& ph) {
-    Slot<R> e;
+static Slot entry_of(SlotMem& m, SolveState* st, const Phys& ph) {
+    Slot e;
     std::memset(&e, 0, sizeof(e));
     for (int b = 0; b < NBUF; ++b) e.buf[b] = m.buf[b];
     e.pv = m.pv;
@@ -668,24 +695,28 @@ static Slot<R> entry_of(SlotMem<R>& m, SolveState* st, const Phys& ph) {
     return e;
 }
 
-template <typename R>
-static Geo<R> geo_of(const gs_grid& g, long long M, RedGeom rg, const cpx<R>* const tw[3], int rot_any) {
-    Geo<R> G;
+template <typename RS, typename RD>
+static Geo<RS, RD> geo_of(const gs_grid& g, long long M, RedGeom rg, const cpx<RS>* const tws[3],
+                          const cpx<RD>* const twd[3], int rot_any) {
+    Geo<RS, RD> G;
     G.dim = g.dim;
     G.n[0] = g.n[0];
     G.n[1] = g.n[1];
     G.n[2] = g.dim == 3 ? g.n[2] : 1;
     G.M = M;
     G.g = rg;
-    for (int a = 0; a < 3; ++a) G.tw[a] = tw[a];
+    for (int a = 0; a < 3; ++a) {
+        G.tws[a] = tws[a];
+        G.twd[a] = twd[a];
+    }
     G.rot_any = rot_any;
     return G;
 }
 
 // Release the device memory of idle slots (any class) until `need` more bytes
 // fit in the budget.
-template <typename R>
-static void trim_class(Class<R>& c, Ctx& cx, size_t need) {
+template <typename RS, typename RD>
+static void trim_class(Class<RS, RD>& c, Ctx& cx, size_t need) {
     for (size_t k = 0; k < c.mem.size() && cx.allocated + need > cx.budget; ++k) {
         if (c.mem[k] && !c.owner[k]) {
             cx.allocated -= c.mem[k]->bytes;
@@ -695,8 +726,7 @@ static void trim_class(Class<R>& c, Ctx& cx, size_t need) {
 }
 static void trim(Ctx& cx, size_t need) {
     (void)hipDeviceSynchronize();   // pending work may still read a released slot
-    for (auto& kv : cx.c32) trim_class(*kv.second, cx, need);
-    for (auto& kv : cx.c64) trim_class(*kv.second, cx, need);
+    each_class(cx, [&](auto& c) { trim_class(c, cx, need); return 0; });
 }
 
 constexpr int SLOT_WAIT = 1;
@@ -704,8 +734,8 @@ constexpr int SLOT_WAIT = 1;
 // Free slot of the class for job j (allocated if needed; a new slot is zeroed
 // on stream s, which must precede every later use of the slot). GS_OK,
 // SLOT_WAIT (no memory now) or an error.
-template <typename R>
-static int acquire_slot(Ctx& cx, Class<R>& c, Job* j, hipStream_t s, int* out) {
+template <typename RS, typename RD>
+static int acquire_slot(Ctx& cx, Class<RS, RD>& c, Job* j, hipStream_t s, int* out) {
     int id = -1;
     for (size_t k = 0; k < c.mem.size(); ++k)
         if (c.mem[k] && !c.owner[k]) { id = (int)k; break; }
@@ -718,10 +748,10 @@ static int acquire_slot(Ctx& cx, Class<R>& c, Job* j, hipStream_t s, int* out) {
             c.mem.emplace_back();
             c.owner.push_back(nullptr);
         }
-        const size_t need = slot_buffer_bytes<R>(&c.grid);
+        const size_t need = slot_buffer_bytes<RS, RD>(&c.grid);
         if (cx.allocated + need > cx.budget) trim(cx, need);
         if (cx.allocated + need > cx.budget) return SLOT_WAIT;
-        int rc = alloc_slot_mem<R>(&c.grid, s, c.mem[id]);
+        int rc = alloc_slot_mem<RS, RD>(&c.grid, s, c.mem[id]);
         if (rc) return rc;
         cx.allocated += need;
     }
@@ -747,16 +777,18 @@ static void finish_job(Ctx& cx, Job* j, int rc, const SolveState* h, const std::
 
 // Float phase of a mixed solve finished with a switch request: hand Phi (made
 // double on the float stream) and the state (beta reset, phase FP64) to the
-// double class of the same grid.
-static int hand_over(Ctx& cx, Class<float>& c, int k, Job* j) {
-    Class<double>* d = nullptr;
-    int rc = get_class<double>(cx, &j->grid, c.check_every, &d);
+// double-state class of the same grid (with the search direction in RD).
+template <typename RD>
+static int hand_over_to(Ctx& cx, Class<float, float>& c, int k, Job* j) {
+    Class<double, RD>* d = nullptr;
+    int rc = get_class<double, RD>(cx, &j->grid, c.check_every, &d);
     if (rc) return rc;
     int kd = -1;
-    rc = acquire_slot<double>(cx, *d, j, c.stream, &kd);
+    rc = acquire_slot<double, RD>(cx, *d, j, c.stream, &kd);
     if (rc == SLOT_WAIT) return fail(GS_ENOMEM, "no device memory for the double phase");
     if (rc) return rc;
-    HIPCHK(launch_convert_f2d(c.mem[k]->buf[B_PHI], d->mem[kd]->buf[B_PHI], 3 * c.M, c.stream));
+    HIPCHK(launch_convert_f2d(static_cast<cpx<float>*>(c.mem[k]->buf[B_PHI]),
+                              static_cast<cpx<double>*>(d->mem[kd]->buf[B_PHI]), 3 * c.M, c.stream));
     if (!j->ev) HIPCHK(hipEventCreateWithFlags(&j->ev, hipEventDisableTiming));
     HIPCHK(hipEventRecord(j->ev, c.stream));
     j->wait_ev = true;
@@ -778,35 +810,39 @@ static int hand_over(Ctx& cx, Class<float>& c, int k, Job* j) {
     cx.moves++;
     return GS_OK;
 }
+static int hand_over(Ctx& cx, Class<float, float>& c, int k, Job* j) {
+    return j->opt.dir_precision == GS_FP32 ? hand_over_to<float>(cx, c, k, j) : hand_over_to<double>(cx, c, k, j);
+}
 
 // Initial guess of job j into slot k's Phi (the Gaussian guess is built in
-// double, then rounded when the slot is float).
-template <typename R>
-static int load_guess(Class<R>& c, int k, Job* j) {
-    SlotMem<R>& m = *c.mem[k];
+// double, then rounded when the state is float).
+template <typename RS, typename RD>
+static int load_guess(Class<RS, RD>& c, int k, Job* j) {
+    SlotMem& m = *c.mem[k];
     const long long n3 = 3 * c.M;
-    if constexpr (std::is_same<R, double>::value) {
-        if (j->psi0) HIPCHK(hipMemcpyAsync(m.buf[B_PHI], j->psi0, sizeof(cpx<double>) * n3, hipMemcpyDeviceToDevice, c.stream));
-        else HIPCHK(launch_gaussian(m.buf[B_PHI], j->ph, c.stream));
+    if constexpr (std::is_same<RS, double>::value) {
+        cpx<double>* phi = static_cast<cpx<double>*>(m.buf[B_PHI]);
+        if (j->psi0) HIPCHK(hipMemcpyAsync(phi, j->psi0, sizeof(cpx<double>) * n3, hipMemcpyDeviceToDevice, c.stream));
+        else HIPCHK(launch_gaussian(phi, j->ph, c.stream));
     } else {
         const cpx<double>* src = j->psi0;
         if (!src) {
-            cpx<double>* tmp = reinterpret_cast<cpx<double>*>(m.buf[B_T6A]);   // 2 float fields = 1 double field
+            cpx<double>* tmp = static_cast<cpx<double>*>(m.buf[B_T6A]);   // 2 float fields = 1 double field
             HIPCHK(launch_gaussian(tmp, j->ph, c.stream));
             src = tmp;
         }
-        HIPCHK(launch_convert_d2f(src, m.buf[B_PHI], n3, c.stream));
+        HIPCHK(launch_convert_d2f(src, static_cast<cpx<float>*>(m.buf[B_PHI]), n3, c.stream));
     }
     return GS_OK;
 }
 
-template <typename R>
-static int copy_out(Class<R>& c, int k, Job* j) {
+template <typename RS, typename RD>
+static int copy_out(Class<RS, RD>& c, int k, Job* j) {
     const long long n3 = 3 * c.M;
-    if constexpr (std::is_same<R, double>::value)
+    if constexpr (std::is_same<RS, double>::value)
         HIPCHK(hipMemcpyAsync(j->out, c.mem[k]->buf[B_PHI], sizeof(cpx<double>) * n3, hipMemcpyDeviceToDevice, c.stream));
     else
-        HIPCHK(launch_convert_f2d(c.mem[k]->buf[B_PHI], j->out, n3, c.stream));
+        HIPCHK(launch_convert_f2d(static_cast<cpx<float>*>(c.mem[k]->buf[B_PHI]), j->out, n3, c.stream));
     return GS_OK;
 }
 
@@ -832,6 +868,27 @@ static gs_grid level_grid(const gs_grid& fine, int nlevels, int level) {
     for (int a = 0; a < fine.dim; ++a) g.n[a] = fine.n[a] >> sh;
     if (fine.dim == 2) g.n[2] = 1;
     return g;
+}
+
+// Queue request j in the class that runs its first precision phase on its
+// current grid: double state for FP64 solves, float state otherwise; the
+// direction precision of an FP64 solve follows its dir_precision option.
+static int enqueue(Ctx& cx, Job* j, bool front) {
+    int rc;
+    if (j->opt.precision == GS_FP64 && j->opt.dir_precision == GS_FP32) {
+        Class<double, float>* c;
+        if ((rc = get_class<double, float>(cx, &j->grid, j->opt.check_every, &c))) return rc;
+        front ? c->queue.push_front(j) : c->queue.push_back(j);
+    } else if (j->opt.precision == GS_FP64) {
+        Class<double, double>* c;
+        if ((rc = get_class<double, double>(cx, &j->grid, j->opt.check_every, &c))) return rc;
+        front ? c->queue.push_front(j) : c->queue.push_back(j);
+    } else {
+        Class<float, float>* c;
+        if ((rc = get_class<float, float>(cx, &j->grid, j->opt.check_every, &c))) return rc;
+        front ? c->queue.push_front(j) : c->queue.push_back(j);
+    }
+    return GS_OK;
 }
 
 // Cascadic multigrid: the level just finished wrote its result to cm_buf[0];
@@ -860,15 +917,7 @@ static int next_level(Ctx& cx, Job* j, hipStream_t s) {
     j->stage = JS_QUEUED;
     j->slot = -1;
     j->handover = false;
-    if (j->opt.precision == GS_FP64) {
-        Class<double>* c;
-        if ((rc = get_class<double>(cx, &gf, j->opt.check_every, &c))) return rc;
-        c->queue.push_front(j);
-    } else {
-        Class<float>* c;
-        if ((rc = get_class<float>(cx, &gf, j->opt.check_every, &c))) return rc;
-        c->queue.push_front(j);
-    }
+    if ((rc = enqueue(cx, j, true))) return rc;
     cx.moves++;
     return GS_OK;
 }
@@ -876,9 +925,9 @@ static int next_level(Ctx& cx, Job* j, hipStream_t s) {
 // Chunk boundary of a class whose previous chunk (if any) has completed:
 // retire finished solves, start final evaluations, hand over float phases,
 // admit queued requests, then enqueue the next chunk.
-template <typename R>
-static int boundary(Ctx& cx, Class<R>& c) {
-    constexpr bool is64 = std::is_same<R, double>::value;
+template <typename RS, typename RD>
+static int boundary(Ctx& cx, Class<RS, RD>& c) {
+    constexpr bool is64 = std::is_same<RS, double>::value;
     int rc;
     // 1. final evaluations enqueued at the previous boundary have completed
     for (int k : c.fin) {
@@ -962,7 +1011,7 @@ static int boundary(Ctx& cx, Class<R>& c) {
                 waiting.push_back(j);
                 continue;
             }
-            rc = acquire_slot<R>(cx, c, j, c.stream, &k);
+            rc = acquire_slot<RS, RD>(cx, c, j, c.stream, &k);
             if (rc == SLOT_WAIT) {
                 blocked = blocked || !j->admitted;
                 waiting.push_back(j);
@@ -987,9 +1036,9 @@ static int boundary(Ctx& cx, Class<R>& c) {
             j->handover = false;
         } else {
             init_state(&c.h_st[k], &j->opt, j->opt.precision == GS_MIXED ? PH_FP32 : PH_FP64);
-            if ((rc = load_guess<R>(c, k, j))) return rc;
+            if ((rc = load_guess<RS, RD>(c, k, j))) return rc;
         }
-        HIPCHK(hipMemsetAsync(c.mem[k]->buf[B_P], 0, sizeof(cpx<R>) * 3 * c.M, c.stream));
+        HIPCHK(hipMemsetAsync(c.mem[k]->buf[B_P], 0, sizeof(cpx<RD>) * 3 * c.M, c.stream));
         fresh.push_back(k);
         j->stage = JS_RUNNING;
     }
@@ -1007,7 +1056,7 @@ static int boundary(Ctx& cx, Class<R>& c) {
     for (int k : c.run) c.iter0.push_back(c.h_st[k].iter);
     auto put = [&](int k) {
         const Phys& ph = c.owner[k]->ph;
-        c.h_tab[nt++] = entry_of<R>(*c.mem[k], c.d_st + k, ph);
+        c.h_tab[nt++] = entry_of(*c.mem[k], c.d_st + k, ph);
         rot_any |= ph.omega != 0.0;
         maxk = std::max(maxk, k + 1);
     };
@@ -1016,23 +1065,23 @@ static int boundary(Ctx& cx, Class<R>& c) {
     const int nrun = (int)c.run.size(), nfin = (int)c.fin.size(), nnew = (int)fresh.size();
     hipStream_t s = c.stream;
     HIPCHK(hipMemcpyAsync(c.d_st, c.h_st, sizeof(SolveState) * maxk, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(c.d_tab, c.h_tab, sizeof(Slot<R>) * nt, hipMemcpyHostToDevice, s));
-    const Geo<R> G = geo_of<R>(c.grid, c.M, c.g, c.tw, rot_any);
+    HIPCHK(hipMemcpyAsync(c.d_tab, c.h_tab, sizeof(Slot) * nt, hipMemcpyHostToDevice, s));
+    const Geo<RS, RD> G = geo_of<RS, RD>(c.grid, c.M, c.g, c.tws, c.twd, rot_any);
     if (nfin) {
-        const Sub<R> Lf{c.d_tab + nrun, nfin};
-        HIPCHK(refresh<R>(G, Lf, s, nullptr));
-        HIPCHK(resid_final<R>(G, Lf, s));
+        const Sub Lf{c.d_tab + nrun, nfin};
+        HIPCHK((refresh<RS, RD>(G, Lf, s, nullptr)));
+        HIPCHK((resid_final<RS, RD>(G, Lf, s)));
         for (int k : c.fin)
-            if ((rc = copy_out<R>(c, k, c.owner[k]))) return rc;
+            if ((rc = copy_out<RS, RD>(c, k, c.owner[k]))) return rc;
     }
-    if (nnew) HIPCHK(normalize<R>(G, Sub<R>{c.d_tab, nnew}, s));
+    if (nnew) HIPCHK((normalize<RS, RD>(G, Sub{c.d_tab, nnew}, s)));
     if (nrun) {
         c.tm.kind = cx.timer.kind;
         Timer* tm = c.tm.kind >= 0 ? &c.tm : nullptr;
-        const Sub<R> Lr{c.d_tab, nrun};
+        const Sub Lr{c.d_tab, nrun};
         for (int it = 0; it < c.check_every; ++it) {
             if (tm) tm->iter_in_chunk = it;
-            HIPCHK(iterate<R>(G, Lr, it == 0, s, tm));
+            HIPCHK((iterate<RS, RD>(G, Lr, it == 0, s, tm)));
         }
     }
     HIPCHK(hipMemcpyAsync(c.h_st, c.d_st, sizeof(SolveState) * maxk, hipMemcpyDeviceToHost, s));
@@ -1042,8 +1091,8 @@ static int boundary(Ctx& cx, Class<R>& c) {
     return GS_OK;
 }
 
-template <typename R>
-static int visit(Ctx& cx, Class<R>& c, bool& did) {
+template <typename RS, typename RD>
+static int visit(Ctx& cx, Class<RS, RD>& c, bool& did) {
     if (c.inflight) {
         hipError_t q = hipEventQuery(c.ev);
         if (q == hipErrorNotReady) return GS_OK;
@@ -1052,7 +1101,7 @@ static int visit(Ctx& cx, Class<R>& c, bool& did) {
     } else if (c.queue.empty() && c.run.empty() && c.fin.empty()) {
         return GS_OK;
     }
-    int rc = boundary<R>(cx, c);
+    int rc = boundary<RS, RD>(cx, c);
     if (rc) return rc;
     did = did || c.inflight;
     return GS_OK;
@@ -1065,21 +1114,27 @@ static int progress(Ctx& cx, bool block) {
         bool did = false;
         int rc;
         const uint64_t moves0 = cx.moves;
-        for (auto& kv : cx.c32)
-            if ((rc = visit<float>(cx, *kv.second, did))) return rc;
-        for (auto& kv : cx.c64)
-            if ((rc = visit<double>(cx, *kv.second, did))) return rc;
+        if ((rc = each_class(cx, [&](auto& c) { return visit(cx, c, did); }))) return rc;
         if (cx.moves != moves0) continue;   // a request entered a class already visited
         if (!block || did) return GS_OK;
         hipEvent_t e = nullptr;
         uint64_t best = UINT64_MAX;
-        for (auto& kv : cx.c32)
-            if (kv.second->inflight && kv.second->seq < best) { best = kv.second->seq; e = kv.second->ev; }
-        for (auto& kv : cx.c64)
-            if (kv.second->inflight && kv.second->seq < best) { best = kv.second->seq; e = kv.second->ev; }
+        each_class(cx, [&](auto& c) {
+            if (c.inflight && c.seq < best) { best = c.seq; e = c.ev; }
+            return 0;
+        });
         if (!e) return GS_OK;   // nothing in flight
         HIPCHK(hipEventSynchronize(e));
     }
+}
+
+// Slot bytes of every precision phase of a solve of grid g.
+static size_t footprint(const gs_grid* g, const gs_options* o) {
+    size_t b = 0;
+    if (o->precision != GS_FP64) b += slot_bytes<float, float>(g);
+    if (o->precision != GS_FP32)
+        b += o->dir_precision == GS_FP32 ? slot_bytes<double, float>(g) : slot_bytes<double, double>(g);
+    return b;
 }
 
 static int submit_job(Ctx& cx, const gs_request* q, uint64_t* ticket) {
@@ -1107,8 +1162,7 @@ static int submit_job(Ctx& cx, const gs_request* q, uint64_t* ticket) {
     if ((rc = make_phys(&j->grid, &q->trap, &q->params, &j->ph))) return rc;
     const long long M = npts(&j->fine);
     j->reserve = 0;
-    if (q->options.precision != GS_FP32) j->reserve += slot_bytes<double>(&j->fine);
-    if (q->options.precision != GS_FP64) j->reserve += slot_bytes<float>(&j->fine);
+    j->reserve = footprint(&j->fine, &q->options);
     if (q->trap.V) j->reserve += sizeof(double) * M;
     if (j->nlevels > 1) j->reserve += 2 * sizeof(cpx<double>) * 3 * M;
     if (j->reserve > cx.budget) return fail(GS_ENOMEM, "request needs more device memory than the budget");
@@ -1132,15 +1186,7 @@ static int submit_job(Ctx& cx, const gs_request* q, uint64_t* ticket) {
     j->user_out = (cpx<double>*)q->d_psi_out;
     j->out = j->nlevels > 1 ? j->cm_buf[0] : j->user_out;
     j->t0 = std::chrono::steady_clock::now();
-    if (q->options.precision == GS_FP64) {
-        Class<double>* c;
-        if ((rc = get_class<double>(cx, &j->grid, j->opt.check_every, &c))) return rc;
-        c->queue.push_back(j.get());
-    } else {
-        Class<float>* c;
-        if ((rc = get_class<float>(cx, &j->grid, j->opt.check_every, &c))) return rc;
-        c->queue.push_back(j.get());
-    }
+    if ((rc = enqueue(cx, j.get(), false))) return rc;
     j->ticket = cx.next_ticket++;
     *ticket = j->ticket;
     cx.jobs[j->ticket] = std::move(j);
@@ -1166,8 +1212,7 @@ static int wait_job(Ctx& cx, uint64_t ticket, gs_result* res) {
         int rc = progress(cx, true);
         if (rc) return rc;
         bool any = false;
-        for (auto& kv : cx.c32) any = any || kv.second->inflight;
-        for (auto& kv : cx.c64) any = any || kv.second->inflight;
+        each_class(cx, [&](auto& c) { any = any || c.inflight; return 0; });
         if (!any && j->stage != JS_DONE) return fail(GS_EDEVICE, "request is not progressing");
     }
     return take_result(cx, ticket, res);
@@ -1215,14 +1260,14 @@ static int get_opplan(Ctx& cx, const gs_grid* g, OpPlan<R>** out, hipStream_t s)
     int rc;
     for (int a = 0; a < g->dim; ++a)
         if ((rc = get_twiddle<R>(cx, g->n[a], &op->tw[a]))) return rc;
-    if ((rc = alloc_slot_mem<R>(g, s, op->mem))) return rc;
+    if ((rc = alloc_slot_mem<R, R>(g, s, op->mem))) return rc;
     if (hipMalloc((void**)&op->d_st, sizeof(SolveState)) != hipSuccess ||
-        hipMalloc((void**)&op->d_tab, sizeof(Slot<R>)) != hipSuccess) {
+        hipMalloc((void**)&op->d_tab, sizeof(Slot)) != hipSuccess) {
         (void)hipGetLastError();
         return fail(GS_ENOMEM, "device allocation failed (operator plan)");
     }
     if (hipHostMalloc((void**)&op->h_st, sizeof(SolveState), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&op->h_tab, sizeof(Slot<R>), hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void**)&op->h_tab, sizeof(Slot), hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         return fail(GS_ENOMEM, "pinned allocation failed (operator plan)");
     }
@@ -1241,11 +1286,11 @@ static int op_setup(OpPlan<R>& op, const Phys& ph, const void* x0, void* x1, hip
     gs_default_options(&o);
     o.max_iter = 1 << 30;
     init_state(op.h_st, &o, PH_FP64);
-    *op.h_tab = entry_of<R>(*op.mem, op.d_st, ph);
-    op.h_tab->buf[B_X0] = (cpx<R>*)x0;
-    op.h_tab->buf[B_X1] = (cpx<R>*)x1;
+    *op.h_tab = entry_of(*op.mem, op.d_st, ph);
+    op.h_tab->buf[B_X0] = const_cast<void*>(x0);
+    op.h_tab->buf[B_X1] = x1;
     HIPCHK(hipMemcpyAsync(op.d_st, op.h_st, sizeof(SolveState), hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(op.d_tab, op.h_tab, sizeof(Slot<R>), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(op.d_tab, op.h_tab, sizeof(Slot), hipMemcpyHostToDevice, s));
     return GS_OK;
 }
 
@@ -1259,15 +1304,15 @@ static int fft_impl(Ctx& cx, const gs_grid* g, int sign, const cpx<R>* in, cpx<R
     if ((rc = op_setup<R>(*op, ph, in, out, s))) return rc;
     const int Nx = g->n[0], Ny = g->n[1], Nz = g->dim == 3 ? g->n[2] : 1;
     const double invM = 1.0 / (double)op->M;
-    const Slot<R>* T = op->d_tab;
+    const Slot* T = op->d_tab;
     if (sign < 0) {
         if (g->dim == 2) {
-            HIPCHK(launch_fwdT<R>(Nx, PRO_PLAIN, 0, T, 1, B_X0, B_T0, B_NONE, B_NONE, 1, Ny, 3, op->tw[0], s));
-            HIPCHK(launch_fwdT<R>(Ny, PRO_PLAIN, 0, T, 1, B_T0, B_X1, B_NONE, B_NONE, 1, Nx, 3, op->tw[1], s));
+            HIPCHK((launch_fwdT<R, R>(Nx, PRO_PLAIN, 0, T, 1, B_X0, B_T0, B_NONE, B_NONE, 1, Ny, 3, op->tw[0], s)));
+            HIPCHK((launch_fwdT<R, R>(Ny, PRO_PLAIN, 0, T, 1, B_T0, B_X1, B_NONE, B_NONE, 1, Nx, 3, op->tw[1], s)));
         } else {
-            HIPCHK(launch_fwdT<R>(Nx, PRO_PLAIN, 0, T, 1, B_X0, B_T0, B_NONE, B_NONE, Nz, Ny, 3, op->tw[0], s));
-            HIPCHK(launch_fwdT<R>(Ny, PRO_PLAIN, 0, T, 1, B_T0, B_T1, B_NONE, B_NONE, Nx, Nz, 3, op->tw[1], s));
-            HIPCHK(launch_fwdT<R>(Nz, PRO_PLAIN, 0, T, 1, B_T1, B_X1, B_NONE, B_NONE, Ny, Nx, 3, op->tw[2], s));
+            HIPCHK((launch_fwdT<R, R>(Nx, PRO_PLAIN, 0, T, 1, B_X0, B_T0, B_NONE, B_NONE, Nz, Ny, 3, op->tw[0], s)));
+            HIPCHK((launch_fwdT<R, R>(Ny, PRO_PLAIN, 0, T, 1, B_T0, B_T1, B_NONE, B_NONE, Nx, Nz, 3, op->tw[1], s)));
+            HIPCHK((launch_fwdT<R, R>(Nz, PRO_PLAIN, 0, T, 1, B_T1, B_X1, B_NONE, B_NONE, Ny, Nx, 3, op->tw[2], s)));
         }
     } else {
         if (g->dim == 2) {
@@ -1308,12 +1353,12 @@ static int ham_impl(Ctx& cx, const gs_grid* g, const gs_trap* t, const gs_params
     double* Vdev = nullptr;
     if ((rc = op_potential(cx, t, ph, &Vdev))) return rc;
     rc = op_setup<R>(*op, ph, psi, hpsi, s);
-    const Sub<R> L{op->d_tab, 1};
-    const Geo<R> G = geo_of<R>(op->grid, op->M, op->g, op->tw, ph.omega != 0.0);
+    const Sub L{op->d_tab, 1};
+    const Geo<R, R> G = geo_of<R, R>(op->grid, op->M, op->g, op->tw, op->tw, ph.omega != 0.0);
     hipError_t e = hipSuccess;
     if (!rc) e = hipMemcpyAsync(op->mem->buf[B_PHI], psi, sizeof(cpx<R>) * 3 * op->M, hipMemcpyDeviceToDevice, s);
-    if (!rc && !e) e = refresh<R>(G, L, s, nullptr);
-    if (!rc && !e) e = resid_final<R>(G, L, s);
+    if (!rc && !e) e = refresh<R, R>(G, L, s, nullptr);
+    if (!rc && !e) e = resid_final<R, R>(G, L, s);
     if (!rc && !e) e = launch_hphi<R>(L.tab, 1, G.g, s);
     if (!rc && !e && (res || Vdev)) {
         e = hipMemcpyAsync(op->h_st, op->d_st, sizeof(SolveState), hipMemcpyDeviceToHost, s);
@@ -1340,13 +1385,13 @@ static int pre_impl(Ctx& cx, const gs_grid* g, const gs_trap* t, const gs_params
     double* Vdev = nullptr;
     if ((rc = op_potential(cx, t, ph, &Vdev))) return rc;
     rc = op_setup<R>(*op, ph, r, out, s);
-    const Sub<R> L{op->d_tab, 1};
-    const Geo<R> G = geo_of<R>(op->grid, op->M, op->g, op->tw, ph.omega != 0.0);
+    const Sub L{op->d_tab, 1};
+    const Geo<R, R> G = geo_of<R, R>(op->grid, op->M, op->g, op->tw, op->tw, ph.omega != 0.0);
     hipError_t e = hipSuccess;
     if (!rc) e = hipMemcpyAsync(op->mem->buf[B_PHI], psi, sizeof(cpx<R>) * 3 * op->M, hipMemcpyDeviceToDevice, s);
-    if (!rc && !e) e = refresh<R>(G, L, s, nullptr);
+    if (!rc && !e) e = refresh<R, R>(G, L, s, nullptr);
     if (!rc && !e) e = launch_pvin<R>(L.tab, 1, G.g, s);
-    if (!rc && !e) e = chain_pre<R>(G, L, 0, B_X1, s, nullptr);
+    if (!rc && !e) e = chain_pre<R, R>(G, L, 0, B_X1, s, nullptr);
     if (!rc && !e && Vdev) e = hipStreamSynchronize(s);
     if (Vdev) (void)hipFree(Vdev);
     if (rc) return rc;
@@ -1383,16 +1428,12 @@ void gs_default_options(gs_options* o) {
     o->max_backtrack = 40;
     o->check_every = 32;
     o->cm_levels = 1;
+    o->dir_precision = GS_FP64;
 }
 
-size_t gs_footprint_bytes(const gs_grid* g, int precision) {
-    if (check_grid(g) != GS_OK) return 0;
-    switch (precision) {
-    case GS_FP64: return slot_bytes<double>(g);
-    case GS_FP32: return slot_bytes<float>(g);
-    case GS_MIXED: return slot_bytes<double>(g) + slot_bytes<float>(g);
-    default: return 0;
-    }
+size_t gs_footprint_bytes(const gs_grid* g, const gs_options* o) {
+    if (check_grid(g) != GS_OK || check_options(o) != GS_OK) return 0;
+    return footprint(g, o);
 }
 
 int gs_create(gs_ctx** out, int device) {
@@ -1537,14 +1578,10 @@ int gs_batch_solve(gs_ctx* ctx, int nreq, const gs_request* reqs, gs_result* res
             const std::string msg = "request " + std::to_string(i) + ": " + g_err;
             for (uint64_t u : tickets) {   // nothing has been launched yet
                 Job* j = cx.jobs[u].get();
-                for (auto& kv : cx.c32) {
-                    auto& qq = kv.second->queue;
-                    qq.erase(std::remove(qq.begin(), qq.end(), j), qq.end());
-                }
-                for (auto& kv : cx.c64) {
-                    auto& qq = kv.second->queue;
-                    qq.erase(std::remove(qq.begin(), qq.end(), j), qq.end());
-                }
+                each_class(cx, [&](auto& c) {
+                    c.queue.erase(std::remove(c.queue.begin(), c.queue.end(), j), c.queue.end());
+                    return 0;
+                });
                 cx.jobs.erase(u);
             }
             return fail(rc, msg);

@@ -213,16 +213,18 @@ __device__ __forceinline__ void lds_fft(cpx<R>* buf, const cpx<R>* __restrict__ 
 // ---------------------------------------------------------------------------
 // DUAL (with PRO_DIR): components 3..5 of the output are the plain transform
 // of aux1 (Phi), so that the middle pass sees both spectra.
-template <typename R, int N, int TILE, int PRO, bool DUAL, int NT>
-__global__ __launch_bounds__(NT) void k_fwdT(const Slot<R>* __restrict__ slots, int iin, int iout, int iaux0,
+template <typename R, typename RX, int N, int TILE, int PRO, bool DUAL, int NT>
+__global__ __launch_bounds__(NT) void k_fwdT(const Slot* __restrict__ slots, int iin, int iout, int iaux0,
                                              int iaux1, int A, int B, const cpx<R>* __restrict__ tw) {
-    const Slot<R>& S = slots[blockIdx.y];
+    const Slot& S = slots[blockIdx.y];
     const SolveState* st = S.st;
     if (st->done) return;
-    cpx<R>* inp = S.buf[iin];
-    cpx<R>* __restrict__ out = S.buf[iout];
-    const cpx<R>* __restrict__ aux0 = iaux0 >= 0 ? S.buf[iaux0] : nullptr;
-    const cpx<R>* __restrict__ aux1 = iaux1 >= 0 ? S.buf[iaux1] : nullptr;
+    cpx<R>* inp = fld<R>(S, iin);
+    cpx<R>* __restrict__ out = fld<R>(S, iout);
+    // PRO_UPDATE: aux0 = P (type RX); PRO_DIR: aux0 = P_C r (type R), aux1 = Phi (type RX)
+    const cpx<RX>* __restrict__ auxP = (PRO == PRO_UPDATE && iaux0 >= 0) ? fld<RX>(S, iaux0) : nullptr;
+    const cpx<R>* __restrict__ auxR = (PRO == PRO_DIR && iaux0 >= 0) ? fld<R>(S, iaux0) : nullptr;
+    const cpx<RX>* __restrict__ aux1 = iaux1 >= 0 ? fld<RX>(S, iaux1) : nullptr;
     constexpr int PITCH = Lay<N>::P;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
@@ -237,37 +239,43 @@ __global__ __launch_bounds__(NT) void k_fwdT(const Slot<R>* __restrict__ slots, 
     const int cin = second ? c - 3 : c;
     const long long base = (((long long)cin * A + a) * B + b0) * N;
 
+    // the prologue combinations are formed in double and rounded once
     int mode = second ? PRO_PLAIN : PRO;
-    R k0 = 1, k1 = 0, k2 = 1;
+    double k0 = 1, k1 = 0, k2 = 1;
     if (PRO == PRO_UPDATE) {
         if (!st->pending_step) mode = PRO_PLAIN;
         else {
-            k0 = (R)st->c;
-            k1 = (R)(st->s * st->invnP);
-            k2 = (R)st->inv_norm;
+            k0 = st->c;
+            k1 = st->s * st->invnP;
+            k2 = st->inv_norm;
             if (st->s == 0.0) mode = -1;   // rescale only
         }
     } else if (PRO == PRO_DIR) {
-        k0 = (R)st->beta;
-        k1 = (R)st->dphi;
-        k2 = (R)st->invnP;
+        k0 = st->beta;
+        k1 = st->dphi;
+        k2 = st->invnP;
     }
-    const cpx<R>* src = second ? aux1 : inp;
     for (int e = threadIdx.x; e < TILE * N; e += NT) {
         const int l = e / N, m = e - l * N;
         const long long gi = base + (long long)l * N + m;
-        cpx<R> v = src[gi];
-        if (mode == PRO_UPDATE) {
-            v = k2 * (k0 * v + k1 * aux0[gi]);
-            inp[gi] = v;
-        } else if (mode == -1) {
-            v = k2 * (k0 * v);
-            inp[gi] = v;
-        } else if (mode == PRO_DIR) {
-            // D = -P r + beta P^{n-1};  P^n = D - Re<D,Phi> Phi  (stored), transform P^n / |P^n|
-            v = k0 * v - aux0[gi] - k1 * aux1[gi];
-            inp[gi] = v;
-            v = k2 * v;
+        cpx<R> v;
+        if (second) {
+            v = cvt<R>(aux1[gi]);
+        } else {
+            v = inp[gi];
+            if (mode == PRO_UPDATE) {
+                v = cvt<R>(k2 * (k0 * wid(v) + k1 * wid(auxP[gi])));
+                inp[gi] = v;
+            } else if (mode == -1) {
+                v = cvt<R>(k2 * (k0 * wid(v)));
+                inp[gi] = v;
+            } else if (mode == PRO_DIR) {
+                // D = -P r + beta P^{n-1};  P^n = D - Re<D,Phi> Phi  (stored), transform P^n / |P^n|
+                const cpx<double> d = k0 * wid(v) - wid(auxR[gi]) - k1 * wid(aux1[gi]);
+                v = cvt<R>(d);
+                inp[gi] = v;
+                v = (R)k2 * v;
+            }
         }
         lds[l * PITCH + lx(m)] = v;
     }
@@ -289,20 +297,20 @@ __global__ __launch_bounds__(NT) void k_fwdT(const Slot<R>* __restrict__ slots, 
 //              out = IFFT(A) + Omega y k_x uin / Nx, out2 = IFFT(B)
 //              (uin = the x-transformed input, same layout)
 template <typename R, int N, int TILE, int EPI, int NT>
-__global__ __launch_bounds__(NT) void k_invT(const Slot<R>* __restrict__ slots, int iin, int iin2, int iout,
+__global__ __launch_bounds__(NT) void k_invT(const Slot* __restrict__ slots, int iin, int iin2, int iout,
                                              int iout2, int iuin, int B, int Cc, double scale, int use_invnP,
                                              int rot_any, const cpx<R>* __restrict__ tw) {
-    const Slot<R>& S = slots[blockIdx.y];
+    const Slot& S = slots[blockIdx.y];
     const SolveState* st = S.st;
     if (st->done) return;
     const Phys p = S.p;
     // the rotation input/output pair exists for rotating slots of the H_L chain
     const int nin = (EPI != EPI_SCALE && rot_any && p.omega != 0.0) ? 2 : 1;
-    const cpx<R>* __restrict__ in = S.buf[iin];
-    const cpx<R>* __restrict__ in2 = nin == 2 ? S.buf[iin2] : nullptr;
-    cpx<R>* __restrict__ out = S.buf[iout];
-    cpx<R>* __restrict__ out2 = (nin == 2 && iout2 >= 0) ? S.buf[iout2] : nullptr;
-    const cpx<R>* __restrict__ uin = iuin >= 0 ? S.buf[iuin] : nullptr;
+    const cpx<R>* __restrict__ in = fld<R>(S, iin);
+    const cpx<R>* __restrict__ in2 = nin == 2 ? fld<R>(S, iin2) : nullptr;
+    cpx<R>* __restrict__ out = fld<R>(S, iout);
+    cpx<R>* __restrict__ out2 = (nin == 2 && iout2 >= 0) ? fld<R>(S, iout2) : nullptr;
+    const cpx<R>* __restrict__ uin = iuin >= 0 ? fld<R>(S, iuin) : nullptr;
     constexpr int PITCH = Lay<N>::P;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
@@ -359,15 +367,15 @@ __global__ __launch_bounds__(NT) void k_invT(const Slot<R>* __restrict__ slots, 
 // partial sums of the direction reductions of the next step fused in
 // (Re<r,Pr>, Re<r_prev,Pr>, Re<phi,Pr>, |Pr|^2, Re<Pr,P^{n-1}>).
 // ---------------------------------------------------------------------------
-template <typename R, int N, int TILE, int NT>
-__global__ __launch_bounds__(NT) void k_invT_pre(const Slot<R>* __restrict__ slots, int iin, int iout, int B,
+template <typename R, typename RS, int N, int TILE, int NT>
+__global__ __launch_bounds__(NT) void k_invT_pre(const Slot* __restrict__ slots, int iin, int iout, int B,
                                                  int Cc, int dir, const cpx<R>* __restrict__ tw) {
-    const Slot<R>& S = slots[blockIdx.y];
+    const Slot& S = slots[blockIdx.y];
     SolveState* st = S.st;
     if (st->done) return;
-    const cpx<R>* __restrict__ in = S.buf[iin];
-    cpx<R>* __restrict__ out = S.buf[iout];
-    const R* __restrict__ pv = S.pv;
+    const cpx<R>* __restrict__ in = fld<R>(S, iin);
+    cpx<R>* __restrict__ out = fld<R>(S, iout);
+    const R* __restrict__ pv = pvf<R>(S);
     constexpr int PITCH = Lay<N>::P;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
@@ -385,10 +393,10 @@ __global__ __launch_bounds__(NT) void k_invT_pre(const Slot<R>* __restrict__ slo
     __syncthreads();
     lds_fft<R, N, TILE, NT, true>(lds, tw);
     double acc[NS_DIR] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    const cpx<R>* r = dir ? S.buf[B_R0 + st->cur] : nullptr;
-    const cpx<R>* rp = dir ? S.buf[B_R0 + (st->cur ^ 1)] : nullptr;
-    const cpx<R>* phi = S.buf[B_PHI];
-    const cpx<R>* Pprev = S.buf[B_P];
+    const cpx<RS>* r = dir ? fld<RS>(S, B_R0 + st->cur) : nullptr;
+    const cpx<RS>* rp = dir ? fld<RS>(S, B_R0 + (st->cur ^ 1)) : nullptr;
+    const cpx<RS>* phi = fld<RS>(S, B_PHI);
+    const cpx<R>* Pprev = fld<R>(S, B_P);
     for (int e = threadIdx.x; e < TILE * N; e += NT) {
         const int l = e / N, m = e - l * N;
         const long long go = (((long long)c * B + bb) * Cc + c0 + l) * N + m;
@@ -419,17 +427,17 @@ __global__ __launch_bounds__(NT) void k_invT_pre(const Slot<R>* __restrict__ slo
 //            of 1/2|k|^2 |Phi^_l|^2, 1/2|k|^2 Re Phi^_l conj(v_l), 1/2|k|^2 |v_l|^2.
 //   MID_PRE: A = v_l / (alpha_l + 1/2 |k|^2) / M.
 template <typename R, int N, int LPB, int OP, int NT>
-__global__ __launch_bounds__(NT) void k_mid(const Slot<R>* __restrict__ slots, int iin, int ioutA, int ioutB,
+__global__ __launch_bounds__(NT) void k_mid(const Slot* __restrict__ slots, int iin, int ioutA, int ioutB,
                                             int nlines, int rot_any, const cpx<R>* __restrict__ tw) {
-    const Slot<R>& S = slots[blockIdx.y];
+    const Slot& S = slots[blockIdx.y];
     const SolveState* st = S.st;
     if (st->done) return;
     const Phys p = S.p;
     const int rot = rot_any && p.omega != 0.0;
-    const cpx<R>* __restrict__ in = S.buf[iin];
+    const cpx<R>* __restrict__ in = fld<R>(S, iin);
     const cpx<R>* __restrict__ in2 = (OP == MID_HLX) ? in + 3 * p.M : nullptr;
-    cpx<R>* __restrict__ outA = S.buf[ioutA];
-    cpx<R>* __restrict__ outB = ioutB >= 0 ? S.buf[ioutB] : nullptr;
+    cpx<R>* __restrict__ outA = fld<R>(S, ioutA);
+    cpx<R>* __restrict__ outB = ioutB >= 0 ? fld<R>(S, ioutB) : nullptr;
     double* __restrict__ red = S.red_mid;
     constexpr int PITCH = Lay<N>::P;
     constexpr int NLN = 3 * LPB;
@@ -595,8 +603,8 @@ template <typename R> int invT_pre_blocks(int N, int B, int Cc) { return 3 * B *
 template int invT_pre_blocks<double>(int, int, int);
 template int invT_pre_blocks<float>(int, int, int);
 
-template <typename R, int N>
-static hipError_t fwdT_n(int pro, int dual, const Slot<R>* slots, int nslots, int in, int out, int aux0, int aux1,
+template <typename R, typename RX, int N>
+static hipError_t fwdT_n(int pro, int dual, const Slot* slots, int nslots, int in, int out, int aux0, int aux1,
                          int A, int B, int ncomp, const cpx<R>* tw, hipStream_t s) {
     constexpr int TILE = tile_fwd<R>(N);
     constexpr int NTB = nt_tile<R>(N);
@@ -605,18 +613,18 @@ static hipError_t fwdT_n(int pro, int dual, const Slot<R>* slots, int nslots, in
     const size_t lds = (size_t)TILE * Lay<N>::P * sizeof(cpx<R>);
     dim3 grid((unsigned)((long long)(dual ? 6 : ncomp) * A * (B / TILE)), (unsigned)nslots);
     if (dual) {
-        GS_LAUNCH((k_fwdT<R, N, TILE, PRO_DIR, true, NTB>), grid, dim3(NTB), lds, s, slots, in, out, aux0, aux1, A, B, tw);
+        GS_LAUNCH((k_fwdT<R, RX, N, TILE, PRO_DIR, true, NTB>), grid, dim3(NTB), lds, s, slots, in, out, aux0, aux1, A, B, tw);
         return hipGetLastError();
     }
     switch (pro) {
     case PRO_PLAIN:
-        GS_LAUNCH((k_fwdT<R, N, TILE, PRO_PLAIN, false, NTB>), grid, dim3(NTB), lds, s, slots, in, out, aux0, aux1, A, B, tw);
+        GS_LAUNCH((k_fwdT<R, RX, N, TILE, PRO_PLAIN, false, NTB>), grid, dim3(NTB), lds, s, slots, in, out, aux0, aux1, A, B, tw);
         break;
     case PRO_UPDATE:
-        GS_LAUNCH((k_fwdT<R, N, TILE, PRO_UPDATE, false, NTB>), grid, dim3(NTB), lds, s, slots, in, out, aux0, aux1, A, B, tw);
+        GS_LAUNCH((k_fwdT<R, RX, N, TILE, PRO_UPDATE, false, NTB>), grid, dim3(NTB), lds, s, slots, in, out, aux0, aux1, A, B, tw);
         break;
     case PRO_DIR:
-        GS_LAUNCH((k_fwdT<R, N, TILE, PRO_DIR, false, NTB>), grid, dim3(NTB), lds, s, slots, in, out, aux0, aux1, A, B, tw);
+        GS_LAUNCH((k_fwdT<R, RX, N, TILE, PRO_DIR, false, NTB>), grid, dim3(NTB), lds, s, slots, in, out, aux0, aux1, A, B, tw);
         break;
     default:
         return hipErrorInvalidValue;
@@ -625,7 +633,7 @@ static hipError_t fwdT_n(int pro, int dual, const Slot<R>* slots, int nslots, in
 }
 
 template <typename R, int N>
-static hipError_t invT_n(int epi, const Slot<R>* slots, int nslots, int in, int in2, int out, int out2, int uin,
+static hipError_t invT_n(int epi, const Slot* slots, int nslots, int in, int in2, int out, int out2, int uin,
                          int B, int Cc, double scale, int use_invnP, int rot_any, const cpx<R>* tw, hipStream_t s) {
     constexpr int TILE = tile_inv<R>(N);
     constexpr int NTB = nt_tile<R>(N);
@@ -648,8 +656,8 @@ static hipError_t invT_n(int epi, const Slot<R>* slots, int nslots, int in, int 
     return hipGetLastError();
 }
 
-template <typename R, int N>
-static hipError_t invT_pre_n(const Slot<R>* slots, int nslots, int in, int out, int B, int Cc, int dir,
+template <typename R, typename RS, int N>
+static hipError_t invT_pre_n(const Slot* slots, int nslots, int in, int out, int B, int Cc, int dir,
                              const cpx<R>* tw, hipStream_t s) {
     constexpr int TILE = tile_pre<R>(N);
     constexpr int NTB = nt_tile<R>(N);
@@ -657,12 +665,12 @@ static hipError_t invT_pre_n(const Slot<R>* slots, int nslots, int in, int out, 
     const size_t lds = (size_t)TILE * Lay<N>::P * sizeof(cpx<R>);
     dim3 grid((unsigned)(3LL * B * (Cc / TILE)), (unsigned)nslots);
     static_assert(NS_DIR <= RED_DIR_STRIDE, "partial-sum row");
-    GS_LAUNCH((k_invT_pre<R, N, TILE, NTB>), grid, dim3(NTB), lds, s, slots, in, out, B, Cc, dir, tw);
+    GS_LAUNCH((k_invT_pre<R, RS, N, TILE, NTB>), grid, dim3(NTB), lds, s, slots, in, out, B, Cc, dir, tw);
     return hipGetLastError();
 }
 
 template <typename R, int N>
-static hipError_t mid_n(int op, const Slot<R>* slots, int nslots, int in, int outA, int outB, int nlines,
+static hipError_t mid_n(int op, const Slot* slots, int nslots, int in, int outA, int outB, int nlines,
                         int rot_any, const cpx<R>* tw, hipStream_t s) {
     constexpr int LPB = lpb_mid(N);
     constexpr int NTB = nt_mid<R>(N);
@@ -691,16 +699,16 @@ static hipError_t mid_n(int op, const Slot<R>* slots, int nslots, int in, int ou
     default: return hipErrorInvalidValue;        \
     }
 
-template <typename R>
-hipError_t launch_fwdT(int N, int pro, int dual, const Slot<R>* slots, int nslots, int in, int out, int aux0,
+template <typename R, typename RX>
+hipError_t launch_fwdT(int N, int pro, int dual, const Slot* slots, int nslots, int in, int out, int aux0,
                        int aux1, int A, int B, int ncomp, const cpx<R>* tw, hipStream_t s) {
-#define CALL(n) fwdT_n<R, n>(pro, dual, slots, nslots, in, out, aux0, aux1, A, B, ncomp, tw, s)
+#define CALL(n) fwdT_n<R, RX, n>(pro, dual, slots, nslots, in, out, aux0, aux1, A, B, ncomp, tw, s)
     GS_SWITCH_N(CALL)
 #undef CALL
 }
 
 template <typename R>
-hipError_t launch_invT(int N, int epi, const Slot<R>* slots, int nslots, int in, int in2, int out, int out2,
+hipError_t launch_invT(int N, int epi, const Slot* slots, int nslots, int in, int in2, int out, int out2,
                        int uin, int B, int Cc, double scale, int use_invnP, int rot_any, const cpx<R>* tw,
                        hipStream_t s) {
 #define CALL(n) invT_n<R, n>(epi, slots, nslots, in, in2, out, out2, uin, B, Cc, scale, use_invnP, rot_any, tw, s)
@@ -708,16 +716,16 @@ hipError_t launch_invT(int N, int epi, const Slot<R>* slots, int nslots, int in,
 #undef CALL
 }
 
-template <typename R>
-hipError_t launch_invT_pre(int N, const Slot<R>* slots, int nslots, int in, int out, int B, int Cc, int dir,
+template <typename R, typename RS>
+hipError_t launch_invT_pre(int N, const Slot* slots, int nslots, int in, int out, int B, int Cc, int dir,
                            const cpx<R>* tw, hipStream_t s) {
-#define CALL(n) invT_pre_n<R, n>(slots, nslots, in, out, B, Cc, dir, tw, s)
+#define CALL(n) invT_pre_n<R, RS, n>(slots, nslots, in, out, B, Cc, dir, tw, s)
     GS_SWITCH_N(CALL)
 #undef CALL
 }
 
 template <typename R>
-hipError_t launch_mid(int N, int op, const Slot<R>* slots, int nslots, int in, int outA, int outB, int nlines,
+hipError_t launch_mid(int N, int op, const Slot* slots, int nslots, int in, int outA, int outB, int nlines,
                       int rot_any, const cpx<R>* tw, hipStream_t s) {
 #define CALL(n) mid_n<R, n>(op, slots, nslots, in, outA, outB, nlines, rot_any, tw, s)
     GS_SWITCH_N(CALL)
@@ -725,15 +733,20 @@ hipError_t launch_mid(int N, int op, const Slot<R>* slots, int nslots, int in, i
 }
 
 #define GS_INST_FFT(R)                                                                                           \
-    template hipError_t launch_fwdT<R>(int, int, int, const Slot<R>*, int, int, int, int, int, int, int, int,     \
-                                       const cpx<R>*, hipStream_t);                                              \
-    template hipError_t launch_invT<R>(int, int, const Slot<R>*, int, int, int, int, int, int, int, int, double,  \
+    template hipError_t launch_invT<R>(int, int, const Slot*, int, int, int, int, int, int, int, int, double,     \
                                        int, int, const cpx<R>*, hipStream_t);                                    \
-    template hipError_t launch_invT_pre<R>(int, const Slot<R>*, int, int, int, int, int, int, const cpx<R>*,      \
-                                           hipStream_t);                                                         \
-    template hipError_t launch_mid<R>(int, int, const Slot<R>*, int, int, int, int, int, int, const cpx<R>*,      \
+    template hipError_t launch_mid<R>(int, int, const Slot*, int, int, int, int, int, int, const cpx<R>*,         \
                                       hipStream_t);
+#define GS_INST_FFT2(R, RX)                                                                                      \
+    template hipError_t launch_fwdT<R, RX>(int, int, int, const Slot*, int, int, int, int, int, int, int, int,   \
+                                           const cpx<R>*, hipStream_t);                                          \
+    template hipError_t launch_invT_pre<R, RX>(int, const Slot*, int, int, int, int, int, int, const cpx<R>*,    \
+                                               hipStream_t);
 GS_INST_FFT(double)
 GS_INST_FFT(float)
+GS_INST_FFT2(double, double)
+GS_INST_FFT2(float, float)
+GS_INST_FFT2(float, double)
+GS_INST_FFT2(double, float)
 
 }  // namespace gs

@@ -150,16 +150,27 @@ constexpr int NS_MAX = 64;          // row stride of the pointwise partial sums
 constexpr int RED_MID_STRIDE = 12;  // row stride of the middle-pass partial sums
 constexpr int RED_DIR_STRIDE = 8;   // row stride of the preconditioner's last-pass partial sums
 
-template <typename R>
+// A slot's fields come in two precisions: the state (Phi, H_L Phi, r^n,
+// r^{n-1}; type RS) and the direction (P_C r, P, H_L P^, u and the P_V factors;
+// type RD). Scratch fields are sized for RS and used by the transforms of both.
+// (RS, RD) is (double, double), (float, float), or (double, float) for the
+// double phase of a mixed solve.
 struct Slot {
-    cpx<R>* buf[NBUF];
-    R* pv;               // [3][M] P_V^{1/2} factors (alpha_l + V + c0 rho)^{-1/2}
+    void* buf[NBUF];
+    void* pv;            // [3][M] P_V^{1/2} factors (alpha_l + V + c0 rho)^{-1/2}, type RD
     SolveState* st;
     double* red_mid;     // [nblk_mid][RED_MID_STRIDE]
     double* red_pw;      // [nblk_pw][NS_MAX]
     double* red_dir;     // [nblk_dir][RED_DIR_STRIDE]
     Phys p;
 };
+template <typename T> __host__ __device__ __forceinline__ cpx<T>* fld(const Slot& S, int b) {
+    return static_cast<cpx<T>*>(S.buf[b]);
+}
+template <typename T> __host__ __device__ __forceinline__ T* pvf(const Slot& S) { return static_cast<T*>(S.pv); }
+template <typename T, typename U> __host__ __device__ __forceinline__ cpx<T> cvt(cpx<U> a) {
+    return cpx<T>{(T)a.x, (T)a.y};
+}
 
 // reduction geometry of a grid class (same for every slot of the class): the
 // number of partial-sum rows each reducing pass writes
@@ -183,8 +194,10 @@ enum MidOp : int { MID_HL = 0, MID_PRE = 1, MID_HLX = 2 };
 //   PRO_UPDATE: if pending_step, in <- (c in + s invnP aux0) inv_norm (written back)
 //   PRO_DIR:    in <- -aux0 + beta in - dphi aux1 (written back), transform invnP * in
 // dual (PRO_DIR only): also transform aux1 into components 3..5 of out.
-template <typename R>
-hipError_t launch_fwdT(int N, int pro, int dual, const Slot<R>* slots, int nslots, int in, int out, int aux0,
+// in, out and (PRO_DIR) aux0 are of type R; the other operand (PRO_UPDATE:
+// aux0 = P; PRO_DIR: aux1 = Phi) is of type RX.
+template <typename R, typename RX>
+hipError_t launch_fwdT(int N, int pro, int dual, const Slot* slots, int nslots, int in, int out, int aux0,
                        int aux1, int A, int B, int ncomp, const cpx<R>* tw, hipStream_t s);
 
 // Inverse transform along the slowest axis of in[3][N][B][Cc] (and in2 when the
@@ -193,14 +206,15 @@ hipError_t launch_fwdT(int N, int pro, int dual, const Slot<R>* slots, int nslot
 // rot_any: some slot of the launch rotates (LDS and buffers for the second
 // input/output are provided); each slot decides from its own Omega.
 template <typename R>
-hipError_t launch_invT(int N, int epi, const Slot<R>* slots, int nslots, int in, int in2, int out, int out2,
+hipError_t launch_invT(int N, int epi, const Slot* slots, int nslots, int in, int in2, int out, int out2,
                        int uin, int B, int Cc, double scale, int use_invnP, int rot_any, const cpx<R>* tw,
                        hipStream_t s);
 
 // Last pass of the preconditioner: out = pv * IFFT(in); with dir = 1 also the
-// partial sums of the direction reductions (rows in red_dir).
-template <typename R>
-hipError_t launch_invT_pre(int N, const Slot<R>* slots, int nslots, int in, int out, int B, int Cc, int dir,
+// partial sums of the direction reductions (rows in red_dir). Transform, pv,
+// out and P are of type R; r^n, r^{n-1} and Phi of type RS.
+template <typename R, typename RS>
+hipError_t launch_invT_pre(int N, const Slot* slots, int nslots, int in, int out, int B, int Cc, int dir,
                            const cpx<R>* tw, hipStream_t s);
 
 // Middle pass: transform the contiguous axis of three component lines,
@@ -208,7 +222,7 @@ hipError_t launch_invT_pre(int N, const Slot<R>* slots, int nslots, int in, int 
 // transform back. in/outA/outB are [3][nlines][N]; for MID_HLX components 3..5
 // of `in` hold the spectrum of Phi.
 template <typename R>
-hipError_t launch_mid(int N, int op, const Slot<R>* slots, int nslots, int in, int outA, int outB, int nlines,
+hipError_t launch_mid(int N, int op, const Slot* slots, int nslots, int in, int outA, int outB, int nlines,
                       int rot_any, const cpx<R>* tw, hipStream_t s);
 
 int mid_blocks(int N, int nlines);
@@ -219,11 +233,12 @@ template <typename R> int invT_pre_blocks(int N, int B, int Cc);
 // pointwise kernels with fused partial sums (pw_kernels.hip), and the control
 // kernel that reduces the rows and takes the decisions of the iteration
 // ---------------------------------------------------------------------------
-template <typename R> hipError_t launch_eval(const Slot<R>* slots, int nslots, RedGeom g, hipStream_t s);
-template <typename R> hipError_t launch_resid(const Slot<R>* slots, int nslots, RedGeom g, int final_only, hipStream_t s);
-template <typename R> hipError_t launch_lsred(const Slot<R>* slots, int nslots, RedGeom g, hipStream_t s);
+template <typename RS> hipError_t launch_eval(const Slot* slots, int nslots, RedGeom g, hipStream_t s);
+template <typename RS, typename RD>
+hipError_t launch_resid(const Slot* slots, int nslots, RedGeom g, int final_only, hipStream_t s);
+template <typename RS, typename RD> hipError_t launch_lsred(const Slot* slots, int nslots, RedGeom g, hipStream_t s);
 // partial sums of |Phi|^2 (the control step FIN_NORM sets the rescale Phi <- Phi / |Phi|)
-template <typename R> hipError_t launch_normalize(const Slot<R>* slots, int nslots, RedGeom g, hipStream_t s);
+template <typename RS> hipError_t launch_normalize(const Slot* slots, int nslots, RedGeom g, hipStream_t s);
 enum Fin : int {
     FIN_EVAL = 0,     // energy parts, mu, alpha_l of a fresh evaluation
     FIN_DIR = 1,      // stopping tests of the residual pass, then PRP beta and projection
@@ -233,14 +248,14 @@ enum Fin : int {
 };
 // one block per slot: gather the partial-sum rows of the preceding pass(es) in
 // a fixed order and run the scalar control on thread 0
-template <typename R> hipError_t launch_fin(const Slot<R>* slots, int nslots, RedGeom g, int what, hipStream_t s);
+hipError_t launch_fin(const Slot* slots, int nslots, RedGeom g, int what, hipStream_t s);
 // precision conversion of a field of n complex values
 hipError_t launch_convert_d2f(const cpx<double>* in, cpx<float>* out, long long n, hipStream_t s);
 hipError_t launch_convert_f2d(const cpx<float>* in, cpx<double>* out, long long n, hipStream_t s);
 // X1 = H_L Phi + nonlinear terms = H(Phi)Phi (operator-level entry point)
-template <typename R> hipError_t launch_hphi(const Slot<R>* slots, int nslots, RedGeom g, hipStream_t s);
+template <typename R> hipError_t launch_hphi(const Slot* slots, int nslots, RedGeom g, hipStream_t s);
 // preconditioner input for the given r in X0: pv = (alpha_l + V + c0 rho)^{-1/2}, u = pv r
-template <typename R> hipError_t launch_pvin(const Slot<R>* slots, int nslots, RedGeom g, hipStream_t s);
+template <typename R> hipError_t launch_pvin(const Slot* slots, int nslots, RedGeom g, hipStream_t s);
 // zero-padding of a [3][nc] spectrum to [3][nf] (n[2] = 1 in 2D), scaled by Mf/Mc
 hipError_t launch_spec_pad(const cpx<double>* in, cpx<double>* out, int dim, const int nc[3], const int nf[3],
                            hipStream_t s);

@@ -22,14 +22,14 @@ int pw_blocks(long long M) {
 // fresh evaluation after an H_L application: energy parts, mu (2.9), alpha_l
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ __launch_bounds__(PT) void k_eval(const Slot<R>* slots, RedGeom g) {
-    const Slot<R>& S = slots[blockIdx.y];
+__global__ __launch_bounds__(PT) void k_eval(const Slot* slots, RedGeom g) {
+    const Slot& S = slots[blockIdx.y];
     SolveState* st = S.st;
     if (st->done) return;
     const Phys p = S.p;
     const long long M = p.M;
-    const cpx<R>* phi = S.buf[B_PHI];
-    const cpx<R>* hlf = S.buf[B_HL];
+    const cpx<R>* phi = fld<R>(S, B_PHI);
+    const cpx<R>* hlf = fld<R>(S, B_HL);
     double acc[NS_EVAL];
     for (int k = 0; k < NS_EVAL; ++k) acc[k] = 0.0;
     for (long long i = (long long)blockIdx.x * PT + threadIdx.x; i < M; i += (long long)gridDim.x * PT) {
@@ -64,25 +64,25 @@ __global__ __launch_bounds__(PT) void k_eval(const Slot<R>* slots, RedGeom g) {
 //   reductions: max |r| and the P^{n-1} terms of the next direction.
 // final_only: residual norm of the current iterate only (no writes, no control).
 // ---------------------------------------------------------------------------
-template <typename R>
-__global__ __launch_bounds__(PT) void k_resid(const Slot<R>* slots, RedGeom g, int final_only) {
-    const Slot<R>& S = slots[blockIdx.y];
+template <typename R, typename RD>
+__global__ __launch_bounds__(PT) void k_resid(const Slot* slots, RedGeom g, int final_only) {
+    const Slot& S = slots[blockIdx.y];
     SolveState* st = S.st;
     if (st->done && !final_only) return;
     const Phys p = S.p;
     const long long M = p.M;
-    cpx<R>* phif = S.buf[B_PHI];
-    cpx<R>* hlf = S.buf[B_HL];
-    const cpx<R>* Pf = S.buf[B_P];
-    const cpx<R>* hlpf = S.buf[B_HLP];
-    cpx<R>* uf = S.buf[B_U];
-    R* pvf = S.pv;
+    cpx<R>* phif = fld<R>(S, B_PHI);
+    cpx<R>* hlf = fld<R>(S, B_HL);
+    const cpx<RD>* Pf = fld<RD>(S, B_P);
+    const cpx<RD>* hlpf = fld<RD>(S, B_HLP);
+    cpx<RD>* uf = fld<RD>(S, B_U);
+    RD* pvv = pvf<RD>(S);
     const int pending = st->pending_step && !final_only;
     const double k0 = st->c, k1 = st->s * st->invnP, ks = st->s, k2 = st->inv_norm;
     const double mu = st->mu;
     const double al[3] = {st->alpha[0], st->alpha[1], st->alpha[2]};
     const double fl = 1e-12 * fmax(1.0, fmax(al[0], fmax(al[1], al[2])));
-    cpx<R>* r = S.buf[B_R0 + st->cur];
+    cpx<R>* r = fld<R>(S, B_R0 + st->cur);
     double acc[NS_RES] = {0.0, 0.0, 0.0, 0.0};
     for (long long i = (long long)blockIdx.x * PT + threadIdx.x; i < M; i += (long long)gridDim.x * PT) {
         double x, y, z, V2, V4;
@@ -114,9 +114,9 @@ __global__ __launch_bounds__(PT) void k_resid(const Slot<R>* slots, RedGeom g, i
             const cpx<R> rr = cmk((R)rc.x, (R)rc.y);
             r[c * M + i] = rr;
             const double d = fmax(al[c] + V2 + V4 + p.c0 * sp.rho, fl);
-            const R w = (R)(1.0 / sqrt(d));
-            pvf[c * M + i] = w;
-            uf[c * M + i] = w * rr;
+            const RD w = (RD)(1.0 / sqrt(d));
+            pvv[c * M + i] = w;
+            uf[c * M + i] = w * cvt<RD>(rr);
             const cpx<double> rw = wid(rr);
             acc[1] += re_dot(rw, P[c]);
             acc[2] += re_dot(ph[c], P[c]);
@@ -134,9 +134,9 @@ __global__ __launch_bounds__(PT) void k_resid(const Slot<R>* slots, RedGeom g, i
 // (layout in control.h, NS_LS); the kinetic coefficients come from the middle
 // pass of the H_L P^ application
 // ---------------------------------------------------------------------------
-template <typename R>
-__global__ __launch_bounds__(PT) void k_lsred(const Slot<R>* slots, RedGeom g) {
-    const Slot<R>& S = slots[blockIdx.y];
+template <typename R, typename RD>
+__global__ __launch_bounds__(PT) void k_lsred(const Slot* slots, RedGeom g) {
+    const Slot& S = slots[blockIdx.y];
     SolveState* st = S.st;
     if (st->done) return;
     const Phys p = S.p;
@@ -151,10 +151,10 @@ __global__ __launch_bounds__(PT) void k_lsred(const Slot<R>* slots, RedGeom g) {
         trap_at(p, i, x, y, z, V2, V4);
         const double V = V2 + V4;
         cpx<double> ph[3], P[3], hl[3], hp[3];
-        load3(S.buf[B_PHI], i, M, ph);
-        load3(S.buf[B_P], i, M, P);
-        load3(S.buf[B_HL], i, M, hl);
-        load3(S.buf[B_HLP], i, M, hp);
+        load3(fld<R>(S, B_PHI), i, M, ph);
+        load3(fld<RD>(S, B_P), i, M, P);
+        load3(fld<R>(S, B_HL), i, M, hl);
+        load3(fld<RD>(S, B_HLP), i, M, hp);
         for (int c = 0; c < 3; ++c) P[c] = ip * P[c];
         double n0[3], n1[3], n2[3];
         for (int c = 0; c < 3; ++c) {
@@ -211,11 +211,11 @@ __global__ __launch_bounds__(PT) void k_lsred(const Slot<R>* slots, RedGeom g) {
 // normalisation: sets the pending rescale Phi <- Phi / |Phi|
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ __launch_bounds__(PT) void k_normalize(const Slot<R>* slots, RedGeom g) {
-    const Slot<R>& S = slots[blockIdx.y];
+__global__ __launch_bounds__(PT) void k_normalize(const Slot* slots, RedGeom g) {
+    const Slot& S = slots[blockIdx.y];
     SolveState* st = S.st;
     const Phys p = S.p;
-    const cpx<R>* phi = S.buf[B_PHI];
+    const cpx<R>* phi = fld<R>(S, B_PHI);
     const long long n3 = 3 * p.M;
     double acc[1] = {0.0};
     for (long long i = (long long)blockIdx.x * PT + threadIdx.x; i < n3; i += (long long)gridDim.x * PT)
@@ -232,9 +232,8 @@ __global__ __launch_bounds__(PT) void k_normalize(const Slot<R>* slots, RedGeom 
 //   FIN_LS:     line-search rows + middle-pass rows -> ctrl_ls
 //   FIN_NORM:   |Phi|^2 rows -> rescale of Phi (pending step with s = 0)
 //   FIN_RFINAL: residual rows of a final-only residual pass
-template <typename R>
-__global__ __launch_bounds__(PT) void k_fin(const Slot<R>* slots, RedGeom g, int what) {
-    const Slot<R>& S = slots[blockIdx.y];
+__global__ __launch_bounds__(PT) void k_fin(const Slot* slots, RedGeom g, int what) {
+    const Slot& S = slots[blockIdx.y];
     SolveState* st = S.st;
     const Phys p = S.p;
     if (what != FIN_NORM && what != FIN_RFINAL && st->done) return;
@@ -297,12 +296,12 @@ __global__ void k_f2d(const cpx<float>* in, cpx<double>* out, long long n) {
 }
 
 template <typename R>
-__global__ void k_hphi(const Slot<R>* slots) {
-    const Slot<R>& S = slots[blockIdx.y];
+__global__ void k_hphi(const Slot* slots) {
+    const Slot& S = slots[blockIdx.y];
     const Phys p = S.p;
-    const cpx<R>* phi = S.buf[B_PHI];
-    const cpx<R>* hl = S.buf[B_HL];
-    cpx<R>* out = S.buf[B_X1];
+    const cpx<R>* phi = fld<R>(S, B_PHI);
+    const cpx<R>* hl = fld<R>(S, B_HL);
+    cpx<R>* out = fld<R>(S, B_X1);
     const long long M = p.M;
     for (long long i = (long long)blockIdx.x * PT + threadIdx.x; i < M; i += (long long)gridDim.x * PT) {
         cpx<double> ph[3], h[3], nl[3];
@@ -317,14 +316,14 @@ __global__ void k_hphi(const Slot<R>* slots) {
 
 // preconditioner input for a given r: pv = (alpha_l + V + c0 rho)^{-1/2}, u = pv r
 template <typename R>
-__global__ void k_pvin(const Slot<R>* slots) {
-    const Slot<R>& S = slots[blockIdx.y];
+__global__ void k_pvin(const Slot* slots) {
+    const Slot& S = slots[blockIdx.y];
     const Phys p = S.p;
     const SolveState* st = S.st;
-    const cpx<R>* phi = S.buf[B_PHI];
-    const cpx<R>* r = S.buf[B_X0];
-    R* pv = S.pv;
-    cpx<R>* u = S.buf[B_U];
+    const cpx<R>* phi = fld<R>(S, B_PHI);
+    const cpx<R>* r = fld<R>(S, B_X0);
+    R* pv = pvf<R>(S);
+    cpx<R>* u = fld<R>(S, B_U);
     const long long M = p.M;
     const double al[3] = {st->alpha[0], st->alpha[1], st->alpha[2]};
     const double fl = 1e-12 * fmax(1.0, fmax(al[0], fmax(al[1], al[2])));
@@ -385,24 +384,25 @@ __global__ void k_spec_pad(const cpx<double>* in, cpx<double>* out, int dim, int
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <typename R> hipError_t launch_eval(const Slot<R>* slots, int nslots, RedGeom g, hipStream_t s) {
+template <typename R> hipError_t launch_eval(const Slot* slots, int nslots, RedGeom g, hipStream_t s) {
     GS_LAUNCH(k_eval<R>, dim3(g.nblk_pw, nslots), dim3(PT), 0, s, slots, g);
     return hipGetLastError();
 }
-template <typename R> hipError_t launch_resid(const Slot<R>* slots, int nslots, RedGeom g, int final_only, hipStream_t s) {
-    GS_LAUNCH(k_resid<R>, dim3(g.nblk_pw, nslots), dim3(PT), 0, s, slots, g, final_only);
+template <typename R, typename RD>
+hipError_t launch_resid(const Slot* slots, int nslots, RedGeom g, int final_only, hipStream_t s) {
+    GS_LAUNCH((k_resid<R, RD>), dim3(g.nblk_pw, nslots), dim3(PT), 0, s, slots, g, final_only);
     return hipGetLastError();
 }
-template <typename R> hipError_t launch_lsred(const Slot<R>* slots, int nslots, RedGeom g, hipStream_t s) {
-    GS_LAUNCH(k_lsred<R>, dim3(g.nblk_pw, nslots), dim3(PT), 0, s, slots, g);
+template <typename R, typename RD> hipError_t launch_lsred(const Slot* slots, int nslots, RedGeom g, hipStream_t s) {
+    GS_LAUNCH((k_lsred<R, RD>), dim3(g.nblk_pw, nslots), dim3(PT), 0, s, slots, g);
     return hipGetLastError();
 }
-template <typename R> hipError_t launch_normalize(const Slot<R>* slots, int nslots, RedGeom g, hipStream_t s) {
+template <typename R> hipError_t launch_normalize(const Slot* slots, int nslots, RedGeom g, hipStream_t s) {
     GS_LAUNCH(k_normalize<R>, dim3(g.nblk_pw, nslots), dim3(PT), 0, s, slots, g);
     return hipGetLastError();
 }
-template <typename R> hipError_t launch_fin(const Slot<R>* slots, int nslots, RedGeom g, int what, hipStream_t s) {
-    GS_LAUNCH(k_fin<R>, dim3(1, nslots), dim3(PT), 0, s, slots, g, what);
+hipError_t launch_fin(const Slot* slots, int nslots, RedGeom g, int what, hipStream_t s) {
+    GS_LAUNCH(k_fin, dim3(1, nslots), dim3(PT), 0, s, slots, g, what);
     return hipGetLastError();
 }
 hipError_t launch_convert_d2f(const cpx<double>* in, cpx<float>* out, long long n, hipStream_t s) {
@@ -413,11 +413,11 @@ hipError_t launch_convert_f2d(const cpx<float>* in, cpx<double>* out, long long 
     GS_LAUNCH(k_f2d, dim3(pw_blocks(n)), dim3(PT), 0, s, in, out, n);
     return hipGetLastError();
 }
-template <typename R> hipError_t launch_hphi(const Slot<R>* slots, int nslots, RedGeom g, hipStream_t s) {
+template <typename R> hipError_t launch_hphi(const Slot* slots, int nslots, RedGeom g, hipStream_t s) {
     GS_LAUNCH(k_hphi<R>, dim3(g.nblk_pw, nslots), dim3(PT), 0, s, slots);
     return hipGetLastError();
 }
-template <typename R> hipError_t launch_pvin(const Slot<R>* slots, int nslots, RedGeom g, hipStream_t s) {
+template <typename R> hipError_t launch_pvin(const Slot* slots, int nslots, RedGeom g, hipStream_t s) {
     GS_LAUNCH(k_pvin<R>, dim3(g.nblk_pw, nslots), dim3(PT), 0, s, slots);
     return hipGetLastError();
 }
@@ -433,15 +433,18 @@ hipError_t launch_gaussian(cpx<double>* out, const Phys& p, hipStream_t s) {
     return hipGetLastError();
 }
 
-#define GS_INST(R)                                                                                    \
-    template hipError_t launch_eval<R>(const Slot<R>*, int, RedGeom, hipStream_t);                    \
-    template hipError_t launch_resid<R>(const Slot<R>*, int, RedGeom, int, hipStream_t);              \
-    template hipError_t launch_lsred<R>(const Slot<R>*, int, RedGeom, hipStream_t);                   \
-    template hipError_t launch_normalize<R>(const Slot<R>*, int, RedGeom, hipStream_t);               \
-    template hipError_t launch_fin<R>(const Slot<R>*, int, RedGeom, int, hipStream_t);                \
-    template hipError_t launch_hphi<R>(const Slot<R>*, int, RedGeom, hipStream_t);                    \
-    template hipError_t launch_pvin<R>(const Slot<R>*, int, RedGeom, hipStream_t);
+#define GS_INST(R)                                                                              \
+    template hipError_t launch_eval<R>(const Slot*, int, RedGeom, hipStream_t);                 \
+    template hipError_t launch_normalize<R>(const Slot*, int, RedGeom, hipStream_t);            \
+    template hipError_t launch_hphi<R>(const Slot*, int, RedGeom, hipStream_t);                 \
+    template hipError_t launch_pvin<R>(const Slot*, int, RedGeom, hipStream_t);
+#define GS_INST2(R, RD)                                                                         \
+    template hipError_t launch_resid<R, RD>(const Slot*, int, RedGeom, int, hipStream_t);       \
+    template hipError_t launch_lsred<R, RD>(const Slot*, int, RedGeom, hipStream_t);
 GS_INST(double)
 GS_INST(float)
+GS_INST2(double, double)
+GS_INST2(float, float)
+GS_INST2(double, float)
 
 }  // namespace gs

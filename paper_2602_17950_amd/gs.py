@@ -53,7 +53,8 @@ class gs_options(C.Structure):
     _fields_ = [("stop_kind", C.c_int), ("tol", C.c_double), ("max_iter", C.c_int),
                 ("precision", C.c_int), ("switch_resid", C.c_double), ("fp32_max_iter", C.c_int),
                 ("stall_window", C.c_int), ("theta_trial", C.c_double), ("sigma", C.c_double),
-                ("max_backtrack", C.c_int), ("check_every", C.c_int), ("cm_levels", C.c_int)]
+                ("max_backtrack", C.c_int), ("check_every", C.c_int), ("cm_levels", C.c_int),
+                ("dir_precision", C.c_int)]
 
 
 class gs_result(C.Structure):
@@ -96,7 +97,7 @@ def load():
     lib.gs_destroy.restype = None
     lib.gs_default_options.argtypes = [C.POINTER(gs_options)]
     lib.gs_default_options.restype = None
-    lib.gs_footprint_bytes.argtypes = [C.POINTER(gs_grid), C.c_int]
+    lib.gs_footprint_bytes.argtypes = [C.POINTER(gs_grid), C.POINTER(gs_options)]
     lib.gs_footprint_bytes.restype = C.c_size_t
     lib.gs_solve.argtypes = [vp, C.POINTER(gs_grid), C.POINTER(gs_trap), C.POINTER(gs_params),
                              C.POINTER(gs_options), vp, vp, C.POINTER(gs_result)]
@@ -173,9 +174,11 @@ def default_options(**kw) -> gs_options:
     return o
 
 
-def footprint_bytes(pb, precision=GS_FP64) -> int:
+def footprint_bytes(pb, precision=GS_FP64, **kw) -> int:
+    """Device bytes of a solve of pb (0 for an invalid grid or options); kw: other option fields."""
     g = grid_of(pb)
-    return int(load().gs_footprint_bytes(C.byref(g), int(precision)))
+    o = default_options(precision=precision, **kw)
+    return int(load().gs_footprint_bytes(C.byref(g), C.byref(o)))
 
 
 def make_request(pb, psi0, out, options: gs_options | None = None, V=None):

@@ -65,6 +65,11 @@ def test_default_options_and_footprint():
     assert field * 16 + 3 * M * 8 <= b64 <= field * 16 + 3 * M * 8 + 2 * 2 ** 20
     assert field * 8 + 3 * M * 4 <= b32 <= field * 8 + 3 * M * 4 + 2 * 2 ** 20
     assert gs.footprint_bytes(pb, gs.GS_MIXED) == b64 + b32
+    # double state, float direction: Pr, P, H_L P^, u and the P_V factors halve
+    bmx = gs.footprint_bytes(pb, gs.GS_FP64, dir_precision=gs.GS_FP32)
+    assert abs(b64 - bmx - (4 * field // 2 + 3 * M * 4)) <= 2 ** 20   # reduction rows differ slightly
+    assert gs.footprint_bytes(pb, gs.GS_MIXED, dir_precision=gs.GS_FP32) == bmx + b32
+    assert gs.footprint_bytes(pb, gs.GS_FP64, dir_precision=7) == 0
     bad = inputs.Problem(dim=2, n=(48, 64), L=(12.0, 12.0))
     assert gs.footprint_bytes(bad, gs.GS_FP64) == 0
     pb3 = inputs.Problem(dim=3, n=(128, 128, 128), L=(8.0, 8.0, 8.0))

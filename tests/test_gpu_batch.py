@@ -54,10 +54,11 @@ def same_bits(a, b):
     return torch.equal(a.view(torch.float64), b.view(torch.float64))
 
 
-@pytest.mark.parametrize("precision", [gs.GS_FP64, gs.GS_MIXED])
-def test_batch_equals_alone_bitwise(gpu_ctx, precision):
-    print(f"[batch] precision={precision}", flush=True)
-    opt = gs.default_options(precision=precision, tol=1e-11, switch_resid=1e-4)
+@pytest.mark.parametrize("precision,dirp", [(gs.GS_FP64, gs.GS_FP64), (gs.GS_MIXED, gs.GS_FP64),
+                                           (gs.GS_FP64, gs.GS_FP32), (gs.GS_MIXED, gs.GS_FP32)])
+def test_batch_equals_alone_bitwise(gpu_ctx, precision, dirp):
+    print(f"[batch] precision={precision} dir_precision={dirp}", flush=True)
+    opt = gs.default_options(precision=precision, tol=1e-11, switch_resid=1e-4, dir_precision=dirp)
     probs = problems()
     ref = [alone(gpu_ctx, pb, psi0, opt) for pb, psi0 in probs]
     outs = [torch.empty((3,) + pb.shape, dtype=torch.complex128, device=DEV) for pb, _ in probs]

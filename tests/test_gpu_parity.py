@@ -190,6 +190,39 @@ def test_solve_mixed_matches_fp64(gpu_ctx):
     assert rel(r32["E"], r64["E"]) < 1e-6
 
 
+@pytest.mark.parametrize("which", ["small2d", "vortex64", "3d16"])
+def test_solve_fp32_direction_matches_oracle(gpu_ctx, which):
+    """Double state with a float search direction (dir_precision GS_FP32): the
+    residual, the line search and the stopping test stay double, so the limit
+    is the FP64 one; E and mu are held to the FP64 solves' bars against the
+    oracle, both sides stopping on the residual."""
+    if which == "small2d":
+        pb, psi0 = inputs.workload_small_2d()
+        tol = 1e-11
+    elif which == "vortex64":
+        pb, psi0 = inputs.workload_vortex_2d(n=64)
+        tol = 1e-9
+    else:
+        pb = inputs.Problem(dim=3, n=(16, 16, 16), L=(6.0, 6.0, 6.0), g=(1.0, 1.0, 2.0), omega=0.5,
+                            gamma=1.0, c0=200.0, c1=5.0)
+        psi0 = inputs.initial_guess(pb, ("a", "a", "a"))
+        tol = 1e-10
+    g, t, p = orc(pb)
+    ref = O.pcg(g, t, p, psi0, O.Options(stop_kind=gs.GS_STOP_RESIDUAL, tol=tol))
+    ev = O.evaluate(g, t, p, ref.psi)
+    for prec in (gs.GS_FP64, gs.GS_MIXED):
+        opt = gs.default_options(precision=prec, stop_kind=gs.GS_STOP_RESIDUAL, tol=tol,
+                                 dir_precision=gs.GS_FP32, switch_resid=1e-4)
+        psi, res = gpu_ctx.solve(pb, psi0, opt)
+        print(f"[fp32 dir {which} prec={prec}] gpu E={res['E']!r} mu={res['mu']!r} it={res['iters']} "
+              f"| oracle E={ev['E']!r} mu={ev['mu']!r} it={ref.iters}", flush=True)
+        assert res["status"] == 0 and ref.status == 0
+        assert res["resid_inf"] < tol
+        assert rel(res["E"], ev["E"]) < 1e-10
+        assert rel(res["mu"], ev["mu"]) < 1e-8
+        assert abs(sum(res["norm_comp"]) - 1.0) < 1e-13
+
+
 def test_solve_3d_small(gpu_ctx):
     pb = inputs.Problem(dim=3, n=(16, 16, 16), L=(6.0, 6.0, 6.0), g=(1.0, 1.0, 2.0), omega=0.5,
                         gamma=1.0, c0=200.0, c1=5.0)
