@@ -132,6 +132,8 @@ def main():
     ap.add_argument("--batch", type=int, default=32, help="solves per headline step")
     ap.add_argument("--n", type=int, default=256, help="grid points per axis of the headline workload")
     ap.add_argument("--kernel", default="hl_mid", help="kernel kind timed for the roofline")
+    ap.add_argument("--mixed-dir", choices=("fp32", "fp64"), default="fp32",
+                    help="direction precision of the double phase of mixed solves")
     ap.add_argument("--sections", default=",".join(SECTIONS))
     ap.add_argument("--serve-requests", type=int, default=32)
     ap.add_argument("--serve-load", type=float, default=0.5, help="arrival rate / measured sweep capacity")
@@ -164,7 +166,8 @@ def main():
 
     ctx = gs.Context(0)
     o64 = gs.default_options(precision=gs.GS_FP64, tol=TOL)
-    omx = gs.default_options(precision=gs.GS_MIXED, tol=TOL)
+    mdir = gs.GS_FP32 if args.mixed_dir == "fp32" else gs.GS_FP64
+    omx = gs.default_options(precision=gs.GS_MIXED, tol=TOL, dir_precision=mdir)
     line = {"metric": METRIC, "value": None, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "fp32->fp64", "data": "synthetic"}
@@ -264,7 +267,8 @@ def main():
         out3 = torch.empty((3,) + pb3.shape, dtype=torch.complex128, device="cuda")
         cm = {}
         for name, prec in (("fp64", gs.GS_FP64), ("mixed", gs.GS_MIXED)):
-            opt = gs.default_options(precision=prec, tol=1e-12, cm_levels=3)
+            opt = gs.default_options(precision=prec, tol=1e-12, cm_levels=3,
+                                     dir_precision=mdir if prec == gs.GS_MIXED else gs.GS_FP64)
             t = time.perf_counter()
             r = ctx.solve_device(pb3, g3, out3, opt)
             cm[name] = {"s": time.perf_counter() - t, "E": r["E"], "mu": r["mu"], "iters_fine": r["iters"],
@@ -285,7 +289,8 @@ def main():
         out = {}
         E = {}
         for name, prec in (("fp64", gs.GS_FP64), ("mixed", gs.GS_MIXED)):
-            opt = gs.default_options(precision=prec, tol=1e-12)
+            opt = gs.default_options(precision=prec, tol=1e-12,
+                                     dir_precision=mdir if prec == gs.GS_MIXED else gs.GS_FP64)
             t = time.perf_counter()
             rs = ctx.batch_solve(sw.requests(opt))
             dt = time.perf_counter() - t
@@ -314,7 +319,7 @@ def main():
         sv = Batch(torch, [(pb, inputs.initial_guess(pb, k)) for pb, k in spec])
         rng = np.random.default_rng(2603)
         arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(spec)))
-        opt = gs.default_options(precision=gs.GS_MIXED, tol=1e-12)
+        opt = gs.default_options(precision=gs.GS_MIXED, tol=1e-12, dir_precision=mdir)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         pending, tickets, done = 0, {}, {}
@@ -359,7 +364,9 @@ def main():
         "workload": (f"2D {args.n}x{args.n} on [-12,12]^2, harmonic trap, Omega=0.6, SOC 1.0, c0=500, c1=-2, "
                      "guess ((x+iy)phi_a, phi_a, phi_a)+1e-3 noise; a step = one batch of "
                      f"{args.batch} solves (noise seeds 2602..{2601 + args.batch}), energy criterion 1e-14; "
-                     "mixed FP32->FP64 PCG, counted against plain FP64 PCG of the same seed"),
+                     "mixed FP32->FP64 PCG (double phase with a float search direction: "
+                     f"{args.mixed_dir == 'fp32'}), counted against plain FP64 PCG of the same seed"),
+        "mixed_dir_precision": args.mixed_dir,
         "parallelism": "single GPU; the solves of a batch share every kernel launch",
     }
     line["kernel_source_sha256_16"] = kernel_source_hash()

@@ -139,7 +139,8 @@ __device__ inline void ctrl_dir(SolveState* st, const Phys& p, const double (&s)
 //    c0 rho |phi_l|^2 is quartic with coefficients T0..T4.
 // The second-order expansion of the energy change gives a_n, b_n of
 // eqs. (3.7)-(3.8); the same polynomial evaluates every trial step.
-// s[0] Re<H_L P^,P^>  s[1] Re<H_L Phi,P^>  s[2] |P^|^2  s[3] Re<Phi,P^>
+// s[0] Re<H_L P^,P^>  s[1] Re<H_L Phi,P^>  s[2], s[3] unused (|P^|^2 and Re<Phi,P^>
+// are the sums of n2_l and n1_l)
 // s[4..8] I01 I02 I11 I21 I22   s[9] I00
 // s[10..12] n0_l  s[13..15] n1_l  s[16..18] n2_l  s[19..21] V0_l  s[22..24] V1_l  s[25..27] V2_l
 // s[28+5l+j] T_j,l (j = 0..4)
@@ -172,7 +173,8 @@ __device__ __forceinline__ double dE_at(double c, double s, const LsPoly& k) {
 
 __device__ inline void ctrl_ls(SolveState* st, const Phys& p, const double (&s)[NS_LS], const double (&kin)[NS_KIN]) {
     const double h = p.cell, kM = h / (double)p.M;
-    const double Cq = s[0] * h, B = s[1] * h, PhPh = s[2] * h, phiPh = s[3] * h;
+    const double Cq = s[0] * h, B = s[1] * h;
+    const double PhPh = (s[16] + s[17] + s[18]) * h, phiPh = (s[13] + s[14] + s[15]) * h;
     const double I[5] = {s[4] * h, s[5] * h, s[6] * h, s[7] * h, s[8] * h};
     const double I00 = s[9] * h;
     const LsPoly K{st->norm2, st->lin, B, Cq, phiPh, PhPh, I00, {I[0], I[1], I[2], I[3], I[4]}};

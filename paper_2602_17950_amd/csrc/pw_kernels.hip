@@ -135,7 +135,7 @@ __global__ __launch_bounds__(PT) void k_resid(const Slot* slots, RedGeom g, int 
 // pass of the H_L P^ application
 // ---------------------------------------------------------------------------
 template <typename R, typename RD>
-__global__ __launch_bounds__(PT) void k_lsred(const Slot* slots, RedGeom g) {
+__global__ __launch_bounds__(PT, 3) void k_lsred(const Slot* slots, RedGeom g) {
     const Slot& S = slots[blockIdx.y];
     SolveState* st = S.st;
     if (st->done) return;
@@ -165,8 +165,6 @@ __global__ __launch_bounds__(PT) void k_lsred(const Slot* slots, RedGeom g) {
             n2[c] = cabs2(P[c]);
         }
         const double q0r = n0[0] + n0[1] + n0[2], q1r = n1[0] + n1[1] + n1[2], q2r = n2[0] + n2[1] + n2[2];
-        acc[2] += q2r;
-        acc[3] += q1r;
         double F0[3], F1[3], F2[3];
         spin_bil(ph, ph, F0);
         spin_bil(ph, P, F1);

@@ -40,12 +40,14 @@ def _check_against_oracle(pb, psi, r, tol_E=1e-12, tol_mu=1e-10):
     return ev
 
 
-def test_batched_256_vortex_states_match_oracle(gpu_ctx):
+@pytest.mark.parametrize("prec,dirp", [(gs.GS_FP64, gs.GS_FP64), (gs.GS_MIXED, gs.GS_FP32)])
+def test_batched_256_vortex_states_match_oracle(gpu_ctx, prec, dirp):
     """Four seeds of the 256^2 rotating workload solved in one batch (one grid
-    class, every launch shared), FP64 to the paper's energy criterion 1e-14."""
+    class, every launch shared) to the paper's energy criterion 1e-14: plain
+    FP64, and mixed with a float direction in its double phase."""
     O.set_threads(16)
     work = [inputs.workload_vortex_2d(seed=2602 + i) for i in range(4)]
-    opt = gs.default_options(precision=gs.GS_FP64, tol=1e-14)
+    opt = gs.default_options(precision=prec, tol=1e-14, dir_precision=dirp)
     outs = [torch.empty((3,) + pb.shape, dtype=torch.complex128, device=DEV) for pb, _ in work]
     res = gpu_ctx.batch_solve([(pb, torch.from_numpy(p0).to(DEV), o, opt, None)
                                for (pb, p0), o in zip(work, outs)])
