@@ -88,7 +88,7 @@ __device__ __forceinline__ void halve_all(double* v, int lane) {
 // power of two, instead of 6 NV), the four wave totals of each value added in
 // a fixed order, and the row stored by NV threads at once.
 template <int NV, int NTB = PT>
-__device__ __forceinline__ void block_row(const double (&acc)[NV], double* rows, int stride) {
+__device__ __forceinline__ void block_row(const double (&acc)[NV], double* rows, int stride, int row) {
     constexpr int P = Pow2Ceil<NV>::v;
     static_assert(P <= 64, "at most 64 sums per row");
     static_assert(NTB % 64 == 0 && NTB <= 1024, "whole waves");
@@ -104,8 +104,12 @@ __device__ __forceinline__ void block_row(const double (&acc)[NV], double* rows,
     if (threadIdx.x < NV) {
         double t = sh[0][threadIdx.x];
         for (int w = 1; w < NTB / 64; ++w) t += sh[w][threadIdx.x];
-        rows[(long long)blockIdx.x * stride + threadIdx.x] = t;
+        rows[(long long)row * stride + threadIdx.x] = t;
     }
+}
+template <int NV, int NTB = PT>
+__device__ __forceinline__ void block_row(const double (&acc)[NV], double* rows, int stride) {
+    block_row<NV, NTB>(acc, rows, stride, (int)blockIdx.x);
 }
 
 // Totals over nrows rows (fixed order) of NV values at the given stride, on

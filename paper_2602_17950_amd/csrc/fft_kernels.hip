@@ -164,8 +164,15 @@ __device__ __forceinline__ void fft_pass(cpx<R>* buf, const cpx<R>* __restrict__
 #pragma unroll
             for (int r = 0; r < RAD; ++r) v[i][r] = src[lx(j + r * NB)];
             if constexpr (NS > 1) {
+                // w^r as a running product of one table value (at most 15
+                // products: relative error ~ RAD ulp)
+                const cpx<R> w1 = twid<R, INV>(tw, k * TWS);
+                cpx<R> w = w1;
 #pragma unroll
-                for (int r = 1; r < RAD; ++r) v[i][r] = cmul(v[i][r], twid<R, INV>(tw, r * k * TWS));
+                for (int r = 1; r < RAD; ++r) {
+                    v[i][r] = cmul(v[i][r], w);
+                    if (r + 1 < RAD) w = cmul(w, w1);
+                }
             }
             dftr<R, RAD, INV>(v[i]);
             lb[i] = l * P;
@@ -426,9 +433,58 @@ __global__ __launch_bounds__(NT) void k_invT_pre(const Slot* __restrict__ slots,
 //   MID_HLX: as MID_HL for v = P^, and in2 holds the spectrum of Phi: block sums
 //            of 1/2|k|^2 |Phi^_l|^2, 1/2|k|^2 Re Phi^_l conj(v_l), 1/2|k|^2 |v_l|^2.
 //   MID_PRE: A = v_l / (alpha_l + 1/2 |k|^2) / M.
+// Values per thread of a middle pass over NLN lines, and whether the block
+// pipelines its line groups: the next group's input is loaded into registers
+// while the current one is transformed (when that takes at most 6 values).
+template <typename R, int N, int LPB, int OP, int NT> struct MidPlan {
+    static constexpr int NLN = 3 * LPB;
+    static constexpr int EPT = (NLN * N + NT - 1) / NT;
+    static constexpr bool PIPE = EPT * (OP == MID_HLX ? 2 : 1) <= 6;
+    // LDS copy of the input for the 2D rotation term when three line groups fit in 64 KB
+    static constexpr bool CLDS = 3 * NLN * Lay<N>::P * (int)sizeof(cpx<R>) <= 65536;
+};
+
+// one complex value as a single vector access (keeps register arrays of
+// complex values out of private memory)
+template <typename R> using vec2 = R __attribute__((ext_vector_type(2)));
+template <typename R> __device__ __forceinline__ void ld2(cpx<R>& d, const cpx<R>* p) {
+    const vec2<R> v = *reinterpret_cast<const vec2<R>*>(p);
+    d.x = v.x;
+    d.y = v.y;
+}
+template <typename R> __device__ __forceinline__ void st2(cpx<R>* p, const cpx<R>& a) {
+    vec2<R> v;
+    v.x = a.x;
+    v.y = a.y;
+    *reinterpret_cast<vec2<R>*>(p) = v;
+}
+
+template <typename R, int N, int LPB, int OP, int NT>
+__device__ __forceinline__ void mid_fetch(const cpx<R>* __restrict__ in, const cpx<R>* __restrict__ in2,
+                                          long long cs, int l0, cpx<R> (&a)[MidPlan<R, N, LPB, OP, NT>::EPT],
+                                          cpx<R> (&b)[MidPlan<R, N, LPB, OP, NT>::EPT]) {
+    using MP = MidPlan<R, N, LPB, OP, NT>;
+#pragma unroll
+    for (int i = 0; i < MP::EPT; ++i) {
+        const int e = threadIdx.x + i * NT;
+        if (MP::NLN * N % NT == 0 || e < MP::NLN * N) {
+            const int L = e / N, m = e - L * N;
+            const int c = L / LPB, q = L - c * LPB;
+            const long long gi = c * cs + (long long)(l0 + q) * N + m;
+            ld2(a[i], in + gi);
+            if (OP == MID_HLX) ld2(b[i], in2 + gi);
+        }
+    }
+}
+
+// Middle pass: FFT along the contiguous axis of NLN = 3 LPB lines (the three
+// components of LPB line positions), the spectral operator, inverse FFT.
+// Block b of a slot takes line groups b, b + gridDim.x, ...; every group
+// writes its own partial-sum row, so the sums do not depend on the grid.
 template <typename R, int N, int LPB, int OP, int NT>
 __global__ __launch_bounds__(NT) void k_mid(const Slot* __restrict__ slots, int iin, int ioutA, int ioutB,
                                             int nlines, int rot_any, const cpx<R>* __restrict__ tw) {
+    using MP = MidPlan<R, N, LPB, OP, NT>;
     const Slot& S = slots[blockIdx.y];
     const SolveState* st = S.st;
     if (st->done) return;
@@ -440,7 +496,8 @@ __global__ __launch_bounds__(NT) void k_mid(const Slot* __restrict__ slots, int 
     cpx<R>* __restrict__ outB = ioutB >= 0 ? fld<R>(S, ioutB) : nullptr;
     double* __restrict__ red = S.red_mid;
     constexpr int PITCH = Lay<N>::P;
-    constexpr int NLN = 3 * LPB;
+    constexpr int NLN = MP::NLN;
+    constexpr int EPT = MP::EPT;
     constexpr bool HL = OP == MID_HL || OP == MID_HLX;
     constexpr bool X2 = OP == MID_HLX;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
@@ -449,132 +506,137 @@ __global__ __launch_bounds__(NT) void k_mid(const Slot* __restrict__ slots, int 
     // rotation output B; with MID_HLX it takes Z's place (each point's Z values
     // are read by the thread that then writes its B values)
     cpx<R>* Y = X + NLN * PITCH;
+    cpx<R>* Cp = X + 2 * NLN * PITCH;                  // input copy for the 2D rotation term
     const bool doB = HL && rot;
     const bool rot2d = doB && p.dim == 2;
-    const int l0 = blockIdx.x * LPB;
     const long long cs = (long long)nlines * N;
-    // the input values stay in registers for the 2D rotation term of the
-    // epilogue when a thread holds few of them (else they are read again)
-    constexpr int EPT = (NLN * N + NT - 1) / NT;
-    constexpr bool KEEP = EPT <= 4;
+    const int ngroups = nlines / LPB;
     // transforms of two line groups at once when a thread then holds at most
     // 8 (double) or 16 (float) values
     constexpr bool JOINT = 2 * NLN * N <= (sizeof(R) == 8 ? 8 : 16) * NT;
-    cpx<R> keep[KEEP ? EPT : 1];
-#pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-        const int e = threadIdx.x + i * NT;
-        if (NLN * N % NT == 0 || e < NLN * N) {
-            const int L = e / N, m = e - L * N;
-            const int c = L / LPB, q = L - c * LPB;
-            const long long gi = c * cs + (long long)(l0 + q) * N + m;
-            const cpx<R> x = in[gi];
-            if constexpr (KEEP) keep[i] = x;
-            X[L * PITCH + lx(m)] = x;
-            if (X2) Z[L * PITCH + lx(m)] = in2[gi];
-        }
-    }
-    __syncthreads();
-    if constexpr (X2 && JOINT) {
-        lds_fft<R, N, 2 * NLN, NT, false>(X, tw);   // X and Z are adjacent
-    } else {
-        lds_fft<R, N, NLN, NT, false>(X, tw);
-        if constexpr (X2) lds_fft<R, N, NLN, NT, false>(Z, tw);
-    }
+    cpx<R> pa[EPT], pb[EPT];
+    int grp = blockIdx.x;
+    if (MP::PIPE && grp < ngroups) mid_fetch<R, N, LPB, OP, NT>(in, in2, cs, grp * LPB, pa, pb);
     const double invM = 1.0 / (double)p.M;
-    double acc[X2 ? NS_KIN : 4];
-    for (int k = 0; k < (X2 ? NS_KIN : 4); ++k) acc[k] = 0.0;
     double al[3] = {0.0, 0.0, 0.0}, fl = 0.0;
     if (OP == MID_PRE) {
         al[0] = st->alpha[0]; al[1] = st->alpha[1]; al[2] = st->alpha[2];
         fl = 1e-12 * fmax(1.0, fmax(al[0], fmax(al[1], al[2])));
     }
-    for (int e = threadIdx.x; e < LPB * N; e += NT) {
-        const int q = e / N, m = e - q * N;
-        const int line = l0 + q;
-        double kx, ky, kz;
-        if (p.dim == 2) {
-            kx = wavenum(line, p.n[0], p.L[0]);
-            ky = wavenum(m, p.n[1], p.L[1]);
-            kz = 0.0;
-        } else {
-            kx = wavenum(line % p.n[0], p.n[0], p.L[0]);
-            ky = wavenum(line / p.n[0], p.n[1], p.L[1]);
-            kz = wavenum(m, p.n[2], p.L[2]);
-        }
-        const double K = 0.5 * (kx * kx + ky * ky + kz * kz);
-        cpx<R>* x0 = X + (0 * LPB + q) * PITCH + lx(m);
-        cpx<R>* x1 = X + (1 * LPB + q) * PITCH + lx(m);
-        cpx<R>* x2 = X + (2 * LPB + q) * PITCH + lx(m);
-        if (HL) {
-            const cpx<double> v0 = wid(*x0), v1 = wid(*x1), v2 = wid(*x2);
-            const cpx<double> s0 = cmk(-kx, ky), s1 = cmk(-kx, -ky);
-            const cpx<double> S0 = cmul(s0, v1);
-            const cpx<double> S1 = cmul(s1, v0) + cmul(s0, v2);
-            const cpx<double> S2 = cmul(s1, v1);
-            if (X2) {
-                const cpx<double> v[3] = {v0, v1, v2};
-                for (int cc = 0; cc < 3; ++cc) {
-                    const cpx<double> z = wid(Z[(cc * LPB + q) * PITCH + lx(m)]);
-                    acc[3 * cc] += K * cabs2(z);
-                    acc[3 * cc + 1] += K * re_dot(z, v[cc]);
-                    acc[3 * cc + 2] += K * cabs2(v[cc]);
-                }
-            } else {
-                acc[0] += K * cabs2(v0);
-                acc[1] += K * cabs2(v1);
-                acc[2] += K * cabs2(v2);
-                acc[3] += cmulc(S0, v0).x + cmulc(S1, v1).x + cmulc(S2, v2).x;
-            }
-            const double gm = p.gamma;
-            const cpx<double> a0 = invM * (K * v0 - gm * S0);
-            const cpx<double> a1 = invM * (K * v1 - gm * S1);
-            const cpx<double> a2 = invM * (K * v2 - gm * S2);
-            if (doB) {
-                const double fb = ky * invM;
-                Y[(0 * LPB + q) * PITCH + lx(m)] = cmk((R)(fb * v0.x), (R)(fb * v0.y));
-                Y[(1 * LPB + q) * PITCH + lx(m)] = cmk((R)(fb * v1.x), (R)(fb * v1.y));
-                Y[(2 * LPB + q) * PITCH + lx(m)] = cmk((R)(fb * v2.x), (R)(fb * v2.y));
-            }
-            *x0 = cmk((R)a0.x, (R)a0.y);
-            *x1 = cmk((R)a1.x, (R)a1.y);
-            *x2 = cmk((R)a2.x, (R)a2.y);
-        } else {
-            const R d0 = (R)(invM / fmax(al[0] + K, fl));
-            const R d1 = (R)(invM / fmax(al[1] + K, fl));
-            const R d2 = (R)(invM / fmax(al[2] + K, fl));
-            *x0 = d0 * *x0;
-            *x1 = d1 * *x1;
-            *x2 = d2 * *x2;
-        }
-    }
-    __syncthreads();
-    if constexpr (HL && JOINT) {
-        if (doB) lds_fft<R, N, 2 * NLN, NT, true>(X, tw);   // X and Y are adjacent
-        else lds_fft<R, N, NLN, NT, true>(X, tw);
-    } else {
-        lds_fft<R, N, NLN, NT, true>(X, tw);
-        if (doB) lds_fft<R, N, NLN, NT, true>(Y, tw);
-    }
+    for (; grp < ngroups; grp += gridDim.x) {
+        const int l0 = grp * LPB;
+        if (!MP::PIPE) mid_fetch<R, N, LPB, OP, NT>(in, in2, cs, l0, pa, pb);
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-        const int e = threadIdx.x + i * NT;
-        if (NLN * N % NT == 0 || e < NLN * N) {
-            const int L = e / N, m = e - L * N;
-            const int c = L / LPB, q = L - c * LPB;
-            const long long go = c * cs + (long long)(l0 + q) * N + m;
-            cpx<R> v = X[L * PITCH + lx(m)];
-            if (rot2d) {
-                const double kx = wavenum(l0 + q, p.n[0], p.L[0]);
-                const double y = -p.L[1] + m * p.h[1];
-                const cpx<R> x = KEEP ? keep[KEEP ? i : 0] : in[go];
-                v = v + (R)(p.omega * y * kx / p.n[0]) * x;
+        for (int i = 0; i < EPT; ++i) {
+            const int e = threadIdx.x + i * NT;
+            if (NLN * N % NT == 0 || e < NLN * N) {
+                const int L = e / N, m = e - L * N;
+                st2(X + L * PITCH + lx(m), pa[i]);
+                if (X2) st2(Z + L * PITCH + lx(m), pb[i]);
+                if (MP::CLDS && rot2d) st2(Cp + L * PITCH + lx(m), pa[i]);
             }
-            outA[go] = v;
-            if (doB) outB[go] = Y[L * PITCH + lx(m)];
         }
+        __syncthreads();
+        if (MP::PIPE && grp + (int)gridDim.x < ngroups)
+            mid_fetch<R, N, LPB, OP, NT>(in, in2, cs, (grp + gridDim.x) * LPB, pa, pb);
+        if constexpr (X2 && JOINT) {
+            lds_fft<R, N, 2 * NLN, NT, false>(X, tw);   // X and Z are adjacent
+        } else {
+            lds_fft<R, N, NLN, NT, false>(X, tw);
+            if constexpr (X2) lds_fft<R, N, NLN, NT, false>(Z, tw);
+        }
+        double acc[X2 ? NS_KIN : 4];
+#pragma unroll
+        for (int k = 0; k < (X2 ? NS_KIN : 4); ++k) acc[k] = 0.0;
+        for (int e = threadIdx.x; e < LPB * N; e += NT) {
+            const int q = e / N, m = e - q * N;
+            const int line = l0 + q;
+            double kx, ky, kz;
+            if (p.dim == 2) {
+                kx = wavenum(line, p.n[0], p.L[0]);
+                ky = wavenum(m, p.n[1], p.L[1]);
+                kz = 0.0;
+            } else {
+                kx = wavenum(line % p.n[0], p.n[0], p.L[0]);
+                ky = wavenum(line / p.n[0], p.n[1], p.L[1]);
+                kz = wavenum(m, p.n[2], p.L[2]);
+            }
+            const double K = 0.5 * (kx * kx + ky * ky + kz * kz);
+            cpx<R>* x0 = X + (0 * LPB + q) * PITCH + lx(m);
+            cpx<R>* x1 = X + (1 * LPB + q) * PITCH + lx(m);
+            cpx<R>* x2 = X + (2 * LPB + q) * PITCH + lx(m);
+            if (HL) {
+                const cpx<double> v0 = wid(*x0), v1 = wid(*x1), v2 = wid(*x2);
+                const cpx<double> s0 = cmk(-kx, ky), s1 = cmk(-kx, -ky);
+                const cpx<double> S0 = cmul(s0, v1);
+                const cpx<double> S1 = cmul(s1, v0) + cmul(s0, v2);
+                const cpx<double> S2 = cmul(s1, v1);
+                if (X2) {
+                    const cpx<double> v[3] = {v0, v1, v2};
+#pragma unroll
+                    for (int cc = 0; cc < 3; ++cc) {
+                        const cpx<double> z = wid(Z[(cc * LPB + q) * PITCH + lx(m)]);
+                        acc[3 * cc] += K * cabs2(z);
+                        acc[3 * cc + 1] += K * re_dot(z, v[cc]);
+                        acc[3 * cc + 2] += K * cabs2(v[cc]);
+                    }
+                } else {
+                    acc[0] += K * cabs2(v0);
+                    acc[1] += K * cabs2(v1);
+                    acc[2] += K * cabs2(v2);
+                    acc[3] += cmulc(S0, v0).x + cmulc(S1, v1).x + cmulc(S2, v2).x;
+                }
+                const double gm = p.gamma;
+                const cpx<double> a0 = invM * (K * v0 - gm * S0);
+                const cpx<double> a1 = invM * (K * v1 - gm * S1);
+                const cpx<double> a2 = invM * (K * v2 - gm * S2);
+                if (doB) {
+                    const double fb = ky * invM;
+                    Y[(0 * LPB + q) * PITCH + lx(m)] = cmk((R)(fb * v0.x), (R)(fb * v0.y));
+                    Y[(1 * LPB + q) * PITCH + lx(m)] = cmk((R)(fb * v1.x), (R)(fb * v1.y));
+                    Y[(2 * LPB + q) * PITCH + lx(m)] = cmk((R)(fb * v2.x), (R)(fb * v2.y));
+                }
+                *x0 = cmk((R)a0.x, (R)a0.y);
+                *x1 = cmk((R)a1.x, (R)a1.y);
+                *x2 = cmk((R)a2.x, (R)a2.y);
+            } else {
+                const R d0 = (R)(invM / fmax(al[0] + K, fl));
+                const R d1 = (R)(invM / fmax(al[1] + K, fl));
+                const R d2 = (R)(invM / fmax(al[2] + K, fl));
+                *x0 = d0 * *x0;
+                *x1 = d1 * *x1;
+                *x2 = d2 * *x2;
+            }
+        }
+        __syncthreads();
+        if constexpr (HL && JOINT) {
+            if (doB) lds_fft<R, N, 2 * NLN, NT, true>(X, tw);   // X and Y are adjacent
+            else lds_fft<R, N, NLN, NT, true>(X, tw);
+        } else {
+            lds_fft<R, N, NLN, NT, true>(X, tw);
+            if (doB) lds_fft<R, N, NLN, NT, true>(Y, tw);
+        }
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            const int e = threadIdx.x + i * NT;
+            if (NLN * N % NT == 0 || e < NLN * N) {
+                const int L = e / N, m = e - L * N;
+                const int c = L / LPB, q = L - c * LPB;
+                const long long go = c * cs + (long long)(l0 + q) * N + m;
+                cpx<R> v = X[L * PITCH + lx(m)];
+                if (rot2d) {
+                    const double kx = wavenum(l0 + q, p.n[0], p.L[0]);
+                    const double y = -p.L[1] + m * p.h[1];
+                    const cpx<R> x = MP::CLDS ? Cp[L * PITCH + lx(m)] : in[go];
+                    v = v + (R)(p.omega * y * kx / p.n[0]) * x;
+                }
+                outA[go] = v;
+                if (doB) outB[go] = Y[L * PITCH + lx(m)];
+            }
+        }
+        if (HL) block_row<(X2 ? NS_KIN : 4), NT>(acc, red, RED_MID_STRIDE, grp);
+        __syncthreads();   // X, Z, Y and the copy are refilled by the next group
     }
-    if (HL) block_row<(X2 ? NS_KIN : 4), NT>(acc, red, RED_MID_STRIDE);
 }
 
 // ---------------------------------------------------------------------------
@@ -669,22 +731,54 @@ static hipError_t invT_pre_n(const Slot* slots, int nslots, int in, int out, int
     return hipGetLastError();
 }
 
+// Blocks per slot of a middle pass: one per line group, or, for a pipelined
+// kernel, as many as fill the device once (every resident block then loops
+// over several groups; the occupancy is queried once per kernel).
+static int cu_count() {
+    static int n = 0;
+    if (!n) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+            n = 256;
+    }
+    return n;
+}
+template <auto KERNEL, typename MP, typename... Args>
+static hipError_t mid_go(int ngroups, int nslots, int ntb, size_t lds, hipStream_t s, Args... args) {
+    int G = ngroups;
+    if (MP::PIPE) {
+        static int per_cu = -1;
+        if (per_cu < 0) {
+            int nb = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, KERNEL, ntb, lds) != hipSuccess || nb <= 0) nb = 1;
+            per_cu = nb;
+        }
+        const long long resident = (long long)per_cu * cu_count();
+        G = (int)std::min<long long>(ngroups, std::max<long long>(1, (resident + nslots - 1) / nslots));
+    }
+    GS_LAUNCH(KERNEL, dim3((unsigned)G, (unsigned)nslots), dim3(ntb), lds, s, args...);
+    return hipGetLastError();
+}
+
 template <typename R, int N>
 static hipError_t mid_n(int op, const Slot* slots, int nslots, int in, int outA, int outB, int nlines,
                         int rot_any, const cpx<R>* tw, hipStream_t s) {
     constexpr int LPB = lpb_mid(N);
     constexpr int NTB = nt_mid<R>(N);
     if (nlines % LPB) return hipErrorInvalidValue;
-    const int nbuf = (op == MID_HLX || (op == MID_HL && rot_any)) ? 2 : 1;
-    const size_t lds = (size_t)nbuf * 3 * LPB * Lay<N>::P * sizeof(cpx<R>);
-    dim3 grid((unsigned)(nlines / LPB), (unsigned)nslots);
+    const int ngroups = nlines / LPB;
+    const size_t buf = (size_t)3 * LPB * Lay<N>::P * sizeof(cpx<R>);
     if (op == MID_HL)
-        GS_LAUNCH((k_mid<R, N, LPB, MID_HL, NTB>), grid, dim3(NTB), lds, s, slots, in, outA, outB, nlines, rot_any, tw);
-    else if (op == MID_HLX)
-        GS_LAUNCH((k_mid<R, N, LPB, MID_HLX, NTB>), grid, dim3(NTB), lds, s, slots, in, outA, outB, nlines, rot_any, tw);
-    else
-        GS_LAUNCH((k_mid<R, N, LPB, MID_PRE, NTB>), grid, dim3(NTB), lds, s, slots, in, outA, outB, nlines, 0, tw);
-    return hipGetLastError();
+        return mid_go<k_mid<R, N, LPB, MID_HL, NTB>, MidPlan<R, N, LPB, MID_HL, NTB>>(
+            ngroups, nslots, NTB, (rot_any ? 2 + MidPlan<R, N, LPB, MID_HL, NTB>::CLDS : 1) * buf, s, slots, in,
+            outA, outB, nlines, rot_any, tw);
+    if (op == MID_HLX)
+        return mid_go<k_mid<R, N, LPB, MID_HLX, NTB>, MidPlan<R, N, LPB, MID_HLX, NTB>>(
+            ngroups, nslots, NTB, (rot_any ? 2 + MidPlan<R, N, LPB, MID_HLX, NTB>::CLDS : 2) * buf, s, slots, in,
+            outA, outB, nlines, rot_any, tw);
+    return mid_go<k_mid<R, N, LPB, MID_PRE, NTB>, MidPlan<R, N, LPB, MID_PRE, NTB>>(
+        ngroups, nslots, NTB, buf, s, slots, in, outA, outB, nlines, 0, tw);
 }
 
 #define GS_SWITCH_N(CALL)                        \
