@@ -24,7 +24,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gs_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-STOP_ENERGY, STOP_RESIDUAL, STOP_BOTH = 0, 1, 2
+STOP_ENERGY, STOP_RESIDUAL, STOP_BOTH, STOP_WAVEFN = 0, 1, 2, 3
+PC_COMBINED, PC_KINETIC, PC_POTENTIAL = 0, 1, 2
 OK, MAXITER, STAGNATED, NONFINITE = 0, 1, 2, -4
 
 
@@ -56,7 +57,7 @@ class _Params(C.Structure):
 class _Options(C.Structure):
     _fields_ = [("stop_kind", C.c_int), ("tol", C.c_double), ("max_iter", C.c_int),
                 ("theta_trial", C.c_double), ("sigma", C.c_double),
-                ("max_backtrack", C.c_int)]
+                ("max_backtrack", C.c_int), ("precond", C.c_int)]
 
 
 class _Eval(C.Structure):
@@ -157,10 +158,11 @@ class Options:
     theta_trial: float = 0.1
     sigma: float = 0.5
     max_backtrack: int = 40
+    precond: int = 0          # PC_COMBINED (3.15), PC_KINETIC (3.12), PC_POTENTIAL (3.14)
 
     def _c(self):
         return _Options(self.stop_kind, self.tol, self.max_iter, self.theta_trial,
-                        self.sigma, self.max_backtrack)
+                        self.sigma, self.max_backtrack, self.precond)
 
 
 @dataclass
@@ -326,14 +328,16 @@ def alpha(grid, trap, params, phi):
     return list(a)
 
 
-def precond(grid, trap, params, phi, alpha_, r):
+def precond(grid, trap, params, phi, alpha_, r, kind=0):
+    """Preconditioner of Sec. 3.4 applied to r: combined (3.15) (kind 0),
+    kinetic (3.12) (kind 1) or potential (3.14) (kind 2)."""
     keep = []
     phi = _cplx(phi, (3,) + grid.shape)
     r = _cplx(r, (3,) + grid.shape)
     out = np.empty_like(r)
     g, t, p = grid._c(), trap._c(keep), params._c()
     a = (C.c_double * 3)(*alpha_)
-    _load().orc_precond(C.byref(g), C.byref(t), C.byref(p), _p(phi), a, _p(r), _p(out))
+    _load().orc_precond_kind(C.byref(g), C.byref(t), C.byref(p), _p(phi), a, int(kind), _p(r), _p(out))
     return out
 
 

@@ -44,14 +44,18 @@ typedef struct { int dim; int n[3]; double L[3]; } orc_grid;          /* n[0]=Nx
  * harmonic-plus-quartic trap: eq. (4.1) of Example 5). */
 typedef struct { double g[3]; double q2; double q4; const double* V; } orc_trap;
 typedef struct { double omega, gamma, c0, c1; } orc_params;         /* Omega, gamma (SOC), c0, c1 */
-enum { ORC_STOP_ENERGY = 0, ORC_STOP_RESIDUAL = 1, ORC_STOP_BOTH = 2 };
+enum { ORC_STOP_ENERGY = 0, ORC_STOP_RESIDUAL = 1, ORC_STOP_BOTH = 2, ORC_STOP_WAVEFN = 3 };
+/* preconditioners of Sec. 3.4: combined (3.15), kinetic (3.12), potential (3.14) */
+enum { ORC_PC_COMBINED = 0, ORC_PC_KINETIC = 1, ORC_PC_POTENTIAL = 2 };
 typedef struct {
-    int stop_kind;        /* stop on the energy difference (3.11), the residual (3.10), or both */
+    int stop_kind;        /* stop on the energy difference (3.11), the residual (3.10), either of
+                             the two, or the wave-function difference (3.9) */
     double tol;
     int max_iter;
     double theta_trial;   /* the "prescribed small positive number" of Algorithm 2 */
     double sigma;         /* backtracking factor of Algorithm 2 */
     int max_backtrack;    /* cap on Step 4 repetitions (the paper gives none) */
+    int precond;          /* ORC_PC_*; every kind uses the shifts alpha_l of (3.13) */
 } orc_options;
 typedef struct {
     double E, e_kin, e_pot, e_rot, e_spin, e_soc, e_pot2, e_pot4;
@@ -553,6 +557,41 @@ void orc_precond(const orc_grid* g, const orc_trap* t, const orc_params* p,
     free(w);
 }
 
+/* The three preconditioners of Sec. 3.4 by kind (ORC_PC_*), with the shifts
+ * alpha_l of (3.13) for both the kinetic and the potential factor:
+ *   kinetic   (3.12): (alpha_l - Lap/2)^{-1}, diagonal in Fourier space;
+ *   potential (3.14): (alpha_l + V + c0 rho)^{-1}, pointwise;
+ *   combined  (3.15): the potential factor's square root on both sides of the
+ *                     kinetic one (orc_precond). */
+void orc_precond_kind(const orc_grid* g, const orc_trap* t, const orc_params* p,
+                      const cplx* phi, const double alpha[3], int kind, const cplx* r, cplx* out) {
+    long M = npts(g);
+    double amax = fmax(1.0, fmax(alpha[0], fmax(alpha[1], alpha[2])));
+    double floor_ = 1e-12 * amax;
+    if (kind == ORC_PC_COMBINED) {
+        orc_precond(g, t, p, phi, alpha, r, out);
+        return;
+    }
+    for (int c = 0; c < 3; ++c) {
+        if (kind == ORC_PC_KINETIC) {
+            memcpy(out + c * M, r + c * M, sizeof(cplx) * M);
+            orc_fftn(g, out + c * M, -1);
+            for (long i = 0; i < M; ++i) {
+                double kx, ky, kz;
+                kvec(g, i, &kx, &ky, &kz);
+                out[c * M + i] /= fmax(alpha[c] + 0.5 * (kx * kx + ky * ky + kz * kz), floor_);
+            }
+            orc_fftn(g, out + c * M, +1);
+        } else {
+            for (long i = 0; i < M; ++i) {
+                double rho = creal(phi[i] * conj(phi[i]) + phi[M + i] * conj(phi[M + i]) +
+                                   phi[2 * M + i] * conj(phi[2 * M + i]));
+                out[c * M + i] = r[c * M + i] / fmax(alpha[c] + pot_at(g, t, i) + p->c0 * rho, floor_);
+            }
+        }
+    }
+}
+
 /* ------------------------------------------------------------------------- */
 /* line search coefficients a_n, b_n, eqs. (3.6)-(3.8)                         */
 /* ------------------------------------------------------------------------- */
@@ -686,6 +725,7 @@ int orc_pcg(const orc_grid* g, const orc_trap* t, const orc_params* p, const orc
     int n = 0;
     int use_e = (o->stop_kind == ORC_STOP_ENERGY || o->stop_kind == ORC_STOP_BOTH);
     int use_r = (o->stop_kind == ORC_STOP_RESIDUAL || o->stop_kind == ORC_STOP_BOTH);
+    int use_w = (o->stop_kind == ORC_STOP_WAVEFN);
     for (;;) {
         if (!isfinite(E_cur)) { status = ORC_NONFINITE; break; }
         /* mu_n and the residual r^n */
@@ -703,7 +743,7 @@ int orc_pcg(const orc_grid* g, const orc_trap* t, const orc_params* p, const orc
         /* preconditioned residual */
         double alpha[3];
         orc_alpha(g, t, p, phi, alpha);
-        orc_precond(g, t, p, phi, alpha, r, pr);
+        orc_precond_kind(g, t, p, phi, alpha, o->precond, r, pr);
         double rpr = orc_re_inner(g, r, pr);
         /* PRP beta, clipped at zero */
         double beta = 0.0;
@@ -745,8 +785,14 @@ int orc_pcg(const orc_grid* g, const orc_trap* t, const orc_params* p, const orc
         if (!accepted || !isfinite(dE)) { status = ORC_STAGNATED; break; }
         double cs = cos(theta), sn = sin(theta);
         for (long i = 0; i < n3; ++i) trial[i] = cs * phi[i] + sn * trial[i];
+        normalise(g, trial);
+        /* criterion (3.9): max over components and points of |phi^{n+1} - phi^n| */
+        double werr = 0.0;
+        for (long i = 0; i < n3; ++i) {
+            double a = cabs(trial[i] - phi[i]);
+            if (a > werr) werr = a;
+        }
         memcpy(phi, trial, bytes);
-        normalise(g, phi);
         E_cur = orc_energy(g, t, p, phi);
         memcpy(r_prev, r, bytes);
         memcpy(P_prev, P, bytes);
@@ -755,6 +801,7 @@ int orc_pcg(const orc_grid* g, const orc_trap* t, const orc_params* p, const orc
         st->dE_last = dE;
         if (etrace) etrace[n] = E_cur;
         if (use_e && fabs(dE) < o->tol) { status = ORC_OK; break; }
+        if (use_w && werr < o->tol) { status = ORC_OK; break; }
     }
     st->iters = n;
     st->status = status;

@@ -488,3 +488,100 @@ def test_preconditioner_closed_forms():
     out = O.precond(g2, t2, p2, phi2, al, r)
     for cc in range(3):
         assert rel(out[cc], 1.0 / (al[cc] * np.sqrt(al[cc] + V + pb2.c0 * rho))) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# the other preconditioners of Sec. 3.4 and the wave-function criterion (3.9)
+# ---------------------------------------------------------------------------
+def test_kinetic_and_potential_preconditioners_closed_forms():
+    """Kinetic (3.12): a plane wave e^{ik.x} is an eigenfunction with eigenvalue
+    1/(alpha_l + |k|^2/2). Potential (3.14): a unit value at one grid point is
+    divided by alpha_l + V + c0 rho there (V = 0 at the centre, (g L)^2 at a
+    corner of [-L, L]^2 for g = (g, g); rho of a constant field). With V = 0 and
+    c0 = 0 the potential factor is the number 1/alpha_l, so the combined
+    preconditioner (3.15) is the kinetic one divided by alpha_l."""
+    n, L = 16, 4.0
+    al = [0.7, 1.3, 2.1]
+    pb = inputs.Problem(dim=2, n=(n, n), L=(L, L), g=(0.0, 0.0, 0.0))
+    g, t, p = orc(pb)
+    phi = inputs.initial_guess(pb, ("a", "a", "a"))
+    Yi, Xi = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    pw = np.exp(2j * np.pi * (3 * Xi + 14 * Yi) / n)
+    kx, ky = np.pi * 3 / L, np.pi * (14 - 16) / L
+    r = np.stack([pw] * 3)
+    kin = O.precond(g, t, p, phi, al, r, kind=O.PC_KINETIC)
+    pot = O.precond(g, t, p, phi, al, r, kind=O.PC_POTENTIAL)
+    com = O.precond(g, t, p, phi, al, r, kind=O.PC_COMBINED)
+    for cc in range(3):
+        assert rel(kin[cc], pw / (al[cc] + 0.5 * (kx * kx + ky * ky))) < 1e-13
+        assert rel(pot[cc], pw / al[cc]) < 1e-15
+        assert rel(com[cc], kin[cc] / al[cc]) < 1e-13
+    # point sources with a trap and a constant density
+    gg, c0 = 1.5, 30.0
+    pb2 = inputs.Problem(dim=2, n=(n, n), L=(L, L), g=(gg, gg, 0.0), c0=c0)
+    g2, t2, p2 = orc(pb2)
+    phic = np.full((3, n, n), 1.0 + 0j)
+    phic /= np.sqrt(np.sum(np.abs(phic) ** 2) * (2 * L / n) ** 2)   # unit norm
+    rho = 3 * abs(phic[0, 0, 0]) ** 2
+    for (iy, ix), V in (((n // 2, n // 2), 0.0), ((0, 0), (gg * L) ** 2)):
+        r = np.zeros((3, n, n), complex)
+        r[:, iy, ix] = 1.0
+        out = O.precond(g2, t2, p2, phic, al, r, kind=O.PC_POTENTIAL)
+        for cc in range(3):
+            assert abs(out[cc, iy, ix] - 1.0 / (al[cc] + V + c0 * rho)) < 1e-15
+            assert np.count_nonzero(out[cc]) == 1
+
+
+@pytest.mark.parametrize("kind", [O.PC_KINETIC, O.PC_POTENTIAL])
+def test_preconditioner_kinds_reach_the_same_minimiser(kind):
+    """The preconditioner changes the path, not the fixed point: from the same
+    guess every kind reaches the combined preconditioner's E and mu."""
+    pb, psi0 = inputs.workload_small_2d()
+    g, t, p = orc(pb)
+    ref = O.pcg(g, t, p, psi0, O.Options(stop_kind=O.STOP_RESIDUAL, tol=1e-10))
+    res = O.pcg(g, t, p, psi0, O.Options(stop_kind=O.STOP_RESIDUAL, tol=1e-10, precond=kind))
+    assert ref.status == O.OK and res.status == O.OK
+    e0, e1 = O.evaluate(g, t, p, ref.psi), O.evaluate(g, t, p, res.psi)
+    assert rel(e1["E"], e0["E"]) < 1e-12
+    assert rel(e1["mu"], e0["mu"]) < 1e-9
+
+
+def test_preconditioner_iteration_counts_follow_sec_3_4():
+    """Sec. 3.4: on a fixed domain the kinetic preconditioner's iteration count
+    does not grow as the mesh is refined, the potential one's grows as h
+    decreases, and the combined one is stable and needs the fewest (measured
+    here 386 -> 414, 287 -> 612 and 159 -> 162 from 32^2 to 64^2)."""
+    its = {}
+    for n in (32, 64):
+        pb = inputs.Problem(dim=2, n=(n, n), L=(8.0, 8.0), gamma=0.5, c0=100.0, c1=-0.5)
+        psi0 = inputs.initial_guess(pb, ("a", "a", "a"))
+        g, t, p = orc(pb)
+        for kind in (O.PC_KINETIC, O.PC_POTENTIAL, O.PC_COMBINED):
+            r = O.pcg(g, t, p, psi0, O.Options(stop_kind=O.STOP_RESIDUAL, tol=1e-6, precond=kind,
+                                               max_iter=5000))
+            assert r.status == O.OK
+            its[(n, kind)] = r.iters
+    print(its)
+    assert its[(64, O.PC_KINETIC)] <= 1.2 * its[(32, O.PC_KINETIC)]
+    assert its[(64, O.PC_POTENTIAL)] > 1.5 * its[(32, O.PC_POTENTIAL)]
+    assert its[(64, O.PC_COMBINED)] <= 1.2 * its[(32, O.PC_COMBINED)]
+    for n in (32, 64):
+        assert its[(n, O.PC_COMBINED)] < min(its[(n, O.PC_KINETIC)], its[(n, O.PC_POTENTIAL)])
+
+
+def test_wavefunction_criterion_stops_at_first_small_change():
+    """Criterion (3.9), checked by brute force: with max_iter = k the oracle
+    returns Phi^k, so the changes max |Phi^n - Phi^{n-1}| and the one before it
+    are formed here from three truncated runs."""
+    pb, psi0 = inputs.workload_small_2d()
+    g, t, p = orc(pb)
+    tol = 1e-5
+    res = O.pcg(g, t, p, psi0, O.Options(stop_kind=O.STOP_WAVEFN, tol=tol))
+    assert res.status == O.OK
+    n = res.iters
+    assert n >= 2
+    runs = {k: O.pcg(g, t, p, psi0, O.Options(stop_kind=O.STOP_ENERGY, tol=0.0, max_iter=k)).psi
+            for k in (n - 2, n - 1, n)}
+    assert np.array_equal(runs[n], res.psi)
+    assert np.max(np.abs(runs[n] - runs[n - 1])) < tol
+    assert np.max(np.abs(runs[n - 1] - runs[n - 2])) >= tol
