@@ -56,7 +56,14 @@ extern "C" {
 /* stopping criteria (Sec. 3.4) */
 #define GS_STOP_ENERGY 0     /* |E(Phi^{n+1}) - E(Phi^n)| < tol, eq. (3.11) */
 #define GS_STOP_RESIDUAL 1   /* max_l ||r_l^n||_inf < tol, eq. (3.10) */
-#define GS_STOP_EITHER 2     /* stop at whichever holds first */
+#define GS_STOP_EITHER 2     /* stop at whichever of the two holds first */
+#define GS_STOP_WAVEFN 3     /* max_l ||phi_l^{n+1} - phi_l^n||_inf < tol, eq. (3.9) */
+
+/* Preconditioners of Sec. 3.4, all with the shifts alpha_l of eq. (3.13) */
+#define GS_PC_COMBINED 0     /* P_V^{1/2} P_Delta P_V^{1/2}, eq. (3.15) (the paper's choice) */
+#define GS_PC_KINETIC 1      /* P_Delta = (alpha_l - Lap/2)^{-1}, eq. (3.12) */
+#define GS_PC_POTENTIAL 2    /* P_V = (alpha_l + V + c0 rho)^{-1}, eq. (3.14); runs the same
+                                transforms with a unit spectral factor */
 
 /* arithmetic of the iteration */
 #define GS_FP64 0            /* all fields and transforms in double */
@@ -113,6 +120,7 @@ typedef struct {
                              or GS_FP32. Every reduction stays double; the line search and the
                              stopping tests act on double quantities, so the limit is the same
                              and only the path to it changes. */
+    int precond;          /* GS_PC_* (default GS_PC_COMBINED) */
 } gs_options;
 
 /* Results; quantities refer to the returned Phi. */
@@ -132,6 +140,8 @@ typedef struct {
     int status;           /* return code of the solve */
     double wall_s;        /* wall time of the call */
     int iters_coarse;     /* accepted steps on the coarser levels of a cascadic multigrid solve */
+    double dphi_inf;      /* max_l ||phi_l^{n+1} - phi_l^n||_inf of the last step (eq. (3.9));
+                             infinity before the first step of the last precision phase */
 } gs_result;
 
 /* One solve request of the batch and serving entry points. The trap's V (host)
@@ -157,7 +167,7 @@ void gs_destroy(gs_ctx* ctx);
 /* Fill *o with the defaults: energy criterion, tol 1e-12, max_iter 100000,
  * FP64, switch_resid 1e-6, fp32_max_iter 20000, stall_window 50,
  * theta_trial 0.1, sigma 0.5, max_backtrack 40, check_every 32, cm_levels 1,
- * dir_precision GS_FP64. */
+ * dir_precision GS_FP64, precond GS_PC_COMBINED. */
 void gs_default_options(gs_options* o);
 /* Device bytes a solve of this grid needs with these options (GS_MIXED counts
  * both the float and the double working sets; dir_precision GS_FP32 halves the

@@ -75,8 +75,11 @@ __device__ inline void ctrl_resid(SolveState* st, const Phys& p, const double (&
         if (rinf < 0.5 * st->best_resid) { st->best_resid = rinf; st->best_iter = st->iter_phase; }
         else if (st->iter_phase - st->best_iter >= st->stall_window) { st->switch_req = 1; st->done = 1; return; }
         if (st->iter_phase >= st->phase_max_iter) { st->switch_req = 1; st->done = 1; return; }
-    } else if (st->stop_kind != GS_STOP_ENERGY && rinf < st->tol) {
+    } else if ((st->stop_kind == GS_STOP_RESIDUAL || st->stop_kind == GS_STOP_EITHER) && rinf < st->tol) {
         st->done = 1;   // criterion (3.10)
+        return;
+    } else if (st->stop_kind == GS_STOP_WAVEFN && st->iter > 0 && st->wchange < st->tol) {
+        st->done = 1;   // criterion (3.9), for the step that produced this iterate
         return;
     }
     if (st->iter >= st->max_iter) { st->status = GS_WMAXITER; st->done = 1; return; }
@@ -230,7 +233,8 @@ __device__ inline void ctrl_ls(SolveState* st, const Phys& p, const double (&s)[
     st->rpr_prev = st->rpr;
     st->have_prev = 1;
     st->cur ^= 1;
-    if (st->phase != PH_FP32 && st->stop_kind != GS_STOP_RESIDUAL && fabs(dE) < st->tol)
+    if (st->phase != PH_FP32 && (st->stop_kind == GS_STOP_ENERGY || st->stop_kind == GS_STOP_EITHER) &&
+        fabs(dE) < st->tol)
         st->final_pending = 1;   // criterion (3.11)
 }
 

@@ -64,7 +64,8 @@ static long long npts(const gs_grid* g) {
 
 static int check_options(const gs_options* o) {
     if (!o) return fail(GS_EINVAL, "options is NULL");
-    if (o->stop_kind < 0 || o->stop_kind > 2) return fail(GS_EINVAL, "options.stop_kind invalid");
+    if (o->stop_kind < GS_STOP_ENERGY || o->stop_kind > GS_STOP_WAVEFN) return fail(GS_EINVAL, "options.stop_kind invalid");
+    if (o->precond < GS_PC_COMBINED || o->precond > GS_PC_POTENTIAL) return fail(GS_EINVAL, "options.precond invalid");
     if (!(o->tol >= 0.0)) return fail(GS_EINVAL, "options.tol must be >= 0");
     if (o->max_iter < 0) return fail(GS_EINVAL, "options.max_iter must be >= 0");
     if (o->precision < GS_FP64 || o->precision > GS_MIXED) return fail(GS_EINVAL, "options.precision invalid");
@@ -289,6 +290,8 @@ static void init_state(SolveState* h, const gs_options* o, int phase) {
     h->switch_resid = o->switch_resid;
     h->phase_max_iter = o->fp32_max_iter;
     h->stall_window = o->stall_window;
+    h->precond = o->precond;
+    h->wchange = INFINITY;
     h->phase = phase;
     h->best_resid = INFINITY;
     h->inv_norm = 1.0;
@@ -317,6 +320,9 @@ static void fill_result(const SolveState* h, gs_result* r, int iters_fp32, doubl
         r->backtracks = h->backtracks;
         r->resets = h->resets;
         r->status = h->status;
+        r->dphi_inf = h->wchange;
+    } else {
+        r->dphi_inf = INFINITY;
     }
     r->iters_fp32 = iters_fp32;
     r->wall_s = wall;
@@ -342,7 +348,7 @@ struct Sub {
 
 // out = H_L in  (H_L = -1/2 Lap + V - Omega L_z - gamma S), transforms in type R,
 // with the prologue `pro` applied to `in` first (see launch_fwdT; the operand
-// of the other type RX is aux0 for PRO_UPDATE, aux1 for PRO_DIR). dual (with
+// of the other type RX is aux1 for PRO_DIR). dual (with
 // PRO_DIR): aux1 (Phi) is transformed with in, and the middle pass reduces the
 // kinetic coefficients of both for the next iterate's alpha_l.
 template <typename R, typename RX>
@@ -350,7 +356,7 @@ static hipError_t chain_HL(int dim, const int n[3], long long M, int rot, const 
                            int dual, int in, int out, int aux0, int aux1, int use_invnP, hipStream_t s, Timer* tm) {
     const int Nx = n[0], Ny = n[1], Nz = n[2];
     const double F = 3.0 * M * sizeof(cpx<R>) * L.ns, Fx = 3.0 * M * sizeof(cpx<RX>) * L.ns;
-    const double b_fwd = dual ? 5 * F + Fx : (pro == PRO_DIR ? 4 * F + Fx : (pro == PRO_UPDATE ? 3 * F + Fx : 2 * F));
+    const double b_fwd = dual ? 5 * F + Fx : (pro == PRO_DIR ? 4 * F + Fx : 2 * F);
     const double b_mid = (rot ? 2 : 1) * F + (dual ? 2 : 1) * F, b_inv = (rot ? 4 : 3) * F;
     const int midop = dual ? MID_HLX : MID_HL;
     const int outB = rot ? B_T1 : B_NONE;
@@ -412,12 +418,14 @@ static hipError_t fin(const RedGeom& g, Sub L, int what, hipStream_t s, Timer* t
 }
 
 // Fresh evaluation of the current iterate, in the state type: apply a pending
-// update to Phi, H_L Phi from scratch, energy parts, mu, alpha_l.
+// update to Phi (with the largest change, criterion (3.9)), H_L Phi from
+// scratch, energy parts, mu, alpha_l.
 template <typename RS, typename RD>
 static hipError_t refresh(const Geo<RS, RD>& G, Sub L, hipStream_t s, Timer* tm) {
     const double Fs = 3.0 * G.M * sizeof(cpx<RS>) * L.ns;
     hipError_t e;
-    if ((e = chain_HL<RS, RD>(G.dim, G.n, G.M, G.rot_any, G.tws, L, PRO_UPDATE, 0, B_PHI, B_HL, B_P, B_NONE, 0, s, tm))) return e;
+    if ((e = launch_apply<RS, RD>(L.tab, L.ns, G.g, s))) return e;
+    if ((e = chain_HL<RS, RD>(G.dim, G.n, G.M, G.rot_any, G.tws, L, PRO_PLAIN, 0, B_PHI, B_HL, B_NONE, B_NONE, 0, s, tm))) return e;
     if ((e = timed_ns(tm, KK_EVAL, 2 * Fs, L.ns, s, [&] { return launch_eval<RS>(L.tab, L.ns, G.g, s); }))) return e;
     return fin(G.g, L, FIN_EVAL, s, tm);
 }
@@ -802,6 +810,7 @@ static int hand_over_to(Ctx& cx, Class<float, float>& c, int k, Job* j) {
     h.final_pending = 0;
     h.iter_phase = 0;
     h.status = GS_OK;
+    h.wchange = INFINITY;
     j->mig = h;
     j->slot = kd;
     j->handover = true;
@@ -1429,6 +1438,7 @@ void gs_default_options(gs_options* o) {
     o->check_every = 32;
     o->cm_levels = 1;
     o->dir_precision = GS_FP64;
+    o->precond = GS_PC_COMBINED;
 }
 
 size_t gs_footprint_bytes(const gs_grid* g, const gs_options* o) {

@@ -228,8 +228,7 @@ __global__ __launch_bounds__(NT) void k_fwdT(const Slot* __restrict__ slots, int
     if (st->done) return;
     cpx<R>* inp = fld<R>(S, iin);
     cpx<R>* __restrict__ out = fld<R>(S, iout);
-    // PRO_UPDATE: aux0 = P (type RX); PRO_DIR: aux0 = P_C r (type R), aux1 = Phi (type RX)
-    const cpx<RX>* __restrict__ auxP = (PRO == PRO_UPDATE && iaux0 >= 0) ? fld<RX>(S, iaux0) : nullptr;
+    // PRO_DIR: aux0 = P_C r (type R), aux1 = Phi (type RX)
     const cpx<R>* __restrict__ auxR = (PRO == PRO_DIR && iaux0 >= 0) ? fld<R>(S, iaux0) : nullptr;
     const cpx<RX>* __restrict__ aux1 = iaux1 >= 0 ? fld<RX>(S, iaux1) : nullptr;
     constexpr int PITCH = Lay<N>::P;
@@ -249,15 +248,7 @@ __global__ __launch_bounds__(NT) void k_fwdT(const Slot* __restrict__ slots, int
     // the prologue combinations are formed in double and rounded once
     int mode = second ? PRO_PLAIN : PRO;
     double k0 = 1, k1 = 0, k2 = 1;
-    if (PRO == PRO_UPDATE) {
-        if (!st->pending_step) mode = PRO_PLAIN;
-        else {
-            k0 = st->c;
-            k1 = st->s * st->invnP;
-            k2 = st->inv_norm;
-            if (st->s == 0.0) mode = -1;   // rescale only
-        }
-    } else if (PRO == PRO_DIR) {
+    if (PRO == PRO_DIR) {
         k0 = st->beta;
         k1 = st->dphi;
         k2 = st->invnP;
@@ -270,13 +261,7 @@ __global__ __launch_bounds__(NT) void k_fwdT(const Slot* __restrict__ slots, int
             v = cvt<R>(aux1[gi]);
         } else {
             v = inp[gi];
-            if (mode == PRO_UPDATE) {
-                v = cvt<R>(k2 * (k0 * wid(v) + k1 * wid(auxP[gi])));
-                inp[gi] = v;
-            } else if (mode == -1) {
-                v = cvt<R>(k2 * (k0 * wid(v)));
-                inp[gi] = v;
-            } else if (mode == PRO_DIR) {
+            if (mode == PRO_DIR) {
                 // D = -P r + beta P^{n-1};  P^n = D - Re<D,Phi> Phi  (stored), transform P^n / |P^n|
                 const cpx<double> d = k0 * wid(v) - wid(auxR[gi]) - k1 * wid(aux1[gi]);
                 v = cvt<R>(d);
@@ -519,6 +504,8 @@ __global__ __launch_bounds__(NT) void k_mid(const Slot* __restrict__ slots, int 
     if (MP::PIPE && grp < ngroups) mid_fetch<R, N, LPB, OP, NT>(in, in2, cs, grp * LPB, pa, pb);
     const double invM = 1.0 / (double)p.M;
     double al[3] = {0.0, 0.0, 0.0}, fl = 0.0;
+    // the potential preconditioner (3.14) has no kinetic factor: unit multiplier
+    const bool unit = OP == MID_PRE && st->precond == GS_PC_POTENTIAL;
     if (OP == MID_PRE) {
         al[0] = st->alpha[0]; al[1] = st->alpha[1]; al[2] = st->alpha[2];
         fl = 1e-12 * fmax(1.0, fmax(al[0], fmax(al[1], al[2])));
@@ -600,9 +587,9 @@ __global__ __launch_bounds__(NT) void k_mid(const Slot* __restrict__ slots, int 
                 *x1 = cmk((R)a1.x, (R)a1.y);
                 *x2 = cmk((R)a2.x, (R)a2.y);
             } else {
-                const R d0 = (R)(invM / fmax(al[0] + K, fl));
-                const R d1 = (R)(invM / fmax(al[1] + K, fl));
-                const R d2 = (R)(invM / fmax(al[2] + K, fl));
+                const R d0 = (R)(unit ? invM : invM / fmax(al[0] + K, fl));
+                const R d1 = (R)(unit ? invM : invM / fmax(al[1] + K, fl));
+                const R d2 = (R)(unit ? invM : invM / fmax(al[2] + K, fl));
                 *x0 = d0 * *x0;
                 *x1 = d1 * *x1;
                 *x2 = d2 * *x2;
@@ -681,9 +668,6 @@ static hipError_t fwdT_n(int pro, int dual, const Slot* slots, int nslots, int i
     switch (pro) {
     case PRO_PLAIN:
         GS_LAUNCH((k_fwdT<R, RX, N, TILE, PRO_PLAIN, false, NTB>), grid, dim3(NTB), lds, s, slots, in, out, aux0, aux1, A, B, tw);
-        break;
-    case PRO_UPDATE:
-        GS_LAUNCH((k_fwdT<R, RX, N, TILE, PRO_UPDATE, false, NTB>), grid, dim3(NTB), lds, s, slots, in, out, aux0, aux1, A, B, tw);
         break;
     case PRO_DIR:
         GS_LAUNCH((k_fwdT<R, RX, N, TILE, PRO_DIR, false, NTB>), grid, dim3(NTB), lds, s, slots, in, out, aux0, aux1, A, B, tw);

@@ -112,7 +112,7 @@ struct SolveState {
     int best_iter;       // stagnation tracking (FP32 phase)
     int nonfinite;
     // options
-    int stop_kind, max_iter, max_backtrack, phase_max_iter, stall_window;
+    int stop_kind, max_iter, max_backtrack, phase_max_iter, stall_window, precond;
     double tol, switch_resid, theta_trial, sigma;
     // current iterate
     double E, mu, norm2, alpha[3];
@@ -120,6 +120,7 @@ struct SolveState {
     double mu_comp[3], norm_comp[3];
     double lin;          // <H_L Phi, Phi>
     double resid_inf, best_resid;
+    double wchange;      // max |Phi^{n+1} - Phi^n| of the last applied step (criterion (3.9))
     // direction
     double rpr, rpr_prev, beta, dphi, nP, invnP, bdir;
     double rP, phiP, PP;   // Re<r,P^{n-1}>, Re<Phi,P^{n-1}>, |P^{n-1}|^2 (from the residual pass)
@@ -147,6 +148,7 @@ enum BufSel : int {
     B_NONE = -1
 };
 constexpr int NS_MAX = 64;          // row stride of the pointwise partial sums
+constexpr int W_ROW = NS_MAX - 1;    // row entry of the step's largest change (no other pass uses it)
 constexpr int RED_MID_STRIDE = 12;  // row stride of the middle-pass partial sums
 constexpr int RED_DIR_STRIDE = 8;   // row stride of the preconditioner's last-pass partial sums
 
@@ -183,7 +185,7 @@ struct RedGeom {
 // ---------------------------------------------------------------------------
 // FFT pass launchers (fft_kernels.hip); nslots = grid.y
 // ---------------------------------------------------------------------------
-enum Pro : int { PRO_PLAIN = 0, PRO_UPDATE = 1, PRO_DIR = 2 };
+enum Pro : int { PRO_PLAIN = 0, PRO_DIR = 2 };
 enum Epi : int { EPI_SCALE = 0, EPI_HL = 1, EPI_ROTX = 2 };
 enum MidOp : int { MID_HL = 0, MID_PRE = 1, MID_HLX = 2 };
 
@@ -191,11 +193,9 @@ enum MidOp : int { MID_HL = 0, MID_PRE = 1, MID_HLX = 2 };
 // with that axis moved to the slowest position: out[ncomp][N][A][B].
 // Prologue (in place on the physical input, before the transform):
 //   PRO_PLAIN:  transform in as is
-//   PRO_UPDATE: if pending_step, in <- (c in + s invnP aux0) inv_norm (written back)
 //   PRO_DIR:    in <- -aux0 + beta in - dphi aux1 (written back), transform invnP * in
 // dual (PRO_DIR only): also transform aux1 into components 3..5 of out.
-// in, out and (PRO_DIR) aux0 are of type R; the other operand (PRO_UPDATE:
-// aux0 = P; PRO_DIR: aux1 = Phi) is of type RX.
+// in, out and (PRO_DIR) aux0 are of type R; aux1 (Phi) is of type RX.
 template <typename R, typename RX>
 hipError_t launch_fwdT(int N, int pro, int dual, const Slot* slots, int nslots, int in, int out, int aux0,
                        int aux1, int A, int B, int ncomp, const cpx<R>* tw, hipStream_t s);
@@ -239,6 +239,9 @@ hipError_t launch_resid(const Slot* slots, int nslots, RedGeom g, int final_only
 template <typename RS, typename RD> hipError_t launch_lsred(const Slot* slots, int nslots, RedGeom g, hipStream_t s);
 // partial sums of |Phi|^2 (the control step FIN_NORM sets the rescale Phi <- Phi / |Phi|)
 template <typename RS> hipError_t launch_normalize(const Slot* slots, int nslots, RedGeom g, hipStream_t s);
+// pending step Phi <- (c Phi + s P^) inv_norm of every slot, with the block
+// maxima of |change| in entry W_ROW of the partial-sum rows
+template <typename RS, typename RD> hipError_t launch_apply(const Slot* slots, int nslots, RedGeom g, hipStream_t s);
 enum Fin : int {
     FIN_EVAL = 0,     // energy parts, mu, alpha_l of a fresh evaluation
     FIN_DIR = 1,      // stopping tests of the residual pass, then PRP beta and projection

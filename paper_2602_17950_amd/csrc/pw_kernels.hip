@@ -83,7 +83,9 @@ __global__ __launch_bounds__(PT) void k_resid(const Slot* slots, RedGeom g, int 
     const double al[3] = {st->alpha[0], st->alpha[1], st->alpha[2]};
     const double fl = 1e-12 * fmax(1.0, fmax(al[0], fmax(al[1], al[2])));
     cpx<R>* r = fld<R>(S, B_R0 + st->cur);
+    const bool kinetic = st->precond == GS_PC_KINETIC;   // no potential factor (3.12)
     double acc[NS_RES] = {0.0, 0.0, 0.0, 0.0};
+    double wmax = 0.0;
     for (long long i = (long long)blockIdx.x * PT + threadIdx.x; i < M; i += (long long)gridDim.x * PT) {
         double x, y, z, V2, V4;
         coords(p, i, x, y, z);
@@ -94,6 +96,7 @@ __global__ __launch_bounds__(PT) void k_resid(const Slot* slots, RedGeom g, int 
         if (!final_only) load3(Pf, i, M, P);
         if (pending) {
             cpx<double> hp[3];
+            const cpx<double> old[3] = {ph[0], ph[1], ph[2]};
             load3(hlpf, i, M, hp);
             for (int c = 0; c < 3; ++c) {
                 ph[c] = k2 * (k0 * ph[c] + k1 * P[c]);
@@ -104,6 +107,7 @@ __global__ __launch_bounds__(PT) void k_resid(const Slot* slots, RedGeom g, int 
             // continue from the stored (rounded) values
             load3(phif, i, M, ph);
             load3(hlf, i, M, hl);
+            for (int c = 0; c < 3; ++c) wmax = fmax(wmax, sqrt(cabs2(ph[c] - old[c])));
         }
         const Spin sp = spin_of(ph);
         nonlin(p, sp, ph, nl);
@@ -114,7 +118,7 @@ __global__ __launch_bounds__(PT) void k_resid(const Slot* slots, RedGeom g, int 
             const cpx<R> rr = cmk((R)rc.x, (R)rc.y);
             r[c * M + i] = rr;
             const double d = fmax(al[c] + V2 + V4 + p.c0 * sp.rho, fl);
-            const RD w = (RD)(1.0 / sqrt(d));
+            const RD w = kinetic ? (RD)1 : (RD)(1.0 / sqrt(d));
             pvv[c * M + i] = w;
             uf[c * M + i] = w * cvt<RD>(rr);
             const cpx<double> rw = wid(rr);
@@ -125,6 +129,10 @@ __global__ __launch_bounds__(PT) void k_resid(const Slot* slots, RedGeom g, int 
     }
     const double m = bmax(acc[0]);
     if (threadIdx.x == 0) S.red_pw[(long long)blockIdx.x * NS_MAX] = m;
+    if (pending) {   // uniform over the block
+        const double wm = bmax(wmax);
+        if (threadIdx.x == 0) S.red_pw[(long long)blockIdx.x * NS_MAX + W_ROW] = wm;
+    }
     const double t[3] = {acc[1], acc[2], acc[3]};
     block_row<3>(t, S.red_pw + 1, NS_MAX);   // entries 1..3 of the row
 }
@@ -206,6 +214,32 @@ __global__ __launch_bounds__(PT, 3) void k_lsred(const Slot* slots, RedGeom g) {
 }
 
 // ---------------------------------------------------------------------------
+// pending step before a fresh evaluation: Phi <- (c Phi + s P^) inv_norm (a
+// rescale when s = 0), formed in double and rounded once; block maxima of
+// |Phi^{n+1} - Phi^n| (criterion (3.9)) in entry W_ROW of the rows
+// ---------------------------------------------------------------------------
+template <typename R, typename RD>
+__global__ __launch_bounds__(PT) void k_apply(const Slot* slots, RedGeom g) {
+    const Slot& S = slots[blockIdx.y];
+    const SolveState* st = S.st;
+    if (st->done || !st->pending_step) return;
+    const long long n3 = 3 * S.p.M;
+    cpx<R>* phi = fld<R>(S, B_PHI);
+    const cpx<RD>* P = fld<RD>(S, B_P);
+    const double k0 = st->c, k1 = st->s * st->invnP, k2 = st->inv_norm;
+    const bool rescale = st->s == 0.0;
+    double wmax = 0.0;
+    for (long long i = (long long)blockIdx.x * PT + threadIdx.x; i < n3; i += (long long)gridDim.x * PT) {
+        const cpx<double> v = wid(phi[i]);
+        const cpx<R> nv = rescale ? cvt<R>(k2 * (k0 * v)) : cvt<R>(k2 * (k0 * v + k1 * wid(P[i])));
+        phi[i] = nv;
+        wmax = fmax(wmax, sqrt(cabs2(wid(nv) - v)));
+    }
+    const double wm = bmax(wmax);
+    if (threadIdx.x == 0) S.red_pw[(long long)blockIdx.x * NS_MAX + W_ROW] = wm;
+}
+
+// ---------------------------------------------------------------------------
 // normalisation: sets the pending rescale Phi <- Phi / |Phi|
 // ---------------------------------------------------------------------------
 template <typename R>
@@ -235,6 +269,15 @@ __global__ __launch_bounds__(PT) void k_fin(const Slot* slots, RedGeom g, int wh
     SolveState* st = S.st;
     const Phys p = S.p;
     if (what != FIN_NORM && what != FIN_RFINAL && st->done) return;
+    // the pass before this control step applied a step: its largest change (3.9)
+    if (what == FIN_EVAL || what == FIN_DIR) {
+        const int had_step = st->pending_step;   // read by every thread before thread 0 changes it
+        if (had_step) {
+            double wc[1];
+            gather<1>(wc, S.red_pw + W_ROW, g.nblk_pw, NS_MAX, 1u);
+            if (threadIdx.x == 0) st->wchange = wc[0];
+        }
+    }
     if (what == FIN_EVAL) {
         double tot[NS_EVAL], mt[4];
         gather<NS_EVAL>(tot, S.red_pw, g.nblk_pw, NS_MAX);
@@ -395,6 +438,10 @@ template <typename R, typename RD> hipError_t launch_lsred(const Slot* slots, in
     GS_LAUNCH((k_lsred<R, RD>), dim3(g.nblk_pw, nslots), dim3(PT), 0, s, slots, g);
     return hipGetLastError();
 }
+template <typename R, typename RD> hipError_t launch_apply(const Slot* slots, int nslots, RedGeom g, hipStream_t s) {
+    GS_LAUNCH((k_apply<R, RD>), dim3(g.nblk_pw, nslots), dim3(PT), 0, s, slots, g);
+    return hipGetLastError();
+}
 template <typename R> hipError_t launch_normalize(const Slot* slots, int nslots, RedGeom g, hipStream_t s) {
     GS_LAUNCH(k_normalize<R>, dim3(g.nblk_pw, nslots), dim3(PT), 0, s, slots, g);
     return hipGetLastError();
@@ -438,7 +485,8 @@ hipError_t launch_gaussian(cpx<double>* out, const Phys& p, hipStream_t s) {
     template hipError_t launch_pvin<R>(const Slot*, int, RedGeom, hipStream_t);
 #define GS_INST2(R, RD)                                                                         \
     template hipError_t launch_resid<R, RD>(const Slot*, int, RedGeom, int, hipStream_t);       \
-    template hipError_t launch_lsred<R, RD>(const Slot*, int, RedGeom, hipStream_t);
+    template hipError_t launch_lsred<R, RD>(const Slot*, int, RedGeom, hipStream_t);             \
+    template hipError_t launch_apply<R, RD>(const Slot*, int, RedGeom, hipStream_t);
 GS_INST(double)
 GS_INST(float)
 GS_INST2(double, double)

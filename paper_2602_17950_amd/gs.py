@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(_HERE, "libgs.so")
 GS_OK, GS_EINVAL, GS_ENOMEM, GS_EDEVICE, GS_ENONFINITE, GS_ECANCELED = 0, -1, -2, -3, -4, -5
 GS_WMAXITER, GS_WSTAGNATED = 1, 2
 GS_PENDING = 16
-GS_STOP_ENERGY, GS_STOP_RESIDUAL, GS_STOP_EITHER = 0, 1, 2
+GS_STOP_ENERGY, GS_STOP_RESIDUAL, GS_STOP_EITHER, GS_STOP_WAVEFN = 0, 1, 2, 3
+GS_PC_COMBINED, GS_PC_KINETIC, GS_PC_POTENTIAL = 0, 1, 2
 GS_FP64, GS_FP32, GS_MIXED = 0, 1, 2
 
 EXPORTS = ("gs_create", "gs_destroy", "gs_default_options", "gs_footprint_bytes", "gs_solve",
@@ -54,7 +55,7 @@ class gs_options(C.Structure):
                 ("precision", C.c_int), ("switch_resid", C.c_double), ("fp32_max_iter", C.c_int),
                 ("stall_window", C.c_int), ("theta_trial", C.c_double), ("sigma", C.c_double),
                 ("max_backtrack", C.c_int), ("check_every", C.c_int), ("cm_levels", C.c_int),
-                ("dir_precision", C.c_int)]
+                ("dir_precision", C.c_int), ("precond", C.c_int)]
 
 
 class gs_result(C.Structure):
@@ -64,7 +65,7 @@ class gs_result(C.Structure):
                 ("virial", C.c_double), ("resid_inf", C.c_double), ("dE_last", C.c_double),
                 ("iters", C.c_int), ("iters_fp32", C.c_int), ("backtracks", C.c_int),
                 ("resets", C.c_int), ("status", C.c_int), ("wall_s", C.c_double),
-                ("iters_coarse", C.c_int)]
+                ("iters_coarse", C.c_int), ("dphi_inf", C.c_double)]
 
     def to_dict(self):
         d = {}

@@ -70,6 +70,11 @@ def test_default_options_and_footprint():
     assert abs(b64 - bmx - (4 * field // 2 + 3 * M * 4)) <= 2 ** 20   # reduction rows differ slightly
     assert gs.footprint_bytes(pb, gs.GS_MIXED, dir_precision=gs.GS_FP32) == bmx + b32
     assert gs.footprint_bytes(pb, gs.GS_FP64, dir_precision=7) == 0
+    # the options are validated: preconditioner kind and stopping criterion
+    assert gs.footprint_bytes(pb, gs.GS_FP64, precond=gs.GS_PC_POTENTIAL) == b64
+    assert gs.footprint_bytes(pb, gs.GS_FP64, precond=3) == 0
+    assert gs.footprint_bytes(pb, gs.GS_FP64, stop_kind=gs.GS_STOP_WAVEFN) == b64
+    assert gs.footprint_bytes(pb, gs.GS_FP64, stop_kind=4) == 0
     bad = inputs.Problem(dim=2, n=(48, 64), L=(12.0, 12.0))
     assert gs.footprint_bytes(bad, gs.GS_FP64) == 0
     pb3 = inputs.Problem(dim=3, n=(128, 128, 128), L=(8.0, 8.0, 8.0))

@@ -223,6 +223,51 @@ def test_solve_fp32_direction_matches_oracle(gpu_ctx, which):
         assert abs(sum(res["norm_comp"]) - 1.0) < 1e-13
 
 
+@pytest.mark.parametrize("kind", [gs.GS_PC_KINETIC, gs.GS_PC_POTENTIAL])
+@pytest.mark.parametrize("which", ["small2d", "3d16"])
+def test_preconditioner_kinds_match_oracle(gpu_ctx, kind, which):
+    """Kinetic (3.12) and potential (3.14) preconditioners: the same solve on
+    both sides (residual stop), E and mu to the FP64 bars, and iteration
+    counts close to the oracle's (the same algorithm; rounding decides the
+    rest)."""
+    if which == "small2d":
+        pb, psi0 = inputs.workload_small_2d()
+    else:
+        pb = inputs.Problem(dim=3, n=(16, 16, 16), L=(6.0, 6.0, 6.0), g=(1.0, 1.0, 2.0), omega=0.5,
+                            gamma=1.0, c0=200.0, c1=5.0)
+        psi0 = inputs.initial_guess(pb, ("a", "a", "a"))
+    tol = 1e-9
+    g, t, p = orc(pb)
+    ref = O.pcg(g, t, p, psi0, O.Options(stop_kind=gs.GS_STOP_RESIDUAL, tol=tol, precond=kind, max_iter=20000))
+    ev = O.evaluate(g, t, p, ref.psi)
+    psi, res = gpu_ctx.solve(pb, psi0, gs.default_options(stop_kind=gs.GS_STOP_RESIDUAL, tol=tol, precond=kind,
+                                                          max_iter=20000))
+    print(f"[precond {kind} {which}] gpu E={res['E']!r} it={res['iters']} | oracle E={ev['E']!r} it={ref.iters}",
+          flush=True)
+    assert res["status"] == 0 and ref.status == 0
+    assert rel(res["E"], ev["E"]) < 1e-10
+    assert rel(res["mu"], ev["mu"]) < 1e-8
+    assert abs(res["iters"] - ref.iters) <= 0.15 * ref.iters + 5
+
+
+def test_wavefunction_criterion_matches_oracle(gpu_ctx):
+    """Criterion (3.9): the GPU stops when the last step changed no component
+    anywhere by tol or more, at (nearly) the oracle's iteration, with the same
+    energy."""
+    pb, psi0 = inputs.workload_small_2d()
+    tol = 1e-6
+    g, t, p = orc(pb)
+    ref = O.pcg(g, t, p, psi0, O.Options(stop_kind=gs.GS_STOP_WAVEFN, tol=tol))
+    ev = O.evaluate(g, t, p, ref.psi)
+    psi, res = gpu_ctx.solve(pb, psi0, gs.default_options(stop_kind=gs.GS_STOP_WAVEFN, tol=tol))
+    print(f"[wavefn] gpu it={res['iters']} dphi={res['dphi_inf']:.3e} E={res['E']!r} | oracle it={ref.iters} "
+          f"E={ev['E']!r}", flush=True)
+    assert res["status"] == 0 and ref.status == 0
+    assert res["dphi_inf"] < tol
+    assert abs(res["iters"] - ref.iters) <= 3
+    assert rel(res["E"], ev["E"]) < 1e-9
+
+
 def test_solve_3d_small(gpu_ctx):
     pb = inputs.Problem(dim=3, n=(16, 16, 16), L=(6.0, 6.0, 6.0), g=(1.0, 1.0, 2.0), omega=0.5,
                         gamma=1.0, c0=200.0, c1=5.0)
