@@ -57,7 +57,7 @@ class _Params(C.Structure):
 class _Options(C.Structure):
     _fields_ = [("stop_kind", C.c_int), ("tol", C.c_double), ("max_iter", C.c_int),
                 ("theta_trial", C.c_double), ("sigma", C.c_double),
-                ("max_backtrack", C.c_int), ("precond", C.c_int)]
+                ("max_backtrack", C.c_int), ("precond", C.c_int), ("exact_ls", C.c_int)]
 
 
 class _Eval(C.Structure):
@@ -159,10 +159,11 @@ class Options:
     sigma: float = 0.5
     max_backtrack: int = 40
     precond: int = 0          # PC_COMBINED (3.15), PC_KINETIC (3.12), PC_POTENTIAL (3.14)
+    exact_ls: int = 0         # 0: Algorithm 2; 1: minimise E along the retraction curve
 
     def _c(self):
         return _Options(self.stop_kind, self.tol, self.max_iter, self.theta_trial,
-                        self.sigma, self.max_backtrack, self.precond)
+                        self.sigma, self.max_backtrack, self.precond, self.exact_ls)
 
 
 @dataclass
@@ -425,3 +426,12 @@ def tpoly_change(q, theta):
     f = _load().orc_tpoly_change
     f.restype = C.c_double
     return float(f(C.byref(q), C.c_double(theta)))
+
+
+def exact_theta(q, t0, max_halvings=40):
+    """Minimiser over (0, pi/2] of the energy change along the curve (the exact
+    line search option of ``pcg``), from the start t0; 0 if no decrease."""
+    f = _load().orc_exact_theta
+    f.restype = C.c_double
+    nh = C.c_int(0)
+    return float(f(C.byref(q), C.c_double(t0), C.c_int(max_halvings), C.byref(nh)))

@@ -56,6 +56,7 @@ typedef struct {
     double sigma;         /* backtracking factor of Algorithm 2 */
     int max_backtrack;    /* cap on Step 4 repetitions (the paper gives none) */
     int precond;          /* ORC_PC_*; every kind uses the shifts alpha_l of (3.13) */
+    int exact_ls;         /* 0: Algorithm 2; 1: minimise E along the curve (see orc_exact_theta) */
 } orc_options;
 typedef struct {
     double E, e_kin, e_pot, e_rot, e_spin, e_soc, e_pot2, e_pot4;
@@ -699,6 +700,56 @@ double orc_tpoly_change(const orc_tpoly* q, double theta) {
            s * s * s * s * q->e[4];
 }
 
+/* Exact line search along Phi(t) = cos t Phi + sin t Ph: the minimiser of the
+ * explicit energy change over (0, pi/2]. Starting from t0 (halved until the
+ * energy decreases, as in Algorithm 2), t is doubled while the energy keeps
+ * decreasing, which brackets a minimum in [t/2... 2t]; golden-section search
+ * then narrows the bracket to a relative width of 1e-12. Returns 0 when no
+ * decrease was found within max_halvings halvings. */
+double orc_exact_theta(const orc_tpoly* q, double t0, int max_halvings, int* halvings) {
+    const double tmax = 1.5707963267948966;
+    double t = fmin(t0, tmax);
+    double f = orc_tpoly_change(q, t);
+    int k = 0;
+    while (!(f < 0.0)) {
+        if (k >= max_halvings) { *halvings = k; return 0.0; }
+        t *= 0.5;
+        f = orc_tpoly_change(q, t);
+        k++;
+    }
+    *halvings = k;
+    /* bracket: lo < t < hi with f(t) below both ends (f(0) = 0 > f(t)) */
+    double lo = 0.0, hi = fmin(2.0 * t, tmax);
+    double fhi = orc_tpoly_change(q, hi);
+    while (fhi < f && hi < tmax) {
+        lo = t;
+        t = hi;
+        f = fhi;
+        hi = fmin(2.0 * hi, tmax);
+        fhi = orc_tpoly_change(q, hi);
+    }
+    if (fhi < f) return hi;   /* decreasing up to pi/2 */
+    /* golden-section search on [lo, hi] */
+    const double gr = 0.6180339887498949;
+    double a = lo, b = hi;
+    double x1 = b - gr * (b - a), x2 = a + gr * (b - a);
+    double f1 = orc_tpoly_change(q, x1), f2 = orc_tpoly_change(q, x2);
+    for (int it = 0; it < 200 && (b - a) > 1e-12 * b; ++it) {
+        if (f1 < f2) {
+            b = x2; x2 = x1; f2 = f1;
+            x1 = b - gr * (b - a);
+            f1 = orc_tpoly_change(q, x1);
+        } else {
+            a = x1; x1 = x2; f1 = f2;
+            x2 = a + gr * (b - a);
+            f2 = orc_tpoly_change(q, x2);
+        }
+    }
+    double tm = f1 < f2 ? x1 : x2;
+    double fm = f1 < f2 ? f1 : f2;
+    return fm < f ? tm : t;
+}
+
 /* ------------------------------------------------------------------------- */
 /* PCG, Algorithm 1 with the line search of Algorithm 2                      */
 /* ------------------------------------------------------------------------- */
@@ -776,11 +827,21 @@ int orc_pcg(const orc_grid* g, const orc_trap* t, const orc_params* p, const orc
         orc_tpoly_coeffs(g, t, p, phi, trial, &tp);
         int accepted = 0;
         double dE = 0.0;
-        for (int k = 0; k <= o->max_backtrack; ++k) {
-            dE = orc_tpoly_change(&tp, theta);
-            if (dE < 0.0) { accepted = 1; break; }
-            theta *= o->sigma;
-            st->backtracks++;
+        if (o->exact_ls) {
+            int nh = 0;
+            theta = orc_exact_theta(&tp, theta, o->max_backtrack, &nh);
+            st->backtracks += nh;
+            if (theta > 0.0) {
+                dE = orc_tpoly_change(&tp, theta);
+                accepted = dE < 0.0;
+            }
+        } else {
+            for (int k = 0; k <= o->max_backtrack; ++k) {
+                dE = orc_tpoly_change(&tp, theta);
+                if (dE < 0.0) { accepted = 1; break; }
+                theta *= o->sigma;
+                st->backtracks++;
+            }
         }
         if (!accepted || !isfinite(dE)) { status = ORC_STAGNATED; break; }
         double cs = cos(theta), sn = sin(theta);

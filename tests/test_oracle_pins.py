@@ -585,3 +585,42 @@ def test_wavefunction_criterion_stops_at_first_small_change():
     assert np.array_equal(runs[n], res.psi)
     assert np.max(np.abs(runs[n] - runs[n - 1])) < tol
     assert np.max(np.abs(runs[n - 1] - runs[n - 2])) >= tol
+
+
+# ---------------------------------------------------------------------------
+# exact line search (the option that minimises E along the retraction curve)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", [7, 21])
+def test_exact_theta_is_the_brute_force_minimiser(seed):
+    """The step of the exact option against brute force: the energy (1.7)
+    evaluated directly on a grid of 4000 points of (0, pi/2] along
+    cos t Phi + sin t P^ for the steepest-descent direction; the grid minimiser
+    is within one grid spacing and no grid point is lower than the step."""
+    pb, g, t, p, phi, Hp, mu, r = _setup_step(seed)
+    al = O.alpha(g, t, p, phi)
+    D = -O.precond(g, t, p, phi, al, r)
+    P = D - O.re_inner(g, D, phi) * phi
+    Ph = P / np.sqrt(O.re_inner(g, P, P))
+    q = O.tpoly(g, t, p, phi, Ph)
+    th = O.exact_theta(q, 0.1)
+    grid = np.linspace(0.0, np.pi / 2, 4001)[1:]
+    E0 = O.energy(g, t, p, phi)
+    Eg = np.array([O.energy(g, t, p, np.cos(x) * phi + np.sin(x) * Ph) for x in grid])
+    k = int(np.argmin(Eg))
+    print(seed, th, grid[k], Eg[k] - E0)
+    assert abs(th - grid[k]) <= grid[1] - grid[0]
+    E_th = O.energy(g, t, p, np.cos(th) * phi + np.sin(th) * Ph)
+    assert E_th <= Eg.min() + 1e-13 * abs(E0)
+    assert E_th < E0
+
+
+def test_exact_line_search_reaches_the_same_minimiser():
+    """The exact option changes the step, not the fixed point."""
+    pb, psi0 = inputs.workload_small_2d()
+    g, t, p = orc(pb)
+    a = O.pcg(g, t, p, psi0, O.Options(stop_kind=O.STOP_RESIDUAL, tol=1e-10))
+    b = O.pcg(g, t, p, psi0, O.Options(stop_kind=O.STOP_RESIDUAL, tol=1e-10, exact_ls=1))
+    assert a.status == O.OK and b.status == O.OK
+    ea, eb = O.evaluate(g, t, p, a.psi), O.evaluate(g, t, p, b.psi)
+    assert rel(eb["E"], ea["E"]) < 1e-12
+    assert rel(eb["mu"], ea["mu"]) < 1e-9
