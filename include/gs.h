@@ -65,6 +65,13 @@ extern "C" {
 #define GS_PC_POTENTIAL 2    /* P_V = (alpha_l + V + c0 rho)^{-1}, eq. (3.14); runs the same
                                 transforms with a unit spectral factor */
 
+/* Step size */
+#define GS_LS_ALG2 0         /* Algorithm 2: minimiser of the quadratic model (3.6)-(3.8), or
+                                theta_trial, halved by sigma until the energy decreases */
+#define GS_LS_EXACT 1        /* the step of Algorithm 2, then refined to a minimiser of the
+                                energy along the curve cos t Phi + sin t P^ (Newton steps on
+                                its explicit form in cos t and sin t; no transform involved) */
+
 /* arithmetic of the iteration */
 #define GS_FP64 0            /* all fields and transforms in double */
 #define GS_FP32 1            /* fields and transforms in float, reductions in double */
@@ -121,6 +128,7 @@ typedef struct {
                              stopping tests act on double quantities, so the limit is the same
                              and only the path to it changes. */
     int precond;          /* GS_PC_* (default GS_PC_COMBINED) */
+    int line_search;      /* GS_LS_ALG2 (default) or GS_LS_EXACT */
 } gs_options;
 
 /* Results; quantities refer to the returned Phi. */
@@ -167,7 +175,7 @@ void gs_destroy(gs_ctx* ctx);
 /* Fill *o with the defaults: energy criterion, tol 1e-12, max_iter 100000,
  * FP64, switch_resid 1e-6, fp32_max_iter 20000, stall_window 50,
  * theta_trial 0.1, sigma 0.5, max_backtrack 40, check_every 32, cm_levels 1,
- * dir_precision GS_FP64, precond GS_PC_COMBINED. */
+ * dir_precision GS_FP64, precond GS_PC_COMBINED, line_search GS_LS_ALG2. */
 void gs_default_options(gs_options* o);
 /* Device bytes a solve of this grid needs with these options (GS_MIXED counts
  * both the float and the double working sets; dir_precision GS_FP32 halves the

@@ -198,6 +198,30 @@ __device__ inline void ctrl_ls(SolveState* st, const Phys& p, const double (&s)[
         st->backtracks++;
     }
     if (!accepted || !isfinite(dE)) { stop_stagnated(st); return; }
+    if (st->exact_ls) {
+        // minimise the energy change along the curve: Newton steps on dE(t)
+        // from the accepted t, derivatives by central differences (the
+        // points t +- h by rotating (c, s)), a step kept only when it lowers
+        // dE; ends when the step is below 1e-9 t
+        const double h = 1e-4 * theta;
+        const double ch = cos(h), sh = sin(h);
+        for (int it = 0; it < 8; ++it) {
+            const double fp = dE_at(c * ch - sn * sh, sn * ch + c * sh, K);
+            const double fm = dE_at(c * ch + sn * sh, sn * ch - c * sh, K);
+            const double d1 = (fp - fm) / (2.0 * h), d2 = (fp - 2.0 * dE + fm) / (h * h);
+            if (!(d2 > 0.0)) break;
+            const double tn = fmin(fmax(theta - d1 / d2, 0.25 * theta), fmin(4.0 * theta, 1.5707963267948966));
+            const double cn = cos(tn), snn = sin(tn);
+            const double fn = dE_at(cn, snn, K);
+            if (!(fn < dE)) break;
+            const bool small = fabs(tn - theta) < 1e-9 * theta;
+            theta = tn;
+            c = cn;
+            sn = snn;
+            dE = fn;
+            if (small) break;
+        }
+    }
     st->theta = theta;
     st->c = c;
     st->s = sn;

@@ -113,26 +113,49 @@ __device__ __forceinline__ void block_row(const double (&acc)[NV], double* rows,
 }
 
 // Totals over nrows rows (fixed order) of NV values at the given stride, on
-// thread 0 of a block of PT threads. Entries k with (maxmask >> k) & 1 are maxima.
+// thread 0 of a block of PT threads. Entries k < 32 with (maxmask >> k) & 1 are
+// maxima (of non-negative values).
 template <int NV>
 __device__ __forceinline__ void gather(double (&tot)[NV], const double* rows, int nrows, int stride,
                                        unsigned maxmask = 0u) {
-    for (int k = 0; k < NV; ++k) tot[k] = 0.0;
+    // each thread adds its rows (all NV loads of a row in flight at once), then
+    // the sums are reduce-scattered inside each wave (recursive halving) and
+    // thread k adds the four wave partials of value k; maxima by block max
+    constexpr int P = Pow2Ceil<NV>::v;
+    static_assert(P <= 64, "at most 64 values per row");
+    constexpr int SH = 6 - ILog2<P>::v;   // lanes 2^SH apart hold the same value index
+    __shared__ double sh[PT / 64][P];
+    __shared__ double st[NV];
+    double v[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) v[k] = 0.0;
     for (int b = threadIdx.x; b < nrows; b += PT)
+#pragma unroll
         for (int k = 0; k < NV; ++k) {
             const double x = rows[(long long)b * stride + k];
-            tot[k] = ((maxmask >> k) & 1u) ? fmax(tot[k], x) : tot[k] + x;
+            v[k] = (k < 32 && ((maxmask >> k) & 1u)) ? fmax(v[k], x) : v[k] + x;
         }
-    double s[NV], m[NV];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double m[NV];
+#pragma unroll
     for (int k = 0; k < NV; ++k) {
-        const bool mx = (maxmask >> k) & 1u;
-        s[k] = mx ? 0.0 : tot[k];
-        m[k] = mx ? tot[k] : 0.0;
+        const bool mx = k < 32 && ((maxmask >> k) & 1u);
+        m[k] = mx ? bmax(v[k]) : 0.0;   // maxmask is uniform: the block max is taken by all threads
+        if (mx) v[k] = 0.0;
     }
-    bsum<NV>(s);
-    for (int k = 0; k < NV; ++k)
-        if ((maxmask >> k) & 1u) m[k] = bmax(m[k]);
-    for (int k = 0; k < NV; ++k) tot[k] = ((maxmask >> k) & 1u) ? m[k] : s[k];
+    halve_all<P, 32>(v, lane);
+    if ((lane & ((1 << SH) - 1)) == 0) sh[wv][lane >> SH] = v[0];
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        double t = sh[0][threadIdx.x];
+        for (int w = 1; w < PT / 64; ++w) t += sh[w][threadIdx.x];
+        st[threadIdx.x] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) tot[k] = (k < 32 && ((maxmask >> k) & 1u)) ? m[k] : st[k];
+    __syncthreads();   // sh and st are reused by the next gather of this size
 }
 
 // grid coordinates x_m = -L + m h of point index i ([Nz][Ny][Nx], x fastest)

@@ -66,6 +66,8 @@ static int check_options(const gs_options* o) {
     if (!o) return fail(GS_EINVAL, "options is NULL");
     if (o->stop_kind < GS_STOP_ENERGY || o->stop_kind > GS_STOP_WAVEFN) return fail(GS_EINVAL, "options.stop_kind invalid");
     if (o->precond < GS_PC_COMBINED || o->precond > GS_PC_POTENTIAL) return fail(GS_EINVAL, "options.precond invalid");
+    if (o->line_search != GS_LS_ALG2 && o->line_search != GS_LS_EXACT)
+        return fail(GS_EINVAL, "options.line_search invalid");
     if (!(o->tol >= 0.0)) return fail(GS_EINVAL, "options.tol must be >= 0");
     if (o->max_iter < 0) return fail(GS_EINVAL, "options.max_iter must be >= 0");
     if (o->precision < GS_FP64 || o->precision > GS_MIXED) return fail(GS_EINVAL, "options.precision invalid");
@@ -291,6 +293,7 @@ static void init_state(SolveState* h, const gs_options* o, int phase) {
     h->phase_max_iter = o->fp32_max_iter;
     h->stall_window = o->stall_window;
     h->precond = o->precond;
+    h->exact_ls = o->line_search == GS_LS_EXACT;
     h->wchange = INFINITY;
     h->phase = phase;
     h->best_resid = INFINITY;
@@ -1439,6 +1442,7 @@ void gs_default_options(gs_options* o) {
     o->cm_levels = 1;
     o->dir_precision = GS_FP64;
     o->precond = GS_PC_COMBINED;
+    o->line_search = GS_LS_ALG2;
 }
 
 size_t gs_footprint_bytes(const gs_grid* g, const gs_options* o) {

@@ -112,7 +112,7 @@ struct SolveState {
     int best_iter;       // stagnation tracking (FP32 phase)
     int nonfinite;
     // options
-    int stop_kind, max_iter, max_backtrack, phase_max_iter, stall_window, precond;
+    int stop_kind, max_iter, max_backtrack, phase_max_iter, stall_window, precond, exact_ls;
     double tol, switch_resid, theta_trial, sigma;
     // current iterate
     double E, mu, norm2, alpha[3];

@@ -19,6 +19,7 @@ GS_WMAXITER, GS_WSTAGNATED = 1, 2
 GS_PENDING = 16
 GS_STOP_ENERGY, GS_STOP_RESIDUAL, GS_STOP_EITHER, GS_STOP_WAVEFN = 0, 1, 2, 3
 GS_PC_COMBINED, GS_PC_KINETIC, GS_PC_POTENTIAL = 0, 1, 2
+GS_LS_ALG2, GS_LS_EXACT = 0, 1
 GS_FP64, GS_FP32, GS_MIXED = 0, 1, 2
 
 EXPORTS = ("gs_create", "gs_destroy", "gs_default_options", "gs_footprint_bytes", "gs_solve",
@@ -55,7 +56,7 @@ class gs_options(C.Structure):
                 ("precision", C.c_int), ("switch_resid", C.c_double), ("fp32_max_iter", C.c_int),
                 ("stall_window", C.c_int), ("theta_trial", C.c_double), ("sigma", C.c_double),
                 ("max_backtrack", C.c_int), ("check_every", C.c_int), ("cm_levels", C.c_int),
-                ("dir_precision", C.c_int), ("precond", C.c_int)]
+                ("dir_precision", C.c_int), ("precond", C.c_int), ("line_search", C.c_int)]
 
 
 class gs_result(C.Structure):

@@ -250,6 +250,34 @@ def test_preconditioner_kinds_match_oracle(gpu_ctx, kind, which):
     assert abs(res["iters"] - ref.iters) <= 0.15 * ref.iters + 5
 
 
+@pytest.mark.parametrize("which", ["small2d", "3d16", "rot32"])
+def test_exact_line_search_matches_oracle(gpu_ctx, which):
+    """The exact line-search option (the step minimises E along the curve):
+    GPU (Newton refinement of the Algorithm-2 step) and oracle (bracket and
+    golden section) reach the same minimiser, residual stop, FP64 bars."""
+    if which == "small2d":
+        pb, psi0 = inputs.workload_small_2d()
+    elif which == "3d16":
+        pb = inputs.Problem(dim=3, n=(16, 16, 16), L=(6.0, 6.0, 6.0), g=(1.0, 1.0, 2.0), omega=0.5,
+                            gamma=1.0, c0=200.0, c1=5.0)
+        psi0 = inputs.initial_guess(pb, ("a", "a", "a"))
+    else:
+        pb = inputs.Problem(dim=2, n=(32, 32), L=(6.0, 6.0), omega=0.3, gamma=0.8, c0=90.0, c1=0.7)
+        psi0 = inputs.initial_guess(pb, ("b", "a", "a"), noise=1e-3, seed=101)
+    tol = 1e-10
+    g, t, p = orc(pb)
+    ref = O.pcg(g, t, p, psi0, O.Options(stop_kind=gs.GS_STOP_RESIDUAL, tol=tol, exact_ls=1))
+    ev = O.evaluate(g, t, p, ref.psi)
+    psi, res = gpu_ctx.solve(pb, psi0, gs.default_options(stop_kind=gs.GS_STOP_RESIDUAL, tol=tol,
+                                                          line_search=gs.GS_LS_EXACT))
+    _, alg2 = gpu_ctx.solve(pb, psi0, gs.default_options(stop_kind=gs.GS_STOP_RESIDUAL, tol=tol))
+    print(f"[exact ls {which}] gpu E={res['E']!r} it={res['iters']} (Alg. 2: {alg2['iters']}) | oracle "
+          f"E={ev['E']!r} it={ref.iters}", flush=True)
+    assert res["status"] == 0 and ref.status == 0
+    assert rel(res["E"], ev["E"]) < 1e-10
+    assert rel(res["mu"], ev["mu"]) < 1e-8
+
+
 def test_wavefunction_criterion_matches_oracle(gpu_ctx):
     """Criterion (3.9): the GPU stops when the last step changed no component
     anywhere by tol or more, at (nearly) the oracle's iteration, with the same
