@@ -36,6 +36,16 @@ template <int N> struct Lay {
 };
 __device__ __forceinline__ int lx(int e) { return e + (e >> 4); }
 
+// Workgroups are dispatched to the 8 XCDs in turn, and each XCD has its own
+// L2. The transposed passes read tiles of TILE values per line position, 32
+// or 64 bytes: two neighbouring tiles share every 128-byte line. This map
+// hands each XCD a contiguous range of tiles in order (when the grid width is
+// a multiple of 8), so the two halves of a line are read by blocks of one XCD
+// at about the same time instead of being fetched once by each of two XCDs.
+__device__ __forceinline__ int xcd_block(int b, int G) {
+    return (G & 7) ? b : (b & 7) * (G >> 3) + (b >> 3);
+}
+
 template <typename R, bool INV>
 __device__ __forceinline__ cpx<R> twid(const cpx<R>* __restrict__ tw, int m) {
     cpx<R> w = tw[m];
@@ -308,7 +318,7 @@ __global__ __launch_bounds__(NT) void k_invT(const Slot* __restrict__ slots, int
     cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
     cpx<R>* lds2 = lds + TILE * PITCH;
     const int tiles = Cc / TILE;
-    int blk = blockIdx.x;
+    int blk = xcd_block(blockIdx.x, gridDim.x);
     const int ct = blk % tiles;
     blk /= tiles;
     const int bb = blk % B;
@@ -372,7 +382,7 @@ __global__ __launch_bounds__(NT) void k_invT_pre(const Slot* __restrict__ slots,
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
     const int tiles = Cc / TILE;
-    int blk = blockIdx.x;
+    int blk = xcd_block(blockIdx.x, gridDim.x);
     const int ct = blk % tiles;
     blk /= tiles;
     const int bb = blk % B;
