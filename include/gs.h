@@ -121,10 +121,11 @@ typedef struct {
     int cm_levels;        /* cascadic multigrid (Algorithm 3): solve on grids n/2^(L-1), ..., n/2, n
                              (every n[a]/2^(L-1) >= 16), each level warm-started from the
                              interpolated result of the previous one; 1 = plain PCG */
-    int dir_precision;    /* precision of the search direction, of its preconditioning (3.15) and of
-                             H_L applied to it while Phi, H_L Phi and the residuals are double
-                             (GS_FP64 solves and the double phase of GS_MIXED): GS_FP64 (default)
-                             or GS_FP32. Every reduction stays double; the line search and the
+    int dir_precision;    /* precision of the search direction, of its preconditioning (3.15), of
+                             H_L applied to it and of the stored residuals r^n, r^{n-1}, while Phi
+                             and H_L Phi are double (GS_FP64 solves and the double phase of
+                             GS_MIXED): GS_FP64 (default) or GS_FP32. The residual is formed in
+                             double and every reduction stays double; the line search and the
                              stopping tests act on double quantities, so the limit is the same
                              and only the path to it changes. */
     int precond;          /* GS_PC_* (default GS_PC_COMBINED) */

@@ -100,7 +100,7 @@ static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // buffers of the state type (the others are of the direction type; scratch
 // fields are sized for the state type, the wider of the two)
-static bool state_buf(int b) { return b == B_PHI || b == B_HL || b == B_R0 || b == B_R1 || b >= B_T6A; }
+static bool state_buf(int b) { return b == B_PHI || b == B_HL || b >= B_T6A; }
 
 // Device memory of one slot: 12 three-component fields (Phi, H_L Phi, r^n,
 // r^{n-1}, Pr, P, H_L P^, u, four scratch), two six-component scratch fields,
@@ -389,7 +389,7 @@ static hipError_t chain_pre(const Geo<RS, RD>& G, Sub L, int dir, int out, hipSt
     const int Nx = G.n[0], Ny = G.n[1], Nz = G.n[2];
     const double F = 3.0 * G.M * sizeof(cpx<RD>) * L.ns, Fr = 3.0 * G.M * sizeof(RD) * L.ns;
     const double Fs = 3.0 * G.M * sizeof(cpx<RS>) * L.ns;
-    const double b_inv = (dir ? 3 * F + 3 * Fs : 2 * F) + Fr;
+    const double b_inv = (dir ? 5 * F + Fs : 2 * F) + Fr;
     hipError_t e;
     if (G.dim == 2) {
         if ((e = timed_ns(tm, KK_PRE_FWD, 2 * F, L.ns, s, [&] { return launch_fwdT<RD, RD>(Nx, PRO_PLAIN, 0, L.tab, L.ns, B_U, B_T6A, B_NONE, B_NONE, 1, Ny, 3, G.twd[0], s); }))) return e;
@@ -472,7 +472,7 @@ static hipError_t iterate(const Geo<RS, RD>& G, Sub L, int do_refresh, hipStream
         if ((e = refresh<RS, RD>(G, L, s, tm))) return e;
     }
     if (tm) tm->chain = 1;
-    if ((e = timed_ns(tm, KK_RESID, 5 * Fs + 3 * Fd + Frd, L.ns, s, [&] { return launch_resid<RS, RD>(L.tab, L.ns, G.g, 0, s); }))) return e;
+    if ((e = timed_ns(tm, KK_RESID, 4 * Fs + 4 * Fd + Frd, L.ns, s, [&] { return launch_resid<RS, RD>(L.tab, L.ns, G.g, 0, s); }))) return e;
     if (tm) tm->chain = 2;
     if ((e = chain_pre<RS, RD>(G, L, 1, B_PR, s, tm))) return e;
     if ((e = fin(G.g, L, FIN_DIR, s, tm))) return e;

@@ -395,8 +395,8 @@ __global__ __launch_bounds__(NT) void k_invT_pre(const Slot* __restrict__ slots,
     __syncthreads();
     lds_fft<R, N, TILE, NT, true>(lds, tw);
     double acc[NS_DIR] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    const cpx<RS>* r = dir ? fld<RS>(S, B_R0 + st->cur) : nullptr;
-    const cpx<RS>* rp = dir ? fld<RS>(S, B_R0 + (st->cur ^ 1)) : nullptr;
+    const cpx<R>* r = dir ? fld<R>(S, B_R0 + st->cur) : nullptr;
+    const cpx<R>* rp = dir ? fld<R>(S, B_R0 + (st->cur ^ 1)) : nullptr;
     const cpx<RS>* phi = fld<RS>(S, B_PHI);
     const cpx<R>* Pprev = fld<R>(S, B_P);
     for (int e = threadIdx.x; e < TILE * N; e += NT) {

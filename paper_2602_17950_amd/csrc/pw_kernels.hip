@@ -82,7 +82,7 @@ __global__ __launch_bounds__(PT) void k_resid(const Slot* slots, RedGeom g, int 
     const double mu = st->mu;
     const double al[3] = {st->alpha[0], st->alpha[1], st->alpha[2]};
     const double fl = 1e-12 * fmax(1.0, fmax(al[0], fmax(al[1], al[2])));
-    cpx<R>* r = fld<R>(S, B_R0 + st->cur);
+    cpx<RD>* r = fld<RD>(S, B_R0 + st->cur);   // held in the direction type (beta sums, P_C input)
     const bool kinetic = st->precond == GS_PC_KINETIC;   // no potential factor (3.12)
     double acc[NS_RES] = {0.0, 0.0, 0.0, 0.0};
     double wmax = 0.0;
@@ -115,12 +115,12 @@ __global__ __launch_bounds__(PT) void k_resid(const Slot* slots, RedGeom g, int 
             const cpx<double> rc = hl[c] + nl[c] - mu * ph[c];
             acc[0] = fmax(acc[0], sqrt(cabs2(rc)));
             if (final_only) continue;
-            const cpx<R> rr = cmk((R)rc.x, (R)rc.y);
+            const cpx<RD> rr = cmk((RD)rc.x, (RD)rc.y);
             r[c * M + i] = rr;
             const double d = fmax(al[c] + V2 + V4 + p.c0 * sp.rho, fl);
             const RD w = kinetic ? (RD)1 : (RD)(1.0 / sqrt(d));
             pvv[c * M + i] = w;
-            uf[c * M + i] = w * cvt<RD>(rr);
+            uf[c * M + i] = w * rr;
             const cpx<double> rw = wid(rr);
             acc[1] += re_dot(rw, P[c]);
             acc[2] += re_dot(ph[c], P[c]);
