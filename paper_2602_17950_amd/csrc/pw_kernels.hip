@@ -13,8 +13,13 @@
 
 namespace gs {
 
+// blocks per slot of the pointwise passes (= partial-sum rows): two points per
+// thread, so that a block's reduction is shared by 512 points, but at least
+// min(M/256, 64) blocks for small grids, and at most 2048
 int pw_blocks(long long M) {
-    long long b = (M + PT - 1) / PT;
+    long long b = (M + 512 - 1) / 512;
+    const long long lo = std::min<long long>((M + PT - 1) / PT, 64);
+    b = std::max(b, lo);
     return (int)(b < 2048 ? b : 2048);
 }
 
