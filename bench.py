@@ -22,6 +22,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import itertools
 import json
 import os
 import re
@@ -40,7 +41,12 @@ KERNEL_SOURCES = ("paper_2602_17950_amd/csrc/fft_kernels.hip", "paper_2602_17950
                   "paper_2602_17950_amd/csrc/device_common.h", "paper_2602_17950_amd/csrc/control.h",
                   "paper_2602_17950_amd/csrc/gs_internal.h")
 TRAFFIC_SUMMARY = "profiles/hbm_traffic_batch256_vortex.md"
-SECTIONS = ("batch", "single", "cm3d", "sweep", "serve")
+SECTIONS = ("batch", "single", "cm3d", "sweep", "table2", "serve")
+# Table 2 (Example 3): lowest energy over the 1000 guess combinations of Sec. 4, and the
+# paper's CM-PCG CPU seconds for that one solve (a Xeon Gold 6248R, threads not stated;
+# context only)
+TABLE2 = {0.6: (2.2833, 7.0), 0.7: (2.0437, 116.0), 0.8: (1.6806, 46.0), 0.9: (1.0492, 1340.0)}
+GUESS_KINDS = ("a", "b", "bbar", "c", "cbar", "d", "dbar", "e", "ebar", "f")
 
 
 def kernel_source_hash():
@@ -311,6 +317,44 @@ def main():
         line["sweep"] = out
         cap = out["mixed"]["solves_per_s"]
         del sw
+
+    # ------------------------------------------------------------------ table2
+    if "table2" in sections:
+        tb = {"rows": {}}
+        total, nsolve, allmatch = 0.0, 0, True
+        combos = list(itertools.product(GUESS_KINDS, repeat=3))
+        opt = gs.default_options(precision=gs.GS_MIXED, dir_precision=mdir, tol=1e-14, cm_levels=3)
+        for om, (E_paper, cpu_paper) in TABLE2.items():
+            kw = dict(dim=2, L=(12.0, 12.0), omega=om, gamma=0.3, c0=50.0, c1=0.5)
+            fine, coarse = inputs.Problem(n=(256, 256), **kw), inputs.Problem(n=(64, 64), **kw)
+            guess = [torch.from_numpy(inputs.initial_guess(coarse, k)).to("cuda") for k in combos]
+            outs = [torch.empty((3, 256, 256), dtype=torch.complex128, device="cuda") for _ in combos]
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            rs = ctx.batch_solve([(fine, g, o, opt, None) for g, o in zip(guess, outs)])
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            E = [r["E"] for r in rs]
+            k = int(np.argmin(E))
+            match = round(E[k], 4) == E_paper
+            allmatch = allmatch and match
+            total += dt
+            nsolve += len(rs)
+            tb["rows"][str(om)] = {"s": dt, "solves": len(rs), "E_lowest": E[k], "from": "".join(
+                c + " " for c in combos[k]).strip(), "paper_E": E_paper, "match_4_decimals": match,
+                "paper_cm_pcg_cpu_s_one_solve": cpu_paper,
+                "fine_iters_mean": float(np.mean([r["iters"] for r in rs])),
+                "coarse_iters_mean": float(np.mean([r["iters_coarse"] for r in rs])),
+                "warnings": sum(1 for r in rs if r["rc"] > 0), "errors": sum(1 for r in rs if r["rc"] < 0)}
+            log(f"table2 omega={om}: {dt:.2f}s, lowest E {E[k]:.8f} ({'matches' if match else 'differs from'} "
+                f"{E_paper})")
+            del guess, outs
+        tb.update({"s": total, "solves": nsolve, "solves_per_s": nsolve / total, "all_match": allmatch,
+                   "workload": ("Table 2 (Example 3): for Omega in {0.6,0.7,0.8,0.9}, the 1000 component-wise "
+                                "combinations of the ten guesses of Sec. 4 on [-12,12]^2 (gamma 0.3, c0 50, "
+                                "c1 0.5), each solved by CM-PCG 64^2->128^2->256^2, mixed precision, energy "
+                                "criterion 1e-14; one batch per Omega; the lowest energy is the ground state")})
+        line["table2"] = tb
 
     # ------------------------------------------------------------------- serve
     if "serve" in sections:
