@@ -174,14 +174,21 @@ __device__ __forceinline__ void fft_pass(cpx<R>* buf, const cpx<R>* __restrict__
 #pragma unroll
             for (int r = 0; r < RAD; ++r) v[i][r] = src[lx(j + r * NB)];
             if constexpr (NS > 1) {
-                // w^r as a running product of one table value (at most 15
-                // products: relative error ~ RAD ulp)
-                const cpx<R> w1 = twid<R, INV>(tw, k * TWS);
-                cpx<R> w = w1;
+                if constexpr (sizeof(R) == 4) {
+                    // float: every power from the table (a running product over
+                    // radix 16 would cost up to 15 ulp)
 #pragma unroll
-                for (int r = 1; r < RAD; ++r) {
-                    v[i][r] = cmul(v[i][r], w);
-                    if (r + 1 < RAD) w = cmul(w, w1);
+                    for (int r = 1; r < RAD; ++r) v[i][r] = cmul(v[i][r], twid<R, INV>(tw, r * k * TWS));
+                } else {
+                    // double: w^r as a running product of one table value (at most
+                    // 7 products, ~1e-15 relative)
+                    const cpx<R> w1 = twid<R, INV>(tw, k * TWS);
+                    cpx<R> w = w1;
+#pragma unroll
+                    for (int r = 1; r < RAD; ++r) {
+                        v[i][r] = cmul(v[i][r], w);
+                        if (r + 1 < RAD) w = cmul(w, w1);
+                    }
                 }
             }
             dftr<R, RAD, INV>(v[i]);
