@@ -634,17 +634,24 @@ static int get_twiddle(Ctx& cx, int N, const cpx<R>** out) {
         *out = (const cpx<R>*)it->second;
         return GS_OK;
     }
+    // exp(-2 pi i m / N) in type R; a float table is followed by the same
+    // table in double (the float passes form twiddle powers from it)
+    const bool dbl_too = sizeof(R) == 4;
     std::vector<cpx<R>> h(N);
+    std::vector<cpx<double>> hd(dbl_too ? N : 0);
     for (int m = 0; m < N; ++m) {
         const long double ang = 2.0L * 3.14159265358979323846264338327950288L * (long double)m / (long double)N;
         h[m] = cpx<R>{(R)cosl(ang), (R)(-sinl(ang))};
+        if (dbl_too) hd[m] = cpx<double>{(double)cosl(ang), (double)(-sinl(ang))};
     }
+    const size_t bytes = sizeof(cpx<R>) * N, dbytes = sizeof(cpx<double>) * hd.size();
     void* d = nullptr;
-    if (hipMalloc(&d, sizeof(cpx<R>) * N) != hipSuccess) {
+    if (hipMalloc(&d, bytes + dbytes) != hipSuccess) {
         (void)hipGetLastError();
         return fail(GS_ENOMEM, "twiddle table allocation failed");
     }
-    HIPCHK(hipMemcpy(d, h.data(), sizeof(cpx<R>) * N, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(d, h.data(), bytes, hipMemcpyHostToDevice));
+    if (dbl_too) HIPCHK(hipMemcpy(static_cast<char*>(d) + bytes, hd.data(), dbytes, hipMemcpyHostToDevice));
     cx.twiddles[key] = d;
     *out = (const cpx<R>*)d;
     return GS_OK;

@@ -175,10 +175,17 @@ __device__ __forceinline__ void fft_pass(cpx<R>* buf, const cpx<R>* __restrict__
             for (int r = 0; r < RAD; ++r) v[i][r] = src[lx(j + r * NB)];
             if constexpr (NS > 1) {
                 if constexpr (sizeof(R) == 4) {
-                    // float: every power from the table (a running product over
-                    // radix 16 would cost up to 15 ulp)
+                    // float: the running product in double from the double table
+                    // that follows the float one (N entries on), each power
+                    // rounded once: correctly rounded twiddles from one load
+                    const cpx<double>* twd = reinterpret_cast<const cpx<double>*>(tw + N);
+                    const cpx<double> w1 = twid<double, INV>(twd, k * TWS);
+                    cpx<double> w = w1;
 #pragma unroll
-                    for (int r = 1; r < RAD; ++r) v[i][r] = cmul(v[i][r], twid<R, INV>(tw, r * k * TWS));
+                    for (int r = 1; r < RAD; ++r) {
+                        v[i][r] = cmul(v[i][r], cmk((R)w.x, (R)w.y));
+                        if (r + 1 < RAD) w = cmul(w, w1);
+                    }
                 } else {
                     // double: w^r as a running product of one table value (at most
                     // 7 products, ~1e-15 relative)
