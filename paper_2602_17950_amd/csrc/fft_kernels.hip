@@ -451,6 +451,18 @@ template <typename R, int N, int LPB, int OP, int NT> struct MidPlan {
     static constexpr bool PIPE = EPT * (OP == MID_HLX ? 2 : 1) <= 6;
     // LDS copy of the input for the 2D rotation term when three line groups fit in 64 KB
     static constexpr bool CLDS = 3 * NLN * Lay<N>::P * (int)sizeof(cpx<R>) <= 65536;
+    // line buffers of the block (X; Z or Y; the input copy) and the byte offset
+    // of the block's copy of the twiddle table after them
+    __host__ __device__ static constexpr int nbuf(bool rot_any) {
+        return OP == MID_PRE ? 1 : (rot_any ? 2 + (CLDS ? 1 : 0) : (OP == MID_HLX ? 2 : 1));
+    }
+    __host__ __device__ static constexpr size_t tw_offset(bool rot_any) {
+        return ((size_t)nbuf(rot_any) * NLN * Lay<N>::P * sizeof(cpx<R>) + 15) & ~(size_t)15;
+    }
+    // the table of exp(-2 pi i m / N), and for float the double table after it;
+    // copied into LDS by a pipelined block, which reuses it for many groups
+    static constexpr size_t TW_BYTES =
+        PIPE ? (size_t)N * sizeof(cpx<R>) + (sizeof(R) == 4 ? (size_t)N * 16 : 0) : 0;
 };
 
 // one complex value as a single vector access (keeps register arrays of
@@ -516,6 +528,16 @@ __global__ __launch_bounds__(NT) void k_mid(const Slot* __restrict__ slots, int 
     // are read by the thread that then writes its B values)
     cpx<R>* Y = X + NLN * PITCH;
     cpx<R>* Cp = X + 2 * NLN * PITCH;                  // input copy for the 2D rotation term
+    // a pipelined block copies the twiddle tables once into LDS: every transform
+    // stage of every line group then reads them there instead of from global
+    // memory (visible after the first barrier of the group loop)
+    const cpx<R>* twl = tw;
+    if constexpr (MP::PIPE) {
+        cpx<R>* t = reinterpret_cast<cpx<R>*>(smem_raw + MP::tw_offset(rot_any != 0));
+        for (int e = threadIdx.x; e < (int)(MP::TW_BYTES / 16); e += NT)
+            reinterpret_cast<vec2<double>*>(t)[e] = reinterpret_cast<const vec2<double>*>(tw)[e];
+        twl = t;
+    }
     const bool doB = HL && rot;
     const bool rot2d = doB && p.dim == 2;
     const long long cs = (long long)nlines * N;
@@ -551,10 +573,10 @@ __global__ __launch_bounds__(NT) void k_mid(const Slot* __restrict__ slots, int 
         if (MP::PIPE && grp + (int)gridDim.x < ngroups)
             mid_fetch<R, N, LPB, OP, NT>(in, in2, cs, (grp + gridDim.x) * LPB, pa, pb);
         if constexpr (X2 && JOINT) {
-            lds_fft<R, N, 2 * NLN, NT, false>(X, tw);   // X and Z are adjacent
+            lds_fft<R, N, 2 * NLN, NT, false>(X, twl);   // X and Z are adjacent
         } else {
-            lds_fft<R, N, NLN, NT, false>(X, tw);
-            if constexpr (X2) lds_fft<R, N, NLN, NT, false>(Z, tw);
+            lds_fft<R, N, NLN, NT, false>(X, twl);
+            if constexpr (X2) lds_fft<R, N, NLN, NT, false>(Z, twl);
         }
         double acc[X2 ? NS_KIN : 4];
 #pragma unroll
@@ -621,11 +643,11 @@ __global__ __launch_bounds__(NT) void k_mid(const Slot* __restrict__ slots, int 
         }
         __syncthreads();
         if constexpr (HL && JOINT) {
-            if (doB) lds_fft<R, N, 2 * NLN, NT, true>(X, tw);   // X and Y are adjacent
-            else lds_fft<R, N, NLN, NT, true>(X, tw);
+            if (doB) lds_fft<R, N, 2 * NLN, NT, true>(X, twl);   // X and Y are adjacent
+            else lds_fft<R, N, NLN, NT, true>(X, twl);
         } else {
-            lds_fft<R, N, NLN, NT, true>(X, tw);
-            if (doB) lds_fft<R, N, NLN, NT, true>(Y, tw);
+            lds_fft<R, N, NLN, NT, true>(X, twl);
+            if (doB) lds_fft<R, N, NLN, NT, true>(Y, twl);
         }
 #pragma unroll
         for (int i = 0; i < EPT; ++i) {
@@ -776,17 +798,18 @@ static hipError_t mid_n(int op, const Slot* slots, int nslots, int in, int outA,
     constexpr int NTB = nt_mid<R>(N);
     if (nlines % LPB) return hipErrorInvalidValue;
     const int ngroups = nlines / LPB;
-    const size_t buf = (size_t)3 * LPB * Lay<N>::P * sizeof(cpx<R>);
+    using HL = MidPlan<R, N, LPB, MID_HL, NTB>;
+    using HX = MidPlan<R, N, LPB, MID_HLX, NTB>;
+    using PR = MidPlan<R, N, LPB, MID_PRE, NTB>;
+    const bool ra = rot_any != 0;
     if (op == MID_HL)
-        return mid_go<k_mid<R, N, LPB, MID_HL, NTB>, MidPlan<R, N, LPB, MID_HL, NTB>>(
-            ngroups, nslots, NTB, (rot_any ? 2 + MidPlan<R, N, LPB, MID_HL, NTB>::CLDS : 1) * buf, s, slots, in,
-            outA, outB, nlines, rot_any, tw);
+        return mid_go<k_mid<R, N, LPB, MID_HL, NTB>, HL>(ngroups, nslots, NTB, HL::tw_offset(ra) + HL::TW_BYTES, s,
+                                                         slots, in, outA, outB, nlines, rot_any, tw);
     if (op == MID_HLX)
-        return mid_go<k_mid<R, N, LPB, MID_HLX, NTB>, MidPlan<R, N, LPB, MID_HLX, NTB>>(
-            ngroups, nslots, NTB, (rot_any ? 2 + MidPlan<R, N, LPB, MID_HLX, NTB>::CLDS : 2) * buf, s, slots, in,
-            outA, outB, nlines, rot_any, tw);
-    return mid_go<k_mid<R, N, LPB, MID_PRE, NTB>, MidPlan<R, N, LPB, MID_PRE, NTB>>(
-        ngroups, nslots, NTB, buf, s, slots, in, outA, outB, nlines, 0, tw);
+        return mid_go<k_mid<R, N, LPB, MID_HLX, NTB>, HX>(ngroups, nslots, NTB, HX::tw_offset(ra) + HX::TW_BYTES, s,
+                                                          slots, in, outA, outB, nlines, rot_any, tw);
+    return mid_go<k_mid<R, N, LPB, MID_PRE, NTB>, PR>(ngroups, nslots, NTB, PR::tw_offset(false) + PR::TW_BYTES, s,
+                                                      slots, in, outA, outB, nlines, 0, tw);
 }
 
 #define GS_SWITCH_N(CALL)                        \
