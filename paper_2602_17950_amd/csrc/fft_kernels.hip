@@ -239,6 +239,67 @@ __device__ __forceinline__ void lds_fft(cpx<R>* buf, const cpx<R>* __restrict__ 
     fft_passes<R, N, NL, NT, rmax<R>(), 1, INV>(buf, tw);
 }
 
+// one complex value as a single vector access (keeps register arrays of
+// complex values out of private memory)
+template <typename R> using vec2 = R __attribute__((ext_vector_type(2)));
+template <typename R> __device__ __forceinline__ void ld2(cpx<R>& d, const cpx<R>* p) {
+    const vec2<R> v = *reinterpret_cast<const vec2<R>*>(p);
+    d.x = v.x;
+    d.y = v.y;
+}
+template <typename R> __device__ __forceinline__ void st2(cpx<R>* p, const cpx<R>& a) {
+    vec2<R> v;
+    v.x = a.x;
+    v.y = a.y;
+    *reinterpret_cast<vec2<R>*>(p) = v;
+}
+
+// Transposed passes (invT, invT_pre): a unit is one tile of TILE lines of one
+// component. A block takes units b, b + G, ... (b in the XCD order); when
+// the prefetch of the next unit's input takes at most 32 registers, the
+// next unit is loaded while the current one is transformed and the twiddle
+// tables are read from a copy in LDS.
+template <typename R, int N, int TILE, int NT> struct TilePlan {
+    static constexpr int EPT = (TILE * N + NT - 1) / NT;
+    static constexpr bool PIPE = 2 * EPT * (int)sizeof(cpx<R>) <= 128;
+    static constexpr size_t TW_BYTES =
+        PIPE ? (size_t)N * sizeof(cpx<R>) + (sizeof(R) == 4 ? (size_t)N * 16 : 0) : 0;
+    __host__ __device__ static constexpr size_t tw_offset(int nbuf) {
+        return ((size_t)nbuf * TILE * Lay<N>::P * sizeof(cpx<R>) + 15) & ~(size_t)15;
+    }
+};
+
+template <typename R, int N, int TILE, int NT>
+__device__ __forceinline__ void tile_fetch(const cpx<R>* __restrict__ in, const cpx<R>* __restrict__ in2, int nin,
+                                           long long base, int B, int Cc,
+                                           cpx<R> (&a)[TilePlan<R, N, TILE, NT>::EPT],
+                                           cpx<R> (&b)[TilePlan<R, N, TILE, NT>::EPT]) {
+#pragma unroll
+    for (int i = 0; i < TilePlan<R, N, TILE, NT>::EPT; ++i) {
+        const int e = threadIdx.x + i * NT;
+        if (TILE * N % NT == 0 || e < TILE * N) {
+            const int l = e % TILE, m = e / TILE;
+            const long long gi = base + (long long)m * B * Cc + l;
+            ld2(a[i], in + gi);
+            if (nin == 2) ld2(b[i], in2 + gi);
+        }
+    }
+}
+// unit u -> component c, position bb and first line c0 of its tile
+__device__ __forceinline__ void tile_unit(int u, int tiles, int B, int TILE_, int& c, int& bb, int& c0) {
+    const int ct = u % tiles;
+    const int blk = u / tiles;
+    bb = blk % B;
+    c = blk / B;
+    c0 = ct * TILE_;
+}
+// copy of the twiddle table(s) into LDS (16-byte chunks)
+template <typename R, int N>
+__device__ __forceinline__ void tw_to_lds(cpx<R>* dst, const cpx<R>* __restrict__ tw, size_t bytes, int nt) {
+    for (int e = threadIdx.x; e < (int)(bytes / 16); e += nt)
+        reinterpret_cast<vec2<double>*>(dst)[e] = reinterpret_cast<const vec2<double>*>(tw)[e];
+}
+
 // ---------------------------------------------------------------------------
 // forward pass with transposed store
 // ---------------------------------------------------------------------------
@@ -327,27 +388,61 @@ __global__ __launch_bounds__(NT) void k_invT(const Slot* __restrict__ slots, int
     cpx<R>* __restrict__ out = fld<R>(S, iout);
     cpx<R>* __restrict__ out2 = (nin == 2 && iout2 >= 0) ? fld<R>(S, iout2) : nullptr;
     const cpx<R>* __restrict__ uin = iuin >= 0 ? fld<R>(S, iuin) : nullptr;
+    using TP = TilePlan<R, N, TILE, NT>;
     constexpr int PITCH = Lay<N>::P;
+    constexpr int EPT = TP::EPT;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
     cpx<R>* lds2 = lds + TILE * PITCH;
+    const cpx<R>* twl = tw;
+    if constexpr (TP::PIPE) {
+        cpx<R>* t = reinterpret_cast<cpx<R>*>(smem_raw + TP::tw_offset(EPI == EPI_SCALE ? 1 : 2));
+        tw_to_lds<R, N>(t, tw, TP::TW_BYTES, NT);
+        twl = t;
+    }
     const int tiles = Cc / TILE;
-    int blk = xcd_block(blockIdx.x, gridDim.x);
-    const int ct = blk % tiles;
-    blk /= tiles;
-    const int bb = blk % B;
-    const int c = blk / B;
-    const int c0 = ct * TILE;
-    for (int e = threadIdx.x; e < TILE * N; e += NT) {
-        const int l = e % TILE, m = e / TILE;
-        const long long gi = (((long long)c * N + m) * B + bb) * Cc + c0 + l;
-        lds[l * PITCH + lx(m)] = in[gi];
-        if (nin == 2) lds2[l * PITCH + lx(m)] = in2[gi];
+    const int units = 3 * B * tiles;
+    const R uscale = (EPI == EPI_HL && use_invnP) ? (R)st->invnP : (R)1;
+    cpx<R> pa[TP::PIPE ? EPT : 1], pb[TP::PIPE ? EPT : 1];
+    int u = xcd_block(blockIdx.x, gridDim.x);
+    int c, bb, c0;
+    if constexpr (TP::PIPE) {
+        if (u < units) {
+            tile_unit(u, tiles, B, TILE, c, bb, c0);
+            tile_fetch<R, N, TILE, NT>(in, in2, nin, (((long long)c * N) * B + bb) * Cc + c0, B, Cc, pa, pb);
+        }
+    }
+    // a loop over units only when pipelined (otherwise one unit per block)
+    if (u < units) do {
+    tile_unit(u, tiles, B, TILE, c, bb, c0);
+    if constexpr (TP::PIPE) {
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            const int e = threadIdx.x + i * NT;
+            if (TILE * N % NT == 0 || e < TILE * N) {
+                const int l = e % TILE, m = e / TILE;
+                st2(lds + l * PITCH + lx(m), pa[i]);
+                if (nin == 2) st2(lds2 + l * PITCH + lx(m), pb[i]);
+            }
+        }
+    } else {
+        for (int e = threadIdx.x; e < TILE * N; e += NT) {
+            const int l = e % TILE, m = e / TILE;
+            const long long gi = (((long long)c * N + m) * B + bb) * Cc + c0 + l;
+            lds[l * PITCH + lx(m)] = in[gi];
+            if (nin == 2) lds2[l * PITCH + lx(m)] = in2[gi];
+        }
     }
     __syncthreads();
-    lds_fft<R, N, TILE, NT, true>(lds, tw);
-    if (nin == 2) lds_fft<R, N, TILE, NT, true>(lds2, tw);
-    const R uscale = (EPI == EPI_HL && use_invnP) ? (R)st->invnP : (R)1;
+    if constexpr (TP::PIPE) {
+        if (u + (int)gridDim.x < units) {
+            int cn, bn, c0n;
+            tile_unit(u + gridDim.x, tiles, B, TILE, cn, bn, c0n);
+            tile_fetch<R, N, TILE, NT>(in, in2, nin, (((long long)cn * N) * B + bn) * Cc + c0n, B, Cc, pa, pb);
+        }
+    }
+    lds_fft<R, N, TILE, NT, true>(lds, twl);
+    if (nin == 2) lds_fft<R, N, TILE, NT, true>(lds2, twl);
     for (int e = threadIdx.x; e < TILE * N; e += NT) {
         const int l = e / N, m = e - l * N;
         const long long go = (((long long)c * B + bb) * Cc + c0 + l) * N + m;
@@ -376,6 +471,8 @@ __global__ __launch_bounds__(NT) void k_invT(const Slot* __restrict__ slots, int
             out[go] = v;
         }
     }
+    if constexpr (TP::PIPE) __syncthreads();   // lds and lds2 are refilled by the next unit
+    } while (TP::PIPE && (u += gridDim.x) < units);
 }
 
 // ---------------------------------------------------------------------------
@@ -392,27 +489,60 @@ __global__ __launch_bounds__(NT) void k_invT_pre(const Slot* __restrict__ slots,
     const cpx<R>* __restrict__ in = fld<R>(S, iin);
     cpx<R>* __restrict__ out = fld<R>(S, iout);
     const R* __restrict__ pv = pvf<R>(S);
+    using TP = TilePlan<R, N, TILE, NT>;
     constexpr int PITCH = Lay<N>::P;
+    constexpr int EPT = TP::EPT;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
-    const int tiles = Cc / TILE;
-    int blk = xcd_block(blockIdx.x, gridDim.x);
-    const int ct = blk % tiles;
-    blk /= tiles;
-    const int bb = blk % B;
-    const int c = blk / B;
-    const int c0 = ct * TILE;
-    for (int e = threadIdx.x; e < TILE * N; e += NT) {
-        const int l = e % TILE, m = e / TILE;
-        lds[l * PITCH + lx(m)] = in[(((long long)c * N + m) * B + bb) * Cc + c0 + l];
+    const cpx<R>* twl = tw;
+    if constexpr (TP::PIPE) {
+        cpx<R>* t = reinterpret_cast<cpx<R>*>(smem_raw + TP::tw_offset(1));
+        tw_to_lds<R, N>(t, tw, TP::TW_BYTES, NT);
+        twl = t;
     }
-    __syncthreads();
-    lds_fft<R, N, TILE, NT, true>(lds, tw);
-    double acc[NS_DIR] = {0.0, 0.0, 0.0, 0.0, 0.0};
     const cpx<R>* r = dir ? fld<R>(S, B_R0 + st->cur) : nullptr;
     const cpx<R>* rp = dir ? fld<R>(S, B_R0 + (st->cur ^ 1)) : nullptr;
     const cpx<RS>* phi = fld<RS>(S, B_PHI);
     const cpx<R>* Pprev = fld<R>(S, B_P);
+    const int tiles = Cc / TILE;
+    const int units = 3 * B * tiles;
+    cpx<R> pa[TP::PIPE ? EPT : 1], pb[TP::PIPE ? EPT : 1];
+    int u = xcd_block(blockIdx.x, gridDim.x);
+    int c, bb, c0;
+    if constexpr (TP::PIPE) {
+        if (u < units) {
+            tile_unit(u, tiles, B, TILE, c, bb, c0);
+            tile_fetch<R, N, TILE, NT>(in, nullptr, 1, (((long long)c * N) * B + bb) * Cc + c0, B, Cc, pa, pb);
+        }
+    }
+    // a loop over units only when pipelined (otherwise one unit per block)
+    if (u < units) do {
+    tile_unit(u, tiles, B, TILE, c, bb, c0);
+    if constexpr (TP::PIPE) {
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            const int e = threadIdx.x + i * NT;
+            if (TILE * N % NT == 0 || e < TILE * N) {
+                const int l = e % TILE, m = e / TILE;
+                st2(lds + l * PITCH + lx(m), pa[i]);
+            }
+        }
+    } else {
+        for (int e = threadIdx.x; e < TILE * N; e += NT) {
+            const int l = e % TILE, m = e / TILE;
+            lds[l * PITCH + lx(m)] = in[(((long long)c * N + m) * B + bb) * Cc + c0 + l];
+        }
+    }
+    __syncthreads();
+    if constexpr (TP::PIPE) {
+        if (u + (int)gridDim.x < units) {
+            int cn, bn, c0n;
+            tile_unit(u + gridDim.x, tiles, B, TILE, cn, bn, c0n);
+            tile_fetch<R, N, TILE, NT>(in, nullptr, 1, (((long long)cn * N) * B + bn) * Cc + c0n, B, Cc, pa, pb);
+        }
+    }
+    lds_fft<R, N, TILE, NT, true>(lds, twl);
+    double acc[NS_DIR] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int e = threadIdx.x; e < TILE * N; e += NT) {
         const int l = e / N, m = e - l * N;
         const long long go = (((long long)c * B + bb) * Cc + c0 + l) * N + m;
@@ -427,8 +557,10 @@ __global__ __launch_bounds__(NT) void k_invT_pre(const Slot* __restrict__ slots,
             acc[4] += re_dot(wid(Pprev[go]), w);
         }
     }
-    if (!dir) return;
-    block_row<NS_DIR, NT>(acc, S.red_dir, RED_DIR_STRIDE);
+    // one partial-sum row per unit, whichever block took it
+    if (dir) block_row<NS_DIR, NT>(acc, S.red_dir, RED_DIR_STRIDE, u);
+    if constexpr (TP::PIPE) __syncthreads();   // lds is refilled by the next unit
+    } while (TP::PIPE && (u += gridDim.x) < units);
 }
 
 // ---------------------------------------------------------------------------
@@ -464,21 +596,6 @@ template <typename R, int N, int LPB, int OP, int NT> struct MidPlan {
     static constexpr size_t TW_BYTES =
         PIPE ? (size_t)N * sizeof(cpx<R>) + (sizeof(R) == 4 ? (size_t)N * 16 : 0) : 0;
 };
-
-// one complex value as a single vector access (keeps register arrays of
-// complex values out of private memory)
-template <typename R> using vec2 = R __attribute__((ext_vector_type(2)));
-template <typename R> __device__ __forceinline__ void ld2(cpx<R>& d, const cpx<R>* p) {
-    const vec2<R> v = *reinterpret_cast<const vec2<R>*>(p);
-    d.x = v.x;
-    d.y = v.y;
-}
-template <typename R> __device__ __forceinline__ void st2(cpx<R>* p, const cpx<R>& a) {
-    vec2<R> v;
-    v.x = a.x;
-    v.y = a.y;
-    *reinterpret_cast<vec2<R>*>(p) = v;
-}
 
 template <typename R, int N, int LPB, int OP, int NT>
 __device__ __forceinline__ void mid_fetch(const cpx<R>* __restrict__ in, const cpx<R>* __restrict__ in2,
@@ -698,6 +815,38 @@ template <typename R> int invT_pre_blocks(int N, int B, int Cc) { return 3 * B *
 template int invT_pre_blocks<double>(int, int, int);
 template int invT_pre_blocks<float>(int, int, int);
 
+static int cu_count() {
+    static int n = 0;
+    if (!n) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+            n = 256;
+    }
+    return n;
+}
+
+// Blocks per slot of a transposed pass: one per unit, or, for a pipelined
+// kernel, as many as fill the device once, in multiples of 8 (the XCD tile
+// order); the occupancy is queried once per kernel.
+template <auto KERNEL, bool PIPE, typename... Args>
+static hipError_t tile_go(int units, int nslots, int ntb, size_t lds, hipStream_t s, Args... args) {
+    int G = units;
+    if (PIPE) {
+        static int per_cu = -1;
+        if (per_cu < 0) {
+            int nb = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, KERNEL, ntb, lds) != hipSuccess || nb <= 0) nb = 1;
+            per_cu = nb;
+        }
+        const long long resident = (long long)per_cu * cu_count();
+        const long long g = std::max<long long>(1, (resident + nslots - 1) / nslots);
+        if (g < units) G = (int)std::min<long long>(units, std::max<long long>(8, g & ~7LL));
+    }
+    GS_LAUNCH(KERNEL, dim3((unsigned)G, (unsigned)nslots), dim3(ntb), lds, s, args...);
+    return hipGetLastError();
+}
+
 template <typename R, typename RX, int N>
 static hipError_t fwdT_n(int pro, int dual, const Slot* slots, int nslots, int in, int out, int aux0, int aux1,
                          int A, int B, int ncomp, const cpx<R>* tw, hipStream_t s) {
@@ -729,23 +878,23 @@ static hipError_t invT_n(int epi, const Slot* slots, int nslots, int in, int in2
                          int B, int Cc, double scale, int use_invnP, int rot_any, const cpx<R>* tw, hipStream_t s) {
     constexpr int TILE = tile_inv<R>(N);
     constexpr int NTB = nt_tile<R>(N);
+    using TP = TilePlan<R, N, TILE, NTB>;
     if (Cc % TILE) return hipErrorInvalidValue;
-    const size_t lds = (size_t)(epi == EPI_SCALE ? 1 : 2) * TILE * Lay<N>::P * sizeof(cpx<R>);
-    dim3 grid((unsigned)(3LL * B * (Cc / TILE)), (unsigned)nslots);
+    const int units = 3 * B * (Cc / TILE);
+    const size_t lds = TP::tw_offset(epi == EPI_SCALE ? 1 : 2) + TP::TW_BYTES;
     switch (epi) {
     case EPI_SCALE:
-        GS_LAUNCH((k_invT<R, N, TILE, EPI_SCALE, NTB>), grid, dim3(NTB), lds, s, slots, in, in2, out, out2, uin, B, Cc, scale, use_invnP, rot_any, tw);
-        break;
+        return tile_go<k_invT<R, N, TILE, EPI_SCALE, NTB>, TP::PIPE>(units, nslots, NTB, lds, s, slots, in, in2, out,
+                                                                      out2, uin, B, Cc, scale, use_invnP, rot_any, tw);
     case EPI_HL:
-        GS_LAUNCH((k_invT<R, N, TILE, EPI_HL, NTB>), grid, dim3(NTB), lds, s, slots, in, in2, out, out2, uin, B, Cc, scale, use_invnP, rot_any, tw);
-        break;
+        return tile_go<k_invT<R, N, TILE, EPI_HL, NTB>, TP::PIPE>(units, nslots, NTB, lds, s, slots, in, in2, out,
+                                                                   out2, uin, B, Cc, scale, use_invnP, rot_any, tw);
     case EPI_ROTX:
-        GS_LAUNCH((k_invT<R, N, TILE, EPI_ROTX, NTB>), grid, dim3(NTB), lds, s, slots, in, in2, out, out2, uin, B, Cc, scale, use_invnP, rot_any, tw);
-        break;
+        return tile_go<k_invT<R, N, TILE, EPI_ROTX, NTB>, TP::PIPE>(units, nslots, NTB, lds, s, slots, in, in2, out,
+                                                                     out2, uin, B, Cc, scale, use_invnP, rot_any, tw);
     default:
         return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 template <typename R, typename RS, int N>
@@ -753,27 +902,17 @@ static hipError_t invT_pre_n(const Slot* slots, int nslots, int in, int out, int
                              const cpx<R>* tw, hipStream_t s) {
     constexpr int TILE = tile_pre<R>(N);
     constexpr int NTB = nt_tile<R>(N);
+    using TP = TilePlan<R, N, TILE, NTB>;
     if (Cc % TILE) return hipErrorInvalidValue;
-    const size_t lds = (size_t)TILE * Lay<N>::P * sizeof(cpx<R>);
-    dim3 grid((unsigned)(3LL * B * (Cc / TILE)), (unsigned)nslots);
     static_assert(NS_DIR <= RED_DIR_STRIDE, "partial-sum row");
-    GS_LAUNCH((k_invT_pre<R, RS, N, TILE, NTB>), grid, dim3(NTB), lds, s, slots, in, out, B, Cc, dir, tw);
-    return hipGetLastError();
+    return tile_go<k_invT_pre<R, RS, N, TILE, NTB>, TP::PIPE>(3 * B * (Cc / TILE), nslots, NTB,
+                                                               TP::tw_offset(1) + TP::TW_BYTES, s, slots, in, out, B,
+                                                               Cc, dir, tw);
 }
 
 // Blocks per slot of a middle pass: one per line group, or, for a pipelined
 // kernel, as many as fill the device once (every resident block then loops
 // over several groups; the occupancy is queried once per kernel).
-static int cu_count() {
-    static int n = 0;
-    if (!n) {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
-            n = 256;
-    }
-    return n;
-}
 template <auto KERNEL, typename MP, typename... Args>
 static hipError_t mid_go(int ngroups, int nslots, int ntb, size_t lds, hipStream_t s, Args... args) {
     int G = ngroups;
