@@ -9,28 +9,7 @@ namespace gs {
 
 constexpr int PT = 256;   // threads per block of every kernel
 
-// deterministic block sum of NV doubles; thread 0 ends with the totals
-template <int NV>
-__device__ __forceinline__ void bsum(double (&v)[NV]) {
-    __shared__ double sh[PT / 64][NV];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int k = 0; k < NV; ++k)
-        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_down(v[k], off, 64);
-    if (lane == 0)
-#pragma unroll
-        for (int k = 0; k < NV; ++k) sh[wv][k] = v[k];
-    __syncthreads();
-    if (threadIdx.x == 0)
-#pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            double s = 0.0;
-            for (int w = 0; w < PT / 64; ++w) s += sh[w][k];
-            v[k] = s;
-        }
-    __syncthreads();
-}
-
+// block maximum; thread 0 ends with it
 __device__ __forceinline__ double bmax(double v) {
     __shared__ double sh[PT / 64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -44,14 +23,6 @@ __device__ __forceinline__ double bmax(double v) {
     }
     __syncthreads();
     return v;
-}
-
-// Thread 0 writes this block's row of NV partial sums (plain stores: the rows
-// are read by a later kernel, after the kernel boundary has made them visible).
-template <int NV>
-__device__ __forceinline__ void write_row(const double (&v)[NV], double* rows, int stride) {
-    if (threadIdx.x == 0)
-        for (int k = 0; k < NV; ++k) rows[(long long)blockIdx.x * stride + k] = v[k];
 }
 
 template <int N> struct Pow2Ceil { static constexpr int v = 2 * Pow2Ceil<(N + 1) / 2>::v; };
