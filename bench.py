@@ -391,7 +391,7 @@ def main():
             "p99_ms": percentile(lat, 99) * 1e3,
             "warnings": sum(1 for r in done.values() if r["rc"] > 0),
             "errors": sum(1 for r in done.values() if r["rc"] < 0),
-            "workload": ("Poisson arrivals (seed 2603); 75% 2D n in {128,256,512,1024} L=16, 25% 3D n in {64,128} "
+            "workload": ("Poisson arrivals (seed 2603); 75% 2D n in {128,256,512,1024} L=16, 25% 3D n in {64,96,128,192} "
                          "L=10; parameters as the sweep; trap harmonic or 0.5r^2+0.01r^4; mixed precision, "
                          "energy criterion 1e-12; latency = arrival to completion"),
         }

@@ -80,7 +80,8 @@ extern "C" {
 typedef struct gs_ctx gs_ctx;
 
 /* Grid: dim = 2 or 3; n[a] points on [-L[a], L[a]] along x, y, z. Each n[a]
- * is a power of two between 16 and 1024 (Sec. 3.2 requires N even). */
+ * is 2^k in [16, 1024] or 3 * 2^k in [24, 768] (Sec. 3.2 requires N even; the
+ * transforms are Stockham passes of radix 3 and powers of two). */
 typedef struct {
     int dim;
     int n[3];

@@ -44,13 +44,18 @@ static int fail(int code, const std::string& msg) {
         if (e_ != hipSuccess) return fail(GS_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-static bool pow2_in_range(int n) { return n >= 16 && n <= 1024 && (n & (n - 1)) == 0; }
+// supported line lengths: 2^a in [16, 1024] and 3 * 2^a in [24, 768]
+static bool size_supported(int n) {
+    const int m = (n % 3 == 0) ? n / 3 : n;
+    return n >= 16 && n <= 1024 && m >= 1 && (m & (m - 1)) == 0 && (n % 3 != 0 || n >= 24);
+}
 
 static int check_grid(const gs_grid* g) {
     if (!g) return fail(GS_EINVAL, "grid is NULL");
     if (g->dim != 2 && g->dim != 3) return fail(GS_EINVAL, "grid.dim must be 2 or 3");
     for (int a = 0; a < g->dim; ++a) {
-        if (!pow2_in_range(g->n[a])) return fail(GS_EINVAL, "grid.n[a] must be a power of two in [16, 1024]");
+        if (!size_supported(g->n[a]))
+            return fail(GS_EINVAL, "grid.n[a] must be 2^a in [16, 1024] or 3 * 2^a in [24, 768]");
         if (!(g->L[a] > 0.0) || !std::isfinite(g->L[a])) return fail(GS_EINVAL, "grid.L[a] must be positive");
     }
     return GS_OK;

@@ -110,6 +110,15 @@ template <typename R, int RAD, bool INV>
 __device__ __forceinline__ void dftr(cpx<R> (&v)[RAD]) {
     if constexpr (RAD == 2) {
         dft2<R, INV>(v[0], v[1]);
+    } else if constexpr (RAD == 3) {
+        // y_q = sum_r v_r w^{rq}, w = exp(-+2 pi i / 3) = -1/2 -+ i sqrt(3)/2
+        const R h = (R)0.866025403784438646763723170752936183;   // sqrt(3)/2
+        const cpx<R> s = v[1] + v[2], d = v[1] - v[2];
+        const cpx<R> m = v[0] - (R)0.5 * s;
+        const cpx<R> id = cmk(-h * d.y, h * d.x);   // i sqrt(3)/2 (v1 - v2)
+        v[0] = v[0] + s;
+        if (INV) { v[1] = m + id; v[2] = m - id; }
+        else     { v[1] = m - id; v[2] = m + id; }
     } else if constexpr (RAD == 4) {
         dft4<R, INV>(v[0], v[1], v[2], v[3]);
     } else if constexpr (RAD == 8) {
@@ -129,7 +138,7 @@ __device__ __forceinline__ void dftr(cpx<R> (&v)[RAD]) {
             v[q2 + 4] = y[1][q2];
         }
     } else {
-        static_assert(RAD == 16, "radix 2, 4, 8 or 16");
+        static_assert(RAD == 16, "radix 2, 3, 4, 8 or 16");
         // A = 4, B = 4
         cpx<R> y[4][4];
 #pragma unroll
@@ -169,7 +178,7 @@ __device__ __forceinline__ void fft_pass(cpx<R>* buf, const cpx<R>* __restrict__
         lb[i] = -1;
         if (TOT % NT == 0 || b < TOT) {
             const int l = b / NB, j = b - l * NB;
-            const int k = j & (NS - 1);
+            const int k = j % NS;
             const cpx<R>* src = buf + l * P;
 #pragma unroll
             for (int r = 0; r < RAD; ++r) v[i][r] = src[lx(j + r * NB)];
@@ -214,12 +223,16 @@ __device__ __forceinline__ void fft_pass(cpx<R>* buf, const cpx<R>* __restrict__
     __syncthreads();
 }
 
-// Passes of radix RMAX while it divides the rest, then one pass of the
-// remaining factor (NS = product of the radices done so far).
+// For N = 3 * 2^a one radix-3 pass first (NS = 1: no twiddles); then passes
+// of radix RMAX while it divides the rest, then one pass of the remaining
+// power of two (NS = product of the radices done so far).
 template <typename R, int N, int NL, int NT, int RMAX, int NS, bool INV>
 __device__ __forceinline__ void fft_passes(cpx<R>* buf, const cpx<R>* __restrict__ tw) {
     constexpr int REST = N / NS;
-    if constexpr (REST >= RMAX) {
+    if constexpr (NS == 1 && N % 3 == 0) {
+        fft_pass<R, N, NL, NT, 3, 1, INV>(buf, tw);
+        fft_passes<R, N, NL, NT, RMAX, 3, INV>(buf, tw);
+    } else if constexpr (REST >= RMAX) {
         fft_pass<R, N, NL, NT, RMAX, NS, INV>(buf, tw);
         fft_passes<R, N, NL, NT, RMAX, NS * RMAX, INV>(buf, tw);
     } else if constexpr (REST > 1) {
@@ -235,7 +248,8 @@ template <typename R> constexpr int rmax() { return sizeof(R) == 8 ? 8 : 16; }
 // buf + l * Lay<N>::P; natural order in and out, unnormalised).
 template <typename R, int N, int NL, int NT, bool INV>
 __device__ __forceinline__ void lds_fft(cpx<R>* buf, const cpx<R>* __restrict__ tw) {
-    static_assert(N >= 16 && N <= 1024 && (N & (N - 1)) == 0, "N");
+    static_assert(N >= 16 && N <= 1024 && ((N & (N - 1)) == 0 || (N % 3 == 0 && ((N / 3) & (N / 3 - 1)) == 0)),
+                  "N = 2^a or 3 * 2^a");
     fft_passes<R, N, NL, NT, rmax<R>(), 1, INV>(buf, tw);
 }
 
@@ -954,6 +968,12 @@ static hipError_t mid_n(int op, const Slot* slots, int nslots, int in, int outA,
 #define GS_SWITCH_N(CALL)                        \
     switch (N) {                                 \
     case 16: return CALL(16);                    \
+    case 24: return CALL(24);                    \
+    case 48: return CALL(48);                    \
+    case 96: return CALL(96);                    \
+    case 192: return CALL(192);                  \
+    case 384: return CALL(384);                  \
+    case 768: return CALL(768);                  \
     case 32: return CALL(32);                    \
     case 64: return CALL(64);                    \
     case 128: return CALL(128);                  \

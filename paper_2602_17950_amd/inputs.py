@@ -187,13 +187,12 @@ def workload_sweep_2d(count: int = 96, seed: int = 17950, sizes=(128, 256, 512))
     return out
 
 
-def workload_serve(count: int = 400, seed: int = 2603, sizes2d=(128, 256, 512, 1024), sizes3d=(64, 128)):
+def workload_serve(count: int = 400, seed: int = 2603, sizes2d=(128, 256, 512, 1024), sizes3d=(64, 96, 128, 192)):
     """Served request stream: 75% 2D (grid uniform over ``sizes2d``, L = 16),
     25% 3D (grid uniform over ``sizes3d``, L = 10); Omega, gamma, c0, c1 and the
     guess kind drawn as in the batched sweep; trap half harmonic, half harmonic
     plus quartic 0.5 r^2 + 0.01 r^4. Returns (Problem, guess kinds) pairs; all
-    draws from one generator in a fixed order. Only power-of-two grids are
-    drawn (the transforms are radix 2 and 4)."""
+    draws from one generator in a fixed order."""
     rng = np.random.default_rng(seed)
     kinds = [("a", "a", "a"), ("b", "a", "a"), ("f", "f", "f")]
     out = []

@@ -77,7 +77,10 @@ def test_default_options_and_footprint():
     assert gs.footprint_bytes(pb, gs.GS_FP64, stop_kind=4) == 0
     assert gs.footprint_bytes(pb, gs.GS_FP64, line_search=gs.GS_LS_EXACT) == b64
     assert gs.footprint_bytes(pb, gs.GS_FP64, line_search=2) == 0
-    bad = inputs.Problem(dim=2, n=(48, 64), L=(12.0, 12.0))
+    # lengths 3 * 2^a are supported, other factors are not
+    assert gs.footprint_bytes(inputs.Problem(dim=2, n=(96, 48), L=(12.0, 12.0)), gs.GS_FP64) > 0
+    assert gs.footprint_bytes(inputs.Problem(dim=2, n=(12, 64), L=(12.0, 12.0)), gs.GS_FP64) == 0
+    bad = inputs.Problem(dim=2, n=(40, 64), L=(12.0, 12.0))
     assert gs.footprint_bytes(bad, gs.GS_FP64) == 0
     pb3 = inputs.Problem(dim=3, n=(128, 128, 128), L=(8.0, 8.0, 8.0))
     M3 = 128 ** 3

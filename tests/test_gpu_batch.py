@@ -183,7 +183,7 @@ def test_cancel(gpu_ctx):
 def test_batch_invalid_request_runs_nothing(gpu_ctx):
     pb, psi0 = problems()[0]
     opt = gs.default_options()
-    bad = inputs.Problem(dim=2, n=(48, 48), L=(6.0, 6.0))
+    bad = inputs.Problem(dim=2, n=(40, 40), L=(6.0, 6.0))
     o1 = torch.empty((3,) + pb.shape, dtype=torch.complex128, device=DEV)
     o2 = torch.empty((3, 48, 48), dtype=torch.complex128, device=DEV)
     with pytest.raises(gs.GsError) as ei:

@@ -60,6 +60,27 @@ def test_batched_256_vortex_states_match_oracle(gpu_ctx, prec, dirp):
         assert r["resid_inf"] < 1e-6
 
 
+def test_cm3d_96_state_matches_oracle(gpu_ctx):
+    """The 3D anisotropic workload on a 96^3 grid (lengths 3 * 2^a: a radix-3
+    pass in every transform), three-level cascadic multigrid 24^3 -> 48^3 ->
+    96^3, mixed precision; the oracle evaluates the result with its own naive
+    DFT for length 96."""
+    O.set_threads(16)
+    pb, _ = inputs.workload_aniso_3d(n=96)
+    pc = inputs.Problem(dim=3, n=(24, 24, 24), L=pb.L, g=pb.g, omega=pb.omega, gamma=pb.gamma, c0=pb.c0, c1=pb.c1)
+    g0 = torch.from_numpy(inputs.initial_guess(pc, ("a", "a", "a"))).to(DEV)
+    out = torch.empty((3,) + pb.shape, dtype=torch.complex128, device=DEV)
+    opt = gs.default_options(precision=gs.GS_MIXED, dir_precision=gs.GS_FP32, stop_kind=gs.GS_STOP_RESIDUAL,
+                             tol=1e-9, cm_levels=3)
+    r = gpu_ctx.solve_device(pb, g0, out, options=opt)
+    torch.cuda.synchronize()
+    assert r["rc"] == gs.GS_OK, r
+    ev = _check_against_oracle(pb, out.cpu().numpy(), r)
+    assert ev["e_soc"] <= 0.0
+    assert abs(ev["virial"]) < 1e-6
+    assert ev["resid_inf"] < 1e-9 * 1.01
+
+
 def test_cm3d_128_state_matches_oracle(gpu_ctx):
     """The 128^3 anisotropic rotating solve by three-level cascadic multigrid."""
     O.set_threads(16)

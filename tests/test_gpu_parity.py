@@ -37,6 +37,10 @@ GRIDS = [
     (2, (1024, 16), (16.0, 2.0)),
     (3, (16, 32, 16), (6.0, 6.0, 5.0)),
     (3, (32, 16, 64), (6.0, 5.0, 8.0)),
+    # lengths 3 * 2^a (a radix-3 pass first)
+    (2, (96, 48), (8.0, 6.0)),
+    (2, (24, 768), (4.0, 16.0)),
+    (3, (48, 24, 96), (6.0, 5.0, 8.0)),
 ]
 
 
@@ -73,10 +77,13 @@ def _problems():
         inputs.Problem(dim=3, n=(32, 16, 32), L=(8.0, 7.0, 8.0), g=(1.0, 1.0, 2.0), omega=0.5,
                        gamma=1.0, c0=800.0, c1=5.0),
         inputs.Problem(dim=3, n=(16, 16, 16), L=(6.0, 6.0, 6.0), omega=0.0, gamma=0.3, c0=50.0, c1=-1.0),
+        inputs.Problem(dim=2, n=(96, 48), L=(10.0, 8.0), omega=0.6, gamma=1.0, c0=500.0, c1=-2.0),
+        inputs.Problem(dim=3, n=(24, 48, 24), L=(7.0, 8.0, 7.0), g=(1.0, 1.0, 2.0), omega=0.5,
+                       gamma=1.0, c0=800.0, c1=5.0),
     ]
 
 
-@pytest.mark.parametrize("k", range(5))
+@pytest.mark.parametrize("k", range(7))
 @pytest.mark.parametrize("prec", [gs.GS_FP64, gs.GS_FP32])
 def test_hamiltonian_and_energy(gpu_ctx, k, prec):
     pb = _problems()[k]
@@ -296,6 +303,18 @@ def test_wavefunction_criterion_matches_oracle(gpu_ctx):
     assert rel(res["E"], ev["E"]) < 1e-9
 
 
+def test_solve_radix3_grid(gpu_ctx):
+    """A 48^2 grid (a radix-3 pass in every transform): the small 2D workload's
+    parameters, residual stop, against the oracle (naive DFT for length 48)."""
+    pb = inputs.Problem(dim=2, n=(48, 48), L=(8.0, 8.0), omega=0.3, gamma=0.5, c0=100.0, c1=-0.5)
+    psi0 = inputs.initial_guess(pb, ("b", "a", "a"))
+    ref, ev, psi, res = _solve_both(gpu_ctx, pb, psi0, gs.GS_STOP_RESIDUAL, 1e-10)
+    print(f"[solve 48] gpu E={res['E']!r} it={res['iters']} | oracle E={ev['E']!r} it={ref.iters}", flush=True)
+    assert res["status"] == 0 and ref.status == 0
+    assert rel(res["E"], ev["E"]) < 1e-10
+    assert rel(res["mu"], ev["mu"]) < 1e-8
+
+
 def test_solve_3d_small(gpu_ctx):
     pb = inputs.Problem(dim=3, n=(16, 16, 16), L=(6.0, 6.0, 6.0), g=(1.0, 1.0, 2.0), omega=0.5,
                         gamma=1.0, c0=200.0, c1=5.0)
@@ -323,7 +342,7 @@ def test_solve_device_matches_host(gpu_ctx):
 
 def test_errors_and_warnings(gpu_ctx):
     pb, psi0 = inputs.workload_small_2d()
-    bad = inputs.Problem(dim=2, n=(48, 64), L=(8.0, 8.0))
+    bad = inputs.Problem(dim=2, n=(40, 64), L=(8.0, 8.0))
     with pytest.raises(gs.GsError) as e:
         gpu_ctx.solve(bad, None, gs.default_options())
     assert e.value.code == gs.GS_EINVAL
