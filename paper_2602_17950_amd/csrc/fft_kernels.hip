@@ -323,7 +323,7 @@ template <typename R, typename RX, int N, int TILE, int PRO, bool DUAL, int NT>
 __global__ __launch_bounds__(NT) void k_fwdT(const Slot* __restrict__ slots, int iin, int iout, int iaux0,
                                              int iaux1, int A, int B, const cpx<R>* __restrict__ tw) {
     const Slot& S = slots[blockIdx.y];
-    const SolveState* st = S.st;
+    const SolveState* st = as_global(S.st);
     if (st->done) return;
     cpx<R>* inp = fld<R>(S, iin);
     cpx<R>* __restrict__ out = fld<R>(S, iout);
@@ -392,7 +392,7 @@ __global__ __launch_bounds__(NT) void k_invT(const Slot* __restrict__ slots, int
                                              int iout2, int iuin, int B, int Cc, double scale, int use_invnP,
                                              int rot_any, const cpx<R>* __restrict__ tw) {
     const Slot& S = slots[blockIdx.y];
-    const SolveState* st = S.st;
+    const SolveState* st = as_global(S.st);
     if (st->done) return;
     const Phys p = S.p;
     // the rotation input/output pair exists for rotating slots of the H_L chain
@@ -498,7 +498,7 @@ template <typename R, typename RS, int N, int TILE, int NT>
 __global__ __launch_bounds__(NT) void k_invT_pre(const Slot* __restrict__ slots, int iin, int iout, int B,
                                                  int Cc, int dir, const cpx<R>* __restrict__ tw) {
     const Slot& S = slots[blockIdx.y];
-    SolveState* st = S.st;
+    SolveState* st = as_global(S.st);
     if (st->done) return;
     const cpx<R>* __restrict__ in = fld<R>(S, iin);
     cpx<R>* __restrict__ out = fld<R>(S, iout);
@@ -572,7 +572,7 @@ __global__ __launch_bounds__(NT) void k_invT_pre(const Slot* __restrict__ slots,
         }
     }
     // one partial-sum row per unit, whichever block took it
-    if (dir) block_row<NS_DIR, NT>(acc, S.red_dir, RED_DIR_STRIDE, u);
+    if (dir) block_row<NS_DIR, NT>(acc, as_global(S.red_dir), RED_DIR_STRIDE, u);
     if constexpr (TP::PIPE) __syncthreads();   // lds is refilled by the next unit
     } while (TP::PIPE && (u += gridDim.x) < units);
 }
@@ -638,7 +638,7 @@ __global__ __launch_bounds__(NT) void k_mid(const Slot* __restrict__ slots, int 
                                             int nlines, int rot_any, const cpx<R>* __restrict__ tw) {
     using MP = MidPlan<R, N, LPB, OP, NT>;
     const Slot& S = slots[blockIdx.y];
-    const SolveState* st = S.st;
+    const SolveState* st = as_global(S.st);
     if (st->done) return;
     const Phys p = S.p;
     const int rot = rot_any && p.omega != 0.0;
@@ -646,7 +646,7 @@ __global__ __launch_bounds__(NT) void k_mid(const Slot* __restrict__ slots, int 
     const cpx<R>* __restrict__ in2 = (OP == MID_HLX) ? in + 3 * p.M : nullptr;
     cpx<R>* __restrict__ outA = fld<R>(S, ioutA);
     cpx<R>* __restrict__ outB = ioutB >= 0 ? fld<R>(S, ioutB) : nullptr;
-    double* __restrict__ red = S.red_mid;
+    double* __restrict__ red = as_global(S.red_mid);
     constexpr int PITCH = Lay<N>::P;
     constexpr int NLN = MP::NLN;
     constexpr int EPT = MP::EPT;

@@ -73,10 +73,22 @@ struct Phys {
     double omega, gamma, c0, c1;
 };
 
+// Every pointer a kernel finds in a slot or a problem description is a device
+// (global-memory) address. Kernels read such pointers through as_global, which
+// loads the stored value as a pointer of the global address space, so the
+// accesses through it compile to global rather than flat memory instructions.
+// A flat access also counts as an LDS access: otherwise each LDS wait before a
+// block barrier would also wait for the block's outstanding HBM loads and
+// stores, prefetches included.
+template <typename T> __device__ __forceinline__ T* as_global(T* const& field) {
+    using G = __attribute__((address_space(1))) T*;
+    return (T*)*reinterpret_cast<const G*>(reinterpret_cast<const void*>(&field));
+}
+
 // trap potential, split into its degree-2 and degree-4 parts (V2 + V4 = V)
 __device__ __forceinline__ void trap_at(const Phys& p, long long i, double x, double y, double z,
                                         double& V2, double& V4) {
-    if (p.V) { V2 = p.V[i]; V4 = 0.0; return; }
+    if (p.V) { V2 = as_global(p.V)[i]; V4 = 0.0; return; }
     double r2 = x * x + y * y + z * z;
     V2 = p.hg[0] * x * x + p.hg[1] * y * y + p.hg[2] * z * z + p.q2 * r2;
     V4 = p.q4 * r2 * r2;
@@ -166,10 +178,10 @@ struct Slot {
     double* red_dir;     // [nblk_dir][RED_DIR_STRIDE]
     Phys p;
 };
-template <typename T> __host__ __device__ __forceinline__ cpx<T>* fld(const Slot& S, int b) {
-    return static_cast<cpx<T>*>(S.buf[b]);
+template <typename T> __device__ __forceinline__ cpx<T>* fld(const Slot& S, int b) {
+    return static_cast<cpx<T>*>(as_global(S.buf[b]));
 }
-template <typename T> __host__ __device__ __forceinline__ T* pvf(const Slot& S) { return static_cast<T*>(S.pv); }
+template <typename T> __device__ __forceinline__ T* pvf(const Slot& S) { return static_cast<T*>(as_global(S.pv)); }
 template <typename T, typename U> __host__ __device__ __forceinline__ cpx<T> cvt(cpx<U> a) {
     return cpx<T>{(T)a.x, (T)a.y};
 }

@@ -29,7 +29,7 @@ int pw_blocks(long long M) {
 template <typename R>
 __global__ __launch_bounds__(PT) void k_eval(const Slot* slots, RedGeom g) {
     const Slot& S = slots[blockIdx.y];
-    SolveState* st = S.st;
+    SolveState* st = as_global(S.st);
     if (st->done) return;
     const Phys p = S.p;
     const long long M = p.M;
@@ -57,7 +57,7 @@ __global__ __launch_bounds__(PT) void k_eval(const Slot* slots, RedGeom g) {
         acc[16] += 0.5 * p.c1 * (2.0 * cabs2(sp.G) + sp.Fz * sp.Fz);   // |F|^2 = 2|G|^2 + F_z^2
         acc[17] += V4 * sp.rho;
     }
-    block_row<NS_EVAL>(acc, S.red_pw, NS_MAX);
+    block_row<NS_EVAL>(acc, as_global(S.red_pw), NS_MAX);
 }
 
 // ---------------------------------------------------------------------------
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(PT) void k_eval(const Slot* slots, RedGeom g) {
 template <typename R, typename RD>
 __global__ __launch_bounds__(PT) void k_resid(const Slot* slots, RedGeom g, int final_only) {
     const Slot& S = slots[blockIdx.y];
-    SolveState* st = S.st;
+    SolveState* st = as_global(S.st);
     if (st->done && !final_only) return;
     const Phys p = S.p;
     const long long M = p.M;
@@ -133,13 +133,13 @@ __global__ __launch_bounds__(PT) void k_resid(const Slot* slots, RedGeom g, int 
         }
     }
     const double m = bmax(acc[0]);
-    if (threadIdx.x == 0) S.red_pw[(long long)blockIdx.x * NS_MAX] = m;
+    if (threadIdx.x == 0) as_global(S.red_pw)[(long long)blockIdx.x * NS_MAX] = m;
     if (pending) {   // uniform over the block
         const double wm = bmax(wmax);
-        if (threadIdx.x == 0) S.red_pw[(long long)blockIdx.x * NS_MAX + W_ROW] = wm;
+        if (threadIdx.x == 0) as_global(S.red_pw)[(long long)blockIdx.x * NS_MAX + W_ROW] = wm;
     }
     const double t[3] = {acc[1], acc[2], acc[3]};
-    block_row<3>(t, S.red_pw + 1, NS_MAX);   // entries 1..3 of the row
+    block_row<3>(t, as_global(S.red_pw) + 1, NS_MAX);   // entries 1..3 of the row
 }
 
 // ---------------------------------------------------------------------------
@@ -150,7 +150,7 @@ __global__ __launch_bounds__(PT) void k_resid(const Slot* slots, RedGeom g, int 
 template <typename R, typename RD>
 __global__ __launch_bounds__(PT, 3) void k_lsred(const Slot* slots, RedGeom g) {
     const Slot& S = slots[blockIdx.y];
-    SolveState* st = S.st;
+    SolveState* st = as_global(S.st);
     if (st->done) return;
     const Phys p = S.p;
     const long long M = p.M;
@@ -164,10 +164,13 @@ __global__ __launch_bounds__(PT, 3) void k_lsred(const Slot* slots, RedGeom g) {
         trap_at(p, i, x, y, z, V2, V4);
         const double V = V2 + V4;
         cpx<double> ph[3], P[3], hl[3], hp[3];
-        load3(fld<R>(S, B_PHI), i, M, ph);
-        load3(fld<RD>(S, B_P), i, M, P);
-        load3(fld<R>(S, B_HL), i, M, hl);
-        load3(fld<RD>(S, B_HLP), i, M, hp);
+        // generic (flat) loads on purpose: this loop uses no LDS, and with
+        // global-address loads the compiler's schedule needs more registers
+        // than three blocks per SIMD allow and spills inside the loop
+        load3(static_cast<const cpx<R>*>(S.buf[B_PHI]), i, M, ph);
+        load3(static_cast<const cpx<RD>*>(S.buf[B_P]), i, M, P);
+        load3(static_cast<const cpx<R>*>(S.buf[B_HL]), i, M, hl);
+        load3(static_cast<const cpx<RD>*>(S.buf[B_HLP]), i, M, hp);
         for (int c = 0; c < 3; ++c) P[c] = ip * P[c];
         double n0[3], n1[3], n2[3];
         for (int c = 0; c < 3; ++c) {
@@ -215,7 +218,7 @@ __global__ __launch_bounds__(PT, 3) void k_lsred(const Slot* slots, RedGeom g) {
             T[4] += p.c0 * q2r * n2[c];
         }
     }
-    block_row<NS_LS>(acc, S.red_pw, NS_MAX);
+    block_row<NS_LS>(acc, as_global(S.red_pw), NS_MAX);
 }
 
 // ---------------------------------------------------------------------------
@@ -226,7 +229,7 @@ __global__ __launch_bounds__(PT, 3) void k_lsred(const Slot* slots, RedGeom g) {
 template <typename R, typename RD>
 __global__ __launch_bounds__(PT) void k_apply(const Slot* slots, RedGeom g) {
     const Slot& S = slots[blockIdx.y];
-    const SolveState* st = S.st;
+    const SolveState* st = as_global(S.st);
     if (st->done || !st->pending_step) return;
     const long long n3 = 3 * S.p.M;
     cpx<R>* phi = fld<R>(S, B_PHI);
@@ -241,7 +244,7 @@ __global__ __launch_bounds__(PT) void k_apply(const Slot* slots, RedGeom g) {
         wmax = fmax(wmax, sqrt(cabs2(wid(nv) - v)));
     }
     const double wm = bmax(wmax);
-    if (threadIdx.x == 0) S.red_pw[(long long)blockIdx.x * NS_MAX + W_ROW] = wm;
+    if (threadIdx.x == 0) as_global(S.red_pw)[(long long)blockIdx.x * NS_MAX + W_ROW] = wm;
 }
 
 // ---------------------------------------------------------------------------
@@ -250,14 +253,13 @@ __global__ __launch_bounds__(PT) void k_apply(const Slot* slots, RedGeom g) {
 template <typename R>
 __global__ __launch_bounds__(PT) void k_normalize(const Slot* slots, RedGeom g) {
     const Slot& S = slots[blockIdx.y];
-    SolveState* st = S.st;
     const Phys p = S.p;
     const cpx<R>* phi = fld<R>(S, B_PHI);
     const long long n3 = 3 * p.M;
     double acc[1] = {0.0};
     for (long long i = (long long)blockIdx.x * PT + threadIdx.x; i < n3; i += (long long)gridDim.x * PT)
         acc[0] += cabs2(wid(phi[i]));
-    block_row<1>(acc, S.red_pw, NS_MAX);
+    block_row<1>(acc, as_global(S.red_pw), NS_MAX);
 }
 
 // ---------------------------------------------------------------------------
@@ -271,7 +273,7 @@ __global__ __launch_bounds__(PT) void k_normalize(const Slot* slots, RedGeom g) 
 //   FIN_RFINAL: residual rows of a final-only residual pass
 __global__ __launch_bounds__(PT) void k_fin(const Slot* slots, RedGeom g, int what) {
     const Slot& S = slots[blockIdx.y];
-    SolveState* st = S.st;
+    SolveState* st = as_global(S.st);
     const Phys p = S.p;
     if (what != FIN_NORM && what != FIN_RFINAL && st->done) return;
     // the pass before this control step applied a step: its largest change (3.9)
@@ -279,18 +281,18 @@ __global__ __launch_bounds__(PT) void k_fin(const Slot* slots, RedGeom g, int wh
         const int had_step = st->pending_step;   // read by every thread before thread 0 changes it
         if (had_step) {
             double wc[1];
-            gather<1>(wc, S.red_pw + W_ROW, g.nblk_pw, NS_MAX, 1u);
+            gather<1>(wc, as_global(S.red_pw) + W_ROW, g.nblk_pw, NS_MAX, 1u);
             if (threadIdx.x == 0) st->wchange = wc[0];
         }
     }
     if (what == FIN_EVAL) {
         double tot[NS_EVAL], mt[4];
-        gather<NS_EVAL>(tot, S.red_pw, g.nblk_pw, NS_MAX);
-        gather<4>(mt, S.red_mid, g.nblk_mid, RED_MID_STRIDE);
+        gather<NS_EVAL>(tot, as_global(S.red_pw), g.nblk_pw, NS_MAX);
+        gather<4>(mt, as_global(S.red_mid), g.nblk_mid, RED_MID_STRIDE);
         if (threadIdx.x == 0) ctrl_eval(st, p, tot, mt);
     } else if (what == FIN_DIR) {
         double tot[NS_RES];
-        gather<NS_RES>(tot, S.red_pw, g.nblk_pw, NS_MAX, 1u);
+        gather<NS_RES>(tot, as_global(S.red_pw), g.nblk_pw, NS_MAX, 1u);
         __shared__ int stop;
         if (threadIdx.x == 0) {
             ctrl_resid(st, p, tot, 0);
@@ -299,16 +301,16 @@ __global__ __launch_bounds__(PT) void k_fin(const Slot* slots, RedGeom g, int wh
         __syncthreads();
         if (stop) return;
         double dt[NS_DIR];
-        gather<NS_DIR>(dt, S.red_dir, g.nblk_dir, RED_DIR_STRIDE);
+        gather<NS_DIR>(dt, as_global(S.red_dir), g.nblk_dir, RED_DIR_STRIDE);
         if (threadIdx.x == 0) ctrl_dir(st, p, dt);
     } else if (what == FIN_LS) {
         double tot[NS_LS], kin[NS_KIN];
-        gather<NS_LS>(tot, S.red_pw, g.nblk_pw, NS_MAX);
-        gather<NS_KIN>(kin, S.red_mid, g.nblk_mid, RED_MID_STRIDE);
+        gather<NS_LS>(tot, as_global(S.red_pw), g.nblk_pw, NS_MAX);
+        gather<NS_KIN>(kin, as_global(S.red_mid), g.nblk_mid, RED_MID_STRIDE);
         if (threadIdx.x == 0) ctrl_ls(st, p, tot, kin);
     } else if (what == FIN_NORM) {
         double tot[1];
-        gather<1>(tot, S.red_pw, g.nblk_pw, NS_MAX);
+        gather<1>(tot, as_global(S.red_pw), g.nblk_pw, NS_MAX);
         if (threadIdx.x == 0) {
             const double n2 = tot[0] * p.cell;
             if (!(n2 > 0.0) || !isfinite(n2)) {
@@ -324,7 +326,7 @@ __global__ __launch_bounds__(PT) void k_fin(const Slot* slots, RedGeom g, int wh
         }
     } else if (what == FIN_RFINAL) {
         double tot[NS_RES];
-        gather<NS_RES>(tot, S.red_pw, g.nblk_pw, NS_MAX, 1u);
+        gather<NS_RES>(tot, as_global(S.red_pw), g.nblk_pw, NS_MAX, 1u);
         if (threadIdx.x == 0) ctrl_resid(st, p, tot, 1);
     }
 }
@@ -365,7 +367,7 @@ template <typename R>
 __global__ void k_pvin(const Slot* slots) {
     const Slot& S = slots[blockIdx.y];
     const Phys p = S.p;
-    const SolveState* st = S.st;
+    const SolveState* st = as_global(S.st);
     const cpx<R>* phi = fld<R>(S, B_PHI);
     const cpx<R>* r = fld<R>(S, B_X0);
     R* pv = pvf<R>(S);
