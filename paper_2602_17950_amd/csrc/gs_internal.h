@@ -81,8 +81,9 @@ struct Phys {
 // block barrier would also wait for the block's outstanding HBM loads and
 // stores, prefetches included.
 template <typename T> __device__ __forceinline__ T* as_global(T* const& field) {
-    using G = __attribute__((address_space(1))) T*;
-    return (T*)*reinterpret_cast<const G*>(reinterpret_cast<const void*>(&field));
+    __attribute__((address_space(1))) T* g;
+    __builtin_memcpy(&g, &field, sizeof g);   // the same 64 bits, read as a global pointer
+    return (T*)g;
 }
 
 // trap potential, split into its degree-2 and degree-4 parts (V2 + V4 = V)
