@@ -143,7 +143,7 @@ def initial_guess(pb: Problem, kinds=("a", "a", "a"), noise: float = 0.0, seed: 
 
 
 # ----------------------------------------------------------------------------
-# the synthetic workloads (their parameter sets; see the design doc for the recipe)
+# the synthetic workloads (each function states its parameter set)
 # ----------------------------------------------------------------------------
 def workload_small_2d():
     """2D 64x64 on [-8,8]^2, harmonic, Omega=0, gamma=0.5, c0=100, c1=-0.5,
