@@ -352,23 +352,53 @@ __global__ __launch_bounds__(NT) void k_fwdT(const Slot* __restrict__ slots, int
         k1 = st->dphi;
         k2 = st->invnP;
     }
-    for (int e = threadIdx.x; e < TILE * N; e += NT) {
-        const int l = e / N, m = e - l * N;
-        const long long gi = base + (long long)l * N + m;
-        cpx<R> v;
-        if (second) {
-            v = cvt<R>(aux1[gi]);
-        } else {
-            v = inp[gi];
-            if (mode == PRO_DIR) {
-                // D = -P r + beta P^{n-1};  P^n = D - Re<D,Phi> Phi  (stored), transform P^n / |P^n|
-                const cpx<double> d = k0 * wid(v) - wid(auxR[gi]) - k1 * wid(aux1[gi]);
-                v = cvt<R>(d);
-                inp[gi] = v;
-                v = (R)k2 * v;
+    // the thread's points in batches of EB: every load of a batch is issued
+    // before its stores (a store to inp would otherwise hold back the loads of
+    // the next point, which the compiler must assume it may alias)
+    constexpr int EPT = TilePlan<R, N, TILE, NT>::EPT;
+    constexpr int EB = EPT < 4 ? EPT : 4;
+#pragma unroll
+    for (int i0 = 0; i0 < EPT; i0 += EB) {
+        cpx<R> vi[EB], va[EB];
+        cpx<RX> vx[EB];
+#pragma unroll
+        for (int j = 0; j < EB; ++j) {
+            if (i0 + j >= EPT) continue;   // EPT need not be a multiple of EB
+            const int e = threadIdx.x + (i0 + j) * NT;
+            if (TILE * N % NT != 0 && e >= TILE * N) continue;
+            const int l = e / N, m = e - l * N;
+            const long long gi = base + (long long)l * N + m;
+            if (second) {
+                vx[j] = aux1[gi];
+            } else {
+                vi[j] = inp[gi];
+                if (mode == PRO_DIR) {
+                    va[j] = auxR[gi];
+                    vx[j] = aux1[gi];
+                }
             }
         }
-        lds[l * PITCH + lx(m)] = v;
+#pragma unroll
+        for (int j = 0; j < EB; ++j) {
+            if (i0 + j >= EPT) continue;   // EPT need not be a multiple of EB
+            const int e = threadIdx.x + (i0 + j) * NT;
+            if (TILE * N % NT != 0 && e >= TILE * N) continue;
+            const int l = e / N, m = e - l * N;
+            cpx<R> v;
+            if (second) {
+                v = cvt<R>(vx[j]);
+            } else {
+                v = vi[j];
+                if (mode == PRO_DIR) {
+                    // D = -P r + beta P^{n-1};  P^n = D - Re<D,Phi> Phi  (stored), transform P^n / |P^n|
+                    const cpx<double> d = k0 * wid(v) - wid(va[j]) - k1 * wid(vx[j]);
+                    v = cvt<R>(d);
+                    inp[base + (long long)l * N + m] = v;
+                    v = (R)k2 * v;
+                }
+            }
+            lds[l * PITCH + lx(m)] = v;
+        }
     }
     __syncthreads();
     lds_fft<R, N, TILE, NT, false>(lds, tw);
@@ -457,32 +487,56 @@ __global__ __launch_bounds__(NT) void k_invT(const Slot* __restrict__ slots, int
     }
     lds_fft<R, N, TILE, NT, true>(lds, twl);
     if (nin == 2) lds_fft<R, N, TILE, NT, true>(lds2, twl);
-    for (int e = threadIdx.x; e < TILE * N; e += NT) {
-        const int l = e / N, m = e - l * N;
-        const long long go = (((long long)c * B + bb) * Cc + c0 + l) * N + m;
-        cpx<R> v = lds[l * PITCH + lx(m)];
-        if (EPI == EPI_SCALE) {
-            out[go] = (R)scale * v;
-        } else if (EPI == EPI_HL) {
-            const int ix = m, iy = c0 + l, iz = bb;
-            const double x = -p.L[0] + ix * p.h[0];
-            const double y = -p.L[1] + iy * p.h[1];
-            const double z = p.dim == 3 ? -p.L[2] + iz * p.h[2] : 0.0;
-            double V2, V4;
-            trap_at(p, go - (long long)c * p.M, x, y, z, V2, V4);
-            const cpx<R> u = uscale * uin[go];
-            v = v + (R)(V2 + V4) * u;
-            if (nin == 2) v = v - (R)(p.omega * x) * lds2[l * PITCH + lx(m)];
-            out[go] = v;
-        } else if (EPI == EPI_ROTX) {
-            if (nin == 2) {
-                const int jx = bb, iy = m;
-                const double kx = wavenum(jx, p.n[0], p.L[0]);
-                const double y = -p.L[1] + iy * p.h[1];
-                v = v + (R)(p.omega * y * kx / p.n[0]) * uin[go];
-                out2[go] = lds2[l * PITCH + lx(m)];
+    // in batches of EB points, the loads of uin (and of a tabulated potential)
+    // issued before the batch's stores (see the forward pass)
+    constexpr int EB = EPT < 4 ? EPT : 4;
+#pragma unroll
+    for (int i0 = 0; i0 < EPT; i0 += EB) {
+        cpx<R> vu[EB];
+        double vV[EB];
+#pragma unroll
+        for (int j = 0; j < EB; ++j) {
+            if (i0 + j >= EPT) continue;   // EPT need not be a multiple of EB
+            const int e = threadIdx.x + (i0 + j) * NT;
+            if (TILE * N % NT != 0 && e >= TILE * N) continue;
+            const int l = e / N, m = e - l * N;
+            const long long go = (((long long)c * B + bb) * Cc + c0 + l) * N + m;
+            if (EPI == EPI_HL) {
+                vu[j] = uin[go];
+                const double x = -p.L[0] + m * p.h[0];
+                const double y = -p.L[1] + (c0 + l) * p.h[1];
+                const double z = p.dim == 3 ? -p.L[2] + bb * p.h[2] : 0.0;
+                double V2, V4;
+                trap_at(p, go - (long long)c * p.M, x, y, z, V2, V4);
+                vV[j] = V2 + V4;
+            } else if (EPI == EPI_ROTX && nin == 2) {
+                vu[j] = uin[go];
             }
-            out[go] = v;
+        }
+#pragma unroll
+        for (int j = 0; j < EB; ++j) {
+            if (i0 + j >= EPT) continue;   // EPT need not be a multiple of EB
+            const int e = threadIdx.x + (i0 + j) * NT;
+            if (TILE * N % NT != 0 && e >= TILE * N) continue;
+            const int l = e / N, m = e - l * N;
+            const long long go = (((long long)c * B + bb) * Cc + c0 + l) * N + m;
+            cpx<R> v = lds[l * PITCH + lx(m)];
+            if (EPI == EPI_SCALE) {
+                out[go] = (R)scale * v;
+            } else if (EPI == EPI_HL) {
+                const double x = -p.L[0] + m * p.h[0];
+                v = v + (R)vV[j] * (uscale * vu[j]);
+                if (nin == 2) v = v - (R)(p.omega * x) * lds2[l * PITCH + lx(m)];
+                out[go] = v;
+            } else if (EPI == EPI_ROTX) {
+                if (nin == 2) {
+                    const double kx = wavenum(bb, p.n[0], p.L[0]);
+                    const double y = -p.L[1] + m * p.h[1];
+                    v = v + (R)(p.omega * y * kx / p.n[0]) * vu[j];
+                    out2[go] = lds2[l * PITCH + lx(m)];
+                }
+                out[go] = v;
+            }
         }
     }
     if constexpr (TP::PIPE) __syncthreads();   // lds and lds2 are refilled by the next unit
@@ -557,6 +611,8 @@ __global__ __launch_bounds__(NT) void k_invT_pre(const Slot* __restrict__ slots,
     }
     lds_fft<R, N, TILE, NT, true>(lds, twl);
     double acc[NS_DIR] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    // one loop over the points (batching its loads as the other passes do
+    // raised the register count and lost occupancy: measured slower)
     for (int e = threadIdx.x; e < TILE * N; e += NT) {
         const int l = e / N, m = e - l * N;
         const long long go = (((long long)c * B + bb) * Cc + c0 + l) * N + m;
