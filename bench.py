@@ -137,7 +137,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=32, help="solves per headline step")
     ap.add_argument("--n", type=int, default=256, help="grid points per axis of the headline workload")
-    ap.add_argument("--kernel", default="hl_mid", help="kernel kind timed for the roofline")
+    ap.add_argument("--kernel", default="pre_inv", help="kernel kind timed for the roofline")
     ap.add_argument("--mixed-dir", choices=("fp32", "fp64"), default="fp32",
                     help="direction precision of the double phase of mixed solves")
     ap.add_argument("--sections", default=",".join(SECTIONS))
