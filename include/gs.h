@@ -51,6 +51,8 @@ extern "C" {
 #define GS_ECANCELED (-5)    /* request cancelled before it completed */
 #define GS_WMAXITER 1        /* max_iter reached before the stopping criterion */
 #define GS_WSTAGNATED 2      /* no descent step found: rounding floor reached */
+#define GS_WEXISTENCE 3      /* converged, but the parameters lie outside the hypotheses of the
+                                existence theorem of Sec. 2.1 (see gs_existence_check) */
 #define GS_PENDING 16        /* gs_poll: the request has not completed yet (not an outcome) */
 
 /* stopping criteria (Sec. 3.4) */
@@ -71,6 +73,11 @@ extern "C" {
 #define GS_LS_EXACT 1        /* the step of Algorithm 2, then refined to a minimiser of the
                                 energy along the curve cos t Phi + sin t P^ (Newton steps on
                                 its explicit form in cos t and sin t; no transform involved) */
+
+/* Symbol of the odd operators D_x, D_y, D_z (and so of L0, L1 and L_z) at the
+ * wavenumber index p = -N/2 of Sec. 3.2 (the kinetic symbol always keeps it) */
+#define GS_NYQ_KEEP 0        /* v_p = -pi N / (2L), the set Lambda_N as printed (default) */
+#define GS_NYQ_ZERO 1        /* symbol 0 at p = -N/2 */
 
 /* arithmetic of the iteration */
 #define GS_FP64 0            /* all fields and transforms in double */
@@ -131,6 +138,7 @@ typedef struct {
                              and only the path to it changes. */
     int precond;          /* GS_PC_* (default GS_PC_COMBINED) */
     int line_search;      /* GS_LS_ALG2 (default) or GS_LS_EXACT */
+    int nyquist_odd;      /* GS_NYQ_KEEP (default) or GS_NYQ_ZERO */
 } gs_options;
 
 /* Results; quantities refer to the returned Phi. */
@@ -172,12 +180,28 @@ typedef struct {
 /* Create a context on HIP device `device`. Returns GS_OK and *out, or an error.
  * The device-memory budget for solves starts at 90% of the free memory. */
 int gs_create(gs_ctx** out, int device);
+/* Hypotheses of the existence theorem of Sec. 2.1 for a harmonic trap
+ * (gs_trap with q4 = 0 and no sampled V; g_a^2 + 2 q2 taken as gamma_a^2):
+ *   |Omega| < min(gamma_x, gamma_y), and
+ *   d = 2: c0 > -C_b and c0 + c1 > -C_b, with C_b the best constant of the
+ *          Gagliardo-Nirenberg inequality of Sec. 2.1 (5.8503..., half the
+ *          mass of the ground state of -Q'' - Q'/r + Q = Q^3 in 2D);
+ *   d = 3: c0 >= 0 and c1 >= 0, or c1 <= 0 and c0 + c1 >= 0.
+ * Returns GS_OK when they hold or do not apply (a quartic part, which bounds
+ * the energy from below for any Omega, or a sampled V), GS_WEXISTENCE when
+ * they are violated, GS_EINVAL for invalid arguments. Host-only; a solve
+ * that converges on parameters that fail the check returns GS_WEXISTENCE in
+ * place of GS_OK (the theorem is sufficient, not necessary: the result may
+ * still be a ground state). */
+int gs_existence_check(const gs_grid* g, const gs_trap* t, const gs_params* p);
+
 /* Release the context and all device memory it owns. NULL is ignored. */
 void gs_destroy(gs_ctx* ctx);
 /* Fill *o with the defaults: energy criterion, tol 1e-12, max_iter 100000,
  * FP64, switch_resid 1e-6, fp32_max_iter 20000, stall_window 50,
  * theta_trial 0.1, sigma 0.5, max_backtrack 40, check_every 32, cm_levels 1,
- * dir_precision GS_FP64, precond GS_PC_COMBINED, line_search GS_LS_ALG2. */
+ * dir_precision GS_FP64, precond GS_PC_COMBINED, line_search GS_LS_ALG2,
+ * nyquist_odd GS_NYQ_KEEP. */
 void gs_default_options(gs_options* o);
 /* Device bytes a solve of this grid needs with these options (GS_MIXED counts
  * both the float and the double working sets; dir_precision GS_FP32 halves the

@@ -41,7 +41,7 @@ def build(force: bool = True) -> str:
 
 
 class _Grid(C.Structure):
-    _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("L", C.c_double * 3)]
+    _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("L", C.c_double * 3), ("nyq_zero", C.c_int)]
 
 
 class _Trap(C.Structure):
@@ -85,12 +85,19 @@ def _load():
     return _lib
 
 
+NYQ_KEEP, NYQ_ZERO = 0, 1
+
+
 @dataclass
 class Grid:
-    """Domain prod_a [-L_a, L_a] with n_a points per axis (n = (Nx, Ny[, Nz]))."""
+    """Domain prod_a [-L_a, L_a] with n_a points per axis (n = (Nx, Ny[, Nz])).
+    nyquist_odd: NYQ_KEEP keeps the mode p = -N/2 in the symbols of the odd
+    operators D_a, L0, L1, L_z (the set Lambda_N of Sec. 3.2); NYQ_ZERO sets
+    their symbol there to zero."""
     dim: int
     n: tuple
     L: tuple
+    nyquist_odd: int = NYQ_KEEP
 
     @property
     def shape(self):
@@ -111,6 +118,7 @@ class Grid:
     def _c(self):
         g = _Grid()
         g.dim = self.dim
+        g.nyq_zero = int(self.nyquist_odd)
         for a in range(3):
             g.n[a] = int(self.n[a]) if a < self.dim else 1
             g.L[a] = float(self.L[a]) if a < self.dim else 1.0

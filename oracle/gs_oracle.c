@@ -38,7 +38,11 @@
 
 typedef double complex cplx;
 
-typedef struct { int dim; int n[3]; double L[3]; } orc_grid;          /* n[0]=Nx, n[1]=Ny, n[2]=Nz */
+/* n[0]=Nx, n[1]=Ny, n[2]=Nz. nyq_zero selects the reading of the mode p = -N/2 in
+ * the symbols of the odd operators D_a (hence L0, L1 and L_z): 0 keeps
+ * v_p = -pi N / (2L) as the set Lambda_N of Sec. 3.2 lists it; 1 sets that
+ * symbol to zero. The kinetic symbol keeps the mode in both readings. */
+typedef struct { int dim; int n[3]; double L[3]; int nyq_zero; } orc_grid;
 /* V(x) = 1/2 sum_a g_a^2 x_a^2 + q2 r^2 + q4 r^4 (r^2 = sum over all d axes),
  * or a sampled array when V != NULL (harmonic trap: Sec. 1 eq. (1.4);
  * harmonic-plus-quartic trap: eq. (4.1) of Example 5). */
@@ -87,6 +91,12 @@ static double wavenum(const orc_grid* g, int a, int j) {
     int n = g->n[a];
     int p = (j < n / 2) ? j : j - n;
     return M_PI * p / g->L[a];
+}
+/* wavenumber in the symbol of an odd operator (D_a): as wavenum, except that
+ * the mode p = -N/2 has symbol 0 when the grid selects that reading */
+static double wavenum_odd(const orc_grid* g, int a, int j) {
+    if (g->nyq_zero && j == g->n[a] / 2) return 0.0;
+    return wavenum(g, a, j);
 }
 static void unpack(const orc_grid* g, long i, int* ix, int* iy, int* iz) {
     *ix = (int)(i % g->n[0]);
@@ -262,6 +272,14 @@ static void kvec(const orc_grid* g, long i, double* kx, double* ky, double* kz) 
     *ky = wavenum(g, 1, jy);
     *kz = g->dim == 3 ? wavenum(g, 2, jz) : 0.0;
 }
+/* wavenumbers in the symbols of the odd operators D_x, D_y, D_z */
+static void kvec_odd(const orc_grid* g, long i, double* kx, double* ky, double* kz) {
+    int jx, jy, jz;
+    unpack(g, i, &jx, &jy, &jz);
+    *kx = wavenum_odd(g, 0, jx);
+    *ky = wavenum_odd(g, 1, jy);
+    *kz = g->dim == 3 ? wavenum_odd(g, 2, jz) : 0.0;
+}
 /* D_a f = -i d/dx_a f, symbol v^a (so that L_z = x D_y - y D_x, Sec. 3.2) */
 void orc_apply_deriv(const orc_grid* g, int axis, const cplx* f, cplx* out) {
     long M = npts(g);
@@ -269,7 +287,7 @@ void orc_apply_deriv(const orc_grid* g, int axis, const cplx* f, cplx* out) {
     orc_fftn(g, out, -1);
     for (long i = 0; i < M; ++i) {
         double k[3];
-        kvec(g, i, &k[0], &k[1], &k[2]);
+        kvec_odd(g, i, &k[0], &k[1], &k[2]);
         out[i] *= k[axis];
     }
     orc_fftn(g, out, +1);
@@ -305,7 +323,7 @@ void orc_apply_soc(const orc_grid* g, const cplx* u, cplx* out) {
     cplx* uh = spectra(g, u);
     for (long i = 0; i < M; ++i) {
         double kx, ky, kz;
-        kvec(g, i, &kx, &ky, &kz);
+        kvec_odd(g, i, &kx, &ky, &kz);
         cplx s0 = sym_L0(kx, ky), s1 = sym_L1(kx, ky);
         out[0 * M + i] = s0 * uh[1 * M + i];
         out[1 * M + i] = s1 * uh[0 * M + i] + s0 * uh[2 * M + i];

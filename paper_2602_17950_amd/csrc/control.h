@@ -78,8 +78,10 @@ __device__ inline void ctrl_resid(SolveState* st, const Phys& p, const double (&
     } else if ((st->stop_kind == GS_STOP_RESIDUAL || st->stop_kind == GS_STOP_EITHER) && rinf < st->tol) {
         st->done = 1;   // criterion (3.10)
         return;
-    } else if (st->stop_kind == GS_STOP_WAVEFN && st->iter > 0 && st->wchange < st->tol) {
-        st->done = 1;   // criterion (3.9), for the step that produced this iterate
+    } else if (st->stop_kind == GS_STOP_WAVEFN && st->iter_phase > 0 && st->wchange < st->tol) {
+        // criterion (3.9), for the PCG step of this precision phase that produced
+        // this iterate (never for a normalisation, nor for the float phase's last step)
+        st->done = 1;
         return;
     }
     if (st->iter >= st->max_iter) { st->status = GS_WMAXITER; st->done = 1; return; }

@@ -83,7 +83,33 @@ static int check_options(const gs_options* o) {
     if (o->cm_levels < 1 || o->cm_levels > 7) return fail(GS_EINVAL, "options.cm_levels must be in [1, 7]");
     if (o->dir_precision != GS_FP64 && o->dir_precision != GS_FP32)
         return fail(GS_EINVAL, "options.dir_precision must be GS_FP64 or GS_FP32");
+    if (o->nyquist_odd != GS_NYQ_KEEP && o->nyquist_odd != GS_NYQ_ZERO)
+        return fail(GS_EINVAL, "options.nyquist_odd must be GS_NYQ_KEEP or GS_NYQ_ZERO");
     return GS_OK;
+}
+
+// Best constant of the Gagliardo-Nirenberg inequality in 2D used by the
+// existence theorem of Sec. 2.1: C_b = inf |grad u|^2 |u|^2 / |u|_4^4, which is
+// half the mass of the positive radial solution Q of Q'' + Q'/r - Q + Q^3 = 0
+// (Weinstein's characterisation of the sharp constant); |Q|_2^2 = 11.700896.
+constexpr double GN_CB_2D = 5.850448;
+
+// Hypotheses of the existence theorem of Sec. 2.1 for a harmonic trap (see
+// gs_existence_check in gs.h).
+static int existence(const gs_grid* g, const gs_trap* t, const gs_params* p) {
+    if (!g || !p || (g->dim != 2 && g->dim != 3)) return fail(GS_EINVAL, "existence check: invalid argument");
+    if (t && (t->V || t->q4 != 0.0)) return GS_OK;   // not a harmonic trap: the theorem says nothing
+    double ga2[3];
+    for (int a = 0; a < 3; ++a) {
+        const double ga = t ? t->g[a] : 1.0;
+        ga2[a] = ga * ga + 2.0 * (t ? t->q2 : 0.0);   // V = 1/2 sum (g_a^2 + 2 q2) x_a^2
+    }
+    for (int a = 0; a < g->dim; ++a)
+        if (!(ga2[a] > 0.0)) return GS_WEXISTENCE;   // not a confining harmonic trap
+    if (!(std::fabs(p->omega) < std::sqrt(std::min(ga2[0], ga2[1])))) return GS_WEXISTENCE;
+    const double c0 = p->c0, c1 = p->c1;
+    if (g->dim == 2) return (c0 > -GN_CB_2D && c0 + c1 > -GN_CB_2D) ? GS_OK : GS_WEXISTENCE;
+    return ((c0 >= 0.0 && c1 >= 0.0) || (c1 <= 0.0 && c0 + c1 >= 0.0)) ? GS_OK : GS_WEXISTENCE;
 }
 
 // slots per class (bounded by the launch grid's y extent and the state arrays)
@@ -247,9 +273,10 @@ static hipError_t timer_collect(Timer& tm, TimerTotals& tot, const std::vector<i
 // ---------------------------------------------------------------------------
 // problem description
 // ---------------------------------------------------------------------------
-static int make_phys(const gs_grid* g, const gs_trap* t, const gs_params* p, Phys* ph) {
+static int make_phys(const gs_grid* g, const gs_trap* t, const gs_params* p, Phys* ph, int nyq_zero = 0) {
     std::memset(ph, 0, sizeof(*ph));
     ph->dim = g->dim;
+    ph->nyq_zero = nyq_zero;
     ph->n[0] = g->n[0];
     ph->n[1] = g->n[1];
     ph->n[2] = g->dim == 3 ? g->n[2] : 1;
@@ -518,6 +545,7 @@ struct Job {
     cpx<double>* cm_buf[2] = {nullptr, nullptr};   // level result / interpolated guess (finest size)
     cpx<double>* user_out = nullptr;
     int iters_coarse = 0;
+    bool warn_existence = false;   // the parameters fail the hypotheses of the existence theorem
     int rc = GS_OK;
     gs_result res{};
     std::string err;
@@ -785,6 +813,7 @@ static int acquire_slot(Ctx& cx, Class<RS, RD>& c, Job* j, hipStream_t s, int* o
 
 static void finish_job(Ctx& cx, Job* j, int rc, const SolveState* h, const std::string& msg) {
     const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() - j->t0).count();
+    if (rc == GS_OK && j->warn_existence) rc = GS_WEXISTENCE;
     fill_result(h, &j->res, j->iters_fp32, wall);
     j->res.iters_coarse = j->iters_coarse;
     j->res.status = rc;
@@ -934,7 +963,7 @@ static int next_level(Ctx& cx, Job* j, hipStream_t s) {
     j->wait_ev = true;
     j->level++;
     j->grid = gf;
-    if ((rc = make_phys(&gf, &j->trap, &j->prm, &j->ph))) return rc;
+    if ((rc = make_phys(&gf, &j->trap, &j->prm, &j->ph, j->opt.nyquist_odd == GS_NYQ_ZERO))) return rc;
     j->psi0 = j->cm_buf[1];
     j->out = j->level + 1 == j->nlevels ? j->user_out : j->cm_buf[0];
     j->iters_fp32 = 0;
@@ -1024,6 +1053,12 @@ static int boundary(Ctx& cx, Class<RS, RD>& c) {
         Job* j = c.queue.front();
         c.queue.pop_front();
         if (j->cancel) {
+            // a handed-over slot may still be the target of the hand-over copy on
+            // another stream: order the slot's next use on this stream after it
+            if (j->wait_ev) {
+                HIPCHK(hipStreamWaitEvent(c.stream, j->ev, 0));
+                j->wait_ev = false;
+            }
             if (j->slot >= 0) c.owner[j->slot] = nullptr;
             finish_job(cx, j, GS_ECANCELED, nullptr, "request cancelled");
             continue;
@@ -1182,8 +1217,10 @@ static int submit_job(Ctx& cx, const gs_request* q, uint64_t* ticket) {
                 return fail(GS_EINVAL, "cm_levels too large: the coarsest grid needs n[a] >= 16");
     }
     j->grid = level_grid(j->fine, j->nlevels, 0);
-    if ((rc = make_phys(&j->fine, &q->trap, &q->params, &j->ph))) return rc;   // validates the full-size V
-    if ((rc = make_phys(&j->grid, &q->trap, &q->params, &j->ph))) return rc;
+    const int nyq = q->options.nyquist_odd == GS_NYQ_ZERO;
+    if ((rc = make_phys(&j->fine, &q->trap, &q->params, &j->ph, nyq))) return rc;   // validates the full-size V
+    if ((rc = make_phys(&j->grid, &q->trap, &q->params, &j->ph, nyq))) return rc;
+    j->warn_existence = existence(&j->fine, &q->trap, &q->params) == GS_WEXISTENCE;
     const long long M = npts(&j->fine);
     j->reserve = 0;
     j->reserve = footprint(&j->fine, &q->options);
@@ -1455,7 +1492,10 @@ void gs_default_options(gs_options* o) {
     o->dir_precision = GS_FP64;
     o->precond = GS_PC_COMBINED;
     o->line_search = GS_LS_ALG2;
+    o->nyquist_odd = GS_NYQ_KEEP;
 }
+
+int gs_existence_check(const gs_grid* g, const gs_trap* t, const gs_params* p) { return existence(g, t, p); }
 
 size_t gs_footprint_bytes(const gs_grid* g, const gs_options* o) {
     if (check_grid(g) != GS_OK || check_options(o) != GS_OK) return 0;

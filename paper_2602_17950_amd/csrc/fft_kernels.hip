@@ -530,7 +530,7 @@ __global__ __launch_bounds__(NT) void k_invT(const Slot* __restrict__ slots, int
                 out[go] = v;
             } else if (EPI == EPI_ROTX) {
                 if (nin == 2) {
-                    const double kx = wavenum(bb, p.n[0], p.L[0]);
+                    const double kx = wavenum_odd(bb, p.n[0], p.L[0], p.nyq_zero);
                     const double y = -p.L[1] + m * p.h[1];
                     v = v + (R)(p.omega * y * kx / p.n[0]) * vu[j];
                     out2[go] = lds2[l * PITCH + lx(m)];
@@ -771,17 +771,19 @@ __global__ __launch_bounds__(NT) void k_mid(const Slot* __restrict__ slots, int 
         for (int e = threadIdx.x; e < LPB * N; e += NT) {
             const int q = e / N, m = e - q * N;
             const int line = l0 + q;
-            double kx, ky, kz;
+            // kinetic symbol from the wavenumbers; the odd symbols (SOC, D_y)
+            // from their odd-operator reading
+            int jx, jy, jz;
             if (p.dim == 2) {
-                kx = wavenum(line, p.n[0], p.L[0]);
-                ky = wavenum(m, p.n[1], p.L[1]);
-                kz = 0.0;
+                jx = line; jy = m; jz = 0;
             } else {
-                kx = wavenum(line % p.n[0], p.n[0], p.L[0]);
-                ky = wavenum(line / p.n[0], p.n[1], p.L[1]);
-                kz = wavenum(m, p.n[2], p.L[2]);
+                jx = line % p.n[0]; jy = line / p.n[0]; jz = m;
             }
-            const double K = 0.5 * (kx * kx + ky * ky + kz * kz);
+            const double wx = wavenum(jx, p.n[0], p.L[0]), wy = wavenum(jy, p.n[1], p.L[1]);
+            const double wz = p.dim == 3 ? wavenum(jz, p.n[2], p.L[2]) : 0.0;
+            const double K = 0.5 * (wx * wx + wy * wy + wz * wz);
+            const double kx = wavenum_odd(jx, p.n[0], p.L[0], p.nyq_zero);
+            const double ky = wavenum_odd(jy, p.n[1], p.L[1], p.nyq_zero);
             cpx<R>* x0 = X + (0 * LPB + q) * PITCH + lx(m);
             cpx<R>* x1 = X + (1 * LPB + q) * PITCH + lx(m);
             cpx<R>* x2 = X + (2 * LPB + q) * PITCH + lx(m);
@@ -845,7 +847,7 @@ __global__ __launch_bounds__(NT) void k_mid(const Slot* __restrict__ slots, int 
                 const long long go = c * cs + (long long)(l0 + q) * N + m;
                 cpx<R> v = X[L * PITCH + lx(m)];
                 if (rot2d) {
-                    const double kx = wavenum(l0 + q, p.n[0], p.L[0]);
+                    const double kx = wavenum_odd(l0 + q, p.n[0], p.L[0], p.nyq_zero);
                     const double y = -p.L[1] + m * p.h[1];
                     const cpx<R> x = MP::CLDS ? Cp[L * PITCH + lx(m)] : in[go];
                     v = v + (R)(p.omega * y * kx / p.n[0]) * x;

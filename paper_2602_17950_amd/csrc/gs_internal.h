@@ -71,6 +71,7 @@ struct Phys {
     double q2, q4;            // isotropic r^2 and r^4 coefficients
     const double* V;          // user potential on the grid (device), or null
     double omega, gamma, c0, c1;
+    int nyq_zero;             // odd-operator symbols vanish at the mode -n/2 (GS_NYQ_ZERO)
 };
 
 // Every pointer a kernel finds in a slot or a problem description is a device
@@ -100,6 +101,11 @@ __device__ __forceinline__ void trap_at(const Phys& p, long long i, double x, do
 __device__ __forceinline__ double wavenum(int j, int n, double L) {
     int p = (j < n / 2) ? j : j - n;
     return 3.141592653589793238462643 * (double)p / L;
+}
+// the same wavenumber in the symbol of an odd operator (D_x, D_y, D_z, hence
+// L0, L1, L_z): zero at the mode -n/2 when the problem selects that reading
+__device__ __forceinline__ double wavenum_odd(int j, int n, double L, int nyq_zero) {
+    return (nyq_zero && j == n / 2) ? 0.0 : wavenum(j, n, L);
 }
 
 // ---------------------------------------------------------------------------

@@ -276,9 +276,11 @@ __global__ __launch_bounds__(PT) void k_fin(const Slot* slots, RedGeom g, int wh
     SolveState* st = as_global(S.st);
     const Phys p = S.p;
     if (what != FIN_NORM && what != FIN_RFINAL && st->done) return;
-    // the pass before this control step applied a step: its largest change (3.9)
+    // the pass before this control step applied a PCG step: its largest change
+    // (3.9); a normalisation rescale (s = 0) leaves the recorded change alone
     if (what == FIN_EVAL || what == FIN_DIR) {
-        const int had_step = st->pending_step;   // read by every thread before thread 0 changes it
+        // read by every thread before thread 0 changes the state
+        const int had_step = st->pending_step && st->s != 0.0;
         if (had_step) {
             double wc[1];
             gather<1>(wc, as_global(S.red_pw) + W_ROW, g.nblk_pw, NS_MAX, 1u);

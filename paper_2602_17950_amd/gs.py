@@ -15,18 +15,19 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgs.so")
 
 GS_OK, GS_EINVAL, GS_ENOMEM, GS_EDEVICE, GS_ENONFINITE, GS_ECANCELED = 0, -1, -2, -3, -4, -5
-GS_WMAXITER, GS_WSTAGNATED = 1, 2
+GS_WMAXITER, GS_WSTAGNATED, GS_WEXISTENCE = 1, 2, 3
 GS_PENDING = 16
 GS_STOP_ENERGY, GS_STOP_RESIDUAL, GS_STOP_EITHER, GS_STOP_WAVEFN = 0, 1, 2, 3
 GS_PC_COMBINED, GS_PC_KINETIC, GS_PC_POTENTIAL = 0, 1, 2
 GS_LS_ALG2, GS_LS_EXACT = 0, 1
 GS_FP64, GS_FP32, GS_MIXED = 0, 1, 2
+GS_NYQ_KEEP, GS_NYQ_ZERO = 0, 1
 
 EXPORTS = ("gs_create", "gs_destroy", "gs_default_options", "gs_footprint_bytes", "gs_solve",
            "gs_solve_device", "gs_fft", "gs_hamiltonian", "gs_precondition", "gs_kernel_timer_start",
            "gs_kernel_timer_read", "gs_last_error", "gs_set_hbm_budget", "gs_memory_stats",
            "gs_batch_solve", "gs_submit", "gs_progress", "gs_poll", "gs_wait", "gs_cancel",
-           "gs_interpolate")
+           "gs_interpolate", "gs_existence_check")
 
 KERNEL_KINDS = {"hl_fwd": 0, "hl_mid": 1, "hl_inv": 2, "pre_fwd": 3, "pre_mid": 4, "pre_inv": 5,
                 "eval": 6, "resid": 7, "lsred": 9, "hl_fwd2": 10, "hl_inv2": 11, "ctrl": 12}
@@ -56,7 +57,8 @@ class gs_options(C.Structure):
                 ("precision", C.c_int), ("switch_resid", C.c_double), ("fp32_max_iter", C.c_int),
                 ("stall_window", C.c_int), ("theta_trial", C.c_double), ("sigma", C.c_double),
                 ("max_backtrack", C.c_int), ("check_every", C.c_int), ("cm_levels", C.c_int),
-                ("dir_precision", C.c_int), ("precond", C.c_int), ("line_search", C.c_int)]
+                ("dir_precision", C.c_int), ("precond", C.c_int), ("line_search", C.c_int),
+                ("nyquist_odd", C.c_int)]
 
 
 class gs_result(C.Structure):
@@ -123,6 +125,7 @@ def load():
     lib.gs_wait.argtypes = [vp, C.c_uint64, C.POINTER(gs_result)]
     lib.gs_cancel.argtypes = [vp, C.c_uint64]
     lib.gs_interpolate.argtypes = [vp, C.POINTER(gs_grid), vp, C.POINTER(gs_grid), vp, vp]
+    lib.gs_existence_check.argtypes = [C.POINTER(gs_grid), C.POINTER(gs_trap), C.POINTER(gs_params)]
     _lib = lib
     return lib
 
@@ -176,6 +179,13 @@ def default_options(**kw) -> gs_options:
     return o
 
 
+def existence_check(pb) -> int:
+    """GS_OK or GS_WEXISTENCE: whether pb satisfies the hypotheses of the
+    existence theorem of Sec. 2.1 (host-side check, no device needed)."""
+    g, (t, keep), p = grid_of(pb), trap_of(pb), params_of(pb)
+    return _check(load().gs_existence_check(C.byref(g), C.byref(t), C.byref(p)))
+
+
 def footprint_bytes(pb, precision=GS_FP64, **kw) -> int:
     """Device bytes of a solve of pb (0 for an invalid grid or options); kw: other option fields."""
     g = grid_of(pb)
@@ -224,6 +234,10 @@ class Context:
         self._h = C.c_void_p()
         _check(lib.gs_create(C.byref(self._h), int(device)))
         self.device = device
+        # ticket -> the request's guess, output and sampled V: the library reads
+        # the guess at admission and writes the output at completion, so they
+        # are held until the ticket's result has been taken
+        self._held = {}
 
     def close(self):
         if self._h:
@@ -300,9 +314,12 @@ class Context:
         return out
 
     def submit(self, pb, psi0, out, options: gs_options | None = None, V=None) -> int:
+        """Queue a request (psi0 may be None); psi0 and out are kept alive by the
+        context until poll() or wait() has returned the ticket's result."""
         q, keep = make_request(pb, psi0, out, options, V)
         t = C.c_uint64()
         _check(load().gs_submit(self._h, C.byref(q), C.byref(t)))
+        self._held[t.value] = (psi0, out, keep)
         return t.value
 
     def progress(self, block: bool = False) -> int:
@@ -314,11 +331,13 @@ class Context:
         rc = load().gs_poll(self._h, C.c_uint64(ticket), C.byref(res))
         if rc == GS_PENDING:
             return None
+        self._held.pop(ticket, None)
         return _result(rc, res)
 
     def wait(self, ticket: int):
         res = gs_result()
         rc = load().gs_wait(self._h, C.c_uint64(ticket), C.byref(res))
+        self._held.pop(ticket, None)
         return _result(rc, res)
 
     def cancel(self, ticket: int):

@@ -136,7 +136,9 @@ def test_admission_by_footprint(gpu_ctx):
         ref = [alone(ctx, pb, psi0, opt) for pb, psi0 in probs]
         ctx.set_hbm_budget(need + need // 2)
         outs = [torch.empty((3,) + pb.shape, dtype=torch.complex128, device=DEV) for pb, _ in probs]
-        tickets = [ctx.submit(pb, dev(p0), o, opt) for (pb, p0), o in zip(probs, outs)]
+        # the guesses are read when each request is admitted: hold them until then
+        guesses = [dev(p0) for _, p0 in probs]
+        tickets = [ctx.submit(pb, g0, o, opt) for (pb, _), g0, o in zip(probs, guesses, outs)]
         peak = 0
         results = {}
         while len(results) < len(tickets):
@@ -170,13 +172,46 @@ def test_cancel(gpu_ctx):
     pb, psi0 = problems()[2]
     opt = gs.default_options(tol=0.0, max_iter=100000, check_every=4)
     out = torch.empty((3,) + pb.shape, dtype=torch.complex128, device=DEV)
-    t = gpu_ctx.submit(pb, dev(psi0), out, opt)
+    g0 = dev(psi0)
+    t = gpu_ctx.submit(pb, g0, out, opt)
     gpu_ctx.progress(block=True)
     gpu_ctx.cancel(t)
     r = gpu_ctx.wait(t)
     assert r["rc"] == gs.GS_ECANCELED
     with pytest.raises(gs.GsError):
         gpu_ctx.poll(t)   # the ticket was released
+    assert gpu_ctx.memory_stats()["reserved"] == 0
+
+
+def test_cancel_mixed_after_hand_over(gpu_ctx):
+    """A mixed request is cancelled around its hand-over to the double-state
+    class (switch_resid = 1 hands over after its first float step; it waits in
+    the double class's queue while that class runs a chunk of request B). The
+    slot it held is taken by a later request C, whose result must equal C
+    alone bit for bit, as must B's: the hand-over copy into the released slot
+    is ordered before the slot's next use."""
+    pb, p0 = problems()[2]
+    pc, pc0 = problems()[3]   # the same 64^2 grid class
+    optB = gs.default_options(tol=1e-11, check_every=4)
+    optA = gs.default_options(precision=gs.GS_MIXED, tol=0.0, max_iter=100000, switch_resid=1.0,
+                              check_every=4)
+    optC = gs.default_options(tol=1e-11, check_every=4)
+    refB = alone(gpu_ctx, pb, p0, optB)
+    refC = alone(gpu_ctx, pc, pc0, optC)
+    gB, gA, gC = dev(p0), dev(p0), dev(pc0)
+    oB, oA, oC = (torch.empty((3,) + pb.shape, dtype=torch.complex128, device=DEV) for _ in range(3))
+    tB = gpu_ctx.submit(pb, gB, oB, optB)
+    tA = gpu_ctx.submit(pb, gA, oA, optA)
+    for _ in range(2):
+        gpu_ctx.progress(block=True)
+    gpu_ctx.cancel(tA)
+    tC = gpu_ctx.submit(pc, gC, oC, optC)
+    rA, rB, rC = gpu_ctx.wait(tA), gpu_ctx.wait(tB), gpu_ctx.wait(tC)
+    torch.cuda.synchronize()
+    assert rA["rc"] == gs.GS_ECANCELED
+    assert rB["rc"] >= 0 and rC["rc"] >= 0
+    assert same_bits(oB, refB[0]) and rB["E"] == refB[1]["E"]
+    assert same_bits(oC, refC[0]) and rC["E"] == refC[1]["E"]
     assert gpu_ctx.memory_stats()["reserved"] == 0
 
 

@@ -303,6 +303,66 @@ def test_wavefunction_criterion_matches_oracle(gpu_ctx):
     assert rel(res["E"], ev["E"]) < 1e-9
 
 
+def test_wavefunction_criterion_mixed(gpu_ctx):
+    """Criterion (3.9) in a mixed solve applies to steps of the double phase
+    only: neither the float phase's last step nor the renormalisation at the
+    hand-over may stop it, so the double phase takes steps and the energy
+    matches the oracle's FP64 run under the same criterion."""
+    pb, psi0 = inputs.workload_small_2d()
+    tol = 1e-6
+    g, t, p = orc(pb)
+    ref = O.pcg(g, t, p, psi0, O.Options(stop_kind=gs.GS_STOP_WAVEFN, tol=tol))
+    ev = O.evaluate(g, t, p, ref.psi)
+    for sw in (1e-4, 1e-7):
+        psi, res = gpu_ctx.solve(pb, psi0, gs.default_options(stop_kind=gs.GS_STOP_WAVEFN, tol=tol,
+                                                              precision=gs.GS_MIXED, switch_resid=sw))
+        print(f"[wavefn mixed sw={sw}] gpu it={res['iters']} (fp32 {res['iters_fp32']}) "
+              f"dphi={res['dphi_inf']:.3e} E={res['E']!r} | oracle it={ref.iters} E={ev['E']!r}", flush=True)
+        assert res["status"] == 0 and ref.status == 0
+        assert res["iters"] > res["iters_fp32"] > 0
+        assert res["dphi_inf"] < tol
+        assert rel(res["E"], ev["E"]) < 1e-9
+
+
+def test_nyquist_readings_match_oracle(gpu_ctx):
+    """The two readings of the mode p = -N/2 in the odd symbols (option
+    nyquist_odd): Table 1's Case 1 at h = 1 (32^2 on [-16,16]^2), where they
+    differ by ~2e-6 in E. Each GPU reading matches the oracle's same reading
+    (residual stop 1e-10)."""
+    pb = inputs.Problem(dim=2, n=(32, 32), L=(16.0, 16.0), omega=0.1, gamma=0.3, c0=100.0, c1=1.0)
+    psi0 = inputs.initial_guess(pb, ("a", "a", "a"))
+    E = {}
+    for nyq in (gs.GS_NYQ_KEEP, gs.GS_NYQ_ZERO):
+        g = O.Grid(2, pb.n, pb.L, nyq)
+        _, t, p = orc(pb)
+        ref = O.pcg(g, t, p, psi0, O.Options(stop_kind=gs.GS_STOP_RESIDUAL, tol=1e-10))
+        ev = O.evaluate(g, t, p, ref.psi)
+        psi, res = gpu_ctx.solve(pb, psi0, gs.default_options(stop_kind=gs.GS_STOP_RESIDUAL, tol=1e-10,
+                                                              nyquist_odd=nyq))
+        print(f"[nyquist {nyq}] gpu E={res['E']!r} mu={res['mu']!r} it={res['iters']} | oracle E={ev['E']!r} "
+              f"mu={ev['mu']!r} it={ref.iters}", flush=True)
+        assert res["status"] == 0 and ref.status == 0
+        assert rel(res["E"], ev["E"]) < 1e-10
+        assert rel(res["mu"], ev["mu"]) < 1e-9
+        E[nyq] = res["E"]
+    assert abs(E[gs.GS_NYQ_KEEP] - E[gs.GS_NYQ_ZERO]) > 1e-7
+
+
+def test_existence_warning(gpu_ctx):
+    """A 3D solve with a weakly attractive c0 < 0 (outside the hypotheses of
+    the existence theorem of Sec. 2.1) that converges to the metastable
+    trapped state returns GS_WEXISTENCE with valid outputs, which match the
+    oracle."""
+    pb = inputs.Problem(dim=3, n=(16, 16, 16), L=(6.0, 6.0, 6.0), gamma=0.5, c0=-0.5, c1=0.2)
+    assert gs.existence_check(pb) == gs.GS_WEXISTENCE
+    psi0 = inputs.initial_guess(pb, ("a", "a", "a"))
+    ref, ev, psi, res = _solve_both(gpu_ctx, pb, psi0, gs.GS_STOP_RESIDUAL, 1e-10)
+    print(f"[existence] gpu rc={res['rc']} E={res['E']!r} | oracle E={ev['E']!r}", flush=True)
+    assert res["rc"] == gs.GS_WEXISTENCE and res["status"] == gs.GS_WEXISTENCE
+    assert ref.status == 0
+    assert rel(res["E"], ev["E"]) < 1e-10
+
+
 def test_solve_radix3_grid(gpu_ctx):
     """A 48^2 grid (a radix-3 pass in every transform): the small 2D workload's
     parameters, residual stop, against the oracle (naive DFT for length 48)."""
