@@ -280,6 +280,20 @@ int gs_interpolate(gs_ctx* ctx, const gs_grid* gc, const void* d_in, const gs_gr
 int gs_fft(gs_ctx* ctx, const gs_grid* g, int precision, int sign, const void* d_in,
            void* d_out, void* stream);
 
+/* gs_fft without device allocation, for callers that cannot allocate (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc). Same transform, arguments and result as gs_fft, from the same
+ * kernels and twiddle tables. Every buffer besides d_in and d_out (the slot
+ * descriptor, the solver state, the scratch fields and the twiddle tables)
+ * lives in one static device array per GPU, set up by gs_create; at most
+ * 2^18 points per component (GS_EINVAL beyond). The call only enqueues
+ * kernels on `stream` and returns (no allocation, no host synchronisation).
+ * The array is shared by every call on the GPU and keeps the last call's
+ * contents: calls that overlap in time on one GPU (other streams or threads)
+ * race and must be serialised by the caller. */
+int gs_fft_noalloc(gs_ctx* ctx, const gs_grid* g, int precision, int sign, const void* d_in, void* d_out,
+                   void* stream);
+
 /* H(Phi)Phi, the right-hand side of the Euler-Lagrange equations (2.6)-(2.8),
  * for the device field d_psi (taken as given, not normalised), written to
  * d_hpsi; when res is not NULL also E, its parts, mu, mu_l, N_l, the virial

@@ -17,6 +17,7 @@
 #include <deque>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <type_traits>
@@ -659,6 +660,22 @@ template <typename R> static auto& opplans(Ctx& cx);
 template <> auto& opplans<double>(Ctx& cx) { return cx.o64; }
 template <> auto& opplans<float>(Ctx& cx) { return cx.o32; }
 
+// Host image of the twiddle table of length N in type R: exp(-2 pi i m / N),
+// m < N, each entry rounded once from long double; a float table is followed
+// by the same table in double (the float passes form twiddle powers from it).
+template <typename R> static std::vector<unsigned char> twiddle_image(int N) {
+    const bool dbl_too = sizeof(R) == 4;
+    std::vector<unsigned char> img(sizeof(cpx<R>) * N + (dbl_too ? sizeof(cpx<double>) * N : 0));
+    cpx<R>* h = reinterpret_cast<cpx<R>*>(img.data());
+    cpx<double>* hd = reinterpret_cast<cpx<double>*>(img.data() + sizeof(cpx<R>) * N);
+    for (int m = 0; m < N; ++m) {
+        const long double ang = 2.0L * 3.14159265358979323846264338327950288L * (long double)m / (long double)N;
+        h[m] = cpx<R>{(R)cosl(ang), (R)(-sinl(ang))};
+        if (dbl_too) hd[m] = cpx<double>{(double)cosl(ang), (double)(-sinl(ang))};
+    }
+    return img;
+}
+
 template <typename R>
 static int get_twiddle(Ctx& cx, int N, const cpx<R>** out) {
     auto key = std::make_pair(N, (int)sizeof(R));
@@ -667,24 +684,13 @@ static int get_twiddle(Ctx& cx, int N, const cpx<R>** out) {
         *out = (const cpx<R>*)it->second;
         return GS_OK;
     }
-    // exp(-2 pi i m / N) in type R; a float table is followed by the same
-    // table in double (the float passes form twiddle powers from it)
-    const bool dbl_too = sizeof(R) == 4;
-    std::vector<cpx<R>> h(N);
-    std::vector<cpx<double>> hd(dbl_too ? N : 0);
-    for (int m = 0; m < N; ++m) {
-        const long double ang = 2.0L * 3.14159265358979323846264338327950288L * (long double)m / (long double)N;
-        h[m] = cpx<R>{(R)cosl(ang), (R)(-sinl(ang))};
-        if (dbl_too) hd[m] = cpx<double>{(double)cosl(ang), (double)(-sinl(ang))};
-    }
-    const size_t bytes = sizeof(cpx<R>) * N, dbytes = sizeof(cpx<double>) * hd.size();
+    const std::vector<unsigned char> img = twiddle_image<R>(N);
     void* d = nullptr;
-    if (hipMalloc(&d, bytes + dbytes) != hipSuccess) {
+    if (hipMalloc(&d, img.size()) != hipSuccess) {
         (void)hipGetLastError();
         return fail(GS_ENOMEM, "twiddle table allocation failed");
     }
-    HIPCHK(hipMemcpy(d, h.data(), bytes, hipMemcpyHostToDevice));
-    if (dbl_too) HIPCHK(hipMemcpy(static_cast<char*>(d) + bytes, hd.data(), dbytes, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(d, img.data(), img.size(), hipMemcpyHostToDevice));
     cx.twiddles[key] = d;
     *out = (const cpx<R>*)d;
     return GS_OK;
@@ -1355,6 +1361,34 @@ static int op_setup(OpPlan<R>& op, const Phys& ph, const void* x0, void* x1, hip
     return GS_OK;
 }
 
+// The passes of a forward (sign -1) or inverse (sign +1) transform of the
+// three components of X0 into X1 (scratch T0, T1) of the one-slot table T.
+template <typename R>
+static int fft_passes(const gs_grid* g, int sign, const Slot* T, const cpx<R>* const tw[3], hipStream_t s) {
+    const int Nx = g->n[0], Ny = g->n[1], Nz = g->dim == 3 ? g->n[2] : 1;
+    const double invM = 1.0 / ((double)Nx * Ny * Nz);
+    if (sign < 0) {
+        if (g->dim == 2) {
+            HIPCHK((launch_fwdT<R, R>(Nx, PRO_PLAIN, 0, T, 1, B_X0, B_T0, B_NONE, B_NONE, 1, Ny, 3, tw[0], s)));
+            HIPCHK((launch_fwdT<R, R>(Ny, PRO_PLAIN, 0, T, 1, B_T0, B_X1, B_NONE, B_NONE, 1, Nx, 3, tw[1], s)));
+        } else {
+            HIPCHK((launch_fwdT<R, R>(Nx, PRO_PLAIN, 0, T, 1, B_X0, B_T0, B_NONE, B_NONE, Nz, Ny, 3, tw[0], s)));
+            HIPCHK((launch_fwdT<R, R>(Ny, PRO_PLAIN, 0, T, 1, B_T0, B_T1, B_NONE, B_NONE, Nx, Nz, 3, tw[1], s)));
+            HIPCHK((launch_fwdT<R, R>(Nz, PRO_PLAIN, 0, T, 1, B_T1, B_X1, B_NONE, B_NONE, Ny, Nx, 3, tw[2], s)));
+        }
+    } else {
+        if (g->dim == 2) {
+            HIPCHK(launch_invT<R>(Ny, EPI_SCALE, T, 1, B_X0, B_NONE, B_T0, B_NONE, B_NONE, 1, Nx, 1.0, 0, 0, tw[1], s));
+            HIPCHK(launch_invT<R>(Nx, EPI_SCALE, T, 1, B_T0, B_NONE, B_X1, B_NONE, B_NONE, 1, Ny, invM, 0, 0, tw[0], s));
+        } else {
+            HIPCHK(launch_invT<R>(Nz, EPI_SCALE, T, 1, B_X0, B_NONE, B_T0, B_NONE, B_NONE, Ny, Nx, 1.0, 0, 0, tw[2], s));
+            HIPCHK(launch_invT<R>(Ny, EPI_SCALE, T, 1, B_T0, B_NONE, B_T1, B_NONE, B_NONE, Nx, Nz, 1.0, 0, 0, tw[1], s));
+            HIPCHK(launch_invT<R>(Nx, EPI_SCALE, T, 1, B_T1, B_NONE, B_X1, B_NONE, B_NONE, Nz, Ny, invM, 0, 0, tw[0], s));
+        }
+    }
+    return GS_OK;
+}
+
 template <typename R>
 static int fft_impl(Ctx& cx, const gs_grid* g, int sign, const cpx<R>* in, cpx<R>* out, hipStream_t s) {
     OpPlan<R>* op;
@@ -1363,29 +1397,108 @@ static int fft_impl(Ctx& cx, const gs_grid* g, int sign, const cpx<R>* in, cpx<R
     Phys ph;
     if ((rc = make_phys(g, nullptr, nullptr, &ph))) return rc;
     if ((rc = op_setup<R>(*op, ph, in, out, s))) return rc;
-    const int Nx = g->n[0], Ny = g->n[1], Nz = g->dim == 3 ? g->n[2] : 1;
-    const double invM = 1.0 / (double)op->M;
-    const Slot* T = op->d_tab;
-    if (sign < 0) {
-        if (g->dim == 2) {
-            HIPCHK((launch_fwdT<R, R>(Nx, PRO_PLAIN, 0, T, 1, B_X0, B_T0, B_NONE, B_NONE, 1, Ny, 3, op->tw[0], s)));
-            HIPCHK((launch_fwdT<R, R>(Ny, PRO_PLAIN, 0, T, 1, B_T0, B_X1, B_NONE, B_NONE, 1, Nx, 3, op->tw[1], s)));
-        } else {
-            HIPCHK((launch_fwdT<R, R>(Nx, PRO_PLAIN, 0, T, 1, B_X0, B_T0, B_NONE, B_NONE, Nz, Ny, 3, op->tw[0], s)));
-            HIPCHK((launch_fwdT<R, R>(Ny, PRO_PLAIN, 0, T, 1, B_T0, B_T1, B_NONE, B_NONE, Nx, Nz, 3, op->tw[1], s)));
-            HIPCHK((launch_fwdT<R, R>(Nz, PRO_PLAIN, 0, T, 1, B_T1, B_X1, B_NONE, B_NONE, Ny, Nx, 3, op->tw[2], s)));
-        }
-    } else {
-        if (g->dim == 2) {
-            HIPCHK(launch_invT<R>(Ny, EPI_SCALE, T, 1, B_X0, B_NONE, B_T0, B_NONE, B_NONE, 1, Nx, 1.0, 0, 0, op->tw[1], s));
-            HIPCHK(launch_invT<R>(Nx, EPI_SCALE, T, 1, B_T0, B_NONE, B_X1, B_NONE, B_NONE, 1, Ny, invM, 0, 0, op->tw[0], s));
-        } else {
-            HIPCHK(launch_invT<R>(Nz, EPI_SCALE, T, 1, B_X0, B_NONE, B_T0, B_NONE, B_NONE, Ny, Nx, 1.0, 0, 0, op->tw[2], s));
-            HIPCHK(launch_invT<R>(Ny, EPI_SCALE, T, 1, B_T0, B_NONE, B_T1, B_NONE, B_NONE, Nx, Nz, 1.0, 0, 0, op->tw[1], s));
-            HIPCHK(launch_invT<R>(Nx, EPI_SCALE, T, 1, B_T1, B_NONE, B_X1, B_NONE, B_NONE, Nz, Ny, invM, 0, 0, op->tw[0], s));
-        }
+    return fft_passes<R>(g, sign, op->d_tab, op->tw, s);
+}
+
+// ---------------------------------------------------------------------------
+// the transform without allocation (gs_fft_noalloc)
+// ---------------------------------------------------------------------------
+// Every buffer of a call lives in `scratch`, one file-scope device array per
+// GPU: the one-slot descriptor table and its solver state (header), the
+// twiddle tables of every supported line length in both precisions (written
+// once per device by gs_create), and the two scratch fields of a 3D transform
+// of up to NA_MAX_POINTS points per component. Host code addresses the array
+// only through the device pointer that hipGetSymbolAddress returned for the
+// device (na_base). Calls on one GPU share the array: calls that overlap in
+// time (different streams or host threads) race.
+constexpr long long NA_MAX_POINTS = 1LL << 18;
+constexpr size_t NA_HDR = 4096;            // descriptor at 0, solver state at 1024
+constexpr int NA_LENGTHS[] = {16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024};
+constexpr int NA_NLEN = (int)(sizeof(NA_LENGTHS) / sizeof(NA_LENGTHS[0]));
+constexpr size_t na_tw_bytes() {
+    size_t b = 0;
+    for (int k = 0; k < NA_NLEN; ++k)   // double table; float table with its double copy
+        b += (size_t)NA_LENGTHS[k] * (sizeof(cpx<double>) + sizeof(cpx<float>) + sizeof(cpx<double>));
+    return (b + 255) & ~(size_t)255;
+}
+constexpr size_t NA_FIELD = (size_t)3 * NA_MAX_POINTS * sizeof(cpx<double>);
+constexpr size_t NA_TW_OFF = NA_HDR, NA_T0_OFF = NA_TW_OFF + na_tw_bytes(), NA_T1_OFF = NA_T0_OFF + NA_FIELD;
+constexpr size_t NA_BYTES = NA_T1_OFF + NA_FIELD;
+static_assert(sizeof(Slot) <= 1024 && sizeof(SolveState) <= NA_HDR - 1024, "header layout");
+
+static __device__ __align__(256) unsigned char scratch[NA_BYTES];
+
+// offset of the twiddle table of length N and element size rsize in scratch
+static size_t na_tw_offset(int N, size_t rsize) {
+    size_t off = NA_TW_OFF;
+    for (int k = 0; k < NA_NLEN; ++k) {
+        const size_t n = (size_t)NA_LENGTHS[k];
+        if (NA_LENGTHS[k] == N) return rsize == sizeof(double) ? off : off + n * sizeof(cpx<double>);
+        off += n * (sizeof(cpx<double>) + sizeof(cpx<float>) + sizeof(cpx<double>));
     }
+    return 0;
+}
+
+constexpr int NA_MAX_DEV = 64;
+static std::mutex na_mutex;
+static unsigned char* na_base[NA_MAX_DEV] = {};
+
+// Once per device, with the device current: the device address of scratch and
+// the twiddle tables (the same images as the allocating path's tables).
+static int na_init(int device) {
+    if (device < 0 || device >= NA_MAX_DEV) return fail(GS_EINVAL, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lk(na_mutex);
+    if (na_base[device]) return GS_OK;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return fail(GS_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    unsigned char* base = static_cast<unsigned char*>(ptr);
+    for (int k = 0; k < NA_NLEN; ++k) {
+        const int N = NA_LENGTHS[k];
+        const std::vector<unsigned char> d = twiddle_image<double>(N), f = twiddle_image<float>(N);
+        HIPCHK(hipMemcpy(base + na_tw_offset(N, sizeof(double)), d.data(), d.size(), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(base + na_tw_offset(N, sizeof(float)), f.data(), f.size(), hipMemcpyHostToDevice));
+    }
+    na_base[device] = base;
     return GS_OK;
+}
+
+// writes the one-slot descriptor and a zeroed solver state (done = 0) on the
+// call's stream, so that no host staging buffer is involved
+__global__ void k_na_setup(Slot e, Slot* dst, SolveState* st) {
+    if (threadIdx.x == 0) {
+        *dst = e;
+        SolveState z;
+        memset(&z, 0, sizeof z);
+        *st = z;
+    }
+}
+
+template <typename R>
+static int fft_noalloc_impl(int device, const gs_grid* g, int sign, const cpx<R>* in, cpx<R>* out, hipStream_t s) {
+    unsigned char* base;
+    {
+        std::lock_guard<std::mutex> lk(na_mutex);
+        base = (device >= 0 && device < NA_MAX_DEV) ? na_base[device] : nullptr;
+    }
+    if (!base) return fail(GS_EDEVICE, "scratch of this device not set up (gs_create)");
+    Phys ph;
+    int rc;
+    if ((rc = make_phys(g, nullptr, nullptr, &ph))) return rc;
+    Slot e;
+    std::memset(&e, 0, sizeof e);
+    e.buf[B_X0] = const_cast<cpx<R>*>(in);
+    e.buf[B_X1] = out;
+    e.buf[B_T0] = base + NA_T0_OFF;
+    e.buf[B_T1] = base + NA_T1_OFF;
+    e.st = reinterpret_cast<SolveState*>(base + 1024);
+    e.p = ph;
+    Slot* T = reinterpret_cast<Slot*>(base);
+    GS_LAUNCH(k_na_setup, dim3(1), dim3(64), 0, s, e, T, e.st);
+    HIPCHK(hipGetLastError());
+    const cpx<R>* tw[3] = {};
+    for (int a = 0; a < g->dim; ++a) tw[a] = reinterpret_cast<const cpx<R>*>(base + na_tw_offset(g->n[a], sizeof(R)));
+    return fft_passes<R>(g, sign, T, tw, s);
 }
 
 // user potential of an operator-level call: a device copy owned by the plan's context
@@ -1515,6 +1628,8 @@ int gs_create(gs_ctx** out, int device) {
     size_t freeb = 0, total = 0;
     if (hipMemGetInfo(&freeb, &total) != hipSuccess) return fail(GS_EDEVICE, "hipMemGetInfo failed");
     cx.budget = (size_t)(0.9 * (double)freeb);
+    int rc = na_init(device);
+    if (rc) return rc;
     *out = c.release();
     return GS_OK;
 }
@@ -1719,6 +1834,22 @@ int gs_fft(gs_ctx* ctx, const gs_grid* g, int precision, int sign, const void* d
     if (precision == GS_FP32)
         return fft_impl<float>(ctx->impl, g, sign, (const cpx<float>*)d_in, (cpx<float>*)d_out, (hipStream_t)stream);
     return fail(GS_EINVAL, "precision must be GS_FP64 or GS_FP32");
+}
+
+int gs_fft_noalloc(gs_ctx* ctx, const gs_grid* g, int precision, int sign, const void* d_in, void* d_out,
+                   void* stream) {
+    if (!ctx || !d_in || !d_out) return fail(GS_EINVAL, "NULL argument");
+    int rc = check_grid(g);
+    if (rc) return rc;
+    if (npts(g) > NA_MAX_POINTS) return fail(GS_EINVAL, "gs_fft_noalloc: more than 2^18 points per component");
+    if (sign != -1 && sign != 1) return fail(GS_EINVAL, "sign must be -1 or +1");
+    if (precision != GS_FP64 && precision != GS_FP32) return fail(GS_EINVAL, "precision must be GS_FP64 or GS_FP32");
+    if (hipSetDevice(ctx->impl.device) != hipSuccess) return fail(GS_EDEVICE, "hipSetDevice failed");
+    if (precision == GS_FP64)
+        return fft_noalloc_impl<double>(ctx->impl.device, g, sign, (const cpx<double>*)d_in, (cpx<double>*)d_out,
+                                        (hipStream_t)stream);
+    return fft_noalloc_impl<float>(ctx->impl.device, g, sign, (const cpx<float>*)d_in, (cpx<float>*)d_out,
+                                   (hipStream_t)stream);
 }
 
 int gs_hamiltonian(gs_ctx* ctx, const gs_grid* g, const gs_trap* t, const gs_params* p, int precision,

@@ -27,7 +27,7 @@ EXPORTS = ("gs_create", "gs_destroy", "gs_default_options", "gs_footprint_bytes"
            "gs_solve_device", "gs_fft", "gs_hamiltonian", "gs_precondition", "gs_kernel_timer_start",
            "gs_kernel_timer_read", "gs_last_error", "gs_set_hbm_budget", "gs_memory_stats",
            "gs_batch_solve", "gs_submit", "gs_progress", "gs_poll", "gs_wait", "gs_cancel",
-           "gs_interpolate", "gs_existence_check")
+           "gs_interpolate", "gs_existence_check", "gs_fft_noalloc")
 
 KERNEL_KINDS = {"hl_fwd": 0, "hl_mid": 1, "hl_inv": 2, "pre_fwd": 3, "pre_mid": 4, "pre_inv": 5,
                 "eval": 6, "resid": 7, "lsred": 9, "hl_fwd2": 10, "hl_inv2": 11, "ctrl": 12}
@@ -108,6 +108,7 @@ def load():
     lib.gs_solve_device.argtypes = [vp, C.POINTER(gs_grid), C.POINTER(gs_trap), C.POINTER(gs_params),
                                     C.POINTER(gs_options), vp, vp, C.POINTER(gs_result), vp]
     lib.gs_fft.argtypes = [vp, C.POINTER(gs_grid), C.c_int, C.c_int, vp, vp, vp]
+    lib.gs_fft_noalloc.argtypes = [vp, C.POINTER(gs_grid), C.c_int, C.c_int, vp, vp, vp]
     lib.gs_hamiltonian.argtypes = [vp, C.POINTER(gs_grid), C.POINTER(gs_trap), C.POINTER(gs_params),
                                    C.c_int, vp, vp, C.POINTER(gs_result), vp]
     lib.gs_precondition.argtypes = [vp, C.POINTER(gs_grid), C.POINTER(gs_trap), C.POINTER(gs_params),
@@ -366,6 +367,12 @@ class Context:
     def fft(self, grid: gs_grid, x, out, sign: int, precision=GS_FP64, stream=None):
         _check(load().gs_fft(self._h, C.byref(grid), int(precision), int(sign),
                              C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out
+
+    def fft_noalloc(self, grid: gs_grid, x, out, sign: int, precision=GS_FP64, stream=None):
+        """gs_fft without device allocation (at most 2^18 points per component)."""
+        _check(load().gs_fft_noalloc(self._h, C.byref(grid), int(precision), int(sign),
+                                     C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()), _stream_ptr(stream)))
         return out
 
     def interpolate(self, grid_c: gs_grid, x, grid_f: gs_grid, out, stream=None):
