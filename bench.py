@@ -2,19 +2,25 @@
 """Benchmark: ground-state solves per second of the rotating SOC spin-1 PCG
 solver on one MI355X, mixed FP32->FP64 against plain FP64.
 
-Headline (`value`): a step is one batch of B independent solves of the 2D
-workload 256x256 on [-12,12]^2, harmonic trap, Omega = 0.6, SOC strength 1.0,
-c0 = 500, c1 = -2, initial guess ((x+iy) phi_a, phi_a, phi_a) + 1e-3 complex
-noise, seeds 2602 ... 2602+B-1, each to the energy criterion at the paper's
-default tolerance 1e-14 (Algorithm 1 with the line search of Algorithm 2). The
-guesses are resident in device memory before the timed region; the solves of
-a batch share every kernel launch (continuous batching). A mixed solve counts
-only when its energy agrees with the plain-FP64 solve of the same seed to
-|dE| / max(|E|, 1) < 1e-10.
+Headline (`value`): a continuous stream of solves of the 2D workload 256x256 on
+[-12,12]^2, harmonic trap, Omega = 0.6, SOC strength 1.0, c0 = 500, c1 = -2,
+initial guess ((x+iy) phi_a, phi_a, phi_a) + 1e-3 complex noise with seeds
+2602, 2603, ..., each to the energy criterion at the paper's default tolerance
+1e-14 (Algorithm 1 with the line search of Algorithm 2). `--inflight` requests
+(default 32) are on the device at all times: a new one is submitted as soon as
+one completes, and requests are admitted into freed slots at chunk boundaries
+(continuous batching). A step is `--inflight` completions; `--warmup` steps
+fill the pipeline untimed, then the clock runs over `--steps` steps. The same
+seeds are streamed in plain FP64 first: a mixed solve counts only when its
+energy agrees with the FP64 solve of the same seed to |dE| / max(|E|, 1) <
+1e-10, and the FP64 stream's rate gives the mixed-vs-FP64 factor. The guesses
+are resident in device memory before the clock starts.
 
-Further sections of the same JSON line: the same workload one solve at a time
-(latency), the 3D 128^3 cascadic-multigrid solve, the 96-solve parameter sweep
-of mixed grid sizes, and a served stream with Poisson arrivals.
+Other sections of the same JSON line: per-kernel timing at full slot
+occupancy (the roofline), the headline workload one solve at a time
+(latency), the 64^2 workload, the 3D 128^3 cascadic-multigrid solve, the
+96-solve parameter sweep, Table 2 by enumeration, a served stream with Poisson
+arrivals, and the CPU oracle on the host cores.
 
 Prints one JSON line; progress goes to stderr.
 """
@@ -40,8 +46,9 @@ TOL = 1e-14               # energy criterion (3.11), the paper's default toleran
 KERNEL_SOURCES = ("paper_2602_17950_amd/csrc/fft_kernels.hip", "paper_2602_17950_amd/csrc/pw_kernels.hip",
                   "paper_2602_17950_amd/csrc/device_common.h", "paper_2602_17950_amd/csrc/control.h",
                   "paper_2602_17950_amd/csrc/gs_internal.h")
-TRAFFIC_SUMMARY = "profiles/hbm_traffic_batch256_vortex.md"
-SECTIONS = ("batch", "single", "cm3d", "sweep", "table2", "serve")
+TRAFFIC_SUMMARY = "profiles/hbm_traffic_kernels256.md"
+SECTIONS = ("headline", "kernels", "single", "c1", "cm3d", "sweep", "table2", "serve")
+KINDS = ("hl_fwd", "hl_mid", "hl_inv", "pre_fwd", "pre_mid", "pre_inv", "resid", "lsred", "ctrl", "eval")
 # Table 2 (Example 3): lowest energy over the 1000 guess combinations of Sec. 4, and the
 # paper's CM-PCG CPU seconds for that one solve (a Xeon Gold 6248R, threads not stated;
 # context only)
@@ -57,9 +64,9 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary, or
-    None when the summary is missing or the kernel sources changed since."""
+def measured_traffic(label):
+    """HBM bytes per launch of kernel `label` from the committed counter summary,
+    or None when the summary is missing or the kernel sources changed since."""
     path = os.path.join(ROOT, TRAFFIC_SUMMARY)
     if not os.path.exists(path):
         return None
@@ -67,7 +74,7 @@ def measured_traffic(kernel):
     m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", txt)
     if not m or m.group(1) != kernel_source_hash():
         return None
-    m = re.search(rf"traffic_bytes_per_launch\[{re.escape(kernel)}\]:\s*([0-9.eE+]+)", txt)
+    m = re.search(rf"traffic_bytes_per_launch\[{re.escape(label)}\]:\s*([0-9.eE+]+)", txt)
     return float(m.group(1)) if m else None
 
 
@@ -87,35 +94,125 @@ def rel(a, b):
     return abs(a - b) / max(abs(b), 1.0)
 
 
-def cpu_baseline(pb, psi0, iters_per_solve, seconds):
-    """The FP64 CPU oracle on the same input, timed on the host cores for a
-    bounded number of PCG iterations and scaled to solves/s by the mean
-    iteration count of the GPU's FP64 solves of the workload."""
+def oracle_objects(O, pb):
+    return (O.Grid(pb.dim, pb.n, pb.L), O.Trap(pb.g, pb.q2, pb.q4), O.Params(pb.omega, pb.gamma, pb.c0, pb.c1))
+
+
+def oracle_rate(pb, psi0, threads, seconds, iters_per_solve):
+    """The oracle's PCG from psi0 for about `seconds` of host time on `threads`
+    threads: (seconds per iteration, iterations run, wall seconds)."""
     import oracle as O
-    threads = max(1, min(16, os.cpu_count() or 1))
     O.set_threads(threads)
-    g = O.Grid(pb.dim, pb.n, pb.L)
-    t = O.Trap(pb.g, pb.q2, pb.q4)
-    p = O.Params(pb.omega, pb.gamma, pb.c0, pb.c1)
+    g, t, p = oracle_objects(O, pb)
     probe = 3
     t0 = time.perf_counter()
     O.pcg(g, t, p, psi0, O.Options(tol=1e-12, max_iter=probe))
     t_probe = time.perf_counter() - t0
-    k = int(max(probe + 2, min(2000, seconds / max(t_probe / probe, 1e-6))))
+    k = int(max(probe + 2, min(iters_per_solve, seconds / max(t_probe / probe, 1e-6))))
     t0 = time.perf_counter()
     r = O.pcg(g, t, p, psi0, O.Options(tol=1e-12, max_iter=k))
     dt = time.perf_counter() - t0
     done = max(1, r.iters)
-    per_iter = dt / done
+    return dt / done, done, dt
+
+
+def cpu_baseline(pb, psi0, iters_per_solve, seconds):
+    """The FP64 CPU oracle on the same input, timed on all host cores for a
+    bounded number of PCG iterations of the headline solve and scaled to
+    solves/s by the mean iteration count of the GPU's FP64 solves of the
+    workload; the same on one thread."""
+    cores = os.cpu_count() or 1
+    per_all, done_all, dt_all = oracle_rate(pb, psi0, cores, seconds, iters_per_solve)
+    per_one, done_one, dt_one = oracle_rate(pb, psi0, 1, seconds / 2, iters_per_solve)
     return {
-        "value": 1.0 / (per_iter * iters_per_solve),
+        "value": 1.0 / (per_all * iters_per_solve),
         "unit": "solves/s",
-        "cores": threads,
+        "cores": cores,
         "kind": "oracle",
-        "sample": (f"first {done} PCG iterations of the seed-2602 256^2 solve on the host "
-                   f"({dt:.1f} s, {per_iter * 1e3:.1f} ms/iteration), scaled by the mean "
-                   f"{iters_per_solve:.0f} iterations of the GPU's FP64 solves of the workload"),
+        "sample": (f"first {done_all} PCG iterations of the seed-2602 256^2 solve on the host "
+                   f"({dt_all:.1f} s, {per_all * 1e3:.1f} ms/iteration on {cores} threads), scaled by the "
+                   f"mean {iters_per_solve:.0f} iterations of the GPU's FP64 solves of the workload"),
+        "one_thread": {"value": 1.0 / (per_one * iters_per_solve), "ms_per_iteration": per_one * 1e3,
+                       "iterations": done_one},
+        "ms_per_iteration": per_all * 1e3,
     }
+
+
+def run_stream(ctx, torch, probs, guesses, outs, opt, inflight, nwarm, ntimed):
+    """Continuous stream over probs in order with `inflight` requests on the
+    device at all times: nwarm + ntimed + inflight requests are submitted, one
+    as each earlier one completes. The clock runs from the nwarm-th completion
+    (after a device synchronisation) to the (nwarm + ntimed)-th, so the window
+    sees a full pipeline at both ends; the last requests then drain untimed.
+    Every submitted request completes, so both streams over the same seeds
+    hold results for every index. Returns (results by index, timed seconds,
+    indices completed in the timed window)."""
+    total = nwarm + ntimed + inflight
+    assert len(probs) >= total
+    tickets, done, order = {}, {}, []
+    nxt = 0
+    t0 = t1 = None
+
+    def fill():
+        nonlocal nxt
+        while len(tickets) < inflight and nxt < total:
+            tickets[nxt] = ctx.submit(probs[nxt], guesses[nxt], outs[nxt], opt)
+            nxt += 1
+
+    fill()
+    if nwarm == 0:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+    while len(done) < total:
+        ctx.progress(block=True)
+        for i in list(tickets):
+            r = ctx.poll(tickets[i])
+            if r is None:
+                continue
+            done[i] = r
+            del tickets[i]
+            order.append(i)
+            if t0 is None and len(order) == nwarm:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+            if t1 is None and len(order) == nwarm + ntimed:
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+        fill()
+    torch.cuda.synchronize()
+    return done, t1 - t0, order[nwarm:nwarm + ntimed]
+
+
+def kernel_table(ctx, torch, probs, guesses, outs, opt, iters):
+    """Average duration and algorithmic bytes per launch of every kernel kind
+    with all slots running every iteration (tol 0, `iters` iterations)."""
+    reqs = [(pb, g, o, opt, None) for pb, g, o in zip(probs, guesses, outs)]
+    ctx.batch_solve(reqs)   # warm
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    ctx.batch_solve(reqs)
+    torch.cuda.synchronize()
+    row = {"ms_per_iteration": (time.perf_counter() - t) / iters * 1e3, "kinds": {}}
+    for kind in KINDS:
+        ctx.kernel_timer_start(kind)
+        ctx.batch_solve(reqs)
+        torch.cuda.synchronize()
+        k = ctx.kernel_timer_read()
+        ctx.kernel_timer_start(None)
+        if k["launches"]:
+            avg_s = k["ms"] * 1e-3 / k["launches"]
+            bpl = k["bytes"] / k["launches"]
+            row["kinds"][kind] = {"avg_us": avg_s * 1e6, "launches": k["launches"], "bytes_per_launch": bpl,
+                                  "GBs": bpl / avg_s / 1e9, "per_iteration_us": k["ms"] * 1e3 / iters}
+    return row
+
+
+def roofline_of(row, kind, label, where):
+    k = row["kinds"][kind]
+    return {"bound": "hbm", "achieved": k["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": k["GBs"] / HBM_PEAK_GBS, "traffic": measured_traffic(label), "kernel": label,
+            "kind": kind, "launches": k["launches"], "avg_us": k["avg_us"],
+            "bytes_per_launch": k["bytes_per_launch"], "timed_in": where}
 
 
 class Batch:
@@ -133,24 +230,25 @@ class Batch:
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--batch", type=int, default=32, help="solves per headline step")
+    ap.add_argument("--steps", type=int, default=4, help="timed steps of --inflight completions")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed steps that fill the pipeline")
+    ap.add_argument("--inflight", type=int, default=32, help="requests on the device at once (headline)")
     ap.add_argument("--n", type=int, default=256, help="grid points per axis of the headline workload")
-    ap.add_argument("--kernel", default="pre_inv", help="kernel kind timed for the roofline")
+    ap.add_argument("--kernel-iters", type=int, default=128, help="iterations per kernel-table run")
     ap.add_argument("--mixed-dir", choices=("fp32", "fp64"), default="fp32",
                     help="direction precision of the double phase of mixed solves")
     ap.add_argument("--sections", default=",".join(SECTIONS))
-    ap.add_argument("--serve-requests", type=int, default=32)
-    ap.add_argument("--serve-load", type=float, default=0.5, help="arrival rate / measured sweep capacity")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--serve-requests", type=int, default=120)
+    ap.add_argument("--serve-capacity-requests", type=int, default=48)
+    ap.add_argument("--serve-loads", default="0.5,0.8", help="arrival rates / measured capacity of the served mix")
+    ap.add_argument("--cpu-seconds", type=float, default=16.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 1 GiB device to device (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: every solve of these workloads fits one MI355X "
-              "(use --gpus 1)", file=sys.stderr)
+        print("bench.py runs on one GPU only: every solve of these workloads fits one MI355X, and the "
+              "path shards over independent solves (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
     sections = [s for s in args.sections.split(",") if s]
     for s in sections:
@@ -171,91 +269,102 @@ def main():
         return
 
     ctx = gs.Context(0)
-    o64 = gs.default_options(precision=gs.GS_FP64, tol=TOL)
     mdir = gs.GS_FP32 if args.mixed_dir == "fp32" else gs.GS_FP64
+    o64 = gs.default_options(precision=gs.GS_FP64, tol=TOL)
     omx = gs.default_options(precision=gs.GS_MIXED, tol=TOL, dir_precision=mdir)
     line = {"metric": METRIC, "value": None, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "fp32->fp64", "data": "synthetic"}
+    B = args.inflight
 
     # ------------------------------------------------------------------ headline
-    seeds = [2602 + i for i in range(args.batch)]
-    work = [inputs.workload_vortex_2d(n=args.n, seed=s) for s in seeds]
-    head = Batch(torch, work)
-    res64 = None
-    if "batch" in sections:
-        for w in range(args.warmup):
-            t = time.perf_counter()
-            ctx.batch_solve(head.requests(omx))
-            log(f"warmup {w}: mixed batch of {args.batch} {time.perf_counter() - t:.3f}s")
-        # plain FP64 batch: reference energies and the roofline kernel's timing
-        ctx.kernel_timer_start(args.kernel)
+    total = B * (args.warmup + args.steps + 1)   # one more step drains after the clock stops
+    iters64 = None
+    if "headline" in sections:
+        seeds = [2602 + i for i in range(total)]
+        work = [inputs.workload_vortex_2d(n=args.n, seed=s) for s in seeds]
+        probs = [pb for pb, _ in work]
+        guesses = [torch.from_numpy(g).to("cuda") for _, g in work]
+        outs = [torch.empty_like(g) for g in guesses]
+        # a short warm run of both paths (class creation, first-launch costs)
+        for opt in (o64, omx):
+            ctx.batch_solve([(probs[i], guesses[i], outs[i], opt, None) for i in range(min(B, 4))])
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        res64 = ctx.batch_solve(head.requests(o64))
-        torch.cuda.synchronize()
-        T64 = time.perf_counter() - t0
-        kt = ctx.kernel_timer_read()
-        ctx.kernel_timer_start(None)
-        E64 = [r["E"] for r in res64]
-        log(f"fp64 batch: {T64:.3f}s iters mean {np.mean([r['iters'] for r in res64]):.0f} "
-            f"max {max(r['iters'] for r in res64)}")
-        # timed region: K mixed batches
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        resmx = []
-        for k in range(args.steps):
-            resmx.append(ctx.batch_solve(head.requests(omx)))
-        torch.cuda.synchronize()
-        Tmx = time.perf_counter() - t0
-        dEs = [rel(r["E"], e) for rs in resmx for r, e in zip(rs, E64)]
-        counted = sum(1 for d in dEs if d < DE_GATE)
-        lat = [r["wall_s"] for rs in resmx for r in rs]
-        itmx = [r["iters"] for rs in resmx for r in rs]
-        log(f"mixed batches: {Tmx:.3f}s for {args.steps} x {args.batch}; counted {counted}; "
-            f"iters mean {np.mean(itmx):.0f} max {max(itmx)}")
+        r64, T64, win64 = run_stream(ctx, torch, probs, guesses, outs, o64, B, B * args.warmup, B * args.steps)
+        log(f"fp64 stream: {len(win64)} solves in {T64:.2f}s ({len(win64) / T64:.2f}/s)")
+        rmx, Tmx, winmx = run_stream(ctx, torch, probs, guesses, outs, omx, B, B * args.warmup, B * args.steps)
+        dEs = {i: rel(rmx[i]["E"], r64[i]["E"]) for i in rmx}
+        counted = sum(1 for i in winmx if dEs[i] < DE_GATE)
+        lat = [rmx[i]["wall_s"] for i in winmx]
+        itmx = [rmx[i]["iters"] for i in winmx]
+        iters64 = float(np.mean([r64[i]["iters"] for i in win64]))
+        log(f"mixed stream: {len(winmx)} solves in {Tmx:.2f}s; counted {counted}; iters mean {np.mean(itmx):.0f}")
         line["value"] = counted / Tmx
         line["ms_per_step"] = Tmx / args.steps * 1e3
         line["p50_ms"] = percentile(lat, 50) * 1e3
         line["p99_ms"] = percentile(lat, 99) * 1e3
         line["iters_per_s"] = sum(itmx) / Tmx
-        line["batch"] = {
-            "solves_per_step": args.batch, "counted": counted, "solves": len(dEs),
-            "dE_rel_max": max(dEs), "dE_rel_median": float(np.median(dEs)),
-            "mixed_iters_mean": float(np.mean(itmx)), "mixed_iters_fp32_mean":
-                float(np.mean([r["iters_fp32"] for rs in resmx for r in rs])),
-            "fp64_solves_per_s": args.batch / T64, "fp64_iters_mean": float(np.mean([r["iters"] for r in res64])),
-            "fp64_p50_ms": percentile([r["wall_s"] for r in res64], 50) * 1e3,
-            "fp64_p99_ms": percentile([r["wall_s"] for r in res64], 99) * 1e3,
-            "speedup_mixed_vs_fp64": (len(dEs) / Tmx) / (args.batch / T64),
-            "latency_note": "p50/p99: submission to completion of each solve inside its batch",
+        fp64_rate = len(win64) / T64
+        line["headline"] = {
+            "inflight": B, "solves_timed": len(winmx), "counted": counted,
+            "solves_per_s_all": len(winmx) / Tmx,
+            "dE_rel_max": max(dEs[i] for i in winmx), "dE_rel_median": float(np.median([dEs[i] for i in winmx])),
+            "mixed_iters_mean": float(np.mean(itmx)),
+            "mixed_iters_fp32_mean": float(np.mean([rmx[i]["iters_fp32"] for i in winmx])),
+            "fp64_solves_per_s": fp64_rate, "fp64_iters_mean": iters64,
+            "fp64_iters_per_s": sum(r64[i]["iters"] for i in win64) / T64,
+            "fp64_p50_ms": percentile([r64[i]["wall_s"] for i in win64], 50) * 1e3,
+            "fp64_p99_ms": percentile([r64[i]["wall_s"] for i in win64], 99) * 1e3,
+            "speedup_counted": (counted / Tmx) / fp64_rate,
+            "speedup_all": (len(winmx) / Tmx) / fp64_rate,
+            "seeds": f"2602..{2601 + total} ({B} more than the warm-up and timed steps: the pipeline stays "
+                     "full until the clock stops)",
+            "latency_note": "p50/p99: submission to completion, over the timed window",
         }
-        roof = None
-        if kt["launches"] > 0 and kt["ms"] > 0:
-            avg_s = kt["ms"] * 1e-3 / kt["launches"]
-            bpl = kt["bytes"] / kt["launches"]
-            achieved = bpl / avg_s / 1e9
-            roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.kernel),
-                    "kernel": args.kernel, "launches": kt["launches"], "avg_us": avg_s * 1e6,
-                    "bytes_per_launch": bpl, "timed_in": f"FP64 batch of {args.batch} solves"}
-        line["roofline"] = roof
+        del guesses, outs
+
+    # ---------------------------------------------------------- kernels at full occupancy
+    if "kernels" in sections:
+        kw = [inputs.workload_vortex_2d(n=args.n, seed=2602 + i) for i in range(B)]
+        kb = Batch(torch, kw)
+        tab = {}
+        for name, opt in (("fp64", gs.default_options(precision=gs.GS_FP64, tol=0.0, max_iter=args.kernel_iters)),
+                          ("fp32", gs.default_options(precision=gs.GS_FP32, tol=0.0, max_iter=args.kernel_iters)),
+                          ("fp64_state_fp32_dir", gs.default_options(precision=gs.GS_FP64, tol=0.0,
+                                                                     max_iter=args.kernel_iters,
+                                                                     dir_precision=gs.GS_FP32))):
+            tab[name] = kernel_table(ctx, torch, kb.probs, kb.guess, kb.out, opt, args.kernel_iters)
+            log(f"kernels {name}: {tab[name]['ms_per_iteration']:.3f} ms/iteration; " + ", ".join(
+                f"{k} {v['avg_us']:.1f}us {v['GBs'] / 1e3:.2f}TB/s" for k, v in tab[name]["kinds"].items()))
+        line["kernels"] = {"slots": B, "iterations": args.kernel_iters, "grid": args.n, "table": tab,
+                           "note": ("every slot runs every iteration (tol 0): launches at full occupancy; "
+                                    "GBs = algorithmic bytes / average launch duration")}
+        # the headline's mixed solves spend almost all iterations in the double phase
+        # (double state, direction in the --mixed-dir precision): its dominant kernel
+        hx = "fp64_state_fp32_dir" if mdir == gs.GS_FP32 else "fp64"
+        dom = max(tab[hx]["kinds"], key=lambda k: tab[hx]["kinds"][k]["avg_us"])
+        line["roofline"] = roofline_of(tab[hx], dom, f"{hx}:{dom}",
+                                       f"double phase of the mixed path, {B} slots of {args.n}^2 at full occupancy")
+        d64 = max(tab["fp64"]["kinds"], key=lambda k: tab["fp64"]["kinds"][k]["avg_us"])
+        line["roofline_fp64"] = roofline_of(tab["fp64"], d64, f"fp64:{d64}",
+                                            f"plain FP64 path, {B} slots of {args.n}^2 at full occupancy")
+        del kb
 
     # ------------------------------------------------------------ single solve
     if "single" in sections:
-        pb, g0 = work[0]
+        pb, g0 = inputs.workload_vortex_2d(n=args.n, seed=2602)
         one = Batch(torch, [(pb, g0)])
         single = {}
         for name, opt in (("fp64", o64), ("mixed", omx)):
             ctx.solve_device(pb, one.guess[0], one.out[0], opt)   # warm
             lat, r = [], None
-            for k in range(args.steps):
+            for k in range(3):
                 t = time.perf_counter()
                 r = ctx.solve_device(pb, one.guess[0], one.out[0], opt)
                 lat.append(time.perf_counter() - t)
             single[name] = {"solves_per_s": len(lat) / sum(lat), "p50_ms": percentile(lat, 50) * 1e3,
-                            "p99_ms": percentile(lat, 99) * 1e3, "iters": r["iters"],
-                            "iters_fp32": r["iters_fp32"], "E": r["E"]}
+                            "iters": r["iters"], "iters_fp32": r["iters_fp32"], "E": r["E"],
+                            "ms_per_iteration": percentile(lat, 50) * 1e3 / r["iters"]}
             log(f"single {name}: {single[name]['p50_ms']:.1f} ms, iters {r['iters']}")
         single["dE_rel"] = rel(single["mixed"]["E"], single["fp64"]["E"])
         single["speedup_mixed_vs_fp64"] = single["mixed"]["solves_per_s"] / single["fp64"]["solves_per_s"]
@@ -263,6 +372,36 @@ def main():
         if line["value"] is None:   # headline section skipped
             line["value"] = single["mixed"]["solves_per_s"] if single["dE_rel"] < DE_GATE else 0.0
             line["ms_per_step"] = single["mixed"]["p50_ms"]
+
+    # --------------------------------------------------- 64^2 workload, GPU and oracle
+    if "c1" in sections:
+        pb, g0 = inputs.workload_small_2d()
+        one = Batch(torch, [(pb, g0)])
+        opt = gs.default_options(precision=gs.GS_FP64, tol=1e-12)
+        ctx.solve_device(pb, one.guess[0], one.out[0], opt)
+        lat = []
+        for k in range(5):
+            t = time.perf_counter()
+            r = ctx.solve_device(pb, one.guess[0], one.out[0], opt)
+            lat.append(time.perf_counter() - t)
+        c1 = {"gpu": {"solves_per_s": len(lat) / sum(lat), "p50_ms": percentile(lat, 50) * 1e3,
+                      "iters": r["iters"], "E": r["E"]},
+              "workload": ("2D 64x64 on [-8,8]^2, harmonic, Omega 0, SOC 0.5, c0 100, c1 -0.5, Gaussian "
+                           "guess, plain FP64, energy criterion 1e-12")}
+        if not args.no_cpu_baseline:
+            import oracle as O
+            g, t, p = oracle_objects(O, pb)
+            for name, th in (("oracle_all_cores", os.cpu_count() or 1), ("oracle_1_thread", 1)):
+                O.set_threads(th)
+                t0 = time.perf_counter()
+                ro = O.pcg(g, t, p, g0, O.Options(tol=1e-12))
+                dt = time.perf_counter() - t0
+                E = O.evaluate(g, t, p, ro.psi)["E"]
+                c1[name] = {"s": dt, "solves_per_s": 1.0 / dt, "iters": ro.iters, "threads": th, "E": E,
+                            "dE_rel_gpu": rel(r["E"], E)}
+            c1["gpu_vs_oracle_all_cores"] = c1["gpu"]["solves_per_s"] / c1["oracle_all_cores"]["solves_per_s"]
+        log(f"c1: gpu {c1['gpu']['p50_ms']:.1f} ms/solve")
+        line["c1"] = c1
 
     # ------------------------------------------------------- 3D multigrid solve
     if "cm3d" in sections:
@@ -275,6 +414,7 @@ def main():
         for name, prec in (("fp64", gs.GS_FP64), ("mixed", gs.GS_MIXED)):
             opt = gs.default_options(precision=prec, tol=1e-12, cm_levels=3,
                                      dir_precision=mdir if prec == gs.GS_MIXED else gs.GS_FP64)
+            ctx.solve_device(pb3, g3, out3, opt)   # warm
             t = time.perf_counter()
             r = ctx.solve_device(pb3, g3, out3, opt)
             cm[name] = {"s": time.perf_counter() - t, "E": r["E"], "mu": r["mu"], "iters_fine": r["iters"],
@@ -309,6 +449,7 @@ def main():
         d = [rel(a, b) for a, b in zip(E["mixed"], E["fp64"])]
         out["counted"] = sum(1 for x in d if x < DE_GATE)
         out["counted_solves_per_s"] = out["counted"] / out["mixed"]["s"]
+        out["speedup_counted"] = out["counted_solves_per_s"] / out["fp64"]["solves_per_s"]
         out["workload"] = ("96 2D solves, n uniform over {128,256,512}, L=16, Omega~U[0,0.9], SOC~U[0,2], "
                            "c0~U[100,2000], c1~U[-5,5], guesses over {(a,a,a),(b,a,a),(f,f,f)}, seed 17950; "
                            "energy criterion 1e-12, one batch")
@@ -321,7 +462,7 @@ def main():
     # ------------------------------------------------------------------ table2
     if "table2" in sections:
         tb = {"rows": {}}
-        total, nsolve, allmatch = 0.0, 0, True
+        total_s, nsolve, allmatch = 0.0, 0, True
         combos = list(itertools.product(GUESS_KINDS, repeat=3))
         opt = gs.default_options(precision=gs.GS_MIXED, dir_precision=mdir, tol=1e-14, cm_levels=3)
         for om, (E_paper, cpu_paper) in TABLE2.items():
@@ -338,7 +479,7 @@ def main():
             k = int(np.argmin(E))
             match = round(E[k], 4) == E_paper
             allmatch = allmatch and match
-            total += dt
+            total_s += dt
             nsolve += len(rs)
             tb["rows"][str(om)] = {"s": dt, "solves": len(rs), "E_lowest": E[k], "from": "".join(
                 c + " " for c in combos[k]).strip(), "paper_E": E_paper, "match_4_decimals": match,
@@ -349,7 +490,7 @@ def main():
             log(f"table2 omega={om}: {dt:.2f}s, lowest E {E[k]:.8f} ({'matches' if match else 'differs from'} "
                 f"{E_paper})")
             del guess, outs
-        tb.update({"s": total, "solves": nsolve, "solves_per_s": nsolve / total, "all_match": allmatch,
+        tb.update({"s": total_s, "solves": nsolve, "solves_per_s": nsolve / total_s, "all_match": allmatch,
                    "workload": ("Table 2 (Example 3): for Omega in {0.6,0.7,0.8,0.9}, the 1000 component-wise "
                                 "combinations of the ten guesses of Sec. 4 on [-12,12]^2 (gamma 0.3, c0 50, "
                                 "c1 0.5), each solved by CM-PCG 64^2->128^2->256^2, mixed precision, energy "
@@ -358,60 +499,71 @@ def main():
 
     # ------------------------------------------------------------------- serve
     if "serve" in sections:
-        rate = args.serve_load * (cap if cap else 1.0)
         spec = inputs.workload_serve(args.serve_requests)
         sv = Batch(torch, [(pb, inputs.initial_guess(pb, k)) for pb, k in spec])
-        rng = np.random.default_rng(2603)
-        arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(spec)))
         opt = gs.default_options(precision=gs.GS_MIXED, tol=1e-12, dir_precision=mdir)
+        # capacity of the served mix: its first requests submitted at once (closed loop)
+        ncap = min(len(spec), args.serve_capacity_requests)
+        t = time.perf_counter()
+        ctx.batch_solve([(sv.probs[i], sv.guess[i], sv.out[i], opt, None) for i in range(ncap)])
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        pending, tickets, done = 0, {}, {}
-        while len(done) < len(spec):
-            now = time.perf_counter() - t0
-            while pending < len(spec) and arrivals[pending] <= now:
-                i = pending
-                tickets[i] = ctx.submit(sv.probs[i], sv.guess[i], sv.out[i], opt)
-                pending += 1
-            for i in list(tickets):
-                r = ctx.poll(tickets[i])
-                if r is not None:
-                    done[i] = r
-                    del tickets[i]
-            if len(done) < len(spec):
-                if tickets:
-                    ctx.progress(block=pending >= len(spec) or arrivals[pending] > time.perf_counter() - t0 + 0.005)
-                else:
-                    time.sleep(max(0.0, min(0.01, arrivals[pending] - (time.perf_counter() - t0))))
-        T = time.perf_counter() - t0
-        lat = [done[i]["wall_s"] for i in range(len(spec))]
-        line["serve"] = {
-            "requests": len(spec), "arrival_rate_per_s": rate, "load_vs_sweep_capacity": args.serve_load,
-            "s": T, "solves_per_s": len(spec) / T, "p50_ms": percentile(lat, 50) * 1e3,
-            "p99_ms": percentile(lat, 99) * 1e3,
-            "warnings": sum(1 for r in done.values() if r["rc"] > 0),
-            "errors": sum(1 for r in done.values() if r["rc"] < 0),
-            "workload": ("Poisson arrivals (seed 2603); 75% 2D n in {128,256,512,1024} L=16, 25% 3D n in {64,96,128,192} "
-                         "L=10; parameters as the sweep; trap harmonic or 0.5r^2+0.01r^4; mixed precision, "
-                         "energy criterion 1e-12; latency = arrival to completion"),
-        }
-        log(f"serve: {T:.2f}s, p50 {line['serve']['p50_ms']:.0f} ms p99 {line['serve']['p99_ms']:.0f} ms")
+        cap_mix = ncap / (time.perf_counter() - t)
+        log(f"serve capacity: {cap_mix:.2f} solves/s over the first {ncap} requests at once")
+        serve = {"requests": len(spec), "capacity_solves_per_s": cap_mix, "capacity_requests": ncap, "loads": {}}
+        for load in [float(x) for x in args.serve_loads.split(",") if x]:
+            rate = load * cap_mix
+            rng = np.random.default_rng(2603)
+            arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(spec)))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pending, tickets, done = 0, {}, {}
+            while len(done) < len(spec):
+                now = time.perf_counter() - t0
+                while pending < len(spec) and arrivals[pending] <= now:
+                    tickets[pending] = ctx.submit(sv.probs[pending], sv.guess[pending], sv.out[pending], opt)
+                    pending += 1
+                for i in list(tickets):
+                    r = ctx.poll(tickets[i])
+                    if r is not None:
+                        done[i] = r
+                        del tickets[i]
+                if len(done) < len(spec):
+                    if tickets:
+                        ctx.progress(block=pending >= len(spec) or
+                                     arrivals[pending] > time.perf_counter() - t0 + 0.005)
+                    else:
+                        time.sleep(max(0.0, min(0.01, arrivals[pending] - (time.perf_counter() - t0))))
+            T = time.perf_counter() - t0
+            lat = [done[i]["wall_s"] for i in range(len(spec))]
+            serve["loads"][str(load)] = {
+                "arrival_rate_per_s": rate, "s": T, "solves_per_s": len(spec) / T,
+                "p50_ms": percentile(lat, 50) * 1e3, "p99_ms": percentile(lat, 99) * 1e3,
+                "warnings": sum(1 for r in done.values() if r["rc"] > 0),
+                "errors": sum(1 for r in done.values() if r["rc"] < 0)}
+            log(f"serve load {load}: {T:.2f}s, p50 {serve['loads'][str(load)]['p50_ms']:.0f} ms "
+                f"p99 {serve['loads'][str(load)]['p99_ms']:.0f} ms")
+        serve["workload"] = ("Poisson arrivals (seed 2603) at the given fractions of the served mix's capacity "
+                             "(its first requests run at once); 75% 2D n in {128,256,512,1024} L=16, 25% 3D n in "
+                             "{64,96,128,192} L=10; parameters as the sweep; trap harmonic or 0.5r^2+0.01r^4; "
+                             "mixed precision, energy criterion 1e-12; latency = arrival to completion")
+        line["serve"] = serve
         del sv
 
     cpu = None
-    if not args.no_cpu_baseline and res64 is not None:
+    if not args.no_cpu_baseline and iters64 is not None:
         log("cpu baseline: timing the oracle ...")
-        cpu = cpu_baseline(work[0][0], work[0][1], float(np.mean([r["iters"] for r in res64])), args.cpu_seconds)
+        pb, g0 = inputs.workload_vortex_2d(n=args.n, seed=2602)
+        cpu = cpu_baseline(pb, g0, iters64, args.cpu_seconds)
         log(f"cpu baseline: {cpu['value']:.4g} solves/s ({cpu['sample']})")
     line["cpu_baseline"] = cpu
     line["config"] = {
         "workload": (f"2D {args.n}x{args.n} on [-12,12]^2, harmonic trap, Omega=0.6, SOC 1.0, c0=500, c1=-2, "
-                     "guess ((x+iy)phi_a, phi_a, phi_a)+1e-3 noise; a step = one batch of "
-                     f"{args.batch} solves (noise seeds 2602..{2601 + args.batch}), energy criterion 1e-14; "
+                     "guess ((x+iy)phi_a, phi_a, phi_a)+1e-3 noise (one seed per solve from 2602); a continuous "
+                     f"stream with {B} solves in flight, a step = {B} completions; energy criterion 1e-14; "
                      "mixed FP32->FP64 PCG (double phase with a float search direction: "
                      f"{args.mixed_dir == 'fp32'}), counted against plain FP64 PCG of the same seed"),
         "mixed_dir_precision": args.mixed_dir,
-        "parallelism": "single GPU; the solves of a batch share every kernel launch",
+        "parallelism": "single GPU; the running solves of a grid class share every kernel launch",
     }
     line["kernel_source_sha256_16"] = kernel_source_hash()
     print(json.dumps(line), flush=True)
