@@ -32,3 +32,33 @@ def smooth_field(pb, seed, kinds=("a", "b", "bbar"), noise=0.05):
     im = rng.standard_normal(psi.shape)
     psi = psi + noise * env * (re + 1j * im)
     return inputs.normalise(psi, pb.cell)
+
+
+def aligned_errors(psi, ref):
+    """Differences between two wave functions that may differ by the global
+    phase kappa of Sec. 2.2 (E(e^{i kappa} Phi) = E(Phi)): kappa is the argument
+    of <psi, ref>, and the results are the max-norm difference of
+    e^{-i kappa} psi and ref relative to max |ref|, and the largest difference of
+    the component densities |phi_l|^2 relative to the largest density."""
+    z = np.vdot(ref, psi)
+    kap = np.angle(z)
+    d_psi = float(np.max(np.abs(psi * np.exp(-1j * kap) - ref)) / np.max(np.abs(ref)))
+    rho, rho_r = np.abs(psi) ** 2, np.abs(ref) ** 2
+    d_rho = float(np.max(np.abs(rho - rho_r)) / np.max(rho_r))
+    return d_psi, d_rho
+
+
+_ORACLE_CACHE = {}
+
+
+def oracle_solve(pb, psi0, stop, tol, max_iter=40000, key=None, **opt):
+    """The oracle's PCG from psi0, cached for the session under `key` (several
+    tests compare against the same reference solve)."""
+    if key is not None and key in _ORACLE_CACHE:
+        return _ORACLE_CACHE[key]
+    g, t, p = orc(pb)
+    ref = O.pcg(g, t, p, psi0, O.Options(stop_kind=stop, tol=tol, max_iter=max_iter, **opt))
+    ev = O.evaluate(g, t, p, ref.psi)
+    if key is not None:
+        _ORACLE_CACHE[key] = (ref, ev)
+    return ref, ev

@@ -3,8 +3,8 @@
 Every comparison uses the same seeded input on both sides. Floating-point
 tolerances: FP64 transforms and operators to 1e-12 (max-norm relative to the
 largest entry; the rounding of a radix FFT grows like eps log N), energies and
-chemical potentials of converged solves to 1e-10 relative; FP32 to 2e-5 for
-operators and 1e-6 relative for converged energies.
+chemical potentials of converged solves to 1e-10 relative; FP32 to 2e-6 for
+transforms and 1e-6 relative for converged energies.
 """
 import numpy as np
 import pytest
@@ -13,7 +13,7 @@ import torch
 import oracle as O
 from paper_2602_17950_amd import gs, inputs
 
-from helpers import orc, rel, smooth_field
+from helpers import aligned_errors, oracle_solve, orc, rel, smooth_field
 
 pytestmark = pytest.mark.gpu
 
@@ -58,7 +58,9 @@ def test_fft_forward_inverse(gpu_ctx, dim, n, L, prec):
     gg = gs.make_grid(dim, n, L)
     gpu_ctx.fft(gg, xd, yd, -1, prec)
     y = to_host(yd)
-    tol = 1e-12 if prec == gs.GS_FP64 else 2e-5
+    # FP32: rounding of a radix FFT with correctly rounded twiddles, ~eps log2 N
+    tol = 1e-12 if prec == gs.GS_FP64 else 2e-6
+    print(f"[fft] forward error {rel(y, ref):.2e}", flush=True)
     assert rel(y, ref) < tol
     # input untouched
     assert np.array_equal(to_host(xd), to_host(to_dev(x, prec)))
@@ -96,8 +98,10 @@ def test_hamiltonian_and_energy(gpu_ctx, k, prec):
     hd = torch.empty_like(psid)
     res = gpu_ctx.hamiltonian(pb, psid, hd, prec)
     H = to_host(hd)
-    op_tol = 1e-12 if prec == gs.GS_FP64 else 2e-5
-    sc_tol = 1e-12 if prec == gs.GS_FP64 else 2e-5
+    # FP32: the float rounding of the input and of the transforms, ~eps log2 N
+    op_tol = 1e-12 if prec == gs.GS_FP64 else 3e-6
+    sc_tol = 1e-12 if prec == gs.GS_FP64 else 3e-6
+    print(f"[ham] operator error {rel(H, H_ref):.2e}, E error {rel(res['E'], ev['E']):.2e}", flush=True)
     assert rel(H, H_ref) < op_tol
     for key in ("E", "mu", "e_kin", "e_pot", "e_rot", "e_spin", "e_soc", "virial", "resid_inf"):
         assert rel(res[key], ev[key]) < sc_tol, (key, res[key], ev[key])
@@ -134,7 +138,8 @@ def test_preconditioner(gpu_ctx, k, prec):
     ref = O.precond(g, t, p, psi, al, r)
     out = torch.empty_like(to_dev(psi, prec))
     gpu_ctx.precondition(pb, to_dev(psi, prec), to_dev(r, prec), out, prec)
-    tol = 1e-12 if prec == gs.GS_FP64 else 2e-5
+    tol = 1e-12 if prec == gs.GS_FP64 else 3e-6
+    print(f"[pre] error {rel(to_host(out), ref):.2e}", flush=True)
     assert rel(to_host(out), ref) < tol
 
 
@@ -167,22 +172,51 @@ def test_solve_small_2d_residual_stop(gpu_ctx):
     assert rel(res["E"], ev["E"]) < 1e-12
     assert rel(res["mu"], ev["mu"]) < 1e-10
     assert res["resid_inf"] < 1e-11
-    rho_g = np.abs(psi) ** 2
-    rho_o = np.abs(ref.psi) ** 2
-    assert rel(rho_g, rho_o) < 1e-8
+    d_psi, d_rho = aligned_errors(psi, ref.psi)
+    print(f"[solve small res] aligned psi {d_psi:.2e} rho {d_rho:.2e}", flush=True)
+    assert d_psi < 1e-11 and d_rho < 1e-11
 
 
 def test_solve_rotating_vortex_2d(gpu_ctx):
     """Rotating SOC case with a vortex guess (the 256^2 workload's parameters on
-    64^2). The iteration converges slowly here, so both sides stop on the
-    residual: at 1e-9 the energy is within ~1e-15 of its limit."""
+    64^2), both sides stopping on the residual at 1e-12, where mu and the
+    densities (first order in the state error) are converged to ~1e-12: E and
+    mu to 1e-10 relative, the wave function after aligning the global phase
+    kappa (Sec. 2.2), and the component densities."""
     pb, psi0 = inputs.workload_vortex_2d(n=64)
-    ref, ev, psi, res = _solve_both(gpu_ctx, pb, psi0, gs.GS_STOP_RESIDUAL, 1e-9)
-    print(f"[solve vortex64] gpu E={res['E']!r} it={res['iters']} | oracle E={ev['E']!r} it={ref.iters}")
+    ref, ev = oracle_solve(pb, psi0, gs.GS_STOP_RESIDUAL, 1e-12, key="vortex64_r12")
+    psi, res = gpu_ctx.solve(pb, psi0, gs.default_options(stop_kind=gs.GS_STOP_RESIDUAL, tol=1e-12,
+                                                          max_iter=40000))
+    d_psi, d_rho = aligned_errors(psi, ref.psi)
+    print(f"[solve vortex64 r12] gpu E={res['E']!r} mu={res['mu']!r} it={res['iters']} | oracle E={ev['E']!r} "
+          f"mu={ev['mu']!r} it={ref.iters} | aligned psi {d_psi:.2e} rho {d_rho:.2e}", flush=True)
     assert res["status"] == 0 and ref.status == 0
-    assert rel(res["E"], ev["E"]) < 1e-10
-    assert rel(res["mu"], ev["mu"]) < 1e-8
+    assert rel(res["E"], ev["E"]) < 1e-12
+    assert rel(res["mu"], ev["mu"]) < 1e-10
+    for a, b in zip(res["mu_comp"], ev["mu_comp"]):
+        assert rel(a, b) < 1e-10
+    assert d_psi < 1e-10 and d_rho < 1e-10   # measured 2e-13 and 5e-14 (the same 7135 steps)
     assert res["e_soc"] <= 0.0
+
+
+def test_solve_fp32_matches_oracle(gpu_ctx):
+    """Pure FP32 solves (fields, transforms and the pointwise work in float,
+    reductions in double) against the oracle's FP64 minimiser: energy to 1e-6
+    relative, the FP32 bar."""
+    for which in ("small2d", "vortex64"):
+        if which == "small2d":
+            pb, psi0 = inputs.workload_small_2d()
+            ref, ev = oracle_solve(pb, psi0, gs.GS_STOP_RESIDUAL, 1e-11, key="small2d_r11")
+        else:
+            pb, psi0 = inputs.workload_vortex_2d(n=64)
+            ref, ev = oracle_solve(pb, psi0, gs.GS_STOP_RESIDUAL, 1e-12, key="vortex64_r12")
+        psi, res = gpu_ctx.solve(pb, psi0, gs.default_options(precision=gs.GS_FP32, tol=1e-9))
+        d_psi, d_rho = aligned_errors(psi, ref.psi)
+        print(f"[fp32 {which}] gpu E={res['E']!r} mu={res['mu']!r} it={res['iters']} rc={res['rc']} | oracle "
+              f"E={ev['E']!r} mu={ev['mu']!r} | E rel {rel(res['E'], ev['E']):.2e} mu rel "
+              f"{rel(res['mu'], ev['mu']):.2e} aligned psi {d_psi:.2e} rho {d_rho:.2e}", flush=True)
+        assert res["rc"] >= 0 and res["iters_fp32"] == res["iters"]
+        assert rel(res["E"], ev["E"]) < 1e-6
 
 
 def test_solve_mixed_matches_fp64(gpu_ctx):
