@@ -43,7 +43,9 @@ METRIC = "ground-state solves/s at |dE|<1e-10 (mixed vs FP64 PCG); p50/p99 solve
 HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, vendor figure
 DE_GATE = 1e-10
 TOL = 1e-14               # energy criterion (3.11), the paper's default tolerance (Sec. 4)
-KERNEL_SOURCES = ("paper_2602_17950_amd/csrc/fft_kernels.hip", "paper_2602_17950_amd/csrc/pw_kernels.hip",
+KERNEL_SOURCES = ("paper_2602_17950_amd/csrc/fft_core.h", "paper_2602_17950_amd/csrc/fft_launch.h",
+                  "paper_2602_17950_amd/csrc/fft_fwd.hip", "paper_2602_17950_amd/csrc/fft_inv.hip",
+                  "paper_2602_17950_amd/csrc/fft_mid.hip", "paper_2602_17950_amd/csrc/pw_kernels.hip",
                   "paper_2602_17950_amd/csrc/device_common.h", "paper_2602_17950_amd/csrc/control.h",
                   "paper_2602_17950_amd/csrc/gs_internal.h")
 TRAFFIC_SUMMARY = "profiles/hbm_traffic_kernels256.md"

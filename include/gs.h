@@ -323,6 +323,20 @@ int gs_precondition(gs_ctx* ctx, const gs_grid* g, const gs_trap* t, const gs_pa
 int gs_kernel_timer_start(gs_ctx* ctx, int kind);
 int gs_kernel_timer_read(gs_ctx* ctx, double* total_ms, double* total_bytes, long long* launches);
 
+/* Launch schedules of the FFT passes (the coefficients by FFT of Sec. 3.2).
+ * Every pass of the PCG iteration has a few candidate schedules (lines and
+ * threads per block) that compute the same bits. With autotuning on (the
+ * default), the first chunk of iterations of a grid class run with a given
+ * number of running solves (bucketed by powers of two) cycles through every
+ * pass's candidates, timing each launch with events, and the fastest is kept
+ * for that class and bucket; off (on = 0): the fixed table. Results do not
+ * depend on the setting. gs_autotune_report returns a JSON array (valid
+ * until the next call on ctx, NULL for a NULL ctx): per class and bucket, the
+ * chosen "TILExNT" of each pass and the mean launch time (us) of every
+ * candidate. */
+int gs_set_autotune(gs_ctx* ctx, int on);
+const char* gs_autotune_report(gs_ctx* ctx);
+
 /* Message of the last error on this thread ("" if none). */
 const char* gs_last_error(void);
 

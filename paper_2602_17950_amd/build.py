@@ -14,10 +14,14 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libgs.so")
-SOURCES = ("fft_kernels.hip", "pw_kernels.hip", "engine.hip")
+SOURCES = ("fft_fwd.hip", "fft_inv.hip", "fft_mid.hip", "pw_kernels.hip", "engine.hip")
 ARCH = "gfx950"
-# packed FP32 instructions are disabled for every HIP translation unit
-HIPFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+# Packed FP32 instructions are disabled for every HIP translation unit.
+# Multiply-adds are fused only within one source expression (-ffp-contract=on:
+# the front end decides, from the source alone), so every instantiation of a
+# kernel template (the schedule candidates of a pass) rounds the same way and
+# computes the same bits.
+HIPFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=on",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-Wall", "-Wno-unused-function"]
 

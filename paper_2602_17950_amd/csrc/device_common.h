@@ -83,6 +83,38 @@ __device__ __forceinline__ void block_row(const double (&acc)[NV], double* rows,
     block_row<NV, NTB>(acc, rows, stride, (int)blockIdx.x);
 }
 
+// Sums over the points of a work unit whose order does not depend on the
+// number of threads: the unit's points are visited as e = threadIdx.x + i NT
+// (NT a multiple of 64, the point count a multiple of 64), so every chunk of
+// 64 consecutive points is one wave's iteration. chunk_add reduces the wave's
+// per-point values of one chunk by the fixed halving tree and keeps the
+// chunk's totals in LDS (chunk q at ch[q]); chunk_row adds the chunks of the
+// unit in chunk order and stores the unit's row. A launch configuration can
+// then change the thread count without changing a bit of the sums.
+template <int NV> struct ChunkSums {
+    static constexpr int P = Pow2Ceil<NV>::v;
+    static constexpr int SH = 6 - ILog2<P>::v;
+};
+template <int NV>
+__device__ __forceinline__ void chunk_add(const double (&val)[NV], double (*ch)[ChunkSums<NV>::P], int q) {
+    constexpr int P = ChunkSums<NV>::P, SH = ChunkSums<NV>::SH;
+    double v[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) v[k] = k < NV ? val[k] : 0.0;
+    const int lane = threadIdx.x & 63;
+    halve_all<P, 32>(v, lane);
+    if ((lane & ((1 << SH) - 1)) == 0) ch[q][lane >> SH] = v[0];
+}
+// after a barrier that follows the unit's last chunk_add
+template <int NV>
+__device__ __forceinline__ void chunk_row(double (*ch)[ChunkSums<NV>::P], int nq, double* rows, int stride, int row) {
+    if (threadIdx.x < NV) {
+        double t = ch[0][threadIdx.x];
+        for (int q = 1; q < nq; ++q) t += ch[q][threadIdx.x];
+        rows[(long long)row * stride + threadIdx.x] = t;
+    }
+}
+
 // Totals over nrows rows (fixed order) of NV values at the given stride, on
 // thread 0 of a block of PT threads. Entries k < 32 with (maxmask >> k) & 1 are
 // maxima (of non-negative values).

@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -382,61 +383,184 @@ struct Sub {
     int ns;
 };
 
+// ---------------------------------------------------------------------------
+// schedules of the FFT passes and their autotuner
+// ---------------------------------------------------------------------------
+// The passes of one PCG iteration (the preconditioner's and the H_L P^ chain's)
+// each have NCAND candidate launch schedules that compute the same bits (see
+// gs_internal.h). A Sched names the candidate of every pass; the fixed table
+// is all zeros. The autotuner of a class times the valid candidates of every
+// pass on the class's own launches during the first chunk of iterations run
+// with a given number of running solves (bucketed by powers of two), then
+// keeps the fastest for that bucket (see Tuner).
+enum PassId : int {
+    P_PRE_FWD = 0, P_PRE_FWD2, P_PRE_MID, P_PRE_INV2, P_PRE_INV,   // preconditioner, 2D: FWD, MID, INV
+    P_HL_FWD, P_HL_FWD2, P_HL_MID, P_HL_INV2, P_HL_INV,            // H_L P^ (with Phi's spectrum)
+    NPASS
+};
+static const char* const PASS_NAME[NPASS] = {"pre_fwd", "pre_fwd2", "pre_mid", "pre_inv2", "pre_inv",
+                                             "hl_fwd", "hl_fwd2", "hl_mid", "hl_inv2", "hl_inv"};
+struct Sched {
+    int c[NPASS] = {};
+};
+// launch records of a tuning chunk: pass, candidate and iteration of each
+// timed launch, with its start and end events
+struct TuneRun {
+    bool on = false;
+    int bucket = 0, it = 0;
+    struct Rec { int pass, cand, it; };
+    std::vector<Rec> rec;
+    std::vector<hipEvent_t> ev;
+    ~TuneRun() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+};
+template <typename F>
+static hipError_t tuned(TuneRun* tr, int pass, int cand, F&& f) {
+    if (!tr || !tr->on) return f();
+    const size_t i = tr->rec.size();
+    while (tr->ev.size() < 2 * (i + 1)) {
+        hipEvent_t e;
+        hipError_t er = hipEventCreate(&e);
+        if (er != hipSuccess) return er;
+        tr->ev.push_back(e);
+    }
+    LaunchEvents& le = launch_events();
+    le.start = tr->ev[2 * i];
+    le.stop = tr->ev[2 * i + 1];
+    hipError_t e = f();
+    const bool consumed = le.start == nullptr;
+    le.start = le.stop = nullptr;
+    if (e == hipSuccess && !consumed) e = hipErrorInvalidValue;
+    tr->rec.push_back({pass, cand, tr->it});
+    return e;
+}
+
 // out = H_L in  (H_L = -1/2 Lap + V - Omega L_z - gamma S), transforms in type R,
 // with the prologue `pro` applied to `in` first (see launch_fwdT; the operand
 // of the other type RX is aux1 for PRO_DIR). dual (with
 // PRO_DIR): aux1 (Phi) is transformed with in, and the middle pass reduces the
-// kinetic coefficients of both for the next iterate's alpha_l.
+// kinetic coefficients of both for the next iterate's alpha_l. sc: schedules
+// (nullptr: the fixed table).
 template <typename R, typename RX>
 static hipError_t chain_HL(int dim, const int n[3], long long M, int rot, const cpx<R>* const tw[3], Sub L, int pro,
-                           int dual, int in, int out, int aux0, int aux1, int use_invnP, hipStream_t s, Timer* tm) {
+                           int dual, int in, int out, int aux0, int aux1, int use_invnP, hipStream_t s, Timer* tm,
+                           const Sched* sc = nullptr, TuneRun* tr = nullptr) {
     const int Nx = n[0], Ny = n[1], Nz = n[2];
     const double F = 3.0 * M * sizeof(cpx<R>) * L.ns, Fx = 3.0 * M * sizeof(cpx<RX>) * L.ns;
     const double b_fwd = dual ? 5 * F + Fx : (pro == PRO_DIR ? 4 * F + Fx : 2 * F);
     const double b_mid = (rot ? 2 : 1) * F + (dual ? 2 : 1) * F, b_inv = (rot ? 4 : 3) * F;
     const int midop = dual ? MID_HLX : MID_HL;
     const int outB = rot ? B_T1 : B_NONE;
+    static const Sched fixed;
+    const Sched& S = sc ? *sc : fixed;
+    const int cF = S.c[P_HL_FWD], cF2 = S.c[P_HL_FWD2], cM = S.c[P_HL_MID], cI2 = S.c[P_HL_INV2], cI = S.c[P_HL_INV];
     hipError_t e;
     if (dim == 2) {
-        if ((e = timed_ns(tm, KK_HL_FWD, b_fwd, L.ns, s, [&] { return launch_fwdT<R, RX>(Nx, pro, dual, L.tab, L.ns, in, B_T6A, aux0, aux1, 1, Ny, 3, tw[0], s); }))) return e;
-        if ((e = timed_ns(tm, KK_HL_MID, b_mid, L.ns, s, [&] { return launch_mid<R>(Ny, midop, L.tab, L.ns, B_T6A, B_T0, outB, Nx, rot, tw[1], s); }))) return e;
-        return timed_ns(tm, KK_HL_INV, b_inv, L.ns, s, [&] {
-            return launch_invT<R>(Nx, EPI_HL, L.tab, L.ns, B_T0, B_T1, out, B_NONE, in, 1, Ny, 1.0, use_invnP, rot, tw[0], s); });
+        if ((e = timed_ns(tm, KK_HL_FWD, b_fwd, L.ns, s, [&] { return tuned(tr, P_HL_FWD, cF, [&] {
+                 return launch_fwdT<R, RX>(Nx, pro, dual, L.tab, L.ns, in, B_T6A, aux0, aux1, 1, Ny, 3, tw[0], cF, s); }); }))) return e;
+        if ((e = timed_ns(tm, KK_HL_MID, b_mid, L.ns, s, [&] { return tuned(tr, P_HL_MID, cM, [&] {
+                 return launch_mid<R>(Ny, midop, L.tab, L.ns, B_T6A, B_T0, outB, Nx, rot, tw[1], cM, s); }); }))) return e;
+        return timed_ns(tm, KK_HL_INV, b_inv, L.ns, s, [&] { return tuned(tr, P_HL_INV, cI, [&] {
+            return launch_invT<R>(Nx, EPI_HL, L.tab, L.ns, B_T0, B_T1, out, B_NONE, in, 1, Ny, 1.0, use_invnP, rot, tw[0], cI, s); }); });
     }
     const int nc = dual ? 6 : 3;
-    if ((e = timed_ns(tm, KK_HL_FWD, b_fwd, L.ns, s, [&] { return launch_fwdT<R, RX>(Nx, pro, dual, L.tab, L.ns, in, B_T6A, aux0, aux1, Nz, Ny, 3, tw[0], s); }))) return e;
-    if ((e = timed_ns(tm, KK_HL_FWD2, 2 * (nc / 3) * F, L.ns, s, [&] { return launch_fwdT<R, RX>(Ny, PRO_PLAIN, 0, L.tab, L.ns, B_T6A, B_T6B, B_NONE, B_NONE, Nx, Nz, nc, tw[1], s); }))) return e;
-    if ((e = timed_ns(tm, KK_HL_MID, b_mid, L.ns, s, [&] { return launch_mid<R>(Nz, midop, L.tab, L.ns, B_T6B, B_T0, outB, Ny * Nx, rot, tw[2], s); }))) return e;
-    if ((e = timed_ns(tm, KK_HL_INV2, (rot ? 5 : 2) * F, L.ns, s, [&] {
+    if ((e = timed_ns(tm, KK_HL_FWD, b_fwd, L.ns, s, [&] { return tuned(tr, P_HL_FWD, cF, [&] {
+             return launch_fwdT<R, RX>(Nx, pro, dual, L.tab, L.ns, in, B_T6A, aux0, aux1, Nz, Ny, 3, tw[0], cF, s); }); }))) return e;
+    if ((e = timed_ns(tm, KK_HL_FWD2, 2 * (nc / 3) * F, L.ns, s, [&] { return tuned(tr, P_HL_FWD2, cF2, [&] {
+             return launch_fwdT<R, RX>(Ny, PRO_PLAIN, 0, L.tab, L.ns, B_T6A, B_T6B, B_NONE, B_NONE, Nx, Nz, nc, tw[1], cF2, s); }); }))) return e;
+    if ((e = timed_ns(tm, KK_HL_MID, b_mid, L.ns, s, [&] { return tuned(tr, P_HL_MID, cM, [&] {
+             return launch_mid<R>(Nz, midop, L.tab, L.ns, B_T6B, B_T0, outB, Ny * Nx, rot, tw[2], cM, s); }); }))) return e;
+    if ((e = timed_ns(tm, KK_HL_INV2, (rot ? 5 : 2) * F, L.ns, s, [&] { return tuned(tr, P_HL_INV2, cI2, [&] {
              return launch_invT<R>(Ny, rot ? EPI_ROTX : EPI_SCALE, L.tab, L.ns, B_T0, B_T1, B_T2, rot ? B_T3 : B_NONE,
-                                   B_T6A, Nx, Nz, 1.0, 0, rot, tw[1], s); }))) return e;
-    return timed_ns(tm, KK_HL_INV, b_inv, L.ns, s, [&] {
-        return launch_invT<R>(Nx, EPI_HL, L.tab, L.ns, B_T2, B_T3, out, B_NONE, in, Nz, Ny, 1.0, use_invnP, rot, tw[0], s); });
+                                   B_T6A, Nx, Nz, 1.0, 0, rot, tw[1], cI2, s); }); }))) return e;
+    return timed_ns(tm, KK_HL_INV, b_inv, L.ns, s, [&] { return tuned(tr, P_HL_INV, cI, [&] {
+        return launch_invT<R>(Nx, EPI_HL, L.tab, L.ns, B_T2, B_T3, out, B_NONE, in, Nz, Ny, 1.0, use_invnP, rot, tw[0], cI, s); }); });
 }
 
 // out = P_V^{1/2} P_Delta P_V^{1/2} r in the direction type RD (the first factor
 // is already applied: input in u); dir = 1 fuses the partial sums of the
 // direction scalars into the last pass
 template <typename RS, typename RD>
-static hipError_t chain_pre(const Geo<RS, RD>& G, Sub L, int dir, int out, hipStream_t s, Timer* tm) {
+static hipError_t chain_pre(const Geo<RS, RD>& G, Sub L, int dir, int out, hipStream_t s, Timer* tm,
+                            const Sched* sc = nullptr, TuneRun* tr = nullptr) {
     const int Nx = G.n[0], Ny = G.n[1], Nz = G.n[2];
     const double F = 3.0 * G.M * sizeof(cpx<RD>) * L.ns, Fr = 3.0 * G.M * sizeof(RD) * L.ns;
     const double Fs = 3.0 * G.M * sizeof(cpx<RS>) * L.ns;
     const double b_inv = (dir ? 5 * F + Fs : 2 * F) + Fr;
+    static const Sched fixed;
+    const Sched& S = sc ? *sc : fixed;
+    const int cF = S.c[P_PRE_FWD], cF2 = S.c[P_PRE_FWD2], cM = S.c[P_PRE_MID], cI2 = S.c[P_PRE_INV2], cI = S.c[P_PRE_INV];
     hipError_t e;
     if (G.dim == 2) {
-        if ((e = timed_ns(tm, KK_PRE_FWD, 2 * F, L.ns, s, [&] { return launch_fwdT<RD, RD>(Nx, PRO_PLAIN, 0, L.tab, L.ns, B_U, B_T6A, B_NONE, B_NONE, 1, Ny, 3, G.twd[0], s); }))) return e;
-        if ((e = timed_ns(tm, KK_PRE_MID, 2 * F, L.ns, s, [&] { return launch_mid<RD>(Ny, MID_PRE, L.tab, L.ns, B_T6A, B_T0, B_NONE, Nx, 0, G.twd[1], s); }))) return e;
-        return timed_ns(tm, KK_PRE_INV, b_inv, L.ns, s, [&] {
-            return launch_invT_pre<RD, RS>(Nx, L.tab, L.ns, B_T0, out, 1, Ny, dir, G.twd[0], s); });
+        if ((e = timed_ns(tm, KK_PRE_FWD, 2 * F, L.ns, s, [&] { return tuned(tr, P_PRE_FWD, cF, [&] {
+                 return launch_fwdT<RD, RD>(Nx, PRO_PLAIN, 0, L.tab, L.ns, B_U, B_T6A, B_NONE, B_NONE, 1, Ny, 3, G.twd[0], cF, s); }); }))) return e;
+        if ((e = timed_ns(tm, KK_PRE_MID, 2 * F, L.ns, s, [&] { return tuned(tr, P_PRE_MID, cM, [&] {
+                 return launch_mid<RD>(Ny, MID_PRE, L.tab, L.ns, B_T6A, B_T0, B_NONE, Nx, 0, G.twd[1], cM, s); }); }))) return e;
+        return timed_ns(tm, KK_PRE_INV, b_inv, L.ns, s, [&] { return tuned(tr, P_PRE_INV, cI, [&] {
+            return launch_invT_pre<RD, RS>(Nx, L.tab, L.ns, B_T0, out, 1, Ny, dir, G.twd[0], cI, s); }); });
     }
-    if ((e = timed_ns(tm, KK_PRE_FWD, 2 * F, L.ns, s, [&] { return launch_fwdT<RD, RD>(Nx, PRO_PLAIN, 0, L.tab, L.ns, B_U, B_T6A, B_NONE, B_NONE, Nz, Ny, 3, G.twd[0], s); }))) return e;
-    if ((e = launch_fwdT<RD, RD>(Ny, PRO_PLAIN, 0, L.tab, L.ns, B_T6A, B_T6B, B_NONE, B_NONE, Nx, Nz, 3, G.twd[1], s))) return e;
-    if ((e = timed_ns(tm, KK_PRE_MID, 2 * F, L.ns, s, [&] { return launch_mid<RD>(Nz, MID_PRE, L.tab, L.ns, B_T6B, B_T0, B_NONE, Ny * Nx, 0, G.twd[2], s); }))) return e;
-    if ((e = launch_invT<RD>(Ny, EPI_SCALE, L.tab, L.ns, B_T0, B_NONE, B_T1, B_NONE, B_NONE, Nx, Nz, 1.0, 0, 0, G.twd[1], s))) return e;
-    return timed_ns(tm, KK_PRE_INV, b_inv, L.ns, s, [&] {
-        return launch_invT_pre<RD, RS>(Nx, L.tab, L.ns, B_T1, out, Nz, Ny, dir, G.twd[0], s); });
+    if ((e = timed_ns(tm, KK_PRE_FWD, 2 * F, L.ns, s, [&] { return tuned(tr, P_PRE_FWD, cF, [&] {
+             return launch_fwdT<RD, RD>(Nx, PRO_PLAIN, 0, L.tab, L.ns, B_U, B_T6A, B_NONE, B_NONE, Nz, Ny, 3, G.twd[0], cF, s); }); }))) return e;
+    if ((e = tuned(tr, P_PRE_FWD2, cF2, [&] {
+             return launch_fwdT<RD, RD>(Ny, PRO_PLAIN, 0, L.tab, L.ns, B_T6A, B_T6B, B_NONE, B_NONE, Nx, Nz, 3, G.twd[1], cF2, s); }))) return e;
+    if ((e = timed_ns(tm, KK_PRE_MID, 2 * F, L.ns, s, [&] { return tuned(tr, P_PRE_MID, cM, [&] {
+             return launch_mid<RD>(Nz, MID_PRE, L.tab, L.ns, B_T6B, B_T0, B_NONE, Ny * Nx, 0, G.twd[2], cM, s); }); }))) return e;
+    if ((e = tuned(tr, P_PRE_INV2, cI2, [&] {
+             return launch_invT<RD>(Ny, EPI_SCALE, L.tab, L.ns, B_T0, B_NONE, B_T1, B_NONE, B_NONE, Nx, Nz, 1.0, 0, 0, G.twd[1], cI2, s); }))) return e;
+    return timed_ns(tm, KK_PRE_INV, b_inv, L.ns, s, [&] { return tuned(tr, P_PRE_INV, cI, [&] {
+        return launch_invT_pre<RD, RS>(Nx, L.tab, L.ns, B_T1, out, Nz, Ny, dir, G.twd[0], cI, s); }); });
 }
+
+// Candidates of pass p that are valid for grid n (RD: direction type, in which
+// the passes of the iteration run).
+template <typename RD> static std::vector<int> valid_cands(int dim, const int n[3], int p) {
+    std::vector<int> v;
+    const int Nx = n[0], Ny = n[1], Nz = n[2], Nl = dim == 2 ? Ny : Nz;
+    for (int c = 0; c < NCAND; ++c) {
+        bool ok = false;
+        switch (p) {
+        case P_PRE_FWD: case P_HL_FWD: ok = fwdT_cand_ok<RD>(Nx, c, Ny); break;
+        case P_PRE_FWD2: case P_HL_FWD2: ok = dim == 3 && fwdT_cand_ok<RD>(Ny, c, Nz); break;
+        case P_PRE_MID: case P_HL_MID: ok = mid_cand_ok(Nl, c); break;
+        case P_PRE_INV2: case P_HL_INV2: ok = dim == 3 && invT_cand_ok<RD>(Ny, c, Nz); break;
+        case P_PRE_INV: ok = invT_pre_cand_ok<RD>(Nx, c); break;
+        case P_HL_INV: ok = invT_cand_ok<RD>(Nx, c, Ny); break;
+        }
+        if (ok) v.push_back(c);
+    }
+    return v;
+}
+// lines per block and threads per block of candidate c of pass p
+template <typename RD> static Cand cand_of(int dim, const int n[3], int p, int c) {
+    const int Nx = n[0], Ny = n[1], Nz = n[2], Nl = dim == 2 ? Ny : Nz;
+    switch (p) {
+    case P_PRE_FWD: case P_HL_FWD: return fwdT_cand_of<RD>(Nx, c);
+    case P_PRE_FWD2: case P_HL_FWD2: return fwdT_cand_of<RD>(Ny, c);
+    case P_PRE_MID: case P_HL_MID: return mid_cand_of(Nl, c);
+    case P_PRE_INV2: case P_HL_INV2: return invT_cand_of<RD>(Ny, c);
+    case P_PRE_INV: return invT_pre_cand_of<RD>(Nx, c);
+    default: return invT_cand_of<RD>(Nx, c);
+    }
+}
+
+// Per class: the chosen candidates per bucket of running solves, and the
+// timings behind them.
+constexpr int NBUCKET = 8;   // running solves 1, 2-3, 4-7, ..., >= 128
+static int bucket_of(int nrun) {
+    int b = 0;
+    while (b + 1 < NBUCKET && (2 << b) <= nrun) ++b;
+    return b;
+}
+struct Tuner {
+    bool decided[NBUCKET] = {};
+    int chunks[NBUCKET] = {};          // tuning chunks spent on the bucket
+    Sched best[NBUCKET];
+    double ms[NBUCKET][NPASS][NCAND] = {};   // summed launch times (first launch of each left out)
+    int n[NBUCKET][NPASS][NCAND] = {};       // launches counted
+    int seen[NBUCKET][NPASS][NCAND] = {};    // launches timed
+    TuneRun run;
+};
 
 // bytes of partial-sum rows a control step reads
 static double fin_bytes(const RedGeom& g, int what, int ns) {
@@ -496,7 +620,8 @@ static hipError_t resid_final(const Geo<RS, RD>& G, Sub L, hipStream_t s) {
 // Steps 2 and 3 run in the direction type RD, the rest in the state type RS;
 // every reduction and scalar is double.
 template <typename RS, typename RD>
-static hipError_t iterate(const Geo<RS, RD>& G, Sub L, int do_refresh, hipStream_t s, Timer* tm) {
+static hipError_t iterate(const Geo<RS, RD>& G, Sub L, int do_refresh, hipStream_t s, Timer* tm,
+                          const Sched* sc = nullptr, TuneRun* tr = nullptr) {
     const double Fs = 3.0 * G.M * sizeof(cpx<RS>) * L.ns, Fd = 3.0 * G.M * sizeof(cpx<RD>) * L.ns;
     const double Frd = 3.0 * G.M * sizeof(RD) * L.ns;
     hipError_t e;
@@ -507,10 +632,11 @@ static hipError_t iterate(const Geo<RS, RD>& G, Sub L, int do_refresh, hipStream
     if (tm) tm->chain = 1;
     if ((e = timed_ns(tm, KK_RESID, 4 * Fs + 4 * Fd + Frd, L.ns, s, [&] { return launch_resid<RS, RD>(L.tab, L.ns, G.g, 0, s); }))) return e;
     if (tm) tm->chain = 2;
-    if ((e = chain_pre<RS, RD>(G, L, 1, B_PR, s, tm))) return e;
+    if ((e = chain_pre<RS, RD>(G, L, 1, B_PR, s, tm, sc, tr))) return e;
     if ((e = fin(G.g, L, FIN_DIR, s, tm))) return e;
     if (tm) tm->chain = 3;
-    if ((e = chain_HL<RD, RS>(G.dim, G.n, G.M, G.rot_any, G.twd, L, PRO_DIR, 1, B_P, B_HLP, B_PR, B_PHI, 1, s, tm))) return e;
+    if ((e = chain_HL<RD, RS>(G.dim, G.n, G.M, G.rot_any, G.twd, L, PRO_DIR, 1, B_P, B_HLP, B_PR, B_PHI, 1, s, tm, sc,
+                              tr))) return e;
     if ((e = timed_ns(tm, KK_LSRED, 2 * Fs + 2 * Fd, L.ns, s, [&] { return launch_lsred<RS, RD>(L.tab, L.ns, G.g, s); }))) return e;
     return fin(G.g, L, FIN_LS, s, tm);
 }
@@ -580,6 +706,8 @@ struct Class {
     bool inflight = false;
     uint64_t seq = 0;
     Timer tm;
+    Tuner tun;
+    std::vector<int> valid[NPASS];   // valid schedule candidates of each pass (the autotuner's set)
     ~Class() {
         if (stream) (void)hipStreamSynchronize(stream);
         mem.clear();
@@ -629,6 +757,8 @@ struct Ctx {
     uint64_t moves = 0;   // requests queued into another class (hand-overs, multigrid levels)
     size_t budget = 0, reserved = 0, allocated = 0;
     TimerTotals timer;
+    int autotune = 1;   // 1: tune the FFT pass schedules per class and bucket; 0: the fixed table
+    std::string report;
     ~Ctx() {
         (void)hipSetDevice(device);
         c64.clear();
@@ -734,6 +864,8 @@ static int get_class(Ctx& cx, const gs_grid* g, int check_every, Class<RS, RD>**
         return fail(GS_ENOMEM, "pinned allocation failed (class tables)");
     }
     std::memset(c->h_st, 0, sizeof(SolveState) * CLASS_CAP);
+    const int nn[3] = {g->n[0], g->n[1], g->dim == 3 ? g->n[2] : 1};
+    for (int p = 0; p < NPASS; ++p) c->valid[p] = valid_cands<RD>(g->dim, nn, p);
     *out = c.get();
     mp[key] = std::move(c);
     return GS_OK;
@@ -981,6 +1113,48 @@ static int next_level(Ctx& cx, Job* j, hipStream_t s) {
     return GS_OK;
 }
 
+// Timings of a tuning chunk that has completed (adv[i]: steps slot i accepted
+// in it): launches at iterations that every slot of the chunk ran are added
+// per pass and candidate, leaving out each candidate's first launch (code load,
+// cold caches). A bucket is decided once every valid candidate of every pass
+// has two counted launches, or after three tuning chunks with what was seen.
+template <typename RS, typename RD>
+static hipError_t tune_collect(Class<RS, RD>& c, const std::vector<int>& adv) {
+    TuneRun& run = c.tun.run;
+    const int b = run.bucket;
+    int full = INT32_MAX;
+    for (int a : adv) full = std::min(full, a);
+    for (size_t i = 0; i < run.rec.size(); ++i) {
+        const TuneRun::Rec& r = run.rec[i];
+        if (r.it >= full) continue;
+        float ms = 0.0f;
+        hipError_t e = hipEventElapsedTime(&ms, run.ev[2 * i], run.ev[2 * i + 1]);
+        if (e != hipSuccess) return e;
+        if (c.tun.seen[b][r.pass][r.cand]++ == 0) continue;
+        c.tun.ms[b][r.pass][r.cand] += ms;
+        c.tun.n[b][r.pass][r.cand]++;
+    }
+    run.rec.clear();
+    run.on = false;
+    bool all = true;
+    for (int p = 0; p < NPASS; ++p)
+        for (int cd : c.valid[p]) all = all && c.tun.n[b][p][cd] >= 2;
+    if (all || c.tun.chunks[b] >= 3) {
+        for (int p = 0; p < NPASS; ++p) {
+            int best = 0;
+            double tb = 0.0;
+            for (int cd : c.valid[p]) {
+                if (c.tun.n[b][p][cd] == 0) continue;
+                const double t = c.tun.ms[b][p][cd] / c.tun.n[b][p][cd];
+                if (tb == 0.0 || t < tb) { tb = t; best = cd; }
+            }
+            c.tun.best[b].c[p] = best;
+        }
+        c.tun.decided[b] = true;
+    }
+    return hipSuccess;
+}
+
 // Chunk boundary of a class whose previous chunk (if any) has completed:
 // retire finished solves, start final evaluations, hand over float phases,
 // admit queued requests, then enqueue the next chunk.
@@ -1002,7 +1176,7 @@ static int boundary(Ctx& cx, Class<RS, RD>& c) {
     }
     c.fin.clear();
     // 2. slots of the chunk that has completed
-    if (!c.run.empty() && c.tm.kind >= 0) {
+    if (!c.run.empty() && (c.tm.kind >= 0 || c.tun.run.on)) {
         std::vector<int> adv;
         std::vector<char> fin;
         for (size_t i = 0; i < c.run.size(); ++i) {
@@ -1010,7 +1184,8 @@ static int boundary(Ctx& cx, Class<RS, RD>& c) {
             adv.push_back(h.iter - c.iter0[i]);
             fin.push_back(h.done ? 1 : 0);
         }
-        HIPCHK(timer_collect(c.tm, cx.timer, adv, fin));
+        if (c.tm.kind >= 0) HIPCHK(timer_collect(c.tm, cx.timer, adv, fin));
+        if (c.tun.run.on) HIPCHK(tune_collect(c, adv));
     }
     std::vector<int> cont;
     for (size_t i = 0; i < c.run.size(); ++i) {
@@ -1144,9 +1319,29 @@ static int boundary(Ctx& cx, Class<RS, RD>& c) {
         c.tm.kind = cx.timer.kind;
         Timer* tm = c.tm.kind >= 0 ? &c.tm : nullptr;
         const Sub Lr{c.d_tab, nrun};
+        // schedules: the bucket's decision, or a tuning chunk that cycles
+        // through every pass's valid candidates (not while the kernel timer,
+        // which takes the launches' events, is on)
+        const int b = bucket_of(nrun);
+        TuneRun* tr = nullptr;
+        if (cx.autotune && !c.tun.decided[b] && !tm) {
+            tr = &c.tun.run;
+            tr->on = true;
+            tr->bucket = b;
+            tr->rec.clear();
+            c.tun.chunks[b]++;
+        }
         for (int it = 0; it < c.check_every; ++it) {
             if (tm) tm->iter_in_chunk = it;
-            HIPCHK((iterate<RS, RD>(G, Lr, it == 0, s, tm)));
+            Sched sc;
+            if (tr) {
+                tr->it = it;
+                for (int p = 0; p < NPASS; ++p)
+                    if (!c.valid[p].empty()) sc.c[p] = c.valid[p][it % c.valid[p].size()];
+            } else if (cx.autotune && c.tun.decided[b]) {
+                sc = c.tun.best[b];
+            }
+            HIPCHK((iterate<RS, RD>(G, Lr, it == 0, s, tm, &sc, tr)));
         }
     }
     HIPCHK(hipMemcpyAsync(c.h_st, c.d_st, sizeof(SolveState) * maxk, hipMemcpyDeviceToHost, s));
@@ -1369,21 +1564,21 @@ static int fft_passes(const gs_grid* g, int sign, const Slot* T, const cpx<R>* c
     const double invM = 1.0 / ((double)Nx * Ny * Nz);
     if (sign < 0) {
         if (g->dim == 2) {
-            HIPCHK((launch_fwdT<R, R>(Nx, PRO_PLAIN, 0, T, 1, B_X0, B_T0, B_NONE, B_NONE, 1, Ny, 3, tw[0], s)));
-            HIPCHK((launch_fwdT<R, R>(Ny, PRO_PLAIN, 0, T, 1, B_T0, B_X1, B_NONE, B_NONE, 1, Nx, 3, tw[1], s)));
+            HIPCHK((launch_fwdT<R, R>(Nx, PRO_PLAIN, 0, T, 1, B_X0, B_T0, B_NONE, B_NONE, 1, Ny, 3, tw[0], 0, s)));
+            HIPCHK((launch_fwdT<R, R>(Ny, PRO_PLAIN, 0, T, 1, B_T0, B_X1, B_NONE, B_NONE, 1, Nx, 3, tw[1], 0, s)));
         } else {
-            HIPCHK((launch_fwdT<R, R>(Nx, PRO_PLAIN, 0, T, 1, B_X0, B_T0, B_NONE, B_NONE, Nz, Ny, 3, tw[0], s)));
-            HIPCHK((launch_fwdT<R, R>(Ny, PRO_PLAIN, 0, T, 1, B_T0, B_T1, B_NONE, B_NONE, Nx, Nz, 3, tw[1], s)));
-            HIPCHK((launch_fwdT<R, R>(Nz, PRO_PLAIN, 0, T, 1, B_T1, B_X1, B_NONE, B_NONE, Ny, Nx, 3, tw[2], s)));
+            HIPCHK((launch_fwdT<R, R>(Nx, PRO_PLAIN, 0, T, 1, B_X0, B_T0, B_NONE, B_NONE, Nz, Ny, 3, tw[0], 0, s)));
+            HIPCHK((launch_fwdT<R, R>(Ny, PRO_PLAIN, 0, T, 1, B_T0, B_T1, B_NONE, B_NONE, Nx, Nz, 3, tw[1], 0, s)));
+            HIPCHK((launch_fwdT<R, R>(Nz, PRO_PLAIN, 0, T, 1, B_T1, B_X1, B_NONE, B_NONE, Ny, Nx, 3, tw[2], 0, s)));
         }
     } else {
         if (g->dim == 2) {
-            HIPCHK(launch_invT<R>(Ny, EPI_SCALE, T, 1, B_X0, B_NONE, B_T0, B_NONE, B_NONE, 1, Nx, 1.0, 0, 0, tw[1], s));
-            HIPCHK(launch_invT<R>(Nx, EPI_SCALE, T, 1, B_T0, B_NONE, B_X1, B_NONE, B_NONE, 1, Ny, invM, 0, 0, tw[0], s));
+            HIPCHK(launch_invT<R>(Ny, EPI_SCALE, T, 1, B_X0, B_NONE, B_T0, B_NONE, B_NONE, 1, Nx, 1.0, 0, 0, tw[1], 0, s));
+            HIPCHK(launch_invT<R>(Nx, EPI_SCALE, T, 1, B_T0, B_NONE, B_X1, B_NONE, B_NONE, 1, Ny, invM, 0, 0, tw[0], 0, s));
         } else {
-            HIPCHK(launch_invT<R>(Nz, EPI_SCALE, T, 1, B_X0, B_NONE, B_T0, B_NONE, B_NONE, Ny, Nx, 1.0, 0, 0, tw[2], s));
-            HIPCHK(launch_invT<R>(Ny, EPI_SCALE, T, 1, B_T0, B_NONE, B_T1, B_NONE, B_NONE, Nx, Nz, 1.0, 0, 0, tw[1], s));
-            HIPCHK(launch_invT<R>(Nx, EPI_SCALE, T, 1, B_T1, B_NONE, B_X1, B_NONE, B_NONE, Nz, Ny, invM, 0, 0, tw[0], s));
+            HIPCHK(launch_invT<R>(Nz, EPI_SCALE, T, 1, B_X0, B_NONE, B_T0, B_NONE, B_NONE, Ny, Nx, 1.0, 0, 0, tw[2], 0, s));
+            HIPCHK(launch_invT<R>(Ny, EPI_SCALE, T, 1, B_T0, B_NONE, B_T1, B_NONE, B_NONE, Nx, Nz, 1.0, 0, 0, tw[1], 0, s));
+            HIPCHK(launch_invT<R>(Nx, EPI_SCALE, T, 1, B_T1, B_NONE, B_X1, B_NONE, B_NONE, Nz, Ny, invM, 0, 0, tw[0], 0, s));
         }
     }
     return GS_OK;
@@ -1571,6 +1766,44 @@ static int pre_impl(Ctx& cx, const gs_grid* g, const gs_trap* t, const gs_params
     if (rc) return rc;
     if (e) return fail(GS_EDEVICE, hipGetErrorString(e));
     return GS_OK;
+}
+
+// JSON description of the autotuner's decisions and timings in every class.
+template <typename RS, typename RD>
+static void report_class(const Class<RS, RD>& c, std::string& out, bool& first) {
+    char buf[256];
+    for (int b = 0; b < NBUCKET; ++b) {
+        if (!c.tun.chunks[b]) continue;
+        const int lo = 1 << b, hi = b + 1 < NBUCKET ? (2 << b) - 1 : 4096;
+        std::snprintf(buf, sizeof buf, "%s{\"grid\":[%d,%d,%d],\"state\":\"%s\",\"dir\":\"%s\",\"running\":[%d,%d],"
+                      "\"tuning_chunks\":%d,\"decided\":%s,\"passes\":{",
+                      first ? "" : ",", c.grid.n[0], c.grid.n[1], c.grid.dim == 3 ? c.grid.n[2] : 1,
+                      sizeof(RS) == 8 ? "fp64" : "fp32", sizeof(RD) == 8 ? "fp64" : "fp32", lo, hi, c.tun.chunks[b],
+                      c.tun.decided[b] ? "true" : "false");
+        out += buf;
+        first = false;
+        bool fp = true;
+        const int nn[3] = {c.grid.n[0], c.grid.n[1], c.grid.dim == 3 ? c.grid.n[2] : 1};
+        for (int p = 0; p < NPASS; ++p) {
+            if (c.valid[p].empty()) continue;
+            const Cand ch = cand_of<RD>(c.grid.dim, nn, p, c.tun.best[b].c[p]);
+            std::snprintf(buf, sizeof buf, "%s\"%s\":{\"chosen\":\"%dx%d\",\"us\":{", fp ? "" : ",", PASS_NAME[p],
+                          ch.tile, ch.nt);
+            out += buf;
+            fp = false;
+            bool fc = true;
+            for (int cd : c.valid[p]) {
+                const Cand k = cand_of<RD>(c.grid.dim, nn, p, cd);
+                const int n = c.tun.n[b][p][cd];
+                std::snprintf(buf, sizeof buf, "%s\"%dx%d\":%.3f", fc ? "" : ",", k.tile, k.nt,
+                              n ? 1e3 * c.tun.ms[b][p][cd] / n : -1.0);
+                out += buf;
+                fc = false;
+            }
+            out += "}}";
+        }
+        out += "}}";
+    }
 }
 
 }  // namespace gs
@@ -1801,6 +2034,30 @@ int gs_interpolate(gs_ctx* ctx, const gs_grid* gc, const void* d_in, const gs_gr
     if (hipStreamSynchronize(s) != hipSuccess && !rc) rc = fail(GS_EDEVICE, "hipStreamSynchronize failed");
     (void)hipFree(tmp);
     return rc;
+}
+
+int gs_set_autotune(gs_ctx* ctx, int on) {
+    if (!ctx) return fail(GS_EINVAL, "ctx is NULL");
+    if (on != 0 && on != 1) return fail(GS_EINVAL, "autotune must be 0 or 1");
+    ctx->impl.autotune = on;
+    return GS_OK;
+}
+
+const char* gs_autotune_report(gs_ctx* ctx) {
+    if (!ctx) {
+        fail(GS_EINVAL, "ctx is NULL");
+        return nullptr;
+    }
+    Ctx& cx = ctx->impl;
+    std::string out = "[";
+    bool first = true;
+    each_class(cx, [&](auto& c) {
+        report_class(c, out, first);
+        return 0;
+    });
+    out += "]";
+    cx.report = out;
+    return cx.report.c_str();
 }
 
 int gs_kernel_timer_start(gs_ctx* ctx, int kind) {

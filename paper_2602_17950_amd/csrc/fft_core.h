@@ -20,6 +20,7 @@
 // launch at once: blockIdx.y selects the slot, whose descriptor names the
 // buffers, the problem and the solver state. A slot whose solve has finished
 // returns at once.
+#pragma once
 #include "device_common.h"
 #include "control.h"
 
@@ -560,6 +561,9 @@ __global__ __launch_bounds__(NT) void k_invT_pre(const Slot* __restrict__ slots,
     using TP = TilePlan<R, N, TILE, NT>;
     constexpr int PITCH = Lay<N>::P;
     constexpr int EPT = TP::EPT;
+    static_assert(NT % 64 == 0, "whole waves");
+    constexpr int NQ = (TILE * N + 63) / 64;   // chunks of 64 points per unit
+    __shared__ double chs[NQ][ChunkSums<NS_DIR>::P];
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
     const cpx<R>* twl = tw;
@@ -610,26 +614,35 @@ __global__ __launch_bounds__(NT) void k_invT_pre(const Slot* __restrict__ slots,
         }
     }
     lds_fft<R, N, TILE, NT, true>(lds, twl);
-    double acc[NS_DIR] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    // one loop over the points (batching its loads as the other passes do
-    // raised the register count and lost occupancy: measured slower)
-    for (int e = threadIdx.x; e < TILE * N; e += NT) {
-        const int l = e / N, m = e - l * N;
-        const long long go = (((long long)c * B + bb) * Cc + c0 + l) * N + m;
-        const cpx<R> v = pv[go] * lds[l * PITCH + lx(m)];
-        out[go] = v;
-        if (dir) {
-            const cpx<double> w = wid(v);
-            acc[0] += re_dot(wid(r[go]), w);
-            acc[1] += re_dot(wid(rp[go]), w);
-            acc[2] += re_dot(wid(phi[go]), w);
-            acc[3] += cabs2(w);
-            acc[4] += re_dot(wid(Pprev[go]), w);
+    // one loop over the points in wave-uniform chunks of 64 (batching its loads
+    // as the other passes do raised the register count and lost occupancy:
+    // measured slower); the partial sums of a chunk are reduced by its wave,
+    // so the unit's row does not depend on NT
+    for (int base = threadIdx.x & ~63; base < TILE * N; base += NT) {
+        const int e = base + (threadIdx.x & 63);
+        double acc[NS_DIR] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        if (e < TILE * N) {
+            const int l = e / N, m = e - l * N;
+            const long long go = (((long long)c * B + bb) * Cc + c0 + l) * N + m;
+            const cpx<R> v = pv[go] * lds[l * PITCH + lx(m)];
+            out[go] = v;
+            if (dir) {
+                const cpx<double> w = wid(v);
+                acc[0] = re_dot(wid(r[go]), w);
+                acc[1] = re_dot(wid(rp[go]), w);
+                acc[2] = re_dot(wid(phi[go]), w);
+                acc[3] = cabs2(w);
+                acc[4] = re_dot(wid(Pprev[go]), w);
+            }
         }
+        if (dir) chunk_add<NS_DIR>(acc, chs, base >> 6);
     }
     // one partial-sum row per unit, whichever block took it
-    if (dir) block_row<NS_DIR, NT>(acc, as_global(S.red_dir), RED_DIR_STRIDE, u);
-    if constexpr (TP::PIPE) __syncthreads();   // lds is refilled by the next unit
+    if (dir) {
+        __syncthreads();
+        chunk_row<NS_DIR>(chs, NQ, as_global(S.red_dir), RED_DIR_STRIDE, u);
+    }
+    if constexpr (TP::PIPE) __syncthreads();   // lds and the chunk sums are refilled by the next unit
     } while (TP::PIPE && (u += gridDim.x) < units);
 }
 
@@ -708,6 +721,9 @@ __global__ __launch_bounds__(NT) void k_mid(const Slot* __restrict__ slots, int 
     constexpr int EPT = MP::EPT;
     constexpr bool HL = OP == MID_HL || OP == MID_HLX;
     constexpr bool X2 = OP == MID_HLX;
+    constexpr int NVM = X2 ? NS_KIN : 4;   // partial sums per line group
+    static_assert(NT % 64 == 0 && (LPB * N) % 64 == 0, "line groups of whole chunks");
+    __shared__ double chs[HL ? LPB * N / 64 : 1][ChunkSums<NVM>::P];
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     cpx<R>* X = reinterpret_cast<cpx<R>*>(smem_raw);
     cpx<R>* Z = X + NLN * PITCH;                       // spectrum of Phi (MID_HLX)
@@ -765,10 +781,12 @@ __global__ __launch_bounds__(NT) void k_mid(const Slot* __restrict__ slots, int 
             lds_fft<R, N, NLN, NT, false>(X, twl);
             if constexpr (X2) lds_fft<R, N, NLN, NT, false>(Z, twl);
         }
-        double acc[X2 ? NS_KIN : 4];
-#pragma unroll
-        for (int k = 0; k < (X2 ? NS_KIN : 4); ++k) acc[k] = 0.0;
+        // the partial sums in chunks of 64 points (each one wave's iteration),
+        // so the row does not depend on NT
         for (int e = threadIdx.x; e < LPB * N; e += NT) {
+            double acc[NVM];
+#pragma unroll
+            for (int k = 0; k < NVM; ++k) acc[k] = 0.0;
             const int q = e / N, m = e - q * N;
             const int line = l0 + q;
             // kinetic symbol from the wavenumbers; the odd symbols (SOC, D_y)
@@ -821,6 +839,7 @@ __global__ __launch_bounds__(NT) void k_mid(const Slot* __restrict__ slots, int 
                 *x0 = cmk((R)a0.x, (R)a0.y);
                 *x1 = cmk((R)a1.x, (R)a1.y);
                 *x2 = cmk((R)a2.x, (R)a2.y);
+                chunk_add<NVM>(acc, chs, e >> 6);
             } else {
                 const R d0 = (R)(unit ? invM : invM / fmax(al[0] + K, fl));
                 const R d1 = (R)(unit ? invM : invM / fmax(al[1] + K, fl));
@@ -856,242 +875,9 @@ __global__ __launch_bounds__(NT) void k_mid(const Slot* __restrict__ slots, int 
                 if (doB) outB[go] = Y[L * PITCH + lx(m)];
             }
         }
-        if (HL) block_row<(X2 ? NS_KIN : 4), NT>(acc, red, RED_MID_STRIDE, grp);
-        __syncthreads();   // X, Z, Y and the copy are refilled by the next group
+        if (HL) chunk_row<NVM>(chs, LPB * N / 64, red, RED_MID_STRIDE, grp);
+        __syncthreads();   // X, Z, Y, the copy and the chunk sums are refilled by the next group
     }
 }
-
-// ---------------------------------------------------------------------------
-// launch configuration (tiles sized so that small grids still give >= ~200
-// blocks and each block's LDS stays near or under 64 KB)
-// ---------------------------------------------------------------------------
-// Lines per block of the transposing passes. In double, 8 lines give 128-byte
-// runs in the transposed stores of the forward passes; the H_L inverse pass,
-// which holds two transforms in LDS, keeps 4, and so does the preconditioner's
-// last pass: its next tile then fits in registers (pipelined), and a lone
-// solve gets twice the blocks (measured at 256^2: same batch time, 10 instead
-// of 14 us per launch for one solve).
-template <typename R> constexpr int tile_fwd(int N) {
-    return sizeof(R) == 8 ? (N >= 1024 ? 2 : (N >= 512 ? 4 : 8)) : (N >= 1024 ? 4 : 8);
-}
-template <typename R> constexpr int tile_pre(int N) { return sizeof(R) == 8 ? (N >= 1024 ? 2 : 4) : tile_fwd<R>(N); }
-template <typename R> constexpr int tile_inv(int N) {
-    return sizeof(R) == 8 ? (N >= 512 ? 2 : 4) : (N >= 512 ? 4 : 8);
-}
-constexpr int lpb_mid(int N) { return N >= 256 ? 1 : (N >= 128 ? 2 : (N >= 64 ? 4 : 8)); }
-
-int mid_blocks(int N, int nlines) { return nlines / lpb_mid(N); }
-
-// threads per block of the FFT passes (whole waves; the transforms of a block
-// hold TILE * N or 3 * LPB * N values)
-template <typename R> constexpr int nt_tile(int N) { return 256; }
-template <typename R> constexpr int nt_mid(int N) { return N >= 1024 ? 512 : 256; }
-template <typename R> int invT_pre_blocks(int N, int B, int Cc) { return 3 * B * (Cc / tile_pre<R>(N)); }
-template int invT_pre_blocks<double>(int, int, int);
-template int invT_pre_blocks<float>(int, int, int);
-
-static int cu_count() {
-    static int n = 0;
-    if (!n) {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
-            n = 256;
-    }
-    return n;
-}
-
-// Blocks per slot of a transposed pass: one per unit, or, for a pipelined
-// kernel, as many as fill the device once, in multiples of 8 (the XCD tile
-// order); the occupancy is queried once per kernel.
-template <auto KERNEL, bool PIPE, typename... Args>
-static hipError_t tile_go(int units, int nslots, int ntb, size_t lds, hipStream_t s, Args... args) {
-    int G = units;
-    if (PIPE) {
-        static int per_cu = -1;
-        if (per_cu < 0) {
-            int nb = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, KERNEL, ntb, lds) != hipSuccess || nb <= 0) nb = 1;
-            per_cu = nb;
-        }
-        const long long resident = (long long)per_cu * cu_count();
-        const long long g = std::max<long long>(1, (resident + nslots - 1) / nslots);
-        if (g < units) G = (int)std::min<long long>(units, std::max<long long>(8, g & ~7LL));
-    }
-    GS_LAUNCH(KERNEL, dim3((unsigned)G, (unsigned)nslots), dim3(ntb), lds, s, args...);
-    return hipGetLastError();
-}
-
-template <typename R, typename RX, int N>
-static hipError_t fwdT_n(int pro, int dual, const Slot* slots, int nslots, int in, int out, int aux0, int aux1,
-                         int A, int B, int ncomp, const cpx<R>* tw, hipStream_t s) {
-    constexpr int TILE = tile_fwd<R>(N);
-    constexpr int NTB = nt_tile<R>(N);
-    if (B % TILE) return hipErrorInvalidValue;
-    if (dual && pro != PRO_DIR) return hipErrorInvalidValue;
-    const size_t lds = (size_t)TILE * Lay<N>::P * sizeof(cpx<R>);
-    dim3 grid((unsigned)((long long)(dual ? 6 : ncomp) * A * (B / TILE)), (unsigned)nslots);
-    if (dual) {
-        GS_LAUNCH((k_fwdT<R, RX, N, TILE, PRO_DIR, true, NTB>), grid, dim3(NTB), lds, s, slots, in, out, aux0, aux1, A, B, tw);
-        return hipGetLastError();
-    }
-    switch (pro) {
-    case PRO_PLAIN:
-        GS_LAUNCH((k_fwdT<R, RX, N, TILE, PRO_PLAIN, false, NTB>), grid, dim3(NTB), lds, s, slots, in, out, aux0, aux1, A, B, tw);
-        break;
-    case PRO_DIR:
-        GS_LAUNCH((k_fwdT<R, RX, N, TILE, PRO_DIR, false, NTB>), grid, dim3(NTB), lds, s, slots, in, out, aux0, aux1, A, B, tw);
-        break;
-    default:
-        return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-template <typename R, int N>
-static hipError_t invT_n(int epi, const Slot* slots, int nslots, int in, int in2, int out, int out2, int uin,
-                         int B, int Cc, double scale, int use_invnP, int rot_any, const cpx<R>* tw, hipStream_t s) {
-    constexpr int TILE = tile_inv<R>(N);
-    constexpr int NTB = nt_tile<R>(N);
-    using TP = TilePlan<R, N, TILE, NTB>;
-    if (Cc % TILE) return hipErrorInvalidValue;
-    const int units = 3 * B * (Cc / TILE);
-    const size_t lds = TP::tw_offset(epi == EPI_SCALE ? 1 : 2) + TP::TW_BYTES;
-    switch (epi) {
-    case EPI_SCALE:
-        return tile_go<k_invT<R, N, TILE, EPI_SCALE, NTB>, TP::PIPE>(units, nslots, NTB, lds, s, slots, in, in2, out,
-                                                                      out2, uin, B, Cc, scale, use_invnP, rot_any, tw);
-    case EPI_HL:
-        return tile_go<k_invT<R, N, TILE, EPI_HL, NTB>, TP::PIPE>(units, nslots, NTB, lds, s, slots, in, in2, out,
-                                                                   out2, uin, B, Cc, scale, use_invnP, rot_any, tw);
-    case EPI_ROTX:
-        return tile_go<k_invT<R, N, TILE, EPI_ROTX, NTB>, TP::PIPE>(units, nslots, NTB, lds, s, slots, in, in2, out,
-                                                                     out2, uin, B, Cc, scale, use_invnP, rot_any, tw);
-    default:
-        return hipErrorInvalidValue;
-    }
-}
-
-template <typename R, typename RS, int N>
-static hipError_t invT_pre_n(const Slot* slots, int nslots, int in, int out, int B, int Cc, int dir,
-                             const cpx<R>* tw, hipStream_t s) {
-    constexpr int TILE = tile_pre<R>(N);
-    constexpr int NTB = nt_tile<R>(N);
-    using TP = TilePlan<R, N, TILE, NTB>;
-    if (Cc % TILE) return hipErrorInvalidValue;
-    static_assert(NS_DIR <= RED_DIR_STRIDE, "partial-sum row");
-    return tile_go<k_invT_pre<R, RS, N, TILE, NTB>, TP::PIPE>(3 * B * (Cc / TILE), nslots, NTB,
-                                                               TP::tw_offset(1) + TP::TW_BYTES, s, slots, in, out, B,
-                                                               Cc, dir, tw);
-}
-
-// Blocks per slot of a middle pass: one per line group, or, for a pipelined
-// kernel, as many as fill the device once (every resident block then loops
-// over several groups; the occupancy is queried once per kernel).
-template <auto KERNEL, typename MP, typename... Args>
-static hipError_t mid_go(int ngroups, int nslots, int ntb, size_t lds, hipStream_t s, Args... args) {
-    int G = ngroups;
-    if (MP::PIPE) {
-        static int per_cu = -1;
-        if (per_cu < 0) {
-            int nb = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, KERNEL, ntb, lds) != hipSuccess || nb <= 0) nb = 1;
-            per_cu = nb;
-        }
-        const long long resident = (long long)per_cu * cu_count();
-        G = (int)std::min<long long>(ngroups, std::max<long long>(1, (resident + nslots - 1) / nslots));
-    }
-    GS_LAUNCH(KERNEL, dim3((unsigned)G, (unsigned)nslots), dim3(ntb), lds, s, args...);
-    return hipGetLastError();
-}
-
-template <typename R, int N>
-static hipError_t mid_n(int op, const Slot* slots, int nslots, int in, int outA, int outB, int nlines,
-                        int rot_any, const cpx<R>* tw, hipStream_t s) {
-    constexpr int LPB = lpb_mid(N);
-    constexpr int NTB = nt_mid<R>(N);
-    if (nlines % LPB) return hipErrorInvalidValue;
-    const int ngroups = nlines / LPB;
-    using HL = MidPlan<R, N, LPB, MID_HL, NTB>;
-    using HX = MidPlan<R, N, LPB, MID_HLX, NTB>;
-    using PR = MidPlan<R, N, LPB, MID_PRE, NTB>;
-    const bool ra = rot_any != 0;
-    if (op == MID_HL)
-        return mid_go<k_mid<R, N, LPB, MID_HL, NTB>, HL>(ngroups, nslots, NTB, HL::tw_offset(ra) + HL::TW_BYTES, s,
-                                                         slots, in, outA, outB, nlines, rot_any, tw);
-    if (op == MID_HLX)
-        return mid_go<k_mid<R, N, LPB, MID_HLX, NTB>, HX>(ngroups, nslots, NTB, HX::tw_offset(ra) + HX::TW_BYTES, s,
-                                                          slots, in, outA, outB, nlines, rot_any, tw);
-    return mid_go<k_mid<R, N, LPB, MID_PRE, NTB>, PR>(ngroups, nslots, NTB, PR::tw_offset(false) + PR::TW_BYTES, s,
-                                                      slots, in, outA, outB, nlines, 0, tw);
-}
-
-#define GS_SWITCH_N(CALL)                        \
-    switch (N) {                                 \
-    case 16: return CALL(16);                    \
-    case 24: return CALL(24);                    \
-    case 48: return CALL(48);                    \
-    case 96: return CALL(96);                    \
-    case 192: return CALL(192);                  \
-    case 384: return CALL(384);                  \
-    case 768: return CALL(768);                  \
-    case 32: return CALL(32);                    \
-    case 64: return CALL(64);                    \
-    case 128: return CALL(128);                  \
-    case 256: return CALL(256);                  \
-    case 512: return CALL(512);                  \
-    case 1024: return CALL(1024);                \
-    default: return hipErrorInvalidValue;        \
-    }
-
-template <typename R, typename RX>
-hipError_t launch_fwdT(int N, int pro, int dual, const Slot* slots, int nslots, int in, int out, int aux0,
-                       int aux1, int A, int B, int ncomp, const cpx<R>* tw, hipStream_t s) {
-#define CALL(n) fwdT_n<R, RX, n>(pro, dual, slots, nslots, in, out, aux0, aux1, A, B, ncomp, tw, s)
-    GS_SWITCH_N(CALL)
-#undef CALL
-}
-
-template <typename R>
-hipError_t launch_invT(int N, int epi, const Slot* slots, int nslots, int in, int in2, int out, int out2,
-                       int uin, int B, int Cc, double scale, int use_invnP, int rot_any, const cpx<R>* tw,
-                       hipStream_t s) {
-#define CALL(n) invT_n<R, n>(epi, slots, nslots, in, in2, out, out2, uin, B, Cc, scale, use_invnP, rot_any, tw, s)
-    GS_SWITCH_N(CALL)
-#undef CALL
-}
-
-template <typename R, typename RS>
-hipError_t launch_invT_pre(int N, const Slot* slots, int nslots, int in, int out, int B, int Cc, int dir,
-                           const cpx<R>* tw, hipStream_t s) {
-#define CALL(n) invT_pre_n<R, RS, n>(slots, nslots, in, out, B, Cc, dir, tw, s)
-    GS_SWITCH_N(CALL)
-#undef CALL
-}
-
-template <typename R>
-hipError_t launch_mid(int N, int op, const Slot* slots, int nslots, int in, int outA, int outB, int nlines,
-                      int rot_any, const cpx<R>* tw, hipStream_t s) {
-#define CALL(n) mid_n<R, n>(op, slots, nslots, in, outA, outB, nlines, rot_any, tw, s)
-    GS_SWITCH_N(CALL)
-#undef CALL
-}
-
-#define GS_INST_FFT(R)                                                                                           \
-    template hipError_t launch_invT<R>(int, int, const Slot*, int, int, int, int, int, int, int, int, double,     \
-                                       int, int, const cpx<R>*, hipStream_t);                                    \
-    template hipError_t launch_mid<R>(int, int, const Slot*, int, int, int, int, int, int, const cpx<R>*,         \
-                                      hipStream_t);
-#define GS_INST_FFT2(R, RX)                                                                                      \
-    template hipError_t launch_fwdT<R, RX>(int, int, int, const Slot*, int, int, int, int, int, int, int, int,   \
-                                           const cpx<R>*, hipStream_t);                                          \
-    template hipError_t launch_invT_pre<R, RX>(int, const Slot*, int, int, int, int, int, int, const cpx<R>*,    \
-                                               hipStream_t);
-GS_INST_FFT(double)
-GS_INST_FFT(float)
-GS_INST_FFT2(double, double)
-GS_INST_FFT2(float, float)
-GS_INST_FFT2(float, double)
-GS_INST_FFT2(double, float)
 
 }  // namespace gs

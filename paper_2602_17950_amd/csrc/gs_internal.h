@@ -208,25 +208,35 @@ enum Pro : int { PRO_PLAIN = 0, PRO_DIR = 2 };
 enum Epi : int { EPI_SCALE = 0, EPI_HL = 1, EPI_ROTX = 2 };
 enum MidOp : int { MID_HL = 0, MID_PRE = 1, MID_HLX = 2 };
 
+// Launch schedule of an FFT pass: lines per block (the tile of a transposing
+// pass, the line positions of a middle-pass group) and threads per block.
+// Every pass has NCAND candidate schedules (candidate 0: the fixed table); all
+// candidates of a pass compute the same bits, so the autotuner may choose any
+// valid one (see fft_launch.h).
+struct Cand {
+    int tile, nt;
+};
+constexpr int NCAND = 3;
+
 // Forward transform along the contiguous axis of in[ncomp][A][B][N], written
 // with that axis moved to the slowest position: out[ncomp][N][A][B].
 // Prologue (in place on the physical input, before the transform):
 //   PRO_PLAIN:  transform in as is
 //   PRO_DIR:    in <- -aux0 + beta in - dphi aux1 (written back), transform invnP * in
-// dual (PRO_DIR only): also transform aux1 into components 3..5 of out.
+//               (with dual = 1 only: aux1 (Phi) is also transformed into components 3..5)
 // in, out and (PRO_DIR) aux0 are of type R; aux1 (Phi) is of type RX.
 template <typename R, typename RX>
-hipError_t launch_fwdT(int N, int pro, int dual, const Slot* slots, int nslots, int in, int out, int aux0,
-                       int aux1, int A, int B, int ncomp, const cpx<R>* tw, hipStream_t s);
+hipError_t launch_fwdT(int N, int pro, int dual, const Slot* slots, int nslots, int in, int out, int aux0, int aux1,
+                       int A, int B, int ncomp, const cpx<R>* tw, int cand, hipStream_t s);
 
-// Inverse transform along the slowest axis of in[3][N][B][Cc] (and in2 when the
+// Inverse transform along the slowest axis of in[3][N][B][C] (and in2 when the
 // slot rotates), written with that axis contiguous: out[3][B][Cc][N]; the
-// epilogue adds the physical-space terms (see fft_kernels.hip).
+// epilogue adds the physical-space terms (see fft_core.h).
 // rot_any: some slot of the launch rotates (LDS and buffers for the second
 // input/output are provided); each slot decides from its own Omega.
 template <typename R>
 hipError_t launch_invT(int N, int epi, const Slot* slots, int nslots, int in, int in2, int out, int out2,
-                       int uin, int B, int Cc, double scale, int use_invnP, int rot_any, const cpx<R>* tw,
+                       int uin, int B, int Cc, double scale, int use_invnP, int rot_any, const cpx<R>* tw, int cand,
                        hipStream_t s);
 
 // Last pass of the preconditioner: out = pv * IFFT(in); with dir = 1 also the
@@ -234,7 +244,7 @@ hipError_t launch_invT(int N, int epi, const Slot* slots, int nslots, int in, in
 // out and P are of type R; r^n, r^{n-1} and Phi of type RS.
 template <typename R, typename RS>
 hipError_t launch_invT_pre(int N, const Slot* slots, int nslots, int in, int out, int B, int Cc, int dir,
-                           const cpx<R>* tw, hipStream_t s);
+                           const cpx<R>* tw, int cand, hipStream_t s);
 
 // Middle pass: transform the contiguous axis of three component lines,
 // apply the spectral operator (all three components at each wavenumber),
@@ -242,11 +252,22 @@ hipError_t launch_invT_pre(int N, const Slot* slots, int nslots, int in, int out
 // of `in` hold the spectrum of Phi.
 template <typename R>
 hipError_t launch_mid(int N, int op, const Slot* slots, int nslots, int in, int outA, int outB, int nlines,
-                      int rot_any, const cpx<R>* tw, hipStream_t s);
+                      int rot_any, const cpx<R>* tw, int cand, hipStream_t s);
 
 int mid_blocks(int N, int nlines);
 // blocks (= partial-sum rows) of launch_invT_pre for these sizes
 template <typename R> int invT_pre_blocks(int N, int B, int Cc);
+
+// validity and description of candidate c for lines of length N (B / Cc: the
+// number of line positions the tile must divide)
+template <typename R> bool fwdT_cand_ok(int N, int c, int B);
+template <typename R> bool invT_cand_ok(int N, int c, int Cc);
+template <typename R> bool invT_pre_cand_ok(int N, int c);
+bool mid_cand_ok(int N, int c);
+template <typename R> Cand fwdT_cand_of(int N, int c);
+template <typename R> Cand invT_cand_of(int N, int c);
+template <typename R> Cand invT_pre_cand_of(int N, int c);
+Cand mid_cand_of(int N, int c);
 
 // ---------------------------------------------------------------------------
 // pointwise kernels with fused partial sums (pw_kernels.hip), and the control

@@ -27,7 +27,8 @@ EXPORTS = ("gs_create", "gs_destroy", "gs_default_options", "gs_footprint_bytes"
            "gs_solve_device", "gs_fft", "gs_hamiltonian", "gs_precondition", "gs_kernel_timer_start",
            "gs_kernel_timer_read", "gs_last_error", "gs_set_hbm_budget", "gs_memory_stats",
            "gs_batch_solve", "gs_submit", "gs_progress", "gs_poll", "gs_wait", "gs_cancel",
-           "gs_interpolate", "gs_existence_check", "gs_fft_noalloc")
+           "gs_interpolate", "gs_existence_check", "gs_fft_noalloc", "gs_set_autotune",
+           "gs_autotune_report")
 
 KERNEL_KINDS = {"hl_fwd": 0, "hl_mid": 1, "hl_inv": 2, "pre_fwd": 3, "pre_mid": 4, "pre_inv": 5,
                 "eval": 6, "resid": 7, "lsred": 9, "hl_fwd2": 10, "hl_inv2": 11, "ctrl": 12}
@@ -127,6 +128,9 @@ def load():
     lib.gs_cancel.argtypes = [vp, C.c_uint64]
     lib.gs_interpolate.argtypes = [vp, C.POINTER(gs_grid), vp, C.POINTER(gs_grid), vp, vp]
     lib.gs_existence_check.argtypes = [C.POINTER(gs_grid), C.POINTER(gs_trap), C.POINTER(gs_params)]
+    lib.gs_set_autotune.argtypes = [vp, C.c_int]
+    lib.gs_autotune_report.argtypes = [vp]
+    lib.gs_autotune_report.restype = C.c_char_p
     _lib = lib
     return lib
 
@@ -351,6 +355,19 @@ class Context:
         b, r, a = C.c_size_t(), C.c_size_t(), C.c_size_t()
         _check(load().gs_memory_stats(self._h, C.byref(b), C.byref(r), C.byref(a)))
         return {"budget": b.value, "reserved": r.value, "allocated": a.value}
+
+    # -- schedules of the FFT passes ------------------------------------------------
+    def set_autotune(self, on: bool):
+        _check(load().gs_set_autotune(self._h, int(bool(on))))
+
+    def autotune_report(self):
+        """Per class and bucket of running solves: the chosen schedule of every
+        FFT pass and the mean launch time of each candidate (list of dicts)."""
+        import json
+        r = load().gs_autotune_report(self._h)
+        if r is None:
+            raise GsError(GS_EINVAL, last_error())
+        return json.loads(r.decode())
 
     # -- measurement ---------------------------------------------------------------
     def kernel_timer_start(self, kind):

@@ -180,3 +180,10 @@ def test_existence_check_sec_2_1():
     assert gs.existence_check(P3(c0=10.0, c1=-10.0)) == ok
     assert gs.existence_check(P3(c0=10.0, c1=-10.5)) == warn
     assert gs.existence_check(P3(c0=-0.1, c1=0.5)) == warn
+
+
+def test_autotune_calls_without_device():
+    lib = gs.load()
+    assert lib.gs_set_autotune(None, 1) == gs.GS_EINVAL
+    assert lib.gs_autotune_report(None) is None
+    assert "NULL" in gs.last_error()
