@@ -33,7 +33,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc (no GPU code involved)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-shared", "-fPIC",
+        cmd = ["gcc", "-O3", "-std=c11", "-fopenmp", "-shared", "-fPIC",
                "-o", tmp, _SRC, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)

@@ -154,7 +154,47 @@ static void fft_radix2(int n, cplx* a, const cplx* w) {
     }
 }
 
-/* One-dimensional transform, unnormalised in both directions. */
+/* Full root table w[j] = e^{sign 2 pi i j / n}, j < n, each entry from cos/sin. */
+static cplx* roots(int n, int sign) {
+    cplx* w = (cplx*)malloc(sizeof(cplx) * n);
+    for (int j = 0; j < n; ++j) {
+        double ang = sign * 2.0 * M_PI * (double)j / n;
+        w[j] = cos(ang) + I * sin(ang);
+    }
+    return w;
+}
+
+/* Mixed-radix Cooley-Tukey by decimation in time, recursive: with p the
+ * smallest of 2, 3, 5 dividing n (the DFT definition itself when none does),
+ * the p subsequences x[s], x[s + p], ... (stride `stride` apart in memory)
+ * are transformed as sequences of length m = n/p into Y_s = X[s m ...], and
+ * out_{k + q m} = sum_s e^{sign 2 pi i s (k + q m) / n} Y_s[k]. The roots of
+ * unity of order n are w[(j mod n) wstep], w the root table of the top-level
+ * length n wstep. tmp: n values. */
+static void fft_mixed(int n, const cplx* x, long stride, cplx* X, cplx* tmp, const cplx* w, int wstep) {
+    if (n == 1) { X[0] = x[0]; return; }
+    int p = (n % 2 == 0) ? 2 : (n % 3 == 0) ? 3 : (n % 5 == 0) ? 5 : n;
+    int m = n / p;
+    if (p == n) {   /* no small factor: the definition */
+        for (int k = 0; k < n; ++k) {
+            cplx acc = 0;
+            for (int j = 0; j < n; ++j) acc += x[j * stride] * w[(((long)j * k) % n) * wstep];
+            X[k] = acc;
+        }
+        return;
+    }
+    for (int s0 = 0; s0 < p; ++s0) fft_mixed(m, x + s0 * stride, stride * p, X + s0 * m, tmp, w, wstep * p);
+    for (int k = 0; k < m; ++k)
+        for (int q = 0; q < p; ++q) {
+            cplx acc = 0;
+            for (int s0 = 0; s0 < p; ++s0) acc += X[s0 * m + k] * w[(((long)s0 * (k + q * m)) % n) * wstep];
+            tmp[k + q * m] = acc;
+        }
+    memcpy(X, tmp, sizeof(cplx) * n);
+}
+
+/* One-dimensional transform, unnormalised in both directions: radix 2 for
+ * powers of two, mixed radix otherwise. */
 void orc_fft1d(int n, cplx* a, int sign) {
     if (is_pow2(n)) {
         cplx* w = twiddles(n, sign);
@@ -162,10 +202,14 @@ void orc_fft1d(int n, cplx* a, int sign) {
         free(w);
         return;
     }
+    cplx* in = (cplx*)malloc(sizeof(cplx) * n);
     cplx* tmp = (cplx*)malloc(sizeof(cplx) * n);
-    orc_dft(n, a, tmp, sign);
-    memcpy(a, tmp, sizeof(cplx) * n);
+    cplx* w = roots(n, sign);
+    memcpy(in, a, sizeof(cplx) * n);
+    fft_mixed(n, in, 1, a, tmp, w, 1);
+    free(in);
     free(tmp);
+    free(w);
 }
 
 /* d-dimensional transform of one grid array, axis by axis (the DFT factorises).
@@ -180,22 +224,24 @@ void orc_fftn(const orc_grid* g, cplx* f, int sign) {
         long nlines = M / n;
         long st = stride;
         int p2 = is_pow2(n);
-        cplx* w = p2 ? twiddles(n, sign) : NULL;
+        cplx* w = p2 ? twiddles(n, sign) : roots(n, sign);
         #pragma omp parallel num_threads(g_threads)
         {
             cplx* line = (cplx*)malloc(sizeof(cplx) * n);
             cplx* tmp = p2 ? NULL : (cplx*)malloc(sizeof(cplx) * n);
+            cplx* tmp2 = p2 ? NULL : (cplx*)malloc(sizeof(cplx) * n);
             #pragma omp for schedule(static)
             for (long l = 0; l < nlines; ++l) {
                 long outer = l / st, inner = l % st;
                 long start = outer * st * n + inner;
                 for (int m = 0; m < n; ++m) line[m] = f[start + m * st];
                 if (p2) fft_radix2(n, line, w);
-                else { orc_dft(n, line, tmp, sign); memcpy(line, tmp, sizeof(cplx) * n); }
+                else { fft_mixed(n, line, 1, tmp, tmp2, w, 1); memcpy(line, tmp, sizeof(cplx) * n); }
                 for (int m = 0; m < n; ++m) f[start + m * st] = line[m];
             }
             free(line);
             free(tmp);
+            free(tmp2);
         }
         free(w);
         stride *= n;
