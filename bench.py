@@ -49,7 +49,7 @@ KERNEL_SOURCES = ("paper_2602_17950_amd/csrc/fft_core.h", "paper_2602_17950_amd/
                   "paper_2602_17950_amd/csrc/device_common.h", "paper_2602_17950_amd/csrc/control.h",
                   "paper_2602_17950_amd/csrc/gs_internal.h")
 TRAFFIC_SUMMARY = "profiles/hbm_traffic_kernels256.md"
-SECTIONS = ("headline", "kernels", "single", "c1", "cm3d", "sweep", "table2", "serve")
+SECTIONS = ("headline", "kernels", "tuner", "single", "c1", "cm3d", "sweep", "table2", "serve")
 KINDS = ("hl_fwd", "hl_mid", "hl_inv", "pre_fwd", "pre_mid", "pre_inv", "resid", "lsred", "ctrl", "eval")
 # Table 2 (Example 3): lowest energy over the 1000 guess combinations of Sec. 4, and the
 # paper's CM-PCG CPU seconds for that one solve (a Xeon Gold 6248R, threads not stated;
@@ -351,6 +351,44 @@ def main():
         line["roofline_fp64"] = roofline_of(tab["fp64"], d64, f"fp64:{d64}",
                                             f"plain FP64 path, {B} slots of {args.n}^2 at full occupancy")
         del kb
+
+    # ------------------------------------------- FFT schedules: fixed table vs tuned
+    if "tuner" in sections:
+        tun = {}
+        for label, nslots, make in (("128^2", B, lambda i: inputs.workload_vortex_2d(n=128, seed=2602 + i)),
+                                    ("256^2", B, lambda i: inputs.workload_vortex_2d(n=256, seed=2602 + i)),
+                                    ("512^2", 16, lambda i: inputs.workload_vortex_2d(n=512, seed=2602 + i)),
+                                    ("1024^2", 8, lambda i: inputs.workload_vortex_2d(n=1024, seed=2602 + i)),
+                                    ("128^3", 4, lambda i: inputs.workload_aniso_3d(n=128))):
+            tb = Batch(torch, [make(i) for i in range(nslots)])
+            row = {"slots": nslots}
+            for name, opt in (("fp64_state_fp32_dir", gs.default_options(precision=gs.GS_FP64, tol=0.0, max_iter=64,
+                                                                         dir_precision=gs.GS_FP32)),
+                              ("fp64", gs.default_options(precision=gs.GS_FP64, tol=0.0, max_iter=64))):
+                ms = {}
+                for tune in (0, 1):
+                    with gs.Context(0) as tctx:
+                        tctx.set_autotune(tune)
+                        tctx.batch_solve(tb.requests(opt))   # warm-up; with tuning on, its first chunk tunes
+                        torch.cuda.synchronize()
+                        t = time.perf_counter()
+                        tctx.batch_solve(tb.requests(opt))
+                        torch.cuda.synchronize()
+                        ms[tune] = (time.perf_counter() - t) / 64 * 1e3
+                        if tune:
+                            rep = [r for r in tctx.autotune_report() if r["decided"]]
+                            chosen = {k: v["chosen"] for r in rep for k, v in r["passes"].items()}
+                row[name] = {"ms_per_iteration_fixed": ms[0], "ms_per_iteration_tuned": ms[1],
+                             "gain": ms[0] / ms[1], "chosen": chosen}
+            log(f"tuner {label}: " + ", ".join(f"{k} {v['ms_per_iteration_fixed']:.3f} -> "
+                                               f"{v['ms_per_iteration_tuned']:.3f} ms"
+                                               for k, v in row.items() if k != "slots"))
+            tun[label] = row
+            del tb
+        tun["note"] = ("ms per batched iteration of the given number of solves (tol 0, every slot running), fixed "
+                       "table against the schedules the autotuner chose in the warm-up's first chunk; candidates are "
+                       "(lines x threads) per block, the same bits for every choice")
+        line["tuner"] = tun
 
     # ------------------------------------------------------------ single solve
     if "single" in sections:

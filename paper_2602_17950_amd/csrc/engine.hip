@@ -46,8 +46,11 @@ static int fail(int code, const std::string& msg) {
         if (e_ != hipSuccess) return fail(GS_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-// supported line lengths: 2^a in [16, 1024] and 3 * 2^a in [24, 768]
+// supported line lengths: 2^a in [16, 1024], 3 * 2^a in [24, 768], and
+// 80, 160, 300, 600, 1200, 2400 (factors of 5: 2400 = 2^5 3 5^2 and its
+// halvings); lengths above 1024 in 2D only
 static bool size_supported(int n) {
+    if (n == 80 || n == 160 || n == 300 || n == 600 || n == 1200 || n == 2400) return true;
     const int m = (n % 3 == 0) ? n / 3 : n;
     return n >= 16 && n <= 1024 && m >= 1 && (m & (m - 1)) == 0 && (n % 3 != 0 || n >= 24);
 }
@@ -57,7 +60,9 @@ static int check_grid(const gs_grid* g) {
     if (g->dim != 2 && g->dim != 3) return fail(GS_EINVAL, "grid.dim must be 2 or 3");
     for (int a = 0; a < g->dim; ++a) {
         if (!size_supported(g->n[a]))
-            return fail(GS_EINVAL, "grid.n[a] must be 2^a in [16, 1024] or 3 * 2^a in [24, 768]");
+            return fail(GS_EINVAL, "grid.n[a] must be 2^a in [16, 1024], 3 * 2^a in [24, 768], "
+                                   "or one of 80, 160, 300, 600, 1200, 2400");
+        if (g->dim == 3 && g->n[a] > LONG_LINE) return fail(GS_EINVAL, "lengths above 1024 are for 2D grids");
         if (!(g->L[a] > 0.0) || !std::isfinite(g->L[a])) return fail(GS_EINVAL, "grid.L[a] must be positive");
     }
     return GS_OK;
@@ -459,7 +464,17 @@ static hipError_t chain_HL(int dim, const int n[3], long long M, int rot, const 
     if (dim == 2) {
         if ((e = timed_ns(tm, KK_HL_FWD, b_fwd, L.ns, s, [&] { return tuned(tr, P_HL_FWD, cF, [&] {
                  return launch_fwdT<R, RX>(Nx, pro, dual, L.tab, L.ns, in, B_T6A, aux0, aux1, 1, Ny, 3, tw[0], cF, s); }); }))) return e;
-        if ((e = timed_ns(tm, KK_HL_MID, b_mid, L.ns, s, [&] { return tuned(tr, P_HL_MID, cM, [&] {
+        if (Ny > LONG_LINE) {
+            // split middle pass: y transforms T6A -> T6B, the operator into
+            // T0 (and T1), inverse y transforms in place (with the rotation
+            // term from the x-transformed input in T6A)
+            if ((e = launch_lfft<R>(Ny, 0, L.tab, L.ns, B_T6A, B_T6B, dual ? 6 : 3, Nx, B_NONE, B_NONE, B_NONE, tw[1], s)))
+                return e;
+            if ((e = timed_ns(tm, KK_HL_MID, b_mid, L.ns, s, [&] {
+                     return launch_lspec<R>(midop, L.tab, L.ns, B_T6B, B_T0, outB, Ny, Nx, rot, s); }))) return e;
+            if ((e = launch_lfft<R>(Ny, 1, L.tab, L.ns, B_T0, B_T0, 3, Nx, rot ? B_T6A : B_NONE, rot ? B_T1 : B_NONE,
+                                    rot ? B_T1 : B_NONE, tw[1], s))) return e;
+        } else if ((e = timed_ns(tm, KK_HL_MID, b_mid, L.ns, s, [&] { return tuned(tr, P_HL_MID, cM, [&] {
                  return launch_mid<R>(Ny, midop, L.tab, L.ns, B_T6A, B_T0, outB, Nx, rot, tw[1], cM, s); }); }))) return e;
         return timed_ns(tm, KK_HL_INV, b_inv, L.ns, s, [&] { return tuned(tr, P_HL_INV, cI, [&] {
             return launch_invT<R>(Nx, EPI_HL, L.tab, L.ns, B_T0, B_T1, out, B_NONE, in, 1, Ny, 1.0, use_invnP, rot, tw[0], cI, s); }); });
@@ -495,7 +510,14 @@ static hipError_t chain_pre(const Geo<RS, RD>& G, Sub L, int dir, int out, hipSt
     if (G.dim == 2) {
         if ((e = timed_ns(tm, KK_PRE_FWD, 2 * F, L.ns, s, [&] { return tuned(tr, P_PRE_FWD, cF, [&] {
                  return launch_fwdT<RD, RD>(Nx, PRO_PLAIN, 0, L.tab, L.ns, B_U, B_T6A, B_NONE, B_NONE, 1, Ny, 3, G.twd[0], cF, s); }); }))) return e;
-        if ((e = timed_ns(tm, KK_PRE_MID, 2 * F, L.ns, s, [&] { return tuned(tr, P_PRE_MID, cM, [&] {
+        if (Ny > LONG_LINE) {
+            if ((e = launch_lfft<RD>(Ny, 0, L.tab, L.ns, B_T6A, B_T6B, 3, Nx, B_NONE, B_NONE, B_NONE, G.twd[1], s)))
+                return e;
+            if ((e = timed_ns(tm, KK_PRE_MID, 2 * F, L.ns, s, [&] {
+                     return launch_lspec<RD>(MID_PRE, L.tab, L.ns, B_T6B, B_T0, B_NONE, Ny, Nx, 0, s); }))) return e;
+            if ((e = launch_lfft<RD>(Ny, 1, L.tab, L.ns, B_T0, B_T0, 3, Nx, B_NONE, B_NONE, B_NONE, G.twd[1], s)))
+                return e;
+        } else if ((e = timed_ns(tm, KK_PRE_MID, 2 * F, L.ns, s, [&] { return tuned(tr, P_PRE_MID, cM, [&] {
                  return launch_mid<RD>(Ny, MID_PRE, L.tab, L.ns, B_T6A, B_T0, B_NONE, Nx, 0, G.twd[1], cM, s); }); }))) return e;
         return timed_ns(tm, KK_PRE_INV, b_inv, L.ns, s, [&] { return tuned(tr, P_PRE_INV, cI, [&] {
             return launch_invT_pre<RD, RS>(Nx, L.tab, L.ns, B_T0, out, 1, Ny, dir, G.twd[0], cI, s); }); });
@@ -1608,7 +1630,7 @@ static int fft_impl(Ctx& cx, const gs_grid* g, int sign, const cpx<R>* in, cpx<R
 // time (different streams or host threads) race.
 constexpr long long NA_MAX_POINTS = 1LL << 18;
 constexpr size_t NA_HDR = 4096;            // descriptor at 0, solver state at 1024
-constexpr int NA_LENGTHS[] = {16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024};
+constexpr int NA_LENGTHS[] = {16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 80, 160, 300, 600, 1200, 2400};
 constexpr int NA_NLEN = (int)(sizeof(NA_LENGTHS) / sizeof(NA_LENGTHS[0]));
 constexpr size_t na_tw_bytes() {
     size_t b = 0;

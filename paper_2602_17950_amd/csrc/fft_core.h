@@ -122,6 +122,20 @@ __device__ __forceinline__ void dftr(cpx<R> (&v)[RAD]) {
         else     { v[1] = m - id; v[2] = m + id; }
     } else if constexpr (RAD == 4) {
         dft4<R, INV>(v[0], v[1], v[2], v[3]);
+    } else if constexpr (RAD == 5) {
+        // y_q = sum_r v_r w^{rq}, w = exp(-+2 pi i / 5): with t1 = v1 + v4,
+        // t2 = v2 + v3, t3 = v1 - v4, t4 = v2 - v3, the cosines and sines of
+        // 2 pi / 5 and 4 pi / 5 give y1,4 = v0 + c1 t1 + c2 t2 -+ i (s1 t3 + s2 t4)
+        // and y2,3 = v0 + c2 t1 + c1 t2 -+ i (s2 t3 - s1 t4) (upper signs forward)
+        const R c1 = (R)0.309016994374947424102293417182819059, c2 = (R)-0.809016994374947424102293417182819059;
+        const R s1 = (R)0.951056516295153572116439333379382143, s2 = (R)0.587785252292473129168705954639072769;
+        const cpx<R> t1 = v[1] + v[4], t2 = v[2] + v[3], t3 = v[1] - v[4], t4 = v[2] - v[3];
+        const cpx<R> a1 = v[0] + c1 * t1 + c2 * t2, a2 = v[0] + c2 * t1 + c1 * t2;
+        const cpx<R> b1 = s1 * t3 + s2 * t4, b2 = s2 * t3 - s1 * t4;
+        const cpx<R> ib1 = cmuli(b1), ib2 = cmuli(b2);   // i b1, i b2
+        v[0] = v[0] + t1 + t2;
+        if (INV) { v[1] = a1 + ib1; v[4] = a1 - ib1; v[2] = a2 + ib2; v[3] = a2 - ib2; }
+        else     { v[1] = a1 - ib1; v[4] = a1 + ib1; v[2] = a2 - ib2; v[3] = a2 + ib2; }
     } else if constexpr (RAD == 8) {
         // A = 2, B = 4
         cpx<R> y[2][4];
@@ -139,7 +153,7 @@ __device__ __forceinline__ void dftr(cpx<R> (&v)[RAD]) {
             v[q2 + 4] = y[1][q2];
         }
     } else {
-        static_assert(RAD == 16, "radix 2, 3, 4, 8 or 16");
+        static_assert(RAD == 16, "radix 2, 3, 4, 5, 8 or 16");
         // A = 4, B = 4
         cpx<R> y[4][4];
 #pragma unroll
@@ -224,15 +238,19 @@ __device__ __forceinline__ void fft_pass(cpx<R>* buf, const cpx<R>* __restrict__
     __syncthreads();
 }
 
-// For N = 3 * 2^a one radix-3 pass first (NS = 1: no twiddles); then passes
-// of radix RMAX while it divides the rest, then one pass of the remaining
-// power of two (NS = product of the radices done so far).
+// For N divisible by 3 one radix-3 pass first (NS = 1: no twiddles), then a
+// radix-5 pass for every factor 5, then passes of radix RMAX while it divides
+// the rest, then one pass of the remaining power of two (NS = product of the
+// radices done so far).
 template <typename R, int N, int NL, int NT, int RMAX, int NS, bool INV>
 __device__ __forceinline__ void fft_passes(cpx<R>* buf, const cpx<R>* __restrict__ tw) {
     constexpr int REST = N / NS;
     if constexpr (NS == 1 && N % 3 == 0) {
         fft_pass<R, N, NL, NT, 3, 1, INV>(buf, tw);
         fft_passes<R, N, NL, NT, RMAX, 3, INV>(buf, tw);
+    } else if constexpr (REST % 5 == 0) {
+        fft_pass<R, N, NL, NT, 5, NS, INV>(buf, tw);
+        fft_passes<R, N, NL, NT, RMAX, NS * 5, INV>(buf, tw);
     } else if constexpr (REST >= RMAX) {
         fft_pass<R, N, NL, NT, RMAX, NS, INV>(buf, tw);
         fft_passes<R, N, NL, NT, RMAX, NS * RMAX, INV>(buf, tw);
@@ -240,6 +258,13 @@ __device__ __forceinline__ void fft_passes(cpx<R>* buf, const cpx<R>* __restrict
         fft_pass<R, N, NL, NT, REST, NS, INV>(buf, tw);
     }
 }
+
+// N = 2^a 3^b 5^c with b <= 1 and c <= 2 (the factors the passes handle)
+template <int N> struct Pow2Part {
+    static constexpr int odd = (N % 3 == 0 ? 3 : 1) * (N % 25 == 0 ? 25 : (N % 5 == 0 ? 5 : 1));
+    static constexpr int p2 = N / odd;
+    static constexpr bool odd_ok = N % odd == 0 && (p2 & (p2 - 1)) == 0 && p2 >= 2;
+};
 
 // Largest radix per pass: 16 in float; 8 in double, which halves the
 // registers a butterfly holds and so keeps more waves resident.
@@ -249,8 +274,7 @@ template <typename R> constexpr int rmax() { return sizeof(R) == 8 ? 8 : 16; }
 // buf + l * Lay<N>::P; natural order in and out, unnormalised).
 template <typename R, int N, int NL, int NT, bool INV>
 __device__ __forceinline__ void lds_fft(cpx<R>* buf, const cpx<R>* __restrict__ tw) {
-    static_assert(N >= 16 && N <= 1024 && ((N & (N - 1)) == 0 || (N % 3 == 0 && ((N / 3) & (N / 3 - 1)) == 0)),
-                  "N = 2^a or 3 * 2^a");
+    static_assert(N >= 16 && N <= 2400 && Pow2Part<N>::odd_ok, "N = 2^a 3^b 5^c, b <= 1, c <= 2");
     fft_passes<R, N, NL, NT, rmax<R>(), 1, INV>(buf, tw);
 }
 
@@ -657,6 +681,56 @@ __global__ __launch_bounds__(NT) void k_invT_pre(const Slot* __restrict__ slots,
 //   MID_HLX: as MID_HL for v = P^, and in2 holds the spectrum of Phi: block sums
 //            of 1/2|k|^2 |Phi^_l|^2, 1/2|k|^2 Re Phi^_l conj(v_l), 1/2|k|^2 |v_l|^2.
 //   MID_PRE: A = v_l / (alpha_l + 1/2 |k|^2) / M.
+// Symbols at the wavenumber of middle-pass line `line` (the flattened
+// positions of the axes transformed before) and position m on the middle
+// axis: the kinetic symbol 1/2 |k|^2 from the wavenumbers, and k_x, k_y of
+// the odd operators (SOC, rotation) in their odd-operator reading.
+struct SpecK {
+    double K, kx, ky;
+};
+__device__ __forceinline__ SpecK spec_k(const Phys& p, int line, int m) {
+    int jx, jy, jz;
+    if (p.dim == 2) {
+        jx = line; jy = m; jz = 0;
+    } else {
+        jx = line % p.n[0]; jy = line / p.n[0]; jz = m;
+    }
+    const double wx = wavenum(jx, p.n[0], p.L[0]), wy = wavenum(jy, p.n[1], p.L[1]);
+    const double wz = p.dim == 3 ? wavenum(jz, p.n[2], p.L[2]) : 0.0;
+    return SpecK{0.5 * (wx * wx + wy * wy + wz * wz), wavenum_odd(jx, p.n[0], p.L[0], p.nyq_zero),
+                 wavenum_odd(jy, p.n[1], p.L[1], p.nyq_zero)};
+}
+// H_L's spectral part at one wavenumber for the three components v (the
+// spectra, unnormalised): a = (1/2 |k|^2 v - gamma S(k) v) / M with
+// S(k) = [[0, s0, 0], [s1, 0, s0], [0, s1, 0]], s0 = -k_x + i k_y (L0),
+// s1 = -k_x - i k_y (L1); the point's partial sums: 1/2 |k|^2 |v_l|^2 and
+// Re v^dag S v, or with the spectrum z of Phi (X2) 1/2 |k|^2 |z_l|^2,
+// 1/2 |k|^2 Re z_l conj(v_l) and 1/2 |k|^2 |v_l|^2.
+template <bool X2>
+__device__ __forceinline__ void hl_point(const SpecK& k, double gamma, double invM, const cpx<double> (&v)[3],
+                                         const cpx<double> (&z)[3], cpx<double> (&a)[3], double (&acc)[X2 ? 9 : 4]) {
+    const cpx<double> s0 = cmk(-k.kx, k.ky), s1 = cmk(-k.kx, -k.ky);
+    const cpx<double> S0 = cmul(s0, v[1]);
+    const cpx<double> S1 = cmul(s1, v[0]) + cmul(s0, v[2]);
+    const cpx<double> S2 = cmul(s1, v[1]);
+    if constexpr (X2) {
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+            acc[3 * cc] = k.K * cabs2(z[cc]);
+            acc[3 * cc + 1] = k.K * re_dot(z[cc], v[cc]);
+            acc[3 * cc + 2] = k.K * cabs2(v[cc]);
+        }
+    } else {
+        acc[0] = k.K * cabs2(v[0]);
+        acc[1] = k.K * cabs2(v[1]);
+        acc[2] = k.K * cabs2(v[2]);
+        acc[3] = cmulc(S0, v[0]).x + cmulc(S1, v[1]).x + cmulc(S2, v[2]).x;
+    }
+    a[0] = invM * (k.K * v[0] - gamma * S0);
+    a[1] = invM * (k.K * v[1] - gamma * S1);
+    a[2] = invM * (k.K * v[2] - gamma * S2);
+}
+
 // Values per thread of a middle pass over NLN lines, and whether the block
 // pipelines its line groups: the next group's input is loaded into registers
 // while the current one is transformed (when that takes at most 6 values).
@@ -722,8 +796,9 @@ __global__ __launch_bounds__(NT) void k_mid(const Slot* __restrict__ slots, int 
     constexpr bool HL = OP == MID_HL || OP == MID_HLX;
     constexpr bool X2 = OP == MID_HLX;
     constexpr int NVM = X2 ? NS_KIN : 4;   // partial sums per line group
-    static_assert(NT % 64 == 0 && (LPB * N) % 64 == 0, "line groups of whole chunks");
-    __shared__ double chs[HL ? LPB * N / 64 : 1][ChunkSums<NVM>::P];
+    static_assert(NT % 64 == 0, "whole waves");
+    constexpr int NQ = (LPB * N + 63) / 64;   // chunks of 64 points of a line group
+    __shared__ double chs[HL ? NQ : 1][ChunkSums<NVM>::P];
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     cpx<R>* X = reinterpret_cast<cpx<R>*>(smem_raw);
     cpx<R>* Z = X + NLN * PITCH;                       // spectrum of Phi (MID_HLX)
@@ -781,73 +856,48 @@ __global__ __launch_bounds__(NT) void k_mid(const Slot* __restrict__ slots, int 
             lds_fft<R, N, NLN, NT, false>(X, twl);
             if constexpr (X2) lds_fft<R, N, NLN, NT, false>(Z, twl);
         }
-        // the partial sums in chunks of 64 points (each one wave's iteration),
-        // so the row does not depend on NT
-        for (int e = threadIdx.x; e < LPB * N; e += NT) {
+        // the partial sums in chunks of 64 points (each one wave's iteration;
+        // the lanes past the group's last point add zeros), so the row does
+        // not depend on NT
+        for (int base = threadIdx.x & ~63; base < LPB * N; base += NT) {
+            const int e = base + (threadIdx.x & 63);
             double acc[NVM];
 #pragma unroll
             for (int k = 0; k < NVM; ++k) acc[k] = 0.0;
-            const int q = e / N, m = e - q * N;
-            const int line = l0 + q;
-            // kinetic symbol from the wavenumbers; the odd symbols (SOC, D_y)
-            // from their odd-operator reading
-            int jx, jy, jz;
-            if (p.dim == 2) {
-                jx = line; jy = m; jz = 0;
-            } else {
-                jx = line % p.n[0]; jy = line / p.n[0]; jz = m;
-            }
-            const double wx = wavenum(jx, p.n[0], p.L[0]), wy = wavenum(jy, p.n[1], p.L[1]);
-            const double wz = p.dim == 3 ? wavenum(jz, p.n[2], p.L[2]) : 0.0;
-            const double K = 0.5 * (wx * wx + wy * wy + wz * wz);
-            const double kx = wavenum_odd(jx, p.n[0], p.L[0], p.nyq_zero);
-            const double ky = wavenum_odd(jy, p.n[1], p.L[1], p.nyq_zero);
-            cpx<R>* x0 = X + (0 * LPB + q) * PITCH + lx(m);
-            cpx<R>* x1 = X + (1 * LPB + q) * PITCH + lx(m);
-            cpx<R>* x2 = X + (2 * LPB + q) * PITCH + lx(m);
-            if (HL) {
-                const cpx<double> v0 = wid(*x0), v1 = wid(*x1), v2 = wid(*x2);
-                const cpx<double> s0 = cmk(-kx, ky), s1 = cmk(-kx, -ky);
-                const cpx<double> S0 = cmul(s0, v1);
-                const cpx<double> S1 = cmul(s1, v0) + cmul(s0, v2);
-                const cpx<double> S2 = cmul(s1, v1);
-                if (X2) {
-                    const cpx<double> v[3] = {v0, v1, v2};
+            if (e < LPB * N) {
+                const int q = e / N, m = e - q * N;
+                const int line = l0 + q;
+                const SpecK sk = spec_k(p, line, m);
+                cpx<R>* x0 = X + (0 * LPB + q) * PITCH + lx(m);
+                cpx<R>* x1 = X + (1 * LPB + q) * PITCH + lx(m);
+                cpx<R>* x2 = X + (2 * LPB + q) * PITCH + lx(m);
+                if (HL) {
+                    const cpx<double> v[3] = {wid(*x0), wid(*x1), wid(*x2)};
+                    cpx<double> z[3] = {};
+                    if (X2)
 #pragma unroll
-                    for (int cc = 0; cc < 3; ++cc) {
-                        const cpx<double> z = wid(Z[(cc * LPB + q) * PITCH + lx(m)]);
-                        acc[3 * cc] += K * cabs2(z);
-                        acc[3 * cc + 1] += K * re_dot(z, v[cc]);
-                        acc[3 * cc + 2] += K * cabs2(v[cc]);
+                        for (int cc = 0; cc < 3; ++cc) z[cc] = wid(Z[(cc * LPB + q) * PITCH + lx(m)]);
+                    cpx<double> a[3];
+                    hl_point<X2>(sk, p.gamma, invM, v, z, a, acc);
+                    if (doB) {
+                        const double fb = sk.ky * invM;
+                        Y[(0 * LPB + q) * PITCH + lx(m)] = cmk((R)(fb * v[0].x), (R)(fb * v[0].y));
+                        Y[(1 * LPB + q) * PITCH + lx(m)] = cmk((R)(fb * v[1].x), (R)(fb * v[1].y));
+                        Y[(2 * LPB + q) * PITCH + lx(m)] = cmk((R)(fb * v[2].x), (R)(fb * v[2].y));
                     }
+                    *x0 = cmk((R)a[0].x, (R)a[0].y);
+                    *x1 = cmk((R)a[1].x, (R)a[1].y);
+                    *x2 = cmk((R)a[2].x, (R)a[2].y);
                 } else {
-                    acc[0] += K * cabs2(v0);
-                    acc[1] += K * cabs2(v1);
-                    acc[2] += K * cabs2(v2);
-                    acc[3] += cmulc(S0, v0).x + cmulc(S1, v1).x + cmulc(S2, v2).x;
+                    const R d0 = (R)(unit ? invM : invM / fmax(al[0] + sk.K, fl));
+                    const R d1 = (R)(unit ? invM : invM / fmax(al[1] + sk.K, fl));
+                    const R d2 = (R)(unit ? invM : invM / fmax(al[2] + sk.K, fl));
+                    *x0 = d0 * *x0;
+                    *x1 = d1 * *x1;
+                    *x2 = d2 * *x2;
                 }
-                const double gm = p.gamma;
-                const cpx<double> a0 = invM * (K * v0 - gm * S0);
-                const cpx<double> a1 = invM * (K * v1 - gm * S1);
-                const cpx<double> a2 = invM * (K * v2 - gm * S2);
-                if (doB) {
-                    const double fb = ky * invM;
-                    Y[(0 * LPB + q) * PITCH + lx(m)] = cmk((R)(fb * v0.x), (R)(fb * v0.y));
-                    Y[(1 * LPB + q) * PITCH + lx(m)] = cmk((R)(fb * v1.x), (R)(fb * v1.y));
-                    Y[(2 * LPB + q) * PITCH + lx(m)] = cmk((R)(fb * v2.x), (R)(fb * v2.y));
-                }
-                *x0 = cmk((R)a0.x, (R)a0.y);
-                *x1 = cmk((R)a1.x, (R)a1.y);
-                *x2 = cmk((R)a2.x, (R)a2.y);
-                chunk_add<NVM>(acc, chs, e >> 6);
-            } else {
-                const R d0 = (R)(unit ? invM : invM / fmax(al[0] + K, fl));
-                const R d1 = (R)(unit ? invM : invM / fmax(al[1] + K, fl));
-                const R d2 = (R)(unit ? invM : invM / fmax(al[2] + K, fl));
-                *x0 = d0 * *x0;
-                *x1 = d1 * *x1;
-                *x2 = d2 * *x2;
             }
+            if (HL) chunk_add<NVM>(acc, chs, e >> 6);   // the whole wave
         }
         __syncthreads();
         if constexpr (HL && JOINT) {
@@ -875,9 +925,127 @@ __global__ __launch_bounds__(NT) void k_mid(const Slot* __restrict__ slots, int 
                 if (doB) outB[go] = Y[L * PITCH + lx(m)];
             }
         }
-        if (HL) chunk_row<NVM>(chs, LPB * N / 64, red, RED_MID_STRIDE, grp);
+        if (HL) chunk_row<NVM>(chs, NQ, red, RED_MID_STRIDE, grp);
         __syncthreads();   // X, Z, Y, the copy and the chunk sums are refilled by the next group
     }
+}
+
+// ---------------------------------------------------------------------------
+// middle pass for lines longer than 1024 (2D, the y axis): the three
+// component lines of one position no longer fit in LDS together, so the pass
+// runs as three kernels: the forward transforms line by line (k_lfft), the
+// spectral operator on the whole spectrum with every component of a
+// wavenumber at hand (k_lspec, with the partial sums of the kinetic
+// coefficients in rows of a fixed pointwise grid), and the inverse
+// transforms line by line, which add the rotation term.
+// ---------------------------------------------------------------------------
+// One line of N contiguous values per block: forward (unscaled) or inverse
+// transform of the [ncomp][nlines][N] field iin into iout (in place when they
+// are equal: a block reads its whole line before it writes), blocks
+// [0, ncomp nlines) of a slot; with iin2 >= 0 the next 3 nlines blocks
+// transform the three components of iin2 into iout2, for rotating slots
+// only. With irot >= 0 (the inverse of the H_L output of a rotating slot) the
+// 2D rotation term is added to iout: Omega y k_x C / Nx, C the x-transformed
+// input of the chain at irot.
+template <typename R, int N, bool INV, int NT>
+__global__ __launch_bounds__(NT) void k_lfft(const Slot* __restrict__ slots, int iin, int iout, int ncomp,
+                                             int nlines, int irot, int iin2, int iout2,
+                                             const cpx<R>* __restrict__ tw) {
+    const Slot& S = slots[blockIdx.y];
+    const SolveState* st = as_global(S.st);
+    if (st->done) return;
+    const Phys p = S.p;
+    const bool second = (int)blockIdx.x >= ncomp * nlines;
+    if (second && p.omega == 0.0) return;
+    const int b = second ? (int)blockIdx.x - ncomp * nlines : (int)blockIdx.x;
+    const int c = b / nlines, l = b - c * nlines;
+    const long long off = (long long)c * nlines * N + (long long)l * N;
+    const cpx<R>* in = fld<R>(S, second ? iin2 : iin) + off;
+    cpx<R>* out = fld<R>(S, second ? iout2 : iout) + off;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
+    for (int m = threadIdx.x; m < N; m += NT) {
+        cpx<R> v;
+        ld2(v, in + m);
+        lds[lx(m)] = v;
+    }
+    __syncthreads();
+    lds_fft<R, N, 1, NT, INV>(lds, tw);
+    const bool rot = !second && irot >= 0 && p.omega != 0.0;
+    const cpx<R>* __restrict__ C = rot ? fld<R>(S, irot) + off : nullptr;
+    const double kx = rot ? wavenum_odd(l, p.n[0], p.L[0], p.nyq_zero) : 0.0;
+    for (int m = threadIdx.x; m < N; m += NT) {
+        cpx<R> v = lds[lx(m)];
+        if (rot) {
+            const double y = -p.L[1] + m * p.h[1];
+            v = v + (R)(p.omega * y * kx / p.n[0]) * C[m];
+        }
+        st2(out + m, v);
+    }
+}
+
+// Spectral operator of the middle pass on the whole spectrum in[c][line][m]
+// (components 3..5: the spectrum of Phi, for MID_HLX), one point per thread
+// in a grid-stride loop over the M points; outputs as in k_mid. The partial
+// sums of a block form row blockIdx.x of red_mid (gridDim.x rows, a function
+// of M only).
+template <typename R, int OP>
+__global__ __launch_bounds__(PT) void k_lspec(const Slot* __restrict__ slots, int iin, int ioutA, int ioutB,
+                                              int N, int rot_any) {
+    const Slot& S = slots[blockIdx.y];
+    const SolveState* st = as_global(S.st);
+    if (st->done) return;
+    const Phys p = S.p;
+    const long long M = p.M;
+    constexpr bool HL = OP == MID_HL || OP == MID_HLX;
+    constexpr bool X2 = OP == MID_HLX;
+    constexpr int NVM = X2 ? NS_KIN : 4;
+    const cpx<R>* __restrict__ in = fld<R>(S, iin);
+    cpx<R>* __restrict__ outA = fld<R>(S, ioutA);
+    const bool doB = HL && rot_any && p.omega != 0.0;
+    cpx<R>* __restrict__ outB = doB ? fld<R>(S, ioutB) : nullptr;
+    const double invM = 1.0 / (double)M;
+    double al[3] = {0.0, 0.0, 0.0}, fl = 0.0;
+    const bool unit = OP == MID_PRE && st->precond == GS_PC_POTENTIAL;
+    if (OP == MID_PRE) {
+        al[0] = st->alpha[0]; al[1] = st->alpha[1]; al[2] = st->alpha[2];
+        fl = 1e-12 * fmax(1.0, fmax(al[0], fmax(al[1], al[2])));
+    }
+    double tot[NVM];
+#pragma unroll
+    for (int k = 0; k < NVM; ++k) tot[k] = 0.0;
+    for (long long i = (long long)blockIdx.x * PT + threadIdx.x; i < M; i += (long long)gridDim.x * PT) {
+        const int line = (int)(i / N), m = (int)(i - (long long)line * N);
+        const SpecK sk = spec_k(p, line, m);
+        if (HL) {
+            const cpx<double> v[3] = {wid(in[i]), wid(in[M + i]), wid(in[2 * M + i])};
+            cpx<double> z[3] = {};
+            if (X2) {
+                z[0] = wid(in[3 * M + i]);
+                z[1] = wid(in[4 * M + i]);
+                z[2] = wid(in[5 * M + i]);
+            }
+            cpx<double> a[3];
+            double acc[NVM];
+            hl_point<X2>(sk, p.gamma, invM, v, z, a, acc);
+#pragma unroll
+            for (int k = 0; k < NVM; ++k) tot[k] += acc[k];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) outA[c * M + i] = cmk((R)a[c].x, (R)a[c].y);
+            if (doB) {
+                const double fb = sk.ky * invM;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) outB[c * M + i] = cmk((R)(fb * v[c].x), (R)(fb * v[c].y));
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const R d = (R)(unit ? invM : invM / fmax(al[c] + sk.K, fl));
+                outA[c * M + i] = d * in[c * M + i];
+            }
+        }
+    }
+    if (HL) block_row<NVM>(tot, as_global(S.red_mid), RED_MID_STRIDE);
 }
 
 }  // namespace gs

@@ -19,12 +19,13 @@ namespace gs {
 // last pass: its next tile then fits in registers (pipelined), and a lone
 // solve gets twice the blocks (measured at 256^2: same batch time, 10 instead
 // of 14 us per launch for one solve).
+// Lines longer than 1024 (1200, 2400) keep the LDS of a block near 82 KB.
 template <typename R> constexpr int tile_fwd(int N) {
-    return sizeof(R) == 8 ? (N >= 1024 ? 2 : (N >= 512 ? 4 : 8)) : (N >= 1024 ? 4 : 8);
+    return sizeof(R) == 8 ? (N >= 1024 ? 2 : (N >= 512 ? 4 : 8)) : (N > 1200 ? 2 : (N >= 1024 ? 4 : 8));
 }
 template <typename R> constexpr int tile_pre(int N) { return sizeof(R) == 8 ? (N >= 1024 ? 2 : 4) : tile_fwd<R>(N); }
 template <typename R> constexpr int tile_inv(int N) {
-    return sizeof(R) == 8 ? (N >= 512 ? 2 : 4) : (N >= 512 ? 4 : 8);
+    return sizeof(R) == 8 ? (N > 1200 ? 1 : (N >= 512 ? 2 : 4)) : (N > 1200 ? 2 : (N >= 512 ? 4 : 8));
 }
 // Line positions per block of the middle pass (its partial-sum rows are one
 // per group of lpb_mid lines: a function of the grid only).
@@ -72,8 +73,9 @@ template <typename R> constexpr bool pre_cand_fits(int N, int c) {
     return pre_cand<R>(N, c).tile * N <= CAND_MAX_EPT * pre_cand<R>(N, c).nt &&
            pre_cand<R>(N, c).tile * N >= pre_cand<R>(N, c).nt / 4;
 }
+// (lines longer than 1024 take the split middle pass: k_lfft, k_lspec)
 constexpr bool mid_cand_fits(int N, int c) {
-    return (c == 0 || nt_mid0(N) >> c >= 64) && 3 * lpb_mid(N) * N <= CAND_MAX_EPT * mid_cand(N, c).nt;
+    return N <= 1024 && (c == 0 || nt_mid0(N) >> c >= 64) && 3 * lpb_mid(N) * N <= CAND_MAX_EPT * mid_cand(N, c).nt;
 }
 
 inline int cu_count() {
@@ -129,6 +131,8 @@ static hipError_t mid_go(int ngroups, int nslots, int ntb, size_t lds, hipStream
     return hipGetLastError();
 }
 
+// the supported line lengths: 2^a (16..1024), 3 2^a (24..768), and the
+// lengths with factors of 5 of the paper's largest grids and their halvings
 #define GS_SWITCH_N(CALL)                        \
     switch (N) {                                 \
     case 16: return CALL(16);                    \
@@ -144,6 +148,12 @@ static hipError_t mid_go(int ngroups, int nslots, int ntb, size_t lds, hipStream
     case 256: return CALL(256);                  \
     case 512: return CALL(512);                  \
     case 1024: return CALL(1024);                \
+    case 80: return CALL(80);                    \
+    case 160: return CALL(160);                  \
+    case 300: return CALL(300);                  \
+    case 600: return CALL(600);                  \
+    case 1200: return CALL(1200);                \
+    case 2400: return CALL(2400);                \
     default: return hipErrorInvalidValue;        \
     }
 

@@ -254,6 +254,22 @@ template <typename R>
 hipError_t launch_mid(int N, int op, const Slot* slots, int nslots, int in, int outA, int outB, int nlines,
                       int rot_any, const cpx<R>* tw, int cand, hipStream_t s);
 
+// Middle pass of lines longer than 1024 (2D), split in three launches:
+// launch_lfft transforms the ncomp component lines of iin into iout (forward,
+// or inverse with inv; in place allowed) and, with iin2 >= 0, the three of
+// iin2 into iout2 for rotating slots; irot >= 0 adds the 2D rotation term
+// Omega y k_x C / Nx with C = field irot to the inverse of iin. launch_lspec
+// applies the spectral operator op to the whole spectrum in (the H_L output
+// in outA, the k_y part in outB for rotating slots, the partial sums in
+// red_mid rows, one per block of pw_blocks(N nlines)).
+template <typename R>
+hipError_t launch_lfft(int N, int inv, const Slot* slots, int nslots, int iin, int iout, int ncomp, int nlines,
+                       int irot, int iin2, int iout2, const cpx<R>* tw, hipStream_t s);
+template <typename R>
+hipError_t launch_lspec(int op, const Slot* slots, int nslots, int in, int outA, int outB, int N, int nlines,
+                        int rot_any, hipStream_t s);
+constexpr int LONG_LINE = 1024;   // middle axes longer than this take the split pass
+
 int mid_blocks(int N, int nlines);
 // blocks (= partial-sum rows) of launch_invT_pre for these sizes
 template <typename R> int invT_pre_blocks(int N, int B, int Cc);

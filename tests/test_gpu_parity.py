@@ -41,6 +41,13 @@ GRIDS = [
     (2, (96, 48), (8.0, 6.0)),
     (2, (24, 768), (4.0, 16.0)),
     (3, (48, 24, 96), (6.0, 5.0, 8.0)),
+    # factors of 5 (a radix-5 pass) and lines longer than 1024: the x axis in
+    # the transposing passes, the y axis as the middle axis
+    (2, (2400, 16), (20.0, 2.0)),
+    (2, (160, 2400), (8.0, 20.0)),
+    (2, (600, 1200), (10.0, 20.0)),
+    (2, (80, 300), (8.0, 8.0)),
+    (3, (80, 16, 300), (6.0, 5.0, 8.0)),
 ]
 
 
@@ -82,10 +89,19 @@ def _problems():
         inputs.Problem(dim=2, n=(96, 48), L=(10.0, 8.0), omega=0.6, gamma=1.0, c0=500.0, c1=-2.0),
         inputs.Problem(dim=3, n=(24, 48, 24), L=(7.0, 8.0, 7.0), g=(1.0, 1.0, 2.0), omega=0.5,
                        gamma=1.0, c0=800.0, c1=5.0),
+        # the trap of Example 5's second case, eq. (4.1), rotating at Omega = 3, on
+        # a strip of its domain with the 2400-point axis as the middle axis
+        inputs.Problem(dim=2, n=(160, 2400), L=(8.0, 20.0), g=(0.0, 0.0, 0.0), q2=-0.2, q4=0.5,
+                       omega=3.0, gamma=0.8, c0=1000.0, c1=1.0),
+        # the 2400-point axis along x (transposing passes), 80 points along y
+        inputs.Problem(dim=2, n=(2400, 80), L=(20.0, 8.0), omega=0.6, gamma=1.0, c0=500.0, c1=-2.0),
+        # 3D, a 300-point middle axis (line groups that end in a partial wave chunk)
+        inputs.Problem(dim=3, n=(16, 80, 300), L=(6.0, 7.0, 9.0), g=(1.0, 1.0, 0.8), omega=0.4,
+                       gamma=0.7, c0=300.0, c1=-1.0),
     ]
 
 
-@pytest.mark.parametrize("k", range(7))
+@pytest.mark.parametrize("k", range(10))
 @pytest.mark.parametrize("prec", [gs.GS_FP64, gs.GS_FP32])
 def test_hamiltonian_and_energy(gpu_ctx, k, prec):
     pb = _problems()[k]
@@ -126,7 +142,7 @@ def test_hamiltonian_user_potential(gpu_ctx):
     assert np.isnan(res["virial"])
 
 
-@pytest.mark.parametrize("k", [0, 1, 3])
+@pytest.mark.parametrize("k", [0, 1, 3, 7, 8, 9])
 @pytest.mark.parametrize("prec", [gs.GS_FP64, gs.GS_FP32])
 def test_preconditioner(gpu_ctx, k, prec):
     pb = _problems()[k]
@@ -407,6 +423,24 @@ def test_solve_radix3_grid(gpu_ctx):
     assert res["status"] == 0 and ref.status == 0
     assert rel(res["E"], ev["E"]) < 1e-10
     assert rel(res["mu"], ev["mu"]) < 1e-8
+
+
+def test_solve_long_middle_axis(gpu_ctx):
+    """A 32 x 1200 grid, rotating: the 1200-point y axis takes the split middle
+    pass (line transforms, the operator over the whole spectrum, the rotation
+    term in the inverse) in both the preconditioner and H_L, with radix-5
+    passes; residual stop, against the oracle's PCG from the same guess."""
+    pb = inputs.Problem(dim=2, n=(32, 1200), L=(6.0, 24.0), g=(1.0, 0.25, 1.0), omega=0.2, gamma=0.5,
+                        c0=100.0, c1=-0.5)
+    psi0 = inputs.initial_guess(pb, ("b", "a", "a"))
+    ref, ev, psi, res = _solve_both(gpu_ctx, pb, psi0, gs.GS_STOP_RESIDUAL, 1e-10)
+    d_psi, d_rho = aligned_errors(psi, ref.psi)
+    print(f"[solve 32x1200] gpu E={res['E']!r} it={res['iters']} | oracle E={ev['E']!r} it={ref.iters} "
+          f"d_psi={d_psi:.1e} d_rho={d_rho:.1e}", flush=True)
+    assert res["status"] == 0 and ref.status == 0
+    assert rel(res["E"], ev["E"]) < 1e-10
+    assert rel(res["mu"], ev["mu"]) < 1e-10
+    assert d_rho < 1e-6
 
 
 def test_solve_3d_small(gpu_ctx):
