@@ -87,9 +87,10 @@ extern "C" {
 typedef struct gs_ctx gs_ctx;
 
 /* Grid: dim = 2 or 3; n[a] points on [-L[a], L[a]] along x, y, z. Each n[a]
- * is 2^k in [16, 1024], 3 * 2^k in [24, 768], or one of 80, 160, 300, 600,
+ * is 2^k in [16, 1024], 3 * 2^k in [24, 768], or one of 80, 160, 600,
  * 1200, 2400 (the 2400-point grid of Example 5's second case, eq. (4.1), and
- * its halvings); lengths above 1024 in 2D only. Sec. 3.2 requires N even; the
+ * its halvings down to 600; every length is a multiple of 8); lengths above
+ * 1024 in 2D only. Sec. 3.2 requires N even; the
  * transforms are Stockham passes of radix 3, 5 and powers of two. */
 typedef struct {
     int dim;

@@ -47,10 +47,11 @@ static int fail(int code, const std::string& msg) {
     } while (0)
 
 // supported line lengths: 2^a in [16, 1024], 3 * 2^a in [24, 768], and
-// 80, 160, 300, 600, 1200, 2400 (factors of 5: 2400 = 2^5 3 5^2 and its
-// halvings); lengths above 1024 in 2D only
+// 80, 160, 600, 1200, 2400 (factors of 5: 2400 = 2^5 3 5^2 and its halvings
+// that are multiples of 8, the largest tile of a transposing pass); lengths
+// above 1024 in 2D only
 static bool size_supported(int n) {
-    if (n == 80 || n == 160 || n == 300 || n == 600 || n == 1200 || n == 2400) return true;
+    if (n == 80 || n == 160 || n == 600 || n == 1200 || n == 2400) return true;
     const int m = (n % 3 == 0) ? n / 3 : n;
     return n >= 16 && n <= 1024 && m >= 1 && (m & (m - 1)) == 0 && (n % 3 != 0 || n >= 24);
 }
@@ -61,7 +62,7 @@ static int check_grid(const gs_grid* g) {
     for (int a = 0; a < g->dim; ++a) {
         if (!size_supported(g->n[a]))
             return fail(GS_EINVAL, "grid.n[a] must be 2^a in [16, 1024], 3 * 2^a in [24, 768], "
-                                   "or one of 80, 160, 300, 600, 1200, 2400");
+                                   "or one of 80, 160, 600, 1200, 2400");
         if (g->dim == 3 && g->n[a] > LONG_LINE) return fail(GS_EINVAL, "lengths above 1024 are for 2D grids");
         if (!(g->L[a] > 0.0) || !std::isfinite(g->L[a])) return fail(GS_EINVAL, "grid.L[a] must be positive");
     }
@@ -1630,7 +1631,7 @@ static int fft_impl(Ctx& cx, const gs_grid* g, int sign, const cpx<R>* in, cpx<R
 // time (different streams or host threads) race.
 constexpr long long NA_MAX_POINTS = 1LL << 18;
 constexpr size_t NA_HDR = 4096;            // descriptor at 0, solver state at 1024
-constexpr int NA_LENGTHS[] = {16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 80, 160, 300, 600, 1200, 2400};
+constexpr int NA_LENGTHS[] = {16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 80, 160, 600, 1200, 2400};
 constexpr int NA_NLEN = (int)(sizeof(NA_LENGTHS) / sizeof(NA_LENGTHS[0]));
 constexpr size_t na_tw_bytes() {
     size_t b = 0;

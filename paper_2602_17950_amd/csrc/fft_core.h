@@ -36,6 +36,30 @@ template <int N> struct Lay {
     static constexpr int P = (N + N / 16) | 1;
 };
 __device__ __forceinline__ int lx(int e) { return e + (e >> 4); }
+__host__ __device__ constexpr int lxc(int e) { return e + (e >> 4); }
+
+// Whether the LDS offsets of the RAD values of a Stockham butterfly (see
+// fft_pass) from its first value are the same for every butterfly j: the
+// reads at j + r N/RAD (RD), the writes at db + r NS, db = (j - k) RAD + k,
+// k = j mod NS (WR). Checked at compile time over every j.
+template <int N, int RAD, int NS> struct PassIdx {
+    static constexpr int NB = N / RAD;
+    static constexpr bool rd() {
+        for (int j = 0; j < NB; ++j)
+            for (int r = 1; r < RAD; ++r)
+                if (lxc(j + r * NB) - lxc(j) != lxc(r * NB)) return false;
+        return true;
+    }
+    static constexpr bool wr() {
+        for (int j = 0; j < NB; ++j) {
+            const int k = j % NS, db = (j - k) * RAD + k;
+            for (int r = 1; r < RAD; ++r)
+                if (lxc(db + r * NS) - lxc(db) != lxc(r * NS)) return false;
+        }
+        return true;
+    }
+    static constexpr bool RD = rd(), WR = wr();
+};
 
 // Workgroups are dispatched to the 8 XCDs in turn, and each XCD has its own
 // L2. The transposed passes read tiles of TILE values per line position, 32
@@ -178,8 +202,11 @@ __device__ __forceinline__ void dftr(cpx<R> (&v)[RAD]) {
 // butterfly j of a line reads x[j + r N/RAD], applies the twiddles of the
 // pass, transforms, and writes to (j - k) RAD + k + r NS with k = j mod NS
 // (NS = product of the radices of the earlier passes). tw[m] = exp(-2 pi i m / N).
+// When the LDS offsets of a butterfly's RAD reads (or writes) from its first
+// one are the same for every butterfly, they are compile-time constants.
 template <typename R, int N, int NL, int NT, int RAD, int NS, bool INV>
 __device__ __forceinline__ void fft_pass(cpx<R>* buf, const cpx<R>* __restrict__ tw) {
+    using PI = PassIdx<N, RAD, NS>;
     constexpr int NB = N / RAD;
     constexpr int TOT = NL * NB;
     constexpr int BPT = (TOT + NT - 1) / NT;
@@ -195,8 +222,14 @@ __device__ __forceinline__ void fft_pass(cpx<R>* buf, const cpx<R>* __restrict__
             const int l = b / NB, j = b - l * NB;
             const int k = j % NS;
             const cpx<R>* src = buf + l * P;
+            if constexpr (PI::RD) {
+                const cpx<R>* s0 = src + lx(j);
 #pragma unroll
-            for (int r = 0; r < RAD; ++r) v[i][r] = src[lx(j + r * NB)];
+                for (int r = 0; r < RAD; ++r) v[i][r] = s0[lxc(r * NB)];
+            } else {
+#pragma unroll
+                for (int r = 0; r < RAD; ++r) v[i][r] = src[lx(j + r * NB)];
+            }
             if constexpr (NS > 1) {
                 if constexpr (sizeof(R) == 4) {
                     // float: the running product in double from the double table
@@ -231,8 +264,14 @@ __device__ __forceinline__ void fft_pass(cpx<R>* buf, const cpx<R>* __restrict__
 #pragma unroll
     for (int i = 0; i < BPT; ++i) {
         if (lb[i] >= 0) {
+            if constexpr (PI::WR) {
+                cpx<R>* d0 = buf + lb[i] + lx(db[i]);
 #pragma unroll
-            for (int r = 0; r < RAD; ++r) buf[lb[i] + lx(db[i] + r * NS)] = v[i][r];
+                for (int r = 0; r < RAD; ++r) d0[lxc(r * NS)] = v[i][r];
+            } else {
+#pragma unroll
+                for (int r = 0; r < RAD; ++r) buf[lb[i] + lx(db[i] + r * NS)] = v[i][r];
+            }
         }
     }
     __syncthreads();
@@ -271,7 +310,8 @@ template <int N> struct Pow2Part {
 template <typename R> constexpr int rmax() { return sizeof(R) == 8 ? 8 : 16; }
 
 // Transform NL lines of length N held in LDS (layout Lay<N>, line l at
-// buf + l * Lay<N>::P; natural order in and out, unnormalised).
+// buf + l * Lay<N>::P; natural order in and out, unnormalised). The
+// radices, and so the bits of the result, do not depend on NT.
 template <typename R, int N, int NL, int NT, bool INV>
 __device__ __forceinline__ void lds_fft(cpx<R>* buf, const cpx<R>* __restrict__ tw) {
     static_assert(N >= 16 && N <= 2400 && Pow2Part<N>::odd_ok, "N = 2^a 3^b 5^c, b <= 1, c <= 2");
@@ -731,6 +771,51 @@ __device__ __forceinline__ void hl_point(const SpecK& k, double gamma, double in
     a[2] = invM * (k.K * v[2] - gamma * S2);
 }
 
+// The spectral operator of a middle pass at point e of a line group (line
+// l0 + e / N, position e mod N of the middle axis), on the group's spectra in
+// LDS: X (three components, line c LPB + q at X + (c LPB + q) PITCH), for
+// MID_HLX Z (Phi's spectrum, same layout), for a rotating slot the output Y
+// (the k_y part, same layout; Y may take Z's place: the point's Z values are
+// read before its Y values are written). acc: the point's partial sums.
+template <typename R, int N, int LPB, int OP>
+__device__ __forceinline__ void mid_point(const Phys& p, int l0, int e, cpx<R>* X, const cpx<R>* Z, cpx<R>* Y,
+                                          bool doB, double invM, bool unit, const double (&al)[3], double fl,
+                                          double (&acc)[OP == MID_HLX ? NS_KIN : 4]) {
+    constexpr int PITCH = Lay<N>::P;
+    constexpr bool HL = OP == MID_HL || OP == MID_HLX;
+    constexpr bool X2 = OP == MID_HLX;
+    const int q = e / N, m = e - q * N;
+    const SpecK sk = spec_k(p, l0 + q, m);
+    cpx<R>* x0 = X + (0 * LPB + q) * PITCH + lx(m);
+    cpx<R>* x1 = X + (1 * LPB + q) * PITCH + lx(m);
+    cpx<R>* x2 = X + (2 * LPB + q) * PITCH + lx(m);
+    if constexpr (HL) {
+        const cpx<double> v[3] = {wid(*x0), wid(*x1), wid(*x2)};
+        cpx<double> z[3] = {};
+        if constexpr (X2)
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) z[cc] = wid(Z[(cc * LPB + q) * PITCH + lx(m)]);
+        cpx<double> a[3];
+        hl_point<X2>(sk, p.gamma, invM, v, z, a, acc);
+        if (doB) {
+            const double fb = sk.ky * invM;
+            Y[(0 * LPB + q) * PITCH + lx(m)] = cmk((R)(fb * v[0].x), (R)(fb * v[0].y));
+            Y[(1 * LPB + q) * PITCH + lx(m)] = cmk((R)(fb * v[1].x), (R)(fb * v[1].y));
+            Y[(2 * LPB + q) * PITCH + lx(m)] = cmk((R)(fb * v[2].x), (R)(fb * v[2].y));
+        }
+        *x0 = cmk((R)a[0].x, (R)a[0].y);
+        *x1 = cmk((R)a[1].x, (R)a[1].y);
+        *x2 = cmk((R)a[2].x, (R)a[2].y);
+    } else {
+        const R d0 = (R)(unit ? invM : invM / fmax(al[0] + sk.K, fl));
+        const R d1 = (R)(unit ? invM : invM / fmax(al[1] + sk.K, fl));
+        const R d2 = (R)(unit ? invM : invM / fmax(al[2] + sk.K, fl));
+        *x0 = d0 * *x0;
+        *x1 = d1 * *x1;
+        *x2 = d2 * *x2;
+    }
+}
+
 // Values per thread of a middle pass over NLN lines, and whether the block
 // pipelines its line groups: the next group's input is loaded into registers
 // while the current one is transformed (when that takes at most 6 values).
@@ -864,39 +949,8 @@ __global__ __launch_bounds__(NT) void k_mid(const Slot* __restrict__ slots, int 
             double acc[NVM];
 #pragma unroll
             for (int k = 0; k < NVM; ++k) acc[k] = 0.0;
-            if (e < LPB * N) {
-                const int q = e / N, m = e - q * N;
-                const int line = l0 + q;
-                const SpecK sk = spec_k(p, line, m);
-                cpx<R>* x0 = X + (0 * LPB + q) * PITCH + lx(m);
-                cpx<R>* x1 = X + (1 * LPB + q) * PITCH + lx(m);
-                cpx<R>* x2 = X + (2 * LPB + q) * PITCH + lx(m);
-                if (HL) {
-                    const cpx<double> v[3] = {wid(*x0), wid(*x1), wid(*x2)};
-                    cpx<double> z[3] = {};
-                    if (X2)
-#pragma unroll
-                        for (int cc = 0; cc < 3; ++cc) z[cc] = wid(Z[(cc * LPB + q) * PITCH + lx(m)]);
-                    cpx<double> a[3];
-                    hl_point<X2>(sk, p.gamma, invM, v, z, a, acc);
-                    if (doB) {
-                        const double fb = sk.ky * invM;
-                        Y[(0 * LPB + q) * PITCH + lx(m)] = cmk((R)(fb * v[0].x), (R)(fb * v[0].y));
-                        Y[(1 * LPB + q) * PITCH + lx(m)] = cmk((R)(fb * v[1].x), (R)(fb * v[1].y));
-                        Y[(2 * LPB + q) * PITCH + lx(m)] = cmk((R)(fb * v[2].x), (R)(fb * v[2].y));
-                    }
-                    *x0 = cmk((R)a[0].x, (R)a[0].y);
-                    *x1 = cmk((R)a[1].x, (R)a[1].y);
-                    *x2 = cmk((R)a[2].x, (R)a[2].y);
-                } else {
-                    const R d0 = (R)(unit ? invM : invM / fmax(al[0] + sk.K, fl));
-                    const R d1 = (R)(unit ? invM : invM / fmax(al[1] + sk.K, fl));
-                    const R d2 = (R)(unit ? invM : invM / fmax(al[2] + sk.K, fl));
-                    *x0 = d0 * *x0;
-                    *x1 = d1 * *x1;
-                    *x2 = d2 * *x2;
-                }
-            }
+            if (e < LPB * N)
+                mid_point<R, N, LPB, OP>(p, l0, e, X, Z, Y, doB, invM, unit, al, fl, acc);
             if (HL) chunk_add<NVM>(acc, chs, e >> 6);   // the whole wave
         }
         __syncthreads();

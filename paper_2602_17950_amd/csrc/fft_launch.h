@@ -150,7 +150,6 @@ static hipError_t mid_go(int ngroups, int nslots, int ntb, size_t lds, hipStream
     case 1024: return CALL(1024);                \
     case 80: return CALL(80);                    \
     case 160: return CALL(160);                  \
-    case 300: return CALL(300);                  \
     case 600: return CALL(600);                  \
     case 1200: return CALL(1200);                \
     case 2400: return CALL(2400);                \

@@ -100,7 +100,8 @@ __device__ __forceinline__ void trap_at(const Phys& p, long long i, double x, do
 // p = j for j < n/2 and j - n otherwise (the mode -n/2 is kept), k = pi p / L
 __device__ __forceinline__ double wavenum(int j, int n, double L) {
     int p = (j < n / 2) ? j : j - n;
-    return 3.141592653589793238462643 * (double)p / L;
+    // pi / L is the same for every point of a kernel: computed once per thread
+    return (3.141592653589793238462643 / L) * (double)p;
 }
 // the same wavenumber in the symbol of an odd operator (D_x, D_y, D_z, hence
 // L0, L1, L_z): zero at the mode -n/2 when the problem selects that reading

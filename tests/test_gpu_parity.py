@@ -46,8 +46,8 @@ GRIDS = [
     (2, (2400, 16), (20.0, 2.0)),
     (2, (160, 2400), (8.0, 20.0)),
     (2, (600, 1200), (10.0, 20.0)),
-    (2, (80, 300), (8.0, 8.0)),
-    (3, (80, 16, 300), (6.0, 5.0, 8.0)),
+    (2, (80, 600), (8.0, 8.0)),
+    (3, (80, 16, 600), (6.0, 5.0, 8.0)),
 ]
 
 
@@ -95,8 +95,8 @@ def _problems():
                        omega=3.0, gamma=0.8, c0=1000.0, c1=1.0),
         # the 2400-point axis along x (transposing passes), 80 points along y
         inputs.Problem(dim=2, n=(2400, 80), L=(20.0, 8.0), omega=0.6, gamma=1.0, c0=500.0, c1=-2.0),
-        # 3D, a 300-point middle axis (line groups that end in a partial wave chunk)
-        inputs.Problem(dim=3, n=(16, 80, 300), L=(6.0, 7.0, 9.0), g=(1.0, 1.0, 0.8), omega=0.4,
+        # 3D, a 600-point middle axis (line groups that end in a partial wave chunk)
+        inputs.Problem(dim=3, n=(16, 80, 600), L=(6.0, 7.0, 9.0), g=(1.0, 1.0, 0.8), omega=0.4,
                        gamma=0.7, c0=300.0, c1=-1.0),
     ]
 
