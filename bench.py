@@ -474,9 +474,9 @@ def main():
         sw = Batch(torch, [(pb, inputs.initial_guess(pb, k)) for pb, k in spec])
         out = {}
         E = {}
-        for name, prec in (("fp64", gs.GS_FP64), ("mixed", gs.GS_MIXED)):
-            opt = gs.default_options(precision=prec, tol=1e-12,
-                                     dir_precision=mdir if prec == gs.GS_MIXED else gs.GS_FP64)
+        for name, prec, dirp in (("fp64", gs.GS_FP64, gs.GS_FP64), ("mixed", gs.GS_MIXED, mdir),
+                                 ("fp64_state_fp32_dir", gs.GS_FP64, gs.GS_FP32)):
+            opt = gs.default_options(precision=prec, tol=1e-12, dir_precision=dirp)
             t = time.perf_counter()
             rs = ctx.batch_solve(sw.requests(opt))
             dt = time.perf_counter() - t
@@ -490,11 +490,23 @@ def main():
         out["counted"] = sum(1 for x in d if x < DE_GATE)
         out["counted_solves_per_s"] = out["counted"] / out["mixed"]["s"]
         out["speedup_counted"] = out["counted_solves_per_s"] / out["fp64"]["solves_per_s"]
+        # where the other solves end: a lower or a higher local minimum than the FP64 run's
+        for name in ("mixed", "fp64_state_fp32_dir"):
+            sgn = [(a - b) / max(abs(b), 1.0) for a, b in zip(E[name], E["fp64"])]
+            out[name]["same_minimum"] = sum(1 for x in sgn if abs(x) < DE_GATE)
+            out[name]["lower_energy"] = sum(1 for x in sgn if x <= -DE_GATE)
+            out[name]["higher_energy"] = sum(1 for x in sgn if x >= DE_GATE)
+            out[name]["log10_dE_histogram"] = {
+                "edges": [-17, -12, -10, -8, -6, -4, -2, 1],
+                "counts": np.histogram(np.log10(np.maximum(np.abs(sgn), 1e-17)),
+                                       bins=[-17, -12, -10, -8, -6, -4, -2, 1])[0].tolist()}
         out["workload"] = ("96 2D solves, n uniform over {128,256,512}, L=16, Omega~U[0,0.9], SOC~U[0,2], "
                            "c0~U[100,2000], c1~U[-5,5], guesses over {(a,a,a),(b,a,a),(f,f,f)}, seed 17950; "
                            "energy criterion 1e-12, one batch")
         out["note"] = ("solves whose mixed and FP64 runs end in different local minima are not counted "
-                       "(the landscape of the rotating problems has many)")
+                       "(the landscape of the rotating problems has many); fp64_state_fp32_dir (no float "
+                       "phase, only the search direction rounded to float) shows that any float rounding on "
+                       "the path moves about half of these solves to another minimum, as often lower as higher")
         line["sweep"] = out
         cap = out["mixed"]["solves_per_s"]
         del sw

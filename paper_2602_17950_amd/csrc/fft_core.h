@@ -231,6 +231,8 @@ __device__ __forceinline__ void fft_pass(cpx<R>* buf, const cpx<R>* __restrict__
                 for (int r = 0; r < RAD; ++r) v[i][r] = src[lx(j + r * NB)];
             }
             if constexpr (NS > 1) {
+                // (forming the powers costs less than loading each from the
+                // table: measured)
                 if constexpr (sizeof(R) == 4) {
                     // float: the running product in double from the double table
                     // that follows the float one (N entries on), each power
@@ -740,6 +742,15 @@ __device__ __forceinline__ SpecK spec_k(const Phys& p, int line, int m) {
     return SpecK{0.5 * (wx * wx + wy * wy + wz * wz), wavenum_odd(jx, p.n[0], p.L[0], p.nyq_zero),
                  wavenum_odd(jy, p.n[1], p.L[1], p.nyq_zero)};
 }
+// 1/x for a positive, finite, normal x: the hardware estimate refined by two
+// Newton steps r <- r + r (1 - x r), each of which squares the relative
+// error (to below 1 ulp, from the estimate's ~2^-26)
+__device__ __forceinline__ double recip_pos(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+
 // H_L's spectral part at one wavenumber for the three components v (the
 // spectra, unnormalised): a = (1/2 |k|^2 v - gamma S(k) v) / M with
 // S(k) = [[0, s0, 0], [s1, 0, s0], [0, s1, 0]], s0 = -k_x + i k_y (L0),
@@ -807,9 +818,9 @@ __device__ __forceinline__ void mid_point(const Phys& p, int l0, int e, cpx<R>* 
         *x1 = cmk((R)a[1].x, (R)a[1].y);
         *x2 = cmk((R)a[2].x, (R)a[2].y);
     } else {
-        const R d0 = (R)(unit ? invM : invM / fmax(al[0] + sk.K, fl));
-        const R d1 = (R)(unit ? invM : invM / fmax(al[1] + sk.K, fl));
-        const R d2 = (R)(unit ? invM : invM / fmax(al[2] + sk.K, fl));
+        const R d0 = (R)(unit ? invM : invM * recip_pos(fmax(al[0] + sk.K, fl)));
+        const R d1 = (R)(unit ? invM : invM * recip_pos(fmax(al[1] + sk.K, fl)));
+        const R d2 = (R)(unit ? invM : invM * recip_pos(fmax(al[2] + sk.K, fl)));
         *x0 = d0 * *x0;
         *x1 = d1 * *x1;
         *x2 = d2 * *x2;
@@ -1094,7 +1105,7 @@ __global__ __launch_bounds__(PT) void k_lspec(const Slot* __restrict__ slots, in
         } else {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const R d = (R)(unit ? invM : invM / fmax(al[c] + sk.K, fl));
+                const R d = (R)(unit ? invM : invM * recip_pos(fmax(al[c] + sk.K, fl)));
                 outA[c * M + i] = d * in[c * M + i];
             }
         }
