@@ -579,6 +579,9 @@ def main():
                     if r is not None:
                         done[i] = r
                         del tickets[i]
+                        if len(done) % 40 == 0:
+                            log(f"serve load {load}: {len(done)} of {len(spec)} done after "
+                                f"{time.perf_counter() - t0:.0f}s")
                 if len(done) < len(spec):
                     if tickets:
                         ctx.progress(block=pending >= len(spec) or

@@ -684,6 +684,8 @@ __global__ __launch_bounds__(NT) void k_invT_pre(const Slot* __restrict__ slots,
     // as the other passes do raised the register count and lost occupancy:
     // measured slower); the partial sums of a chunk are reduced by its wave,
     // so the unit's row does not depend on NT
+    // (two points per lane before the wave's tree, as in the middle pass, was
+    // measured slower here: 103 -> 110 us for the float pass at 32 slots of 256^2)
     for (int base = threadIdx.x & ~63; base < TILE * N; base += NT) {
         const int e = base + (threadIdx.x & 63);
         double acc[NS_DIR] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -893,7 +895,13 @@ __global__ __launch_bounds__(NT) void k_mid(const Slot* __restrict__ slots, int 
     constexpr bool X2 = OP == MID_HLX;
     constexpr int NVM = X2 ? NS_KIN : 4;   // partial sums per line group
     static_assert(NT % 64 == 0, "whole waves");
-    constexpr int NQ = (LPB * N + 63) / 64;   // chunks of 64 points of a line group
+    // the group's points in chunks of 64 KP points: lane l of the wave that takes a
+    // chunk adds the sums of points l, l + 64, ..., l + 64 (KP - 1) of it in that
+    // order before the wave's halving tree, which then runs once per KP points
+    // (at 32 slots of 256^2, KP = 2 took hl_mid from 63 to 60 us in float; four
+    // points per lane, one chunk and one busy wave per group, 69 us)
+    constexpr int KP = LPB * N >= 512 ? 4 : (LPB * N >= 256 ? 2 : 1);
+    constexpr int NQ = (LPB * N + 64 * KP - 1) / (64 * KP);
     __shared__ double chs[HL ? NQ : 1][ChunkSums<NVM>::P];
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     cpx<R>* X = reinterpret_cast<cpx<R>*>(smem_raw);
@@ -952,17 +960,24 @@ __global__ __launch_bounds__(NT) void k_mid(const Slot* __restrict__ slots, int 
             lds_fft<R, N, NLN, NT, false>(X, twl);
             if constexpr (X2) lds_fft<R, N, NLN, NT, false>(Z, twl);
         }
-        // the partial sums in chunks of 64 points (each one wave's iteration;
-        // the lanes past the group's last point add zeros), so the row does
-        // not depend on NT
-        for (int base = threadIdx.x & ~63; base < LPB * N; base += NT) {
-            const int e = base + (threadIdx.x & 63);
+        // the partial sums per chunk (one wave's iteration; the lanes past the
+        // group's last point add zeros), so the row does not depend on NT
+        for (int base = (threadIdx.x & ~63) * KP; base < LPB * N; base += NT * KP) {
             double acc[NVM];
 #pragma unroll
             for (int k = 0; k < NVM; ++k) acc[k] = 0.0;
-            if (e < LPB * N)
-                mid_point<R, N, LPB, OP>(p, l0, e, X, Z, Y, doB, invM, unit, al, fl, acc);
-            if (HL) chunk_add<NVM>(acc, chs, e >> 6);   // the whole wave
+#pragma unroll
+            for (int j = 0; j < KP; ++j) {
+                const int e = base + 64 * j + (threadIdx.x & 63);
+                if (e < LPB * N) {
+                    double a1[NVM];
+                    mid_point<R, N, LPB, OP>(p, l0, e, X, Z, Y, doB, invM, unit, al, fl, a1);
+                    if constexpr (HL)
+#pragma unroll
+                        for (int k = 0; k < NVM; ++k) acc[k] += a1[k];
+                }
+            }
+            if (HL) chunk_add<NVM>(acc, chs, base / (64 * KP));   // the whole wave
         }
         __syncthreads();
         if constexpr (HL && JOINT) {
