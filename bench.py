@@ -50,6 +50,9 @@ KERNEL_SOURCES = ("paper_2602_17950_amd/csrc/fft_core.h", "paper_2602_17950_amd/
                   "paper_2602_17950_amd/csrc/gs_internal.h")
 TRAFFIC_SUMMARY = "profiles/hbm_traffic_kernels256.md"
 SECTIONS = ("headline", "kernels", "tuner", "single", "c1", "cm3d", "sweep", "table2", "serve")
+# host-only sections, run only when named (the oracle on the sweep's 128^2 solves
+# takes about an hour of host time)
+EXTRA_SECTIONS = ("c4oracle",)
 KINDS = ("hl_fwd", "hl_mid", "hl_inv", "pre_fwd", "pre_mid", "pre_inv", "resid", "lsred", "ctrl", "eval")
 # Table 2 (Example 3): lowest energy over the 1000 guess combinations of Sec. 4, and the
 # paper's CM-PCG CPU seconds for that one solve (a Xeon Gold 6248R, threads not stated;
@@ -229,6 +232,38 @@ class Batch:
         return [(pb, g, o, opt, None) for pb, g, o in zip(self.probs, self.guess, self.out)]
 
 
+def host_sections(sections, args):
+    """Sections that run on the host only: `c4oracle`, the FP64 oracle on the
+    128^2 solves of the 96-solve sweep (energy criterion 1e-12, all host cores,
+    each solve to completion)."""
+    import numpy as np
+    from paper_2602_17950_amd import inputs
+    import oracle as O
+    line = {"metric": METRIC, "data": "synthetic", "n_gpus": 0}
+    if "c4oracle" in sections:
+        cores = os.cpu_count() or 1
+        O.set_threads(cores)
+        spec = inputs.workload_sweep_2d()
+        idx = [i for i, (pb, _) in enumerate(spec) if pb.n[0] == 128]
+        rows = []
+        t_all = time.perf_counter()
+        for k, i in enumerate(idx):
+            pb, kinds = spec[i]
+            g, t, p = oracle_objects(O, pb)
+            t0 = time.perf_counter()
+            r = O.pcg(g, t, p, inputs.initial_guess(pb, kinds), O.Options(tol=1e-12))
+            dt = time.perf_counter() - t0
+            rows.append({"index": i, "s": dt, "iters": r.iters, "status": r.status,
+                         "E": O.evaluate(g, t, p, r.psi)["E"]})
+            log(f"c4oracle {k + 1}/{len(idx)}: solve {i} {dt:.1f}s, {r.iters} iterations")
+        T = time.perf_counter() - t_all
+        line["c4oracle"] = {"solves": len(rows), "s": T, "solves_per_s": len(rows) / T, "threads": cores,
+                            "iters_mean": float(np.mean([r["iters"] for r in rows])), "rows": rows,
+                            "workload": "the 128^2 solves of the 96-solve sweep (seed 17950), FP64 oracle, "
+                                        "energy criterion 1e-12, one after another on all host cores"}
+    return line
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -254,8 +289,11 @@ def main():
         sys.exit(2)
     sections = [s for s in args.sections.split(",") if s]
     for s in sections:
-        if s not in SECTIONS:
-            sys.exit(f"unknown section {s!r}; choose from {SECTIONS}")
+        if s not in SECTIONS + EXTRA_SECTIONS:
+            sys.exit(f"unknown section {s!r}; choose from {SECTIONS + EXTRA_SECTIONS}")
+    if all(s in EXTRA_SECTIONS for s in sections):
+        print(json.dumps(host_sections(sections, args)), flush=True)
+        return
 
     import numpy as np
     import torch
@@ -351,6 +389,22 @@ def main():
         line["roofline_fp64"] = roofline_of(tab["fp64"], d64, f"fp64:{d64}",
                                             f"plain FP64 path, {B} slots of {args.n}^2 at full occupancy")
         del kb
+        # achievable bandwidth in the same run: a 1 GiB device-to-device copy
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        copy_gbs = 5 * 2 * a.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        for key in ("roofline", "roofline_fp64"):
+            line[key]["copy_GBs"] = copy_gbs
+            line[key]["frac_of_copy"] = line[key]["achieved"] / copy_gbs
+        log(f"copy: {copy_gbs:.0f} GB/s")
+        del a, b
 
     # ------------------------------------------- FFT schedules: fixed table vs tuned
     if "tuner" in sections:
