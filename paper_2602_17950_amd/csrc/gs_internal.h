@@ -203,7 +203,7 @@ struct RedGeom {
 };
 
 // ---------------------------------------------------------------------------
-// FFT pass launchers (fft_kernels.hip); nslots = grid.y
+// FFT pass launchers (fft_fwd.hip, fft_inv.hip, fft_mid.hip); nslots = grid.y
 // ---------------------------------------------------------------------------
 enum Pro : int { PRO_PLAIN = 0, PRO_DIR = 2 };
 enum Epi : int { EPI_SCALE = 0, EPI_HL = 1, EPI_ROTX = 2 };
