@@ -98,10 +98,15 @@ def _problems():
         # 3D, a 600-point middle axis (line groups that end in a partial wave chunk)
         inputs.Problem(dim=3, n=(16, 80, 600), L=(6.0, 7.0, 9.0), g=(1.0, 1.0, 0.8), omega=0.4,
                        gamma=0.7, c0=300.0, c1=-1.0),
+        # 256 x 64 x 64: the pipelined passes have more tiles and line groups than
+        # resident blocks, so one slot runs the persistent unit loop and the XCD
+        # tile order that batches of slots run
+        inputs.Problem(dim=3, n=(256, 64, 64), L=(10.0, 6.0, 6.0), g=(0.5, 1.0, 1.0), omega=0.3,
+                       gamma=0.6, c0=400.0, c1=2.0),
     ]
 
 
-@pytest.mark.parametrize("k", range(10))
+@pytest.mark.parametrize("k", range(11))
 @pytest.mark.parametrize("prec", [gs.GS_FP64, gs.GS_FP32])
 def test_hamiltonian_and_energy(gpu_ctx, k, prec):
     pb = _problems()[k]
@@ -142,7 +147,7 @@ def test_hamiltonian_user_potential(gpu_ctx):
     assert np.isnan(res["virial"])
 
 
-@pytest.mark.parametrize("k", [0, 1, 3, 7, 8, 9])
+@pytest.mark.parametrize("k", [0, 1, 3, 7, 8, 9, 10])
 @pytest.mark.parametrize("prec", [gs.GS_FP64, gs.GS_FP32])
 def test_preconditioner(gpu_ctx, k, prec):
     pb = _problems()[k]
