@@ -25,6 +25,8 @@ def _cases():
         (2, (128, 128), (10.0, 10.0), 0.3, 0.8, 200.0, 1.0, ("a", "b", "a")),
         (2, (48, 96), (6.0, 8.0), 0.2, 0.5, 80.0, -0.5, ("b", "a", "a")),
         (3, (32, 32, 32), (6.0, 6.0, 6.0), 0.5, 1.0, 200.0, 5.0, ("a", "a", "a")),
+        # 2400-point x lines (radix-5 passes, tiles of one or two lines)
+        (2, (2400, 32), (20.0, 4.0), 0.2, 0.5, 100.0, 1.0, ("a", "a", "a")),
     ]:
         pb = inputs.Problem(dim=dim, n=n, L=L, omega=om, gamma=ga, c0=c0, c1=c1)
         out.append((pb, inputs.initial_guess(pb, kinds, noise=1e-3, seed=7)))
@@ -54,7 +56,7 @@ def test_tuned_schedules_give_the_same_bits(prec, dirp):
     rep = reports[1]
     print("[autotune]", rep, flush=True)
     grids = {tuple(r["grid"]) for r in rep}
-    assert (256, 256, 1) in grids and (32, 32, 32) in grids
+    assert (256, 256, 1) in grids and (32, 32, 32) in grids and (2400, 32, 1) in grids
     assert any(r["decided"] for r in rep)
     for r in rep:
         for name, p in r["passes"].items():
