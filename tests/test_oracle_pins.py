@@ -21,7 +21,7 @@ O.set_threads(4)
 # ---------------------------------------------------------------------------
 # transforms (Sec. 3.2): FFT against the DFT definition
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("n", [2, 4, 8, 16, 32, 64, 6, 12, 15, 20, 45, 75, 80, 150, 160, 300, 600, 2400, 14])
+@pytest.mark.parametrize("n", [2, 4, 8, 16, 32, 64, 6, 12, 15, 20, 45, 75, 80, 150, 160, 300, 600, 1200, 2400, 14])
 def test_fft_matches_brute_force_dft(n):
     """Radix 2 (powers of two) and mixed radix 2, 3, 5 (other lengths; the DFT
     definition for a remaining prime factor) against the defining sum, with the
