@@ -244,7 +244,7 @@ def host_sections(sections, args):
         cores = os.cpu_count() or 1
         O.set_threads(cores)
         spec = inputs.workload_sweep_2d()
-        idx = [i for i, (pb, _) in enumerate(spec) if pb.n[0] == 128]
+        idx = [i for i, (pb, _) in enumerate(spec) if pb.n[0] == 128][args.c4_start:]
         rows = []
         t_all = time.perf_counter()
         for k, i in enumerate(idx):
@@ -279,6 +279,8 @@ def main():
     ap.add_argument("--serve-capacity-requests", type=int, default=48)
     ap.add_argument("--serve-loads", default="0.5,0.8", help="arrival rates / measured capacity of the served mix")
     ap.add_argument("--cpu-seconds", type=float, default=16.0)
+    ap.add_argument("--c4-start", type=int, default=0,
+                    help="c4oracle: skip this many of the sweep's 128^2 solves (resume a run)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 1 GiB device to device (reference for the HBM byte counters)")
