@@ -7,6 +7,8 @@ under staggered (served) submission; these tests compare bit for bit. Parity
 of the solve itself with the CPU oracle is covered by the single-solve tests
 and by a batch-vs-oracle check on the smallest problems here.
 """
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -270,8 +272,12 @@ def test_cm_solve_matches_oracle(gpu_ctx, dim):
     tol = 1e-10
     g_f, t, p = orc(pb)
     g_c, _, _ = orc(pc)
-    rs = O.cmpcg([g_c, g_f], lambda gg: t, p, psi0, O.Options(stop_kind=gs.GS_STOP_RESIDUAL, tol=tol))
-    ev = O.evaluate(g_f, t, p, rs[-1].psi)
+    O.set_threads(min(16, os.cpu_count() or 1))   # the 3-D oracle solve takes minutes on one thread
+    try:
+        rs = O.cmpcg([g_c, g_f], lambda gg: t, p, psi0, O.Options(stop_kind=gs.GS_STOP_RESIDUAL, tol=tol))
+        ev = O.evaluate(g_f, t, p, rs[-1].psi)
+    finally:
+        O.set_threads(1)
     opt = gs.default_options(stop_kind=gs.GS_STOP_RESIDUAL, tol=tol, cm_levels=2)
     out = torch.empty((3,) + pb.shape, dtype=torch.complex128, device=DEV)
     r = gpu_ctx.solve_device(pb, dev(psi0), out, options=opt)
