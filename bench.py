@@ -20,7 +20,10 @@ Other sections of the same JSON line: per-kernel timing at full slot
 occupancy (the roofline), the headline workload one solve at a time
 (latency), the 64^2 workload, the 3D 128^3 cascadic-multigrid solve, the
 96-solve parameter sweep, Table 2 by enumeration, a served stream with Poisson
-arrivals, and the CPU oracle on the host cores.
+arrivals, and the CPU oracle on the host cores. Run only when named: `gaps`
+(the sweep's three grid classes together and alone at a fixed iteration count,
+to be read under a kernel trace) and `c4oracle` (the oracle on the sweep's
+128^2 solves, host only).
 
 Prints one JSON line; progress goes to stderr.
 """
@@ -53,6 +56,9 @@ SECTIONS = ("headline", "kernels", "tuner", "single", "c1", "cm3d", "sweep", "ta
 # host-only sections, run only when named (the oracle on the sweep's 128^2 solves
 # takes about an hour of host time)
 EXTRA_SECTIONS = ("c4oracle",)
+# GPU sections run only when named: `gaps` exists to be run under a kernel trace
+GPU_EXTRA_SECTIONS = ("gaps",)
+GAP_PAUSE_S = 0.25        # host pause between the `gaps` batches: marks them apart in a trace
 KINDS = ("hl_fwd", "hl_mid", "hl_inv", "pre_fwd", "pre_mid", "pre_inv", "resid", "lsred", "ctrl", "eval")
 # Table 2 (Example 3): lowest energy over the 1000 guess combinations of Sec. 4, and the
 # paper's CM-PCG CPU seconds for that one solve (a Xeon Gold 6248R, threads not stated;
@@ -281,6 +287,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=16.0)
     ap.add_argument("--c4-start", type=int, default=0,
                     help="c4oracle: skip this many of the sweep's 128^2 solves (resume a run)")
+    ap.add_argument("--gap-iters", type=int, default=256, help="gaps: iterations of every solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 1 GiB device to device (reference for the HBM byte counters)")
@@ -291,8 +298,8 @@ def main():
         sys.exit(2)
     sections = [s for s in args.sections.split(",") if s]
     for s in sections:
-        if s not in SECTIONS + EXTRA_SECTIONS:
-            sys.exit(f"unknown section {s!r}; choose from {SECTIONS + EXTRA_SECTIONS}")
+        if s not in SECTIONS + EXTRA_SECTIONS + GPU_EXTRA_SECTIONS:
+            sys.exit(f"unknown section {s!r}; choose from {SECTIONS + EXTRA_SECTIONS + GPU_EXTRA_SECTIONS}")
     if all(s in EXTRA_SECTIONS for s in sections):
         print(json.dumps(host_sections(sections, args)), flush=True)
         return
@@ -571,6 +578,44 @@ def main():
                        "the path moves about half of these solves to another minimum, as often lower as higher")
         line["sweep"] = out
         cap = out["mixed"]["solves_per_s"]
+        del sw
+
+    # ------------------------------------------------------------------ gaps
+    if "gaps" in sections:
+        # Device idle time when the sweep's three grid classes (128^2, 256^2, 512^2,
+        # one stream each) share the GPU: its 96 solves with tol 0 and a fixed
+        # iteration count, so every slot of every class runs to the end; then each
+        # class alone. Every configuration runs a warm-up batch (the first chunk of
+        # a class tunes its FFT schedules) and a timed batch, with a host pause
+        # before each batch so that a kernel trace splits into one segment per
+        # batch; the union of kernel intervals over a segment against its span is
+        # the busy fraction.
+        spec = inputs.workload_sweep_2d()
+        sw = Batch(torch, [(pb, inputs.initial_guess(pb, k)) for pb, k in spec])
+        reqs_all = None
+        gp = {"iters": args.gap_iters, "segments": [],
+              "workload": f"the 96 solves of the sweep, tol 0, {args.gap_iters} iterations each; "
+                          "all three classes together, then each class alone"}
+        for name, prec, dirp in (("fp64", gs.GS_FP64, gs.GS_FP64), ("fp64_state_fp32_dir", gs.GS_FP64, gs.GS_FP32)):
+            opt = gs.default_options(precision=prec, tol=0.0, max_iter=args.gap_iters, dir_precision=dirp)
+            reqs_all = sw.requests(opt)
+            groups = [("all", reqs_all)] + [(f"n{n}", [q for q in reqs_all if q[0].n[0] == n]) for n in (128, 256, 512)]
+            for gname, reqs in groups:
+                for phase in ("warm", "timed"):
+                    time.sleep(GAP_PAUSE_S)
+                    t = time.perf_counter()
+                    rs = ctx.batch_solve(reqs)
+                    torch.cuda.synchronize()
+                    dt = time.perf_counter() - t
+                    gp["segments"].append({"precision": name, "classes": gname, "phase": phase,
+                                           "solves": len(reqs), "s": dt,
+                                           "iters_min": min(r["iters"] for r in rs)})
+                    log(f"gaps {name} {gname} {phase}: {len(reqs)} solves, {dt:.3f}s")
+            tm = {g["classes"]: g["s"] for g in gp["segments"] if g["precision"] == name and g["phase"] == "timed"}
+            gp[name] = {"together_s": tm["all"], "alone_sum_s": tm["n128"] + tm["n256"] + tm["n512"],
+                        "alone_max_s": max(tm["n128"], tm["n256"], tm["n512"])}
+        time.sleep(GAP_PAUSE_S)
+        line["gaps"] = gp
         del sw
 
     # ------------------------------------------------------------------ table2
