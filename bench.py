@@ -18,7 +18,8 @@ are resident in device memory before the clock starts.
 
 Other sections of the same JSON line: per-kernel timing at full slot
 occupancy (the roofline), the headline workload one solve at a time
-(latency), the 64^2 workload, the 3D 128^3 cascadic-multigrid solve, the
+(latency), the 64^2 workload, the 3D 128^3 cascadic-multigrid solve, Example
+7's anisotropic cases at 256^3 on the elongated domain, the
 96-solve parameter sweep, Table 2 by enumeration, a served stream with Poisson
 arrivals, and the CPU oracle on the host cores. Run only when named: `gaps`
 (the sweep's three grid classes together and alone at a fixed iteration count,
@@ -52,7 +53,7 @@ KERNEL_SOURCES = ("paper_2602_17950_amd/csrc/fft_core.h", "paper_2602_17950_amd/
                   "paper_2602_17950_amd/csrc/device_common.h", "paper_2602_17950_amd/csrc/control.h",
                   "paper_2602_17950_amd/csrc/gs_internal.h")
 TRAFFIC_SUMMARY = "profiles/hbm_traffic_kernels256.md"
-SECTIONS = ("headline", "kernels", "tuner", "single", "c1", "cm3d", "sweep", "table2", "serve")
+SECTIONS = ("headline", "kernels", "tuner", "single", "c1", "cm3d", "ex7", "sweep", "table2", "serve")
 # host-only sections, run only when named (the oracle on the sweep's 128^2 solves
 # takes about an hour of host time)
 EXTRA_SECTIONS = ("c4oracle",)
@@ -535,6 +536,39 @@ def main():
                           "cascadic multigrid 32^3->64^3->128^3 from (a,a,a); energy criterion 1e-12 per level")
         line["cm3d"] = cm
         del g3, out3
+
+    # ------------------------------------------------------------------- ex7
+    if "ex7" in sections:
+        # Example 7's anisotropic cases on the elongated domain, as the paper runs
+        # them: cascadic multigrid 64^3 -> 128^3 -> 256^3
+        def ex7_problem(n, omega, gamma):
+            return inputs.Problem(dim=3, n=(n, n, n), L=(10.0, 10.0, 80.0), g=(0.97, 1.03, 0.05), omega=omega,
+                                  gamma=gamma, c0=3000.0, c1=1.0)
+        out7 = torch.empty((3,) + ex7_problem(256, 0.5, 0.4).shape, dtype=torch.complex128, device="cuda")
+        ex = {}
+        for case, (omega, gamma) in ((4, (0.5, 0.4)), (5, (0.5, 0.8)), (6, (0.7, 0.4))):
+            pb7, pc7 = ex7_problem(256, omega, gamma), ex7_problem(64, omega, gamma)
+            g7 = torch.from_numpy(inputs.initial_guess(pc7, ("f", "f", "f"))).to("cuda")
+            row = {}
+            for name, prec in (("fp64", gs.GS_FP64), ("mixed", gs.GS_MIXED)):
+                opt = gs.default_options(precision=prec, tol=1e-12, cm_levels=3,
+                                         dir_precision=mdir if prec == gs.GS_MIXED else gs.GS_FP64)
+                ctx.solve_device(pb7, g7, out7, opt)   # warm
+                t = time.perf_counter()
+                r = ctx.solve_device(pb7, g7, out7, opt)
+                row[name] = {"s": time.perf_counter() - t, "E": r["E"], "mu": r["mu"], "iters_fine": r["iters"],
+                             "iters_coarse": r["iters_coarse"], "iters_fp32": r["iters_fp32"],
+                             "resid_inf": r["resid_inf"], "virial": r["virial"], "status": r["rc"]}
+                log(f"ex7 case {case} {name}: {row[name]['s']:.2f}s E={r['E']:.15f} "
+                    f"iters {r['iters']}+{r['iters_coarse']}")
+            row["dE_rel"] = rel(row["mixed"]["E"], row["fp64"]["E"])
+            ex[f"case{case}"] = row
+            del g7
+        ex["workload"] = ("Example 7, Cases 4-6: 3D 256^3 on [-10,10]^2 x [-80,80], gamma = (0.97, 1.03, 0.05), "
+                          "c0=3000, c1=1, (Omega, SOC) = (0.5, 0.4), (0.5, 0.8), (0.7, 0.4); cascadic multigrid "
+                          "64^3->128^3->256^3 from the Thomas-Fermi guess (f,f,f); energy criterion 1e-12 per level")
+        line["ex7"] = ex
+        del out7
 
     # ------------------------------------------------------------------- sweep
     cap = None
