@@ -241,8 +241,9 @@ class Batch:
 
 def host_sections(sections, args):
     """Sections that run on the host only: `c4oracle`, the FP64 oracle on the
-    128^2 solves of the 96-solve sweep (energy criterion 1e-12, all host cores,
-    each solve to completion)."""
+    solves of the 96-solve sweep on one grid size (--c4-n, default 128^2;
+    --c4-count of them after skipping --c4-start), energy criterion 1e-12, all
+    host cores, each solve to completion."""
     import numpy as np
     from paper_2602_17950_amd import inputs
     import oracle as O
@@ -251,7 +252,9 @@ def host_sections(sections, args):
         cores = os.cpu_count() or 1
         O.set_threads(cores)
         spec = inputs.workload_sweep_2d()
-        idx = [i for i, (pb, _) in enumerate(spec) if pb.n[0] == 128][args.c4_start:]
+        idx = [i for i, (pb, _) in enumerate(spec) if pb.n[0] == args.c4_n][args.c4_start:]
+        if args.c4_count > 0:
+            idx = idx[:args.c4_count]
         rows = []
         t_all = time.perf_counter()
         for k, i in enumerate(idx):
@@ -266,8 +269,9 @@ def host_sections(sections, args):
         T = time.perf_counter() - t_all
         line["c4oracle"] = {"solves": len(rows), "s": T, "solves_per_s": len(rows) / T, "threads": cores,
                             "iters_mean": float(np.mean([r["iters"] for r in rows])), "rows": rows,
-                            "workload": "the 128^2 solves of the 96-solve sweep (seed 17950), FP64 oracle, "
-                                        "energy criterion 1e-12, one after another on all host cores"}
+                            "workload": f"the {args.c4_n}^2 solves of the 96-solve sweep (seed 17950), from the "
+                                        f"{args.c4_start + 1}th on, FP64 oracle, energy criterion 1e-12, one after "
+                                        "another on all host cores"}
     return line
 
 
@@ -287,7 +291,10 @@ def main():
     ap.add_argument("--serve-loads", default="0.5,0.8", help="arrival rates / measured capacity of the served mix")
     ap.add_argument("--cpu-seconds", type=float, default=16.0)
     ap.add_argument("--c4-start", type=int, default=0,
-                    help="c4oracle: skip this many of the sweep's 128^2 solves (resume a run)")
+                    help="c4oracle: skip this many of the sweep's solves of the chosen size (resume a run)")
+    ap.add_argument("--c4-n", type=int, default=128, choices=(128, 256, 512),
+                    help="c4oracle: grid size of the sweep's solves to run")
+    ap.add_argument("--c4-count", type=int, default=0, help="c4oracle: at most this many solves (0: all)")
     ap.add_argument("--gap-iters", type=int, default=256, help="gaps: iterations of every solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
