@@ -127,6 +127,56 @@ def test_serving_staggered_submission(gpu_ctx):
     assert gpu_ctx.memory_stats()["reserved"] == 0
 
 
+@pytest.mark.timeout(400)
+def test_served_mix_subset(gpu_ctx):
+    """Requests of the served stream itself (its first ten with a 2D grid of at
+    most 256^2 or a 3D grid of 64^3; harmonic and harmonic-plus-quartic traps,
+    the served options): each submitted while the earlier ones run, each result
+    bit for bit the solve alone, and the final states of the 128^2 and 64^3
+    requests evaluated by the oracle (E, mu to 1e-10, the residual)."""
+    spec = inputs.workload_serve(400)
+    idx = [i for i, (pb, _) in enumerate(spec)
+           if (pb.dim == 2 and pb.n[0] <= 256) or (pb.dim == 3 and pb.n[0] <= 64)][:10]
+    opt = gs.default_options(precision=gs.GS_MIXED, tol=1e-12, dir_precision=gs.GS_FP32)
+    work = [(spec[i][0], inputs.initial_guess(spec[i][0], spec[i][1])) for i in idx]
+    guesses = [dev(psi0) for _, psi0 in work]
+    outs = [torch.empty((3,) + pb.shape, dtype=torch.complex128, device=DEV) for pb, _ in work]
+    print(f"[serve subset] requests {idx}", flush=True)
+    tickets = []
+    for k, (pb, _) in enumerate(work):
+        tickets.append(gpu_ctx.submit(pb, guesses[k], outs[k], opt))
+        for _ in range(2):
+            gpu_ctx.progress(block=True)
+    done = {}
+    while len(done) < len(tickets):
+        for k, t in enumerate(tickets):
+            if k not in done:
+                r = gpu_ctx.poll(t)
+                if r is not None:
+                    done[k] = r
+        if len(done) < len(tickets):
+            gpu_ctx.progress(block=True)
+    torch.cuda.synchronize()
+    O.set_threads(min(16, os.cpu_count() or 1))
+    try:
+        for k, (pb, psi0) in enumerate(work):
+            ref, rref = alone(gpu_ctx, pb, psi0, opt)
+            r = done[k]
+            print(f"[serve subset] {idx[k]}: {pb.dim}D {pb.n[0]} q4={pb.q4} rc={r['rc']} E={r['E']!r} "
+                  f"it={r['iters']}", flush=True)
+            assert r["rc"] >= 0
+            assert same_bits(outs[k], ref) and r["E"] == rref["E"], idx[k]
+            small = (pb.dim == 2 and pb.n[0] <= 128) or (pb.dim == 3 and pb.n[0] <= 64)
+            if small:
+                g, t, p = orc(pb)
+                ev = O.evaluate(g, t, p, outs[k].cpu().numpy())
+                assert rel(r["E"], ev["E"]) < 1e-10, (idx[k], r["E"], ev["E"])
+                assert rel(r["mu"], ev["mu"]) < 1e-10, (idx[k], r["mu"], ev["mu"])
+                assert abs(r["resid_inf"] - ev["resid_inf"]) < 1e-9 + 1e-6 * ev["resid_inf"]
+    finally:
+        O.set_threads(1)
+
+
 def test_admission_by_footprint(gpu_ctx):
     """With a budget that fits one request, requests run one at a time and all
     complete with the bits of the solve alone."""
