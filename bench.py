@@ -56,7 +56,7 @@ TRAFFIC_SUMMARY = "profiles/hbm_traffic_kernels256.md"
 SECTIONS = ("headline", "kernels", "tuner", "single", "c1", "cm3d", "ex7", "sweep", "table2", "serve")
 # host-only sections, run only when named (the oracle on the sweep's 128^2 solves
 # takes about an hour of host time)
-EXTRA_SECTIONS = ("c4oracle",)
+EXTRA_SECTIONS = ("c3oracle", "c4oracle")
 # GPU sections run only when named: `gaps` exists to be run under a kernel trace
 GPU_EXTRA_SECTIONS = ("gaps",)
 GAP_PAUSE_S = 0.25        # host pause between the `gaps` batches: marks them apart in a trace
@@ -240,7 +240,9 @@ class Batch:
 
 
 def host_sections(sections, args):
-    """Sections that run on the host only: `c4oracle`, the FP64 oracle on the
+    """Sections that run on the host only: `c3oracle`, the FP64 oracle on the
+    128^3 cascadic-multigrid solve of `cm3d`, level by level to completion, and
+    `c4oracle`, the FP64 oracle on the
     solves of the 96-solve sweep on one grid size (--c4-n, default 128^2;
     --c4-count of them after skipping --c4-start), energy criterion 1e-12, all
     host cores, each solve to completion."""
@@ -248,6 +250,32 @@ def host_sections(sections, args):
     from paper_2602_17950_amd import inputs
     import oracle as O
     line = {"metric": METRIC, "data": "synthetic", "n_gpus": 0}
+    if "c3oracle" in sections:
+        # the 128^3 cascadic-multigrid solve of the cm3d section on the oracle, level by level
+        cores = os.cpu_count() or 1
+        O.set_threads(cores)
+        pb, _ = inputs.workload_aniso_3d(n=128)
+        levels = [inputs.Problem(dim=3, n=(m, m, m), L=pb.L, g=pb.g, omega=pb.omega, gamma=pb.gamma, c0=pb.c0,
+                                 c1=pb.c1) for m in (32, 64, 128)]
+        psi = inputs.initial_guess(levels[0], ("a", "a", "a"))
+        rows, prev = [], None
+        t_all = time.perf_counter()
+        for q in levels:
+            g, t, p = oracle_objects(O, q)
+            t0 = time.perf_counter()
+            if prev is not None:
+                psi = O.interp(prev, psi, g)
+            r = O.pcg(g, t, p, psi, O.Options(tol=1e-12))
+            dt = time.perf_counter() - t0
+            psi, prev = r.psi, g
+            rows.append({"n": q.n[0], "s": dt, "iters": r.iters, "status": r.status})
+            log(f"c3oracle {q.n[0]}^3: {dt:.1f}s, {r.iters} iterations")
+        ev = O.evaluate(prev, t, p, psi)
+        line["c3oracle"] = {"s": time.perf_counter() - t_all, "threads": cores, "levels": rows, "E": ev["E"],
+                            "mu": ev["mu"], "resid_inf": ev["resid_inf"],
+                            "workload": "the cm3d section's solve: 3D 128^3 on [-8,8]^3, V=(x^2+y^2+4z^2)/2, "
+                                        "Omega=0.5, SOC 1.0, c0=800, c1=5; cascadic multigrid 32^3->64^3->128^3 "
+                                        "from (a,a,a); FP64 oracle, energy criterion 1e-12 per level"}
     if "c4oracle" in sections:
         cores = os.cpu_count() or 1
         O.set_threads(cores)
