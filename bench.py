@@ -688,7 +688,6 @@ def main():
         # the busy fraction.
         spec = inputs.workload_sweep_2d()
         sw = Batch(torch, [(pb, inputs.initial_guess(pb, k)) for pb, k in spec])
-        reqs_all = None
         gp = {"iters": args.gap_iters, "segments": [],
               "workload": f"the 96 solves of the sweep, tol 0, {args.gap_iters} iterations each; "
                           "all three classes together, then each class alone"}
