@@ -273,9 +273,20 @@ __global__ __launch_bounds__(PT) void k_normalize(const Slot* slots, RedGeom g) 
 //   FIN_RFINAL: residual rows of a final-only residual pass
 __global__ __launch_bounds__(PT) void k_fin(const Slot* slots, RedGeom g, int what) {
     const Slot& S = slots[blockIdx.y];
-    SolveState* st = as_global(S.st);
+    SolveState* gst = as_global(S.st);
     const Phys p = S.p;
-    if (what != FIN_NORM && what != FIN_RFINAL && st->done) return;
+    if (what != FIN_NORM && what != FIN_RFINAL && gst->done) return;
+    // Thread 0's control steps read and write the state field by field; they
+    // run on a copy in LDS that the whole block loads at once and stores back
+    // at the end, so those accesses are LDS accesses, not dependent round
+    // trips to memory.
+    static_assert(sizeof(SolveState) % 8 == 0, "state copied in 8-byte words");
+    constexpr int NW = (int)(sizeof(SolveState) / 8);
+    __shared__ SolveState sst;
+    for (int w = threadIdx.x; w < NW; w += PT)
+        reinterpret_cast<unsigned long long*>(&sst)[w] = reinterpret_cast<const unsigned long long*>(gst)[w];
+    __syncthreads();
+    SolveState* st = &sst;
     // the pass before this control step applied a PCG step: its largest change
     // (3.9); a normalisation rescale (s = 0) leaves the recorded change alone
     if (what == FIN_EVAL || what == FIN_DIR) {
@@ -301,10 +312,11 @@ __global__ __launch_bounds__(PT) void k_fin(const Slot* slots, RedGeom g, int wh
             stop = st->done;
         }
         __syncthreads();
-        if (stop) return;
-        double dt[NS_DIR];
-        gather<NS_DIR>(dt, as_global(S.red_dir), g.nblk_dir, RED_DIR_STRIDE);
-        if (threadIdx.x == 0) ctrl_dir(st, p, dt);
+        if (!stop) {   // uniform over the block
+            double dt[NS_DIR];
+            gather<NS_DIR>(dt, as_global(S.red_dir), g.nblk_dir, RED_DIR_STRIDE);
+            if (threadIdx.x == 0) ctrl_dir(st, p, dt);
+        }
     } else if (what == FIN_LS) {
         double tot[NS_LS], kin[NS_KIN];
         gather<NS_LS>(tot, as_global(S.red_pw), g.nblk_pw, NS_MAX);
@@ -331,6 +343,9 @@ __global__ __launch_bounds__(PT) void k_fin(const Slot* slots, RedGeom g, int wh
         gather<NS_RES>(tot, as_global(S.red_pw), g.nblk_pw, NS_MAX, 1u);
         if (threadIdx.x == 0) ctrl_resid(st, p, tot, 1);
     }
+    __syncthreads();
+    for (int w = threadIdx.x; w < NW; w += PT)
+        reinterpret_cast<unsigned long long*>(gst)[w] = reinterpret_cast<const unsigned long long*>(&sst)[w];
 }
 
 // ---------------------------------------------------------------------------
