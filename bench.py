@@ -297,8 +297,8 @@ def host_sections(sections, args):
         T = time.perf_counter() - t_all
         line["c4oracle"] = {"solves": len(rows), "s": T, "solves_per_s": len(rows) / T, "threads": cores,
                             "iters_mean": float(np.mean([r["iters"] for r in rows])), "rows": rows,
-                            "workload": f"the {args.c4_n}^2 solves of the 96-solve sweep (seed 17950), from the "
-                                        f"{args.c4_start + 1}th on, FP64 oracle, energy criterion 1e-12, one after "
+                            "workload": f"the {args.c4_n}^2 solves of the 96-solve sweep (seed 17950) after "
+                                        f"skipping {args.c4_start}, FP64 oracle, energy criterion 1e-12, one after "
                                         "another on all host cores"}
     return line
 
